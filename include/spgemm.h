@@ -1,0 +1,157 @@
+/*
+ * spgemm.h -- C ABI of the MI355X (gfx950) row-wise SpGEMM library.
+ *
+ * The library computes C = A*B for sparse A (M x K) and B (K x N) held in
+ * CSR (Section II-A.3 of the paper: a row-pointer array of M+1 entries,
+ * column indices sorted within each row, values alongside).  It follows the
+ * row-wise dataflow of Eq. (2) (Section II-A.2), the precise allocation
+ * method of Section II-B.2 (a symbolic pass counts each output row, a prefix
+ * sum turns the counts into C's row pointers, the numeric pass writes every
+ * row straight into place; the "BRMerge-Precise" library of Section III-D.2)
+ * and the BRMerge accumulation of Section III-B / Algorithm 1 (for every
+ * output row the scaled rows of B selected by the row of A are written one
+ * after the other into a buffer, then merged two lists at a time, list 0 with
+ * list 1, list 2 with list 3, ..., an odd last list passing unchanged, round
+ * after round between two buffers, with the values of equal columns added).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrix arrays are DEVICE pointers on the handle's device.  The
+ *    caller owns them; the library never frees or keeps them past a call
+ *    (except as documented for spgemm_symbolic -> spgemm_numeric).
+ *  - Input row pointers may be int32 or int64 (spg_csr.rpt_bytes = 4 or 8).
+ *    Column indices are int32, values IEEE-754 double.  Input rows must have
+ *    strictly increasing columns (checked when SPG_OPT_VALIDATE is set).
+ *  - C's row pointers are int64 (rows + 1 entries, c_rpt[0] == 0); C's
+ *    columns are strictly increasing within each row.
+ *  - C is the STRUCTURAL product: (i, j) is stored iff some k has both A_ik
+ *    and B_kj stored.  Values that are zero or cancel to zero are kept.
+ *  - Every value of C is the sum of the products A_ik * B_kj (one rounded
+ *    double multiplication each, no fused multiply-add) grouped by the merge
+ *    tree of Algorithm 1 with the stored entries of A's row as its leaves in
+ *    stored order: the node of level r and index p covers leaves
+ *    [p * 2^r, (p + 1) * 2^r) and adds the values of its two children when
+ *    both hold the column.  The result is therefore bitwise reproducible and
+ *    independent of the kernel class a row is routed to.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously on it unless stated otherwise.
+ *  - Every function returns SPG_OK (0) or a negative spg_status; details of
+ *    the last error are available from spg_last_error().  No C++ exception
+ *    crosses this interface.
+ *  - A handle is not thread-safe: use one handle per host thread / stream.
+ */
+#ifndef SPGEMM_H_
+#define SPGEMM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPG_OK = 0,
+    SPG_ERR_ARG = -1,          /* null pointer, negative size, bad option, rpt_bytes not 4/8 */
+    SPG_ERR_DIM = -2,          /* A.cols != B.rows */
+    SPG_ERR_INVALID_CSR = -3,  /* (validation on) rpt not monotone / rpt[0] != 0 /
+                                  column out of range / columns not strictly increasing */
+    SPG_ERR_CAPACITY = -4,     /* a caller-provided buffer is too small */
+    SPG_ERR_NOMEM = -5,        /* device allocation failed */
+    SPG_ERR_HIP = -6,          /* a HIP runtime call failed (see spg_last_error) */
+    SPG_ERR_NOT_TRAINED = -7,  /* learned allocation asked for before any training/loading */
+    SPG_ERR_STATE = -8         /* spgemm_numeric without a matching spgemm_symbolic */
+} spg_status;
+
+/* A CSR matrix on the device. */
+typedef struct {
+    int64_t rows;        /* M */
+    int64_t cols;        /* N */
+    int64_t nnz;         /* rpt[rows]; must equal the device value */
+    const void *rpt;     /* rows + 1 entries of int32 or int64 */
+    int32_t rpt_bytes;   /* 4 or 8 */
+    const int32_t *col;  /* nnz entries */
+    const double *val;   /* nnz entries (may be NULL for spgemm_symbolic) */
+} spg_csr;
+
+typedef struct spg_handle_s *spg_handle;
+
+/* Create a handle bound to HIP device `device`.  The handle owns the
+ * library's device workspace (row analysis, bins, scan state, the spill pool
+ * of heavy rows) and grows it on demand; everything is freed by
+ * spg_destroy().  Errors: SPG_ERR_ARG (h NULL), SPG_ERR_HIP (bad device). */
+int spg_create(spg_handle *h, int device);
+
+/* Release the handle and all device memory it owns.  Waits for the device. */
+int spg_destroy(spg_handle h);
+
+/* Options (spg_set_option / spg_get_option).  Thresholds are products per
+ * row; they select the kernel class each row is routed to.  Results do not
+ * depend on them (bitwise). */
+typedef enum {
+    SPG_OPT_VALIDATE = 1,        /* 0/1: check A and B before computing (default 0) */
+    SPG_OPT_WAVE_SMALL_MAX = 2,  /* largest row routed to one wavefront with one product per lane (64) */
+    SPG_OPT_WAVE_MAX = 3,        /* largest row routed to one wavefront with an LDS buffer (<= 256) */
+    SPG_OPT_GROUP_MAX = 4,       /* largest row routed to a 256-thread workgroup (<= 1024) */
+    SPG_OPT_BLOCK_MAX = 5,       /* largest row kept in one workgroup's LDS (<= 4096); larger
+                                    rows take the heavy path with HBM spill */
+    SPG_OPT_FORCE_CLASS = 6,     /* -1: normal binning.  2..5: every non-empty row (single-list
+                                    rows included) that fits that class (2 wave-small, 3 wave,
+                                    4 group, 5 block) is routed there, every other row to the
+                                    heavy path; 6: every non-empty row to the heavy path */
+    SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (<= 4096) */
+    SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
+                                    per batch of heavy rows (default 16384) */
+    SPG_OPT_GRID_WAVES = 9       /* waves per launch of the persistent row kernels (0 = auto) */
+} spg_option;
+
+int spg_set_option(spg_handle h, int key, int64_t value);
+int spg_get_option(spg_handle h, int key, int64_t *value);
+
+/* Statistics of the last symbolic/numeric pair (spg_get_stat). */
+typedef enum {
+    SPG_STAT_NPROD = 1,          /* total products of the last symbolic call */
+    SPG_STAT_NNZ = 2,            /* nnz(C) of the last symbolic call */
+    SPG_STAT_CLASS_ROWS0 = 10,   /* rows per class: +0 empty, +1 copy, +2 wave-small,
+                                    +3 wave, +4 group, +5 block, +6 heavy */
+    SPG_STAT_HEAVY_BATCHES = 20, /* spill batches the heavy path used in the last numeric call */
+    SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call
+                                    (16: a numeric row length differed from its symbolic count;
+                                    the row was truncated to its slot).  Synchronizes the device. */
+} spg_stat;
+
+int spg_get_stat(spg_handle h, int key, int64_t *value);
+
+/* Symbolic pass of the precise allocation (Section II-B.2, Section III-D.2
+ * steps 1-4): per-row product counts and binning, the exact number of
+ * distinct columns of every row of C, and their exclusive prefix sum.
+ *   A, B   : device CSR inputs (values not read).
+ *   c_rpt  : device int64[A->rows + 1], written with C's row pointers.
+ *   c_nnz  : host int64, written with nnz(C).
+ * This call BLOCKS until c_nnz is known (one device-to-host copy).  The row
+ * analysis it makes is kept in the handle for the next spgemm_numeric call
+ * with the same A and B.
+ * Errors: SPG_ERR_ARG, SPG_ERR_DIM, SPG_ERR_INVALID_CSR (validation on),
+ * SPG_ERR_NOMEM, SPG_ERR_HIP. */
+int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c_rpt,
+                    int64_t *c_nnz, void *stream);
+
+/* Numeric pass (Section III-D.2 step 5): the BRMerge accumulation of every
+ * row written straight into C at c_rpt[i].
+ *   c_rpt  : the device array filled by spgemm_symbolic.
+ *   c_col  : device int32[nnz(C)], c_val: device double[nnz(C)].
+ * Must follow spgemm_symbolic on this handle with the same A and B (same
+ * device pointers and sizes), else SPG_ERR_STATE.  Asynchronous on `stream`
+ * except for heavy rows, whose spill planning reads their sizes back once.
+ * Errors: SPG_ERR_ARG, SPG_ERR_STATE, SPG_ERR_NOMEM, SPG_ERR_HIP. */
+int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64_t *c_rpt,
+                   int32_t *c_col, double *c_val, void *stream);
+
+/* Text of the last error on this handle ("" if none).  Valid until the next
+ * call on the handle. */
+const char *spg_last_error(spg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGEMM_H_ */

@@ -1,0 +1,223 @@
+"""MI355X (gfx950) row-wise SpGEMM with the BRMerge accumulation.
+
+Thin Python binding of the C ABI in ``include/spgemm.h`` (library
+``libbrmspgemm.so`` built from ``csrc/`` by ``build.py``).  Python only
+marshals arguments: device memory comes from PyTorch tensors, the stream is
+PyTorch's current stream, and every step of the product runs in the HIP
+kernels of the library.  There is no fallback: importing this package fails
+if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbrmspgemm.so")
+
+# status codes
+SPG_OK = 0
+SPG_ERR_ARG = -1
+SPG_ERR_DIM = -2
+SPG_ERR_INVALID_CSR = -3
+SPG_ERR_CAPACITY = -4
+SPG_ERR_NOMEM = -5
+SPG_ERR_HIP = -6
+SPG_ERR_NOT_TRAINED = -7
+SPG_ERR_STATE = -8
+
+# options
+OPT_VALIDATE = 1
+OPT_WAVE_SMALL_MAX = 2
+OPT_WAVE_MAX = 3
+OPT_GROUP_MAX = 4
+OPT_BLOCK_MAX = 5
+OPT_FORCE_CLASS = 6
+OPT_HEAVY_LDS_MAX = 7
+OPT_SPILL_BUDGET_MB = 8
+OPT_GRID_WAVES = 9
+
+# statistics
+STAT_NPROD = 1
+STAT_NNZ = 2
+STAT_CLASS_ROWS0 = 10
+STAT_HEAVY_BATCHES = 20
+STAT_DEVICE_ERR = 30
+
+CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy"]
+
+
+class SpgError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"spgemm error {code}: {message}")
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [
+        ("rows", ctypes.c_int64),
+        ("cols", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("rpt", ctypes.c_void_p),
+        ("rpt_bytes", ctypes.c_int32),
+        ("col", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+    ]
+
+
+def _load_library():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it first (python -m paper_2206_06611_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    PH = ctypes.POINTER(ctypes.c_void_p)
+    PCSR = ctypes.POINTER(_Csr)
+    sig = {
+        "spg_create": ([PH, I32], I32),
+        "spg_destroy": ([P], I32),
+        "spg_set_option": ([P, I32, I64], I32),
+        "spg_get_option": ([P, I32, ctypes.POINTER(I64)], I32),
+        "spg_get_stat": ([P, I32, ctypes.POINTER(I64)], I32),
+        "spgemm_symbolic": ([P, PCSR, PCSR, P, ctypes.POINTER(I64), P], I32),
+        "spgemm_numeric": ([P, PCSR, PCSR, P, P, P, P], I32),
+        "spg_last_error": ([P], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load_library()
+
+# every symbol declared in include/spgemm.h
+EXPORTED = ("spg_create", "spg_destroy", "spg_set_option", "spg_get_option", "spg_get_stat",
+            "spgemm_symbolic", "spgemm_numeric", "spg_last_error")
+
+
+def library():
+    return _lib
+
+
+@dataclass
+class DeviceCSR:
+    """A CSR matrix whose arrays are device tensors."""
+
+    rows: int
+    cols: int
+    rpt: torch.Tensor  # int32 or int64, rows + 1
+    col: torch.Tensor  # int32
+    val: torch.Tensor  # float64
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def from_host(cls, A, device="cuda", rpt_dtype=None) -> "DeviceCSR":
+        """Copy a host CSR (any object with rows, cols, rpt, col, val arrays)."""
+        rpt = torch.as_tensor(A.rpt)
+        if rpt_dtype is not None:
+            rpt = rpt.to(rpt_dtype)
+        return cls(int(A.rows), int(A.cols), rpt.to(device),
+                   torch.as_tensor(A.col, dtype=torch.int32).to(device),
+                   torch.as_tensor(A.val, dtype=torch.float64).to(device))
+
+    def _struct(self) -> _Csr:
+        if self.rpt.dtype not in (torch.int32, torch.int64):
+            raise TypeError("rpt must be int32 or int64")
+        for t in (self.rpt, self.col, self.val):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("CSR arrays must be contiguous device tensors")
+        if self.col.dtype != torch.int32 or self.val.dtype != torch.float64:
+            raise TypeError("col must be int32 and val float64")
+        return _Csr(self.rows, self.cols, self.nnz, self.rpt.data_ptr(),
+                    4 if self.rpt.dtype == torch.int32 else 8,
+                    self.col.data_ptr() if self.nnz else None,
+                    self.val.data_ptr() if self.nnz else None)
+
+
+def _stream_ptr(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Handle:
+    """Owns a library handle (device workspace, options, statistics)."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        rc = _lib.spg_create(ctypes.byref(self._h), device)
+        if rc != SPG_OK:
+            raise SpgError(rc, "spg_create failed")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            _lib.spg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != SPG_OK:
+            raise SpgError(rc, _lib.spg_last_error(self._h).decode())
+
+    def set_option(self, key: int, value: int):
+        self._check(_lib.spg_set_option(self._h, key, int(value)))
+
+    def get_option(self, key: int) -> int:
+        v = ctypes.c_int64()
+        self._check(_lib.spg_get_option(self._h, key, ctypes.byref(v)))
+        return v.value
+
+    def stat(self, key: int) -> int:
+        v = ctypes.c_int64()
+        self._check(_lib.spg_get_stat(self._h, key, ctypes.byref(v)))
+        return v.value
+
+    def class_rows(self) -> dict:
+        return {n: self.stat(STAT_CLASS_ROWS0 + i) for i, n in enumerate(CLASS_NAMES)}
+
+    def symbolic(self, A: DeviceCSR, B: DeviceCSR, c_rpt: torch.Tensor | None = None, stream=None):
+        """Returns (c_rpt int64 device tensor, nnz)."""
+        if c_rpt is None:
+            c_rpt = torch.empty(A.rows + 1, dtype=torch.int64, device=A.rpt.device)
+        nnz = ctypes.c_int64()
+        sa, sb = A._struct(), B._struct()
+        self._check(_lib.spgemm_symbolic(self._h, ctypes.byref(sa), ctypes.byref(sb),
+                                         ctypes.c_void_p(c_rpt.data_ptr()), ctypes.byref(nnz),
+                                         _stream_ptr(stream)))
+        return c_rpt, nnz.value
+
+    def numeric(self, A: DeviceCSR, B: DeviceCSR, c_rpt: torch.Tensor, c_col: torch.Tensor,
+                c_val: torch.Tensor, stream=None):
+        sa, sb = A._struct(), B._struct()
+        self._check(_lib.spgemm_numeric(self._h, ctypes.byref(sa), ctypes.byref(sb),
+                                        ctypes.c_void_p(c_rpt.data_ptr()),
+                                        ctypes.c_void_p(c_col.data_ptr() if c_col.numel() else None),
+                                        ctypes.c_void_p(c_val.data_ptr() if c_val.numel() else None),
+                                        _stream_ptr(stream)))
+
+    def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None) -> DeviceCSR:
+        """C = A*B: symbolic pass, allocation of C, numeric pass."""
+        c_rpt, nnz = self.symbolic(A, B, stream=stream)
+        dev = A.rpt.device
+        c_col = torch.empty(nnz, dtype=torch.int32, device=dev)
+        c_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+        self.numeric(A, B, c_rpt, c_col, c_val, stream=stream)
+        return DeviceCSR(A.rows, B.cols, c_rpt, c_col, c_val)
+
+
+def spgemm(A: DeviceCSR, B: DeviceCSR, handle: Handle | None = None) -> DeviceCSR:
+    h = handle or Handle(A.rpt.device.index or 0)
+    return h.spgemm(A, B)

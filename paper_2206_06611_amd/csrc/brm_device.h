@@ -1,0 +1,165 @@
+// Device-side building blocks shared by the SpGEMM kernels: wavefront
+// primitives (64 lanes on CDNA), team-wide scans for teams of one wavefront or
+// one workgroup, and binary searches over sorted column arrays.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace brm {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Number of set bits of `mask` in the lanes below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// Orders LDS traffic between the lanes of one wavefront (no s_barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename Tv>
+__device__ __forceinline__ Tv wave_incl_scan(Tv x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        Tv y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+template <typename Tv>
+__device__ __forceinline__ Tv wave_sum(Tv x) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+// A team is either one wavefront (T == 64) or a whole workgroup (T > 64).
+template <int T>
+struct Team {
+    static_assert(T % kWave == 0, "team size must be a multiple of the wavefront");
+    static constexpr int kWaves = T / kWave;
+
+    __device__ __forceinline__ static void sync() {
+        if constexpr (T == kWave)
+            wave_sync();
+        else
+            __syncthreads();
+    }
+
+    // Exclusive prefix sum over the team in thread order; *total gets the sum.
+    // `scratch` needs kWaves entries of LDS (unused for one wavefront).
+    template <typename Tv>
+    __device__ __forceinline__ static Tv excl_scan(Tv x, Tv *total, Tv *scratch, int tid) {
+        Tv incl = wave_incl_scan(x);
+        if constexpr (T == kWave) {
+            *total = __shfl(incl, kWave - 1, kWave);
+            return incl - x;
+        } else {
+            const int w = tid / kWave;
+            if (lane_id() == kWave - 1) scratch[w] = incl;
+            __syncthreads();
+            Tv before = 0, all = 0;
+#pragma unroll
+            for (int i = 0; i < kWaves; ++i) {
+                Tv s = scratch[i];
+                before += (i < w) ? s : Tv(0);
+                all += s;
+            }
+            __syncthreads();
+            *total = all;
+            return before + incl - x;
+        }
+    }
+
+    template <typename Tv>
+    __device__ __forceinline__ static Tv sum(Tv x, Tv *scratch, int tid) {
+        Tv s = wave_sum(x);
+        if constexpr (T == kWave) {
+            return s;
+        } else {
+            if (lane_id() == 0) scratch[tid / kWave] = s;
+            __syncthreads();
+            Tv all = 0;
+#pragma unroll
+            for (int i = 0; i < kWaves; ++i) all += scratch[i];
+            __syncthreads();
+            return all;
+        }
+    }
+};
+
+// First index in [0, n) whose value is >= key (n if none).
+template <typename Tk>
+__device__ __forceinline__ int lower_bound(const Tk *a, int n, Tk key) {
+    int lo = 0;
+    while (n > 0) {
+        int half = n >> 1;
+        if (a[lo + half] < key) {
+            lo += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
+    return lo;
+}
+
+// First index in [0, n) whose value is > key (n if none).
+template <typename Tk>
+__device__ __forceinline__ int upper_bound(const Tk *a, int n, Tk key) {
+    int lo = 0;
+    while (n > 0) {
+        int half = n >> 1;
+        if (!(key < a[lo + half])) {
+            lo += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
+    return lo;
+}
+
+template <typename Tk>
+__device__ __forceinline__ int64_t lower_bound64(const Tk *a, int64_t n, Tk key) {
+    int64_t lo = 0;
+    while (n > 0) {
+        int64_t half = n >> 1;
+        if (a[lo + half] < key) {
+            lo += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
+    return lo;
+}
+
+template <typename Tk>
+__device__ __forceinline__ int64_t upper_bound64(const Tk *a, int64_t n, Tk key) {
+    int64_t lo = 0;
+    while (n > 0) {
+        int64_t half = n >> 1;
+        if (!(key < a[lo + half])) {
+            lo += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
+    return lo;
+}
+
+}  // namespace brm

@@ -1,0 +1,100 @@
+// Internal interface between the host orchestration (brm_api.cpp) and the
+// kernel launchers (brm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace brm {
+
+// Kernel classes a row of C is routed to (by its product count).
+enum RowClass : int {
+    kClassEmpty = 0,   // no product: empty row
+    kClassCopy = 1,    // one list: the scaled B row is the result
+    kClassWaveSmall = 2,  // one wavefront, one product per lane
+    kClassWave = 3,    // one wavefront, LDS buffer
+    kClassGroup = 4,   // 256-thread workgroup, LDS buffer
+    kClassBlock = 5,   // 1024-thread workgroup, LDS buffer
+    kClassHeavy = 6,   // beyond one workgroup's LDS: HBM spill
+    kNumClasses = 7
+};
+
+// Compile-time capacities (products per row) of the LDS classes.
+constexpr int kCapWaveSmall = 64;
+constexpr int kCapWave = 256;
+constexpr int kCapGroup = 1024;
+constexpr int kCapBlock = 4096;
+
+struct Thresholds {
+    int64_t wave_small_max;
+    int64_t wave_max;
+    int64_t group_max;
+    int64_t block_max;
+    int32_t force;  // -1: none
+};
+
+// Device control block (one per handle).
+struct Ctl {
+    int64_t count[8];   // rows per class
+    int64_t cursor[8];  // scatter cursors
+    int64_t nnz;        // nnz(C)
+    int64_t nprod;      // total products
+    int64_t err;        // error bits set by kernels
+    int64_t pad[5];
+};
+
+enum CtlErr : int64_t {
+    kErrRptA = 1, kErrColA = 2, kErrRptB = 4, kErrColB = 8,
+    kErrSizeMismatch = 16,  // numeric row length differs from the symbolic count
+    kErrHeavyCapacity = 32
+};
+
+// Row-pointer types are dispatched at run time: 4 or 8 bytes.
+struct CsrView {
+    int64_t rows, cols, nnz;
+    const void *rpt;
+    int rpt_bytes;
+    const int32_t *col;
+    const double *val;
+};
+
+struct Workspace {
+    int64_t *row_nprod;   // [M]
+    uint8_t *row_class;   // [M]
+    int32_t *row_size;    // [M]
+    int32_t *class_rows;  // [M], grouped by class
+    int64_t *tile_sum;    // [ntiles]
+    Ctl *ctl;
+};
+
+constexpr int kScanTile = 4096;  // rows per scan tile (256 threads x 16)
+
+// ---- launchers (brm_kernels.hip) -----------------------------------------
+hipError_t launch_zero_ctl(Ctl *ctl, hipStream_t s);
+hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rpt, int64_t err_col,
+                           Ctl *ctl, hipStream_t s);
+hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds &th,
+                           const Workspace &ws, int grid, hipStream_t s);
+hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s);
+hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
+                           int grid, hipStream_t s);
+hipError_t launch_scan(int64_t M, const Workspace &ws, int64_t *c_rpt, hipStream_t s);
+hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
+                          int64_t rows_in_class, int grid, const int64_t *c_rpt, int32_t *c_col,
+                          double *c_val, hipStream_t s);
+
+// Heavy rows: one workgroup per row, spill buffers in `spill`.
+struct HeavyArgs {
+    const int32_t *rows;      // heavy row ids of this batch
+    const int64_t *spill_off; // element offset of each row's spill region (2 buffers of nprod)
+    int64_t nrows;
+    int32_t *spill_col;
+    double *spill_val;
+    int64_t *spill_leaf;      // leaf offsets, offset by the row's A start... see kernel
+    int lds_max;              // largest leaf range merged in LDS
+};
+hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Workspace &ws,
+                                const HeavyArgs &h, int grid, const int64_t *c_rpt, int32_t *c_col,
+                                double *c_val, hipStream_t s);
+
+}  // namespace brm

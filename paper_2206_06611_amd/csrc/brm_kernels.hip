@@ -1,0 +1,824 @@
+// Kernels of the row-wise SpGEMM C = A*B with the BRMerge accumulation
+// (Section III-B, Algorithm 1) and the precise allocation (Section II-B.2,
+// Section III-D.2), written for CDNA4 (gfx950, 64-lane wavefronts, 160 KB of
+// LDS per workgroup).
+//
+//   analysis  : per row the number of stored A entries (= lists) and of
+//               products (Section III-D.2 step 1); the row's kernel class.
+//   bin       : counting-sort of row ids by class (replaces the static split
+//               of rows into equal-product groups, Section III-D).
+//   symbolic  : exact distinct-column count per row (step 3), by hashing in
+//               LDS (the paper's symbolic method) or, for heavy rows, by an
+//               LDS bitmap over column slabs.
+//   scan      : exclusive prefix sum of the counts into C's int64 row
+//               pointers and nnz(C) (step 4).
+//   numeric   : multiplying phase (scaled B rows appended in the order of
+//               A's entries, coalesced) and accumulating phase (rounds of
+//               pairwise merges, ping-pong between two LDS buffers), written
+//               straight into C (step 5 and Algorithm 1's final store).
+//
+// The merge of two sorted lists inside a round is parallel: every element
+// finds its place in the merged list by a binary search in its sibling list
+// (a merge-path rank), duplicates are detected in the same search and
+// removed with a team-wide prefix count built from wavefront ballots.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "brm_device.h"
+#include "brm_internal.h"
+
+namespace brm {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename I>
+__device__ __forceinline__ int64_t ld_rpt(const void *p, int64_t i) {
+    return (int64_t)(reinterpret_cast<const I *>(p)[i]);
+}
+
+__device__ __forceinline__ int classify(int64_t nlists, int64_t nprod, const Thresholds &th) {
+    if (nprod == 0) return kClassEmpty;
+    const int64_t w = nprod > nlists ? nprod : nlists;  // LDS holds both products and lists
+    if (th.force >= kClassWaveSmall) {
+        // debug routing: every non-empty row that fits the forced class goes
+        // there (single-list rows included), every other row to the heavy path
+        const int64_t cap = th.force == kClassWaveSmall ? kCapWaveSmall
+                            : th.force == kClassWave    ? kCapWave
+                            : th.force == kClassGroup   ? kCapGroup
+                            : th.force == kClassBlock   ? kCapBlock
+                                                        : 0;
+        return w <= cap ? th.force : kClassHeavy;
+    }
+    if (nlists == 1) return kClassCopy;
+    if (w <= th.wave_small_max) return kClassWaveSmall;
+    if (w <= th.wave_max) return kClassWave;
+    if (w <= th.group_max) return kClassGroup;
+    if (w <= th.block_max) return kClassBlock;
+    return kClassHeavy;
+}
+
+// ---------------------------------------------------------------------------
+// control block reset
+// ---------------------------------------------------------------------------
+__global__ void k_zero_ctl(Ctl *ctl) {
+    int64_t *p = reinterpret_cast<int64_t *>(ctl);
+    const int n = (int)(sizeof(Ctl) / sizeof(int64_t));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero_ctl(Ctl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, s, ctl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// validation (optional): rpt[0] == 0, monotone, rpt[rows] == nnz, columns in
+// range and strictly increasing within rows
+// ---------------------------------------------------------------------------
+template <typename I>
+__global__ void k_validate(int64_t rows, int64_t nnz, const void *rpt, const int32_t *col,
+                           int64_t ncols, int64_t err_rpt, int64_t err_col, Ctl *ctl) {
+    int64_t bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += stride) {
+        const int64_t a = ld_rpt<I>(rpt, i), b = ld_rpt<I>(rpt, i + 1);
+        if ((i == 0 && a != 0) || b < a || (i == rows - 1 && b != nnz) || a < 0 || b > nnz) {
+            bad |= err_rpt;
+            continue;
+        }
+        int32_t prev = -1;
+        for (int64_t p = a; p < b; ++p) {
+            const int32_t c = col[p];
+            if (c < 0 || (int64_t)c >= ncols || c <= prev) {
+                bad |= err_col;
+                break;
+            }
+            prev = c;
+        }
+    }
+    if (rows == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ld_rpt<I>(rpt, 0) != 0 || nnz != 0) bad |= err_rpt;
+    }
+    if (bad) atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)bad);
+}
+
+hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rpt, int64_t err_col,
+                           Ctl *ctl, hipStream_t s) {
+    int64_t blocks = (X.rows + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    if (X.rpt_bytes == 4)
+        hipLaunchKernelGGL(k_validate<int32_t>, dim3((unsigned)blocks), dim3(256), 0, s, X.rows,
+                           X.nnz, X.rpt, X.col, ncols_limit, err_rpt, err_col, ctl);
+    else
+        hipLaunchKernelGGL(k_validate<int64_t>, dim3((unsigned)blocks), dim3(256), 0, s, X.rows,
+                           X.nnz, X.rpt, X.col, ncols_limit, err_rpt, err_col, ctl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// analysis: lists, products and class of every row
+// ---------------------------------------------------------------------------
+constexpr int kAnalysisThreads = 256;
+constexpr int kShortRow = 32;  // rows with more A entries are summed by the whole wavefront
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
+    int64_t M, const void *a_rpt, const int32_t *a_col, const void *b_rpt, Thresholds th,
+    int64_t *row_nprod, uint8_t *row_class, int32_t *row_size, Ctl *ctl) {
+    __shared__ int64_t s_count[kNumClasses];
+    __shared__ int64_t s_nprod;
+    if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_nprod = 0;
+    __syncthreads();
+
+    int64_t my_count[kNumClasses];
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
+    int64_t my_nprod = 0;
+
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every wavefront walks the same number of iterations so that the
+    // cooperative part below sees all 64 lanes
+    const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
+    for (int64_t base = base0; base < M; base += stride) {
+        const int64_t i = base + lane;
+        const bool in = i < M;
+        int64_t a0 = 0, a1 = 0, np = 0;
+        if (in) {
+            a0 = ld_rpt<IA>(a_rpt, i);
+            a1 = ld_rpt<IA>(a_rpt, i + 1);
+        }
+        const bool longrow = in && (a1 - a0) > kShortRow;
+        if (in && !longrow) {
+            for (int64_t p = a0; p < a1; ++p) {
+                const int32_t k = a_col[p];
+                np += ld_rpt<IB>(b_rpt, k + 1) - ld_rpt<IB>(b_rpt, k);
+            }
+        }
+        uint64_t lm = wave_ballot(longrow);
+        while (lm) {
+            const int src = __builtin_ctzll(lm);
+            const int64_t r0 = __shfl(a0, src, kWave), r1 = __shfl(a1, src, kWave);
+            int64_t part = 0;
+            for (int64_t p = r0 + lane; p < r1; p += kWave) {
+                const int32_t k = a_col[p];
+                part += ld_rpt<IB>(b_rpt, k + 1) - ld_rpt<IB>(b_rpt, k);
+            }
+            part = wave_sum(part);
+            if (lane == src) np = part;
+            lm &= lm - 1;
+        }
+        if (in) {
+            const int cls = classify(a1 - a0, np, th);
+            row_nprod[i] = np;
+            row_class[i] = (uint8_t)cls;
+            if (cls == kClassEmpty) row_size[i] = 0;
+            if (cls == kClassCopy) row_size[i] = (int32_t)np;
+#pragma unroll
+            for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
+            my_nprod += np;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) {
+        const int64_t t = wave_sum(my_count[c]);
+        if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long *>(&s_count[c]),
+                                      (unsigned long long)t);
+    }
+    {
+        const int64_t t = wave_sum(my_nprod);
+        if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long *>(&s_nprod),
+                                      (unsigned long long)t);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses && s_count[threadIdx.x])
+        atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->count[threadIdx.x]),
+                  (unsigned long long)s_count[threadIdx.x]);
+    if (threadIdx.x == 0 && s_nprod)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->nprod), (unsigned long long)s_nprod);
+}
+
+hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds &th,
+                           const Workspace &ws, int grid, hipStream_t s) {
+    const dim3 g(grid), b(kAnalysisThreads);
+#define BRM_ANALYSIS(IA, IB)                                                                 \
+    hipLaunchKernelGGL((k_analysis<IA, IB>), g, b, 0, s, A.rows, A.rpt, A.col, B.rpt, th,   \
+                       ws.row_nprod, ws.row_class, ws.row_size, ws.ctl)
+    if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_ANALYSIS(int32_t, int32_t);
+    else if (A.rpt_bytes == 4) BRM_ANALYSIS(int32_t, int64_t);
+    else if (B.rpt_bytes == 4) BRM_ANALYSIS(int64_t, int32_t);
+    else BRM_ANALYSIS(int64_t, int64_t);
+#undef BRM_ANALYSIS
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// binning: row ids grouped by class (order inside a class is unspecified)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t class_start(const Ctl *ctl, int cls) {
+    int64_t s = 0;
+    for (int c = 0; c < cls; ++c) s += ctl->count[c];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_bin(int64_t M, const uint8_t *row_class,
+                                             int32_t *class_rows, Ctl *ctl) {
+    __shared__ int64_t s_base[kNumClasses];
+    __shared__ int s_wave_cnt[kNumClasses];
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // pass 1: this block's rows per class, one global reservation per class
+    int64_t my_count[kNumClasses];
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += stride) {
+        const int cls = row_class[i];
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
+    }
+    if (threadIdx.x < kNumClasses) s_wave_cnt[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) {
+        const int64_t t = wave_sum(my_count[c]);
+        if (lane == 0 && t) atomicAdd(&s_wave_cnt[c], (int)t);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses) {
+        const int c = threadIdx.x;
+        const int n = s_wave_cnt[c];
+        s_base[c] = class_start(ctl, c) +
+                    (n ? (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->cursor[c]),
+                                            (unsigned long long)n)
+                       : 0);
+        s_wave_cnt[c] = 0;
+    }
+    __syncthreads();
+    // pass 2: scatter; wavefront-aggregated LDS cursors
+    const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
+    for (int64_t base = base0; base < M; base += stride) {
+        const int64_t i = base + lane;
+        const int cls = i < M ? (int)row_class[i] : -1;
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) {
+            const uint64_t m = wave_ballot(cls == c);
+            if (!m) continue;
+            int wbase = 0;
+            if (lane == __builtin_ctzll(m)) wbase = atomicAdd(&s_wave_cnt[c], __popcll(m));
+            wbase = __shfl(wbase, __builtin_ctzll(m), kWave);
+            if (cls == c) class_rows[s_base[c] + wbase + lanes_below(m)] = (int32_t)i;
+        }
+    }
+}
+
+hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin, dim3(grid), dim3(256), 0, s, M, ws.row_class, ws.class_rows, ws.ctl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gathering the products of one row, chunk of T lists at a time.  For every
+// product the callback receives (position in the row, B entry index, list).
+// ---------------------------------------------------------------------------
+template <int T>
+struct ListStage {
+    int64_t bs[T];    // B row start of each list of the chunk
+    int32_t off[T];   // offset of each list inside the chunk
+    int32_t scan[Team<T>::kWaves + 1];
+};
+
+template <int T, typename IA, typename IB, typename F>
+__device__ __forceinline__ int64_t for_each_product(ListStage<T> &st, int tid, int64_t a0,
+                                                    int64_t L, const int32_t *a_col,
+                                                    const void *b_rpt, F &&f) {
+    int64_t carry = 0;
+    for (int64_t lb = 0; lb < L; lb += T) {
+        const int64_t l = lb + tid;
+        int ln = 0;
+        int64_t bs = 0;
+        if (l < L) {
+            const int32_t k = a_col[a0 + l];
+            bs = ld_rpt<IB>(b_rpt, k);
+            ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
+        }
+        int tot;
+        const int ex = Team<T>::excl_scan(ln, &tot, st.scan, tid);
+        st.bs[tid] = bs;
+        st.off[tid] = ex;
+        const int nl = (int)((L - lb) < T ? (L - lb) : T);
+        Team<T>::sync();
+        for (int q = tid; q < tot; q += T) {
+            const int t = upper_bound(st.off, nl, q) - 1;
+            f(carry + q, st.bs[t] + (q - st.off[t]), (int)(lb + t));
+        }
+        carry += tot;
+        Team<T>::sync();
+    }
+    return carry;
+}
+
+// ---------------------------------------------------------------------------
+// symbolic, LDS hash table (open addressing, linear probing, load <= 1/2)
+// ---------------------------------------------------------------------------
+template <int TS>
+__device__ __forceinline__ int hash_insert(int32_t *tab, int32_t c) {
+    constexpr int kBits = __builtin_ctz(TS);
+    uint32_t h = ((uint32_t)c * 2654435761u) >> (32 - kBits);
+    while (true) {
+        const int32_t old = atomicCAS(&tab[h], -1, c);
+        if (old == -1) return 1;
+        if (old == c) return 0;
+        h = (h + 1) & (TS - 1);
+    }
+}
+
+template <int T, int TS>
+struct SymLds {
+    int32_t tab[TS];
+    ListStage<T> st;
+    int32_t red[Team<T>::kWaves + 1];
+};
+
+template <int T, int TEAMS, int TS, typename IA, typename IB>
+__global__ __launch_bounds__(T *TEAMS) void k_sym_hash(
+    int cls, const void *a_rpt, const int32_t *a_col, const void *b_rpt, const int32_t *b_col,
+    const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
+    __shared__ SymLds<T, TS> lds[TEAMS];
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    SymLds<T, TS> &s = lds[team];
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count;
+         idx += (int64_t)gridDim.x * TEAMS) {
+        const int64_t row = class_rows[start + idx];
+        for (int t = tid; t < TS; t += T) s.tab[t] = -1;
+        Team<T>::sync();
+        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+        const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
+        int added = 0;
+        for_each_product<T, IA, IB>(s.st, tid, a0, L, a_col, b_rpt,
+                                    [&](int64_t, int64_t q, int) { added += hash_insert<TS>(s.tab, b_col[q]); });
+        const int total = Team<T>::sum(added, s.red, tid);
+        if (tid == 0) row_size[row] = total;
+        Team<T>::sync();
+    }
+}
+
+// symbolic for heavy rows: LDS bitmap over column slabs of kBitmapBits
+constexpr int kBitmapWords = 32768;  // 128 KB
+constexpr int64_t kBitmapBits = (int64_t)kBitmapWords * 32;
+constexpr int kHeavyThreads = 1024;
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
+    int cls, int64_t ncols, const void *a_rpt, const int32_t *a_col, const void *b_rpt,
+    const int32_t *b_col, const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
+    __shared__ uint32_t bm[kBitmapWords];
+    __shared__ ListStage<kHeavyThreads> st;
+    __shared__ int64_t red[Team<kHeavyThreads>::kWaves + 1];
+    const int tid = threadIdx.x;
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int64_t row = class_rows[start + idx];
+        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+        const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
+        int64_t total = 0;
+        for (int64_t lo = 0; lo < ncols; lo += kBitmapBits) {
+            for (int w = tid; w < kBitmapWords; w += kHeavyThreads) bm[w] = 0u;
+            __syncthreads();
+            for_each_product<kHeavyThreads, IA, IB>(st, tid, a0, L, a_col, b_rpt,
+                                                    [&](int64_t, int64_t q, int) {
+                                                        const int64_t c = (int64_t)b_col[q] - lo;
+                                                        if (c >= 0 && c < kBitmapBits)
+                                                            atomicOr(&bm[c >> 5], 1u << (c & 31));
+                                                    });
+            int64_t cnt = 0;
+            for (int w = tid; w < kBitmapWords; w += kHeavyThreads) cnt += __popc(bm[w]);
+            total += Team<kHeavyThreads>::sum(cnt, red, tid);
+        }
+        if (tid == 0) row_size[row] = (int32_t)total;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
+                           int grid, hipStream_t s) {
+#define BRM_SYM(KERNEL, BLOCK, IA, IB)                                                        \
+    hipLaunchKernelGGL((KERNEL), dim3(grid), dim3(BLOCK), 0, s, cls, A.rpt, A.col, B.rpt,    \
+                       B.col, ws.class_rows, ws.row_size, ws.ctl)
+#define BRM_SYM_ALL(T, TEAMS, TS)                                                             \
+    do {                                                                                      \
+        if (A.rpt_bytes == 4 && B.rpt_bytes == 4)                                             \
+            BRM_SYM((k_sym_hash<T, TEAMS, TS, int32_t, int32_t>), T *TEAMS, int32_t, int32_t); \
+        else if (A.rpt_bytes == 4)                                                            \
+            BRM_SYM((k_sym_hash<T, TEAMS, TS, int32_t, int64_t>), T *TEAMS, int32_t, int64_t); \
+        else if (B.rpt_bytes == 4)                                                            \
+            BRM_SYM((k_sym_hash<T, TEAMS, TS, int64_t, int32_t>), T *TEAMS, int64_t, int32_t); \
+        else                                                                                  \
+            BRM_SYM((k_sym_hash<T, TEAMS, TS, int64_t, int64_t>), T *TEAMS, int64_t, int64_t); \
+    } while (0)
+    switch (cls) {
+        case kClassWaveSmall: BRM_SYM_ALL(64, 4, 2 * kCapWaveSmall); break;
+        case kClassWave: BRM_SYM_ALL(64, 4, 2 * kCapWave); break;
+        case kClassGroup: BRM_SYM_ALL(256, 1, 2 * kCapGroup); break;
+        case kClassBlock: BRM_SYM_ALL(1024, 1, 2 * kCapBlock); break;
+        case kClassHeavy: {
+#define BRM_BM(IA, IB)                                                                         \
+    hipLaunchKernelGGL((k_sym_bitmap<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, cls,     \
+                       B.cols, A.rpt, A.col, B.rpt, B.col, ws.class_rows, ws.row_size, ws.ctl)
+            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_BM(int32_t, int32_t);
+            else if (A.rpt_bytes == 4) BRM_BM(int32_t, int64_t);
+            else if (B.rpt_bytes == 4) BRM_BM(int64_t, int32_t);
+            else BRM_BM(int64_t, int64_t);
+#undef BRM_BM
+            break;
+        }
+        default: return hipErrorInvalidValue;
+    }
+#undef BRM_SYM_ALL
+#undef BRM_SYM
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scan: row sizes (int32) -> C's row pointers (int64) and nnz(C)
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = kScanTile / kScanThreads;  // 16 rows per thread
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t M, const int32_t *row_size,
+                                                              int64_t *tile_sum) {
+    __shared__ int64_t red[Team<kScanThreads>::kWaves + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j)
+        if (base + j < M) s += row_size[base + j];
+    s = Team<kScanThreads>::sum(s, red, threadIdx.x);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t ntiles, int64_t *tile_sum, int64_t M,
+                                                   int64_t *c_rpt, Ctl *ctl) {
+    __shared__ int64_t scr[Team<1024>::kWaves + 1];
+    int64_t carry = 0;
+    for (int64_t b = 0; b < ntiles; b += 1024) {
+        const int64_t i = b + threadIdx.x;
+        const int64_t v = i < ntiles ? tile_sum[i] : 0;
+        int64_t tot;
+        const int64_t ex = Team<1024>::excl_scan(v, &tot, scr, threadIdx.x);
+        if (i < ntiles) tile_sum[i] = carry + ex;  // in place: exclusive tile offsets
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        ctl->nnz = carry;
+        c_rpt[M] = carry;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t M, const int32_t *row_size,
+                                                             const int64_t *tile_off,
+                                                             int64_t *c_rpt) {
+    __shared__ int64_t scr[Team<kScanThreads>::kWaves + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = base + j < M ? row_size[base + j] : 0;
+        s += v[j];
+    }
+    int64_t tot;
+    int64_t run = tile_off[blockIdx.x] + Team<kScanThreads>::excl_scan(s, &tot, scr, threadIdx.x);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        if (base + j < M) c_rpt[base + j] = run;
+        run += v[j];
+    }
+}
+
+hipError_t launch_scan(int64_t M, const Workspace &ws, int64_t *c_rpt, hipStream_t s) {
+    const int64_t ntiles = (M + kScanTile - 1) / kScanTile;
+    if (ntiles > 0)
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M,
+                           ws.row_size, ws.tile_sum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ntiles, ws.tile_sum, M, c_rpt, ws.ctl);
+    if (ntiles > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M,
+                           ws.row_size, ws.tile_sum, c_rpt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// numeric, single list: the result row is the scaled B row (wave per row)
+// ---------------------------------------------------------------------------
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, const int32_t *a_col,
+                                                  const double *a_val, const void *b_rpt,
+                                                  const int32_t *b_col, const double *b_val,
+                                                  const int32_t *class_rows, const int64_t *c_rpt,
+                                                  int32_t *c_col, double *c_val, Ctl *ctl) {
+    const int lane = lane_id();
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; idx < count;
+         idx += waves) {
+        const int64_t row = class_rows[start + idx];
+        const int64_t p = ld_rpt<IA>(a_rpt, row);
+        const int32_t k = a_col[p];
+        const double a = a_val[p];
+        const int64_t bs = ld_rpt<IB>(b_rpt, k);
+        const int64_t n = ld_rpt<IB>(b_rpt, k + 1) - bs;
+        const int64_t cs = c_rpt[row];
+        const int64_t cap = c_rpt[row + 1] - cs;
+        if (n != cap && lane == 0)
+            atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+        const int64_t m = n < cap ? n : cap;
+        for (int64_t j = lane; j < m; j += kWave) {
+            c_col[cs + j] = b_col[bs + j];
+            c_val[cs + j] = a * b_val[bs + j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric, one row in LDS (a team of T threads, CAP products at most)
+// ---------------------------------------------------------------------------
+template <int T, int CAP>
+struct NumLds {
+    static constexpr int kE = CAP / T;                     // positions per thread
+    static constexpr int kSlots = kE * Team<T>::kWaves;    // (slice, wave) counters
+    int32_t col[2][CAP + 1];
+    double val[2][CAP + 1];
+    int32_t off[CAP + 1];  // start of every list (leaf) in the buffers; off[L] = nprod
+    int32_t len[CAP];      // current length of a node, stored at its first leaf
+    int32_t scan[(kSlots > Team<T>::kWaves ? kSlots : Team<T>::kWaves) + 1];
+};
+
+// Exclusive count of `flag` over the positions p = tid + e*T in increasing p.
+// Writes the count before every position p < n into x[p] and the total into x[n].
+template <int T, int CAP>
+__device__ __forceinline__ void team_flag_scan(NumLds<T, CAP> &s, int tid, const bool (&flag)[CAP / T],
+                                               int n, int32_t *x) {
+    constexpr int E = CAP / T;
+    constexpr int W = Team<T>::kWaves;
+    uint64_t m[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) m[e] = wave_ballot(flag[e]);
+    if constexpr (T == kWave) {
+        int run = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = tid + e * T;
+            if (p < n) x[p] = run + lanes_below(m[e]);
+            run += __popcll(m[e]);
+        }
+        if (tid == 0) x[n] = run;
+    } else {
+        const int w = tid / kWave;
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) s.scan[e * W + w] = __popcll(m[e]);
+        }
+        __syncthreads();
+        if (tid < kWave) {
+            // E*W <= 64 slots: one wavefront scans them
+            const int v = tid < E * W ? s.scan[tid] : 0;
+            const int incl = wave_incl_scan(v);
+            if (tid < E * W) s.scan[tid] = incl - v;
+            if (tid == kWave - 1) s.scan[E * W] = incl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = tid + e * T;
+            if (p < n) x[p] = s.scan[e * W + w] + lanes_below(m[e]);
+        }
+        if (tid == 0) x[n] = s.scan[E * W];
+    }
+}
+
+template <int T, int CAP, typename IA, typename IB>
+__device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int64_t row,
+                                                const void *a_rpt, const int32_t *a_col,
+                                                const double *a_val, const void *b_rpt,
+                                                const int32_t *b_col, const double *b_val,
+                                                const int64_t *c_rpt, int32_t *c_col,
+                                                double *c_val, Ctl *ctl) {
+    constexpr int E = CAP / T;
+    static_assert(E * Team<T>::kWaves <= 64, "flag scan assumes at most 64 (slice, wave) slots");
+    const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+    const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
+
+    // list offsets; B row start and A value of every list staged in the
+    // second buffer (free until the first round)
+    int carry = 0;
+    for (int lb = 0; lb < L; lb += T) {
+        const int l = lb + tid;
+        int ln = 0;
+        int64_t bs = 0;
+        double av = 0.0;
+        if (l < L) {
+            const int32_t k = a_col[a0 + l];
+            av = a_val[a0 + l];
+            bs = ld_rpt<IB>(b_rpt, k);
+            ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
+        }
+        int tot;
+        const int ex = Team<T>::excl_scan(ln, &tot, s.scan, tid);
+        if (l < L) {
+            s.off[l] = carry + ex;
+            s.col[1][l] = (int32_t)(uint32_t)(uint64_t)bs;
+            s.len[l] = (int32_t)(bs >> 32);
+            s.val[1][l] = av;
+        }
+        carry += tot;
+    }
+    const int nprod = carry;
+    if (tid == 0) s.off[L] = nprod;
+    Team<T>::sync();
+
+    // multiplying phase: position p of the row holds A_ik * B_kj of list
+    // (leaf) leaf[e]; consecutive positions read consecutive B entries
+    int leaf[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = tid + e * T;
+        leaf[e] = 0;
+        if (p < nprod) {
+            const int lf = upper_bound(s.off, L + 1, p) - 1;
+            leaf[e] = lf;
+            const int64_t bs = ((int64_t)s.len[lf] << 32) | (int64_t)(uint32_t)s.col[1][lf];
+            const int64_t q = bs + (p - s.off[lf]);
+            s.col[0][p] = b_col[q];
+            s.val[0][p] = s.val[1][lf] * b_val[q];
+        }
+    }
+    Team<T>::sync();
+    for (int l = tid; l < L; l += T) s.len[l] = s.off[l + 1] - s.off[l];
+    Team<T>::sync();
+
+    // accumulating phase: round sh merges the nodes of level sh pairwise
+    int cur = 0;
+    for (int sh = 0; (1 << sh) < L; ++sh) {
+        const int nxt = cur ^ 1;
+        const int32_t *sc = s.col[cur];
+        const double *sv = s.val[cur];
+        int32_t *dc = s.col[nxt];
+        double *dv = s.val[nxt];
+        int32_t c[E];
+        double v[E];
+        int k[E], i[E], st[E], sst[E], ln[E], sln[E], node[E];
+        bool valid[E], dup[E], sib[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = tid + e * T;
+            valid[e] = false;
+            dup[e] = false;
+            sib[e] = false;
+            k[e] = 0;
+            c[e] = 0;
+            v[e] = 0.0;
+            node[e] = leaf[e] >> sh;
+            const int fl = node[e] << sh;
+            st[e] = s.off[fl];
+            ln[e] = s.len[fl];
+            i[e] = p - st[e];
+            sst[e] = 0;
+            sln[e] = 0;
+            if (p < nprod && i[e] < ln[e]) {
+                valid[e] = true;
+                c[e] = sc[p];
+                v[e] = sv[p];
+                const int sfl = (node[e] ^ 1) << sh;
+                if (sfl < L) {
+                    sib[e] = true;
+                    sst[e] = s.off[sfl];
+                    sln[e] = s.len[sfl];
+                    if ((node[e] & 1) == 0) {
+                        k[e] = lower_bound(sc + sst[e], sln[e], c[e]);
+                        if (k[e] < sln[e] && sc[sst[e] + k[e]] == c[e]) v[e] = v[e] + sv[sst[e] + k[e]];
+                    } else {
+                        k[e] = upper_bound(sc + sst[e], sln[e], c[e]);
+                        dup[e] = k[e] > 0 && sc[sst[e] + k[e] - 1] == c[e];
+                    }
+                }
+            }
+        }
+        // dup counts over positions, kept in the destination column buffer
+        team_flag_scan<T, CAP>(s, tid, dup, nprod, dc);
+        Team<T>::sync();
+        int dest[E], newlen[E], newlen_at[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            dest[e] = -1;
+            newlen[e] = -1;
+            newlen_at[e] = 0;
+            if (valid[e] && !dup[e]) {
+                int pos;
+                if (!sib[e]) {
+                    pos = i[e];
+                } else if ((node[e] & 1) == 0) {
+                    pos = i[e] + k[e] - (dc[sst[e] + k[e]] - dc[sst[e]]);
+                } else {
+                    const int p = tid + e * T;
+                    pos = i[e] + k[e] - (dc[p] - dc[st[e]]);
+                }
+                const int pfl = (node[e] >> 1) << (sh + 1);
+                dest[e] = s.off[pfl] + pos;
+            }
+            if (valid[e] && sib[e] && (node[e] & 1) && i[e] == 0) {
+                // first element of a right list: the parent's length
+                newlen[e] = sln[e] + ln[e] - (dc[st[e] + ln[e]] - dc[st[e]]);
+                newlen_at[e] = (node[e] ^ 1) << sh;
+            }
+        }
+        Team<T>::sync();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (dest[e] >= 0) {
+                dc[dest[e]] = c[e];
+                dv[dest[e]] = v[e];
+            }
+            if (newlen[e] >= 0) s.len[newlen_at[e]] = newlen[e];
+        }
+        Team<T>::sync();
+        cur = nxt;
+    }
+
+    // Algorithm 1's final store: the single list left goes to C's row
+    const int rl = s.len[0];
+    const int64_t cs = c_rpt[row];
+    const int64_t cap = c_rpt[row + 1] - cs;
+    if (tid == 0 && (int64_t)rl != cap)
+        atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+    const int m = (int64_t)rl < cap ? rl : (int)cap;
+    for (int p = tid; p < m; p += T) {
+        c_col[cs + p] = s.col[cur][p];
+        c_val[cs + p] = s.val[cur][p];
+    }
+    Team<T>::sync();
+}
+
+template <int T, int TEAMS, int CAP, typename IA, typename IB>
+__global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt,
+                                                      const int32_t *a_col, const double *a_val,
+                                                      const void *b_rpt, const int32_t *b_col,
+                                                      const double *b_val,
+                                                      const int32_t *class_rows,
+                                                      const int64_t *c_rpt, int32_t *c_col,
+                                                      double *c_val, Ctl *ctl) {
+    __shared__ NumLds<T, CAP> lds[TEAMS];
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count;
+         idx += (int64_t)gridDim.x * TEAMS) {
+        const int64_t row = class_rows[start + idx];
+        brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, row, a_rpt, a_col, a_val, b_rpt, b_col,
+                                        b_val, c_rpt, c_col, c_val, ctl);
+    }
+}
+
+hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
+                          int64_t rows_in_class, int grid, const int64_t *c_rpt, int32_t *c_col,
+                          double *c_val, hipStream_t s) {
+    (void)rows_in_class;
+#define BRM_NUM(KERNEL, BLOCK)                                                                   \
+    hipLaunchKernelGGL((KERNEL), dim3(grid), dim3(BLOCK), 0, s, cls, A.rpt, A.col, A.val, B.rpt, \
+                       B.col, B.val, ws.class_rows, c_rpt, c_col, c_val, ws.ctl)
+#define BRM_NUM_ALL(T, TEAMS, CAP)                                                               \
+    do {                                                                                         \
+        if (A.rpt_bytes == 4 && B.rpt_bytes == 4)                                                \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int32_t, int32_t>), T *TEAMS);                     \
+        else if (A.rpt_bytes == 4)                                                               \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int32_t, int64_t>), T *TEAMS);                     \
+        else if (B.rpt_bytes == 4)                                                               \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int64_t, int32_t>), T *TEAMS);                     \
+        else                                                                                     \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int64_t, int64_t>), T *TEAMS);                     \
+    } while (0)
+    switch (cls) {
+        case kClassCopy:
+            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM((k_num_copy<int32_t, int32_t>), 256);
+            else if (A.rpt_bytes == 4) BRM_NUM((k_num_copy<int32_t, int64_t>), 256);
+            else if (B.rpt_bytes == 4) BRM_NUM((k_num_copy<int64_t, int32_t>), 256);
+            else BRM_NUM((k_num_copy<int64_t, int64_t>), 256);
+            break;
+        case kClassWaveSmall: BRM_NUM_ALL(64, 4, kCapWaveSmall); break;
+        case kClassWave: BRM_NUM_ALL(64, 4, kCapWave); break;
+        case kClassGroup: BRM_NUM_ALL(256, 1, kCapGroup); break;
+        case kClassBlock: BRM_NUM_ALL(1024, 1, kCapBlock); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef BRM_NUM_ALL
+#undef BRM_NUM
+    return hipGetLastError();
+}
+
+}  // namespace brm

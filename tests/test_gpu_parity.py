@@ -1,0 +1,185 @@
+"""GPU parity of the plain two-pass path against the CPU oracle.
+
+Every case compares, through the C ABI, C's row pointers and columns
+bit-exactly with the oracle's definition and the values within
+1e-12 * sum|products| per entry; where noted also bitwise with the CPU run of
+Algorithm 1 (same merge tree).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_matches_oracle, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2206_06611_amd as brm  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def handle():
+    h = brm.Handle(0)
+    h.set_option(brm.OPT_VALIDATE, 1)
+    yield h
+    h.close()
+
+
+def run(h, A, B, rpt_dtype=None):
+    dA = brm.DeviceCSR.from_host(A, rpt_dtype=rpt_dtype)
+    dB = dA if B is A else brm.DeviceCSR.from_host(B, rpt_dtype=rpt_dtype)
+    C = h.spgemm(dA, dB)
+    torch.cuda.synchronize()
+    assert h.stat(brm.STAT_DEVICE_ERR) == 0
+    return C
+
+
+def test_config1_laplacian_exact(handle):
+    print("case: 64x64 5-point Laplacian squared", flush=True)
+    A = synth.laplacian_2d_5pt(64)
+    C = run(handle, A, A)
+    ref = oracle.spgemm(A, A)
+    rpt, col, val = to_host(C)
+    assert C.nnz == 51972
+    assert np.array_equal(rpt, ref.rpt) and np.array_equal(col, ref.col)
+    assert np.array_equal(val, ref.val)  # integer values: exact
+    assert handle.stat(brm.STAT_NPROD) == 100104
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small(handle, seed):
+    rng = np.random.default_rng(seed)
+    M, K, N = (int(x) for x in rng.integers(1, 300, size=3))
+    dens = float(rng.uniform(0.001, 0.08))
+    print(f"case: random seed={seed} M={M} K={K} N={N} density={dens:.4f}", flush=True)
+    A = synth.random_csr(M, K, dens, seed, empty_row_frac=0.1)
+    B = synth.random_csr(K, N, dens * 2, seed + 1000, empty_row_frac=0.1)
+    C = run(handle, A, B)
+    assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+
+
+@pytest.mark.parametrize("force", [2, 3, 4, 5])
+def test_forced_classes_bitwise(handle, force):
+    # rows of every size routed to one kernel class must give identical bits
+    A = synth.random_csr(300, 200, 0.02, 7, empty_row_frac=0.1)
+    B = synth.random_csr(200, 400, 0.02, 8, empty_row_frac=0.1)
+    # keep only rows that fit the smallest class (64 products and lists)
+    w = np.maximum(oracle.row_nprod(A, B), np.diff(A.rpt))
+    d = A.to_dense()
+    pat = A.to_dense() != 0
+    pat[w > 64] = False
+    A = synth.from_dense(np.where(pat, d, 0.0), pat)
+    base = to_host(run(handle, A, B))
+    handle.set_option(brm.OPT_FORCE_CLASS, force)
+    try:
+        C = to_host(run(handle, A, B))
+        assert handle.stat(brm.STAT_CLASS_ROWS0 + force) > 0
+    finally:
+        handle.set_option(brm.OPT_FORCE_CLASS, -1)
+    for x, y in zip(base, C):
+        assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                              y.view(np.int64) if y.dtype == np.float64 else y)
+
+
+def test_row_classes_all_used(handle):
+    # rows spanning single lists, <=64, <=256, <=1024, <=4096 products
+    rng = np.random.default_rng(3)
+    K, N = 400, 6000
+    lens = np.concatenate([np.zeros(5, int), np.ones(10, int), rng.integers(2, 6, 30),
+                           rng.integers(8, 20, 30), rng.integers(40, 80, 20), rng.integers(100, 180, 10)])
+    rows = []
+    for i, l in enumerate(lens):
+        rows.append(np.sort(rng.choice(K, size=min(l, K), replace=False)))
+    rpt = np.zeros(len(rows) + 1, np.int64)
+    rpt[1:] = np.cumsum([len(r) for r in rows])
+    A = synth.CSR(len(rows), K, rpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                  rng.uniform(-1, 1, rpt[-1]))
+    B = synth.random_csr(K, N, 0.0025, 4)
+    C = run(handle, A, B)
+    cls = handle.class_rows()
+    assert cls["heavy"] == 0
+    assert cls["copy"] > 0 and cls["wave_small"] > 0 and cls["wave"] > 0 and cls["group"] > 0
+    assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+
+
+def test_int64_row_pointers(handle):
+    A = synth.random_csr(150, 90, 0.05, 11)
+    B = synth.random_csr(90, 140, 0.05, 12)
+    C = run(handle, A, B, rpt_dtype=torch.int64)
+    assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+
+
+@pytest.mark.parametrize("shape", [(0, 5, 4), (5, 0, 4), (5, 4, 0), (0, 0, 0), (7, 3, 9)])
+def test_empty_and_degenerate(handle, shape):
+    M, K, N = shape
+    A = synth.random_csr(M, K, 0.0 if shape == (7, 3, 9) else 0.5, 1)
+    B = synth.random_csr(K, N, 0.5, 2)
+    C = run(handle, A, B)
+    assert C.nnz == 0 and C.rpt.numel() == M + 1
+    assert int(C.rpt.abs().sum()) == 0
+
+
+def test_stored_zeros_kept(handle):
+    Ad = np.array([[1.0, 1.0, 0.0], [0.0, 0.0, 2.0]])
+    Apat = np.array([[True, True, True], [False, False, True]])
+    Bd = np.array([[3.0, 1.0], [-3.0, 0.0], [5.0, 0.0]])
+    Bpat = np.array([[True, True], [True, False], [True, False]])
+    A, B = synth.from_dense(Ad, Apat), synth.from_dense(Bd, Bpat)
+    C = run(handle, A, B)
+    assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+
+
+def test_errors(handle):
+    A = synth.random_csr(20, 10, 0.3, 1)
+    B = synth.random_csr(11, 10, 0.3, 2)
+    dA, dB = brm.DeviceCSR.from_host(A), brm.DeviceCSR.from_host(B)
+    with pytest.raises(brm.SpgError) as e:
+        handle.spgemm(dA, dB)
+    assert e.value.code == brm.SPG_ERR_DIM
+    # unsorted columns are caught by validation
+    B = synth.random_csr(10, 10, 0.5, 2)
+    bad = synth.CSR(B.rows, B.cols, B.rpt, B.col[::-1].copy(), B.val)
+    with pytest.raises(brm.SpgError) as e:
+        handle.spgemm(dA, brm.DeviceCSR.from_host(bad))
+    assert e.value.code == brm.SPG_ERR_INVALID_CSR
+    # numeric without symbolic
+    h2 = brm.Handle(0)
+    dB = brm.DeviceCSR.from_host(B)
+    c_rpt = torch.zeros(21, dtype=torch.int64, device="cuda")
+    with pytest.raises(brm.SpgError) as e:
+        h2.numeric(dA, dB, c_rpt, torch.empty(1, dtype=torch.int32, device="cuda"),
+                   torch.empty(1, dtype=torch.float64, device="cuda"))
+    assert e.value.code == brm.SPG_ERR_STATE
+    h2.close()
+
+
+def test_deterministic_repeats(handle):
+    A = synth.erdos_renyi_rows(20000, 8, 5)
+    outs = [to_host(run(handle, A, A)) for _ in range(3)]
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                                  y.view(np.int64) if y.dtype == np.float64 else y)
+
+
+def test_config2_erdos_renyi_full(handle):
+    print("case: ER 2^20 x 2^20, 8 per row, seed 2 (full compare)", flush=True)
+    A = synth.erdos_renyi_rows(1 << 20, 8, 2)
+    C = run(handle, A, A)
+    assert handle.stat(brm.STAT_NPROD) == 8 * A.nnz
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+def test_stencil27_square(handle):
+    n = 24
+    A = synth.stencil_3d_27pt(n)
+    C = run(handle, A, A)
+    assert C.nnz == (5 * n - 6) ** 3
+    ref = oracle.spgemm(A, A)
+    rpt, col, val = to_host(C)
+    assert np.array_equal(rpt, ref.rpt) and np.array_equal(col, ref.col)
+    assert np.array_equal(val, ref.val)
