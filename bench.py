@@ -29,6 +29,7 @@ WORKLOADS = {
     "er8_2e20": "C = A*A, A Erdos-Renyi 2^20 x 2^20, 8 distinct uniform columns per row, U[-1,1], seed 2",
     "laplace2d_64": "C = A*A, A 5-point Laplacian on a 64 x 64 grid (4/-1)",
     "rmat_s20": "C = A*A, A R-MAT scale 20, edge factor 16, (0.57,0.19,0.19,0.05), dedup, U[0,1], seed 3",
+    "rmat_s18": "C = A*A, A R-MAT scale 18, edge factor 16, (0.57,0.19,0.19,0.05), dedup, U[0,1], seed 3",
     "stencil27_128": "C = A*A, A 27-point stencil on a 128^3 cube (26/-1)",
 }
 
@@ -41,6 +42,8 @@ def build_input(name):
         return synth.laplacian_2d_5pt(64)
     if name == "rmat_s20":
         return synth.rmat(20, 16, 3)
+    if name == "rmat_s18":
+        return synth.rmat(18, 16, 3)
     if name == "stencil27_128":
         return synth.stencil_3d_27pt(128)
     raise SystemExit(f"unknown workload {name}")

@@ -34,9 +34,11 @@ struct spg_handle_s {
     size_t ws_bytes = 0;
     Ctl *ctl = nullptr;
     Ctl *ctl_host = nullptr;  // pinned
-    // heavy-row spill pool
+    // heavy-row spill pool and per-row descriptors
     void *spill_mem = nullptr;
     size_t spill_bytes = 0;
+    void *hdesc_mem = nullptr;
+    size_t hdesc_bytes = 0;
     // plan left by the last symbolic call
     bool plan_valid = false;
     const void *pa_rpt = nullptr, *pb_rpt = nullptr;
@@ -125,6 +127,104 @@ int ensure_workspace(spg_handle h, int64_t M, Workspace *ws) {
     return SPG_OK;
 }
 
+int grow(spg_handle h, void **mem, size_t *have, size_t need, const char *what) {
+    if (need <= *have) return SPG_OK;
+    if (*mem) HIP_TRY(h, hipFree(*mem));
+    *mem = nullptr;
+    *have = 0;
+    if (hipMalloc(mem, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SPG_ERR_NOMEM, "allocation of %zu bytes for %s failed", need, what);
+    }
+    *have = need;
+    return SPG_OK;
+}
+
+// Heavy rows: read their sizes back, order them largest first, cut them into
+// batches whose spill buffers fit the budget and run one launch per batch.
+int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace &ws,
+              const int64_t *c_rpt, int32_t *c_col, double *c_val, hipStream_t s) {
+    const int64_t n = h->counts[kClassHeavy];
+    int64_t first = 0;
+    for (int c = 0; c < kClassHeavy; ++c) first += h->counts[c];
+    // descriptors: info (3 x int64 per row) then rows (int32), spill_off, leaf_off (int64)
+    const size_t info_b = align_up(24 * (size_t)n, 256);
+    const size_t rows_b = align_up(4 * (size_t)n, 256);
+    const size_t offs_b = align_up(8 * (size_t)n, 256);
+    int rc;
+    if ((rc = grow(h, &h->hdesc_mem, &h->hdesc_bytes, info_b + rows_b + 2 * offs_b + 8 * 4096, "heavy descriptors")))
+        return rc;
+    char *d = static_cast<char *>(h->hdesc_mem);
+    int64_t *d_info = reinterpret_cast<int64_t *>(d);
+    int32_t *d_rows = reinterpret_cast<int32_t *>(d + info_b);
+    int64_t *d_soff = reinterpret_cast<int64_t *>(d + info_b + rows_b);
+    int64_t *d_loff = reinterpret_cast<int64_t *>(d + info_b + rows_b + offs_b);
+    unsigned long long *d_ticket = reinterpret_cast<unsigned long long *>(d + info_b + rows_b + 2 * offs_b);
+    HIP_TRY(h, launch_heavy_info(a, ws, first, n, d_info, s));
+    std::vector<int64_t> info(3 * (size_t)n);
+    HIP_TRY(h, hipMemcpyAsync(info.data(), d_info, 24 * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    std::vector<int64_t> order((size_t)n);
+    for (int64_t i = 0; i < n; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t x, int64_t y) { return info[3 * x + 1] > info[3 * y + 1]; });
+    std::vector<int32_t> rows((size_t)n);
+    std::vector<int64_t> soff((size_t)n), loff((size_t)n);
+    std::vector<std::pair<int64_t, int64_t>> batches;  // [begin, end)
+    const size_t budget = (size_t)h->spill_budget_mb << 20;
+    size_t max_elems = 0, max_leaf = 0;
+    size_t used = 0, elems = 0, leafs = 0;
+    int64_t b0 = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t i = order[(size_t)j];
+        const int64_t np = info[3 * i + 1], nl = info[3 * i + 2];
+        if (np >= INT32_MAX || nl >= INT32_MAX)
+            return fail(h, SPG_ERR_CAPACITY, "row %lld has %lld products (limit 2^31-1 per row)",
+                        (long long)info[3 * i], (long long)np);
+        const size_t need = 24 * (size_t)np + 4 * (size_t)(nl + 1);
+        if (j > b0 && used + need > budget) {
+            batches.emplace_back(b0, j);
+            b0 = j;
+            used = elems = leafs = 0;
+        }
+        rows[(size_t)j] = (int32_t)info[3 * i];
+        soff[(size_t)j] = (int64_t)elems;
+        loff[(size_t)j] = (int64_t)leafs;
+        elems += 2 * (size_t)np;
+        leafs += (size_t)nl + 1;
+        used += need;
+        max_elems = std::max(max_elems, elems);
+        max_leaf = std::max(max_leaf, leafs);
+    }
+    batches.emplace_back(b0, n);
+    if (batches.size() > 4096) return fail(h, SPG_ERR_CAPACITY, "too many spill batches; raise the spill budget");
+    HIP_TRY(h, hipMemcpy(d_rows, rows.data(), 4 * (size_t)n, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_soff, soff.data(), 8 * (size_t)n, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_loff, loff.data(), 8 * (size_t)n, hipMemcpyHostToDevice));
+    const size_t col_b = align_up(4 * max_elems, 256), val_b = align_up(8 * max_elems, 256);
+    if ((rc = grow(h, &h->spill_mem, &h->spill_bytes, col_b + val_b + align_up(4 * max_leaf, 256) + 256, "spill buffers")))
+        return rc;
+    char *sp = static_cast<char *>(h->spill_mem);
+    HIP_TRY(h, launch_zero_words(d_ticket, (int64_t)batches.size(), s));
+    for (size_t bi = 0; bi < batches.size(); ++bi) {
+        const int64_t lo = batches[bi].first, hi = batches[bi].second;
+        HeavyArgs ha;
+        ha.ticket = d_ticket + bi;
+        ha.rows = d_rows + lo;
+        ha.spill_off = d_soff + lo;
+        ha.leaf_off = d_loff + lo;
+        ha.nrows = hi - lo;
+        ha.spill_col = reinterpret_cast<int32_t *>(sp);
+        ha.spill_val = reinterpret_cast<double *>(sp + col_b);
+        ha.leaf = reinterpret_cast<int32_t *>(sp + col_b + val_b);
+        ha.lds_cap = (int)h->heavy_lds_max;
+        const int grid = (int)std::min<int64_t>(hi - lo, h->num_cu);
+        HIP_TRY(h, launch_numeric_heavy(a, b, ha, grid, c_rpt, c_col, c_val, h->ctl, s));
+    }
+    h->heavy_batches = (int64_t)batches.size();
+    return SPG_OK;
+}
+
 Thresholds thresholds(spg_handle h) {
     Thresholds t;
     t.wave_small_max = h->wave_small_max;
@@ -197,6 +297,7 @@ int spg_destroy(spg_handle h) {
     (void)hipDeviceSynchronize();
     if (h->ws_mem) (void)hipFree(h->ws_mem);
     if (h->spill_mem) (void)hipFree(h->spill_mem);
+    if (h->hdesc_mem) (void)hipFree(h->hdesc_mem);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->ctl_host) (void)hipHostFree(h->ctl_host);
     delete h;
@@ -366,8 +467,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
         HIP_TRY(h, launch_numeric(a, b, ws, cls, h->counts[cls], persistent_grid(h, cls, h->counts[cls]),
                                   c_rpt, c_col, c_val, s));
     }
-    if (h->counts[kClassHeavy] > 0)
-        return fail(h, SPG_ERR_ARG, "rows beyond %d products are not supported yet", kCapBlock);
+    if (h->counts[kClassHeavy] > 0) return run_heavy(h, a, b, ws, c_rpt, c_col, c_val, s);
     return SPG_OK;
 }
 

@@ -71,6 +71,7 @@ constexpr int kScanTile = 4096;  // rows per scan tile (256 threads x 16)
 
 // ---- launchers (brm_kernels.hip) -----------------------------------------
 hipError_t launch_zero_ctl(Ctl *ctl, hipStream_t s);
+hipError_t launch_zero_words(unsigned long long *p, int64_t n, hipStream_t s);
 hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rpt, int64_t err_col,
                            Ctl *ctl, hipStream_t s);
 hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds &th,
@@ -83,18 +84,22 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
                           int64_t rows_in_class, int grid, const int64_t *c_rpt, int32_t *c_col,
                           double *c_val, hipStream_t s);
 
-// Heavy rows: one workgroup per row, spill buffers in `spill`.
+// Heavy rows: one 1024-thread workgroup per row, spill buffers in HBM.
 struct HeavyArgs {
-    const int32_t *rows;      // heavy row ids of this batch
-    const int64_t *spill_off; // element offset of each row's spill region (2 buffers of nprod)
+    unsigned long long *ticket;  // zeroed counter handing out the batch's rows
+    const int32_t *rows;       // heavy row ids of this batch, largest first
+    const int64_t *spill_off;  // element offset of each row's two spill buffers (2 * nprod)
+    const int64_t *leaf_off;   // offset of each row's list-offset array (lists + 1 entries)
     int64_t nrows;
     int32_t *spill_col;
     double *spill_val;
-    int64_t *spill_leaf;      // leaf offsets, offset by the row's A start... see kernel
-    int lds_max;              // largest leaf range merged in LDS
+    int32_t *leaf;
+    int lds_cap;               // largest list range merged in LDS (products and lists)
 };
-hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Workspace &ws,
-                                const HeavyArgs &h, int grid, const int64_t *c_rpt, int32_t *c_col,
-                                double *c_val, hipStream_t s);
+hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, int64_t first, int64_t n,
+                             int64_t *info, hipStream_t s);
+hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyArgs &h, int grid,
+                                const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+                                hipStream_t s);
 
 }  // namespace brm

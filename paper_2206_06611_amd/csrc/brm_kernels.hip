@@ -72,6 +72,18 @@ hipError_t launch_zero_ctl(Ctl *ctl, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void k_zero_words(unsigned long long *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+hipError_t launch_zero_words(unsigned long long *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(k_zero_words, dim3(g), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // validation (optional): rpt[0] == 0, monotone, rpt[rows] == nnz, columns in
 // range and strictly increasing within rows
@@ -603,17 +615,18 @@ __device__ __forceinline__ void team_flag_scan(NumLds<T, CAP> &s, int tid, const
     }
 }
 
-template <int T, int CAP, typename IA, typename IB>
-__device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int64_t row,
-                                                const void *a_rpt, const int32_t *a_col,
-                                                const double *a_val, const void *b_rpt,
-                                                const int32_t *b_col, const double *b_val,
-                                                const int64_t *c_rpt, int32_t *c_col,
-                                                double *c_val, Ctl *ctl) {
+// BRMerge of the lists [a0, a0 + L) of A's entries (a whole row, or an
+// aligned range of a heavy row's lists) in the team's LDS.  The merged list
+// is written to out_col / out_val (at most out_cap entries); its length is
+// returned to every thread of the team.
+template <int T, int CAP, typename IB>
+__device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP> &s, int tid, int64_t a0, int L,
+                                                 const int32_t *a_col, const double *a_val,
+                                                 const void *b_rpt, const int32_t *b_col,
+                                                 const double *b_val, int32_t *out_col,
+                                                 double *out_val, int64_t out_cap) {
     constexpr int E = CAP / T;
     static_assert(E * Team<T>::kWaves <= 64, "flag scan assumes at most 64 (slice, wave) slots");
-    const int64_t a0 = ld_rpt<IA>(a_rpt, row);
-    const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
 
     // list offsets; B row start and A value of every list staged in the
     // second buffer (free until the first round)
@@ -751,18 +764,34 @@ __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int6
         cur = nxt;
     }
 
-    // Algorithm 1's final store: the single list left goes to C's row
+    // Algorithm 1's final store: the single list left goes to the output
     const int rl = s.len[0];
-    const int64_t cs = c_rpt[row];
-    const int64_t cap = c_rpt[row + 1] - cs;
-    if (tid == 0 && (int64_t)rl != cap)
-        atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
-    const int m = (int64_t)rl < cap ? rl : (int)cap;
+    const int m = (int64_t)rl < out_cap ? rl : (int)out_cap;
     for (int p = tid; p < m; p += T) {
-        c_col[cs + p] = s.col[cur][p];
-        c_val[cs + p] = s.val[cur][p];
+        out_col[p] = s.col[cur][p];
+        out_val[p] = s.val[cur][p];
     }
     Team<T>::sync();
+    return rl;
+}
+
+template <int T, int CAP, typename IA, typename IB>
+__device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int64_t row,
+                                                const void *a_rpt, const int32_t *a_col,
+                                                const double *a_val, const void *b_rpt,
+                                                const int32_t *b_col, const double *b_val,
+                                                const int64_t *c_rpt, int32_t *c_col,
+                                                double *c_val, Ctl *ctl) {
+    const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+    const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
+    const int64_t cs = c_rpt[row];
+    const int64_t cap = c_rpt[row + 1] - cs;
+    const int rl = brmerge_range_lds<T, CAP, IB>(s, tid, a0, L, a_col, a_val, b_rpt, b_col, b_val,
+                                                 c_col + cs, c_val + cs, cap);
+    // Algorithm 1's final store went straight to C's row; a length that
+    // differs from the symbolic count is reported (the row was truncated)
+    if (tid == 0 && (int64_t)rl != cap)
+        atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
 }
 
 template <int T, int TEAMS, int CAP, typename IA, typename IB>
@@ -818,6 +847,478 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
     }
 #undef BRM_NUM_ALL
 #undef BRM_NUM
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// heavy rows: more products than one workgroup's LDS holds
+//
+// One 1024-thread workgroup per row.  The row's lists are consumed left to
+// right as aligned ranges [p 2^h, (p+1) 2^h) -- nodes of the merge tree --
+// each the largest one whose products fit in LDS; such a node is merged in
+// LDS exactly like a light row, a single list too long for LDS is scaled
+// into place.  Finished nodes go to one of two HBM buffers (ping-pong, every
+// node at the offset of its first list's products, so a parent always fits
+// where its children were) and a stack of finished nodes combines two
+// siblings as soon as both exist (a binary counter over the lists).  When
+// the lists run out, a left child without a right sibling is promoted
+// unchanged (Algorithm 1's odd last list) and right children merge with the
+// node below them.  The grouping of additions is therefore the tree of
+// Algorithm 1; two HBM nodes are merged with a merge-path split per tile of
+// 4096 output steps staged through LDS, equal columns being added across
+// tile boundaries through a carried element.  The root is written straight
+// into C.
+// ---------------------------------------------------------------------------
+constexpr int kMergeTile = kHeavyThreads * 4;
+constexpr int kMaxSplits = 2048;
+
+struct MergeLds {
+    int32_t xc[kMergeTile];
+    double xv[kMergeTile];
+    int32_t yc[kMergeTile];
+    double yv[kMergeTile];
+    int32_t first_c[kHeavyThreads];
+    double first_v[kHeavyThreads];
+    int32_t last_c[kHeavyThreads];
+    int64_t split[kMaxSplits + 1];
+};
+
+struct HeavyNode {
+    int64_t p;    // index of the node at its level
+    int64_t len;  // length of its merged list
+    int h;        // level (the node covers lists [p 2^h, (p+1) 2^h))
+    int buf;      // 0 / 1: spill buffer, 2: C
+};
+
+struct HeavyState {
+    HeavyNode stack[64];
+    int sp;
+    int64_t next_list;  // first list not consumed yet
+    int action;
+    int64_t l0, l1;     // list range of a new node
+    int h;
+    int root;
+    int64_t carry_c;
+    double carry_v;
+    int has_carry;
+    int64_t out;
+    int64_t scr[Team<kHeavyThreads>::kWaves + 1];
+};
+
+enum HeavyAction { kActNode = 0, kActMerge = 1, kActPromote = 2, kActToC = 3, kActDone = 4, kActFail = 5 };
+
+__device__ __forceinline__ int64_t mp_split_global(const int32_t *X, int64_t nx, const int32_t *Y,
+                                                   int64_t ny, int64_t d, int64_t xlo, int64_t xhi) {
+    // number of X elements among the first d of the merged order (X first on
+    // ties), searched inside [xlo, xhi] (a known bracket keeps the probes of Y
+    // at or after the split of an earlier diagonal)
+    int64_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
+    if (lo < xlo) lo = xlo;
+    if (hi > xhi) hi = xhi;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int mp_split_lds(const int32_t *X, int nx, const int32_t *Y, int ny, int d) {
+    int lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Merge sorted lists X (left child) and Y (right child) into Z, adding the
+// values of equal columns (left + right).  Z may alias the region that Y
+// occupies as long as Z starts at or before X's region start and X's region
+// is at least |X| long: a tile's output never reaches the unread part of Y.
+// Writes at most zcap entries; returns the merged length (uniform).
+__device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t *Xc,
+                             const double *Xv, int64_t nx, const int32_t *Yc, const double *Yv,
+                             int64_t ny, int32_t *Zc, double *Zv, int64_t zcap) {
+    const int64_t D = nx + ny;
+    const int64_t ntiles = (D + kMergeTile - 1) / kMergeTile;
+    if (tid == 0) {
+        st.has_carry = 0;
+        st.out = 0;
+    }
+    // split of the first diagonal of the current group of tiles: the outputs
+    // written so far only cover Y entries before it
+    int64_t xprev = 0, dprev = 0;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += kMaxSplits) {
+        const int64_t tn = (ntiles - t0) < kMaxSplits ? (ntiles - t0) : kMaxSplits;
+        for (int64_t j = tid; j <= tn; j += kHeavyThreads) {
+            int64_t d = (t0 + j) * (int64_t)kMergeTile;
+            d = d < D ? d : D;
+            m.split[j] = mp_split_global(Xc, nx, Yc, ny, d, xprev, xprev + (d - dprev));
+        }
+        __syncthreads();
+        for (int64_t t = 0; t < tn; ++t) {
+            const int64_t d0 = (t0 + t) * (int64_t)kMergeTile;
+            const int64_t d1 = (d0 + kMergeTile) < D ? (d0 + kMergeTile) : D;
+            const int64_t x0 = m.split[t], x1 = m.split[t + 1];
+            const int64_t y0 = d0 - x0, y1 = d1 - x1;
+            const int nxs = (int)(x1 - x0), nys = (int)(y1 - y0), tl = (int)(d1 - d0);
+            for (int i = tid; i < nxs; i += kHeavyThreads) {
+                m.xc[i] = Xc[x0 + i];
+                m.xv[i] = Xv[x0 + i];
+            }
+            for (int i = tid; i < nys; i += kHeavyThreads) {
+                m.yc[i] = Yc[y0 + i];
+                m.yv[i] = Yv[y0 + i];
+            }
+            __syncthreads();
+            // four merge steps per thread
+            const int s0 = tid * 4;
+            int cnt = 0;
+            int32_t c[4];
+            double v[4];
+            if (s0 < tl) {
+                int x = mp_split_lds(m.xc, nxs, m.yc, nys, s0);
+                int y = s0 - x;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (s0 + j < tl) {
+                        if (x < nxs && (y >= nys || m.xc[x] <= m.yc[y])) {
+                            c[j] = m.xc[x];
+                            v[j] = m.xv[x];
+                            ++x;
+                        } else {
+                            c[j] = m.yc[y];
+                            v[j] = m.yv[y];
+                            ++y;
+                        }
+                        ++cnt;
+                    }
+                }
+                m.first_c[tid] = c[0];
+                m.first_v[tid] = v[0];
+                m.last_c[tid] = c[cnt - 1];
+            }
+            const int nthr = (tl + 3) / 4;
+            const bool last_tile = (t0 + t) == ntiles - 1;
+            const int has_carry = st.has_carry;
+            const int64_t carry_c = st.carry_c;
+            const double carry_v = st.carry_v;
+            __syncthreads();
+            // heads and their values
+            int32_t oc[5];
+            double ov[5];
+            int items = 0;
+            int new_carry = 0;
+            int32_t ncc = 0;
+            double ncv = 0.0;
+            if (tid == 0 && has_carry) {
+                if (tl > 0 && (int64_t)c[0] == carry_c) {
+                    oc[0] = (int32_t)carry_c;
+                    ov[0] = carry_v + v[0];
+                } else {
+                    oc[0] = (int32_t)carry_c;
+                    ov[0] = carry_v;
+                }
+                items = 1;
+            }
+            for (int j = 0; j < cnt; ++j) {
+                const int g = s0 + j;
+                bool head;
+                if (g == 0) head = !(has_carry && (int64_t)c[0] == carry_c);
+                else head = c[j] != (j > 0 ? c[j - 1] : m.last_c[tid - 1]);
+                if (!head) continue;
+                bool has_next;
+                int32_t nc = 0;
+                double nv = 0.0;
+                if (j + 1 < cnt) {
+                    has_next = true;
+                    nc = c[j + 1];
+                    nv = v[j + 1];
+                } else if (tid + 1 < nthr) {
+                    has_next = true;
+                    nc = m.first_c[tid + 1];
+                    nv = m.first_v[tid + 1];
+                } else {
+                    has_next = false;
+                }
+                if (has_next && nc == c[j]) {
+                    oc[items] = c[j];
+                    ov[items] = v[j] + nv;
+                    ++items;
+                } else if (!has_next && !last_tile) {
+                    // last element of the tile: its partner may open the next tile
+                    new_carry = 1;
+                    ncc = c[j];
+                    ncv = v[j];
+                } else {
+                    oc[items] = c[j];
+                    ov[items] = v[j];
+                    ++items;
+                }
+            }
+            int tot;
+            const int rank = Team<kHeavyThreads>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
+            const int64_t base = st.out;
+            for (int j = 0; j < items; ++j) {
+                const int64_t o = base + rank + j;
+                if (o < zcap) {
+                    Zc[o] = oc[j];
+                    Zv[o] = ov[j];
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                st.out = base + tot;
+                st.has_carry = 0;
+            }
+            __syncthreads();
+            if (new_carry) {
+                st.has_carry = 1;
+                st.carry_c = ncc;
+                st.carry_v = ncv;
+            }
+            __syncthreads();
+        }
+        xprev = m.split[tn];
+        dprev = (t0 + tn) * (int64_t)kMergeTile < D ? (t0 + tn) * (int64_t)kMergeTile : D;
+        __syncthreads();
+    }
+    const int64_t n = st.out;
+    __syncthreads();
+    return n;
+}
+
+struct HeavyBatch {
+    unsigned long long *ticket;  // next row of the batch (zeroed before the launch)
+    const int32_t *rows;
+    const int64_t *spill_off;  // element offset of each row's two spill buffers
+    const int64_t *leaf_off;   // offset of each row's list-offset array
+    int64_t nrows;
+    int32_t *spill_col;
+    double *spill_val;
+    int32_t *leaf;
+    int lds_cap;
+};
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
+    HeavyBatch hb, const void *a_rpt, const int32_t *a_col, const double *a_val, const void *b_rpt,
+    const int32_t *b_col, const double *b_val, const int64_t *c_rpt, int32_t *c_col, double *c_val,
+    Ctl *ctl) {
+    constexpr size_t kUnion = sizeof(NumLds<kHeavyThreads, kCapBlock>) > sizeof(MergeLds)
+                                  ? sizeof(NumLds<kHeavyThreads, kCapBlock>)
+                                  : sizeof(MergeLds);
+    __shared__ __align__(16) unsigned char raw[kUnion];
+    __shared__ HeavyState st;
+    auto &node_lds = *reinterpret_cast<NumLds<kHeavyThreads, kCapBlock> *>(raw);
+    auto &mrg = *reinterpret_cast<MergeLds *>(raw);
+    const int tid = threadIdx.x;
+    __shared__ int64_t s_bi;
+    while (true) {
+        // rows arrive largest first; a ticket hands the next one to a free workgroup
+        if (tid == 0) s_bi = (int64_t)atomicAdd(hb.ticket, 1ull);
+        __syncthreads();
+        const int64_t bi = s_bi;
+        __syncthreads();
+        if (bi >= hb.nrows) break;
+        const int64_t row = hb.rows[bi];
+        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+        const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
+        int32_t *leaf = hb.leaf + hb.leaf_off[bi];
+        // list offsets inside the row's product space
+        int64_t carry = 0;
+        for (int64_t lb = 0; lb < L; lb += kHeavyThreads) {
+            const int64_t l = lb + tid;
+            int64_t ln = 0;
+            if (l < L) {
+                const int32_t k = a_col[a0 + l];
+                ln = ld_rpt<IB>(b_rpt, k + 1) - ld_rpt<IB>(b_rpt, k);
+            }
+            int64_t tot;
+            const int64_t ex = Team<kHeavyThreads>::excl_scan(ln, &tot, st.scr, tid);
+            if (l < L) leaf[l] = (int32_t)(carry + ex);
+            carry += tot;
+        }
+        const int64_t nprod = carry;
+        if (tid == 0) leaf[L] = (int32_t)nprod;
+        int32_t *bcol[2] = {hb.spill_col + hb.spill_off[bi], hb.spill_col + hb.spill_off[bi] + nprod};
+        double *bval[2] = {hb.spill_val + hb.spill_off[bi], hb.spill_val + hb.spill_off[bi] + nprod};
+        const int64_t cs = c_rpt[row];
+        const int64_t ccap = c_rpt[row + 1] - cs;
+        if (tid == 0) {
+            st.sp = 0;
+            st.next_list = 0;
+        }
+        __threadfence();
+        __syncthreads();
+        int64_t guard = 0;
+        while (true) {
+            if (tid == 0) {
+                int act = kActFail;
+                const int sp = st.sp;
+                if (++guard > 4 * (L + 64)) {
+                    act = kActFail;
+                } else if (sp >= 2 && st.stack[sp - 2].h == st.stack[sp - 1].h &&
+                           (st.stack[sp - 1].p & 1) && st.stack[sp - 2].p == st.stack[sp - 1].p - 1) {
+                    act = kActMerge;
+                    const HeavyNode &y = st.stack[sp - 1];
+                    st.root = (y.p >> 1) == 0 && ((int64_t)1 << (y.h + 1)) >= L;
+                } else if (st.next_list < L) {
+                    const int64_t l = st.next_list;
+                    int h = 0;
+                    while (h < 40 && ((l >> h) & 1) == 0 && l + ((int64_t)1 << h) < L) {
+                        const int64_t e = (l + ((int64_t)1 << (h + 1))) < L ? l + ((int64_t)1 << (h + 1)) : L;
+                        if ((int64_t)leaf[e] - leaf[l] <= hb.lds_cap && e - l <= hb.lds_cap) ++h;
+                        else break;
+                    }
+                    st.h = h;
+                    st.l0 = l;
+                    st.l1 = (l + ((int64_t)1 << h)) < L ? l + ((int64_t)1 << h) : L;
+                    st.root = (l == 0 && st.l1 == L);
+                    act = kActNode;
+                } else if (sp == 1) {
+                    act = st.stack[0].buf == 2 ? kActDone : kActToC;
+                } else if (sp >= 2 && (st.stack[sp - 1].p & 1) == 0) {
+                    act = kActPromote;
+                }
+                st.action = act;
+            }
+            __syncthreads();
+            const int act = st.action;
+            if (act == kActDone) break;
+            if (act == kActFail) {
+                if (tid == 0)
+                    atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err),
+                             (unsigned long long)kErrHeavyCapacity);
+                break;
+            }
+            if (act == kActNode) {
+                const int64_t l0 = st.l0, l1 = st.l1;
+                const int root = st.root;
+                const int64_t r0 = leaf[l0];
+                const int64_t np = (int64_t)leaf[l1] - r0;
+                int32_t *oc = root ? c_col + cs : bcol[0] + r0;
+                double *ov = root ? c_val + cs : bval[0] + r0;
+                const int64_t cap = root ? ccap : np;
+                int64_t len;
+                if (np <= hb.lds_cap && (l1 - l0) <= hb.lds_cap) {
+                    len = brmerge_range_lds<kHeavyThreads, kCapBlock, IB>(
+                        node_lds, tid, a0 + l0, (int)(l1 - l0), a_col, a_val, b_rpt, b_col, b_val, oc, ov, cap);
+                } else {
+                    // one list longer than LDS: the scaled B row is the node
+                    const int32_t k = a_col[a0 + l0];
+                    const double a = a_val[a0 + l0];
+                    const int64_t bs = ld_rpt<IB>(b_rpt, k);
+                    for (int64_t j = tid; j < np && j < cap; j += kHeavyThreads) {
+                        oc[j] = b_col[bs + j];
+                        ov[j] = a * b_val[bs + j];
+                    }
+                    len = np;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    if (st.sp < 64) {
+                        HeavyNode &nd = st.stack[st.sp++];
+                        nd.p = l0 >> st.h;
+                        nd.h = st.h;
+                        nd.len = len;
+                        nd.buf = root ? 2 : 0;
+                    }
+                    st.next_list = l1;
+                }
+            } else if (act == kActMerge) {
+                const HeavyNode x = st.stack[st.sp - 2];
+                const HeavyNode y = st.stack[st.sp - 1];
+                const int root = st.root;
+                const int64_t rx = leaf[x.p << x.h];
+                const int64_t ry = leaf[y.p << y.h];
+                const int ob = root ? 2 : (x.buf == y.buf ? 1 - x.buf : y.buf);
+                int32_t *oc = root ? c_col + cs : bcol[ob] + rx;
+                double *ov = root ? c_val + cs : bval[ob] + rx;
+                const int64_t cap = root ? ccap : (nprod - rx);
+                const int64_t len = merge_hbm(mrg, st, tid, bcol[x.buf] + rx, bval[x.buf] + rx, x.len,
+                                              bcol[y.buf] + ry, bval[y.buf] + ry, y.len, oc, ov, cap);
+                if (tid == 0) {
+                    st.sp -= 2;
+                    HeavyNode &nd = st.stack[st.sp++];
+                    nd.p = x.p >> 1;
+                    nd.h = x.h + 1;
+                    nd.len = len;
+                    nd.buf = ob;
+                }
+            } else if (act == kActPromote) {
+                if (tid == 0) {
+                    HeavyNode &nd = st.stack[st.sp - 1];
+                    nd.p >>= 1;
+                    nd.h += 1;
+                }
+            } else if (act == kActToC) {
+                const HeavyNode x = st.stack[0];
+                const int64_t n = x.len < ccap ? x.len : ccap;
+                for (int64_t j = tid; j < n; j += kHeavyThreads) {
+                    c_col[cs + j] = bcol[x.buf][j];
+                    c_val[cs + j] = bval[x.buf][j];
+                }
+                if (tid == 0) st.stack[0].buf = 2;
+            }
+            __threadfence();
+            __syncthreads();
+        }
+        if (tid == 0 && st.sp == 1 && st.stack[0].len != ccap)
+            atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyArgs &h, int grid,
+                                const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+                                hipStream_t s) {
+    HeavyBatch hb;
+    hb.ticket = h.ticket;
+    hb.rows = h.rows;
+    hb.spill_off = h.spill_off;
+    hb.leaf_off = h.leaf_off;
+    hb.nrows = h.nrows;
+    hb.spill_col = h.spill_col;
+    hb.spill_val = h.spill_val;
+    hb.leaf = h.leaf;
+    hb.lds_cap = h.lds_cap;
+#define BRM_HEAVY(IA, IB)                                                                          \
+    hipLaunchKernelGGL((k_num_heavy<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, hb, A.rpt,    \
+                       A.col, A.val, B.rpt, B.col, B.val, c_rpt, c_col, c_val, ctl)
+    if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_HEAVY(int32_t, int32_t);
+    else if (A.rpt_bytes == 4) BRM_HEAVY(int32_t, int64_t);
+    else if (B.rpt_bytes == 4) BRM_HEAVY(int64_t, int32_t);
+    else BRM_HEAVY(int64_t, int64_t);
+#undef BRM_HEAVY
+    return hipGetLastError();
+}
+
+// compact (row, nprod, lists) of the heavy rows, in class order
+template <typename IA>
+__global__ void k_heavy_info(int64_t n, const int32_t *rows, const void *a_rpt,
+                             const int64_t *row_nprod, int64_t *info) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = rows[i];
+        info[3 * i] = r;
+        info[3 * i + 1] = row_nprod[r];
+        info[3 * i + 2] = ld_rpt<IA>(a_rpt, r + 1) - ld_rpt<IA>(a_rpt, r);
+    }
+}
+
+hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, int64_t first, int64_t n,
+                             int64_t *info, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    if (A.rpt_bytes == 4)
+        hipLaunchKernelGGL(k_heavy_info<int32_t>, dim3(g), dim3(256), 0, s, n, ws.class_rows + first,
+                           A.rpt, ws.row_nprod, info);
+    else
+        hipLaunchKernelGGL(k_heavy_info<int64_t>, dim3(g), dim3(256), 0, s, n, ws.class_rows + first,
+                           A.rpt, ws.row_nprod, info);
     return hipGetLastError();
 }
 

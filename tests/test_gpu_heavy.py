@@ -1,0 +1,87 @@
+"""GPU parity of the heavy-row path (rows beyond one workgroup's LDS):
+aligned list ranges merged in LDS, HBM ping-pong merges of tree nodes,
+single lists longer than LDS, spill batches."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_matches_oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2206_06611_amd as brm  # noqa: E402
+
+
+def run(h, A, B):
+    dA = brm.DeviceCSR.from_host(A)
+    dB = dA if B is A else brm.DeviceCSR.from_host(B)
+    C = h.spgemm(dA, dB)
+    torch.cuda.synchronize()
+    assert h.stat(brm.STAT_DEVICE_ERR) == 0
+    return C
+
+
+@pytest.fixture()
+def handle():
+    h = brm.Handle(0)
+    h.set_option(brm.OPT_VALIDATE, 1)
+    yield h
+    h.close()
+
+
+def test_rmat_all_rows_heavy(handle):
+    print("case: R-MAT scale 11, every row forced to the heavy path", flush=True)
+    A = synth.rmat(11, 16, 21)
+    handle.set_option(brm.OPT_FORCE_CLASS, 6)
+    C = run(handle, A, A)
+    assert handle.class_rows()["heavy"] == int((oracle.row_nprod(A, A) > 0).sum())
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+@pytest.mark.parametrize("lds_max", [64, 500])
+def test_rmat_deep_hbm_trees(handle, lds_max):
+    print(f"case: R-MAT scale 13, heavy rows with LDS ranges of at most {lds_max}", flush=True)
+    A = synth.rmat(13, 16, 22)
+    handle.set_option(brm.OPT_HEAVY_LDS_MAX, lds_max)
+    C = run(handle, A, A)
+    assert handle.class_rows()["heavy"] > 0
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+def test_spill_batches(handle):
+    print("case: R-MAT scale 13, 1 MB spill budget", flush=True)
+    A = synth.rmat(13, 16, 23)
+    handle.set_option(brm.OPT_SPILL_BUDGET_MB, 1)
+    C = run(handle, A, A)
+    assert handle.stat(brm.STAT_HEAVY_BATCHES) > 1
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+def test_long_single_lists(handle):
+    # rows whose lists include B rows longer than LDS, odd list counts and
+    # empty lists between them
+    rng = np.random.default_rng(5)
+    K, N = 40, 50000
+    lens = rng.integers(0, 300, K)
+    lens[[0, 7, 13]] = [9000, 5000, 12000]
+    lens[[3, 4]] = 0
+    cols = [np.sort(rng.choice(N, size=l, replace=False)) for l in lens]
+    rpt = np.zeros(K + 1, np.int64)
+    rpt[1:] = np.cumsum(lens)
+    B = synth.CSR(K, N, rpt.astype(np.int32), np.concatenate(cols).astype(np.int32),
+                  rng.uniform(-1, 1, rpt[-1]))
+    rows = [np.arange(K), np.array([0, 3, 4, 7, 13]), np.array([13]), np.array([1, 7, 9, 13, 20, 21, 22]),
+            np.arange(0, K, 3)]
+    arpt = np.zeros(len(rows) + 1, np.int64)
+    arpt[1:] = np.cumsum([len(r) for r in rows])
+    A = synth.CSR(len(rows), K, arpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                  rng.uniform(-1, 1, arpt[-1]))
+    for force in (-1, 6):
+        handle.set_option(brm.OPT_FORCE_CLASS, force)
+        C = run(handle, A, B)
+        assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
