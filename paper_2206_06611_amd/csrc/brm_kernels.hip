@@ -1151,7 +1151,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
             st.sp = 0;
             st.next_list = 0;
         }
-        __threadfence();
+        // global stores of this workgroup become visible to it at the barrier (workgroup scope)
         __syncthreads();
         int64_t guard = 0;
         while (true) {
@@ -1263,7 +1263,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                 }
                 if (tid == 0) st.stack[0].buf = 2;
             }
-            __threadfence();
+            // global stores of this workgroup become visible to it at the barrier (workgroup scope)
             __syncthreads();
         }
         if (tid == 0 && st.sp == 1 && st.stack[0].len != ccap)
