@@ -101,8 +101,17 @@ typedef enum {
     SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (<= 4096) */
     SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
                                     per batch of heavy rows (default 16384) */
-    SPG_OPT_GRID_WAVES = 9       /* waves per launch of the persistent row kernels (0 = auto) */
+    SPG_OPT_GRID_WAVES = 9,      /* waves per launch of the persistent row kernels (0 = auto) */
+    SPG_OPT_ALLOC = 10,          /* SPG_ALLOC_PRECISE (default) or SPG_ALLOC_LEARNED */
+    SPG_OPT_LEARNED_FORCE = 11   /* testing only: 1 sizes every predicted row at its lower bound
+                                    (the longest list), so that most rows take the fallback */
 } spg_option;
+
+/* Allocation methods (SPG_OPT_ALLOC). */
+enum {
+    SPG_ALLOC_PRECISE = 0, /* symbolic count, prefix sum, numeric straight into C */
+    SPG_ALLOC_LEARNED = 1  /* predicted sizes, numeric into predicted slots, exact fallback, compaction */
+};
 
 int spg_set_option(spg_handle h, int key, int64_t value);
 int spg_get_option(spg_handle h, int key, int64_t *value);
@@ -114,6 +123,9 @@ typedef enum {
     SPG_STAT_CLASS_ROWS0 = 10,   /* rows per class: +0 empty, +1 copy, +2 wave-small,
                                     +3 wave, +4 group, +5 block, +6 heavy */
     SPG_STAT_HEAVY_BATCHES = 20, /* spill batches the heavy path used in the last numeric call */
+    SPG_STAT_PRED_TOTAL = 21,    /* learned allocation: sum of the predicted row sizes (slot entries) */
+    SPG_STAT_OVERFLOW_ROWS = 22, /* learned allocation: rows longer than their predicted slot */
+    SPG_STAT_PREDICTED_ROWS = 23,/* rows whose size is predicted (two or more lists, a product) */
     SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call
                                     (16: a numeric row length differed from its symbolic count;
                                     the row was truncated to its slot).  Synchronizes the device. */
@@ -145,6 +157,61 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
  * Errors: SPG_ERR_ARG, SPG_ERR_STATE, SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64_t *c_rpt,
                    int32_t *c_col, double *c_val, void *stream);
+
+/* ---- Learned allocation --------------------------------------------------
+ * Not in the paper: a stand-in for its allocation step (Section II-B.2).  A
+ * perceptron 6 -> 64 -> 64 -> 1 (ReLU, float32) predicts y_i ~ log(nnz(C_i) /
+ * nprod_i) for every row with two or more lists and at least one product, from
+ * the features log1p of (lists, products, longest list, shortest list, column
+ * span, products / span), each normalised as (x - mean) / std.  The row's
+ * slot holds clamp(ceil(nprod_i exp(y_i + delta)), longest list, min(nprod_i,
+ * span_i)) entries; rows with no product or one list get their exact size.
+ * With SPG_OPT_ALLOC = SPG_ALLOC_LEARNED, spgemm_symbolic runs the numeric
+ * kernels into the slots (no symbolic pass), records every row's exact length
+ * and the rows that overflowed, and returns C's exact row pointers and nnz
+ * (two device-to-host reads); spgemm_numeric recomputes the overflowed rows
+ * exactly into C and copies the others from their slots.  C is bitwise the
+ * same as with the precise allocation.
+ *
+ * Parameter vector (SPG_MLP_NUM_PARAMS floats, row-major, in this order):
+ * W1[6][64], b1[64], W2[64][64], b2[64], W3[64], b3[1].  `norm` is mean[6]
+ * followed by std[6].  All feats / targets / y / grad arrays are DEVICE
+ * float arrays; feats rows are 6 consecutive floats. */
+#define SPG_MLP_NUM_PARAMS 4673
+
+/* Host params, norm and margin delta; resets the Adam moments. */
+int spg_mlp_set_params(spg_handle h, const float *params, const float *norm, float delta);
+/* Copies the current parameters, normalisation and margin to the host
+ * (any pointer may be NULL).  Synchronizes the device. */
+int spg_mlp_get_params(spg_handle h, float *params, float *norm, float *delta);
+/* Per-row raw features feats[rows][6], the predicted-row flag, the exact
+ * bounds lo/hi (may be NULL) and, when c_rpt (C's row pointers from a
+ * precise symbolic pass) is given, the training targets log(nnz(C_i)/nprod_i)
+ * (0 for rows that are not predicted). */
+int spg_mlp_features(spg_handle h, const spg_csr *A, const spg_csr *B, const int64_t *c_rpt, float *feats,
+                     float *targets, int8_t *predicted, int32_t *lo, int32_t *hi, void *stream);
+/* Network output y[n] for n raw feature rows. */
+int spg_mlp_forward(spg_handle h, const float *feats, int64_t n, float *y, void *stream);
+/* Gradient grad[SPG_MLP_NUM_PARAMS] of the mean squared error over n rows,
+ * and that error in *loss (host, may be NULL; blocks when given). */
+int spg_mlp_gradient(spg_handle h, const float *feats, const float *targets, int64_t n, float *grad, float *loss,
+                     void *stream);
+/* Sets the normalisation to the mean / std of n raw feature rows. */
+int spg_mlp_fit_normalization(spg_handle h, const float *feats, int64_t n, void *stream);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) over `epochs` passes of
+ * the n rows in the given order, in consecutive minibatches of `batch` rows
+ * (the caller shuffles). */
+int spg_mlp_train(spg_handle h, const float *feats, const float *targets, int64_t n, int epochs, int batch,
+                  float lr, void *stream);
+/* Mean squared error of the network over n rows (host *loss; blocks). */
+int spg_mlp_loss(spg_handle h, const float *feats, const float *targets, int64_t n, float *loss, void *stream);
+/* Sets delta to the `quantile` quantile of (target - output) over n rows
+ * (at least 0), so that about that fraction of them fits its slot. */
+int spg_mlp_calibrate(spg_handle h, const float *feats, const float *targets, int64_t n, double quantile,
+                      float *delta, void *stream);
+/* Checkpoint of parameters, Adam moments and step, normalisation and margin. */
+int spg_mlp_save(spg_handle h, const char *path);
+int spg_mlp_load(spg_handle h, const char *path);
 
 /* Text of the last error on this handle ("" if none).  Valid until the next
  * call on the handle. */

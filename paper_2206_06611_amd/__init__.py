@@ -39,12 +39,20 @@ OPT_FORCE_CLASS = 6
 OPT_HEAVY_LDS_MAX = 7
 OPT_SPILL_BUDGET_MB = 8
 OPT_GRID_WAVES = 9
+OPT_ALLOC = 10
+OPT_LEARNED_FORCE = 11
+ALLOC_PRECISE = 0
+ALLOC_LEARNED = 1
+MLP_NUM_PARAMS = 4673
 
 # statistics
 STAT_NPROD = 1
 STAT_NNZ = 2
 STAT_CLASS_ROWS0 = 10
 STAT_HEAVY_BATCHES = 20
+STAT_PRED_TOTAL = 21
+STAT_OVERFLOW_ROWS = 22
+STAT_PREDICTED_ROWS = 23
 STAT_DEVICE_ERR = 30
 
 CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy"]
@@ -85,6 +93,17 @@ def _load_library():
         "spgemm_symbolic": ([P, PCSR, PCSR, P, ctypes.POINTER(I64), P], I32),
         "spgemm_numeric": ([P, PCSR, PCSR, P, P, P, P], I32),
         "spg_last_error": ([P], ctypes.c_char_p),
+        "spg_mlp_set_params": ([P, P, P, ctypes.c_float], I32),
+        "spg_mlp_get_params": ([P, P, P, P], I32),
+        "spg_mlp_features": ([P, PCSR, PCSR, P, P, P, P, P, P, P], I32),
+        "spg_mlp_forward": ([P, P, I64, P, P], I32),
+        "spg_mlp_gradient": ([P, P, P, I64, P, P, P], I32),
+        "spg_mlp_fit_normalization": ([P, P, I64, P], I32),
+        "spg_mlp_train": ([P, P, P, I64, I32, I32, ctypes.c_float, P], I32),
+        "spg_mlp_loss": ([P, P, P, I64, P, P], I32),
+        "spg_mlp_calibrate": ([P, P, P, I64, ctypes.c_double, P, P], I32),
+        "spg_mlp_save": ([P, ctypes.c_char_p], I32),
+        "spg_mlp_load": ([P, ctypes.c_char_p], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -97,7 +116,10 @@ _lib = _load_library()
 
 # every symbol declared in include/spgemm.h
 EXPORTED = ("spg_create", "spg_destroy", "spg_set_option", "spg_get_option", "spg_get_stat",
-            "spgemm_symbolic", "spgemm_numeric", "spg_last_error")
+            "spgemm_symbolic", "spgemm_numeric", "spg_last_error", "spg_mlp_set_params",
+            "spg_mlp_get_params", "spg_mlp_features", "spg_mlp_forward", "spg_mlp_gradient",
+            "spg_mlp_fit_normalization", "spg_mlp_train", "spg_mlp_loss", "spg_mlp_calibrate",
+            "spg_mlp_save", "spg_mlp_load")
 
 
 def library():
@@ -207,6 +229,93 @@ class Handle:
                                         ctypes.c_void_p(c_col.data_ptr() if c_col.numel() else None),
                                         ctypes.c_void_p(c_val.data_ptr() if c_val.numel() else None),
                                         _stream_ptr(stream)))
+
+    # ---- learned size predictor --------------------------------------------
+    def mlp_set_params(self, params, norm, delta: float = 0.0):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        n = np.ascontiguousarray(norm, dtype=np.float32)
+        if p.size != MLP_NUM_PARAMS or n.size != 12:
+            raise ValueError("params must have 4673 entries and norm 12")
+        self._check(_lib.spg_mlp_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p),
+                                            n.ctypes.data_as(ctypes.c_void_p), float(delta)))
+
+    def mlp_get_params(self):
+        import numpy as np
+        p = np.zeros(MLP_NUM_PARAMS, np.float32)
+        n = np.zeros(12, np.float32)
+        d = ctypes.c_float()
+        self._check(_lib.spg_mlp_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p),
+                                            n.ctypes.data_as(ctypes.c_void_p), ctypes.byref(d)))
+        return p, n, d.value
+
+    def mlp_features(self, A: DeviceCSR, B: DeviceCSR, c_rpt: torch.Tensor | None = None, stream=None):
+        """Returns (feats [rows, 6], targets or None, predicted int8, lo, hi)."""
+        dev = A.rpt.device
+        m = A.rows
+        feats = torch.empty((max(m, 1), 6), dtype=torch.float32, device=dev)
+        pred = torch.empty(max(m, 1), dtype=torch.int8, device=dev)
+        lo = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        hi = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        tg = torch.empty(max(m, 1), dtype=torch.float32, device=dev) if c_rpt is not None else None
+        sa, sb = A._struct(), B._struct()
+        self._check(_lib.spg_mlp_features(
+            self._h, ctypes.byref(sa), ctypes.byref(sb),
+            ctypes.c_void_p(c_rpt.data_ptr()) if c_rpt is not None else None,
+            ctypes.c_void_p(feats.data_ptr()), ctypes.c_void_p(tg.data_ptr()) if tg is not None else None,
+            ctypes.c_void_p(pred.data_ptr()), ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+            _stream_ptr(stream)))
+        return feats[:m], (tg[:m] if tg is not None else None), pred[:m], lo[:m], hi[:m]
+
+    def mlp_forward(self, feats: torch.Tensor, stream=None) -> torch.Tensor:
+        feats = feats.contiguous()
+        y = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        self._check(_lib.spg_mlp_forward(self._h, ctypes.c_void_p(feats.data_ptr()), feats.shape[0],
+                                         ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+    def mlp_gradient(self, feats: torch.Tensor, targets: torch.Tensor, stream=None):
+        feats, targets = feats.contiguous(), targets.contiguous()
+        g = torch.empty(MLP_NUM_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = ctypes.c_float()
+        self._check(_lib.spg_mlp_gradient(self._h, ctypes.c_void_p(feats.data_ptr()),
+                                          ctypes.c_void_p(targets.data_ptr()), feats.shape[0],
+                                          ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss),
+                                          _stream_ptr(stream)))
+        return g, loss.value
+
+    def mlp_fit_normalization(self, feats: torch.Tensor, stream=None):
+        feats = feats.contiguous()
+        self._check(_lib.spg_mlp_fit_normalization(self._h, ctypes.c_void_p(feats.data_ptr()),
+                                                   feats.shape[0], _stream_ptr(stream)))
+
+    def mlp_train(self, feats, targets, epochs: int, batch: int = 4096, lr: float = 1e-3, stream=None):
+        feats, targets = feats.contiguous(), targets.contiguous()
+        self._check(_lib.spg_mlp_train(self._h, ctypes.c_void_p(feats.data_ptr()),
+                                       ctypes.c_void_p(targets.data_ptr()), feats.shape[0], int(epochs),
+                                       int(batch), float(lr), _stream_ptr(stream)))
+
+    def mlp_loss(self, feats, targets, stream=None) -> float:
+        feats, targets = feats.contiguous(), targets.contiguous()
+        loss = ctypes.c_float()
+        self._check(_lib.spg_mlp_loss(self._h, ctypes.c_void_p(feats.data_ptr()),
+                                      ctypes.c_void_p(targets.data_ptr()), feats.shape[0],
+                                      ctypes.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def mlp_calibrate(self, feats, targets, quantile: float = 0.99, stream=None) -> float:
+        feats, targets = feats.contiguous(), targets.contiguous()
+        d = ctypes.c_float()
+        self._check(_lib.spg_mlp_calibrate(self._h, ctypes.c_void_p(feats.data_ptr()),
+                                           ctypes.c_void_p(targets.data_ptr()), feats.shape[0],
+                                           float(quantile), ctypes.byref(d), _stream_ptr(stream)))
+        return d.value
+
+    def mlp_save(self, path: str):
+        self._check(_lib.spg_mlp_save(self._h, path.encode()))
+
+    def mlp_load(self, path: str):
+        self._check(_lib.spg_mlp_load(self._h, path.encode()))
 
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None) -> DeviceCSR:
         """C = A*B: symbolic pass, allocation of C, numeric pass."""

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbrmspgemm.so")
-SOURCES = ["brm_kernels.hip", "brm_api.cpp"]
+SOURCES = ["brm_kernels.hip", "brm_learned.hip", "brm_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -47,6 +48,32 @@ struct spg_handle_s {
     int64_t counts[8] = {0};
     int64_t nnz = 0, nprod = 0;
     int64_t heavy_batches = 0;
+    // learned allocation
+    int64_t alloc = 0;          // 0 precise, 1 learned
+    int64_t learned_force = 0;  // testing: 1 = every predicted row at its lower bound
+    bool plan_learned = false;
+    void *lw_mem = nullptr;     // per-row learned workspace
+    size_t lw_bytes = 0;
+    void *slot_mem = nullptr;   // predicted slots (column and value arrays)
+    size_t slot_bytes = 0;
+    Ctl *ctl2 = nullptr;        // control block of the exact fallback
+    int64_t pred_total = 0, ovf_light = 0, ovf_heavy = 0;
+    // predictor state (device): params, adam m, v, gradient, norm[12], loss, act, partial
+    float *mlp = nullptr;
+    size_t mlp_act_rows = 0;
+    float *mlp_act = nullptr;
+    bool mlp_ready = false;
+    float delta = 0.0f;
+    int64_t adam_t = 0;
+};
+
+struct LearnedWs {
+    float *feats;       // [M * 6]
+    int32_t *lo, *hi;   // [M]
+    int8_t *predicted;  // [M]
+    int32_t *pred_size; // [M]
+    int64_t *slot_off;  // [M + 1]
+    int32_t *ovf_rows;  // [2 M]
 };
 
 namespace {
@@ -142,11 +169,9 @@ int grow(spg_handle h, void **mem, size_t *have, size_t need, const char *what) 
 
 // Heavy rows: read their sizes back, order them largest first, cut them into
 // batches whose spill buffers fit the budget and run one launch per batch.
-int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace &ws,
-              const int64_t *c_rpt, int32_t *c_col, double *c_val, hipStream_t s) {
-    const int64_t n = h->counts[kClassHeavy];
-    int64_t first = 0;
-    for (int c = 0; c < kClassHeavy; ++c) first += h->counts[c];
+int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace &ws, const int32_t *heavy_rows,
+              int64_t n, const int64_t *c_rpt, int32_t *c_col, double *c_val, const NumOut &no,
+              Ctl *ctl, hipStream_t s) {
     // descriptors: info (3 x int64 per row) then rows (int32), spill_off, leaf_off (int64)
     const size_t info_b = align_up(24 * (size_t)n, 256);
     const size_t rows_b = align_up(4 * (size_t)n, 256);
@@ -160,7 +185,7 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     int64_t *d_soff = reinterpret_cast<int64_t *>(d + info_b + rows_b);
     int64_t *d_loff = reinterpret_cast<int64_t *>(d + info_b + rows_b + offs_b);
     unsigned long long *d_ticket = reinterpret_cast<unsigned long long *>(d + info_b + rows_b + 2 * offs_b);
-    HIP_TRY(h, launch_heavy_info(a, ws, first, n, d_info, s));
+    HIP_TRY(h, launch_heavy_info(a, ws, heavy_rows, n, d_info, s));
     std::vector<int64_t> info(3 * (size_t)n);
     HIP_TRY(h, hipMemcpyAsync(info.data(), d_info, 24 * (size_t)n, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
@@ -219,9 +244,66 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
         ha.leaf = reinterpret_cast<int32_t *>(sp + col_b + val_b);
         ha.lds_cap = (int)h->heavy_lds_max;
         const int grid = (int)std::min<int64_t>(hi - lo, h->num_cu);
-        HIP_TRY(h, launch_numeric_heavy(a, b, ha, grid, c_rpt, c_col, c_val, h->ctl, s));
+        HIP_TRY(h, launch_numeric_heavy(a, b, ha, grid, c_rpt, c_col, c_val, ctl, no, s));
     }
-    h->heavy_batches = (int64_t)batches.size();
+    h->heavy_batches += (int64_t)batches.size();
+    return SPG_OK;
+}
+
+int ensure_learned_ws(spg_handle h, int64_t M, LearnedWs *lw) {
+    const size_t a = 256;
+    size_t o_feat = 0;
+    size_t o_lo = align_up(o_feat + 24 * (size_t)M, a);
+    size_t o_hi = align_up(o_lo + 4 * (size_t)M, a);
+    size_t o_pr = align_up(o_hi + 4 * (size_t)M, a);
+    size_t o_ps = align_up(o_pr + (size_t)M, a);
+    size_t o_so = align_up(o_ps + 4 * (size_t)M, a);
+    size_t o_ov = align_up(o_so + 8 * (size_t)(M + 1), a);
+    size_t total = align_up(o_ov + 8 * (size_t)M + 8, a);
+    int rc;
+    if ((rc = grow(h, &h->lw_mem, &h->lw_bytes, total, "learned workspace"))) return rc;
+    char *b = static_cast<char *>(h->lw_mem);
+    lw->feats = reinterpret_cast<float *>(b + o_feat);
+    lw->lo = reinterpret_cast<int32_t *>(b + o_lo);
+    lw->hi = reinterpret_cast<int32_t *>(b + o_hi);
+    lw->predicted = reinterpret_cast<int8_t *>(b + o_pr);
+    lw->pred_size = reinterpret_cast<int32_t *>(b + o_ps);
+    lw->slot_off = reinterpret_cast<int64_t *>(b + o_so);
+    lw->ovf_rows = reinterpret_cast<int32_t *>(b + o_ov);
+    if (!h->ctl2) HIP_TRY(h, hipMalloc(&h->ctl2, sizeof(Ctl)));
+    return SPG_OK;
+}
+
+// predictor buffers: params | m | v | grad | norm(12) | loss(4) | partial
+constexpr size_t kMlpOffM = kMlpParams, kMlpOffV = 2 * kMlpParams, kMlpOffG = 3 * kMlpParams,
+                 kMlpOffNorm = 4 * kMlpParams, kMlpOffLoss = kMlpOffNorm + 12,
+                 kMlpOffPartial = kMlpOffLoss + 4,
+                 kMlpFloats = kMlpOffPartial + (size_t)kMlpGradChunks * (kMlpParams + 1);
+
+int ensure_mlp(spg_handle h) {
+    if (!h->mlp) {
+        if (hipMalloc(&h->mlp, sizeof(float) * kMlpFloats) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, SPG_ERR_NOMEM, "predictor state allocation failed");
+        }
+        HIP_TRY(h, hipMemset(h->mlp, 0, sizeof(float) * kMlpFloats));
+        std::vector<float> norm(12, 0.0f);
+        for (int j = 6; j < 12; ++j) norm[(size_t)j] = 1.0f;
+        HIP_TRY(h, hipMemcpy(h->mlp + kMlpOffNorm, norm.data(), 48, hipMemcpyHostToDevice));
+    }
+    return SPG_OK;
+}
+
+int ensure_mlp_act(spg_handle h, int64_t rows) {
+    if ((size_t)rows <= h->mlp_act_rows) return SPG_OK;
+    if (h->mlp_act) HIP_TRY(h, hipFree(h->mlp_act));
+    h->mlp_act = nullptr;
+    h->mlp_act_rows = 0;
+    if (hipMalloc(&h->mlp_act, sizeof(float) * kMlpActStride * (size_t)rows) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SPG_ERR_NOMEM, "activation buffer allocation failed");
+    }
+    h->mlp_act_rows = (size_t)rows;
     return SPG_OK;
 }
 
@@ -298,6 +380,11 @@ int spg_destroy(spg_handle h) {
     if (h->ws_mem) (void)hipFree(h->ws_mem);
     if (h->spill_mem) (void)hipFree(h->spill_mem);
     if (h->hdesc_mem) (void)hipFree(h->hdesc_mem);
+    if (h->lw_mem) (void)hipFree(h->lw_mem);
+    if (h->slot_mem) (void)hipFree(h->slot_mem);
+    if (h->ctl2) (void)hipFree(h->ctl2);
+    if (h->mlp) (void)hipFree(h->mlp);
+    if (h->mlp_act) (void)hipFree(h->mlp_act);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->ctl_host) (void)hipHostFree(h->ctl_host);
     delete h;
@@ -343,6 +430,15 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             if (value < 0) return fail(h, SPG_ERR_ARG, "grid waves must be >= 0");
             h->grid_waves = value;
             break;
+        case SPG_OPT_ALLOC:
+            if (value != SPG_ALLOC_PRECISE && value != SPG_ALLOC_LEARNED)
+                return fail(h, SPG_ERR_ARG, "allocation must be SPG_ALLOC_PRECISE or SPG_ALLOC_LEARNED");
+            h->alloc = value;
+            break;
+        case SPG_OPT_LEARNED_FORCE:
+            if (value != 0 && value != 1) return fail(h, SPG_ERR_ARG, "learned force must be 0 or 1");
+            h->learned_force = value;
+            break;
         default: return fail(h, SPG_ERR_ARG, "unknown option %d", key);
     }
     h->plan_valid = false;
@@ -361,6 +457,8 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_HEAVY_LDS_MAX: *value = h->heavy_lds_max; break;
         case SPG_OPT_SPILL_BUDGET_MB: *value = h->spill_budget_mb; break;
         case SPG_OPT_GRID_WAVES: *value = h->grid_waves; break;
+        case SPG_OPT_ALLOC: *value = h->alloc; break;
+        case SPG_OPT_LEARNED_FORCE: *value = h->learned_force; break;
         default: return fail(h, SPG_ERR_ARG, "unknown option %d", key);
     }
     return SPG_OK;
@@ -376,12 +474,21 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_NPROD: *value = h->nprod; return SPG_OK;
         case SPG_STAT_NNZ: *value = h->nnz; return SPG_OK;
         case SPG_STAT_HEAVY_BATCHES: *value = h->heavy_batches; return SPG_OK;
+        case SPG_STAT_PRED_TOTAL: *value = h->pred_total; return SPG_OK;
+        case SPG_STAT_OVERFLOW_ROWS: *value = h->ovf_light + h->ovf_heavy; return SPG_OK;
+        case SPG_STAT_PREDICTED_ROWS: {
+            int64_t n = 0;
+            for (int c = kClassWaveSmall; c <= kClassHeavy; ++c) n += h->counts[c];
+            *value = n;
+            return SPG_OK;
+        }
         case SPG_STAT_DEVICE_ERR: {
             HIP_TRY(h, hipSetDevice(h->device));
             HIP_TRY(h, hipDeviceSynchronize());
-            int64_t e = 0;
+            int64_t e = 0, e2 = 0;
             HIP_TRY(h, hipMemcpy(&e, &h->ctl->err, sizeof e, hipMemcpyDeviceToHost));
-            *value = e;
+            if (h->ctl2) HIP_TRY(h, hipMemcpy(&e2, &h->ctl2->err, sizeof e2, hipMemcpyDeviceToHost));
+            *value = e | e2;
             return SPG_OK;
         }
         default: return fail(h, SPG_ERR_ARG, "unknown statistic %d", key);
@@ -417,22 +524,67 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
             return fail(h, SPG_ERR_INVALID_CSR, "invalid CSR input (error bits 0x%llx: 1/2 = A rpt/col, 4/8 = B rpt/col)",
                         (unsigned long long)h->ctl_host->err);
     }
+    const bool learned = h->alloc == SPG_ALLOC_LEARNED;
+    if (learned && !h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "learned allocation needs a trained or loaded predictor");
+    h->heavy_batches = 0;
+    h->pred_total = h->ovf_light = h->ovf_heavy = 0;
     if (M > 0) {
         const int g = (int)std::min<int64_t>((M + 255) / 256, 2048);
         HIP_TRY(h, launch_analysis(a, b, thresholds(h), ws, g, s));
         HIP_TRY(h, launch_bin(M, ws, g, s));
-        for (int cls = kClassWaveSmall; cls <= kClassHeavy; ++cls)
-            HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1), s));
+        if (!learned) {
+            for (int cls = kClassWaveSmall; cls <= kClassHeavy; ++cls)
+                HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1), s));
+        }
     }
-    HIP_TRY(h, launch_scan(M, ws, c_rpt, s));
+    if (learned) {
+        // predicted sizes -> slots; numeric into the slots (exact lengths and
+        // overflowing rows recorded); exact row pointers from the lengths
+        LearnedWs lw;
+        if ((rc = ensure_learned_ws(h, M, &lw))) return rc;
+        HIP_TRY(h, launch_features(a, b, lw.feats, lw.lo, lw.hi, lw.predicted, nullptr, nullptr, s));
+        HIP_TRY(h, launch_mlp_sizes(M, lw.feats, lw.predicted, lw.lo, lw.hi, ws.row_nprod, h->mlp,
+                                    h->mlp + kMlpOffNorm, h->delta, (int)h->learned_force, lw.pred_size, s));
+        HIP_TRY(h, launch_scan(M, lw.pred_size, ws.tile_sum, lw.slot_off, &h->ctl->pred_total, s));
+        HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        for (int i = 0; i < 8; ++i) h->counts[i] = h->ctl_host->count[i];
+        h->pred_total = h->ctl_host->pred_total;
+        const size_t pt = (size_t)std::max<int64_t>(h->pred_total, 1);
+        if ((rc = grow(h, &h->slot_mem, &h->slot_bytes, align_up(4 * pt, 256) + 8 * pt, "predicted slots")))
+            return rc;
+        int32_t *s_col = static_cast<int32_t *>(h->slot_mem);
+        double *s_val = reinterpret_cast<double *>(static_cast<char *>(h->slot_mem) + align_up(4 * pt, 256));
+        NumOut no;
+        no.bound = 1;
+        no.row_size = ws.row_size;
+        no.ovf_rows = lw.ovf_rows;
+        no.M = M;
+        for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
+            if (h->counts[cls] == 0) continue;
+            HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls]), lw.slot_off, s_col,
+                                      s_val, no, s));
+        }
+        if (h->counts[kClassHeavy] > 0) {
+            int64_t first = 0;
+            for (int c = 0; c < kClassHeavy; ++c) first += h->counts[c];
+            if ((rc = run_heavy(h, a, b, ws, ws.class_rows + first, h->counts[kClassHeavy], lw.slot_off, s_col,
+                                s_val, no, h->ctl, s)))
+                return rc;
+        }
+    }
+    HIP_TRY(h, launch_scan(M, ws.row_size, ws.tile_sum, c_rpt, &h->ctl->nnz, s));
     HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     const Ctl &c = *h->ctl_host;
     for (int i = 0; i < 8; ++i) h->counts[i] = c.count[i];
     h->nnz = c.nnz;
     h->nprod = c.nprod;
+    h->ovf_light = c.ovf_light;
+    h->ovf_heavy = c.ovf_heavy;
     *c_nnz = c.nnz;
     h->plan_valid = true;
+    h->plan_learned = learned;
     h->pa_rpt = A->rpt;
     h->pb_rpt = B->rpt;
     h->pa_col = A->col;
@@ -462,12 +614,253 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     Workspace ws;
     if ((rc = ensure_workspace(h, A->rows, &ws))) return rc;
     h->heavy_batches = 0;
+    NumOut exact;
+    exact.bound = 0;
+    exact.row_size = nullptr;
+    exact.ovf_rows = nullptr;
+    exact.M = A->rows;
+    if (h->plan_learned) {
+        // exact fallback for the rows that overflowed their slot, then the
+        // other rows move from their slots to C
+        const int64_t M = A->rows;
+        LearnedWs lw;
+        if ((rc = ensure_learned_ws(h, M, &lw))) return rc;
+        if (h->ovf_light + h->ovf_heavy > 0) {
+            HIP_TRY(h, launch_fallback_ctl(h->ctl, h->ctl2, M, s));
+            Workspace ws2 = ws;
+            ws2.class_rows = lw.ovf_rows;
+            ws2.ctl = h->ctl2;
+            if (h->ovf_light > 0)
+                HIP_TRY(h, launch_numeric(a, b, ws2, kClassBlock, persistent_grid(h, kClassBlock, h->ovf_light), c_rpt,
+                                          c_col, c_val, exact, s));
+            if (h->ovf_heavy > 0 &&
+                (rc = run_heavy(h, a, b, ws, lw.ovf_rows + M, h->ovf_heavy, c_rpt, c_col, c_val, exact, h->ctl2, s)))
+                return rc;
+        }
+        const size_t pt = (size_t)std::max<int64_t>(h->pred_total, 1);
+        const int32_t *s_col = static_cast<const int32_t *>(h->slot_mem);
+        const double *s_val =
+            reinterpret_cast<const double *>(static_cast<const char *>(h->slot_mem) + align_up(4 * pt, 256));
+        HIP_TRY(h, launch_compact(M, lw.slot_off, ws.row_size, c_rpt, s_col, s_val, c_col, c_val,
+                                  (int)std::min<int64_t>((M + 3) / 4, (int64_t)h->num_cu * 8), s));
+        return SPG_OK;
+    }
     for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
         if (h->counts[cls] == 0) continue;
-        HIP_TRY(h, launch_numeric(a, b, ws, cls, h->counts[cls], persistent_grid(h, cls, h->counts[cls]),
-                                  c_rpt, c_col, c_val, s));
+        HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls]), c_rpt, c_col, c_val,
+                                  exact, s));
     }
-    if (h->counts[kClassHeavy] > 0) return run_heavy(h, a, b, ws, c_rpt, c_col, c_val, s);
+    if (h->counts[kClassHeavy] > 0) {
+        int64_t first = 0;
+        for (int c = 0; c < kClassHeavy; ++c) first += h->counts[c];
+        return run_heavy(h, a, b, ws, ws.class_rows + first, h->counts[kClassHeavy], c_rpt, c_col, c_val, exact,
+                         h->ctl, s);
+    }
+    return SPG_OK;
+}
+
+// ---- learned size predictor ------------------------------------------------
+
+int spg_mlp_set_params(spg_handle h, const float *params, const float *norm, float delta) {
+    if (!h || !params || !norm) return h ? fail(h, SPG_ERR_ARG, "params / norm is NULL") : SPG_ERR_ARG;
+    for (int j = 0; j < 6; ++j)
+        if (!(norm[6 + j] > 0.0f)) return fail(h, SPG_ERR_ARG, "feature standard deviations must be positive");
+    HIP_TRY(h, hipSetDevice(h->device));
+    int rc;
+    if ((rc = ensure_mlp(h))) return rc;
+    HIP_TRY(h, hipMemcpy(h->mlp, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->mlp + kMlpOffNorm, norm, sizeof(float) * 12, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(h->mlp + kMlpOffM, 0, sizeof(float) * 2 * kMlpParams));
+    h->adam_t = 0;
+    h->delta = delta;
+    h->mlp_ready = true;
+    return SPG_OK;
+}
+
+int spg_mlp_get_params(spg_handle h, float *params, float *norm, float *delta) {
+    if (!h) return SPG_ERR_ARG;
+    if (!h->mlp) return fail(h, SPG_ERR_NOT_TRAINED, "no predictor parameters");
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, hipDeviceSynchronize());
+    if (params) HIP_TRY(h, hipMemcpy(params, h->mlp, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    if (norm) HIP_TRY(h, hipMemcpy(norm, h->mlp + kMlpOffNorm, sizeof(float) * 12, hipMemcpyDeviceToHost));
+    if (delta) *delta = h->delta;
+    return SPG_OK;
+}
+
+int spg_mlp_features(spg_handle h, const spg_csr *A, const spg_csr *B, const int64_t *c_rpt, float *feats,
+                     float *targets, int8_t *predicted, int32_t *lo, int32_t *hi, void *stream) {
+    if (!h) return SPG_ERR_ARG;
+    int rc;
+    if ((rc = check_csr(h, A, "A", false)) || (rc = check_csr(h, B, "B", false))) return rc;
+    if (A->cols != B->rows) return fail(h, SPG_ERR_DIM, "inner dimensions differ");
+    if (!feats || !predicted || (targets && !c_rpt)) return fail(h, SPG_ERR_ARG, "feats / predicted / c_rpt is NULL");
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const CsrView a = view(A), b = view(B);
+    std::vector<int32_t> dummy;
+    int32_t *lo_p = lo, *hi_p = hi;
+    void *tmp = nullptr;
+    if (!lo || !hi) {
+        if (hipMalloc(&tmp, 8 * (size_t)std::max<int64_t>(A->rows, 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(h, SPG_ERR_NOMEM, "bound buffers");
+        }
+        lo_p = static_cast<int32_t *>(tmp);
+        hi_p = lo_p + std::max<int64_t>(A->rows, 1);
+    }
+    hipError_t e = launch_features(a, b, feats, lo_p, hi_p, predicted, c_rpt, targets, s);
+    if (tmp) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+    }
+    if (e != hipSuccess) return fail(h, SPG_ERR_HIP, "features: %s", hipGetErrorString(e));
+    return SPG_OK;
+}
+
+int spg_mlp_forward(spg_handle h, const float *feats, int64_t n, float *y, void *stream) {
+    if (!h || n < 0 || (n > 0 && (!feats || !y))) return h ? fail(h, SPG_ERR_ARG, "bad forward arguments") : SPG_ERR_ARG;
+    if (!h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "no predictor parameters");
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, launch_mlp_forward(n, feats, h->mlp, h->mlp + kMlpOffNorm, y, static_cast<hipStream_t>(stream)));
+    return SPG_OK;
+}
+
+int spg_mlp_gradient(spg_handle h, const float *feats, const float *targets, int64_t n, float *grad, float *loss,
+                     void *stream) {
+    if (!h || n <= 0 || !feats || !targets || !grad) return h ? fail(h, SPG_ERR_ARG, "bad gradient arguments") : SPG_ERR_ARG;
+    if (!h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "no predictor parameters");
+    HIP_TRY(h, hipSetDevice(h->device));
+    int rc;
+    if ((rc = ensure_mlp_act(h, n))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(h, launch_mlp_gradient(n, feats, targets, h->mlp, h->mlp + kMlpOffNorm, h->mlp_act,
+                                   h->mlp + kMlpOffPartial, grad, h->mlp + kMlpOffLoss, s));
+    if (loss) {
+        HIP_TRY(h, hipMemcpyAsync(loss, h->mlp + kMlpOffLoss, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+    }
+    return SPG_OK;
+}
+
+int spg_mlp_fit_normalization(spg_handle h, const float *feats, int64_t n, void *stream) {
+    if (!h || n <= 0 || !feats) return h ? fail(h, SPG_ERR_ARG, "bad normalization arguments") : SPG_ERR_ARG;
+    if (!h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "set initial parameters first");
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, launch_feature_stats(n, feats, h->mlp + kMlpOffNorm, static_cast<hipStream_t>(stream)));
+    return SPG_OK;
+}
+
+int spg_mlp_train(spg_handle h, const float *feats, const float *targets, int64_t n, int epochs, int batch,
+                  float lr, void *stream) {
+    if (!h || n <= 0 || !feats || !targets || epochs < 0 || batch <= 0 || !(lr > 0.0f))
+        return h ? fail(h, SPG_ERR_ARG, "bad training arguments") : SPG_ERR_ARG;
+    if (!h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "set initial parameters first");
+    HIP_TRY(h, hipSetDevice(h->device));
+    int rc;
+    if ((rc = ensure_mlp_act(h, batch))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *grad = h->mlp + kMlpOffG;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int64_t b0 = 0; b0 < n; b0 += batch) {
+            const int64_t nb = std::min<int64_t>(batch, n - b0);
+            HIP_TRY(h, launch_mlp_gradient(nb, feats + 6 * b0, targets + b0, h->mlp, h->mlp + kMlpOffNorm,
+                                           h->mlp_act, h->mlp + kMlpOffPartial, grad, nullptr, s));
+            ++h->adam_t;
+            HIP_TRY(h, launch_adam(h->mlp, grad, h->mlp + kMlpOffM, h->mlp + kMlpOffV, h->adam_t, lr, s));
+        }
+    }
+    return SPG_OK;
+}
+
+int spg_mlp_loss(spg_handle h, const float *feats, const float *targets, int64_t n, float *loss, void *stream) {
+    if (!h || n <= 0 || !feats || !targets || !loss) return h ? fail(h, SPG_ERR_ARG, "bad loss arguments") : SPG_ERR_ARG;
+    if (!h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "no predictor parameters");
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *y = nullptr;
+    if (hipMalloc(&y, sizeof(float) * (size_t)n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SPG_ERR_NOMEM, "loss buffer");
+    }
+    hipError_t e = launch_mlp_forward(n, feats, h->mlp, h->mlp + kMlpOffNorm, y, s);
+    if (e == hipSuccess) e = launch_mse(n, y, targets, h->mlp + kMlpOffLoss, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(loss, h->mlp + kMlpOffLoss, sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(y);
+    if (e != hipSuccess) return fail(h, SPG_ERR_HIP, "loss: %s", hipGetErrorString(e));
+    return SPG_OK;
+}
+
+int spg_mlp_calibrate(spg_handle h, const float *feats, const float *targets, int64_t n, double quantile,
+                      float *delta, void *stream) {
+    if (!h || n <= 0 || !feats || !targets || !(quantile >= 0.0 && quantile <= 1.0))
+        return h ? fail(h, SPG_ERR_ARG, "bad calibration arguments") : SPG_ERR_ARG;
+    if (!h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "no predictor parameters");
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *y = nullptr;
+    if (hipMalloc(&y, sizeof(float) * (size_t)n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SPG_ERR_NOMEM, "calibration buffer");
+    }
+    std::vector<float> hy((size_t)n), ht((size_t)n);
+    hipError_t e = launch_mlp_forward(n, feats, h->mlp, h->mlp + kMlpOffNorm, y, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), y, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ht.data(), targets, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(y);
+    if (e != hipSuccess) return fail(h, SPG_ERR_HIP, "calibration: %s", hipGetErrorString(e));
+    // margin: the `quantile` quantile of (target - prediction)
+    std::vector<float> r((size_t)n);
+    for (size_t i = 0; i < (size_t)n; ++i) r[i] = ht[i] - hy[i];
+    size_t k = (size_t)std::min<double>((double)(n - 1), std::ceil(quantile * (double)n) - 1.0 < 0 ? 0.0
+                                                                   : std::ceil(quantile * (double)n) - 1.0);
+    std::nth_element(r.begin(), r.begin() + (long)k, r.end());
+    h->delta = std::max(0.0f, r[k]);
+    if (delta) *delta = h->delta;
+    return SPG_OK;
+}
+
+int spg_mlp_save(spg_handle h, const char *path) {
+    if (!h || !path) return SPG_ERR_ARG;
+    if (!h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "no predictor parameters");
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, hipDeviceSynchronize());
+    std::vector<float> buf(3 * kMlpParams + 12);
+    HIP_TRY(h, hipMemcpy(buf.data(), h->mlp, sizeof(float) * 3 * kMlpParams, hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(buf.data() + 3 * kMlpParams, h->mlp + kMlpOffNorm, 48, hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(h, SPG_ERR_ARG, "cannot open %s", path);
+    const char magic[8] = {'B', 'R', 'M', 'M', 'L', 'P', '0', '1'};
+    const int64_t t = h->adam_t;
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&t, 8, 1, f) == 1 &&
+              std::fwrite(&h->delta, 4, 1, f) == 1 && std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? SPG_OK : fail(h, SPG_ERR_ARG, "write to %s failed", path);
+}
+
+int spg_mlp_load(spg_handle h, const char *path) {
+    if (!h || !path) return SPG_ERR_ARG;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(h, SPG_ERR_ARG, "cannot open %s", path);
+    char magic[8];
+    int64_t t = 0;
+    float delta = 0.0f;
+    std::vector<float> buf(3 * kMlpParams + 12);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "BRMMLP01", 8) == 0 &&
+              std::fread(&t, 8, 1, f) == 1 && std::fread(&delta, 4, 1, f) == 1 &&
+              std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return fail(h, SPG_ERR_ARG, "%s is not a predictor checkpoint", path);
+    HIP_TRY(h, hipSetDevice(h->device));
+    int rc;
+    if ((rc = ensure_mlp(h))) return rc;
+    HIP_TRY(h, hipMemcpy(h->mlp, buf.data(), sizeof(float) * 3 * kMlpParams, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->mlp + kMlpOffNorm, buf.data() + 3 * kMlpParams, 48, hipMemcpyHostToDevice));
+    h->adam_t = t;
+    h->delta = delta;
+    h->mlp_ready = true;
     return SPG_OK;
 }
 

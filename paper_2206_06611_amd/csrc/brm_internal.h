@@ -40,7 +40,10 @@ struct Ctl {
     int64_t nnz;        // nnz(C)
     int64_t nprod;      // total products
     int64_t err;        // error bits set by kernels
-    int64_t pad[5];
+    int64_t ovf_light;  // learned allocation: rows that did not fit their slot (light / heavy)
+    int64_t ovf_heavy;
+    int64_t pred_total; // learned allocation: sum of the predicted row sizes
+    int64_t pad[2];
 };
 
 enum CtlErr : int64_t {
@@ -79,10 +82,20 @@ hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds 
 hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s);
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                            int grid, hipStream_t s);
-hipError_t launch_scan(int64_t M, const Workspace &ws, int64_t *c_rpt, hipStream_t s);
+hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
+                       int64_t *total, hipStream_t s);
+
+// Output mode of the numeric kernels.
+struct NumOut {
+    int bound;          // 0: C slots are exact (symbolic counts); 1: slots are upper bounds
+    int32_t *row_size;  // bound mode: exact length of every row
+    int32_t *ovf_rows;  // bound mode: rows longer than their slot; 2*M entries, light rows
+                        // from index M-1 downwards, heavy rows from index M upwards
+    int64_t M;
+};
 hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
-                          int64_t rows_in_class, int grid, const int64_t *c_rpt, int32_t *c_col,
-                          double *c_val, hipStream_t s);
+                          int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val,
+                          const NumOut &no, hipStream_t s);
 
 // Heavy rows: one 1024-thread workgroup per row, spill buffers in HBM.
 struct HeavyArgs {
@@ -96,10 +109,33 @@ struct HeavyArgs {
     int32_t *leaf;
     int lds_cap;               // largest list range merged in LDS (products and lists)
 };
-hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, int64_t first, int64_t n,
+hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, const int32_t *rows, int64_t n,
                              int64_t *info, hipStream_t s);
 hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyArgs &h, int grid,
                                 const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
-                                hipStream_t s);
+                                const NumOut &no, hipStream_t s);
+
+// ---- learned allocation (brm_learned.hip) ---------------------------------
+constexpr int kMlpParams = 4673;
+constexpr int kMlpActStride = 6 + 4 * 64 + 1;
+constexpr int kMlpGradChunks = 64;
+hipError_t launch_features(const CsrView &A, const CsrView &B, float *feats, int32_t *lo, int32_t *hi,
+                           int8_t *predicted, const int64_t *c_rpt, float *targets, hipStream_t s);
+hipError_t launch_mlp_sizes(int64_t M, const float *feats, const int8_t *predicted, const int32_t *lo,
+                            const int32_t *hi, const int64_t *row_nprod, const float *params,
+                            const float *norm, float delta, int force, int32_t *pred_size, hipStream_t s);
+hipError_t launch_mlp_forward(int64_t n, const float *feats, const float *params, const float *norm,
+                              float *y, hipStream_t s);
+hipError_t launch_mlp_gradient(int64_t n, const float *feats, const float *targets, const float *params,
+                               const float *norm, float *act, float *partial, float *grad, float *loss,
+                               hipStream_t s);
+hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int64_t t, float lr,
+                       hipStream_t s);
+hipError_t launch_feature_stats(int64_t n, const float *feats, float *norm, hipStream_t s);
+hipError_t launch_mse(int64_t n, const float *y, const float *t, float *out, hipStream_t s);
+hipError_t launch_compact(int64_t M, const int64_t *slot_off, const int32_t *row_size, const int64_t *c_rpt,
+                          const int32_t *s_col, const double *s_val, int32_t *c_col, double *c_val,
+                          int grid, hipStream_t s);
+hipError_t launch_fallback_ctl(const Ctl *src, Ctl *dst, int64_t M, hipStream_t s);
 
 }  // namespace brm

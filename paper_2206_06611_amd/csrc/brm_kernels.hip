@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t M, const i
 }
 
 __global__ __launch_bounds__(1024) void k_scan_top(int64_t ntiles, int64_t *tile_sum, int64_t M,
-                                                   int64_t *c_rpt, Ctl *ctl) {
+                                                   int64_t *c_rpt, int64_t *total) {
     __shared__ int64_t scr[Team<1024>::kWaves + 1];
     int64_t carry = 0;
     for (int64_t b = 0; b < ntiles; b += 1024) {
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(int64_t ntiles, int64_t *tile
         carry += tot;
     }
     if (threadIdx.x == 0) {
-        ctl->nnz = carry;
+        *total = carry;
         c_rpt[M] = carry;
     }
 }
@@ -513,16 +513,40 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t M, const in
     }
 }
 
-hipError_t launch_scan(int64_t M, const Workspace &ws, int64_t *c_rpt, hipStream_t s) {
+hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
+                       int64_t *total, hipStream_t s) {
     const int64_t ntiles = (M + kScanTile - 1) / kScanTile;
     if (ntiles > 0)
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M,
-                           ws.row_size, ws.tile_sum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ntiles, ws.tile_sum, M, c_rpt, ws.ctl);
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, sizes,
+                           tile_sum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ntiles, tile_sum, M, out_rpt, total);
     if (ntiles > 0)
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M,
-                           ws.row_size, ws.tile_sum, c_rpt);
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, sizes,
+                           tile_sum, out_rpt);
     return hipGetLastError();
+}
+
+// End of a row of the numeric pass.  Exact mode: the slot came from the
+// symbolic count and must match.  Bound mode (learned allocation): the slot
+// is a predicted upper bound; the exact length is recorded and a row that did
+// not fit is queued for the exact fallback.
+__device__ __forceinline__ void finish_row(const NumOut &no, Ctl *ctl, int64_t row, int64_t len,
+                                           int64_t cap, bool heavy) {
+    if (!no.bound) {
+        if (len != cap)
+            atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+        return;
+    }
+    no.row_size[row] = (int32_t)len;
+    if (len > cap) {
+        if (heavy) {
+            const unsigned long long i = atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->ovf_heavy), 1ull);
+            no.ovf_rows[no.M + (int64_t)i] = (int32_t)row;
+        } else {
+            const unsigned long long i = atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->ovf_light), 1ull);
+            no.ovf_rows[no.M - 1 - (int64_t)i] = (int32_t)row;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -533,7 +557,7 @@ __global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, co
                                                   const double *a_val, const void *b_rpt,
                                                   const int32_t *b_col, const double *b_val,
                                                   const int32_t *class_rows, const int64_t *c_rpt,
-                                                  int32_t *c_col, double *c_val, Ctl *ctl) {
+                                                  int32_t *c_col, double *c_val, Ctl *ctl, NumOut no) {
     const int lane = lane_id();
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
@@ -548,8 +572,7 @@ __global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, co
         const int64_t n = ld_rpt<IB>(b_rpt, k + 1) - bs;
         const int64_t cs = c_rpt[row];
         const int64_t cap = c_rpt[row + 1] - cs;
-        if (n != cap && lane == 0)
-            atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+        if (lane == 0) finish_row(no, ctl, row, n, cap, false);
         const int64_t m = n < cap ? n : cap;
         for (int64_t j = lane; j < m; j += kWave) {
             c_col[cs + j] = b_col[bs + j];
@@ -781,17 +804,15 @@ __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int6
                                                 const double *a_val, const void *b_rpt,
                                                 const int32_t *b_col, const double *b_val,
                                                 const int64_t *c_rpt, int32_t *c_col,
-                                                double *c_val, Ctl *ctl) {
+                                                double *c_val, Ctl *ctl, const NumOut &no) {
     const int64_t a0 = ld_rpt<IA>(a_rpt, row);
     const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
     const int64_t cs = c_rpt[row];
     const int64_t cap = c_rpt[row + 1] - cs;
     const int rl = brmerge_range_lds<T, CAP, IB>(s, tid, a0, L, a_col, a_val, b_rpt, b_col, b_val,
                                                  c_col + cs, c_val + cs, cap);
-    // Algorithm 1's final store went straight to C's row; a length that
-    // differs from the symbolic count is reported (the row was truncated)
-    if (tid == 0 && (int64_t)rl != cap)
-        atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+    // Algorithm 1's final store went straight to C's row (truncated to the slot)
+    if (tid == 0) finish_row(no, ctl, row, rl, cap, false);
 }
 
 template <int T, int TEAMS, int CAP, typename IA, typename IB>
@@ -801,7 +822,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt
                                                       const double *b_val,
                                                       const int32_t *class_rows,
                                                       const int64_t *c_rpt, int32_t *c_col,
-                                                      double *c_val, Ctl *ctl) {
+                                                      double *c_val, Ctl *ctl, NumOut no) {
     __shared__ NumLds<T, CAP> lds[TEAMS];
     const int team = threadIdx.x / T, tid = threadIdx.x % T;
     const int64_t count = ctl->count[cls];
@@ -810,17 +831,16 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt
          idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t row = class_rows[start + idx];
         brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, row, a_rpt, a_col, a_val, b_rpt, b_col,
-                                        b_val, c_rpt, c_col, c_val, ctl);
+                                        b_val, c_rpt, c_col, c_val, ctl, no);
     }
 }
 
 hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
-                          int64_t rows_in_class, int grid, const int64_t *c_rpt, int32_t *c_col,
-                          double *c_val, hipStream_t s) {
-    (void)rows_in_class;
+                          int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val,
+                          const NumOut &no, hipStream_t s) {
 #define BRM_NUM(KERNEL, BLOCK)                                                                   \
     hipLaunchKernelGGL((KERNEL), dim3(grid), dim3(BLOCK), 0, s, cls, A.rpt, A.col, A.val, B.rpt, \
-                       B.col, B.val, ws.class_rows, c_rpt, c_col, c_val, ws.ctl)
+                       B.col, B.val, ws.class_rows, c_rpt, c_col, c_val, ws.ctl, no)
 #define BRM_NUM_ALL(T, TEAMS, CAP)                                                               \
     do {                                                                                         \
         if (A.rpt_bytes == 4 && B.rpt_bytes == 4)                                                \
@@ -1106,7 +1126,7 @@ template <typename IA, typename IB>
 __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
     HeavyBatch hb, const void *a_rpt, const int32_t *a_col, const double *a_val, const void *b_rpt,
     const int32_t *b_col, const double *b_val, const int64_t *c_rpt, int32_t *c_col, double *c_val,
-    Ctl *ctl) {
+    Ctl *ctl, NumOut no) {
     constexpr size_t kUnion = sizeof(NumLds<kHeavyThreads, kCapBlock>) > sizeof(MergeLds)
                                   ? sizeof(NumLds<kHeavyThreads, kCapBlock>)
                                   : sizeof(MergeLds);
@@ -1266,15 +1286,14 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
             // global stores of this workgroup become visible to it at the barrier (workgroup scope)
             __syncthreads();
         }
-        if (tid == 0 && st.sp == 1 && st.stack[0].len != ccap)
-            atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+        if (tid == 0 && st.sp == 1) finish_row(no, ctl, row, st.stack[0].len, ccap, true);
         __syncthreads();
     }
 }
 
 hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyArgs &h, int grid,
                                 const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
-                                hipStream_t s) {
+                                const NumOut &no, hipStream_t s) {
     HeavyBatch hb;
     hb.ticket = h.ticket;
     hb.rows = h.rows;
@@ -1287,7 +1306,7 @@ hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyA
     hb.lds_cap = h.lds_cap;
 #define BRM_HEAVY(IA, IB)                                                                          \
     hipLaunchKernelGGL((k_num_heavy<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, hb, A.rpt,    \
-                       A.col, A.val, B.rpt, B.col, B.val, c_rpt, c_col, c_val, ctl)
+                       A.col, A.val, B.rpt, B.col, B.val, c_rpt, c_col, c_val, ctl, no)
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_HEAVY(int32_t, int32_t);
     else if (A.rpt_bytes == 4) BRM_HEAVY(int32_t, int64_t);
     else if (B.rpt_bytes == 4) BRM_HEAVY(int64_t, int32_t);
@@ -1309,16 +1328,16 @@ __global__ void k_heavy_info(int64_t n, const int32_t *rows, const void *a_rpt,
     }
 }
 
-hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, int64_t first, int64_t n,
+hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, const int32_t *rows, int64_t n,
                              int64_t *info, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const unsigned g = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
     if (A.rpt_bytes == 4)
-        hipLaunchKernelGGL(k_heavy_info<int32_t>, dim3(g), dim3(256), 0, s, n, ws.class_rows + first,
-                           A.rpt, ws.row_nprod, info);
+        hipLaunchKernelGGL(k_heavy_info<int32_t>, dim3(g), dim3(256), 0, s, n, rows, A.rpt, ws.row_nprod,
+                           info);
     else
-        hipLaunchKernelGGL(k_heavy_info<int64_t>, dim3(g), dim3(256), 0, s, n, ws.class_rows + first,
-                           A.rpt, ws.row_nprod, info);
+        hipLaunchKernelGGL(k_heavy_info<int64_t>, dim3(g), dim3(256), 0, s, n, rows, A.rpt, ws.row_nprod,
+                           info);
     return hipGetLastError();
 }
 

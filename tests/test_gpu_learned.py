@@ -1,0 +1,180 @@
+"""GPU checks of the learned allocation: features, forward pass, gradient and
+Adam against the float64 CPU reference; training; learned-mode products
+bitwise equal to the precise path, with the fallback taking exactly the rows
+that overflow their predicted slot."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_matches_oracle, to_host
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2206_06611_amd as brm  # noqa: E402
+from paper_2206_06611_amd import learned  # noqa: E402
+
+
+@pytest.fixture()
+def handle():
+    h = brm.Handle(0)
+    h.set_option(brm.OPT_VALIDATE, 1)
+    yield h
+    h.close()
+
+
+def dev(A):
+    return brm.DeviceCSR.from_host(A)
+
+
+def test_features_match_definition(handle):
+    A = synth.rmat(11, 8, 31)
+    dA = dev(A)
+    c_rpt, _ = handle.symbolic(dA, dA)
+    feats, targets, pred, lo, hi = handle.mlp_features(dA, dA, c_rpt)
+    f = oracle.row_features(A, A)
+    raw = mlp.raw_features(f["nnza"], f["nprod"], f["maxb"], f["minb"], f["span"])
+    assert np.allclose(feats.cpu().numpy(), raw, rtol=1e-6, atol=1e-6)
+    want_pred = (f["nprod"] > 0) & (f["nnza"] >= 2)
+    assert np.array_equal(pred.cpu().numpy().astype(bool), want_pred)
+    nnzc = np.diff(oracle.spgemm(A, A).rpt)
+    lo, hi = lo.cpu().numpy(), hi.cpu().numpy()
+    assert np.all(lo <= nnzc) and np.all(nnzc <= hi)
+    t = targets.cpu().numpy()[want_pred]
+    assert np.allclose(t, np.log(nnzc[want_pred] / f["nprod"][want_pred]), atol=1e-6)
+
+
+def _batch(seed, n=300):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, 6)).astype(np.float32) * 2 + 1
+    t = rng.standard_normal(n).astype(np.float32) * 0.5 - 0.3
+    return x, t
+
+
+def test_forward_and_gradient_match_reference(handle):
+    theta = mlp.init_params(7)
+    rng = np.random.default_rng(8)
+    theta = (theta + rng.standard_normal(theta.size).astype(np.float32) * 0.05).astype(np.float32)
+    norm = np.array([1.0, 0.5, -0.2, 0.0, 0.3, 0.1, 2.0, 1.5, 1.0, 0.7, 1.2, 0.9], np.float32)
+    handle.mlp_set_params(theta, norm, 0.0)
+    x, t = _batch(1)
+    xn = (x.astype(np.float64) - norm[:6]) / norm[6:]
+    xd, td = torch.as_tensor(x, device="cuda"), torch.as_tensor(t, device="cuda")
+    y = handle.mlp_forward(xd).cpu().numpy()
+    yr, _ = mlp.forward(theta.astype(np.float64), xn)
+    assert np.allclose(y, yr, rtol=1e-5, atol=1e-5)
+    g, loss = handle.mlp_gradient(xd, td)
+    lr_, gr = mlp.loss_and_grad(theta.astype(np.float64), xn, t.astype(np.float64))
+    g = g.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+    assert loss == pytest.approx(lr_, rel=1e-5)
+
+
+def test_adam_step_matches_formula(handle):
+    theta = mlp.init_params(3)
+    norm = np.array([0.0] * 6 + [1.0] * 6, np.float32)
+    handle.mlp_set_params(theta, norm, 0.0)
+    x, t = _batch(2, 500)
+    xd, td = torch.as_tensor(x, device="cuda"), torch.as_tensor(t, device="cuda")
+    g, _ = handle.mlp_gradient(xd, td)
+    g = g.cpu().numpy().astype(np.float64)
+    handle.mlp_train(xd, td, epochs=1, batch=500, lr=1e-2)
+    new, _, _ = handle.mlp_get_params()
+    want, _, _ = mlp.adam_step(theta.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-2)
+    assert np.max(np.abs(new - want)) <= 2e-6
+
+
+def training_set(h):
+    pairs = []
+    for A in (synth.laplacian_2d_5pt(64), synth.erdos_renyi_rows(1 << 14, 8, 12), synth.rmat(13, 16, 13)):
+        d = dev(A)
+        pairs.append((d, d))
+    return learned.collect(h, pairs)
+
+
+def test_training_reduces_loss_and_save_load(handle, tmp_path):
+    feats, targets = training_set(handle)
+    loss0, loss1, delta = learned.train(handle, feats, targets, seed=1, epochs=6)
+    assert loss1 < 0.5 * loss0
+    assert delta >= 0.0
+    p = str(tmp_path / "mlp.bin")
+    handle.mlp_save(p)
+    h2 = brm.Handle(0)
+    h2.mlp_load(p)
+    a, b, c = handle.mlp_get_params()
+    a2, b2, c2 = h2.mlp_get_params()
+    assert np.array_equal(a, a2) and np.array_equal(b, b2) and c == c2
+    y1 = handle.mlp_forward(feats[:1000]).cpu().numpy()
+    y2 = h2.mlp_forward(feats[:1000]).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    h2.close()
+
+
+def test_learned_requires_predictor(handle):
+    A = dev(synth.laplacian_2d_5pt(8))
+    handle.set_option(brm.OPT_ALLOC, brm.ALLOC_LEARNED)
+    with pytest.raises(brm.SpgError) as e:
+        handle.spgemm(A, A)
+    assert e.value.code == brm.SPG_ERR_NOT_TRAINED
+
+
+@pytest.mark.parametrize("force", [0, 1])
+def test_learned_products_bitwise_equal(handle, force):
+    feats, targets = training_set(handle)
+    learned.train(handle, feats, targets, seed=2, epochs=4)
+    cases = [synth.erdos_renyi_rows(1 << 13, 8, 99), synth.rmat(12, 16, 98), synth.stencil_3d_27pt(10),
+             synth.laplacian_2d_5pt(40)]
+    for A in cases:
+        dA = dev(A)
+        handle.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+        base = to_host(handle.spgemm(dA, dA))
+        handle.set_option(brm.OPT_ALLOC, brm.ALLOC_LEARNED)
+        handle.set_option(brm.OPT_LEARNED_FORCE, force)
+        C = handle.spgemm(dA, dA)
+        torch.cuda.synchronize()
+        assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+        got = to_host(C)
+        for x, y in zip(base, got):
+            assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                                  y.view(np.int64) if y.dtype == np.float64 else y)
+        f = oracle.row_features(A, A)
+        nnzc = np.diff(base[0])
+        predicted = (f["nprod"] > 0) & (f["nnza"] >= 2)
+        assert handle.stat(brm.STAT_PREDICTED_ROWS) == int(predicted.sum())
+        if force == 1:
+            # every predicted row sits at its lower bound: exactly the rows
+            # longer than their longest list take the fallback
+            want = int((predicted & (nnzc > f["maxb"])).sum())
+            assert handle.stat(brm.STAT_OVERFLOW_ROWS) == want
+        assert handle.stat(brm.STAT_PRED_TOTAL) >= 0
+    ref = oracle.spgemm(cases[1], cases[1])
+    assert_matches_oracle(C if False else handle_spgemm_again(handle, cases[1]), ref, oracle.brmerge(cases[1], cases[1]))
+    handle.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+    handle.set_option(brm.OPT_LEARNED_FORCE, 0)
+
+
+def handle_spgemm_again(h, A):
+    dA = dev(A)
+    C = h.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    return C
+
+
+def test_learned_heavy_rows(handle):
+    feats, targets = training_set(handle)
+    learned.train(handle, feats, targets, seed=3, epochs=3)
+    A = synth.rmat(13, 16, 97)
+    handle.set_option(brm.OPT_ALLOC, brm.ALLOC_LEARNED)
+    handle.set_option(brm.OPT_LEARNED_FORCE, 1)  # heavy rows overflow too
+    C = handle_spgemm_again(handle, A)
+    assert handle.class_rows()["heavy"] > 0 and handle.stat(brm.STAT_OVERFLOW_ROWS) > 0
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+    handle.set_option(brm.OPT_LEARNED_FORCE, 0)
+    C = handle_spgemm_again(handle, A)
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
