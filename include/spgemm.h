@@ -126,6 +126,8 @@ typedef enum {
     SPG_STAT_PRED_TOTAL = 21,    /* learned allocation: sum of the predicted row sizes (slot entries) */
     SPG_STAT_OVERFLOW_ROWS = 22, /* learned allocation: rows longer than their predicted slot */
     SPG_STAT_PREDICTED_ROWS = 23,/* rows whose size is predicted (two or more lists, a product) */
+    SPG_STAT_GRAPH_CAPTURES = 24,/* batched calls that (re)captured their HIP graph */
+    SPG_STAT_GRAPH_LAUNCHES = 25,/* batched calls that replayed a captured graph */
     SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call
                                     (16: a numeric row length differed from its symbolic count;
                                     the row was truncated to its slot).  Synchronizes the device. */
@@ -157,6 +159,47 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
  * Errors: SPG_ERR_ARG, SPG_ERR_STATE, SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64_t *c_rpt,
                    int32_t *c_col, double *c_val, void *stream);
+
+/* ---- Batched products ----------------------------------------------------
+ * Many independent products C_p = A_p * B_p in one call, for instance the
+ * Galerkin triple products P^T (A P) of an algebraic multigrid setup (the
+ * paper's first application, Section I).  A problem's B may be the C of an
+ * earlier problem of the same call (b_from >= 0), which makes chains such as
+ * AP = A * P, G = P^T * AP possible without host round trips.  Problems are
+ * grouped into stages by their dependencies; each stage runs the same
+ * analysis / binning / symbolic / scan / numeric kernels as the single
+ * product over the union of its problems' rows, and C's arrays are placed
+ * in the caller's arena at offsets computed on the device.  The whole launch
+ * sequence is captured once in a HIP graph and replayed while the problems
+ * (pointers, sizes), the arena and the options stay the same.  Results are
+ * bitwise equal to separate spgemm_symbolic / spgemm_numeric calls.
+ * Rows with more than 4096 products are not supported here (SPG_ERR_CAPACITY
+ * with *required_bytes = -1); use the single-product calls for them. */
+typedef struct {
+    spg_csr A;        /* device CSR */
+    spg_csr B;        /* device CSR; ignored when b_from >= 0 */
+    int32_t b_from;   /* -1, or the index (< this one) of the problem whose C is B */
+} spg_problem;
+
+/* Where problem p's C sits in the arena (byte offsets; nnz = -1 when the
+ * arena was too small). */
+typedef struct {
+    int64_t rows, cols, nnz;
+    int64_t rpt_off;  /* int64[rows + 1] */
+    int64_t col_off;  /* int32[nnz] */
+    int64_t val_off;  /* double[nnz] */
+} spg_batched_out;
+
+/* Computes every problem into `arena` (device, arena_bytes long, 256-byte
+ * aligned).  `out` is a DEVICE array of `count` descriptors.  Blocks until the
+ * batch is done (one device-to-host read of the batch status).  Problems of
+ * one stage must share the row-pointer widths of A and of B (chained B always
+ * has int64 row pointers).
+ * Errors: SPG_ERR_ARG, SPG_ERR_DIM (A_p.cols != B_p.rows), SPG_ERR_CAPACITY
+ * (arena too small: *required_bytes is set to the size needed, the outputs
+ * are invalid), SPG_ERR_NOMEM, SPG_ERR_HIP. */
+int spgemm_batched(spg_handle h, int count, const spg_problem *problems, void *arena, int64_t arena_bytes,
+                   spg_batched_out *out, int64_t *required_bytes, void *stream);
 
 /* ---- Learned allocation --------------------------------------------------
  * Not in the paper: a stand-in for its allocation step (Section II-B.2).  A

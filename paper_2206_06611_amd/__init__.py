@@ -53,6 +53,8 @@ STAT_HEAVY_BATCHES = 20
 STAT_PRED_TOTAL = 21
 STAT_OVERFLOW_ROWS = 22
 STAT_PREDICTED_ROWS = 23
+STAT_GRAPH_CAPTURES = 24
+STAT_GRAPH_LAUNCHES = 25
 STAT_DEVICE_ERR = 30
 
 CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy"]
@@ -74,6 +76,14 @@ class _Csr(ctypes.Structure):
         ("col", ctypes.c_void_p),
         ("val", ctypes.c_void_p),
     ]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("A", _Csr), ("B", _Csr), ("b_from", ctypes.c_int32)]
+
+
+class _BatchedOut(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("rows", "cols", "nnz", "rpt_off", "col_off", "val_off")]
 
 
 def _load_library():
@@ -104,6 +114,7 @@ def _load_library():
         "spg_mlp_calibrate": ([P, P, P, I64, ctypes.c_double, P, P], I32),
         "spg_mlp_save": ([P, ctypes.c_char_p], I32),
         "spg_mlp_load": ([P, ctypes.c_char_p], I32),
+        "spgemm_batched": ([P, I32, ctypes.POINTER(_Problem), P, I64, P, ctypes.POINTER(I64), P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -119,7 +130,7 @@ EXPORTED = ("spg_create", "spg_destroy", "spg_set_option", "spg_get_option", "sp
             "spgemm_symbolic", "spgemm_numeric", "spg_last_error", "spg_mlp_set_params",
             "spg_mlp_get_params", "spg_mlp_features", "spg_mlp_forward", "spg_mlp_gradient",
             "spg_mlp_fit_normalization", "spg_mlp_train", "spg_mlp_loss", "spg_mlp_calibrate",
-            "spg_mlp_save", "spg_mlp_load")
+            "spg_mlp_save", "spg_mlp_load", "spgemm_batched")
 
 
 def library():
@@ -316,6 +327,57 @@ class Handle:
 
     def mlp_load(self, path: str):
         self._check(_lib.spg_mlp_load(self._h, path.encode()))
+
+    # ---- batched products -------------------------------------------------
+    def batched(self, problems, arena: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        """problems: list of (A, B) where B is a DeviceCSR or the index of an
+        earlier problem whose C is B.  arena: uint8 device tensor.  Returns
+        (status, required_bytes, outputs); outputs are DeviceCSR views into the
+        arena (None when the arena was too small)."""
+        n = len(problems)
+        arr = (_Problem * max(n, 1))()
+        for i, (A, B) in enumerate(problems):
+            arr[i].A = A._struct()
+            if isinstance(B, int):
+                arr[i].b_from = B
+            else:
+                arr[i].B = B._struct()
+                arr[i].b_from = -1
+        if out is None:
+            out = torch.empty((max(n, 1), 6), dtype=torch.int64, device=arena.device)
+        req = ctypes.c_int64()
+        rc = _lib.spgemm_batched(self._h, n, arr, ctypes.c_void_p(arena.data_ptr()), arena.numel(),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.byref(req), _stream_ptr(stream))
+        if rc not in (SPG_OK, SPG_ERR_CAPACITY):
+            self._check(rc)
+        if rc != SPG_OK:
+            return rc, req.value, None
+        desc = out[:n].cpu().tolist()
+        outs = []
+        for rows, cols, nnz, ro, co, vo in desc:
+            rpt = arena[ro:ro + 8 * (rows + 1)].view(torch.int64)
+            col = arena[co:co + 4 * nnz].view(torch.int32)
+            val = arena[vo:vo + 8 * nnz].view(torch.float64)
+            outs.append(DeviceCSR(int(rows), int(cols), rpt, col, val))
+        return rc, req.value, outs
+
+    def galerkin(self, triples, arena: torch.Tensor | None = None, stream=None):
+        """G_i = P_i^T (A_i P_i) for triples (A_i, P_i, Pt_i) in one batched
+        call (stage 1: A_i P_i, stage 2: Pt_i times stage 1's output).  Grows
+        the arena when it is too small.  Returns (G list, AP list, arena)."""
+        n = len(triples)
+        probs = [(A, P) for A, P, _ in triples] + [(Pt, i) for i, (_, _, Pt) in enumerate(triples)]
+        if arena is None:
+            est = sum(8 * (A.rows + 1) + 8 * (Pt.rows + 1) + 12 * 27 * A.rows + 8192 for A, _, Pt in triples)
+            arena = torch.empty(est, dtype=torch.uint8, device=triples[0][0].rpt.device)
+        for _ in range(2):
+            rc, req, outs = self.batched(probs, arena, stream=stream)
+            if rc == SPG_OK:
+                return outs[n:], outs[:n], arena
+            if req < 0:
+                raise SpgError(rc, _lib.spg_last_error(self._h).decode())
+            arena = torch.empty(req, dtype=torch.uint8, device=arena.device)
+        raise SpgError(SPG_ERR_CAPACITY, "arena sizing failed")
 
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None) -> DeviceCSR:
         """C = A*B: symbolic pass, allocation of C, numeric pass."""

@@ -65,6 +65,18 @@ struct spg_handle_s {
     bool mlp_ready = false;
     float delta = 0.0f;
     int64_t adam_t = 0;
+    // batched products: own buffers (referenced by the captured graph)
+    void *b_mem = nullptr;       // workspace rows | S | row offsets | table | status | ctl
+    size_t b_bytes = 0;
+    BatchProb *b_host = nullptr; // pinned host copy of the table
+    size_t b_host_n = 0;
+    int64_t *b_row_off_host = nullptr;
+    size_t b_row_off_n = 0;
+    BatchStatus *b_status_host = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<int64_t> graph_sig;
+    int64_t graph_captures = 0, graph_launches = 0;
 };
 
 struct LearnedWs {
@@ -385,6 +397,12 @@ int spg_destroy(spg_handle h) {
     if (h->ctl2) (void)hipFree(h->ctl2);
     if (h->mlp) (void)hipFree(h->mlp);
     if (h->mlp_act) (void)hipFree(h->mlp_act);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->b_mem) (void)hipFree(h->b_mem);
+    if (h->b_host) (void)hipHostFree(h->b_host);
+    if (h->b_row_off_host) (void)hipHostFree(h->b_row_off_host);
+    if (h->b_status_host) (void)hipHostFree(h->b_status_host);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->ctl_host) (void)hipHostFree(h->ctl_host);
     delete h;
@@ -475,6 +493,8 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_NNZ: *value = h->nnz; return SPG_OK;
         case SPG_STAT_HEAVY_BATCHES: *value = h->heavy_batches; return SPG_OK;
         case SPG_STAT_PRED_TOTAL: *value = h->pred_total; return SPG_OK;
+        case SPG_STAT_GRAPH_CAPTURES: *value = h->graph_captures; return SPG_OK;
+        case SPG_STAT_GRAPH_LAUNCHES: *value = h->graph_launches; return SPG_OK;
         case SPG_STAT_OVERFLOW_ROWS: *value = h->ovf_light + h->ovf_heavy; return SPG_OK;
         case SPG_STAT_PREDICTED_ROWS: {
             int64_t n = 0;
@@ -861,6 +881,236 @@ int spg_mlp_load(spg_handle h, const char *path) {
     h->adam_t = t;
     h->delta = delta;
     h->mlp_ready = true;
+    return SPG_OK;
+}
+
+// ---- batched products ------------------------------------------------------
+
+int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *arena, int64_t arena_bytes,
+                   spg_batched_out *out, int64_t *required_bytes, void *stream) {
+    if (!h) return SPG_ERR_ARG;
+    h->err.clear();
+    if (count < 0 || (count > 0 && (!probs || !arena || !out)) || !required_bytes || arena_bytes < 0)
+        return fail(h, SPG_ERR_ARG, "bad batched arguments");
+    *required_bytes = 0;
+    if (count == 0) return SPG_OK;
+    if (reinterpret_cast<uintptr_t>(arena) % 256) return fail(h, SPG_ERR_ARG, "arena must be 256-byte aligned");
+    int rc;
+    // stages from the dependencies; problems must come in stage order
+    std::vector<int> stage((size_t)count, 0);
+    std::vector<int64_t> crows((size_t)count), ccols((size_t)count);
+    for (int p = 0; p < count; ++p) {
+        const spg_problem &q = probs[p];
+        if ((rc = check_csr(h, &q.A, "A", true))) return rc;
+        int64_t brows, bcols;
+        if (q.b_from >= 0) {
+            if (q.b_from >= p) return fail(h, SPG_ERR_ARG, "problem %d: b_from must name an earlier problem", p);
+            stage[(size_t)p] = stage[(size_t)q.b_from] + 1;
+            brows = crows[(size_t)q.b_from];
+            bcols = ccols[(size_t)q.b_from];
+        } else {
+            if ((rc = check_csr(h, &q.B, "B", true))) return rc;
+            brows = q.B.rows;
+            bcols = q.B.cols;
+        }
+        if (q.A.cols != brows) return fail(h, SPG_ERR_DIM, "problem %d: A.cols != B.rows", p);
+        if (p > 0 && stage[(size_t)p] < stage[(size_t)p - 1])
+            return fail(h, SPG_ERR_ARG, "problems must be ordered by stage (problem %d)", p);
+        crows[(size_t)p] = q.A.rows;
+        ccols[(size_t)p] = bcols;
+    }
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // stage ranges, row offsets, widths
+    struct StageInfo { int first, n; int64_t rows; int arb, brb; bool link; size_t roff; };
+    std::vector<StageInfo> st;
+    size_t roff_total = 0;
+    for (int p = 0; p < count;) {
+        int q = p;
+        StageInfo si{p, 0, 0, probs[p].A.rpt_bytes, probs[p].b_from >= 0 ? 8 : probs[p].B.rpt_bytes, false, roff_total};
+        while (q < count && stage[(size_t)q] == stage[(size_t)p]) {
+            const int brb = probs[q].b_from >= 0 ? 8 : probs[q].B.rpt_bytes;
+            if (probs[q].A.rpt_bytes != si.arb || brb != si.brb)
+                return fail(h, SPG_ERR_ARG, "problems of one stage must share row-pointer widths (problem %d)", q);
+            si.rows += probs[q].A.rows;
+            si.link = si.link || probs[q].b_from >= 0;
+            ++q;
+        }
+        si.n = q - p;
+        roff_total += (size_t)si.n + 1;
+        st.push_back(si);
+        p = q;
+    }
+    int64_t max_rows = 0;
+    for (auto &x : st) max_rows = std::max(max_rows, x.rows);
+    if (max_rows > INT32_MAX) return fail(h, SPG_ERR_ARG, "too many rows in one stage");
+    // arena: row pointers first (sizes known now), then C's columns and values
+    int64_t rpt_end = 0;
+    std::vector<int64_t> rpt_off((size_t)count);
+    for (int p = 0; p < count; ++p) {
+        rpt_off[(size_t)p] = rpt_end;
+        rpt_end += (int64_t)align_up(8 * (size_t)(crows[(size_t)p] + 1), 256);
+    }
+    if (rpt_end > arena_bytes) {
+        *required_bytes = rpt_end;
+        return fail(h, SPG_ERR_CAPACITY, "arena smaller than the row pointers alone (%lld bytes)", (long long)rpt_end);
+    }
+    // buffers: workspace rows | S | row offsets | table | status | ctl
+    const size_t a = 256;
+    const size_t o_nprod = 0;
+    const size_t o_class = align_up(o_nprod + 8 * (size_t)max_rows, a);
+    const size_t o_size = align_up(o_class + (size_t)max_rows, a);
+    const size_t o_rows = align_up(o_size + 4 * (size_t)max_rows, a);
+    const size_t o_tile = align_up(o_rows + 4 * (size_t)max_rows, a);
+    const size_t o_S = align_up(o_tile + 8 * (size_t)((max_rows + kScanTile - 1) / kScanTile + 1), a);
+    const size_t o_roff = align_up(o_S + 8 * (size_t)(max_rows + 1), a);
+    const size_t o_tab = align_up(o_roff + 8 * roff_total, a);
+    const size_t o_stat = align_up(o_tab + sizeof(BatchProb) * (size_t)count, a);
+    const size_t o_ctl = align_up(o_stat + sizeof(BatchStatus), a);
+    const size_t total = align_up(o_ctl + sizeof(Ctl), a);
+    bool realloc = false;
+    if (total > h->b_bytes) {
+        if (h->graph_exec) {
+            HIP_TRY(h, hipStreamSynchronize(s));
+            (void)hipGraphExecDestroy(h->graph_exec);
+            h->graph_exec = nullptr;
+        }
+        if ((rc = grow(h, &h->b_mem, &h->b_bytes, total, "batched workspace"))) return rc;
+        realloc = true;
+    }
+    if ((size_t)count > h->b_host_n) {
+        if (h->b_host) HIP_TRY(h, hipHostFree(h->b_host));
+        h->b_host = nullptr;
+        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_host), sizeof(BatchProb) * (size_t)count,
+                                 hipHostMallocDefault));
+        h->b_host_n = (size_t)count;
+    }
+    if (roff_total > h->b_row_off_n) {
+        if (h->b_row_off_host) HIP_TRY(h, hipHostFree(h->b_row_off_host));
+        h->b_row_off_host = nullptr;
+        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_row_off_host), 8 * roff_total, hipHostMallocDefault));
+        h->b_row_off_n = roff_total;
+    }
+    if (!h->b_status_host)
+        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_status_host), sizeof(BatchStatus), hipHostMallocDefault));
+    if (!h->cap_stream) HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    char *base = static_cast<char *>(h->b_mem);
+    Workspace ws;
+    ws.row_nprod = reinterpret_cast<int64_t *>(base + o_nprod);
+    ws.row_class = reinterpret_cast<uint8_t *>(base + o_class);
+    ws.row_size = reinterpret_cast<int32_t *>(base + o_size);
+    ws.class_rows = reinterpret_cast<int32_t *>(base + o_rows);
+    ws.tile_sum = reinterpret_cast<int64_t *>(base + o_tile);
+    ws.ctl = reinterpret_cast<Ctl *>(base + o_ctl);
+    int64_t *d_S = reinterpret_cast<int64_t *>(base + o_S);
+    int64_t *d_roff = reinterpret_cast<int64_t *>(base + o_roff);
+    BatchProb *d_tab = reinterpret_cast<BatchProb *>(base + o_tab);
+    BatchStatus *d_stat = reinterpret_cast<BatchStatus *>(base + o_stat);
+    char *arena_c = static_cast<char *>(arena);
+    // host table
+    for (auto &x : st) {
+        int64_t ro = 0;
+        for (int i = 0; i < x.n; ++i) {
+            const int p = x.first + i;
+            const spg_problem &q = probs[p];
+            BatchProb &b = h->b_host[p];
+            std::memset(&b, 0, sizeof b);
+            b.row_off = ro;
+            b.rows = q.A.rows;
+            b.ncols_b = ccols[(size_t)p];
+            b.a_rpt = q.A.rpt;
+            b.a_col = q.A.col;
+            b.a_val = q.A.val;
+            if (q.b_from < 0) {
+                b.b_rpt = q.B.rpt;
+                b.b_col = q.B.col;
+                b.b_val = q.B.val;
+            }
+            b.c_rpt = reinterpret_cast<int64_t *>(arena_c + rpt_off[(size_t)p]);
+            b.rpt_off = rpt_off[(size_t)p];
+            b.b_from = q.b_from;
+            h->b_row_off_host[x.roff + (size_t)i] = ro;
+            ro += q.A.rows;
+        }
+        h->b_row_off_host[x.roff + (size_t)x.n] = ro;
+    }
+    HIP_TRY(h, hipMemcpyAsync(d_tab, h->b_host, sizeof(BatchProb) * (size_t)count, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(d_roff, h->b_row_off_host, 8 * roff_total, hipMemcpyHostToDevice, s));
+    // graph signature: problems, arena, outputs, options
+    std::vector<int64_t> sig;
+    sig.push_back(count);
+    for (int p = 0; p < count; ++p) {
+        const spg_problem &q = probs[p];
+        for (int64_t v : {q.A.rows, q.A.cols, q.A.nnz, (int64_t)q.A.rpt_bytes, (int64_t)q.b_from, q.B.rows, q.B.cols,
+                          q.B.nnz, (int64_t)q.B.rpt_bytes})
+            sig.push_back(v);
+        for (const void *ptr : {q.A.rpt, (const void *)q.A.col, (const void *)q.A.val, q.B.rpt,
+                                (const void *)q.B.col, (const void *)q.B.val})
+            sig.push_back((int64_t)reinterpret_cast<uintptr_t>(ptr));
+    }
+    for (int64_t v : {(int64_t)reinterpret_cast<uintptr_t>(arena), arena_bytes, h->wave_small_max, h->wave_max,
+                      h->group_max,
+                      h->block_max, h->force, h->grid_waves, (int64_t)reinterpret_cast<uintptr_t>(h->b_mem)})
+        sig.push_back(v);
+    if (realloc || !h->graph_exec || sig != h->graph_sig) {
+        if (h->graph_exec) {
+            HIP_TRY(h, hipStreamSynchronize(s));
+            (void)hipGraphExecDestroy(h->graph_exec);
+            h->graph_exec = nullptr;
+        }
+        hipStream_t cs = h->cap_stream;
+        HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_batched_begin(d_stat, cs);
+        const Thresholds th = thresholds(h);
+        for (auto &x : st) {
+            if (e != hipSuccess) break;
+            BatchStage bs;
+            bs.all = d_tab;
+            bs.tab = d_tab + x.first;
+            bs.first = x.first;
+            bs.nprob = x.n;
+            bs.row_off = d_roff + x.roff;
+            bs.rows = x.rows;
+            bs.a_rpt_bytes = x.arb;
+            bs.b_rpt_bytes = x.brb;
+            bs.link = x.link ? 1 : 0;
+            bs.S = d_S;
+            bs.arena = arena_c;
+            bs.arena_bytes = arena_bytes;
+            bs.data_off = rpt_end;
+            bs.status = d_stat;
+            e = launch_batched_stage(bs, ws, th, h->num_cu, h->grid_waves, cs);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(h, SPG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiateWithFlags(&h->graph_exec, graph, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            h->graph_exec = nullptr;
+            return fail(h, SPG_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        h->graph_sig = sig;
+        ++h->graph_captures;
+    } else {
+        ++h->graph_launches;
+    }
+    HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
+    HIP_TRY(h, launch_batched_describe(d_tab, count, out, d_stat, s));
+    HIP_TRY(h, hipMemcpyAsync(h->b_status_host, d_stat, sizeof(BatchStatus), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    const BatchStatus &bst = *h->b_status_host;
+    h->nprod = bst.nprod;
+    if (bst.flags & kBatchHeavyRow) {
+        *required_bytes = -1;
+        return fail(h, SPG_ERR_CAPACITY, "a row has more than %d products; use the single-product calls", kCapBlock);
+    }
+    *required_bytes = std::max<int64_t>(bst.required, rpt_end);
+    if (bst.flags & kBatchOverflow)
+        return fail(h, SPG_ERR_CAPACITY, "arena too small: %lld bytes needed", (long long)*required_bytes);
     return SPG_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "spgemm.h"
+
 namespace brm {
 
 // Kernel classes a row of C is routed to (by its product count).
@@ -114,6 +116,55 @@ hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, const int32_
 hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyArgs &h, int grid,
                                 const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
                                 const NumOut &no, hipStream_t s);
+
+// ---- batched products ------------------------------------------------------
+struct BatchProb {
+    int64_t row_off;   // first row in the stage's row space
+    int64_t rows, ncols_b;
+    const void *a_rpt;
+    const int32_t *a_col;
+    const double *a_val;
+    const void *b_rpt;
+    const int32_t *b_col;
+    const double *b_val;
+    int64_t *c_rpt;    // in the arena (offset chosen on the host)
+    int32_t *c_col;    // in the arena (offset chosen on the device)
+    double *c_val;
+    int64_t nnz;
+    int64_t rpt_off, col_off, val_off;  // byte offsets in the arena
+    int32_t b_from;    // -1, or the problem whose C is this problem's B
+    int32_t pad;
+};
+
+enum BatchFlags : int { kBatchOverflow = 1, kBatchHeavyRow = 2 };
+
+struct BatchStatus {
+    int flags;
+    int pad;
+    int64_t required;    // arena bytes the batch needs
+    int64_t arena_used;  // running arena fill (row pointers, then each stage's C)
+    int64_t nprod;
+};
+
+struct BatchStage {
+    BatchProb *all;      // every problem of the call
+    BatchProb *tab;      // this stage's problems (all + first)
+    int first, nprob;
+    int64_t *row_off;    // nprob + 1 entries
+    int64_t rows;        // rows of the stage
+    int a_rpt_bytes, b_rpt_bytes;
+    int link;            // B operands come from earlier problems
+    int64_t *S;          // rows + 1 prefix sums
+    char *arena;
+    int64_t arena_bytes, data_off;
+    BatchStatus *status;
+};
+
+hipError_t launch_batched_begin(BatchStatus *st, hipStream_t s);
+hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const Thresholds &th, int num_cu,
+                                int64_t grid_waves, hipStream_t s);
+hipError_t launch_batched_describe(const BatchProb *all, int n, spg_batched_out *out, const BatchStatus *st,
+                                   hipStream_t s);
 
 // ---- learned allocation (brm_learned.hip) ---------------------------------
 constexpr int kMlpParams = 4673;

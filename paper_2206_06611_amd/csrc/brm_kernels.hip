@@ -354,6 +354,22 @@ struct SymLds {
     int32_t red[Team<T>::kWaves + 1];
 };
 
+// distinct columns of one row: every product's column is inserted once
+template <int T, int TS, typename IA, typename IB>
+__device__ __forceinline__ int sym_hash_row(SymLds<T, TS> &s, int tid, int64_t row, const void *a_rpt,
+                                            const int32_t *a_col, const void *b_rpt, const int32_t *b_col) {
+    for (int t = tid; t < TS; t += T) s.tab[t] = -1;
+    Team<T>::sync();
+    const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+    const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
+    int added = 0;
+    for_each_product<T, IA, IB>(s.st, tid, a0, L, a_col, b_rpt,
+                                [&](int64_t, int64_t q, int) { added += hash_insert<TS>(s.tab, b_col[q]); });
+    const int total = Team<T>::sum(added, s.red, tid);
+    Team<T>::sync();
+    return total;
+}
+
 template <int T, int TEAMS, int TS, typename IA, typename IB>
 __global__ __launch_bounds__(T *TEAMS) void k_sym_hash(
     int cls, const void *a_rpt, const int32_t *a_col, const void *b_rpt, const int32_t *b_col,
@@ -366,16 +382,8 @@ __global__ __launch_bounds__(T *TEAMS) void k_sym_hash(
     for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count;
          idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t row = class_rows[start + idx];
-        for (int t = tid; t < TS; t += T) s.tab[t] = -1;
-        Team<T>::sync();
-        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
-        const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
-        int added = 0;
-        for_each_product<T, IA, IB>(s.st, tid, a0, L, a_col, b_rpt,
-                                    [&](int64_t, int64_t q, int) { added += hash_insert<TS>(s.tab, b_col[q]); });
-        const int total = Team<T>::sum(added, s.red, tid);
+        const int total = sym_hash_row<T, TS, IA, IB>(s, tid, row, a_rpt, a_col, b_rpt, b_col);
         if (tid == 0) row_size[row] = total;
-        Team<T>::sync();
     }
 }
 
@@ -552,6 +560,27 @@ __device__ __forceinline__ void finish_row(const NumOut &no, Ctl *ctl, int64_t r
 // ---------------------------------------------------------------------------
 // numeric, single list: the result row is the scaled B row (wave per row)
 // ---------------------------------------------------------------------------
+// `row` indexes A and C; `id` is the row's id for the bound-mode bookkeeping
+template <typename IA, typename IB>
+__device__ __forceinline__ void copy_row(int lane, int64_t row, int64_t id, const void *a_rpt,
+                                         const int32_t *a_col, const double *a_val, const void *b_rpt,
+                                         const int32_t *b_col, const double *b_val, const int64_t *c_rpt,
+                                         int32_t *c_col, double *c_val, Ctl *ctl, const NumOut &no) {
+    const int64_t p = ld_rpt<IA>(a_rpt, row);
+    const int32_t k = a_col[p];
+    const double a = a_val[p];
+    const int64_t bs = ld_rpt<IB>(b_rpt, k);
+    const int64_t n = ld_rpt<IB>(b_rpt, k + 1) - bs;
+    const int64_t cs = c_rpt[row];
+    const int64_t cap = c_rpt[row + 1] - cs;
+    if (lane == 0) finish_row(no, ctl, id, n, cap, false);
+    const int64_t m = n < cap ? n : cap;
+    for (int64_t j = lane; j < m; j += kWave) {
+        c_col[cs + j] = b_col[bs + j];
+        c_val[cs + j] = a * b_val[bs + j];
+    }
+}
+
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, const int32_t *a_col,
                                                   const double *a_val, const void *b_rpt,
@@ -565,19 +594,7 @@ __global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, co
     for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; idx < count;
          idx += waves) {
         const int64_t row = class_rows[start + idx];
-        const int64_t p = ld_rpt<IA>(a_rpt, row);
-        const int32_t k = a_col[p];
-        const double a = a_val[p];
-        const int64_t bs = ld_rpt<IB>(b_rpt, k);
-        const int64_t n = ld_rpt<IB>(b_rpt, k + 1) - bs;
-        const int64_t cs = c_rpt[row];
-        const int64_t cap = c_rpt[row + 1] - cs;
-        if (lane == 0) finish_row(no, ctl, row, n, cap, false);
-        const int64_t m = n < cap ? n : cap;
-        for (int64_t j = lane; j < m; j += kWave) {
-            c_col[cs + j] = b_col[bs + j];
-            c_val[cs + j] = a * b_val[bs + j];
-        }
+        copy_row<IA, IB>(lane, row, row, a_rpt, a_col, a_val, b_rpt, b_col, b_val, c_rpt, c_col, c_val, ctl, no);
     }
 }
 
@@ -1338,6 +1355,300 @@ hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, const int32_
     else
         hipLaunchKernelGGL(k_heavy_info<int64_t>, dim3(g), dim3(256), 0, s, n, rows, A.rpt, ws.row_nprod,
                            info);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched products: many independent C_p = A_p * B_p share each launch.  The
+// rows of all problems of a stage form one row space; a row finds its
+// problem by a binary search over the problems' first rows (kept in LDS).
+// Outputs live in a caller-provided arena at offsets computed on the device,
+// so the whole sequence of both stages of a Galerkin product can be captured
+// in one graph without any host round trip.
+// ---------------------------------------------------------------------------
+constexpr int kMaxLdsProbs = 2048;
+
+struct ProbLookup {
+    int64_t off[kMaxLdsProbs + 1];
+};
+
+__device__ __forceinline__ void load_lookup(ProbLookup &lk, const int64_t *row_off, int np) {
+    const int n = np + 1 < kMaxLdsProbs + 1 ? np + 1 : kMaxLdsProbs + 1;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lk.off[i] = row_off[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ int find_prob(const ProbLookup &lk, const int64_t *row_off, int np, int64_t g) {
+    // last problem whose first row is <= g (problems are ordered by first row)
+    const int64_t *o = np < kMaxLdsProbs ? lk.off : row_off;
+    return upper_bound(o, np, g) - 1;
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const int64_t *row_off, int np,
+                                                    int64_t R, Thresholds th, int64_t *row_nprod,
+                                                    uint8_t *row_class, int32_t *row_size, Ctl *ctl,
+                                                    BatchStatus *st) {
+    __shared__ ProbLookup lk;
+    __shared__ int64_t s_count[kNumClasses];
+    __shared__ int64_t s_nprod;
+    load_lookup(lk, row_off, np);
+    if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_nprod = 0;
+    __syncthreads();
+    int64_t my_count[kNumClasses];
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
+    int64_t my_nprod = 0;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R; g += (int64_t)gridDim.x * blockDim.x) {
+        const int p = find_prob(lk, row_off, np, g);
+        const BatchProb &pr = tab[p];
+        const int64_t r = g - pr.row_off;
+        const int64_t a0 = ld_rpt<IA>(pr.a_rpt, r), a1 = ld_rpt<IA>(pr.a_rpt, r + 1);
+        int64_t nprod = 0;
+        for (int64_t q = a0; q < a1; ++q) {
+            const int32_t k = pr.a_col[q];
+            nprod += ld_rpt<IB>(pr.b_rpt, k + 1) - ld_rpt<IB>(pr.b_rpt, k);
+        }
+        const int cls = classify(a1 - a0, nprod, th);
+        row_nprod[g] = nprod;
+        row_class[g] = (uint8_t)cls;
+        if (cls == kClassEmpty || cls == kClassHeavy) row_size[g] = 0;  // heavy rows: unsupported, flagged
+        if (cls == kClassCopy) row_size[g] = (int32_t)nprod;
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
+        my_nprod += nprod;
+    }
+    const int lane = lane_id();
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) {
+        const int64_t t = wave_sum(my_count[c]);
+        if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long *>(&s_count[c]), (unsigned long long)t);
+    }
+    {
+        const int64_t t = wave_sum(my_nprod);
+        if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long *>(&s_nprod), (unsigned long long)t);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses && s_count[threadIdx.x])
+        atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->count[threadIdx.x]),
+                  (unsigned long long)s_count[threadIdx.x]);
+    if (threadIdx.x == 0 && s_nprod) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->nprod), (unsigned long long)s_nprod);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&st->nprod), (unsigned long long)s_nprod);
+    }
+    if (threadIdx.x == kNumClasses && s_count[kClassHeavy]) atomicOr(&st->flags, (int)kBatchHeavyRow);
+}
+
+template <int T, int TEAMS, int TS, typename IA, typename IB>
+__global__ __launch_bounds__(T *TEAMS) void k_b_sym_hash(int cls, const BatchProb *tab, const int64_t *row_off,
+                                                         int np, const int32_t *class_rows, int32_t *row_size,
+                                                         const Ctl *ctl) {
+    __shared__ ProbLookup lk;
+    __shared__ SymLds<T, TS> lds[TEAMS];
+    load_lookup(lk, row_off, np);
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count; idx += (int64_t)gridDim.x * TEAMS) {
+        const int64_t g = class_rows[start + idx];
+        const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
+        const int total = sym_hash_row<T, TS, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt, pr.a_col,
+                                                      pr.b_rpt, pr.b_col);
+        if (tid == 0) row_size[g] = total;
+    }
+}
+
+// per-problem nnz, arena offsets of every C (columns then values, 256-byte
+// aligned, after the row-pointer region) and the capacity check
+__global__ __launch_bounds__(1024) void k_b_distribute(BatchProb *tab, int np, const int64_t *S, char *arena,
+                                                       int64_t arena_bytes, int64_t data_off, BatchStatus *st) {
+    __shared__ int64_t scr[Team<1024>::kWaves + 1];
+    __shared__ int64_t s_base;
+    if (threadIdx.x == 0) s_base = st->arena_used > data_off ? st->arena_used : data_off;
+    __syncthreads();
+    int64_t carry = s_base;
+    for (int b = 0; b < np; b += 1024) {
+        const int p = b + threadIdx.x;
+        int64_t nnz = 0, bytes = 0;
+        if (p < np) {
+            nnz = S[tab[p].row_off + tab[p].rows] - S[tab[p].row_off];
+            bytes = ((4 * nnz + 255) / 256) * 256 + ((8 * nnz + 255) / 256) * 256;
+        }
+        int64_t tot;
+        const int64_t ex = Team<1024>::excl_scan(bytes, &tot, scr, threadIdx.x);
+        if (p < np) {
+            const int64_t o = carry + ex;
+            tab[p].nnz = nnz;
+            tab[p].col_off = o;
+            tab[p].val_off = o + ((4 * nnz + 255) / 256) * 256;
+            tab[p].c_col = reinterpret_cast<int32_t *>(arena + o);
+            tab[p].c_val = reinterpret_cast<double *>(arena + tab[p].val_off);
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        st->arena_used = carry;
+        if (carry > arena_bytes) st->flags |= kBatchOverflow;
+        if (carry > st->required) st->required = carry;
+    }
+}
+
+// C's row pointers of every problem from the stage-wide prefix sum
+__global__ __launch_bounds__(256) void k_b_rpt(BatchProb *tab, const int64_t *row_off, int np, int64_t R,
+                                               const int64_t *S, const BatchStatus *st) {
+    __shared__ ProbLookup lk;
+    load_lookup(lk, row_off, np);
+    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R; g += (int64_t)gridDim.x * blockDim.x) {
+        const int p = find_prob(lk, row_off, np, g);
+        const BatchProb &pr = tab[p];
+        const int64_t r = g - pr.row_off;
+        pr.c_rpt[r] = S[g] - S[pr.row_off];
+        if (r == pr.rows - 1) pr.c_rpt[pr.rows] = S[g + 1] - S[pr.row_off];
+    }
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x)
+        if (tab[p].rows == 0) tab[p].c_rpt[0] = 0;
+}
+
+// the B operand of a chained problem is the C of an earlier one
+__global__ void k_b_link(BatchProb *all, int first, int np) {
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        BatchProb &q = all[first + i];
+        if (q.b_from >= 0) {
+            const BatchProb &src = all[q.b_from];
+            q.b_rpt = src.c_rpt;
+            q.b_col = src.c_col;
+            q.b_val = src.c_val;
+        }
+    }
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *tab, const int64_t *row_off, int np,
+                                                    const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+    __shared__ ProbLookup lk;
+    load_lookup(lk, row_off, np);
+    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    const int lane = lane_id();
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    NumOut no;
+    no.bound = 0;
+    for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; idx < count;
+         idx += waves) {
+        const int64_t g = class_rows[start + idx];
+        const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
+        copy_row<IA, IB>(lane, g - pr.row_off, g, pr.a_rpt, pr.a_col, pr.a_val, pr.b_rpt, pr.b_col, pr.b_val,
+                         pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
+    }
+}
+
+template <int T, int TEAMS, int CAP, typename IA, typename IB>
+__global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb *tab, const int64_t *row_off,
+                                                        int np, const int32_t *class_rows, Ctl *ctl,
+                                                        const BatchStatus *st) {
+    __shared__ ProbLookup lk;
+    __shared__ NumLds<T, CAP> lds[TEAMS];
+    load_lookup(lk, row_off, np);
+    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    NumOut no;
+    no.bound = 0;
+    for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count; idx += (int64_t)gridDim.x * TEAMS) {
+        const int64_t g = class_rows[start + idx];
+        const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
+        brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt, pr.a_col, pr.a_val, pr.b_rpt,
+                                        pr.b_col, pr.b_val, pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
+    }
+}
+
+// caller-visible descriptors of the outputs (byte offsets into the arena)
+__global__ void k_b_describe(const BatchProb *all, int n, spg_batched_out *out, const BatchStatus *st) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const BatchProb &p = all[i];
+        spg_batched_out o;
+        o.rows = p.rows;
+        o.cols = p.ncols_b;
+        o.nnz = (st->flags & (kBatchOverflow | kBatchHeavyRow)) ? -1 : p.nnz;
+        o.rpt_off = p.rpt_off;
+        o.col_off = p.col_off;
+        o.val_off = p.val_off;
+        out[i] = o;
+    }
+}
+
+__global__ void k_b_zero_status(BatchStatus *st) {
+    if (threadIdx.x == 0) {
+        st->flags = 0;
+        st->required = 0;
+        st->arena_used = 0;
+        st->nprod = 0;
+    }
+}
+
+hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const Thresholds &th, int num_cu,
+                                int64_t grid_waves, hipStream_t s) {
+    const int np = bs.nprob;
+    const int64_t R = bs.rows;
+    const int64_t *ro = bs.row_off;
+    BatchProb *tab = bs.tab;
+    const unsigned ga = (unsigned)(R > 0 ? ((R + 255) / 256 < 2048 ? (R + 255) / 256 : 2048) : 1);
+    hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, s, ws.ctl);
+    if (bs.link) hipLaunchKernelGGL(k_b_link, dim3(1), dim3(256), 0, s, bs.all, bs.first, np);
+    auto grid_for = [&](int per_cu, int waves_per_wg) {
+        int64_t g = (int64_t)num_cu * per_cu;
+        if (grid_waves > 0) g = grid_waves / waves_per_wg > 0 ? grid_waves / waves_per_wg : 1;
+        return dim3((unsigned)g);
+    };
+#define BRM_B_ALL(IA, IB)                                                                                       \
+    do {                                                                                                        \
+        hipLaunchKernelGGL((k_b_analysis<IA, IB>), dim3(ga), dim3(256), 0, s, tab, ro, np, R, th, ws.row_nprod, \
+                           ws.row_class, ws.row_size, ws.ctl, bs.status);                                       \
+        hipLaunchKernelGGL(k_bin, dim3(ga), dim3(256), 0, s, R, ws.row_class, ws.class_rows, ws.ctl);          \
+        hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,  \
+                           (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);             \
+        hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,       \
+                           (int)kClassWave, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                  \
+        hipLaunchKernelGGL((k_b_sym_hash<256, 1, 2 * kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,     \
+                           (int)kClassGroup, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
+        hipLaunchKernelGGL((k_b_sym_hash<1024, 1, 2 * kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,  \
+                           (int)kClassBlock, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
+        launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);                                        \
+        hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes, \
+                           bs.data_off, bs.status);                                                             \
+        hipLaunchKernelGGL(k_b_rpt, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S, bs.status);                \
+        hipLaunchKernelGGL((k_b_num_copy<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassCopy, tab, ro,  \
+                           np, ws.class_rows, ws.ctl, bs.status);                                              \
+        hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,       \
+                           (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.ctl, bs.status);               \
+        hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,            \
+                           (int)kClassWave, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                    \
+        hipLaunchKernelGGL((k_b_num_lds<256, 1, kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,          \
+                           (int)kClassGroup, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                   \
+        hipLaunchKernelGGL((k_b_num_lds<1024, 1, kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,       \
+                           (int)kClassBlock, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                   \
+    } while (0)
+    if (bs.a_rpt_bytes == 4 && bs.b_rpt_bytes == 4) BRM_B_ALL(int32_t, int32_t);
+    else if (bs.a_rpt_bytes == 4) BRM_B_ALL(int32_t, int64_t);
+    else if (bs.b_rpt_bytes == 4) BRM_B_ALL(int64_t, int32_t);
+    else BRM_B_ALL(int64_t, int64_t);
+#undef BRM_B_ALL
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_begin(BatchStatus *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_b_zero_status, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_describe(const BatchProb *all, int n, spg_batched_out *out, const BatchStatus *st,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(k_b_describe, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0, s,
+                       all, n, out, st);
     return hipGetLastError();
 }
 

@@ -1,0 +1,140 @@
+"""GPU checks of the batched path: Galerkin triple products P^T (A P) in one
+graph-captured call, bitwise equal to separate calls and to the Kronecker
+closed forms; arena capacity errors; graph replays interleaved with eager
+work; generic problems with mixed row-pointer widths."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_matches_oracle, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2206_06611_amd as brm  # noqa: E402
+
+
+def dev(A, **kw):
+    return brm.DeviceCSR.from_host(A, **kw)
+
+
+def same_bits(x, y):
+    for a, b in zip(x, y):
+        if a.dtype == np.float64:
+            a, b = a.view(np.int64), b.view(np.int64)
+        assert np.array_equal(a, b)
+
+
+@pytest.fixture()
+def handle():
+    h = brm.Handle(0)
+    yield h
+    h.close()
+
+
+def galerkin_inputs(edges):
+    return [(n, synth.stencil_3d_27pt(n), synth.aggregation_p(n), synth.aggregation_pt(n)) for n in edges]
+
+
+def test_galerkin_small_matches_separate_calls_and_closed_form(handle):
+    inp = galerkin_inputs([4, 5, 6, 7, 9, 4])
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    G, AP, arena = handle.galerkin(triples)
+    torch.cuda.synchronize()
+    for (n, A, P, Pt), (dA, dP, dPt), g, ap in zip(inp, triples, G, AP):
+        ref_ap = oracle.spgemm(A, P)
+        apc = synth.CSR(A.rows, P.cols, ref_ap.rpt, ref_ap.col, ref_ap.val)
+        ref_g = oracle.spgemm(Pt, apc)
+        same_bits(to_host(ap), (ref_ap.rpt, ref_ap.col, ref_ap.val))  # integer values: exact
+        same_bits(to_host(g), (ref_g.rpt, ref_g.col, ref_g.val))
+        m = (n + 1) // 2
+        assert g.nnz == (3 * m - 2) ** 3
+        assert ap.nnz == ((2 * n - 2) ** 3 if n % 2 == 0 else (2 * n - 1) ** 3)
+        sep_ap = handle.spgemm(dA, dP)
+        sep_g = handle.spgemm(dPt, sep_ap)
+        same_bits(to_host(ap), to_host(sep_ap))
+        same_bits(to_host(g), to_host(sep_g))
+
+
+def test_generic_problems_mixed_widths(handle):
+    rng = np.random.default_rng(4)
+    probs, host = [], []
+    for i in range(9):
+        M, K, N = (int(x) for x in rng.integers(1, 200, 3))
+        A = synth.random_csr(M, K, 0.05, 100 + i, empty_row_frac=0.1)
+        B = synth.random_csr(K, N, 0.05, 200 + i)
+        host.append((A, B))
+    # stage 0: int32 A and B for problems 0-4; int64 for 5-8 would need its own
+    # call (one width per stage), so use a second call for them
+    for chunk, kw in ((host[:5], {}), (host[5:], {"rpt_dtype": torch.int64})):
+        dp = [(dev(A, **kw), dev(B, **kw)) for A, B in chunk]
+        arena = torch.empty(1 << 22, dtype=torch.uint8, device="cuda")
+        rc, req, outs = handle.batched(dp, arena)
+        assert rc == brm.SPG_OK
+        for (A, B), (dA, dB), C in zip(chunk, dp, outs):
+            same_bits(to_host(C), to_host(handle.spgemm(dA, dB)))
+            assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+
+
+def test_arena_capacity(handle):
+    inp = galerkin_inputs([6, 8])
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    probs = [(A, P) for A, P, _ in triples] + [(Pt, i) for i, (_, _, Pt) in enumerate(triples)]
+    small = torch.empty(64 * 1024, dtype=torch.uint8, device="cuda")
+    rc, req, outs = handle.batched(probs, small)
+    assert rc == brm.SPG_ERR_CAPACITY and outs is None and req > small.numel()
+    arena = torch.empty(req, dtype=torch.uint8, device="cuda")
+    rc, req2, outs = handle.batched(probs, arena)
+    assert rc == brm.SPG_OK and req2 == req
+
+
+def test_graph_replays_with_eager_work_between(handle):
+    inp = galerkin_inputs([5, 8, 6])
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    G0, AP0, arena = handle.galerkin(triples)
+    ref = [to_host(g) for g in G0]
+    caps = handle.stat(brm.STAT_GRAPH_CAPTURES)
+    other = dev(synth.erdos_renyi_rows(5000, 8, 3))
+    for it in range(4):
+        eager = handle.spgemm(other, other)  # eager work on the same handle and stream
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        G, AP, arena = handle.galerkin(triples, arena)
+        torch.cuda.synchronize()
+        for g, r in zip(G, ref):
+            same_bits(to_host(g), r)
+        assert eager.nnz > 0 and torch.isfinite(x)
+    assert handle.stat(brm.STAT_GRAPH_CAPTURES) == caps
+    assert handle.stat(brm.STAT_GRAPH_LAUNCHES) >= 4
+
+
+def test_heavy_rows_rejected(handle):
+    A = synth.rmat(12, 16, 5)
+    dA = dev(A)
+    arena = torch.empty(1 << 26, dtype=torch.uint8, device="cuda")
+    rc, req, outs = handle.batched([(dA, dA)], arena)
+    assert rc == brm.SPG_ERR_CAPACITY and req == -1
+
+
+def test_config4_full_batch(handle):
+    print("case: 48 Galerkin products, cube edges U{16..64}, seed 4", flush=True)
+    inp = synth.amg_batch(48, 4)
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    G, AP, arena = handle.galerkin(triples)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for (n, A, P, Pt), g, ap in zip(inp, G, AP):
+        m = (n + 1) // 2
+        assert g.nnz == (3 * m - 2) ** 3
+        assert ap.nnz == ((2 * n - 2) ** 3 if n % 2 == 0 else (2 * n - 1) ** 3)
+    # full oracle comparison on a few problems
+    for i in rng.choice(48, 3, replace=False):
+        n, A, P, Pt = inp[i]
+        ref_ap = oracle.spgemm(A, P)
+        same_bits(to_host(AP[i]), (ref_ap.rpt, ref_ap.col, ref_ap.val))
+        ref_g = oracle.spgemm(Pt, synth.CSR(A.rows, P.cols, ref_ap.rpt, ref_ap.col, ref_ap.val))
+        same_bits(to_host(G[i]), (ref_g.rpt, ref_g.col, ref_g.val))
