@@ -86,6 +86,119 @@ def cpu_baseline(A, nprod, budget_s=15.0):
                       f"{threads} OpenMP threads"}
 
 
+def time_plain(h, dA, dB, reps, warmup=1):
+    """Mean wall time (ms) of whole products C = A*B on the current stream."""
+    import torch
+    for _ in range(warmup):
+        h.spgemm(dA, dB)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C = h.spgemm(dA, dB)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps, C
+
+
+def batched_extra(reps=10):
+    """48 Galerkin products P^T (A P) (27-point cubes, edges U{16..64}, seed 4):
+    one graph-replayed batched call against 96 separate plain products."""
+    import torch
+    import synth
+    import paper_2206_06611_amd as brm
+    from paper_2206_06611_amd import autotune
+
+    inp = synth.amg_batch(48, 4)
+    triples = [(brm.DeviceCSR.from_host(A), brm.DeviceCSR.from_host(P), brm.DeviceCSR.from_host(Pt))
+               for _, A, P, Pt in inp]
+    h = brm.Handle(0)
+    tune = autotune.tune_galerkin(h, triples, cache=os.path.join(ROOT, "gpurun_out", "autotune.json")
+                                  if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    G, AP, arena = h.galerkin(triples)
+    torch.cuda.synchronize()
+    nprod = h.stat(brm.STAT_NPROD)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G, AP, arena = h.galerkin(triples, arena)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) * 1e3 / reps
+    hp = brm.Handle(0)
+    for A, P, Pt in triples:  # warm-up
+        hp.spgemm(Pt, hp.spgemm(A, P))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, reps // 2)):
+        outs = [hp.spgemm(Pt, hp.spgemm(A, P)) for A, P, Pt in triples]
+    torch.cuda.synchronize()
+    t_p = (time.perf_counter() - t0) * 1e3 / max(1, reps // 2)
+    same = all(torch.equal(g.col, o.col) and torch.equal(g.val.view(torch.int64), o.val.view(torch.int64))
+               for g, o in zip(G, outs))
+    h.close()
+    hp.close()
+    return {"workload": "48 x P^T (A P), 27-point cubes edge U{16..64}, 2x2x2 aggregation, seed 4",
+            "nprod": nprod, "batched_ms": round(t_b, 4), "plain_ms": round(t_p, 4),
+            "batched_gflops": round(2 * nprod / (t_b / 1e3) / 1e9, 3),
+            "plain_gflops": round(2 * nprod / (t_p / 1e3) / 1e9, 3),
+            "speedup_vs_plain": round(t_p / t_b, 3), "bitwise_equal_to_plain": bool(same),
+            "autotune": tune}
+
+
+def learned_extra(reps=5, eval_workloads=("stencil27_128", "er8_2e20")):
+    """Size predictor trained on the symbolic counts of the 64^2 Laplacian,
+    ER-8 2^20 (seed 2) and R-MAT scale 20 (seed 3), evaluated against the
+    plain two-pass method on held-out inputs."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2206_06611_amd as brm
+    from paper_2206_06611_amd import learned
+
+    h = brm.Handle(0)
+    g = torch.Generator().manual_seed(0)
+    fs, ts = [], []
+    for A in (synth.laplacian_2d_5pt(64), synth.erdos_renyi_rows(1 << 20, 8, 2), synth.rmat(20, 16, 3)):
+        dA = brm.DeviceCSR.from_host(A)
+        f, t = learned.collect(h, [(dA, dA)])
+        if f.shape[0] > 200000:  # comparable weight per training input
+            idx = torch.randperm(f.shape[0], generator=g)[:200000].to(f.device)
+            f, t = f[idx], t[idx]
+        fs.append(f)
+        ts.append(t)
+        del dA
+    feats, targets = torch.cat(fs), torch.cat(ts)
+    t0 = time.perf_counter()
+    loss0, loss1, delta = learned.train(h, feats, targets, seed=0, epochs=8)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"training": {"rows": int(feats.shape[0]), "epochs": 8, "loss_before": round(loss0, 5),
+                        "loss_after": round(loss1, 5), "delta": round(delta, 5), "seconds": round(train_s, 3)},
+           "eval": {}}
+    for name in eval_workloads:
+        A = build_input(name)
+        dA = brm.DeviceCSR.from_host(A)
+        h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+        t_plain, Cp = time_plain(h, dA, dA, reps)
+        nnz = Cp.nnz
+        nprod = h.stat(brm.STAT_NPROD)
+        h.set_option(brm.OPT_ALLOC, brm.ALLOC_LEARNED)
+        t_learn, Cl = time_plain(h, dA, dA, reps)
+        pred_rows = h.stat(brm.STAT_PREDICTED_ROWS)
+        ovf = h.stat(brm.STAT_OVERFLOW_ROWS)
+        slots = h.stat(brm.STAT_PRED_TOTAL)
+        same = torch.equal(Cp.col, Cl.col) and torch.equal(Cp.val.view(torch.int64), Cl.val.view(torch.int64))
+        out["eval"][name] = {"plain_ms": round(t_plain, 4), "learned_ms": round(t_learn, 4),
+                             "speedup_vs_plain": round(t_plain / t_learn, 3),
+                             "predicted_rows": pred_rows, "fallback_rows": ovf,
+                             "misprediction_rate": round(ovf / pred_rows, 6) if pred_rows else 0.0,
+                             "slot_entries_over_nnz": round(slots / nnz, 4) if nnz else None,
+                             "slot_entries_over_nprod": round(slots / nprod, 4) if nprod else None,
+                             "bitwise_equal_to_plain": bool(same)}
+        h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+        del dA, Cp, Cl
+        torch.cuda.empty_cache()
+    h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +206,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="er8_2e20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the learned and batched comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path is "
@@ -165,9 +279,15 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "algorithmic_bytes": nb},
     }
+    h.close()
+    del dA
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["batched"] = batched_extra()
+        torch.cuda.empty_cache()
+        out["learned"] = learned_extra()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, nprod)
-    h.close()
     print(json.dumps(out), flush=True)
 
 
