@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--workload", default="er8_2e20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the learned and batched comparisons")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy 1 GiB once (a reference kernel for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path is "
@@ -282,6 +284,14 @@ def main():
     h.close()
     del dA
     torch.cuda.empty_cache()
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 8
+        del src, dst
     if not args.no_extras:
         out["batched"] = batched_extra()
         torch.cuda.empty_cache()
