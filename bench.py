@@ -207,6 +207,7 @@ def main():
     ap.add_argument("--workload", default="er8_2e20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the learned and batched comparisons")
+    ap.add_argument("--group-rows", type=int, default=None, help="rows per wavefront for short rows (1 or 4)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB once (a reference kernel for traffic counters)")
     args = ap.parse_args()
@@ -223,6 +224,8 @@ def main():
     dev = torch.device("cuda:0")
     dA = brm.DeviceCSR.from_host(A, device=dev)
     h = brm.Handle(0)
+    if args.group_rows is not None:
+        h.set_option(brm.OPT_GROUP_ROWS, args.group_rows)
     stream = torch.cuda.current_stream()
 
     def step(ev=None):

@@ -103,8 +103,12 @@ typedef enum {
                                     per batch of heavy rows (default 16384) */
     SPG_OPT_GRID_WAVES = 9,      /* waves per launch of the persistent row kernels (0 = auto) */
     SPG_OPT_ALLOC = 10,          /* SPG_ALLOC_PRECISE (default) or SPG_ALLOC_LEARNED */
-    SPG_OPT_LEARNED_FORCE = 11   /* testing only: 1 sizes every predicted row at its lower bound
+    SPG_OPT_LEARNED_FORCE = 11,  /* testing only: 1 sizes every predicted row at its lower bound
                                     (the longest list), so that most rows take the fallback */
+    SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
+                                    1 (default) one row per wavefront, merged in registers when its
+                                    lists fit power-of-two lane windows (else in LDS); 0 one row
+                                    per wavefront in LDS; 4 four rows per wavefront in LDS */
 } spg_option;
 
 /* Allocation methods (SPG_OPT_ALLOC). */

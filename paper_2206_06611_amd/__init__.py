@@ -41,6 +41,7 @@ OPT_SPILL_BUDGET_MB = 8
 OPT_GRID_WAVES = 9
 OPT_ALLOC = 10
 OPT_LEARNED_FORCE = 11
+OPT_GROUP_ROWS = 12
 ALLOC_PRECISE = 0
 ALLOC_LEARNED = 1
 MLP_NUM_PARAMS = 4673

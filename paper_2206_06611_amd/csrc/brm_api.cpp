@@ -30,6 +30,7 @@ struct spg_handle_s {
     int64_t heavy_lds_max = kCapBlock;
     int64_t spill_budget_mb = 16384;
     int64_t grid_waves = 0;
+    int64_t group_rows = 1;  // rows of the wave-small class per wavefront (1 or kGroupRows)
     // workspace
     void *ws_mem = nullptr;
     size_t ws_bytes = 0;
@@ -136,7 +137,7 @@ CsrView view(const spg_csr *X) {
     return v;
 }
 
-int ensure_workspace(spg_handle h, int64_t M, Workspace *ws) {
+int ensure_workspace(spg_handle h, int64_t M, int64_t nnzA, Workspace *ws) {
     const int64_t ntiles = (M + kScanTile - 1) / kScanTile + 1;
     const size_t a = 256;
     size_t off_nprod = 0;
@@ -144,7 +145,9 @@ int ensure_workspace(spg_handle h, int64_t M, Workspace *ws) {
     size_t off_size = align_up(off_class + (size_t)M, a);
     size_t off_rows = align_up(off_size + 4 * (size_t)M, a);
     size_t off_tile = align_up(off_rows + 4 * (size_t)M, a);
-    size_t total = align_up(off_tile + 8 * (size_t)ntiles, a);
+    size_t off_ebs = align_up(off_tile + 8 * (size_t)ntiles, a);
+    size_t off_elen = align_up(off_ebs + 8 * (size_t)nnzA, a);
+    size_t total = align_up(off_elen + 4 * (size_t)nnzA, a);
     if (total > h->ws_bytes) {
         if (h->ws_mem) HIP_TRY(h, hipFree(h->ws_mem));
         h->ws_mem = nullptr;
@@ -162,6 +165,8 @@ int ensure_workspace(spg_handle h, int64_t M, Workspace *ws) {
     ws->row_size = reinterpret_cast<int32_t *>(base + off_size);
     ws->class_rows = reinterpret_cast<int32_t *>(base + off_rows);
     ws->tile_sum = reinterpret_cast<int64_t *>(base + off_tile);
+    ws->ent_bs = base + off_ebs;
+    ws->ent_len = reinterpret_cast<int32_t *>(base + off_elen);
     ws->ctl = h->ctl;
     return SPG_OK;
 }
@@ -256,7 +261,7 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
         ha.leaf = reinterpret_cast<int32_t *>(sp + col_b + val_b);
         ha.lds_cap = (int)h->heavy_lds_max;
         const int grid = (int)std::min<int64_t>(hi - lo, h->num_cu);
-        HIP_TRY(h, launch_numeric_heavy(a, b, ha, grid, c_rpt, c_col, c_val, ctl, no, s));
+        HIP_TRY(h, launch_numeric_heavy(a, b, ws, ha, grid, c_rpt, c_col, c_val, ctl, no, s));
     }
     h->heavy_batches += (int64_t)batches.size();
     return SPG_OK;
@@ -282,7 +287,10 @@ int ensure_learned_ws(spg_handle h, int64_t M, LearnedWs *lw) {
     lw->pred_size = reinterpret_cast<int32_t *>(b + o_ps);
     lw->slot_off = reinterpret_cast<int64_t *>(b + o_so);
     lw->ovf_rows = reinterpret_cast<int32_t *>(b + o_ov);
-    if (!h->ctl2) HIP_TRY(h, hipMalloc(&h->ctl2, sizeof(Ctl)));
+    if (!h->ctl2) {
+        HIP_TRY(h, hipMalloc(&h->ctl2, sizeof(Ctl)));
+        HIP_TRY(h, hipMemset(h->ctl2, 0, sizeof(Ctl)));
+    }
     return SPG_OK;
 }
 
@@ -335,7 +343,7 @@ int persistent_grid(spg_handle h, int cls, int64_t rows) {
     int teams_per_wg;
     switch (cls) {
         case kClassCopy: per_cu = 8; teams_per_wg = 4; break;
-        case kClassWaveSmall: per_cu = 8; teams_per_wg = 4; break;
+        case kClassWaveSmall: per_cu = 8; teams_per_wg = 4 * (h->group_rows > 1 ? (int)h->group_rows : 1); break;
         case kClassWave: per_cu = 4; teams_per_wg = 4; break;
         case kClassGroup: per_cu = 4; teams_per_wg = 1; break;
         case kClassBlock: per_cu = 1; teams_per_wg = 1; break;
@@ -448,6 +456,11 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             if (value < 0) return fail(h, SPG_ERR_ARG, "grid waves must be >= 0");
             h->grid_waves = value;
             break;
+        case SPG_OPT_GROUP_ROWS:
+            if (value != 0 && value != 1 && value != kGroupRows)
+                return fail(h, SPG_ERR_ARG, "group rows must be 0, 1 or %d", kGroupRows);
+            h->group_rows = value;
+            break;
         case SPG_OPT_ALLOC:
             if (value != SPG_ALLOC_PRECISE && value != SPG_ALLOC_LEARNED)
                 return fail(h, SPG_ERR_ARG, "allocation must be SPG_ALLOC_PRECISE or SPG_ALLOC_LEARNED");
@@ -476,6 +489,7 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_SPILL_BUDGET_MB: *value = h->spill_budget_mb; break;
         case SPG_OPT_GRID_WAVES: *value = h->grid_waves; break;
         case SPG_OPT_ALLOC: *value = h->alloc; break;
+        case SPG_OPT_GROUP_ROWS: *value = h->group_rows; break;
         case SPG_OPT_LEARNED_FORCE: *value = h->learned_force; break;
         default: return fail(h, SPG_ERR_ARG, "unknown option %d", key);
     }
@@ -532,7 +546,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     const CsrView a = view(A), b = view(B);
     const int64_t M = A->rows;
     Workspace ws;
-    if ((rc = ensure_workspace(h, M, &ws))) return rc;
+    if ((rc = ensure_workspace(h, M, A->nnz, &ws))) return rc;
 
     HIP_TRY(h, launch_zero_ctl(h->ctl, s));
     if (h->validate) {
@@ -554,7 +568,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         HIP_TRY(h, launch_bin(M, ws, g, s));
         if (!learned) {
             for (int cls = kClassWaveSmall; cls <= kClassHeavy; ++cls)
-                HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1), s));
+                HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1), s, (int)h->group_rows));
         }
     }
     if (learned) {
@@ -562,6 +576,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         // overflowing rows recorded); exact row pointers from the lengths
         LearnedWs lw;
         if ((rc = ensure_learned_ws(h, M, &lw))) return rc;
+        HIP_TRY(h, launch_zero_ctl(h->ctl2, s));
         HIP_TRY(h, launch_features(a, b, lw.feats, lw.lo, lw.hi, lw.predicted, nullptr, nullptr, s));
         HIP_TRY(h, launch_mlp_sizes(M, lw.feats, lw.predicted, lw.lo, lw.hi, ws.row_nprod, h->mlp,
                                     h->mlp + kMlpOffNorm, h->delta, (int)h->learned_force, lw.pred_size, s));
@@ -583,7 +598,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
             if (h->counts[cls] == 0) continue;
             HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls]), lw.slot_off, s_col,
-                                      s_val, no, s));
+                                      s_val, no, s, (int)h->group_rows));
         }
         if (h->counts[kClassHeavy] > 0) {
             int64_t first = 0;
@@ -632,7 +647,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     hipStream_t s = static_cast<hipStream_t>(stream);
     const CsrView a = view(A), b = view(B);
     Workspace ws;
-    if ((rc = ensure_workspace(h, A->rows, &ws))) return rc;
+    if ((rc = ensure_workspace(h, A->rows, A->nnz, &ws))) return rc;
     h->heavy_batches = 0;
     NumOut exact;
     exact.bound = 0;
@@ -652,7 +667,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
             ws2.ctl = h->ctl2;
             if (h->ovf_light > 0)
                 HIP_TRY(h, launch_numeric(a, b, ws2, kClassBlock, persistent_grid(h, kClassBlock, h->ovf_light), c_rpt,
-                                          c_col, c_val, exact, s));
+                                          c_col, c_val, exact, s, (int)h->group_rows));
             if (h->ovf_heavy > 0 &&
                 (rc = run_heavy(h, a, b, ws, lw.ovf_rows + M, h->ovf_heavy, c_rpt, c_col, c_val, exact, h->ctl2, s)))
                 return rc;
@@ -668,7 +683,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
         if (h->counts[cls] == 0) continue;
         HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls]), c_rpt, c_col, c_val,
-                                  exact, s));
+                                  exact, s, (int)h->group_rows));
     }
     if (h->counts[kClassHeavy] > 0) {
         int64_t first = 0;

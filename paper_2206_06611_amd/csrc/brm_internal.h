@@ -26,6 +26,7 @@ constexpr int kCapWaveSmall = 64;
 constexpr int kCapWave = 256;
 constexpr int kCapGroup = 1024;
 constexpr int kCapBlock = 4096;
+constexpr int kGroupRows = 4;  // rows of the wave-small class merged together by one wavefront
 
 struct Thresholds {
     int64_t wave_small_max;
@@ -70,6 +71,8 @@ struct Workspace {
     int32_t *class_rows;  // [M], grouped by class
     int64_t *tile_sum;    // [ntiles]
     Ctl *ctl;
+    void *ent_bs;         // [nnz(A)] start of each A entry's B row (B's row-pointer type)
+    int32_t *ent_len;     // [nnz(A)] length of each A entry's B row
 };
 
 constexpr int kScanTile = 4096;  // rows per scan tile (256 threads x 16)
@@ -83,7 +86,7 @@ hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds 
                            const Workspace &ws, int grid, hipStream_t s);
 hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s);
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
-                           int grid, hipStream_t s);
+                           int grid, hipStream_t s, int group_rows);
 hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
                        int64_t *total, hipStream_t s);
 
@@ -97,7 +100,7 @@ struct NumOut {
 };
 hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                           int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val,
-                          const NumOut &no, hipStream_t s);
+                          const NumOut &no, hipStream_t s, int group_rows);
 
 // Heavy rows: one 1024-thread workgroup per row, spill buffers in HBM.
 struct HeavyArgs {
@@ -113,8 +116,8 @@ struct HeavyArgs {
 };
 hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, const int32_t *rows, int64_t n,
                              int64_t *info, hipStream_t s);
-hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyArgs &h, int grid,
-                                const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Workspace &ws, const HeavyArgs &h,
+                                int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
                                 const NumOut &no, hipStream_t s);
 
 // ---- batched products ------------------------------------------------------

@@ -58,6 +58,47 @@ __device__ __forceinline__ int classify(int64_t nlists, int64_t nprod, const Thr
     return kClassHeavy;
 }
 
+// Where the list (B row) of A's entry p comes from: B's row pointers through
+// A's column index, or the per-entry (start, length) arrays that the analysis
+// pass fills (one coalesced read instead of a dependent gather).
+template <typename IB>
+struct Lists {
+    const int32_t *a_col;
+    const void *b_rpt;
+    const void *ent_bs;      // IB per entry of A, or nullptr
+    const int32_t *ent_len;  // per entry of A, or nullptr
+    __device__ __forceinline__ void get(int64_t p, int64_t &bs, int &ln) const {
+        if (ent_len) {
+            bs = ld_rpt<IB>(ent_bs, p);
+            ln = ent_len[p];
+        } else {
+            const int32_t k = a_col[p];
+            bs = ld_rpt<IB>(b_rpt, k);
+            ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
+        }
+    }
+};
+
+template <typename IB>
+__host__ __device__ __forceinline__ Lists<IB> direct_lists(const int32_t *a_col, const void *b_rpt) {
+    Lists<IB> l;
+    l.a_col = a_col;
+    l.b_rpt = b_rpt;
+    l.ent_bs = nullptr;
+    l.ent_len = nullptr;
+    return l;
+}
+
+template <typename IB>
+__host__ __forceinline__ Lists<IB> ws_lists(const CsrView &A, const CsrView &B, const Workspace &ws) {
+    Lists<IB> l;
+    l.a_col = A.col;
+    l.b_rpt = B.rpt;
+    l.ent_bs = ws.ent_bs;
+    l.ent_len = ws.ent_len;
+    return l;
+}
+
 // ---------------------------------------------------------------------------
 // control block reset
 // ---------------------------------------------------------------------------
@@ -133,14 +174,16 @@ hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rp
 // analysis: lists, products and class of every row
 // ---------------------------------------------------------------------------
 constexpr int kAnalysisThreads = 256;
-constexpr int kShortRow = 32;  // rows with more A entries are summed by the whole wavefront
 
 template <typename IA, typename IB>
 __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
     int64_t M, const void *a_rpt, const int32_t *a_col, const void *b_rpt, Thresholds th,
-    int64_t *row_nprod, uint8_t *row_class, int32_t *row_size, Ctl *ctl) {
+    int64_t *row_nprod, uint8_t *row_class, int32_t *row_size, Ctl *ctl, IB *ent_bs, int32_t *ent_len) {
+    constexpr int kW = kAnalysisThreads / kWave;
     __shared__ int64_t s_count[kNumClasses];
     __shared__ int64_t s_nprod;
+    __shared__ int64_t s_start[kW][kWave + 1];  // entry offset of every row of the wave's chunk
+    __shared__ unsigned long long s_np[kW][kWave];
     if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nprod = 0;
     __syncthreads();
@@ -151,39 +194,37 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
     int64_t my_nprod = 0;
 
     const int lane = lane_id();
+    const int w = threadIdx.x / kWave;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // every wavefront walks the same number of iterations so that the
-    // cooperative part below sees all 64 lanes
+    // a wavefront takes 64 consecutive rows; their entries are one contiguous
+    // range of A, walked entry by entry so that every access is coalesced
     const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
     for (int64_t base = base0; base < M; base += stride) {
         const int64_t i = base + lane;
         const bool in = i < M;
-        int64_t a0 = 0, a1 = 0, np = 0;
+        const int nrows = (M - base) < kWave ? (int)(M - base) : kWave;
+        int64_t a0 = 0, a1 = 0;
         if (in) {
             a0 = ld_rpt<IA>(a_rpt, i);
             a1 = ld_rpt<IA>(a_rpt, i + 1);
+            s_start[w][lane] = a0;
+            s_np[w][lane] = 0ull;
         }
-        const bool longrow = in && (a1 - a0) > kShortRow;
-        if (in && !longrow) {
-            for (int64_t p = a0; p < a1; ++p) {
-                const int32_t k = a_col[p];
-                np += ld_rpt<IB>(b_rpt, k + 1) - ld_rpt<IB>(b_rpt, k);
-            }
+        if (lane == nrows - 1) s_start[w][nrows] = a1;
+        wave_sync();
+        const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
+        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+            const int32_t k = a_col[e];
+            const IB bs = reinterpret_cast<const IB *>(b_rpt)[k];
+            const int64_t n = (int64_t)reinterpret_cast<const IB *>(b_rpt)[k + 1] - (int64_t)bs;
+            ent_bs[e] = bs;
+            ent_len[e] = (int32_t)n;
+            const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
+            atomicAdd(&s_np[w][r], (unsigned long long)n);
         }
-        uint64_t lm = wave_ballot(longrow);
-        while (lm) {
-            const int src = __builtin_ctzll(lm);
-            const int64_t r0 = __shfl(a0, src, kWave), r1 = __shfl(a1, src, kWave);
-            int64_t part = 0;
-            for (int64_t p = r0 + lane; p < r1; p += kWave) {
-                const int32_t k = a_col[p];
-                part += ld_rpt<IB>(b_rpt, k + 1) - ld_rpt<IB>(b_rpt, k);
-            }
-            part = wave_sum(part);
-            if (lane == src) np = part;
-            lm &= lm - 1;
-        }
+        wave_sync();
         if (in) {
+            const int64_t np = (int64_t)s_np[w][lane];
             const int cls = classify(a1 - a0, np, th);
             row_nprod[i] = np;
             row_class[i] = (uint8_t)cls;
@@ -193,6 +234,7 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
             my_nprod += np;
         }
+        wave_sync();
     }
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) {
@@ -218,7 +260,8 @@ hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds 
     const dim3 g(grid), b(kAnalysisThreads);
 #define BRM_ANALYSIS(IA, IB)                                                                 \
     hipLaunchKernelGGL((k_analysis<IA, IB>), g, b, 0, s, A.rows, A.rpt, A.col, B.rpt, th,   \
-                       ws.row_nprod, ws.row_class, ws.row_size, ws.ctl)
+                       ws.row_nprod, ws.row_class, ws.row_size, ws.ctl,                      \
+                       reinterpret_cast<IB *>(ws.ent_bs), ws.ent_len)
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_ANALYSIS(int32_t, int32_t);
     else if (A.rpt_bytes == 4) BRM_ANALYSIS(int32_t, int64_t);
     else if (B.rpt_bytes == 4) BRM_ANALYSIS(int64_t, int32_t);
@@ -302,20 +345,15 @@ struct ListStage {
     int32_t scan[Team<T>::kWaves + 1];
 };
 
-template <int T, typename IA, typename IB, typename F>
+template <int T, typename IB, typename F>
 __device__ __forceinline__ int64_t for_each_product(ListStage<T> &st, int tid, int64_t a0,
-                                                    int64_t L, const int32_t *a_col,
-                                                    const void *b_rpt, F &&f) {
+                                                    int64_t L, const Lists<IB> &lists, F &&f) {
     int64_t carry = 0;
     for (int64_t lb = 0; lb < L; lb += T) {
         const int64_t l = lb + tid;
         int ln = 0;
         int64_t bs = 0;
-        if (l < L) {
-            const int32_t k = a_col[a0 + l];
-            bs = ld_rpt<IB>(b_rpt, k);
-            ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
-        }
+        if (l < L) lists.get(a0 + l, bs, ln);
         int tot;
         const int ex = Team<T>::excl_scan(ln, &tot, st.scan, tid);
         st.bs[tid] = bs;
@@ -357,14 +395,14 @@ struct SymLds {
 // distinct columns of one row: every product's column is inserted once
 template <int T, int TS, typename IA, typename IB>
 __device__ __forceinline__ int sym_hash_row(SymLds<T, TS> &s, int tid, int64_t row, const void *a_rpt,
-                                            const int32_t *a_col, const void *b_rpt, const int32_t *b_col) {
+                                            const Lists<IB> &lists, const int32_t *b_col) {
     for (int t = tid; t < TS; t += T) s.tab[t] = -1;
     Team<T>::sync();
     const int64_t a0 = ld_rpt<IA>(a_rpt, row);
     const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
     int added = 0;
-    for_each_product<T, IA, IB>(s.st, tid, a0, L, a_col, b_rpt,
-                                [&](int64_t, int64_t q, int) { added += hash_insert<TS>(s.tab, b_col[q]); });
+    for_each_product<T, IB>(s.st, tid, a0, L, lists,
+                            [&](int64_t, int64_t q, int) { added += hash_insert<TS>(s.tab, b_col[q]); });
     const int total = Team<T>::sum(added, s.red, tid);
     Team<T>::sync();
     return total;
@@ -372,7 +410,7 @@ __device__ __forceinline__ int sym_hash_row(SymLds<T, TS> &s, int tid, int64_t r
 
 template <int T, int TEAMS, int TS, typename IA, typename IB>
 __global__ __launch_bounds__(T *TEAMS) void k_sym_hash(
-    int cls, const void *a_rpt, const int32_t *a_col, const void *b_rpt, const int32_t *b_col,
+    int cls, const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
     const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
     __shared__ SymLds<T, TS> lds[TEAMS];
     const int team = threadIdx.x / T, tid = threadIdx.x % T;
@@ -382,7 +420,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_sym_hash(
     for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count;
          idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t row = class_rows[start + idx];
-        const int total = sym_hash_row<T, TS, IA, IB>(s, tid, row, a_rpt, a_col, b_rpt, b_col);
+        const int total = sym_hash_row<T, TS, IA, IB>(s, tid, row, a_rpt, lists, b_col);
         if (tid == 0) row_size[row] = total;
     }
 }
@@ -394,7 +432,7 @@ constexpr int kHeavyThreads = 1024;
 
 template <typename IA, typename IB>
 __global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
-    int cls, int64_t ncols, const void *a_rpt, const int32_t *a_col, const void *b_rpt,
+    int cls, int64_t ncols, const void *a_rpt, Lists<IB> lists,
     const int32_t *b_col, const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
     __shared__ uint32_t bm[kBitmapWords];
     __shared__ ListStage<kHeavyThreads> st;
@@ -410,8 +448,8 @@ __global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
         for (int64_t lo = 0; lo < ncols; lo += kBitmapBits) {
             for (int w = tid; w < kBitmapWords; w += kHeavyThreads) bm[w] = 0u;
             __syncthreads();
-            for_each_product<kHeavyThreads, IA, IB>(st, tid, a0, L, a_col, b_rpt,
-                                                    [&](int64_t, int64_t q, int) {
+            for_each_product<kHeavyThreads, IB>(st, tid, a0, L, lists,
+                                                [&](int64_t, int64_t q, int) {
                                                         const int64_t c = (int64_t)b_col[q] - lo;
                                                         if (c >= 0 && c < kBitmapBits)
                                                             atomicOr(&bm[c >> 5], 1u << (c & 31));
@@ -425,10 +463,82 @@ __global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
     }
 }
 
+// symbolic for several short rows per team: one hash table of TS slots per row
+template <int T, int G, int TS>
+struct SymGroupLds {
+    int32_t tab[G][TS];
+    int32_t cnt[G];
+    int32_t fl[G + 1];
+    int64_t a0[G];
+    int32_t L[G];
+    int64_t row[G];
+    int64_t bs[T];
+    int32_t off[T + 1];
+    int32_t lseg[T];
+    int32_t scan[Team<T>::kWaves + 1];
+};
+
+template <int T, int TEAMS, int G, int TS, typename IA, typename IB>
+__global__ __launch_bounds__(T *TEAMS) void k_sym_group(int cls, const void *a_rpt, Lists<IB> lists,
+                                                        const int32_t *b_col, const int32_t *class_rows,
+                                                        int32_t *row_size, const Ctl *ctl) {
+    __shared__ SymGroupLds<T, G, TS> lds[TEAMS];
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    SymGroupLds<T, G, TS> &s = lds[team];
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t base = ((int64_t)blockIdx.x * TEAMS + team) * G; base < count;
+         base += (int64_t)gridDim.x * TEAMS * G) {
+        const int n = (count - base) < G ? (int)(count - base) : G;
+        for (int t = tid; t < G * TS; t += T) (&s.tab[0][0])[t] = -1;
+        if (tid < kWave) {
+            int Lj = 0;
+            if (tid < n) {
+                const int64_t row = class_rows[start + base + tid];
+                const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+                Lj = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
+                s.row[tid] = row;
+                s.a0[tid] = a0;
+                s.L[tid] = Lj;
+                s.cnt[tid] = 0;
+            }
+            const int incl = wave_incl_scan(Lj);
+            if (tid < n) s.fl[tid + 1] = incl;
+            if (tid == 0) s.fl[0] = 0;
+        }
+        Team<T>::sync();
+        const int LT = s.fl[n];
+        for (int lb = 0; lb < LT; lb += T) {
+            const int gl = lb + tid;
+            int ln = 0, j = 0;
+            int64_t bs = 0;
+            if (gl < LT) {
+                j = upper_bound(s.fl, n, gl) - 1;
+                lists.get(s.a0[j] + (gl - s.fl[j]), bs, ln);
+            }
+            int tot;
+            const int ex = Team<T>::excl_scan(ln, &tot, s.scan, tid);
+            s.bs[tid] = bs;
+            s.off[tid] = ex;
+            s.lseg[tid] = j;
+            const int nl = (LT - lb) < T ? (LT - lb) : T;
+            Team<T>::sync();
+            for (int q = tid; q < tot; q += T) {
+                const int t = upper_bound(s.off, nl, q) - 1;
+                const int jj = s.lseg[t];
+                if (hash_insert<TS>(s.tab[jj], b_col[s.bs[t] + (q - s.off[t])])) atomicAdd(&s.cnt[jj], 1);
+            }
+            Team<T>::sync();
+        }
+        if (tid < n) row_size[s.row[tid]] = s.cnt[tid];
+        Team<T>::sync();
+    }
+}
+
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
-                           int grid, hipStream_t s) {
+                           int grid, hipStream_t s, int group_rows) {
 #define BRM_SYM(KERNEL, BLOCK, IA, IB)                                                        \
-    hipLaunchKernelGGL((KERNEL), dim3(grid), dim3(BLOCK), 0, s, cls, A.rpt, A.col, B.rpt,    \
+    hipLaunchKernelGGL((KERNEL), dim3(grid), dim3(BLOCK), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), \
                        B.col, ws.class_rows, ws.row_size, ws.ctl)
 #define BRM_SYM_ALL(T, TEAMS, TS)                                                             \
     do {                                                                                      \
@@ -442,14 +552,27 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
             BRM_SYM((k_sym_hash<T, TEAMS, TS, int64_t, int64_t>), T *TEAMS, int64_t, int64_t); \
     } while (0)
     switch (cls) {
-        case kClassWaveSmall: BRM_SYM_ALL(64, 4, 2 * kCapWaveSmall); break;
+        case kClassWaveSmall:
+            if (group_rows <= 1) {
+                BRM_SYM_ALL(64, 4, 2 * kCapWaveSmall);
+                break;
+            }
+            if (A.rpt_bytes == 4 && B.rpt_bytes == 4)
+                BRM_SYM((k_sym_group<64, 4, kGroupRows, 2 * kCapWaveSmall, int32_t, int32_t>), 256, int32_t, int32_t);
+            else if (A.rpt_bytes == 4)
+                BRM_SYM((k_sym_group<64, 4, kGroupRows, 2 * kCapWaveSmall, int32_t, int64_t>), 256, int32_t, int64_t);
+            else if (B.rpt_bytes == 4)
+                BRM_SYM((k_sym_group<64, 4, kGroupRows, 2 * kCapWaveSmall, int64_t, int32_t>), 256, int64_t, int32_t);
+            else
+                BRM_SYM((k_sym_group<64, 4, kGroupRows, 2 * kCapWaveSmall, int64_t, int64_t>), 256, int64_t, int64_t);
+            break;
         case kClassWave: BRM_SYM_ALL(64, 4, 2 * kCapWave); break;
         case kClassGroup: BRM_SYM_ALL(256, 1, 2 * kCapGroup); break;
         case kClassBlock: BRM_SYM_ALL(1024, 1, 2 * kCapBlock); break;
         case kClassHeavy: {
 #define BRM_BM(IA, IB)                                                                         \
     hipLaunchKernelGGL((k_sym_bitmap<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, cls,     \
-                       B.cols, A.rpt, A.col, B.rpt, B.col, ws.class_rows, ws.row_size, ws.ctl)
+                       B.cols, A.rpt, ws_lists<IB>(A, B, ws), B.col, ws.class_rows, ws.row_size, ws.ctl)
             if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_BM(int32_t, int32_t);
             else if (A.rpt_bytes == 4) BRM_BM(int32_t, int64_t);
             else if (B.rpt_bytes == 4) BRM_BM(int64_t, int32_t);
@@ -563,14 +686,15 @@ __device__ __forceinline__ void finish_row(const NumOut &no, Ctl *ctl, int64_t r
 // `row` indexes A and C; `id` is the row's id for the bound-mode bookkeeping
 template <typename IA, typename IB>
 __device__ __forceinline__ void copy_row(int lane, int64_t row, int64_t id, const void *a_rpt,
-                                         const int32_t *a_col, const double *a_val, const void *b_rpt,
+                                         const Lists<IB> &lists, const double *a_val,
                                          const int32_t *b_col, const double *b_val, const int64_t *c_rpt,
                                          int32_t *c_col, double *c_val, Ctl *ctl, const NumOut &no) {
     const int64_t p = ld_rpt<IA>(a_rpt, row);
-    const int32_t k = a_col[p];
     const double a = a_val[p];
-    const int64_t bs = ld_rpt<IB>(b_rpt, k);
-    const int64_t n = ld_rpt<IB>(b_rpt, k + 1) - bs;
+    int64_t bs;
+    int ln;
+    lists.get(p, bs, ln);
+    const int64_t n = ln;
     const int64_t cs = c_rpt[row];
     const int64_t cap = c_rpt[row + 1] - cs;
     if (lane == 0) finish_row(no, ctl, id, n, cap, false);
@@ -582,8 +706,8 @@ __device__ __forceinline__ void copy_row(int lane, int64_t row, int64_t id, cons
 }
 
 template <typename IA, typename IB>
-__global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, const int32_t *a_col,
-                                                  const double *a_val, const void *b_rpt,
+__global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, Lists<IB> lists,
+                                                  const double *a_val,
                                                   const int32_t *b_col, const double *b_val,
                                                   const int32_t *class_rows, const int64_t *c_rpt,
                                                   int32_t *c_col, double *c_val, Ctl *ctl, NumOut no) {
@@ -594,28 +718,44 @@ __global__ __launch_bounds__(256) void k_num_copy(int cls, const void *a_rpt, co
     for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; idx < count;
          idx += waves) {
         const int64_t row = class_rows[start + idx];
-        copy_row<IA, IB>(lane, row, row, a_rpt, a_col, a_val, b_rpt, b_col, b_val, c_rpt, c_col, c_val, ctl, no);
+        copy_row<IA, IB>(lane, row, row, a_rpt, lists, a_val, b_col, b_val, c_rpt, c_col, c_val, ctl, no);
     }
 }
 
 // ---------------------------------------------------------------------------
 // numeric, one row in LDS (a team of T threads, CAP products at most)
 // ---------------------------------------------------------------------------
-template <int T, int CAP>
+// One output list to build: the lists [a0, a0 + L) of A's entries (a whole
+// row, or an aligned range of a heavy row's lists), merged into out_col /
+// out_val (at most out_cap entries are written).
+struct Seg {
+    int64_t a0;
+    int32_t *out_col;
+    double *out_val;
+    int64_t out_cap;
+    int32_t L;
+    int32_t pad;
+};
+
+template <int T, int CAP, int G = 1>
 struct NumLds {
     static constexpr int kE = CAP / T;                     // positions per thread
     static constexpr int kSlots = kE * Team<T>::kWaves;    // (slice, wave) counters
     int32_t col[2][CAP + 1];
     double val[2][CAP + 1];
-    int32_t off[CAP + 1];  // start of every list (leaf) in the buffers; off[L] = nprod
+    int32_t off[CAP + 1];  // start of every list (leaf) of the group; off[leaves] = products
     int32_t len[CAP];      // current length of a node, stored at its first leaf
     int32_t scan[(kSlots > Team<T>::kWaves ? kSlots : Team<T>::kWaves) + 1];
+    int32_t fl[G + 1];     // first leaf of every segment
+    int32_t seg_len[G];    // merged length of every segment
+    int64_t row[G];
+    Seg seg[G];
 };
 
 // Exclusive count of `flag` over the positions p = tid + e*T in increasing p.
 // Writes the count before every position p < n into x[p] and the total into x[n].
-template <int T, int CAP>
-__device__ __forceinline__ void team_flag_scan(NumLds<T, CAP> &s, int tid, const bool (&flag)[CAP / T],
+template <int T, int CAP, int G>
+__device__ __forceinline__ void team_flag_scan(NumLds<T, CAP, G> &s, int tid, const bool (&flag)[CAP / T],
                                                int n, int32_t *x) {
     constexpr int E = CAP / T;
     constexpr int W = Team<T>::kWaves;
@@ -655,16 +795,196 @@ __device__ __forceinline__ void team_flag_scan(NumLds<T, CAP> &s, int tid, const
     }
 }
 
-// BRMerge of the lists [a0, a0 + L) of A's entries (a whole row, or an
-// aligned range of a heavy row's lists) in the team's LDS.  The merged list
+// BRMerge of n segments (s.seg[0..n), set and visible to the team) in the
+// team's LDS: the lists of all segments share the two buffers, each
+// segment's merge tree stays its own (a node never pairs with another
+// segment's lists).  Requires the segments' lists and products to total at
+// most CAP each.  On return s.seg_len[j] holds segment j's merged length.
+template <int T, int CAP, int G, typename IB>
+__device__ __forceinline__ void brmerge_segs_lds(NumLds<T, CAP, G> &s, int tid, int n, const Lists<IB> &lists,
+                                                 const double *a_val, const int32_t *b_col,
+                                                 const double *b_val) {
+    constexpr int E = CAP / T;
+    static_assert(E * Team<T>::kWaves <= 64, "flag scan assumes at most 64 (slice, wave) slots");
+    static_assert(G <= kWave, "at most one wavefront of segments");
+    // first list of every segment
+    if (tid < kWave) {
+        const int Lj = tid < n ? s.seg[tid].L : 0;
+        const int incl = wave_incl_scan(Lj);
+        if (tid < n) s.fl[tid + 1] = incl;
+        if (tid == 0) s.fl[0] = 0;
+    }
+    Team<T>::sync();
+    const int LT = s.fl[n];
+    int maxL = 0;
+    for (int j = 0; j < n; ++j) maxL = s.seg[j].L > maxL ? s.seg[j].L : maxL;
+
+    // list offsets; B row start and A value of every list staged in the
+    // second buffer (free until the first round)
+    int carry = 0;
+    for (int lb = 0; lb < LT; lb += T) {
+        const int gl = lb + tid;
+        int ln = 0;
+        int64_t bs = 0;
+        double av = 0.0;
+        if (gl < LT) {
+            const int j = upper_bound(s.fl, n, gl) - 1;
+            const int64_t p = s.seg[j].a0 + (gl - s.fl[j]);
+            av = a_val[p];
+            lists.get(p, bs, ln);
+        }
+        int tot;
+        const int ex = Team<T>::excl_scan(ln, &tot, s.scan, tid);
+        if (gl < LT) {
+            s.off[gl] = carry + ex;
+            s.col[1][gl] = (int32_t)(uint32_t)(uint64_t)bs;
+            s.len[gl] = (int32_t)(bs >> 32);
+            s.val[1][gl] = av;
+        }
+        carry += tot;
+    }
+    const int nprod = carry;
+    if (tid == 0) s.off[LT] = nprod;
+    Team<T>::sync();
+
+    // multiplying phase: position p holds A_ik * B_kj of list leaf[e] of
+    // segment sg[e]; consecutive positions read consecutive B entries
+    int leaf[E], sg[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = tid + e * T;
+        leaf[e] = 0;
+        sg[e] = 0;
+        if (p < nprod) {
+            const int gl = upper_bound(s.off, LT + 1, p) - 1;
+            leaf[e] = gl;
+            sg[e] = upper_bound(s.fl, n, gl) - 1;
+            const int64_t bs = ((int64_t)s.len[gl] << 32) | (int64_t)(uint32_t)s.col[1][gl];
+            const int64_t q = bs + (p - s.off[gl]);
+            s.col[0][p] = b_col[q];
+            s.val[0][p] = s.val[1][gl] * b_val[q];
+        }
+    }
+    Team<T>::sync();
+    for (int gl = tid; gl < LT; gl += T) s.len[gl] = s.off[gl + 1] - s.off[gl];
+    Team<T>::sync();
+
+    // accumulating phase: round sh merges the nodes of level sh pairwise
+    int cur = 0;
+    for (int sh = 0; (1 << sh) < maxL; ++sh) {
+        const int nxt = cur ^ 1;
+        const int32_t *sc = s.col[cur];
+        const double *sv = s.val[cur];
+        int32_t *dc = s.col[nxt];
+        double *dv = s.val[nxt];
+        int32_t c[E];
+        double v[E];
+        int k[E], i[E], st[E], sst[E], ln[E], sln[E], node[E], rfl[E];
+        bool valid[E], dup[E], sib[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = tid + e * T;
+            valid[e] = false;
+            dup[e] = false;
+            sib[e] = false;
+            k[e] = 0;
+            c[e] = 0;
+            v[e] = 0.0;
+            rfl[e] = s.fl[sg[e]];
+            const int rL = s.fl[sg[e] + 1] - rfl[e];
+            node[e] = (leaf[e] - rfl[e]) >> sh;
+            const int fl = rfl[e] + (node[e] << sh);
+            st[e] = s.off[fl];
+            ln[e] = s.len[fl];
+            i[e] = p - st[e];
+            sst[e] = 0;
+            sln[e] = 0;
+            if (p < nprod && i[e] < ln[e]) {
+                valid[e] = true;
+                c[e] = sc[p];
+                v[e] = sv[p];
+                const int sl = (node[e] ^ 1) << sh;
+                if (sl < rL) {
+                    sib[e] = true;
+                    sst[e] = s.off[rfl[e] + sl];
+                    sln[e] = s.len[rfl[e] + sl];
+                    if ((node[e] & 1) == 0) {
+                        k[e] = lower_bound(sc + sst[e], sln[e], c[e]);
+                        if (k[e] < sln[e] && sc[sst[e] + k[e]] == c[e]) v[e] = v[e] + sv[sst[e] + k[e]];
+                    } else {
+                        k[e] = upper_bound(sc + sst[e], sln[e], c[e]);
+                        dup[e] = k[e] > 0 && sc[sst[e] + k[e] - 1] == c[e];
+                    }
+                }
+            }
+        }
+        // dup counts over positions, kept in the destination column buffer
+        team_flag_scan<T, CAP, G>(s, tid, dup, nprod, dc);
+        Team<T>::sync();
+        int dest[E], newlen[E], newlen_at[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            dest[e] = -1;
+            newlen[e] = -1;
+            newlen_at[e] = 0;
+            if (valid[e] && !dup[e]) {
+                int pos;
+                if (!sib[e]) {
+                    pos = i[e];
+                } else if ((node[e] & 1) == 0) {
+                    pos = i[e] + k[e] - (dc[sst[e] + k[e]] - dc[sst[e]]);
+                } else {
+                    const int p = tid + e * T;
+                    pos = i[e] + k[e] - (dc[p] - dc[st[e]]);
+                }
+                dest[e] = s.off[rfl[e] + ((node[e] >> 1) << (sh + 1))] + pos;
+            }
+            if (valid[e] && sib[e] && (node[e] & 1) && i[e] == 0) {
+                // first element of a right list: the parent's length
+                newlen[e] = sln[e] + ln[e] - (dc[st[e] + ln[e]] - dc[st[e]]);
+                newlen_at[e] = rfl[e] + ((node[e] ^ 1) << sh);
+            }
+        }
+        Team<T>::sync();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (dest[e] >= 0) {
+                dc[dest[e]] = c[e];
+                dv[dest[e]] = v[e];
+            }
+            if (newlen[e] >= 0) s.len[newlen_at[e]] = newlen[e];
+        }
+        Team<T>::sync();
+        cur = nxt;
+    }
+
+    // Algorithm 1's final store: every segment's single list goes out
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = tid + e * T;
+        if (p < nprod) {
+            const int j = sg[e];
+            const int f = s.fl[j];
+            const int o = p - s.off[f];
+            if (o < s.len[f] && (int64_t)o < s.seg[j].out_cap) {
+                s.seg[j].out_col[o] = s.col[cur][p];
+                s.seg[j].out_val[o] = s.val[cur][p];
+            }
+        }
+    }
+    if (tid < n) s.seg_len[tid] = s.len[s.fl[tid]];
+    Team<T>::sync();
+}
+
+// BRMerge of one segment, the lists [a0, a0 + L) of A's entries (a whole row,
+// or an aligned range of a heavy row's lists), in the team's LDS.  The merged list
 // is written to out_col / out_val (at most out_cap entries); its length is
 // returned to every thread of the team.
-template <int T, int CAP, typename IB>
-__device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP> &s, int tid, int64_t a0, int L,
-                                                 const int32_t *a_col, const double *a_val,
-                                                 const void *b_rpt, const int32_t *b_col,
-                                                 const double *b_val, int32_t *out_col,
-                                                 double *out_val, int64_t out_cap) {
+template <int T, int CAP, int G, typename IB>
+__device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP, G> &s, int tid, int64_t a0, int L,
+                                                 const Lists<IB> &lists, const double *a_val,
+                                                 const int32_t *b_col, const double *b_val,
+                                                 int32_t *out_col, double *out_val, int64_t out_cap) {
     constexpr int E = CAP / T;
     static_assert(E * Team<T>::kWaves <= 64, "flag scan assumes at most 64 (slice, wave) slots");
 
@@ -677,10 +997,8 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP> &s, int tid, int
         int64_t bs = 0;
         double av = 0.0;
         if (l < L) {
-            const int32_t k = a_col[a0 + l];
             av = a_val[a0 + l];
-            bs = ld_rpt<IB>(b_rpt, k);
-            ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
+            lists.get(a0 + l, bs, ln);
         }
         int tot;
         const int ex = Team<T>::excl_scan(ln, &tot, s.scan, tid);
@@ -764,7 +1082,7 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP> &s, int tid, int
             }
         }
         // dup counts over positions, kept in the destination column buffer
-        team_flag_scan<T, CAP>(s, tid, dup, nprod, dc);
+        team_flag_scan<T, CAP, G>(s, tid, dup, nprod, dc);
         Team<T>::sync();
         int dest[E], newlen[E], newlen_at[E];
 #pragma unroll
@@ -817,8 +1135,8 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP> &s, int tid, int
 
 template <int T, int CAP, typename IA, typename IB>
 __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int64_t row,
-                                                const void *a_rpt, const int32_t *a_col,
-                                                const double *a_val, const void *b_rpt,
+                                                const void *a_rpt, const Lists<IB> &lists,
+                                                const double *a_val,
                                                 const int32_t *b_col, const double *b_val,
                                                 const int64_t *c_rpt, int32_t *c_col,
                                                 double *c_val, Ctl *ctl, const NumOut &no) {
@@ -826,7 +1144,7 @@ __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int6
     const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
     const int64_t cs = c_rpt[row];
     const int64_t cap = c_rpt[row + 1] - cs;
-    const int rl = brmerge_range_lds<T, CAP, IB>(s, tid, a0, L, a_col, a_val, b_rpt, b_col, b_val,
+    const int rl = brmerge_range_lds<T, CAP, 1, IB>(s, tid, a0, L, lists, a_val, b_col, b_val,
                                                  c_col + cs, c_val + cs, cap);
     // Algorithm 1's final store went straight to C's row (truncated to the slot)
     if (tid == 0) finish_row(no, ctl, row, rl, cap, false);
@@ -834,9 +1152,8 @@ __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int6
 
 template <int T, int TEAMS, int CAP, typename IA, typename IB>
 __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt,
-                                                      const int32_t *a_col, const double *a_val,
-                                                      const void *b_rpt, const int32_t *b_col,
-                                                      const double *b_val,
+                                                      Lists<IB> lists, const double *a_val,
+                                                      const int32_t *b_col, const double *b_val,
                                                       const int32_t *class_rows,
                                                       const int64_t *c_rpt, int32_t *c_col,
                                                       double *c_val, Ctl *ctl, NumOut no) {
@@ -847,36 +1164,227 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt
     for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count;
          idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t row = class_rows[start + idx];
-        brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, row, a_rpt, a_col, a_val, b_rpt, b_col,
+        brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, row, a_rpt, lists, a_val, b_col,
                                         b_val, c_rpt, c_col, c_val, ctl, no);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric, rows of at most 64 products whose lists fit power-of-two lane
+// windows (lists padded to W0 = the next power of two of the longest list,
+// their count to the next power of two, W0 * lists <= 64): the whole BRMerge
+// runs in registers.  Every lane holds one entry; list p occupies lanes
+// [p W0, (p+1) W0) in ascending column order, padded with an empty marker.
+// Round r merges windows 2q and 2q+1 of width W0 2^r with a bitonic merge
+// (a mirror compare-exchange, then half-cleaners at distances W/2 .. 1), so
+// the two lists of a pair are merged, never mixed with another pair.  Equal
+// columns (one from each list) end up adjacent; the first keeps the sum of
+// the two values, the second is emptied and the pair's window is compacted
+// through LDS (skipped when the wavefront has no duplicate).  Rows that do
+// not fit the windows take the LDS path of the same class.
+// ---------------------------------------------------------------------------
+constexpr int32_t kEmptyCol = 0x7fffffff;
+
+__device__ __forceinline__ int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_num_win(int cls, const void *a_rpt, Lists<IB> lists,
+                                                 const double *a_val, const int32_t *b_col,
+                                                 const double *b_val, const int32_t *class_rows,
+                                                 const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+                                                 NumOut no) {
+    __shared__ NumLds<kWave, kCapWaveSmall> lds[4];
+    __shared__ int32_t xc[4][kWave];
+    __shared__ double xv[4][kWave];
+    const int team = threadIdx.x / kWave, lane = lane_id();
+    NumLds<kWave, kCapWaveSmall> &s = lds[team];
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t idx = (int64_t)blockIdx.x * 4 + team; idx < count; idx += (int64_t)gridDim.x * 4) {
+        const int64_t row = class_rows[start + idx];
+        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+        const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
+        const int64_t cs = c_rpt[row];
+        const int64_t cap = c_rpt[row + 1] - cs;
+        int64_t bs = 0;
+        int ln = 0;
+        double av = 0.0;
+        if (lane < L) {
+            lists.get(a0 + lane, bs, ln);
+            av = a_val[a0 + lane];
+        }
+        int mx = ln;
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) {
+            const int o = __shfl_xor(mx, d, kWave);
+            mx = o > mx ? o : mx;
+        }
+        const int W0 = next_pow2(mx > 0 ? mx : 1);
+        const int LP = next_pow2(L);
+        if (L > kWave || W0 * LP > kWave) {
+            // lists too uneven for the windows: LDS merge
+            const int rl = brmerge_range_lds<kWave, kCapWaveSmall, 1, IB>(s, lane, a0, L, lists, a_val, b_col,
+                                                                          b_val, c_col + cs, c_val + cs, cap);
+            if (lane == 0) finish_row(no, ctl, row, rl, cap, false);
+            continue;
+        }
+        // multiplying phase: lane t holds entry t mod W0 of list t / W0
+        const int sw = __builtin_ctz(W0);
+        const int li = lane >> sw, o = lane & (W0 - 1);
+        const int64_t lbs = __shfl(bs, li, kWave);
+        const int lln = __shfl(ln, li, kWave);
+        const double lav = __shfl(av, li, kWave);
+        int32_t c = kEmptyCol;
+        double v = 0.0;
+        if (li < L && o < lln) {
+            c = b_col[lbs + o];
+            v = lav * b_val[lbs + o];
+        }
+        // accumulating phase: ceil(log2 L) rounds of pairwise merges
+        for (int W = W0; W < W0 * LP; W <<= 1) {
+            // mirror stage over the window pair of width 2W, then half-cleaners
+            for (int d = 2 * W - 1, first = 1; d >= 1; d = first ? W / 2 : d / 2, first = 0) {
+                const int32_t pc = __shfl_xor(c, d, kWave);
+                const double pv = __shfl_xor(v, d, kWave);
+                const bool lower = first ? (lane & W) == 0 : (lane & d) == 0;
+                const bool take = lower ? pc < c : pc > c;
+                if (take) {
+                    c = pc;
+                    v = pv;
+                }
+                if (d == 1 && !first) break;
+                if (first && W == 1) break;
+            }
+            // equal columns of the pair are now neighbours: the first takes
+            // the sum, the second is emptied
+            const int W2 = 2 * W;
+            const int wpos = lane & (W2 - 1);
+            const int32_t nc = __shfl_down(c, 1, kWave);
+            const double nv = __shfl_down(v, 1, kWave);
+            const int32_t pc = __shfl_up(c, 1, kWave);
+            const bool has_next = wpos + 1 < W2, has_prev = wpos > 0;
+            const bool dead = c != kEmptyCol && has_prev && pc == c;
+            if (c != kEmptyCol && !dead && has_next && nc == c) v = v + nv;
+            const uint64_t dm = wave_ballot(dead);
+            if (dm) {
+                if (dead) {
+                    c = kEmptyCol;
+                    v = 0.0;
+                }
+                // compact every window: live entries to its front, in order
+                const uint64_t live = wave_ballot(c != kEmptyCol);
+                const int wbase = lane & ~(W2 - 1);
+                const uint64_t wmask = (W2 == 64) ? ~0ull : (((1ull << W2) - 1) << wbase);
+                const int rank = __popcll(live & wmask & ((1ull << lane) - 1));
+                xc[team][lane] = kEmptyCol;
+                xv[team][lane] = 0.0;
+                wave_sync();
+                if (c != kEmptyCol) {
+                    xc[team][wbase + rank] = c;
+                    xv[team][wbase + rank] = v;
+                }
+                wave_sync();
+                c = xc[team][lane];
+                v = xv[team][lane];
+                wave_sync();
+            }
+        }
+        // Algorithm 1's final store: the live entries are the sorted row
+        const bool live = c != kEmptyCol;
+        const uint64_t lm = wave_ballot(live);
+        const int n = __popcll(lm);
+        if (live && lane < cap) {
+            c_col[cs + lane] = c;
+            c_val[cs + lane] = v;
+        }
+        if (lane == 0) finish_row(no, ctl, row, n, cap, false);
+    }
+}
+
+// Several short rows per team: the rows of a class whose lists and products
+// each stay within CAP / G are merged G at a time, so that one wavefront
+// keeps G rows' loads in flight.
+template <int T, int TEAMS, int CAP, int G, typename IA, typename IB>
+__global__ __launch_bounds__(T *TEAMS) void k_num_group(int cls, const void *a_rpt, Lists<IB> lists,
+                                                        const double *a_val, const int32_t *b_col,
+                                                        const double *b_val, const int32_t *class_rows,
+                                                        const int64_t *c_rpt, int32_t *c_col, double *c_val,
+                                                        Ctl *ctl, NumOut no) {
+    __shared__ NumLds<T, CAP, G> lds[TEAMS];
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    NumLds<T, CAP, G> &s = lds[team];
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t base = ((int64_t)blockIdx.x * TEAMS + team) * G; base < count;
+         base += (int64_t)gridDim.x * TEAMS * G) {
+        const int n = (count - base) < G ? (int)(count - base) : G;
+        if (tid < n) {
+            const int64_t row = class_rows[start + base + tid];
+            const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+            const int64_t cs = c_rpt[row];
+            s.row[tid] = row;
+            s.seg[tid].a0 = a0;
+            s.seg[tid].L = (int32_t)(ld_rpt<IA>(a_rpt, row + 1) - a0);
+            s.seg[tid].out_col = c_col + cs;
+            s.seg[tid].out_val = c_val + cs;
+            s.seg[tid].out_cap = c_rpt[row + 1] - cs;
+        }
+        Team<T>::sync();
+        brmerge_segs_lds<T, CAP, G, IB>(s, tid, n, lists, a_val, b_col, b_val);
+        if (tid < n) finish_row(no, ctl, s.row[tid], s.seg_len[tid], s.seg[tid].out_cap, false);
+        Team<T>::sync();
     }
 }
 
 hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                           int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val,
-                          const NumOut &no, hipStream_t s) {
-#define BRM_NUM(KERNEL, BLOCK)                                                                   \
-    hipLaunchKernelGGL((KERNEL), dim3(grid), dim3(BLOCK), 0, s, cls, A.rpt, A.col, A.val, B.rpt, \
-                       B.col, B.val, ws.class_rows, c_rpt, c_col, c_val, ws.ctl, no)
+                          const NumOut &no, hipStream_t s, int group_rows) {
+#define BRM_NUM(KERNEL, BLOCK, IB)                                                               \
+    hipLaunchKernelGGL((KERNEL), dim3(grid), dim3(BLOCK), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), \
+                       A.val, B.col, B.val, ws.class_rows, c_rpt, c_col, c_val, ws.ctl, no)
 #define BRM_NUM_ALL(T, TEAMS, CAP)                                                               \
     do {                                                                                         \
         if (A.rpt_bytes == 4 && B.rpt_bytes == 4)                                                \
-            BRM_NUM((k_num_lds<T, TEAMS, CAP, int32_t, int32_t>), T *TEAMS);                     \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int32_t, int32_t>), T *TEAMS, int32_t);            \
         else if (A.rpt_bytes == 4)                                                               \
-            BRM_NUM((k_num_lds<T, TEAMS, CAP, int32_t, int64_t>), T *TEAMS);                     \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int32_t, int64_t>), T *TEAMS, int64_t);            \
         else if (B.rpt_bytes == 4)                                                               \
-            BRM_NUM((k_num_lds<T, TEAMS, CAP, int64_t, int32_t>), T *TEAMS);                     \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int64_t, int32_t>), T *TEAMS, int32_t);            \
         else                                                                                     \
-            BRM_NUM((k_num_lds<T, TEAMS, CAP, int64_t, int64_t>), T *TEAMS);                     \
+            BRM_NUM((k_num_lds<T, TEAMS, CAP, int64_t, int64_t>), T *TEAMS, int64_t);            \
     } while (0)
     switch (cls) {
         case kClassCopy:
-            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM((k_num_copy<int32_t, int32_t>), 256);
-            else if (A.rpt_bytes == 4) BRM_NUM((k_num_copy<int32_t, int64_t>), 256);
-            else if (B.rpt_bytes == 4) BRM_NUM((k_num_copy<int64_t, int32_t>), 256);
-            else BRM_NUM((k_num_copy<int64_t, int64_t>), 256);
+            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM((k_num_copy<int32_t, int32_t>), 256, int32_t);
+            else if (A.rpt_bytes == 4) BRM_NUM((k_num_copy<int32_t, int64_t>), 256, int64_t);
+            else if (B.rpt_bytes == 4) BRM_NUM((k_num_copy<int64_t, int32_t>), 256, int32_t);
+            else BRM_NUM((k_num_copy<int64_t, int64_t>), 256, int64_t);
             break;
-        case kClassWaveSmall: BRM_NUM_ALL(64, 4, kCapWaveSmall); break;
+        case kClassWaveSmall:
+            if (group_rows == 0) {
+                BRM_NUM_ALL(64, 4, kCapWaveSmall);
+                break;
+            }
+            if (group_rows == 1) {
+                if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM((k_num_win<int32_t, int32_t>), 256, int32_t);
+                else if (A.rpt_bytes == 4) BRM_NUM((k_num_win<int32_t, int64_t>), 256, int64_t);
+                else if (B.rpt_bytes == 4) BRM_NUM((k_num_win<int64_t, int32_t>), 256, int32_t);
+                else BRM_NUM((k_num_win<int64_t, int64_t>), 256, int64_t);
+                break;
+            }
+            if (A.rpt_bytes == 4 && B.rpt_bytes == 4)
+                BRM_NUM((k_num_group<64, 4, kGroupRows * kCapWaveSmall, kGroupRows, int32_t, int32_t>), 256, int32_t);
+            else if (A.rpt_bytes == 4)
+                BRM_NUM((k_num_group<64, 4, kGroupRows * kCapWaveSmall, kGroupRows, int32_t, int64_t>), 256, int64_t);
+            else if (B.rpt_bytes == 4)
+                BRM_NUM((k_num_group<64, 4, kGroupRows * kCapWaveSmall, kGroupRows, int64_t, int32_t>), 256, int32_t);
+            else
+                BRM_NUM((k_num_group<64, 4, kGroupRows * kCapWaveSmall, kGroupRows, int64_t, int64_t>), 256, int64_t);
+            break;
         case kClassWave: BRM_NUM_ALL(64, 4, kCapWave); break;
         case kClassGroup: BRM_NUM_ALL(256, 1, kCapGroup); break;
         case kClassBlock: BRM_NUM_ALL(1024, 1, kCapBlock); break;
@@ -1141,7 +1649,7 @@ struct HeavyBatch {
 
 template <typename IA, typename IB>
 __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
-    HeavyBatch hb, const void *a_rpt, const int32_t *a_col, const double *a_val, const void *b_rpt,
+    HeavyBatch hb, const void *a_rpt, Lists<IB> lists, const double *a_val,
     const int32_t *b_col, const double *b_val, const int64_t *c_rpt, int32_t *c_col, double *c_val,
     Ctl *ctl, NumOut no) {
     constexpr size_t kUnion = sizeof(NumLds<kHeavyThreads, kCapBlock>) > sizeof(MergeLds)
@@ -1170,8 +1678,10 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
             const int64_t l = lb + tid;
             int64_t ln = 0;
             if (l < L) {
-                const int32_t k = a_col[a0 + l];
-                ln = ld_rpt<IB>(b_rpt, k + 1) - ld_rpt<IB>(b_rpt, k);
+                int64_t bs;
+                int n;
+                lists.get(a0 + l, bs, n);
+                ln = n;
             }
             int64_t tot;
             const int64_t ex = Team<kHeavyThreads>::excl_scan(ln, &tot, st.scr, tid);
@@ -1241,13 +1751,14 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                 const int64_t cap = root ? ccap : np;
                 int64_t len;
                 if (np <= hb.lds_cap && (l1 - l0) <= hb.lds_cap) {
-                    len = brmerge_range_lds<kHeavyThreads, kCapBlock, IB>(
-                        node_lds, tid, a0 + l0, (int)(l1 - l0), a_col, a_val, b_rpt, b_col, b_val, oc, ov, cap);
+                    len = brmerge_range_lds<kHeavyThreads, kCapBlock, 1, IB>(
+                        node_lds, tid, a0 + l0, (int)(l1 - l0), lists, a_val, b_col, b_val, oc, ov, cap);
                 } else {
                     // one list longer than LDS: the scaled B row is the node
-                    const int32_t k = a_col[a0 + l0];
                     const double a = a_val[a0 + l0];
-                    const int64_t bs = ld_rpt<IB>(b_rpt, k);
+                    int64_t bs;
+                    int nb;
+                    lists.get(a0 + l0, bs, nb);
                     for (int64_t j = tid; j < np && j < cap; j += kHeavyThreads) {
                         oc[j] = b_col[bs + j];
                         ov[j] = a * b_val[bs + j];
@@ -1308,8 +1819,8 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
     }
 }
 
-hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyArgs &h, int grid,
-                                const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Workspace &ws, const HeavyArgs &h,
+                                int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
                                 const NumOut &no, hipStream_t s) {
     HeavyBatch hb;
     hb.ticket = h.ticket;
@@ -1323,7 +1834,7 @@ hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const HeavyA
     hb.lds_cap = h.lds_cap;
 #define BRM_HEAVY(IA, IB)                                                                          \
     hipLaunchKernelGGL((k_num_heavy<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, hb, A.rpt,    \
-                       A.col, A.val, B.rpt, B.col, B.val, c_rpt, c_col, c_val, ctl, no)
+                       ws_lists<IB>(A, B, ws), A.val, B.col, B.val, c_rpt, c_col, c_val, ctl, no)
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_HEAVY(int32_t, int32_t);
     else if (A.rpt_bytes == 4) BRM_HEAVY(int32_t, int64_t);
     else if (B.rpt_bytes == 4) BRM_HEAVY(int64_t, int32_t);
@@ -1453,8 +1964,8 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_sym_hash(int cls, const BatchPro
     for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count; idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t g = class_rows[start + idx];
         const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
-        const int total = sym_hash_row<T, TS, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt, pr.a_col,
-                                                      pr.b_rpt, pr.b_col);
+        const int total = sym_hash_row<T, TS, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt,
+                                                      direct_lists<IB>(pr.a_col, pr.b_rpt), pr.b_col);
         if (tid == 0) row_size[g] = total;
     }
 }
@@ -1540,8 +2051,8 @@ __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *ta
          idx += waves) {
         const int64_t g = class_rows[start + idx];
         const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
-        copy_row<IA, IB>(lane, g - pr.row_off, g, pr.a_rpt, pr.a_col, pr.a_val, pr.b_rpt, pr.b_col, pr.b_val,
-                         pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
+        copy_row<IA, IB>(lane, g - pr.row_off, g, pr.a_rpt, direct_lists<IB>(pr.a_col, pr.b_rpt), pr.a_val,
+                         pr.b_col, pr.b_val, pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
     }
 }
 
@@ -1561,8 +2072,9 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb
     for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count; idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t g = class_rows[start + idx];
         const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
-        brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt, pr.a_col, pr.a_val, pr.b_rpt,
-                                        pr.b_col, pr.b_val, pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
+        brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt,
+                                        direct_lists<IB>(pr.a_col, pr.b_rpt), pr.a_val, pr.b_col, pr.b_val,
+                                        pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
     }
 }
 
@@ -1617,7 +2129,7 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
                            (int)kClassGroup, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
         hipLaunchKernelGGL((k_b_sym_hash<1024, 1, 2 * kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,  \
                            (int)kClassBlock, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
-        launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);                                        \
+        (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);                                        \
         hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes, \
                            bs.data_off, bs.status);                                                             \
         hipLaunchKernelGGL(k_b_rpt, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S, bs.status);                \
