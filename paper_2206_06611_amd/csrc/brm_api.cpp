@@ -30,7 +30,8 @@ struct spg_handle_s {
     int64_t heavy_lds_max = kCapBlock;
     int64_t spill_budget_mb = 16384;
     int64_t grid_waves = 0;
-    int64_t group_rows = 1;  // rows of the wave-small class per wavefront (1 or kGroupRows)
+    int64_t group_rows = 1;  // kernel of the wave-small class (see SPG_OPT_GROUP_ROWS)
+    int plan_group_rows = 1;  // the one the last symbolic pass classified for
     // workspace
     void *ws_mem = nullptr;
     size_t ws_bytes = 0;
@@ -327,23 +328,31 @@ int ensure_mlp_act(spg_handle h, int64_t rows) {
     return SPG_OK;
 }
 
-Thresholds thresholds(spg_handle h) {
+// windows: the wave-small class is served by the register-window kernels,
+// which take only rows whose lists fit lane windows
+Thresholds thresholds(spg_handle h, bool windows) {
     Thresholds t;
     t.wave_small_max = h->wave_small_max;
     t.wave_max = h->wave_max;
     t.group_max = h->group_max;
     t.block_max = h->block_max;
     t.force = (int32_t)h->force;
+    t.windows = windows ? 1 : 0;
     return t;
 }
 
-int persistent_grid(spg_handle h, int cls, int64_t rows) {
+bool uses_windows(int64_t group_rows) { return group_rows == 1 || group_rows == 2; }
+
+int persistent_grid(spg_handle h, int cls, int64_t rows, int group_rows) {
     // workgroups per launch of the persistent row kernels
     int per_cu;
-    int teams_per_wg;
+    int teams_per_wg;  // rows a workgroup takes per pass
     switch (cls) {
         case kClassCopy: per_cu = 8; teams_per_wg = 4; break;
-        case kClassWaveSmall: per_cu = 8; teams_per_wg = 4 * (h->group_rows > 1 ? (int)h->group_rows : 1); break;
+        case kClassWaveSmall:
+            per_cu = 8;
+            teams_per_wg = uses_windows(group_rows) ? 4 * 64 : 4 * (group_rows > 1 ? group_rows : 1);  // chunks of 64 rows
+            break;
         case kClassWave: per_cu = 4; teams_per_wg = 4; break;
         case kClassGroup: per_cu = 4; teams_per_wg = 1; break;
         case kClassBlock: per_cu = 1; teams_per_wg = 1; break;
@@ -457,8 +466,8 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             h->grid_waves = value;
             break;
         case SPG_OPT_GROUP_ROWS:
-            if (value != 0 && value != 1 && value != kGroupRows)
-                return fail(h, SPG_ERR_ARG, "group rows must be 0, 1 or %d", kGroupRows);
+            if (value != 0 && value != 1 && value != 2 && value != kGroupRows)
+                return fail(h, SPG_ERR_ARG, "group rows must be 0, 1, 2 or %d", kGroupRows);
             h->group_rows = value;
             break;
         case SPG_OPT_ALLOC:
@@ -559,16 +568,21 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
                         (unsigned long long)h->ctl_host->err);
     }
     const bool learned = h->alloc == SPG_ALLOC_LEARNED;
+    // the short-row kernels are fixed with the classification: the numeric
+    // pass uses what this call chose
+    const int gr = (int)h->group_rows;
+    h->plan_valid = false;
+    h->plan_group_rows = gr;
     if (learned && !h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "learned allocation needs a trained or loaded predictor");
     h->heavy_batches = 0;
     h->pred_total = h->ovf_light = h->ovf_heavy = 0;
     if (M > 0) {
         const int g = (int)std::min<int64_t>((M + 255) / 256, 2048);
-        HIP_TRY(h, launch_analysis(a, b, thresholds(h), ws, g, s));
+        HIP_TRY(h, launch_analysis(a, b, thresholds(h, uses_windows(gr)), ws, g, s));
         HIP_TRY(h, launch_bin(M, ws, g, s));
         if (!learned) {
             for (int cls = kClassWaveSmall; cls <= kClassHeavy; ++cls)
-                HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1), s, (int)h->group_rows));
+                HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1, gr), s, gr));
         }
     }
     if (learned) {
@@ -597,8 +611,8 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         no.M = M;
         for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
             if (h->counts[cls] == 0) continue;
-            HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls]), lw.slot_off, s_col,
-                                      s_val, no, s, (int)h->group_rows));
+            HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls], gr), lw.slot_off, s_col,
+                                      s_val, no, s, gr));
         }
         if (h->counts[kClassHeavy] > 0) {
             int64_t first = 0;
@@ -666,8 +680,9 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
             ws2.class_rows = lw.ovf_rows;
             ws2.ctl = h->ctl2;
             if (h->ovf_light > 0)
-                HIP_TRY(h, launch_numeric(a, b, ws2, kClassBlock, persistent_grid(h, kClassBlock, h->ovf_light), c_rpt,
-                                          c_col, c_val, exact, s, (int)h->group_rows));
+                HIP_TRY(h, launch_numeric(a, b, ws2, kClassBlock,
+                                          persistent_grid(h, kClassBlock, h->ovf_light, h->plan_group_rows), c_rpt,
+                                          c_col, c_val, exact, s, h->plan_group_rows));
             if (h->ovf_heavy > 0 &&
                 (rc = run_heavy(h, a, b, ws, lw.ovf_rows + M, h->ovf_heavy, c_rpt, c_col, c_val, exact, h->ctl2, s)))
                 return rc;
@@ -682,8 +697,8 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     }
     for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
         if (h->counts[cls] == 0) continue;
-        HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls]), c_rpt, c_col, c_val,
-                                  exact, s, (int)h->group_rows));
+        HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls], h->plan_group_rows), c_rpt,
+                                  c_col, c_val, exact, s, h->plan_group_rows));
     }
     if (h->counts[kClassHeavy] > 0) {
         int64_t first = 0;
@@ -1076,7 +1091,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
         hipStream_t cs = h->cap_stream;
         HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t e = launch_batched_begin(d_stat, cs);
-        const Thresholds th = thresholds(h);
+        const Thresholds th = thresholds(h, false);
         for (auto &x : st) {
             if (e != hipSuccess) break;
             BatchStage bs;

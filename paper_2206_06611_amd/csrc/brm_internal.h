@@ -34,7 +34,13 @@ struct Thresholds {
     int64_t group_max;
     int64_t block_max;
     int32_t force;  // -1: none
+    int32_t windows;  // 1: the wave-small class holds only rows whose lists fit lane windows
 };
+
+// row_class byte: the class in the low bits; for wave-small rows under
+// lane windows, log2 of the window width above them
+constexpr int kClassBits = 3;
+constexpr uint8_t kClassMask = (1u << kClassBits) - 1;
 
 // Device control block (one per handle).
 struct Ctl {

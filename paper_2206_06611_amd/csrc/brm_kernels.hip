@@ -37,9 +37,28 @@ __device__ __forceinline__ int64_t ld_rpt(const void *p, int64_t i) {
     return (int64_t)(reinterpret_cast<const I *>(p)[i]);
 }
 
-__device__ __forceinline__ int classify(int64_t nlists, int64_t nprod, const Thresholds &th) {
+__host__ __device__ __forceinline__ int ceil_log2(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << r) < x) ++r;
+    return r;
+}
+
+// Lane windows of a row (register merging of rows with at most 64 products):
+// its lists padded to the next power of two of the longest, their count to
+// the next power of two, all in one wavefront.  Returns log2 of the window
+// width, or -1 when the row does not fit.
+__device__ __forceinline__ int window_shift(int64_t nlists, int64_t maxlen) {
+    if (nlists > kWave || maxlen > kWave) return -1;
+    const int sw = ceil_log2(maxlen > 0 ? maxlen : 1);
+    const int sl = ceil_log2(nlists > 0 ? nlists : 1);
+    return sw + sl <= 6 ? sw : -1;
+}
+
+__device__ __forceinline__ int classify(int64_t nlists, int64_t nprod, int64_t maxlen, const Thresholds &th) {
     if (nprod == 0) return kClassEmpty;
     const int64_t w = nprod > nlists ? nprod : nlists;  // LDS holds both products and lists
+    // under lane windows, the wave-small class takes only rows that fit them
+    const bool small_ok = !th.windows || window_shift(nlists, maxlen) >= 0;
     if (th.force >= kClassWaveSmall) {
         // debug routing: every non-empty row that fits the forced class goes
         // there (single-list rows included), every other row to the heavy path
@@ -48,10 +67,11 @@ __device__ __forceinline__ int classify(int64_t nlists, int64_t nprod, const Thr
                             : th.force == kClassGroup   ? kCapGroup
                             : th.force == kClassBlock   ? kCapBlock
                                                         : 0;
+        if (th.force == kClassWaveSmall && !small_ok) return kClassHeavy;
         return w <= cap ? th.force : kClassHeavy;
     }
     if (nlists == 1) return kClassCopy;
-    if (w <= th.wave_small_max) return kClassWaveSmall;
+    if (w <= th.wave_small_max && small_ok) return kClassWaveSmall;
     if (w <= th.wave_max) return kClassWave;
     if (w <= th.group_max) return kClassGroup;
     if (w <= th.block_max) return kClassBlock;
@@ -76,6 +96,11 @@ struct Lists {
             bs = ld_rpt<IB>(b_rpt, k);
             ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
         }
+    }
+    // the per-entry arrays only (they must be present)
+    __device__ __forceinline__ void get_ent(int64_t p, int64_t &bs, int &ln) const {
+        bs = ld_rpt<IB>(ent_bs, p);
+        ln = ent_len[p];
     }
 };
 
@@ -184,6 +209,7 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
     __shared__ int64_t s_nprod;
     __shared__ int64_t s_start[kW][kWave + 1];  // entry offset of every row of the wave's chunk
     __shared__ unsigned long long s_np[kW][kWave];
+    __shared__ int32_t s_mx[kW][kWave];  // longest list of every row
     if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nprod = 0;
     __syncthreads();
@@ -209,6 +235,7 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             a1 = ld_rpt<IA>(a_rpt, i + 1);
             s_start[w][lane] = a0;
             s_np[w][lane] = 0ull;
+            s_mx[w][lane] = 0;
         }
         if (lane == nrows - 1) s_start[w][nrows] = a1;
         wave_sync();
@@ -221,13 +248,16 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             ent_len[e] = (int32_t)n;
             const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
             atomicAdd(&s_np[w][r], (unsigned long long)n);
+            atomicMax(&s_mx[w][r], (int32_t)n);
         }
         wave_sync();
         if (in) {
             const int64_t np = (int64_t)s_np[w][lane];
-            const int cls = classify(a1 - a0, np, th);
+            const int mx = s_mx[w][lane];
+            const int cls = classify(a1 - a0, np, mx, th);
             row_nprod[i] = np;
-            row_class[i] = (uint8_t)cls;
+            const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx) : 0;
+            row_class[i] = (uint8_t)(cls | (sw << kClassBits));
             if (cls == kClassEmpty) row_size[i] = 0;
             if (cls == kClassCopy) row_size[i] = (int32_t)np;
 #pragma unroll
@@ -290,7 +320,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const uint8_t *row_class
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += stride) {
-        const int cls = row_class[i];
+        const int cls = row_class[i] & kClassMask;
 #pragma unroll
         for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
     }
@@ -316,7 +346,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const uint8_t *row_class
     const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
     for (int64_t base = base0; base < M; base += stride) {
         const int64_t i = base + lane;
-        const int cls = i < M ? (int)row_class[i] : -1;
+        const int cls = i < M ? (int)(row_class[i] & kClassMask) : -1;
 #pragma unroll
         for (int c = 0; c < kNumClasses; ++c) {
             const uint64_t m = wave_ballot(cls == c);
@@ -535,6 +565,12 @@ __global__ __launch_bounds__(T *TEAMS) void k_sym_group(int cls, const void *a_r
     }
 }
 
+// pipelined counting of short rows (defined with the numeric kernels)
+template <bool HASH, typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lists<IB> lists,
+                                                 const int32_t *b_col, const uint8_t *row_class,
+                                                 const int32_t *class_rows, int32_t *row_size, Ctl *ctl);
+
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                            int grid, hipStream_t s, int group_rows) {
 #define BRM_SYM(KERNEL, BLOCK, IA, IB)                                                        \
@@ -553,8 +589,27 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
     } while (0)
     switch (cls) {
         case kClassWaveSmall:
-            if (group_rows <= 1) {
+            if (group_rows == 0) {
                 BRM_SYM_ALL(64, 4, 2 * kCapWaveSmall);
+                break;
+            }
+            if (group_rows == 1 || group_rows == 2) {
+                // 1: LDS hash counts, 2: window-merge counts
+#define BRM_SYM_WIN(H, IA, IB)                                                                              \
+    hipLaunchKernelGGL((k_sym_win<H, IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), \
+                       B.col, ws.row_class, ws.class_rows, ws.row_size, ws.ctl)
+#define BRM_SYM_WIN_ALL(H)                                                        \
+    if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_SYM_WIN(H, int32_t, int32_t);  \
+    else if (A.rpt_bytes == 4) BRM_SYM_WIN(H, int32_t, int64_t);                 \
+    else if (B.rpt_bytes == 4) BRM_SYM_WIN(H, int64_t, int32_t);                 \
+    else BRM_SYM_WIN(H, int64_t, int64_t)
+                if (group_rows == 1) {
+                    BRM_SYM_WIN_ALL(true);
+                } else {
+                    BRM_SYM_WIN_ALL(false);
+                }
+#undef BRM_SYM_WIN_ALL
+#undef BRM_SYM_WIN
                 break;
             }
             if (A.rpt_bytes == 4 && B.rpt_bytes == 4)
@@ -1170,10 +1225,10 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt
 }
 
 // ---------------------------------------------------------------------------
-// numeric, rows of at most 64 products whose lists fit power-of-two lane
-// windows (lists padded to W0 = the next power of two of the longest list,
-// their count to the next power of two, W0 * lists <= 64): the whole BRMerge
-// runs in registers.  Every lane holds one entry; list p occupies lanes
+// rows of at most 64 products whose lists fit power-of-two lane windows
+// (lists padded to W0 = the next power of two of the longest list, their
+// count to the next power of two, W0 * lists <= 64): the whole BRMerge runs
+// in registers.  Every lane holds one entry; list p occupies lanes
 // [p W0, (p+1) W0) in ascending column order, padded with an empty marker.
 // Round r merges windows 2q and 2q+1 of width W0 2^r with a bitonic merge
 // (a mirror compare-exchange, then half-cleaners at distances W/2 .. 1), so
@@ -1181,7 +1236,9 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt
 // columns (one from each list) end up adjacent; the first keeps the sum of
 // the two values, the second is emptied and the pair's window is compacted
 // through LDS (skipped when the wavefront has no duplicate).  Rows that do
-// not fit the windows take the LDS path of the same class.
+// not fit the windows take the LDS path of the same class.  The next rows'
+// indices, row pointers and list descriptors are loaded while the current
+// row merges (three-stage software pipeline).
 // ---------------------------------------------------------------------------
 constexpr int32_t kEmptyCol = 0x7fffffff;
 
@@ -1191,118 +1248,321 @@ __device__ __forceinline__ int next_pow2(int x) {
     return p;
 }
 
+// value of lane (lane ^ D) for a distance known at compile time: DPP inside
+// a row of 16 lanes where one pattern serves, ds_swizzle inside 32 lanes,
+// ds_bpermute across the halves of the wavefront.  Every lane must be active.
+template <int D>
+__device__ __forceinline__ int xor_lane(int x, int lane) {
+    static_assert(D > 0 && D < kWave, "lane distance");
+    if constexpr (D == 1)
+        return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    else if constexpr (D == 2)
+        return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    else if constexpr (D == 3)
+        return __builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+    else if constexpr (D == 7)
+        return __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    else if constexpr (D == 15)
+        return __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false);  // row_mirror
+    else if constexpr (D < 32)
+        return __builtin_amdgcn_ds_swizzle(x, 0x1F | (D << 10));  // bit mode: and 31, xor D
+    else
+        return __builtin_amdgcn_ds_bpermute((lane ^ D) << 2, x);
+}
+
+template <int D>
+__device__ __forceinline__ double xor_lane(double x, int lane) {
+    const int64_t b = __double_as_longlong(x);
+    const int lo = xor_lane<D>((int)(uint32_t)b, lane);
+    const int hi = xor_lane<D>((int)(b >> 32), lane);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// one compare-exchange of a bitonic network at distance D; the lower lane of
+// a pair keeps the smaller column
+template <bool VALUES, int D>
+__device__ __forceinline__ void win_cmpx(int32_t &c, double &v, int lane, bool lower) {
+    const int32_t pc = xor_lane<D>(c, lane);
+    double pv = 0.0;
+    if constexpr (VALUES) pv = xor_lane<D>(v, lane);
+    const bool take = lower ? pc < c : pc > c;
+    if (take) {
+        c = pc;
+        if constexpr (VALUES) v = pv;
+    }
+}
+
+template <bool VALUES, int D>
+__device__ __forceinline__ void win_half_cleaners(int32_t &c, double &v, int lane) {
+    if constexpr (D >= 1) {
+        win_cmpx<VALUES, D>(c, v, lane, (lane & D) == 0);
+        win_half_cleaners<VALUES, D / 2>(c, v, lane);
+    }
+}
+
+// One round of the accumulating phase on lane windows: window pairs of width
+// W (two sorted lists, each padded with empty markers) become sorted windows
+// of width 2W by a bitonic merge (the mirror stage turns the pair into a
+// bitonic sequence, the half-cleaners sort it).  Equal columns, one from each
+// list, end up adjacent; the first takes the sum, the second is emptied and
+// the windows are compacted through LDS when the wavefront has any such
+// pair.  VALUES = false only counts (symbolic use).
+template <bool VALUES, int W>
+__device__ __forceinline__ void win_round(int32_t &c, double &v, int lane, int32_t *xc, double *xv) {
+    win_cmpx<VALUES, 2 * W - 1>(c, v, lane, (lane & W) == 0);
+    win_half_cleaners<VALUES, W / 2>(c, v, lane);
+    constexpr int W2 = 2 * W;
+    const int wpos = lane & (W2 - 1);
+    const int32_t pc = __shfl_up(c, 1, kWave);
+    const bool dead = c != kEmptyCol && wpos > 0 && pc == c;
+    if constexpr (VALUES) {
+        const int32_t nc = __shfl_down(c, 1, kWave);
+        const double nv = __shfl_down(v, 1, kWave);
+        if (c != kEmptyCol && !dead && wpos + 1 < W2 && nc == c) v = v + nv;
+    }
+    if (wave_ballot(dead)) {
+        if (dead) c = kEmptyCol;
+        // compact every window: live entries to its front, in order
+        const uint64_t live = wave_ballot(c != kEmptyCol);
+        const int wbase = lane & ~(W2 - 1);
+        const uint64_t wmask = (W2 == 64) ? ~0ull : (((1ull << W2) - 1) << wbase);
+        const int rank = __popcll(live & wmask & ((1ull << lane) - 1));
+        xc[lane] = kEmptyCol;
+        wave_sync();
+        if (c != kEmptyCol) {
+            xc[wbase + rank] = c;
+            if constexpr (VALUES) xv[wbase + rank] = v;
+        }
+        wave_sync();
+        c = xc[lane];
+        if constexpr (VALUES) v = c != kEmptyCol ? xv[lane] : 0.0;
+        wave_sync();
+    }
+}
+
+// rounds from list width W0 up to the padded total T (both powers of two,
+// wavefront-uniform)
+template <bool VALUES>
+__device__ __forceinline__ void win_rounds(int32_t &c, double &v, int W0, int T, int lane, int32_t *xc,
+                                           double *xv) {
+    for (int W = W0; W < T; W <<= 1) {
+        switch (W) {
+            case 1: win_round<VALUES, 1>(c, v, lane, xc, xv); break;
+            case 2: win_round<VALUES, 2>(c, v, lane, xc, xv); break;
+            case 4: win_round<VALUES, 4>(c, v, lane, xc, xv); break;
+            case 8: win_round<VALUES, 8>(c, v, lane, xc, xv); break;
+            case 16: win_round<VALUES, 16>(c, v, lane, xc, xv); break;
+            default: win_round<VALUES, 32>(c, v, lane, xc, xv); break;
+        }
+    }
+}
+
+// 64-bit value of lane j (j wavefront-uniform)
+__device__ __forceinline__ int64_t lane_value(int64_t x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), j);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int lane_value(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x, int lane) {
+    T o = xor_lane<1>(x, lane);
+    x = o > x ? o : x;
+    o = xor_lane<2>(x, lane);
+    x = o > x ? o : x;
+    o = xor_lane<4>(x, lane);
+    x = o > x ? o : x;
+    o = xor_lane<8>(x, lane);
+    x = o > x ? o : x;
+    o = xor_lane<16>(x, lane);
+    x = o > x ? o : x;
+    o = xor_lane<32>(x, lane);
+    return o > x ? o : x;
+}
+
+// What masked lanes of the pipelined short-row kernels read instead of A's
+// and B's arrays: an empty column and zeros, so that no value needs masking
+// after its load.  Never written; not const, so that the compiler keeps them
+// as global loads instead of folding their contents into branches.
+__device__ int32_t g_empty_col[1] = {kEmptyCol};
+__device__ int64_t g_zeros[1] = {0};
+
+// Global load through an address the optimiser may not look into: a select
+// between a real and a sentinel address stays one load, instead of becoming
+// a branch per case (which would make the count of loads in flight depend on
+// the path).  The asm statement only pins the address register; it emits no
+// instruction.
+template <typename T>
+__device__ __forceinline__ T load_opaque(const T *p) {
+    using GP = const __attribute__((address_space(1))) T *;
+    GP g = (GP)p;
+    asm volatile("" : "+v"(g));
+    return *g;
+}
+
+// The rows of the wave-small class under lane windows (every one fits them:
+// the analysis put the others in the next class), streamed by one wavefront
+// in chunks of kWave rows.  A chunk's row ids, A row pointers, window widths
+// and C row pointers are loaded at once (lane j holds row j's), so the
+// per-row chain of dependent loads is list descriptors -> B entries only, and
+// that chain is software-pipelined: while row j merges, the B entries of row
+// j+1 and the list descriptors of row j+2 are in flight.  Every lane issues
+// every load of a stage on every iteration (masked lanes read the sentinels
+// above), so the number of memory operations in flight does not depend on
+// the path and the waits stay partial.  VALUES = false counts row sizes;
+// HASH then selects counting by LDS hash instead of window merges.
+template <bool VALUES, bool HASH, typename IA, typename IB>
+__device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
+                                           const int32_t *b_col, const double *b_val, const uint8_t *row_class,
+                                           const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
+                                           double *c_val, int32_t *row_size, Ctl *ctl, const NumOut &no,
+                                           int32_t *tab, int32_t *xc, double *xv, int64_t first, int64_t stride) {
+    const int lane = lane_id();
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    const int64_t nchunks = (count + kWave - 1) / kWave;
+    const IB *ent_bs = static_cast<const IB *>(lists.ent_bs);
+    const int32_t *ent_len = lists.ent_len;
+    for (int64_t ch = first; ch < nchunks; ch += stride) {
+        const int64_t base = ch * kWave;
+        const int n = (int)(count - base < kWave ? count - base : kWave);
+        // chunk meta data, one row per lane: row, first entry of A, lists,
+        // window width (log2) and padded total (0 beyond the chunk)
+        int64_t m_row = 0, m_a0 = 0, m_cs = 0;
+        int m_L = 0, m_sw = 0, m_T = 0, m_cap = 0;
+        if (lane < n) {
+            m_row = class_rows[start + base + lane];
+            m_a0 = ld_rpt<IA>(a_rpt, m_row);
+            m_L = (int)(ld_rpt<IA>(a_rpt, m_row + 1) - m_a0);
+            m_sw = row_class[m_row] >> kClassBits;
+            m_T = 1 << (m_sw + ceil_log2(m_L > 0 ? m_L : 1));
+            if constexpr (VALUES) {
+                m_cs = c_rpt[m_row];
+                m_cap = (int)(c_rpt[m_row + 1] - m_cs);  // a row's size fits 31 bits
+            }
+        }
+        // list descriptors of row j: lane t < L holds list t (empty beyond)
+        auto load_lists = [&](int j, IB &bs, int &ln, double &av) {
+            const int jj = j < n ? j : 0;
+            const int64_t p = lane_value(m_a0, jj) + lane;
+            const bool ok = j < n && lane < lane_value(m_L, jj);
+            bs = load_opaque(ok ? ent_bs + p : reinterpret_cast<const IB *>(&g_zeros[0]));
+            ln = load_opaque(ok ? ent_len + p : reinterpret_cast<const int32_t *>(&g_zeros[0]));
+            if constexpr (VALUES) av = load_opaque(ok ? a_val + p : reinterpret_cast<const double *>(&g_zeros[0]));
+        };
+        // multiplying phase of row j into the lane windows (the products are
+        // formed where the row is consumed): lane t holds entry t mod W0 of
+        // list t / W0
+        auto gather = [&](int j, IB bs, int ln, double av, int32_t &c, double &bv, double &lav) {
+            const int jj = j < n ? j : 0;
+            const int L = j < n ? lane_value(m_L, jj) : 0;
+            const int sw = lane_value(m_sw, jj);
+            const int li = lane >> sw, o = lane & ((1 << sw) - 1);
+            // every shuffle with all lanes active
+            const int64_t lbs = __shfl((int64_t)bs, li, kWave);
+            const int lln = __shfl(ln, li, kWave);
+            lav = 0.0;
+            if constexpr (VALUES) lav = __shfl(av, li, kWave);
+            const bool ok = li < L && o < lln;
+            c = load_opaque(ok ? b_col + (lbs + o) : &g_empty_col[0]);
+            bv = 0.0;
+            if constexpr (VALUES) bv = load_opaque(ok ? b_val + (lbs + o) : reinterpret_cast<const double *>(&g_zeros[0]));
+        };
+        struct ListStageRegs {  // list descriptors of one row
+            IB bs;
+            int ln;
+            double av;
+        };
+        struct GatherRegs {  // B entries of one row in the lane windows
+            int32_t c;
+            double bv, av;
+        };
+        // one pipeline step: lists of row j+2 -> lo, B entries of row j+1
+        // (from li) -> go, accumulating phase and write-out of row j (gi)
+        auto step = [&](int j, const ListStageRegs &li, ListStageRegs &lo, const GatherRegs &gi, GatherRegs &go) {
+            load_lists(j + 2, lo.bs, lo.ln, lo.av);
+            gather(j + 1, li.bs, li.ln, li.av, go.c, go.bv, go.av);
+            const int64_t row = lane_value(m_row, j);
+            int32_t c = gi.c;
+            double v = 0.0;
+            if constexpr (VALUES) v = gi.av * gi.bv;  // one rounded product
+            int len;
+            if constexpr (!VALUES && HASH) {
+                tab[lane] = -1;
+                tab[lane + kWave] = -1;
+                wave_sync();
+                const int added = c != kEmptyCol ? hash_insert<2 * kWave>(tab, c) : 0;
+                len = __popcll(wave_ballot(added != 0));
+                wave_sync();
+            } else {
+                win_rounds<VALUES>(c, v, 1 << lane_value(m_sw, j), lane_value(m_T, j), lane, xc, xv);
+                const bool live = c != kEmptyCol;
+                len = __popcll(wave_ballot(live));
+                if constexpr (VALUES) {
+                    const int64_t cs = lane_value(m_cs, j);
+                    const int cap = lane_value(m_cap, j);
+                    if (live && lane < cap) {
+                        c_col[cs + lane] = c;
+                        c_val[cs + lane] = v;
+                    }
+                }
+            }
+            if (lane == 0) {
+                if constexpr (VALUES)
+                    finish_row(no, ctl, row, len, lane_value(m_cap, j), false);
+                else
+                    row_size[row] = len;
+            }
+        };
+        ListStageRegs la, lb;
+        GatherRegs ga, gb;
+        la.av = lb.av = 0.0;
+        {
+            ListStageRegs l0;
+            l0.av = 0.0;
+            load_lists(0, l0.bs, l0.ln, l0.av);
+            load_lists(1, la.bs, la.ln, la.av);
+            gather(0, l0.bs, l0.ln, l0.av, ga.c, ga.bv, ga.av);
+        }
+        // unrolled by two: the register sets alternate roles, so no register
+        // with a load in flight is copied at the loop latch
+        for (int j = 0; j < n; j += 2) {
+            step(j, la, lb, ga, gb);
+            if (j + 1 < n) step(j + 1, lb, la, gb, ga);
+        }
+        // the stages loaded past the chunk's end are drained here, once
+        asm volatile("" ::"v"(ga.c), "v"(gb.c), "v"(la.ln), "v"(lb.ln), "v"(la.bs), "v"(lb.bs));
+        if constexpr (VALUES) asm volatile("" ::"v"(ga.bv), "v"(gb.bv), "v"(la.av), "v"(lb.av));
+    }
+}
+
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_num_win(int cls, const void *a_rpt, Lists<IB> lists,
                                                  const double *a_val, const int32_t *b_col,
-                                                 const double *b_val, const int32_t *class_rows,
-                                                 const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
-                                                 NumOut no) {
-    __shared__ NumLds<kWave, kCapWaveSmall> lds[4];
+                                                 const double *b_val, const uint8_t *row_class,
+                                                 const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
+                                                 double *c_val, Ctl *ctl, NumOut no) {
     __shared__ int32_t xc[4][kWave];
     __shared__ double xv[4][kWave];
-    const int team = threadIdx.x / kWave, lane = lane_id();
-    NumLds<kWave, kCapWaveSmall> &s = lds[team];
-    const int64_t count = ctl->count[cls];
-    const int64_t start = class_start(ctl, cls);
-    for (int64_t idx = (int64_t)blockIdx.x * 4 + team; idx < count; idx += (int64_t)gridDim.x * 4) {
-        const int64_t row = class_rows[start + idx];
-        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
-        const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
-        const int64_t cs = c_rpt[row];
-        const int64_t cap = c_rpt[row + 1] - cs;
-        int64_t bs = 0;
-        int ln = 0;
-        double av = 0.0;
-        if (lane < L) {
-            lists.get(a0 + lane, bs, ln);
-            av = a_val[a0 + lane];
-        }
-        int mx = ln;
-#pragma unroll
-        for (int d = kWave / 2; d >= 1; d >>= 1) {
-            const int o = __shfl_xor(mx, d, kWave);
-            mx = o > mx ? o : mx;
-        }
-        const int W0 = next_pow2(mx > 0 ? mx : 1);
-        const int LP = next_pow2(L);
-        if (L > kWave || W0 * LP > kWave) {
-            // lists too uneven for the windows: LDS merge
-            const int rl = brmerge_range_lds<kWave, kCapWaveSmall, 1, IB>(s, lane, a0, L, lists, a_val, b_col,
-                                                                          b_val, c_col + cs, c_val + cs, cap);
-            if (lane == 0) finish_row(no, ctl, row, rl, cap, false);
-            continue;
-        }
-        // multiplying phase: lane t holds entry t mod W0 of list t / W0
-        const int sw = __builtin_ctz(W0);
-        const int li = lane >> sw, o = lane & (W0 - 1);
-        const int64_t lbs = __shfl(bs, li, kWave);
-        const int lln = __shfl(ln, li, kWave);
-        const double lav = __shfl(av, li, kWave);
-        int32_t c = kEmptyCol;
-        double v = 0.0;
-        if (li < L && o < lln) {
-            c = b_col[lbs + o];
-            v = lav * b_val[lbs + o];
-        }
-        // accumulating phase: ceil(log2 L) rounds of pairwise merges
-        for (int W = W0; W < W0 * LP; W <<= 1) {
-            // mirror stage over the window pair of width 2W, then half-cleaners
-            for (int d = 2 * W - 1, first = 1; d >= 1; d = first ? W / 2 : d / 2, first = 0) {
-                const int32_t pc = __shfl_xor(c, d, kWave);
-                const double pv = __shfl_xor(v, d, kWave);
-                const bool lower = first ? (lane & W) == 0 : (lane & d) == 0;
-                const bool take = lower ? pc < c : pc > c;
-                if (take) {
-                    c = pc;
-                    v = pv;
-                }
-                if (d == 1 && !first) break;
-                if (first && W == 1) break;
-            }
-            // equal columns of the pair are now neighbours: the first takes
-            // the sum, the second is emptied
-            const int W2 = 2 * W;
-            const int wpos = lane & (W2 - 1);
-            const int32_t nc = __shfl_down(c, 1, kWave);
-            const double nv = __shfl_down(v, 1, kWave);
-            const int32_t pc = __shfl_up(c, 1, kWave);
-            const bool has_next = wpos + 1 < W2, has_prev = wpos > 0;
-            const bool dead = c != kEmptyCol && has_prev && pc == c;
-            if (c != kEmptyCol && !dead && has_next && nc == c) v = v + nv;
-            const uint64_t dm = wave_ballot(dead);
-            if (dm) {
-                if (dead) {
-                    c = kEmptyCol;
-                    v = 0.0;
-                }
-                // compact every window: live entries to its front, in order
-                const uint64_t live = wave_ballot(c != kEmptyCol);
-                const int wbase = lane & ~(W2 - 1);
-                const uint64_t wmask = (W2 == 64) ? ~0ull : (((1ull << W2) - 1) << wbase);
-                const int rank = __popcll(live & wmask & ((1ull << lane) - 1));
-                xc[team][lane] = kEmptyCol;
-                xv[team][lane] = 0.0;
-                wave_sync();
-                if (c != kEmptyCol) {
-                    xc[team][wbase + rank] = c;
-                    xv[team][wbase + rank] = v;
-                }
-                wave_sync();
-                c = xc[team][lane];
-                v = xv[team][lane];
-                wave_sync();
-            }
-        }
-        // Algorithm 1's final store: the live entries are the sorted row
-        const bool live = c != kEmptyCol;
-        const uint64_t lm = wave_ballot(live);
-        const int n = __popcll(lm);
-        if (live && lane < cap) {
-            c_col[cs + lane] = c;
-            c_val[cs + lane] = v;
-        }
-        if (lane == 0) finish_row(no, ctl, row, n, cap, false);
-    }
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    win_chunks<true, false, IA, IB>(cls, a_rpt, lists, a_val, b_col, b_val, row_class, class_rows, c_rpt, c_col,
+                                    c_val, nullptr, ctl, no, nullptr, xc[team], xv[team],
+                                    (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
+}
+
+template <bool HASH, typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lists<IB> lists,
+                                                 const int32_t *b_col, const uint8_t *row_class,
+                                                 const int32_t *class_rows, int32_t *row_size, Ctl *ctl) {
+    __shared__ int32_t tab[4][2 * kWave];
+    __shared__ int32_t xc[4][kWave];
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    NumOut no;
+    no.bound = 0;
+    win_chunks<false, HASH, IA, IB>(cls, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows, nullptr,
+                                    nullptr, nullptr, row_size, ctl, no, tab[team], xc[team], nullptr,
+                                    (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
 }
 
 // Several short rows per team: the rows of a class whose lists and products
@@ -1369,11 +1629,15 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
                 BRM_NUM_ALL(64, 4, kCapWaveSmall);
                 break;
             }
-            if (group_rows == 1) {
-                if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM((k_num_win<int32_t, int32_t>), 256, int32_t);
-                else if (A.rpt_bytes == 4) BRM_NUM((k_num_win<int32_t, int64_t>), 256, int64_t);
-                else if (B.rpt_bytes == 4) BRM_NUM((k_num_win<int64_t, int32_t>), 256, int32_t);
-                else BRM_NUM((k_num_win<int64_t, int64_t>), 256, int64_t);
+            if (group_rows == 1 || group_rows == 2) {
+#define BRM_NUM_WIN(IA, IB)                                                                                      \
+    hipLaunchKernelGGL((k_num_win<IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), A.val, \
+                       B.col, B.val, ws.row_class, ws.class_rows, c_rpt, c_col, c_val, ws.ctl, no)
+                if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM_WIN(int32_t, int32_t);
+                else if (A.rpt_bytes == 4) BRM_NUM_WIN(int32_t, int64_t);
+                else if (B.rpt_bytes == 4) BRM_NUM_WIN(int64_t, int32_t);
+                else BRM_NUM_WIN(int64_t, int64_t);
+#undef BRM_NUM_WIN
                 break;
             }
             if (A.rpt_bytes == 4 && B.rpt_bytes == 4)
@@ -1921,7 +2185,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
             const int32_t k = pr.a_col[q];
             nprod += ld_rpt<IB>(pr.b_rpt, k + 1) - ld_rpt<IB>(pr.b_rpt, k);
         }
-        const int cls = classify(a1 - a0, nprod, th);
+        const int cls = classify(a1 - a0, nprod, 0, th);
         row_nprod[g] = nprod;
         row_class[g] = (uint8_t)cls;
         if (cls == kClassEmpty || cls == kClassHeavy) row_size[g] = 0;  // heavy rows: unsupported, flagged
