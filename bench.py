@@ -279,7 +279,7 @@ def main():
                    "classes": h.class_rows()},
         "effective_gbs_all_phases": round(total_bytes / (ms_step / 1e3) / 1e9, 2),
         "numeric_ms": round(num_ms, 4),
-        "roofline": {"bound": "hbm", "kernel": "numeric pass (k_num_lds, BRMerge in LDS)",
+        "roofline": {"bound": "hbm", "kernel": "numeric pass, rows of <= 64 products (k_num_win, BRMerge in registers)",
                      "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "algorithmic_bytes": nb},

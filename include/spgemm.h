@@ -106,9 +106,14 @@ typedef enum {
     SPG_OPT_LEARNED_FORCE = 11,  /* testing only: 1 sizes every predicted row at its lower bound
                                     (the longest list), so that most rows take the fallback */
     SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
-                                    1 (default) one row per wavefront, merged in registers when its
-                                    lists fit power-of-two lane windows (else in LDS); 0 one row
-                                    per wavefront in LDS; 4 four rows per wavefront in LDS */
+                                    1 (default) one row per wavefront, merged in registers; the
+                                    class then holds only rows whose lists fit power-of-two lane
+                                    windows (the others go to the next class), and only when
+                                    B has fewer than 2^26 columns (else 0 is used); 2 as 1, with
+                                    symbolic counts by LDS hash instead of register merges; 0 one
+                                    row per wavefront in LDS; 4 four rows per wavefront in LDS.
+                                    The value in force at spgemm_symbolic also serves the
+                                    spgemm_numeric that follows it. */
 } spg_option;
 
 /* Allocation methods (SPG_OPT_ALLOC). */

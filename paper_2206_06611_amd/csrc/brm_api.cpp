@@ -570,7 +570,9 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     const bool learned = h->alloc == SPG_ALLOC_LEARNED;
     // the short-row kernels are fixed with the classification: the numeric
     // pass uses what this call chose
-    const int gr = (int)h->group_rows;
+    int gr = (int)h->group_rows;
+    // the register merges key columns in 26 bits
+    if (uses_windows(gr) && B->cols >= ((int64_t)1 << 26)) gr = 0;
     h->plan_valid = false;
     h->plan_group_rows = gr;
     if (learned && !h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "learned allocation needs a trained or loaded predictor");

@@ -594,7 +594,7 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
                 break;
             }
             if (group_rows == 1 || group_rows == 2) {
-                // 1: LDS hash counts, 2: window-merge counts
+                // 1: window-merge counts, 2: LDS hash counts
 #define BRM_SYM_WIN(H, IA, IB)                                                                              \
     hipLaunchKernelGGL((k_sym_win<H, IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), \
                        B.col, ws.row_class, ws.class_rows, ws.row_size, ws.ctl)
@@ -603,7 +603,7 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
     else if (A.rpt_bytes == 4) BRM_SYM_WIN(H, int32_t, int64_t);                 \
     else if (B.rpt_bytes == 4) BRM_SYM_WIN(H, int64_t, int32_t);                 \
     else BRM_SYM_WIN(H, int64_t, int64_t)
-                if (group_rows == 1) {
+                if (group_rows == 2) {
                     BRM_SYM_WIN_ALL(true);
                 } else {
                     BRM_SYM_WIN_ALL(false);
@@ -1229,132 +1229,155 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt
 // (lists padded to W0 = the next power of two of the longest list, their
 // count to the next power of two, W0 * lists <= 64): the whole BRMerge runs
 // in registers.  Every lane holds one entry; list p occupies lanes
-// [p W0, (p+1) W0) in ascending column order, padded with an empty marker.
+// [p W0, (p+1) W0) in ascending column order, padded with empty slots.
 // Round r merges windows 2q and 2q+1 of width W0 2^r with a bitonic merge
 // (a mirror compare-exchange, then half-cleaners at distances W/2 .. 1), so
-// the two lists of a pair are merged, never mixed with another pair.  Equal
-// columns (one from each list) end up adjacent; the first keeps the sum of
-// the two values, the second is emptied and the pair's window is compacted
-// through LDS (skipped when the wavefront has no duplicate).  Rows that do
-// not fit the windows take the LDS path of the same class.  The next rows'
-// indices, row pointers and list descriptors are loaded while the current
-// row merges (three-stage software pipeline).
+// the two lists of a pair are merged, never mixed with another pair.
+//
+// What the network sorts is a 32-bit key: the column above kKeyLaneBits bits
+// that name the lane holding the entry's value; an empty slot has all column
+// bits set (it sorts after every column) and its own lane below them.  The
+// fp64 values stay where the multiplying phase formed them, so a
+// compare-exchange moves one register.  Lanes of the left list of a pair
+// always have lower numbers than those of the right list (entries never
+// leave their window pair), so of two equal columns the left one comes
+// first.  When a round leaves equal columns (one from each list) side by
+// side, the first takes the sum left + right, the second is dropped and
+// every window is compacted through LDS, values moving into key order
+// (skipped when the wavefront has no such pair).  Columns must be below
+// 2^(32 - kKeyLaneBits) - 1.
 // ---------------------------------------------------------------------------
 constexpr int32_t kEmptyCol = 0x7fffffff;
-
-__device__ __forceinline__ int next_pow2(int x) {
-    int p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
+constexpr int kKeyLaneBits = 6;
+constexpr uint32_t kKeyEmpty = ~0u << kKeyLaneBits;
+constexpr uint32_t kKeyLaneMask = (1u << kKeyLaneBits) - 1;
 
 // value of lane (lane ^ D) for a distance known at compile time: DPP inside
 // a row of 16 lanes where one pattern serves, ds_swizzle inside 32 lanes,
 // ds_bpermute across the halves of the wavefront.  Every lane must be active.
 template <int D>
-__device__ __forceinline__ int xor_lane(int x, int lane) {
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x, int lane) {
     static_assert(D > 0 && D < kWave, "lane distance");
+    const int xi = (int)x;
     if constexpr (D == 1)
-        return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
     else if constexpr (D == 2)
-        return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
     else if constexpr (D == 3)
-        return __builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
     else if constexpr (D == 7)
-        return __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x141, 0xF, 0xF, false);  // row_half_mirror
     else if constexpr (D == 15)
-        return __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false);  // row_mirror
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x140, 0xF, 0xF, false);  // row_mirror
     else if constexpr (D < 32)
-        return __builtin_amdgcn_ds_swizzle(x, 0x1F | (D << 10));  // bit mode: and 31, xor D
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(xi, 0x1F | (D << 10));  // bit mode: and 31, xor D
     else
-        return __builtin_amdgcn_ds_bpermute((lane ^ D) << 2, x);
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ D) << 2, xi);
+}
+
+// value of lane - 1 / lane + 1 (DPP shifts across the wavefront; the lane
+// at the edge gets 0)
+__device__ __forceinline__ uint32_t lane_prev(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, false);  // wave_shr:1
+}
+__device__ __forceinline__ uint32_t lane_next(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+
+// compare-exchange at distance D: the lower lane of a pair keeps the smaller
+// key (keys of a wavefront are distinct, or equal keys are interchangeable)
+template <int D>
+__device__ __forceinline__ void key_cmpx(uint32_t &k, int lane, bool lower) {
+    const uint32_t p = xor_lane<D>(k, lane);
+    const uint32_t lo = p < k ? p : k;
+    const uint32_t hi = p < k ? k : p;
+    k = lower ? lo : hi;
 }
 
 template <int D>
-__device__ __forceinline__ double xor_lane(double x, int lane) {
-    const int64_t b = __double_as_longlong(x);
-    const int lo = xor_lane<D>((int)(uint32_t)b, lane);
-    const int hi = xor_lane<D>((int)(b >> 32), lane);
-    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-}
-
-// one compare-exchange of a bitonic network at distance D; the lower lane of
-// a pair keeps the smaller column
-template <bool VALUES, int D>
-__device__ __forceinline__ void win_cmpx(int32_t &c, double &v, int lane, bool lower) {
-    const int32_t pc = xor_lane<D>(c, lane);
-    double pv = 0.0;
-    if constexpr (VALUES) pv = xor_lane<D>(v, lane);
-    const bool take = lower ? pc < c : pc > c;
-    if (take) {
-        c = pc;
-        if constexpr (VALUES) v = pv;
-    }
-}
-
-template <bool VALUES, int D>
-__device__ __forceinline__ void win_half_cleaners(int32_t &c, double &v, int lane) {
+__device__ __forceinline__ void key_half_cleaners(uint32_t &k, int lane) {
     if constexpr (D >= 1) {
-        win_cmpx<VALUES, D>(c, v, lane, (lane & D) == 0);
-        win_half_cleaners<VALUES, D / 2>(c, v, lane);
+        key_cmpx<D>(k, lane, (lane & D) == 0);
+        key_half_cleaners<D / 2>(k, lane);
     }
 }
 
-// One round of the accumulating phase on lane windows: window pairs of width
-// W (two sorted lists, each padded with empty markers) become sorted windows
-// of width 2W by a bitonic merge (the mirror stage turns the pair into a
-// bitonic sequence, the half-cleaners sort it).  Equal columns, one from each
-// list, end up adjacent; the first takes the sum, the second is emptied and
-// the windows are compacted through LDS when the wavefront has any such
-// pair.  VALUES = false only counts (symbolic use).
-template <bool VALUES, int W>
-__device__ __forceinline__ void win_round(int32_t &c, double &v, int lane, int32_t *xc, double *xv) {
-    win_cmpx<VALUES, 2 * W - 1>(c, v, lane, (lane & W) == 0);
-    win_half_cleaners<VALUES, W / 2>(c, v, lane);
+// bitonic merge of every pair of sorted windows of width W into one sorted
+// window of width 2W (the mirror stage turns the pair into a bitonic
+// sequence, the half-cleaners sort it)
+template <int W>
+__device__ __forceinline__ void key_merge(uint32_t &k, int lane) {
+    key_cmpx<2 * W - 1>(k, lane, (lane & W) == 0);
+    key_half_cleaners<W / 2>(k, lane);
+}
+
+// One round of the accumulating phase (see above).  v: the values, held by
+// the lanes the keys name.  Returns whether the round compacted (values are
+// then in key order: every key names its own lane).
+template <int W>
+__device__ __forceinline__ bool key_round(uint32_t &k, double &v, int lane, uint32_t *xk, double *xv) {
+    key_merge<W>(k, lane);
     constexpr int W2 = 2 * W;
     const int wpos = lane & (W2 - 1);
-    const int32_t pc = __shfl_up(c, 1, kWave);
-    const bool dead = c != kEmptyCol && wpos > 0 && pc == c;
-    if constexpr (VALUES) {
-        const int32_t nc = __shfl_down(c, 1, kWave);
-        const double nv = __shfl_down(v, 1, kWave);
-        if (c != kEmptyCol && !dead && wpos + 1 < W2 && nc == c) v = v + nv;
+    const uint32_t pk = lane_prev(k);
+    const bool dead = wpos > 0 && k < kKeyEmpty && (k & kKeyEmpty) == (pk & kKeyEmpty);
+    if (!wave_ballot(dead)) return false;
+    const uint32_t nk = lane_next(k);
+    const bool head_dup = wpos + 1 < W2 && k < kKeyEmpty && (k & kKeyEmpty) == (nk & kKeyEmpty);
+    double mv = __shfl(v, (int)(k & kKeyLaneMask), kWave);
+    const double nv = __shfl(v, (int)(nk & kKeyLaneMask), kWave);
+    if (head_dup) mv = mv + nv;  // left + right
+    const bool live = !dead && k < kKeyEmpty;
+    const uint64_t lm = wave_ballot(live);
+    const int wbase = lane & ~(W2 - 1);
+    const uint64_t wmask = (W2 == 64) ? ~0ull : (((1ull << W2) - 1) << wbase);
+    const int rank = __popcll(lm & wmask & ((1ull << lane) - 1));
+    xk[lane] = kKeyEmpty | (uint32_t)lane;
+    wave_sync();
+    if (live) {
+        xk[wbase + rank] = (k & kKeyEmpty) | (uint32_t)(wbase + rank);
+        xv[wbase + rank] = mv;
     }
-    if (wave_ballot(dead)) {
-        if (dead) c = kEmptyCol;
-        // compact every window: live entries to its front, in order
-        const uint64_t live = wave_ballot(c != kEmptyCol);
-        const int wbase = lane & ~(W2 - 1);
-        const uint64_t wmask = (W2 == 64) ? ~0ull : (((1ull << W2) - 1) << wbase);
-        const int rank = __popcll(live & wmask & ((1ull << lane) - 1));
-        xc[lane] = kEmptyCol;
-        wave_sync();
-        if (c != kEmptyCol) {
-            xc[wbase + rank] = c;
-            if constexpr (VALUES) xv[wbase + rank] = v;
-        }
-        wave_sync();
-        c = xc[lane];
-        if constexpr (VALUES) v = c != kEmptyCol ? xv[lane] : 0.0;
-        wave_sync();
-    }
+    wave_sync();
+    k = xk[lane];
+    v = xv[lane];
+    wave_sync();
+    return true;
 }
 
 // rounds from list width W0 up to the padded total T (both powers of two,
-// wavefront-uniform)
-template <bool VALUES>
-__device__ __forceinline__ void win_rounds(int32_t &c, double &v, int W0, int T, int lane, int32_t *xc,
+// wavefront-uniform); returns whether values are in key order at the end
+__device__ __forceinline__ bool key_rounds(uint32_t &k, double &v, int W0, int T, int lane, uint32_t *xk,
                                            double *xv) {
+    bool placed = true;
     for (int W = W0; W < T; W <<= 1) {
         switch (W) {
-            case 1: win_round<VALUES, 1>(c, v, lane, xc, xv); break;
-            case 2: win_round<VALUES, 2>(c, v, lane, xc, xv); break;
-            case 4: win_round<VALUES, 4>(c, v, lane, xc, xv); break;
-            case 8: win_round<VALUES, 8>(c, v, lane, xc, xv); break;
-            case 16: win_round<VALUES, 16>(c, v, lane, xc, xv); break;
-            default: win_round<VALUES, 32>(c, v, lane, xc, xv); break;
+            case 1: placed = key_round<1>(k, v, lane, xk, xv); break;
+            case 2: placed = key_round<2>(k, v, lane, xk, xv); break;
+            case 4: placed = key_round<4>(k, v, lane, xk, xv); break;
+            case 8: placed = key_round<8>(k, v, lane, xk, xv); break;
+            case 16: placed = key_round<16>(k, v, lane, xk, xv); break;
+            default: placed = key_round<32>(k, v, lane, xk, xv); break;
         }
     }
+    return placed;
+}
+
+// Symbolic use: the same merges on bare columns (empty = all ones), equal
+// columns left in place; the distinct columns are counted at the end.
+__device__ __forceinline__ int count_distinct_merged(uint32_t k, int W0, int T, int lane) {
+    for (int W = W0; W < T; W <<= 1) {
+        switch (W) {
+            case 1: key_merge<1>(k, lane); break;
+            case 2: key_merge<2>(k, lane); break;
+            case 4: key_merge<4>(k, lane); break;
+            case 8: key_merge<8>(k, lane); break;
+            case 16: key_merge<16>(k, lane); break;
+            default: key_merge<32>(k, lane); break;
+        }
+    }
+    const uint32_t pk = lane_prev(k);
+    return __popcll(wave_ballot(k != ~0u && (lane == 0 || pk != k)));
 }
 
 // 64-bit value of lane j (j wavefront-uniform)
@@ -1365,21 +1388,6 @@ __device__ __forceinline__ int64_t lane_value(int64_t x, int j) {
 }
 __device__ __forceinline__ int lane_value(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
 
-template <typename T>
-__device__ __forceinline__ T wave_max(T x, int lane) {
-    T o = xor_lane<1>(x, lane);
-    x = o > x ? o : x;
-    o = xor_lane<2>(x, lane);
-    x = o > x ? o : x;
-    o = xor_lane<4>(x, lane);
-    x = o > x ? o : x;
-    o = xor_lane<8>(x, lane);
-    x = o > x ? o : x;
-    o = xor_lane<16>(x, lane);
-    x = o > x ? o : x;
-    o = xor_lane<32>(x, lane);
-    return o > x ? o : x;
-}
 
 // What masked lanes of the pipelined short-row kernels read instead of A's
 // and B's arrays: an empty column and zeros, so that no value needs masking
@@ -1417,7 +1425,7 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                                            const int32_t *b_col, const double *b_val, const uint8_t *row_class,
                                            const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
                                            double *c_val, int32_t *row_size, Ctl *ctl, const NumOut &no,
-                                           int32_t *tab, int32_t *xc, double *xv, int64_t first, int64_t stride) {
+                                           int32_t *tab, uint32_t *xk, double *xv, int64_t first, int64_t stride) {
     const int lane = lane_id();
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
@@ -1484,28 +1492,30 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             load_lists(j + 2, lo.bs, lo.ln, lo.av);
             gather(j + 1, li.bs, li.ln, li.av, go.c, go.bv, go.av);
             const int64_t row = lane_value(m_row, j);
-            int32_t c = gi.c;
-            double v = 0.0;
-            if constexpr (VALUES) v = gi.av * gi.bv;  // one rounded product
+            const int sw = lane_value(m_sw, j);
+            const int T = lane_value(m_T, j);
             int len;
             if constexpr (!VALUES && HASH) {
                 tab[lane] = -1;
                 tab[lane + kWave] = -1;
                 wave_sync();
-                const int added = c != kEmptyCol ? hash_insert<2 * kWave>(tab, c) : 0;
+                const int added = gi.c != kEmptyCol ? hash_insert<2 * kWave>(tab, gi.c) : 0;
                 len = __popcll(wave_ballot(added != 0));
                 wave_sync();
+            } else if constexpr (!VALUES) {
+                len = count_distinct_merged(gi.c == kEmptyCol ? ~0u : (uint32_t)gi.c, 1 << sw, T, lane);
             } else {
-                win_rounds<VALUES>(c, v, 1 << lane_value(m_sw, j), lane_value(m_T, j), lane, xc, xv);
-                const bool live = c != kEmptyCol;
+                uint32_t k = gi.c == kEmptyCol ? (kKeyEmpty | (uint32_t)lane)
+                                               : (((uint32_t)gi.c << kKeyLaneBits) | (uint32_t)lane);
+                double v = gi.av * gi.bv;  // one rounded product
+                if (!key_rounds(k, v, 1 << sw, T, lane, xk, xv)) v = __shfl(v, (int)(k & kKeyLaneMask), kWave);
+                const bool live = k < kKeyEmpty;
                 len = __popcll(wave_ballot(live));
-                if constexpr (VALUES) {
-                    const int64_t cs = lane_value(m_cs, j);
-                    const int cap = lane_value(m_cap, j);
-                    if (live && lane < cap) {
-                        c_col[cs + lane] = c;
-                        c_val[cs + lane] = v;
-                    }
+                const int64_t cs = lane_value(m_cs, j);
+                const int cap = lane_value(m_cap, j);
+                if (live && lane < cap) {
+                    c_col[cs + lane] = (int32_t)(k >> kKeyLaneBits);
+                    c_val[cs + lane] = v;
                 }
             }
             if (lane == 0) {
@@ -1543,11 +1553,11 @@ __global__ __launch_bounds__(256) void k_num_win(int cls, const void *a_rpt, Lis
                                                  const double *b_val, const uint8_t *row_class,
                                                  const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
                                                  double *c_val, Ctl *ctl, NumOut no) {
-    __shared__ int32_t xc[4][kWave];
+    __shared__ uint32_t xk[4][kWave];
     __shared__ double xv[4][kWave];
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     win_chunks<true, false, IA, IB>(cls, a_rpt, lists, a_val, b_col, b_val, row_class, class_rows, c_rpt, c_col,
-                                    c_val, nullptr, ctl, no, nullptr, xc[team], xv[team],
+                                    c_val, nullptr, ctl, no, nullptr, xk[team], xv[team],
                                     (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
 }
 
@@ -1556,12 +1566,11 @@ __global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lis
                                                  const int32_t *b_col, const uint8_t *row_class,
                                                  const int32_t *class_rows, int32_t *row_size, Ctl *ctl) {
     __shared__ int32_t tab[4][2 * kWave];
-    __shared__ int32_t xc[4][kWave];
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     NumOut no;
     no.bound = 0;
     win_chunks<false, HASH, IA, IB>(cls, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows, nullptr,
-                                    nullptr, nullptr, row_size, ctl, no, tab[team], xc[team], nullptr,
+                                    nullptr, nullptr, row_size, ctl, no, tab[team], nullptr, nullptr,
                                     (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
 }
 
