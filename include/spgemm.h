@@ -111,9 +111,7 @@ typedef enum {
                                     windows (the others go to the next class), and only when
                                     B has fewer than 2^26 columns (else 0 is used); 2 as 1, with
                                     symbolic counts by LDS hash instead of register merges; 0 one
-                                    row per wavefront in LDS; 4 four rows per wavefront in LDS.
-                                    The value in force at spgemm_symbolic also serves the
-                                    spgemm_numeric that follows it. */
+                                    row per wavefront in LDS; 4 four rows per wavefront in LDS */
 } spg_option;
 
 /* Allocation methods (SPG_OPT_ALLOC). */
@@ -122,6 +120,9 @@ enum {
     SPG_ALLOC_LEARNED = 1  /* predicted sizes, numeric into predicted slots, exact fallback, compaction */
 };
 
+/* Setting any option voids the plan of the last spgemm_symbolic: a
+ * spgemm_numeric after it returns SPG_ERR_STATE until spgemm_symbolic runs
+ * again.  Errors: SPG_ERR_ARG (unknown key or value out of range). */
 int spg_set_option(spg_handle h, int key, int64_t value);
 int spg_get_option(spg_handle h, int key, int64_t *value);
 

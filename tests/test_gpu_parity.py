@@ -183,3 +183,99 @@ def test_stencil27_square(handle):
     rpt, col, val = to_host(C)
     assert np.array_equal(rpt, ref.rpt) and np.array_equal(col, ref.col)
     assert np.array_equal(val, ref.val)
+
+
+def _mixed_short_rows(seed):
+    # rows of at most 64 products; some with lists too uneven for lane
+    # windows (one long list beside short ones), some with many tiny lists
+    rng = np.random.default_rng(seed)
+    K, N = 500, 3000
+    blens = np.where(rng.random(K) < 0.1, rng.integers(20, 40, K), rng.integers(0, 4, K))
+    brows = [np.sort(rng.choice(N, size=l, replace=False)) for l in blens]
+    brpt = np.zeros(K + 1, np.int64)
+    brpt[1:] = np.cumsum(blens)
+    B = synth.CSR(K, N, brpt.astype(np.int32), np.concatenate(brows).astype(np.int32),
+                  rng.uniform(-1, 1, brpt[-1]))
+    long_rows = np.flatnonzero(blens >= 20)
+    short_rows = np.flatnonzero(blens < 4)
+    rows = []
+    for i in range(400):
+        kind = i % 4
+        if kind == 0:  # one long list and a few short ones: uneven
+            r = np.concatenate([rng.choice(long_rows, 1), rng.choice(short_rows, int(rng.integers(2, 6)), replace=False)])
+        elif kind == 1:  # many tiny lists
+            r = rng.choice(short_rows, int(rng.integers(8, 30)), replace=False)
+        elif kind == 2:  # two long lists
+            r = rng.choice(long_rows, 2, replace=False)
+        else:
+            r = rng.choice(K, int(rng.integers(0, 5)), replace=False)
+        rows.append(np.unique(r))
+    rpt = np.zeros(len(rows) + 1, np.int64)
+    rpt[1:] = np.cumsum([len(r) for r in rows])
+    A = synth.CSR(len(rows), K, rpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                  rng.uniform(-1, 1, rpt[-1]))
+    return A, B
+
+
+def test_short_row_kernels_agree(handle):
+    # every kernel choice for the wave-small class gives the same bits; with
+    # lane windows the rows whose lists do not fit them move to the next class
+    A, B = _mixed_short_rows(21)
+    ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+    outs, classes = {}, {}
+    try:
+        for g in (0, 1, 2, 4):
+            print(f"case: mixed short rows, group rows {g}", flush=True)
+            handle.set_option(brm.OPT_GROUP_ROWS, g)
+            C = run(handle, A, B)
+            assert_matches_oracle(C, ref, model)
+            outs[g] = to_host(C)
+            classes[g] = handle.class_rows()
+    finally:
+        handle.set_option(brm.OPT_GROUP_ROWS, 1)
+    for g in (1, 2, 4):
+        for x, y in zip(outs[0], outs[g]):
+            assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                                  y.view(np.int64) if y.dtype == np.float64 else y)
+    assert classes[1]["wave_small"] > 0
+    assert classes[1]["wave_small"] < classes[0]["wave_small"]
+    assert classes[1]["wave"] > classes[0]["wave"]
+
+
+def test_option_change_between_passes(handle):
+    # an option set between the passes voids the symbolic plan (the kernels
+    # are tied to its classification); the numeric pass then refuses
+    A, B = _mixed_short_rows(22)
+    dA, dB = brm.DeviceCSR.from_host(A), brm.DeviceCSR.from_host(B)
+    try:
+        handle.set_option(brm.OPT_GROUP_ROWS, 0)
+        c_rpt, nnz = handle.symbolic(dA, dB)
+        handle.set_option(brm.OPT_GROUP_ROWS, 1)
+        c_col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+        c_val = torch.empty(nnz, dtype=torch.float64, device="cuda")
+        with pytest.raises(brm.SpgError) as e:
+            handle.numeric(dA, dB, c_rpt, c_col, c_val)
+        assert e.value.code == brm.SPG_ERR_STATE
+    finally:
+        handle.set_option(brm.OPT_GROUP_ROWS, 1)
+
+
+def test_wide_b_columns(handle):
+    # B with 2^26 + 5 columns (beyond the 26-bit keys of the register
+    # merges, which are then switched off).  Checked against the oracle on a
+    # monotone relabelling of B's columns to a compact range: the product
+    # commutes with it.
+    A, Bc = _mixed_short_rows(23)
+    N = (1 << 26) + 5
+    rng = np.random.default_rng(24)
+    wide = np.sort(rng.choice(N - 1, size=Bc.cols - 1, replace=False))
+    wide = np.append(wide, N - 1).astype(np.int32)  # the last column is used
+    Bw = synth.CSR(Bc.rows, N, Bc.rpt, wide[Bc.col], Bc.val)
+    ref = oracle.spgemm(A, Bc)
+    Cw = run(handle, A, Bw)
+    cls_w = handle.class_rows()
+    run(handle, A, Bc)
+    cls_c = handle.class_rows()
+    ref.col = wide[ref.col]
+    assert_matches_oracle(Cw, ref)
+    assert cls_w["wave_small"] > cls_c["wave_small"]
