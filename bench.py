@@ -24,6 +24,34 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the numeric kernel per launch, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the counter
+# reads for a 1 GiB device copy (fetch x 2.0, write x 1.0).  Valid only for
+# the kernel sources they were taken on (sha256 of the three files below);
+# reported as null otherwise.
+KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
+                  "paper_2206_06611_amd/csrc/brm_internal.h")
+TRAFFIC = {
+    "er8_2e20": {"sources_sha256": "c862901f62418798fe8405464721665a509a99cb1f5edf3021378f5175a9a5c2",
+                 "fetch_kib": 1095471.8, "write_kib": 858489.6, "fetch_scale": 2.0, "write_scale": 1.0},
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    t = TRAFFIC.get(workload)
+    if t is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return int(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
 WORKLOADS = {
     # name: (description, builder)
     "er8_2e20": "C = A*A, A Erdos-Renyi 2^20 x 2^20, 8 distinct uniform columns per row, U[-1,1], seed 2",
@@ -281,7 +309,7 @@ def main():
         "numeric_ms": round(num_ms, 4),
         "roofline": {"bound": "hbm", "kernel": "numeric pass, rows of <= 64 products (k_num_win, BRMerge in registers)",
                      "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload),
                      "algorithmic_bytes": nb},
     }
     h.close()
