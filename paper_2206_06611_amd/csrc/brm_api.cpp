@@ -88,6 +88,7 @@ struct LearnedWs {
     int32_t *pred_size; // [M]
     int64_t *slot_off;  // [M + 1]
     int32_t *ovf_rows;  // [2 M]
+    int32_t *b_ends;    // [2 K] first and last column of every row of B (-1 / -1 when empty)
 };
 
 namespace {
@@ -268,7 +269,7 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     return SPG_OK;
 }
 
-int ensure_learned_ws(spg_handle h, int64_t M, LearnedWs *lw) {
+int ensure_learned_ws(spg_handle h, int64_t M, LearnedWs *lw, int64_t K = 0) {
     const size_t a = 256;
     size_t o_feat = 0;
     size_t o_lo = align_up(o_feat + 24 * (size_t)M, a);
@@ -277,7 +278,8 @@ int ensure_learned_ws(spg_handle h, int64_t M, LearnedWs *lw) {
     size_t o_ps = align_up(o_pr + (size_t)M, a);
     size_t o_so = align_up(o_ps + 4 * (size_t)M, a);
     size_t o_ov = align_up(o_so + 8 * (size_t)(M + 1), a);
-    size_t total = align_up(o_ov + 8 * (size_t)M + 8, a);
+    size_t o_be = align_up(o_ov + 8 * (size_t)M + 8, a);
+    size_t total = align_up(o_be + 8 * (size_t)K + 8, a);
     int rc;
     if ((rc = grow(h, &h->lw_mem, &h->lw_bytes, total, "learned workspace"))) return rc;
     char *b = static_cast<char *>(h->lw_mem);
@@ -288,6 +290,7 @@ int ensure_learned_ws(spg_handle h, int64_t M, LearnedWs *lw) {
     lw->pred_size = reinterpret_cast<int32_t *>(b + o_ps);
     lw->slot_off = reinterpret_cast<int64_t *>(b + o_so);
     lw->ovf_rows = reinterpret_cast<int32_t *>(b + o_ov);
+    lw->b_ends = reinterpret_cast<int32_t *>(b + o_be);
     if (!h->ctl2) {
         HIP_TRY(h, hipMalloc(&h->ctl2, sizeof(Ctl)));
         HIP_TRY(h, hipMemset(h->ctl2, 0, sizeof(Ctl)));
@@ -578,9 +581,21 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     if (learned && !h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "learned allocation needs a trained or loaded predictor");
     h->heavy_batches = 0;
     h->pred_total = h->ovf_light = h->ovf_heavy = 0;
+    LearnedWs lw;
+    RowFeatures rf{};
+    if (learned) {
+        if ((rc = ensure_learned_ws(h, M, &lw, B->rows))) return rc;
+        HIP_TRY(h, launch_row_ends(b, lw.b_ends, s));
+        rf.b_ends = lw.b_ends;
+        rf.feats = lw.feats;
+        rf.lo = lw.lo;
+        rf.hi = lw.hi;
+        rf.predicted = lw.predicted;
+    }
     if (M > 0) {
         const int g = (int)std::min<int64_t>((M + 255) / 256, 2048);
-        HIP_TRY(h, launch_analysis(a, b, thresholds(h, uses_windows(gr)), ws, g, s));
+        // the learned allocation takes the predictor's features from the same pass
+        HIP_TRY(h, launch_analysis(a, b, thresholds(h, uses_windows(gr)), ws, g, s, learned ? &rf : nullptr));
         HIP_TRY(h, launch_bin(M, ws, g, s));
         if (!learned) {
             for (int cls = kClassWaveSmall; cls <= kClassHeavy; ++cls)
@@ -590,10 +605,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     if (learned) {
         // predicted sizes -> slots; numeric into the slots (exact lengths and
         // overflowing rows recorded); exact row pointers from the lengths
-        LearnedWs lw;
-        if ((rc = ensure_learned_ws(h, M, &lw))) return rc;
         HIP_TRY(h, launch_zero_ctl(h->ctl2, s));
-        HIP_TRY(h, launch_features(a, b, lw.feats, lw.lo, lw.hi, lw.predicted, nullptr, nullptr, s));
         HIP_TRY(h, launch_mlp_sizes(M, lw.feats, lw.predicted, lw.lo, lw.hi, ws.row_nprod, h->mlp,
                                     h->mlp + kMlpOffNorm, h->delta, (int)h->learned_force, lw.pred_size, s));
         HIP_TRY(h, launch_scan(M, lw.pred_size, ws.tile_sum, lw.slot_off, &h->ctl->pred_total, s));
@@ -677,14 +689,18 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
         LearnedWs lw;
         if ((rc = ensure_learned_ws(h, M, &lw))) return rc;
         if (h->ovf_light + h->ovf_heavy > 0) {
+            // the light rows that overflowed go, by class, to their kernels
+            // (the class lists of the symbolic pass are free by now)
             HIP_TRY(h, launch_fallback_ctl(h->ctl, h->ctl2, M, s));
             Workspace ws2 = ws;
-            ws2.class_rows = lw.ovf_rows;
             ws2.ctl = h->ctl2;
-            if (h->ovf_light > 0)
-                HIP_TRY(h, launch_numeric(a, b, ws2, kClassBlock,
-                                          persistent_grid(h, kClassBlock, h->ovf_light, h->plan_group_rows), c_rpt,
-                                          c_col, c_val, exact, s, h->plan_group_rows));
+            if (h->ovf_light > 0) {
+                HIP_TRY(h, launch_bin_list(h->ovf_light, lw.ovf_rows + (M - h->ovf_light), ws.row_class,
+                                           ws.class_rows, h->ctl2, s));
+                for (int cls = kClassCopy; cls <= kClassBlock; ++cls)
+                    HIP_TRY(h, launch_numeric(a, b, ws2, cls, persistent_grid(h, cls, h->ovf_light, h->plan_group_rows),
+                                              c_rpt, c_col, c_val, exact, s, h->plan_group_rows));
+            }
             if (h->ovf_heavy > 0 &&
                 (rc = run_heavy(h, a, b, ws, lw.ovf_rows + M, h->ovf_heavy, c_rpt, c_col, c_val, exact, h->ctl2, s)))
                 return rc;

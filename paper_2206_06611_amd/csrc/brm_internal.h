@@ -88,9 +88,21 @@ hipError_t launch_zero_ctl(Ctl *ctl, hipStream_t s);
 hipError_t launch_zero_words(unsigned long long *p, int64_t n, hipStream_t s);
 hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rpt, int64_t err_col,
                            Ctl *ctl, hipStream_t s);
+// the size predictor's inputs per row, written by the analysis when asked
+struct RowFeatures {
+    const int32_t *b_ends;  // first and last column of every row of B (launch_row_ends)
+    float *feats;       // [M * 6]
+    int32_t *lo, *hi;   // bounds of the row size
+    int8_t *predicted;  // 1: the row's size is predicted (products, two lists or more)
+};
+// ends[2k], ends[2k+1]: first and last column of B's row k (-1, -1 when empty)
+hipError_t launch_row_ends(const CsrView &B, int32_t *ends, hipStream_t s);
 hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds &th,
-                           const Workspace &ws, int grid, hipStream_t s);
+                           const Workspace &ws, int grid, hipStream_t s, const RowFeatures *rf = nullptr);
 hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s);
+// counts then bins the rows of a list by their class (ctl zeroed beforehand)
+hipError_t launch_bin_list(int64_t n, const int32_t *rows, const uint8_t *row_class, int32_t *class_rows,
+                           Ctl *ctl, hipStream_t s);
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                            int grid, hipStream_t s, int group_rows);
 hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,

@@ -200,16 +200,44 @@ hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rp
 // ---------------------------------------------------------------------------
 constexpr int kAnalysisThreads = 256;
 
-template <typename IA, typename IB>
+// first and last column of every row of B
+template <typename IB>
+__global__ __launch_bounds__(256) void k_row_ends(int64_t K, const IB *rpt, const int32_t *col, int2 *ends) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b0 = rpt[k], b1 = rpt[k + 1];
+        ends[k] = b1 > b0 ? make_int2(col[b0], col[b1 - 1]) : make_int2(-1, -1);
+    }
+}
+
+hipError_t launch_row_ends(const CsrView &B, int32_t *ends, hipStream_t s) {
+    if (B.rows == 0) return hipSuccess;
+    const int g = (int)std::min<int64_t>((B.rows + 255) / 256, 4096);
+    if (B.rpt_bytes == 4)
+        hipLaunchKernelGGL((k_row_ends<int32_t>), dim3(g), dim3(256), 0, s, B.rows,
+                           static_cast<const int32_t *>(B.rpt), B.col, reinterpret_cast<int2 *>(ends));
+    else
+        hipLaunchKernelGGL((k_row_ends<int64_t>), dim3(g), dim3(256), 0, s, B.rows,
+                           static_cast<const int64_t *>(B.rpt), B.col, reinterpret_cast<int2 *>(ends));
+    return hipGetLastError();
+}
+
+// FEAT: also the size predictor's features of every row (the learned
+// allocation), from the same pass over A's entries
+template <typename IA, typename IB, bool FEAT>
 __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
     int64_t M, const void *a_rpt, const int32_t *a_col, const void *b_rpt, Thresholds th,
-    int64_t *row_nprod, uint8_t *row_class, int32_t *row_size, Ctl *ctl, IB *ent_bs, int32_t *ent_len) {
+    int64_t *row_nprod, uint8_t *row_class, int32_t *row_size, Ctl *ctl, IB *ent_bs, int32_t *ent_len,
+    RowFeatures rf) {
     constexpr int kW = kAnalysisThreads / kWave;
     __shared__ int64_t s_count[kNumClasses];
     __shared__ int64_t s_nprod;
     __shared__ int64_t s_start[kW][kWave + 1];  // entry offset of every row of the wave's chunk
     __shared__ unsigned long long s_np[kW][kWave];
     __shared__ int32_t s_mx[kW][kWave];  // longest list of every row
+    // features only: shortest list, lowest first column, highest last column
+    __shared__ int32_t s_mn[FEAT ? kW : 1][kWave];
+    __shared__ int32_t s_first[FEAT ? kW : 1][kWave];
+    __shared__ int32_t s_last[FEAT ? kW : 1][kWave];
     if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nprod = 0;
     __syncthreads();
@@ -236,6 +264,11 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             s_start[w][lane] = a0;
             s_np[w][lane] = 0ull;
             s_mx[w][lane] = 0;
+            if constexpr (FEAT) {
+                s_mn[w][lane] = INT32_MAX;
+                s_first[w][lane] = INT32_MAX;
+                s_last[w][lane] = -1;
+            }
         }
         if (lane == nrows - 1) s_start[w][nrows] = a1;
         wave_sync();
@@ -249,6 +282,14 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
             atomicAdd(&s_np[w][r], (unsigned long long)n);
             atomicMax(&s_mx[w][r], (int32_t)n);
+            if constexpr (FEAT) {
+                atomicMin(&s_mn[w][r], (int32_t)n);
+                if (n > 0) {
+                    const int2 fl = reinterpret_cast<const int2 *>(rf.b_ends)[k];
+                    atomicMin(&s_first[w][r], fl.x);
+                    atomicMax(&s_last[w][r], fl.y);
+                }
+            }
         }
         wave_sync();
         if (in) {
@@ -258,6 +299,24 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             row_nprod[i] = np;
             const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx) : 0;
             row_class[i] = (uint8_t)(cls | (sw << kClassBits));
+            if constexpr (FEAT) {
+                // log1p of (lists, products, longest, shortest list, column span,
+                // products per spanned column); bounds of the row size
+                const int64_t L = a1 - a0;
+                const int64_t mn = L == 0 ? 0 : s_mn[w][lane];
+                const int64_t first = s_first[w][lane], last = s_last[w][lane];
+                const int64_t span = last >= first ? last - first + 1 : 0;
+                float *f = rf.feats + 6 * i;
+                f[0] = log1pf((float)L);
+                f[1] = log1pf((float)np);
+                f[2] = log1pf((float)mx);
+                f[3] = log1pf((float)mn);
+                f[4] = log1pf((float)span);
+                f[5] = log1pf(span > 0 ? (float)((double)np / (double)span) : 0.0f);
+                rf.predicted[i] = (np > 0 && L >= 2) ? 1 : 0;
+                rf.lo[i] = (int32_t)(np == 0 ? 0 : (L == 1 ? np : mx));
+                rf.hi[i] = (int32_t)(np == 0 ? 0 : (L == 1 ? np : (np < span ? np : span)));
+            }
             if (cls == kClassEmpty) row_size[i] = 0;
             if (cls == kClassCopy) row_size[i] = (int32_t)np;
 #pragma unroll
@@ -286,12 +345,20 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
 }
 
 hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds &th,
-                           const Workspace &ws, int grid, hipStream_t s) {
+                           const Workspace &ws, int grid, hipStream_t s, const RowFeatures *rf) {
     const dim3 g(grid), b(kAnalysisThreads);
-#define BRM_ANALYSIS(IA, IB)                                                                 \
-    hipLaunchKernelGGL((k_analysis<IA, IB>), g, b, 0, s, A.rows, A.rpt, A.col, B.rpt, th,   \
-                       ws.row_nprod, ws.row_class, ws.row_size, ws.ctl,                      \
-                       reinterpret_cast<IB *>(ws.ent_bs), ws.ent_len)
+    RowFeatures none{};
+#define BRM_ANALYSIS(IA, IB)                                                                         \
+    do {                                                                                             \
+        if (rf)                                                                                      \
+            hipLaunchKernelGGL((k_analysis<IA, IB, true>), g, b, 0, s, A.rows, A.rpt, A.col, B.rpt, th, \
+                               ws.row_nprod, ws.row_class, ws.row_size, ws.ctl,                      \
+                               reinterpret_cast<IB *>(ws.ent_bs), ws.ent_len, *rf);                  \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_analysis<IA, IB, false>), g, b, 0, s, A.rows, A.rpt, A.col, B.rpt,    \
+                               th, ws.row_nprod, ws.row_class, ws.row_size, ws.ctl,                  \
+                               reinterpret_cast<IB *>(ws.ent_bs), ws.ent_len, none);                 \
+    } while (0)
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_ANALYSIS(int32_t, int32_t);
     else if (A.rpt_bytes == 4) BRM_ANALYSIS(int32_t, int64_t);
     else if (B.rpt_bytes == 4) BRM_ANALYSIS(int64_t, int32_t);
@@ -309,7 +376,10 @@ __device__ __forceinline__ int64_t class_start(const Ctl *ctl, int cls) {
     return s;
 }
 
-__global__ __launch_bounds__(256) void k_bin(int64_t M, const uint8_t *row_class,
+// Counting sort of rows by class: class_rows[class_start(c) + k] is the k-th
+// row of class c.  The rows are 0 .. M-1, or rows[0 .. M-1] when a list is
+// given; ctl->count must hold the totals per class, ctl->cursor zero.
+__global__ __launch_bounds__(256) void k_bin(int64_t M, const int32_t *rows, const uint8_t *row_class,
                                              int32_t *class_rows, Ctl *ctl) {
     __shared__ int64_t s_base[kNumClasses];
     __shared__ int s_wave_cnt[kNumClasses];
@@ -320,7 +390,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const uint8_t *row_class
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += stride) {
-        const int cls = row_class[i] & kClassMask;
+        const int cls = row_class[rows ? (int64_t)rows[i] : i] & kClassMask;
 #pragma unroll
         for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
     }
@@ -346,7 +416,8 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const uint8_t *row_class
     const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
     for (int64_t base = base0; base < M; base += stride) {
         const int64_t i = base + lane;
-        const int cls = i < M ? (int)(row_class[i] & kClassMask) : -1;
+        const int64_t r = i < M ? (rows ? (int64_t)rows[i] : i) : 0;
+        const int cls = i < M ? (int)(row_class[r] & kClassMask) : -1;
 #pragma unroll
         for (int c = 0; c < kNumClasses; ++c) {
             const uint64_t m = wave_ballot(cls == c);
@@ -354,13 +425,48 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const uint8_t *row_class
             int wbase = 0;
             if (lane == __builtin_ctzll(m)) wbase = atomicAdd(&s_wave_cnt[c], __popcll(m));
             wbase = __shfl(wbase, __builtin_ctzll(m), kWave);
-            if (cls == c) class_rows[s_base[c] + wbase + lanes_below(m)] = (int32_t)i;
+            if (cls == c) class_rows[s_base[c] + wbase + lanes_below(m)] = (int32_t)r;
         }
     }
 }
 
 hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin, dim3(grid), dim3(256), 0, s, M, ws.row_class, ws.class_rows, ws.ctl);
+    hipLaunchKernelGGL(k_bin, dim3(grid), dim3(256), 0, s, M, nullptr, ws.row_class, ws.class_rows, ws.ctl);
+    return hipGetLastError();
+}
+
+// per-class counts of a row list (wavefront-aggregated atomics)
+__global__ __launch_bounds__(256) void k_count_list(int64_t n, const int32_t *rows, const uint8_t *row_class,
+                                                    Ctl *ctl) {
+    __shared__ int s_cnt[kNumClasses];
+    const int lane = lane_id();
+    if (threadIdx.x < kNumClasses) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int my[kNumClasses];
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) my[c] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int cls = (int)(row_class[rows[i]] & kClassMask);
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) my[c] += cls == c;
+    }
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) {
+        const int t = wave_sum(my[c]);
+        if (lane == 0 && t) atomicAdd(&s_cnt[c], t);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses && s_cnt[threadIdx.x])
+        atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->count[threadIdx.x]),
+                  (unsigned long long)s_cnt[threadIdx.x]);
+}
+
+hipError_t launch_bin_list(int64_t n, const int32_t *rows, const uint8_t *row_class, int32_t *class_rows,
+                           Ctl *ctl, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_count_list, dim3(grid), dim3(256), 0, s, n, rows, row_class, ctl);
+    hipLaunchKernelGGL(k_bin, dim3(grid), dim3(256), 0, s, n, rows, row_class, class_rows, ctl);
     return hipGetLastError();
 }
 
@@ -1486,6 +1592,7 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             int32_t c;
             double bv, av;
         };
+        uint64_t ovf_mask = 0;  // rows of the chunk that overflowed their slot (slot mode)
         // one pipeline step: lists of row j+2 -> lo, B entries of row j+1
         // (from li) -> go, accumulating phase and write-out of row j (gi)
         auto step = [&](int j, const ListStageRegs &li, ListStageRegs &lo, const GatherRegs &gi, GatherRegs &go) {
@@ -1518,11 +1625,18 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     c_val[cs + lane] = v;
                 }
             }
-            if (lane == 0) {
-                if constexpr (VALUES)
-                    finish_row(no, ctl, row, len, lane_value(m_cap, j), false);
-                else
-                    row_size[row] = len;
+            if constexpr (VALUES) {
+                const int cap = lane_value(m_cap, j);
+                if (no.bound) {
+                    // slot mode: exact length kept; an overflowing row is
+                    // listed for the fallback once per chunk (below)
+                    if (lane == 0) no.row_size[row] = len;
+                    if (len > cap) ovf_mask |= 1ull << j;
+                } else if (lane == 0 && len != cap) {
+                    atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+                }
+            } else {
+                if (lane == 0) row_size[row] = len;
             }
         };
         ListStageRegs la, lb;
@@ -1543,7 +1657,22 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
         }
         // the stages loaded past the chunk's end are drained here, once
         asm volatile("" ::"v"(ga.c), "v"(gb.c), "v"(la.ln), "v"(lb.ln), "v"(la.bs), "v"(lb.bs));
-        if constexpr (VALUES) asm volatile("" ::"v"(ga.bv), "v"(gb.bv), "v"(la.av), "v"(lb.av));
+        if constexpr (VALUES) {
+            asm volatile("" ::"v"(ga.bv), "v"(gb.bv), "v"(la.av), "v"(lb.av));
+            if (ovf_mask) {
+                // one reservation for the chunk's overflowing rows (light rows
+                // fill the list from its end)
+                unsigned long long at = 0;
+                if (lane == 0)
+                    at = atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->ovf_light),
+                                   (unsigned long long)__popcll(ovf_mask));
+                at = (unsigned long long)wave_uniform((int64_t)__shfl((int64_t)at, 0, kWave));
+                if ((ovf_mask >> lane) & 1) {
+                    const int rank = __popcll(ovf_mask & ((1ull << lane) - 1));
+                    no.ovf_rows[no.M - 1 - (int64_t)(at + rank)] = (int32_t)m_row;
+                }
+            }
+        }
     }
 }
 
@@ -2393,7 +2522,7 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
     do {                                                                                                        \
         hipLaunchKernelGGL((k_b_analysis<IA, IB>), dim3(ga), dim3(256), 0, s, tab, ro, np, R, th, ws.row_nprod, \
                            ws.row_class, ws.row_size, ws.ctl, bs.status);                                       \
-        hipLaunchKernelGGL(k_bin, dim3(ga), dim3(256), 0, s, R, ws.row_class, ws.class_rows, ws.ctl);          \
+        hipLaunchKernelGGL(k_bin, dim3(ga), dim3(256), 0, s, R, nullptr, ws.row_class, ws.class_rows, ws.ctl); \
         hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,  \
                            (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);             \
         hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,       \

@@ -163,25 +163,34 @@ __device__ __forceinline__ void load_mlp(MlpLds &s, const float *params, const f
     __syncthreads();
 }
 
-__device__ __forceinline__ float mlp_eval(const MlpLds &s, const float *raw) {
+// One row through the network, one thread per row.  The weights are read
+// from global memory at wavefront-uniform addresses, so they arrive through
+// scalar loads and every multiply-add takes its weight from a scalar
+// register (no LDS traffic).  The hidden layer is formed in outer-product
+// order: hidden unit k of layer 1 is computed when needed and added into
+// all 64 accumulators of layer 2, so only those 64 stay in vector registers;
+// each accumulator still sums k = 0 .. 63 in order, from its bias.  Fused
+// multiply-adds: the predictor only sizes slots, its rounding never reaches C.
+__device__ __forceinline__ float mlp_eval(const float *__restrict__ w, const float *__restrict__ norm,
+                                          const float *raw) {
     float x[kIn];
 #pragma unroll
-    for (int j = 0; j < kIn; ++j) x[j] = (raw[j] - s.mean[j]) * s.inv_std[j];
-    float h1[kH];
+    for (int j = 0; j < kIn; ++j) x[j] = (raw[j] - norm[j]) / norm[kIn + j];
+    float acc[kH];
 #pragma unroll
+    for (int j = 0; j < kH; ++j) acc[j] = w[oB2 + j];
+#pragma unroll 1
     for (int k = 0; k < kH; ++k) {
-        float a = s.w[oB1 + k];
+        float a = w[oB1 + k];
 #pragma unroll
-        for (int j = 0; j < kIn; ++j) a += x[j] * s.w[oW1 + j * kH + k];
-        h1[k] = a > 0.0f ? a : 0.0f;
-    }
-    float y = s.w[oB3];
-    for (int j = 0; j < kH; ++j) {
-        float a = s.w[oB2 + j];
+        for (int j = 0; j < kIn; ++j) a = __builtin_fmaf(x[j], w[oW1 + j * kH + k], a);
+        const float hk = a > 0.0f ? a : 0.0f;
 #pragma unroll
-        for (int k = 0; k < kH; ++k) a += h1[k] * s.w[oW2 + k * kH + j];
-        y += (a > 0.0f ? a : 0.0f) * s.w[oW3 + j];
+        for (int j = 0; j < kH; ++j) acc[j] = __builtin_fmaf(hk, w[oW2 + k * kH + j], acc[j]);
     }
+    float y = w[oB3];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) y = __builtin_fmaf(acc[j] > 0.0f ? acc[j] : 0.0f, w[oW3 + j], y);
     return y;
 }
 
@@ -190,11 +199,9 @@ __device__ __forceinline__ float mlp_eval(const MlpLds &s, const float *raw) {
 // (testing only): 1 predicts every such row at its lower bound.
 __global__ __launch_bounds__(256) void k_mlp_sizes(int64_t M, const float *feats, const int8_t *predicted,
                                                    const int32_t *lo, const int32_t *hi,
-                                                   const int64_t *row_nprod, const float *params,
-                                                   const float *norm, float delta, int force,
+                                                   const int64_t *row_nprod, const float *__restrict__ params,
+                                                   const float *__restrict__ norm, float delta, int force,
                                                    int32_t *pred_size) {
-    __shared__ MlpLds s;
-    load_mlp(s, params, norm);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t sz;
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(256) void k_mlp_sizes(int64_t M, const float *feats
         } else if (force == 1) {
             sz = lo[i];
         } else {
-            const float y = mlp_eval(s, feats + 6 * i);
+            const float y = mlp_eval(params, norm, feats + 6 * i);
             const double e = ceil((double)row_nprod[i] * exp((double)y + (double)delta));
             sz = e > (double)hi[i] ? hi[i] : (e < (double)lo[i] ? lo[i] : (int64_t)e);
         }
@@ -221,13 +228,12 @@ hipError_t launch_mlp_sizes(int64_t M, const float *feats, const int8_t *predict
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward(int64_t n, const float *feats, const float *params,
-                                                     const float *norm, float *y) {
-    __shared__ MlpLds s;
-    load_mlp(s, params, norm);
+__global__ __launch_bounds__(256) void k_mlp_forward(int64_t n, const float *feats,
+                                                     const float *__restrict__ params,
+                                                     const float *__restrict__ norm, float *y) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = mlp_eval(s, feats + 6 * i);
+        y[i] = mlp_eval(params, norm, feats + 6 * i);
 }
 
 hipError_t launch_mlp_forward(int64_t n, const float *feats, const float *params, const float *norm,
@@ -479,8 +485,7 @@ __global__ void k_fallback_ctl(const Ctl *src, Ctl *dst, int64_t M) {
         dst->count[c] = 0;
         dst->cursor[c] = 0;
     }
-    dst->count[kClassGroup] = M - src->ovf_light;  // placeholder rows, never launched
-    dst->count[kClassBlock] = src->ovf_light;
+    // the light rows' counts per class are added by the binning of their list
     dst->count[kClassHeavy] = src->ovf_heavy;
     dst->err = 0;
     dst->ovf_light = dst->ovf_heavy = 0;
