@@ -1816,18 +1816,19 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 // tile boundaries through a carried element.  The root is written straight
 // into C.
 // ---------------------------------------------------------------------------
-constexpr int kMergeTile = kHeavyThreads * 4;
-constexpr int kMaxSplits = 2048;
+// entries of each input staged per tile, and merge steps per thread
+constexpr int kMergeWin = kHeavyThreads * 2;
+constexpr int kMergeSteps = 4;
+constexpr int kWinPer = kMergeWin / kHeavyThreads;  // staged entries per thread and input
 
 struct MergeLds {
-    int32_t xc[kMergeTile];
-    double xv[kMergeTile];
-    int32_t yc[kMergeTile];
-    double yv[kMergeTile];
+    int32_t xc[kMergeWin];
+    double xv[kMergeWin];
+    int32_t yc[kMergeWin];
+    double yv[kMergeWin];
     int32_t first_c[kHeavyThreads];
     double first_v[kHeavyThreads];
     int32_t last_c[kHeavyThreads];
-    int64_t split[kMaxSplits + 1];
 };
 
 struct HeavyNode {
@@ -1854,22 +1855,6 @@ struct HeavyState {
 
 enum HeavyAction { kActNode = 0, kActMerge = 1, kActPromote = 2, kActToC = 3, kActDone = 4, kActFail = 5 };
 
-__device__ __forceinline__ int64_t mp_split_global(const int32_t *X, int64_t nx, const int32_t *Y,
-                                                   int64_t ny, int64_t d, int64_t xlo, int64_t xhi) {
-    // number of X elements among the first d of the merged order (X first on
-    // ties), searched inside [xlo, xhi] (a known bracket keeps the probes of Y
-    // at or after the split of an earlier diagonal)
-    int64_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
-    if (lo < xlo) lo = xlo;
-    if (hi > xhi) hi = xhi;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ int mp_split_lds(const int32_t *X, int nx, const int32_t *Y, int ny, int d) {
     int lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
     while (lo < hi) {
@@ -1880,161 +1865,147 @@ __device__ __forceinline__ int mp_split_lds(const int32_t *X, int nx, const int3
     return lo;
 }
 
-// Merge sorted lists X (left child) and Y (right child) into Z, adding the
-// values of equal columns (left + right).  Z may alias the region that Y
-// occupies as long as Z starts at or before X's region start and X's region
-// is at least |X| long: a tile's output never reaches the unread part of Y.
-// Writes at most zcap entries; returns the merged length (uniform).
+// Merge sorted, duplicate-free lists X (left child) and Y (right child) into
+// Z, adding the values of equal columns (left + right).  Tiles: the next
+// kMergeWin entries of X and of Y sit in LDS; when a window stops short of
+// its list's end, every later entry of that list has a larger column than its
+// last one, so all entries up to the smaller such last column are present in
+// both windows.  The tile merges exactly those (a tile ends on a column
+// boundary: the two entries of a column are never split between tiles), and
+// the next windows are loaded into registers while it merges.  Z may alias
+// the region that Y occupies as long as Z starts at or before X's region
+// start and X's region is at least |X| long: output written so far never
+// passes the first Y entry not yet consumed, and the next windows are read
+// before the tile writes.  Writes at most zcap entries; returns the merged
+// length (uniform).
 __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t *Xc,
                              const double *Xv, int64_t nx, const int32_t *Yc, const double *Yv,
                              int64_t ny, int32_t *Zc, double *Zv, int64_t zcap) {
-    const int64_t D = nx + ny;
-    const int64_t ntiles = (D + kMergeTile - 1) / kMergeTile;
-    if (tid == 0) {
-        st.has_carry = 0;
-        st.out = 0;
-    }
-    // split of the first diagonal of the current group of tiles: the outputs
-    // written so far only cover Y entries before it
-    int64_t xprev = 0, dprev = 0;
-    for (int64_t t0 = 0; t0 < ntiles; t0 += kMaxSplits) {
-        const int64_t tn = (ntiles - t0) < kMaxSplits ? (ntiles - t0) : kMaxSplits;
-        for (int64_t j = tid; j <= tn; j += kHeavyThreads) {
-            int64_t d = (t0 + j) * (int64_t)kMergeTile;
-            d = d < D ? d : D;
-            m.split[j] = mp_split_global(Xc, nx, Yc, ny, d, xprev, xprev + (d - dprev));
-        }
-        __syncthreads();
-        for (int64_t t = 0; t < tn; ++t) {
-            const int64_t d0 = (t0 + t) * (int64_t)kMergeTile;
-            const int64_t d1 = (d0 + kMergeTile) < D ? (d0 + kMergeTile) : D;
-            const int64_t x0 = m.split[t], x1 = m.split[t + 1];
-            const int64_t y0 = d0 - x0, y1 = d1 - x1;
-            const int nxs = (int)(x1 - x0), nys = (int)(y1 - y0), tl = (int)(d1 - d0);
-            for (int i = tid; i < nxs; i += kHeavyThreads) {
-                m.xc[i] = Xc[x0 + i];
-                m.xv[i] = Xv[x0 + i];
-            }
-            for (int i = tid; i < nys; i += kHeavyThreads) {
-                m.yc[i] = Yc[y0 + i];
-                m.yv[i] = Yv[y0 + i];
-            }
-            __syncthreads();
-            // four merge steps per thread
-            const int s0 = tid * 4;
-            int cnt = 0;
-            int32_t c[4];
-            double v[4];
-            if (s0 < tl) {
-                int x = mp_split_lds(m.xc, nxs, m.yc, nys, s0);
-                int y = s0 - x;
+    int32_t pxc[kWinPer], pyc[kWinPer];
+    double pxv[kWinPer], pyv[kWinPer];
+    auto win = [](int64_t n, int64_t at) -> int {
+        return (int)((n - at) < (int64_t)kMergeWin ? (n - at) : (int64_t)kMergeWin);
+    };
+    auto fetch = [&](int64_t xs, int64_t ys) {
+        const int wx = win(nx, xs), wy = win(ny, ys);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (s0 + j < tl) {
-                        if (x < nxs && (y >= nys || m.xc[x] <= m.yc[y])) {
-                            c[j] = m.xc[x];
-                            v[j] = m.xv[x];
-                            ++x;
-                        } else {
-                            c[j] = m.yc[y];
-                            v[j] = m.yv[y];
-                            ++y;
-                        }
-                        ++cnt;
-                    }
-                }
-                m.first_c[tid] = c[0];
-                m.first_v[tid] = v[0];
-                m.last_c[tid] = c[cnt - 1];
+        for (int e = 0; e < kWinPer; ++e) {
+            const int i = tid + e * kHeavyThreads;
+            if (i < wx) {
+                pxc[e] = Xc[xs + i];
+                pxv[e] = Xv[xs + i];
             }
-            const int nthr = (tl + 3) / 4;
-            const bool last_tile = (t0 + t) == ntiles - 1;
-            const int has_carry = st.has_carry;
-            const int64_t carry_c = st.carry_c;
-            const double carry_v = st.carry_v;
-            __syncthreads();
-            // heads and their values
-            int32_t oc[5];
-            double ov[5];
-            int items = 0;
-            int new_carry = 0;
-            int32_t ncc = 0;
-            double ncv = 0.0;
-            if (tid == 0 && has_carry) {
-                if (tl > 0 && (int64_t)c[0] == carry_c) {
-                    oc[0] = (int32_t)carry_c;
-                    ov[0] = carry_v + v[0];
-                } else {
-                    oc[0] = (int32_t)carry_c;
-                    ov[0] = carry_v;
-                }
-                items = 1;
+            if (i < wy) {
+                pyc[e] = Yc[ys + i];
+                pyv[e] = Yv[ys + i];
             }
-            for (int j = 0; j < cnt; ++j) {
-                const int g = s0 + j;
-                bool head;
-                if (g == 0) head = !(has_carry && (int64_t)c[0] == carry_c);
-                else head = c[j] != (j > 0 ? c[j - 1] : m.last_c[tid - 1]);
-                if (!head) continue;
-                bool has_next;
-                int32_t nc = 0;
-                double nv = 0.0;
-                if (j + 1 < cnt) {
-                    has_next = true;
-                    nc = c[j + 1];
-                    nv = v[j + 1];
-                } else if (tid + 1 < nthr) {
-                    has_next = true;
-                    nc = m.first_c[tid + 1];
-                    nv = m.first_v[tid + 1];
-                } else {
-                    has_next = false;
-                }
-                if (has_next && nc == c[j]) {
-                    oc[items] = c[j];
-                    ov[items] = v[j] + nv;
-                    ++items;
-                } else if (!has_next && !last_tile) {
-                    // last element of the tile: its partner may open the next tile
-                    new_carry = 1;
-                    ncc = c[j];
-                    ncv = v[j];
-                } else {
-                    oc[items] = c[j];
-                    ov[items] = v[j];
-                    ++items;
-                }
-            }
-            int tot;
-            const int rank = Team<kHeavyThreads>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
-            const int64_t base = st.out;
-            for (int j = 0; j < items; ++j) {
-                const int64_t o = base + rank + j;
-                if (o < zcap) {
-                    Zc[o] = oc[j];
-                    Zv[o] = ov[j];
-                }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                st.out = base + tot;
-                st.has_carry = 0;
-            }
-            __syncthreads();
-            if (new_carry) {
-                st.has_carry = 1;
-                st.carry_c = ncc;
-                st.carry_v = ncv;
-            }
-            __syncthreads();
         }
-        xprev = m.split[tn];
-        dprev = (t0 + tn) * (int64_t)kMergeTile < D ? (t0 + tn) * (int64_t)kMergeTile : D;
+    };
+    auto stage = [&](int64_t xs, int64_t ys) {
+        const int wx = win(nx, xs), wy = win(ny, ys);
+#pragma unroll
+        for (int e = 0; e < kWinPer; ++e) {
+            const int i = tid + e * kHeavyThreads;
+            if (i < wx) {
+                m.xc[i] = pxc[e];
+                m.xv[i] = pxv[e];
+            }
+            if (i < wy) {
+                m.yc[i] = pyc[e];
+                m.yv[i] = pyv[e];
+            }
+        }
+    };
+    int64_t x0 = 0, y0 = 0, out = 0;  // uniform
+    fetch(0, 0);
+    stage(0, 0);
+    __syncthreads();
+    while (x0 < nx || y0 < ny) {
+        const int wx = win(nx, x0), wy = win(ny, y0);
+        // the tile: every entry of both windows up to the column `lim`
+        int cx = wx, cy = wy;
+        {
+            const bool tx = x0 + wx < nx, ty = y0 + wy < ny;
+            if (tx || ty) {
+                int32_t lim = INT32_MAX;
+                if (tx) lim = m.xc[wx - 1];
+                if (ty && m.yc[wy - 1] < lim) lim = m.yc[wy - 1];
+                cx = upper_bound(m.xc, wx, lim);
+                cy = upper_bound(m.yc, wy, lim);
+            }
+        }
+        const int64_t nx0 = x0 + cx, ny0 = y0 + cy;
+        fetch(nx0, ny0);
+        // kMergeSteps merge steps per thread
+        const int D = cx + cy;
+        const int s0 = tid * kMergeSteps;
+        int cnt = 0;
+        int32_t c[kMergeSteps];
+        double v[kMergeSteps];
+        if (s0 < D) {
+            int x = mp_split_lds(m.xc, cx, m.yc, cy, s0);
+            int y = s0 - x;
+#pragma unroll
+            for (int j = 0; j < kMergeSteps; ++j) {
+                if (s0 + j < D) {
+                    if (x < cx && (y >= cy || m.xc[x] <= m.yc[y])) {
+                        c[j] = m.xc[x];
+                        v[j] = m.xv[x];
+                        ++x;
+                    } else {
+                        c[j] = m.yc[y];
+                        v[j] = m.yv[y];
+                        ++y;
+                    }
+                    ++cnt;
+                }
+            }
+            m.first_c[tid] = c[0];
+            m.first_v[tid] = v[0];
+            m.last_c[tid] = c[cnt - 1];
+        }
+        const int nthr = (D + kMergeSteps - 1) / kMergeSteps;
+        __syncthreads();
+        // heads (first entry of a column) and their values: the two entries
+        // of a column are adjacent, the left one first
+        int items = 0;
+        for (int j = 0; j < cnt; ++j) {
+            const bool head = j > 0 ? c[j] != c[j - 1] : (tid == 0 || c[0] != m.last_c[tid - 1]);
+            if (!head) continue;
+            bool has_next = false;
+            int32_t nc = 0;
+            double nv = 0.0;
+            if (j + 1 < cnt) {
+                has_next = true;
+                nc = c[j + 1];
+                nv = v[j + 1];
+            } else if (tid + 1 < nthr) {
+                has_next = true;
+                nc = m.first_c[tid + 1];
+                nv = m.first_v[tid + 1];
+            }
+            c[items] = c[j];
+            v[items] = (has_next && nc == c[j]) ? v[j] + nv : v[j];  // left + right
+            ++items;
+        }
+        int tot;
+        const int rank = Team<kHeavyThreads>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
+        for (int j = 0; j < items; ++j) {
+            const int64_t o = out + rank + j;
+            if (o < zcap) {
+                Zc[o] = c[j];
+                Zv[o] = v[j];
+            }
+        }
+        out += tot;
+        x0 = nx0;
+        y0 = ny0;
+        // every thread is done with the windows and the boundary arrays
+        __syncthreads();
+        stage(x0, y0);
         __syncthreads();
     }
-    const int64_t n = st.out;
-    __syncthreads();
-    return n;
+    return out;
 }
 
 struct HeavyBatch {
