@@ -911,7 +911,25 @@ struct NumLds {
     int32_t seg_len[G];    // merged length of every segment
     int64_t row[G];
     Seg seg[G];
+    // merge-path rounds with one position per thread: every thread's first
+    // entry and last column (with more positions per thread they sit in the
+    // round's destination buffers, free at that point)
+    int32_t bnd_c[kE == 1 ? T : 1];
+    double bnd_v[kE == 1 ? T : 1];
+    int32_t bnd_last[kE == 1 ? T : 1];
 };
+
+// Merge path: how many entries of X are among the first d entries of the
+// merge of sorted X and Y (X first on equal columns).
+__device__ __forceinline__ int mp_split_lds(const int32_t *X, int nx, const int32_t *Y, int ny, int d) {
+    int lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 
 // Exclusive count of `flag` over the positions p = tid + e*T in increasing p.
 // Writes the count before every position p < n into x[p] and the total into x[n].
@@ -1195,7 +1213,23 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP, G> &s, int tid, 
     for (int l = tid; l < L; l += T) s.len[l] = s.off[l + 1] - s.off[l];
     Team<T>::sync();
 
-    // accumulating phase: round sh merges the nodes of level sh pairwise
+    // accumulating phase: round sh merges the nodes of level sh pairwise.
+    // Thread tid owns the E consecutive positions tid*E .. tid*E+E-1 of the
+    // merge-path order of whichever sibling pair covers them (a pair's merged
+    // sequence, duplicates included, starts at its left node's offset); one
+    // merge-path search per pair a thread meets, then sequential steps.
+    int leafc[E];
+    {
+        const int p0 = tid * E;
+        int lf = p0 < nprod ? upper_bound(s.off, L + 1, p0) - 1 : 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = p0 + e;
+            if (p < nprod)
+                while (s.off[lf + 1] <= p) ++lf;  // lists may be empty: skip leaves that end before p
+            leafc[e] = lf;
+        }
+    }
     int cur = 0;
     for (int sh = 0; (1 << sh) < L; ++sh) {
         const int nxt = cur ^ 1;
@@ -1205,70 +1239,107 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP, G> &s, int tid, 
         double *dv = s.val[nxt];
         int32_t c[E];
         double v[E];
-        int k[E], i[E], st[E], sst[E], ln[E], sln[E], node[E];
-        bool valid[E], dup[E], sib[E];
+        int base[E], span[E], d[E];
+        bool valid[E], left[E], dup[E];
+        {
+            int run_pfl = -1, x = 0, y = 0, rb = 0, lnL = 0, lnR = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int p = tid + e * T;
-            valid[e] = false;
-            dup[e] = false;
-            sib[e] = false;
-            k[e] = 0;
-            c[e] = 0;
-            v[e] = 0.0;
-            node[e] = leaf[e] >> sh;
-            const int fl = node[e] << sh;
-            st[e] = s.off[fl];
-            ln[e] = s.len[fl];
-            i[e] = p - st[e];
-            sst[e] = 0;
-            sln[e] = 0;
-            if (p < nprod && i[e] < ln[e]) {
-                valid[e] = true;
-                c[e] = sc[p];
-                v[e] = sv[p];
-                const int sfl = (node[e] ^ 1) << sh;
-                if (sfl < L) {
-                    sib[e] = true;
-                    sst[e] = s.off[sfl];
-                    sln[e] = s.len[sfl];
-                    if ((node[e] & 1) == 0) {
-                        k[e] = lower_bound(sc + sst[e], sln[e], c[e]);
-                        if (k[e] < sln[e] && sc[sst[e] + k[e]] == c[e]) v[e] = v[e] + sv[sst[e] + k[e]];
-                    } else {
-                        k[e] = upper_bound(sc + sst[e], sln[e], c[e]);
-                        dup[e] = k[e] > 0 && sc[sst[e] + k[e] - 1] == c[e];
+            for (int e = 0; e < E; ++e) {
+                const int p = tid * E + e;
+                const int pfl = (leafc[e] >> (sh + 1)) << (sh + 1);
+                valid[e] = false;
+                left[e] = true;
+                c[e] = 0;
+                v[e] = 0.0;
+                base[e] = 0;
+                span[e] = 0;
+                d[e] = 0;
+                if (p < nprod) {
+                    if (pfl != run_pfl) {
+                        // a new pair: its merged sequence and this position's split
+                        run_pfl = pfl;
+                        const int sfl = pfl + (1 << sh);
+                        lnL = s.len[pfl];
+                        lnR = sfl < L ? s.len[sfl] : 0;
+                        rb = sfl < L ? s.off[sfl] : 0;
+                        const int dd = p - s.off[pfl];
+                        if (dd < lnL + lnR) {
+                            x = mp_split_lds(sc + s.off[pfl], lnL, sc + rb, lnR, dd);
+                            y = dd - x;
+                        }
+                    }
+                    base[e] = s.off[pfl];
+                    span[e] = lnL + lnR;
+                    d[e] = p - base[e];
+                    if (d[e] < span[e]) {
+                        valid[e] = true;
+                        if (x < lnL && (y >= lnR || sc[base[e] + x] <= sc[rb + y])) {
+                            c[e] = sc[base[e] + x];
+                            v[e] = sv[base[e] + x];
+                            ++x;
+                        } else {
+                            c[e] = sc[rb + y];
+                            v[e] = sv[rb + y];
+                            left[e] = false;
+                            ++y;
+                        }
                     }
                 }
             }
         }
-        // dup counts over positions, kept in the destination column buffer
-        team_flag_scan<T, CAP, G>(s, tid, dup, nprod, dc);
+        // neighbours across threads: the merged entries just before and
+        // after this thread's positions
+        int32_t *bnd_c = E == 1 ? s.bnd_c : dc;
+        int32_t *bnd_last = E == 1 ? s.bnd_last : dc + T;
+        double *bnd_v = E == 1 ? s.bnd_v : dv;
+        bnd_c[tid] = c[0];
+        bnd_v[tid] = v[0];
+        bnd_last[tid] = c[E - 1];
         Team<T>::sync();
-        int dest[E], newlen[E], newlen_at[E];
+        int ndup = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            dup[e] = false;
+            if (!valid[e]) continue;
+            // a right entry equal to the entry before it: the pair's column
+            // already held by the left list (inputs have no repeats)
+            if (!left[e] && d[e] > 0) {
+                const int32_t pc = e > 0 ? c[e - 1] : bnd_last[tid - 1];
+                dup[e] = pc == c[e];
+            }
+            // a left entry whose next entry repeats its column takes left + right
+            if (left[e] && d[e] + 1 < span[e]) {
+                const int32_t nc = e + 1 < E ? c[e + 1] : bnd_c[tid + 1];
+                const double nv = e + 1 < E ? v[e + 1] : bnd_v[tid + 1];
+                if (nc == c[e]) v[e] = v[e] + nv;
+            }
+            ndup += dup[e];
+        }
+        // exclusive count of duplicates over positions, kept in the
+        // destination column buffer (and its total at nprod); the scan's
+        // barriers come after every read of the neighbours above
+        int tot;
+        const int before = Team<T>::excl_scan(ndup, &tot, s.scan, tid);
+        {
+            int run = before;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int p = tid * E + e;
+                if (p < nprod) dc[p] = run;
+                run += dup[e];
+            }
+            if (tid == 0) dc[nprod] = tot;
+        }
+        Team<T>::sync();
+        // (a thread may hold the first position of several pairs)
+        int dest[E], newlen[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             dest[e] = -1;
             newlen[e] = -1;
-            newlen_at[e] = 0;
-            if (valid[e] && !dup[e]) {
-                int pos;
-                if (!sib[e]) {
-                    pos = i[e];
-                } else if ((node[e] & 1) == 0) {
-                    pos = i[e] + k[e] - (dc[sst[e] + k[e]] - dc[sst[e]]);
-                } else {
-                    const int p = tid + e * T;
-                    pos = i[e] + k[e] - (dc[p] - dc[st[e]]);
-                }
-                const int pfl = (node[e] >> 1) << (sh + 1);
-                dest[e] = s.off[pfl] + pos;
-            }
-            if (valid[e] && sib[e] && (node[e] & 1) && i[e] == 0) {
-                // first element of a right list: the parent's length
-                newlen[e] = sln[e] + ln[e] - (dc[st[e] + ln[e]] - dc[st[e]]);
-                newlen_at[e] = (node[e] ^ 1) << sh;
-            }
+            if (valid[e] && !dup[e]) dest[e] = base[e] + d[e] - (dc[tid * E + e] - dc[base[e]]);
+            // the pair's first position: the parent's length
+            if (valid[e] && d[e] == 0) newlen[e] = span[e] - (dc[base[e] + span[e]] - dc[base[e]]);
         }
         Team<T>::sync();
 #pragma unroll
@@ -1277,7 +1348,7 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP, G> &s, int tid, 
                 dc[dest[e]] = c[e];
                 dv[dest[e]] = v[e];
             }
-            if (newlen[e] >= 0) s.len[newlen_at[e]] = newlen[e];
+            if (newlen[e] >= 0) s.len[(leafc[e] >> (sh + 1)) << (sh + 1)] = newlen[e];
         }
         Team<T>::sync();
         cur = nxt;
@@ -1854,16 +1925,6 @@ struct HeavyState {
 };
 
 enum HeavyAction { kActNode = 0, kActMerge = 1, kActPromote = 2, kActToC = 3, kActDone = 4, kActFail = 5 };
-
-__device__ __forceinline__ int mp_split_lds(const int32_t *X, int nx, const int32_t *Y, int ny, int d) {
-    int lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
 
 // Merge sorted, duplicate-free lists X (left child) and Y (right child) into
 // Z, adding the values of equal columns (left + right).  Tiles: the next
