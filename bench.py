@@ -32,9 +32,14 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "c862901f62418798fe8405464721665a509a99cb1f5edf3021378f5175a9a5c2",
-                 "fetch_kib": 1095471.8, "write_kib": 858489.6, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "69e35e39b712e8b653724997058c992ea454d8eeb6714297468136e379aa1416",
+                 "fetch_kib": 1095450.5, "write_kib": 858760.7, "fetch_scale": 2.0, "write_scale": 1.0},
 }
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sources_sha256():
@@ -170,10 +175,118 @@ def batched_extra(reps=10):
             "autotune": tune}
 
 
-def learned_extra(reps=5, eval_workloads=("stencil27_128", "er8_2e20")):
+def laplace_throughput_extra(count=512, reps=20):
+    """The 64 x 64 Laplacian squared: one product as measured (launch- and
+    latency-bound: about 3.3 MB of traffic), and a throughput mode with
+    `count` independent copies in one batched call (one graph replay)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2206_06611_amd as brm
+
+    A = synth.laplacian_2d_5pt(64)
+    h = brm.Handle(0)
+    d1 = brm.DeviceCSR.from_host(A)
+    t_one, C1 = time_plain(h, d1, d1, reps, warmup=3)
+    nprod, nnz = h.stat(brm.STAT_NPROD), C1.nnz
+    per = (numeric_bytes(A.rows, A.nnz, nprod, nnz) + symbolic_bytes(A.rows, A.nnz, nprod)
+           + analysis_bytes(A.rows, A.nnz) + scan_bytes(A.rows))
+    copies = [brm.DeviceCSR.from_host(A) for _ in range(count)]
+    problems = [(d, d) for d in copies]
+    arena = torch.empty(1 << 20, dtype=torch.uint8, device=d1.rpt.device)
+    for _ in range(3):  # the first call reports the size the arena needs
+        rc, req, outs = h.batched(problems, arena)
+        if rc == brm.SPG_OK:
+            break
+        arena = torch.empty(req, dtype=torch.uint8, device=d1.rpt.device)
+    if rc != brm.SPG_OK:
+        raise RuntimeError(f"batched call failed with status {rc}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rc, req, outs = h.batched(problems, arena)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) * 1e3 / reps
+    same = all(torch.equal(o.col, C1.col) and torch.equal(o.val.view(torch.int64), C1.val.view(torch.int64))
+               for o in outs)
+    h.close()
+    return {"workload": "C = A*A, 64 x 64 5-point Laplacian (4096 rows, 20,224 nnz)",
+            "single_ms": round(t_one, 4), "single_gflops": round(2 * nprod / (t_one / 1e3) / 1e9, 3),
+            "single_effective_gbs": round(per / (t_one / 1e3) / 1e9, 2),
+            "algorithmic_bytes_per_product": per,
+            "throughput_mode": {"instances": count, "ms": round(t_b, 4),
+                                "gflops": round(2 * nprod * count / (t_b / 1e3) / 1e9, 3),
+                                "effective_gbs": round(per * count / (t_b / 1e3) / 1e9, 2),
+                                "frac_of_peak": round(per * count / (t_b / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                                "bitwise_equal_to_single": bool(same)}}
+
+
+def learned_rmat21(h, reps=1):
+    """Plain against learned and upper-bound allocation on R-MAT scale 21
+    (held-out seed 5), in row blocks of at most 2^32 products (C is larger
+    than device memory)."""
+    import torch
+    import synth
+    import paper_2206_06611_amd as brm
+
+    A = synth.rmat(21, 16, 5)
+    dA = brm.DeviceCSR.from_host(A)
+    blocks = h.row_blocks(dA, dA, 1 << 32)
+    tot = {"plain_ms": 0.0, "learned_ms": 0.0, "predicted_rows": 0, "fallback_rows": 0, "nnz": 0, "nprod": 0,
+           "slots": 0}
+    same = same_u = True
+    tot["upper_ms"] = 0.0
+    per_block = []
+    for b, e in blocks:
+        progress(f"R-MAT 21 rows [{b}, {e})")
+        dAb = dA.row_block(b, e)
+        h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+        t_plain, Cp = time_plain(h, dAb, dA, reps)
+        nprod = h.stat(brm.STAT_NPROD)
+        h.set_option(brm.OPT_ALLOC, brm.ALLOC_LEARNED)
+        t_learn, Cl = time_plain(h, dAb, dA, reps)
+        ovf, pred = h.stat(brm.STAT_OVERFLOW_ROWS), h.stat(brm.STAT_PREDICTED_ROWS)
+        tot["slots"] += h.stat(brm.STAT_PRED_TOTAL)
+        same = same and torch.equal(Cp.col, Cl.col) and torch.equal(Cp.val.view(torch.int64),
+                                                                    Cl.val.view(torch.int64))
+        del Cl
+        h.set_option(brm.OPT_ALLOC, brm.ALLOC_UPPER)
+        t_upper, Cu = time_plain(h, dAb, dA, reps)
+        same_u = same_u and torch.equal(Cp.col, Cu.col) and torch.equal(Cp.val.view(torch.int64),
+                                                                        Cu.val.view(torch.int64))
+        del Cu
+        tot["upper_ms"] += t_upper
+        tot["plain_ms"] += t_plain
+        tot["learned_ms"] += t_learn
+        tot["predicted_rows"] += pred
+        tot["fallback_rows"] += ovf
+        tot["nnz"] += Cp.nnz
+        tot["nprod"] += nprod
+        per_block.append({"rows": [b, e], "plain_ms": round(t_plain, 3), "learned_ms": round(t_learn, 3),
+                          "upper_bound_ms": round(t_upper, 3), "fallback_rows": ovf})
+        del Cp
+        torch.cuda.empty_cache()
+    h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+    return {"row_blocks": len(blocks), "max_products_per_block": 1 << 32, "nprod": tot["nprod"], "nnz": tot["nnz"],
+            "plain_ms": round(tot["plain_ms"], 3), "learned_ms": round(tot["learned_ms"], 3),
+            "speedup_vs_plain": round(tot["plain_ms"] / tot["learned_ms"], 3),
+            "plain_gflops": round(2 * tot["nprod"] / (tot["plain_ms"] / 1e3) / 1e9, 3),
+            "predicted_rows": tot["predicted_rows"], "fallback_rows": tot["fallback_rows"],
+            "misprediction_rate": round(tot["fallback_rows"] / max(tot["predicted_rows"], 1), 6),
+            "slot_entries_over_nnz": round(tot["slots"] / tot["nnz"], 4),
+            "slot_entries_over_nprod": round(tot["slots"] / tot["nprod"], 4),
+            "bitwise_equal_to_plain": bool(same),
+            "upper_bound_ms": round(tot["upper_ms"], 3),
+            "upper_bound_speedup_vs_plain": round(tot["plain_ms"] / tot["upper_ms"], 3),
+            "upper_bound_bitwise_equal_to_plain": bool(same_u), "blocks": per_block}
+
+
+def learned_extra(reps=5, eval_workloads=("stencil27_128", "er8_2e20"), rmat21=True):
     """Size predictor trained on the symbolic counts of the 64^2 Laplacian,
     ER-8 2^20 (seed 2) and R-MAT scale 20 (seed 3), evaluated against the
-    plain two-pass method on held-out inputs."""
+    plain two-pass method and the upper-bound allocation on held-out
+    inputs: the 128^3 27-point stencil,
+    ER-8 2^20, and R-MAT scale 21 (seed 5) in row blocks."""
     import numpy as np
     import torch
     import synth
@@ -201,6 +314,7 @@ def learned_extra(reps=5, eval_workloads=("stencil27_128", "er8_2e20")):
                         "loss_after": round(loss1, 5), "delta": round(delta, 5), "seconds": round(train_s, 3)},
            "eval": {}}
     for name in eval_workloads:
+        progress(f"learned allocation on {name}")
         A = build_input(name)
         dA = brm.DeviceCSR.from_host(A)
         h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
@@ -213,16 +327,26 @@ def learned_extra(reps=5, eval_workloads=("stencil27_128", "er8_2e20")):
         ovf = h.stat(brm.STAT_OVERFLOW_ROWS)
         slots = h.stat(brm.STAT_PRED_TOTAL)
         same = torch.equal(Cp.col, Cl.col) and torch.equal(Cp.val.view(torch.int64), Cl.val.view(torch.int64))
+        del Cl
+        h.set_option(brm.OPT_ALLOC, brm.ALLOC_UPPER)
+        t_upper, Cu = time_plain(h, dA, dA, reps)
+        same_u = torch.equal(Cp.col, Cu.col) and torch.equal(Cp.val.view(torch.int64), Cu.val.view(torch.int64))
+        del Cu
         out["eval"][name] = {"plain_ms": round(t_plain, 4), "learned_ms": round(t_learn, 4),
                              "speedup_vs_plain": round(t_plain / t_learn, 3),
+                             "upper_bound_ms": round(t_upper, 4),
+                             "upper_bound_speedup_vs_plain": round(t_plain / t_upper, 3),
+                             "upper_bound_bitwise_equal_to_plain": bool(same_u),
                              "predicted_rows": pred_rows, "fallback_rows": ovf,
                              "misprediction_rate": round(ovf / pred_rows, 6) if pred_rows else 0.0,
                              "slot_entries_over_nnz": round(slots / nnz, 4) if nnz else None,
                              "slot_entries_over_nprod": round(slots / nprod, 4) if nprod else None,
                              "bitwise_equal_to_plain": bool(same)}
         h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
-        del dA, Cp, Cl
+        del dA, Cp
         torch.cuda.empty_cache()
+    if rmat21:
+        out["eval"]["rmat_s21"] = learned_rmat21(h)
     h.close()
     return out
 
@@ -323,12 +447,19 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 8
         del src, dst
+    progress(f"main workload done: {ms_step:.4f} ms per step")
     if not args.no_extras:
+        out["laplace2d_64"] = laplace_throughput_extra()
+        progress("64 x 64 Laplacian done")
+        torch.cuda.empty_cache()
         out["batched"] = batched_extra()
+        progress("batched Galerkin products done")
         torch.cuda.empty_cache()
         out["learned"] = learned_extra()
+        progress("learned allocation done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, nprod)
+        progress("CPU oracle baseline done")
     print(json.dumps(out), flush=True)
 
 

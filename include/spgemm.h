@@ -39,6 +39,12 @@
  *    the last error are available from spg_last_error().  No C++ exception
  *    crosses this interface.
  *  - A handle is not thread-safe: use one handle per host thread / stream.
+ *  - Column-wise products (CSC in, CSC out; the column-wise dataflow of
+ *    Eq. (3)): the CSC arrays of a matrix X are the CSR arrays of X^T, so
+ *    C = A*B in CSC is the row-wise product C^T = B^T A^T: pass B's CSC
+ *    arrays as A (rows = B's columns) and A's as B; c_rpt / c_col / c_val
+ *    are then C's column pointers, row indices and values.  The leaves of
+ *    column j's merge tree are the stored entries of column j of B.
  */
 #ifndef SPGEMM_H_
 #define SPGEMM_H_
@@ -102,7 +108,7 @@ typedef enum {
     SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
                                     per batch of heavy rows (default 16384) */
     SPG_OPT_GRID_WAVES = 9,      /* waves per launch of the persistent row kernels (0 = auto) */
-    SPG_OPT_ALLOC = 10,          /* SPG_ALLOC_PRECISE (default) or SPG_ALLOC_LEARNED */
+    SPG_OPT_ALLOC = 10,          /* SPG_ALLOC_PRECISE (default), SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER */
     SPG_OPT_LEARNED_FORCE = 11,  /* testing only: 1 sizes every predicted row at its lower bound
                                     (the longest list), so that most rows take the fallback */
     SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
@@ -117,7 +123,13 @@ typedef enum {
 /* Allocation methods (SPG_OPT_ALLOC). */
 enum {
     SPG_ALLOC_PRECISE = 0, /* symbolic count, prefix sum, numeric straight into C */
-    SPG_ALLOC_LEARNED = 1  /* predicted sizes, numeric into predicted slots, exact fallback, compaction */
+    SPG_ALLOC_LEARNED = 1, /* predicted sizes, numeric into predicted slots, exact fallback, compaction */
+    SPG_ALLOC_UPPER = 2    /* the upper-bound method (Section II-B.1, the "BRMerge-Upper" library of
+                              Section III-D.1): every row gets a slot of nprod_i entries, the numeric
+                              pass runs into the slots inside spgemm_symbolic (no symbolic count), and
+                              spgemm_numeric copies the rows into C.  The slots take 12 bytes per
+                              product of device memory (SPG_ERR_NOMEM when they do not fit: cut A
+                              into row blocks with spgemm_row_products) */
 };
 
 /* Setting any option voids the plan of the last spgemm_symbolic: a
@@ -133,7 +145,7 @@ typedef enum {
     SPG_STAT_CLASS_ROWS0 = 10,   /* rows per class: +0 empty, +1 copy, +2 wave-small,
                                     +3 wave, +4 group, +5 block, +6 heavy */
     SPG_STAT_HEAVY_BATCHES = 20, /* spill batches the heavy path used in the last numeric call */
-    SPG_STAT_PRED_TOTAL = 21,    /* learned allocation: sum of the predicted row sizes (slot entries) */
+    SPG_STAT_PRED_TOTAL = 21,    /* learned / upper-bound allocation: sum of the slot sizes (entries) */
     SPG_STAT_OVERFLOW_ROWS = 22, /* learned allocation: rows longer than their predicted slot */
     SPG_STAT_PREDICTED_ROWS = 23,/* rows whose size is predicted (two or more lists, a product) */
     SPG_STAT_GRAPH_CAPTURES = 24,/* batched calls that (re)captured their HIP graph */
@@ -153,8 +165,11 @@ int spg_get_stat(spg_handle h, int key, int64_t *value);
  *   c_nnz  : host int64, written with nnz(C).
  * This call BLOCKS until c_nnz is known (one device-to-host copy).  The row
  * analysis it makes is kept in the handle for the next spgemm_numeric call
- * with the same A and B.
+ * with the same A and B.  With SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER
+ * (spg_option) it computes the rows into slots in handle memory instead and
+ * derives c_rpt from their exact lengths; the same contract holds.
  * Errors: SPG_ERR_ARG, SPG_ERR_DIM, SPG_ERR_INVALID_CSR (validation on),
+ * SPG_ERR_NOT_TRAINED (learned allocation without a predictor),
  * SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c_rpt,
                     int64_t *c_nnz, void *stream);
@@ -169,6 +184,18 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
  * Errors: SPG_ERR_ARG, SPG_ERR_STATE, SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64_t *c_rpt,
                    int32_t *c_col, double *c_val, void *stream);
+
+/* Row analysis (step 1 of both libraries of Section III-D): the number of
+ * products of every row of C, nprod_i = sum over the stored A_ik of the
+ * length of row k of B; an upper bound of the row's size.  A caller that
+ * must cut a product into row blocks (C larger than device memory) plans
+ * the blocks with it.
+ *   A, B      : device CSR inputs (values not read).
+ *   row_nprod : device int64[A->rows], written.
+ * Asynchronous on `stream`.  Voids the plan of the last spgemm_symbolic (the
+ * analysis shares its workspace).
+ * Errors: SPG_ERR_ARG, SPG_ERR_DIM, SPG_ERR_NOMEM, SPG_ERR_HIP. */
+int spgemm_row_products(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *row_nprod, void *stream);
 
 /* ---- Batched products ----------------------------------------------------
  * Many independent products C_p = A_p * B_p in one call, for instance the

@@ -44,6 +44,7 @@ OPT_LEARNED_FORCE = 11
 OPT_GROUP_ROWS = 12
 ALLOC_PRECISE = 0
 ALLOC_LEARNED = 1
+ALLOC_UPPER = 2
 MLP_NUM_PARAMS = 4673
 
 # statistics
@@ -103,6 +104,7 @@ def _load_library():
         "spg_get_stat": ([P, I32, ctypes.POINTER(I64)], I32),
         "spgemm_symbolic": ([P, PCSR, PCSR, P, ctypes.POINTER(I64), P], I32),
         "spgemm_numeric": ([P, PCSR, PCSR, P, P, P, P], I32),
+        "spgemm_row_products": ([P, PCSR, PCSR, P, P], I32),
         "spg_last_error": ([P], ctypes.c_char_p),
         "spg_mlp_set_params": ([P, P, P, ctypes.c_float], I32),
         "spg_mlp_get_params": ([P, P, P, P], I32),
@@ -131,7 +133,7 @@ EXPORTED = ("spg_create", "spg_destroy", "spg_set_option", "spg_get_option", "sp
             "spgemm_symbolic", "spgemm_numeric", "spg_last_error", "spg_mlp_set_params",
             "spg_mlp_get_params", "spg_mlp_features", "spg_mlp_forward", "spg_mlp_gradient",
             "spg_mlp_fit_normalization", "spg_mlp_train", "spg_mlp_loss", "spg_mlp_calibrate",
-            "spg_mlp_save", "spg_mlp_load", "spgemm_batched")
+            "spg_mlp_save", "spg_mlp_load", "spgemm_batched", "spgemm_row_products")
 
 
 def library():
@@ -162,6 +164,16 @@ class DeviceCSR:
                    torch.as_tensor(A.col, dtype=torch.int32).to(device),
                    torch.as_tensor(A.val, dtype=torch.float64).to(device))
 
+    def row_block(self, begin: int, end: int) -> "DeviceCSR":
+        """Rows [begin, end) as a CSR of their own: the column and value
+        arrays are views into this matrix, the row pointers are rebased to
+        start at zero (a new array of end - begin + 1 entries)."""
+        if not 0 <= begin <= end <= self.rows:
+            raise ValueError(f"row block [{begin}, {end}) outside 0..{self.rows}")
+        rpt = self.rpt[begin:end + 1]
+        lo, hi = (int(x) for x in rpt[[0, -1]].tolist())
+        return DeviceCSR(end - begin, self.cols, (rpt - lo).contiguous(), self.col[lo:hi], self.val[lo:hi])
+
     def _struct(self) -> _Csr:
         if self.rpt.dtype not in (torch.int32, torch.int64):
             raise TypeError("rpt must be int32 or int64")
@@ -174,6 +186,55 @@ class DeviceCSR:
                     4 if self.rpt.dtype == torch.int32 else 8,
                     self.col.data_ptr() if self.nnz else None,
                     self.val.data_ptr() if self.nnz else None)
+
+
+@dataclass
+class DeviceCSC:
+    """A CSC matrix whose arrays are device tensors: cpt[cols + 1] column
+    pointers, row indices strictly increasing within each column."""
+
+    rows: int
+    cols: int
+    cpt: torch.Tensor  # int32 or int64, cols + 1
+    row: torch.Tensor  # int32
+    val: torch.Tensor  # float64
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row.numel())
+
+    def transposed_csr(self) -> DeviceCSR:
+        """The same arrays read as the CSR of the transpose (no copy)."""
+        return DeviceCSR(self.cols, self.rows, self.cpt, self.row, self.val)
+
+    @classmethod
+    def from_host_csr(cls, A, device="cuda") -> "DeviceCSC":
+        """CSC of a host CSR matrix (transposed on the host, then copied)."""
+        import numpy as np
+        order = np.lexsort((np.repeat(np.arange(A.rows), np.diff(np.asarray(A.rpt, np.int64))),
+                            np.asarray(A.col)))
+        counts = np.bincount(np.asarray(A.col), minlength=A.cols)
+        cpt = np.zeros(A.cols + 1, np.int64)
+        cpt[1:] = np.cumsum(counts)
+        rows = np.repeat(np.arange(A.rows, dtype=np.int32), np.diff(np.asarray(A.rpt, np.int64)))[order]
+        return cls(int(A.rows), int(A.cols), torch.as_tensor(cpt.astype(np.int32 if cpt[-1] < 2**31 else np.int64),
+                                                                device=device),
+                   torch.as_tensor(rows, device=device), torch.as_tensor(np.asarray(A.val)[order], device=device))
+
+
+def cut_row_blocks(row_nprod, max_products: int):
+    """Greedy cut of consecutive rows into blocks whose product counts sum to
+    at most `max_products` (a row with more is a block of its own)."""
+    import numpy as np
+    n = len(row_nprod)
+    csum = np.concatenate([[0], np.cumsum(np.asarray(row_nprod, np.int64))])
+    blocks, r = [], 0
+    while r < n:
+        e = int(np.searchsorted(csum, csum[r] + max_products, side="right")) - 1
+        e = min(max(e, r + 1), n)
+        blocks.append((r, e))
+        r = e
+    return blocks
 
 
 def _stream_ptr(stream):
@@ -241,6 +302,29 @@ class Handle:
                                         ctypes.c_void_p(c_col.data_ptr() if c_col.numel() else None),
                                         ctypes.c_void_p(c_val.data_ptr() if c_val.numel() else None),
                                         _stream_ptr(stream)))
+
+    def row_products(self, A: DeviceCSR, B: DeviceCSR, stream=None) -> torch.Tensor:
+        """Products of every row of A*B (int64 device tensor of A.rows)."""
+        out = torch.empty(max(A.rows, 1), dtype=torch.int64, device=A.rpt.device)
+        sa, sb = A._struct(), B._struct()
+        self._check(_lib.spgemm_row_products(self._h, ctypes.byref(sa), ctypes.byref(sb),
+                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out[:A.rows]
+
+    def row_blocks(self, A: DeviceCSR, B: DeviceCSR, max_products: int, stream=None):
+        """Cuts A's rows into consecutive blocks of at most `max_products`
+        products each (a row with more forms a block of its own); the
+        products bound each block's C.  Returns [(begin, end), ...]."""
+        if A.rows == 0:
+            return []
+        return cut_row_blocks(self.row_products(A, B, stream).cpu().numpy(), max_products)
+
+    def spgemm_row_blocks(self, A: DeviceCSR, B: DeviceCSR, max_products: int, stream=None):
+        """C = A*B one row block at a time, for products whose C does not fit
+        in device memory at once: yields (begin, end, C_block) with C_block
+        the rows [begin, end) of C (each a complete product of its own)."""
+        for b, e in self.row_blocks(A, B, max_products, stream):
+            yield b, e, self.spgemm(A.row_block(b, e), B, stream)
 
     # ---- learned size predictor --------------------------------------------
     def mlp_set_params(self, params, norm, delta: float = 0.0):
@@ -379,6 +463,17 @@ class Handle:
                 raise SpgError(rc, _lib.spg_last_error(self._h).decode())
             arena = torch.empty(req, dtype=torch.uint8, device=arena.device)
         raise SpgError(SPG_ERR_CAPACITY, "arena sizing failed")
+
+    def spgemm_csc(self, A: DeviceCSC, B: DeviceCSC, stream=None) -> DeviceCSC:
+        """C = A*B with A, B and C in CSC: the column-wise dataflow (column j
+        of C merges the columns of A selected by column j of B, Eq. (3)),
+        which is the row-wise product of the transposes, C^T = B^T A^T, on
+        the same arrays.  The merge tree's leaves are the stored entries of
+        column j of B in stored order."""
+        if A.cols != B.rows:
+            raise SpgError(SPG_ERR_DIM, f"A is {A.rows} x {A.cols} but B has {B.rows} rows")
+        Ct = self.spgemm(B.transposed_csr(), A.transposed_csr(), stream)
+        return DeviceCSC(A.rows, B.cols, Ct.rpt, Ct.col, Ct.val)
 
     def spgemm(self, A: DeviceCSR, B: DeviceCSR, stream=None) -> DeviceCSR:
         """C = A*B: symbolic pass, allocation of C, numeric pass."""

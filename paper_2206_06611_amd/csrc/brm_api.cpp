@@ -51,7 +51,7 @@ struct spg_handle_s {
     int64_t nnz = 0, nprod = 0;
     int64_t heavy_batches = 0;
     // learned allocation
-    int64_t alloc = 0;          // 0 precise, 1 learned
+    int64_t alloc = 0;          // 0 precise, 1 learned, 2 upper bound
     int64_t learned_force = 0;  // testing: 1 = every predicted row at its lower bound
     bool plan_learned = false;
     void *lw_mem = nullptr;     // per-row learned workspace
@@ -474,8 +474,8 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             h->group_rows = value;
             break;
         case SPG_OPT_ALLOC:
-            if (value != SPG_ALLOC_PRECISE && value != SPG_ALLOC_LEARNED)
-                return fail(h, SPG_ERR_ARG, "allocation must be SPG_ALLOC_PRECISE or SPG_ALLOC_LEARNED");
+            if (value != SPG_ALLOC_PRECISE && value != SPG_ALLOC_LEARNED && value != SPG_ALLOC_UPPER)
+                return fail(h, SPG_ERR_ARG, "allocation must be SPG_ALLOC_PRECISE, SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER");
             h->alloc = value;
             break;
         case SPG_OPT_LEARNED_FORCE:
@@ -571,6 +571,9 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
                         (unsigned long long)h->ctl_host->err);
     }
     const bool learned = h->alloc == SPG_ALLOC_LEARNED;
+    // learned and upper-bound allocation both compute the rows into slots
+    // during this call and compact them in spgemm_numeric
+    const bool slotted = learned || h->alloc == SPG_ALLOC_UPPER;
     // the short-row kernels are fixed with the classification: the numeric
     // pass uses what this call chose
     int gr = (int)h->group_rows;
@@ -583,8 +586,8 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     h->pred_total = h->ovf_light = h->ovf_heavy = 0;
     LearnedWs lw;
     RowFeatures rf{};
+    if (slotted && (rc = ensure_learned_ws(h, M, &lw, learned ? B->rows : 0))) return rc;
     if (learned) {
-        if ((rc = ensure_learned_ws(h, M, &lw, B->rows))) return rc;
         HIP_TRY(h, launch_row_ends(b, lw.b_ends, s));
         rf.b_ends = lw.b_ends;
         rf.feats = lw.feats;
@@ -597,17 +600,21 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         // the learned allocation takes the predictor's features from the same pass
         HIP_TRY(h, launch_analysis(a, b, thresholds(h, uses_windows(gr)), ws, g, s, learned ? &rf : nullptr));
         HIP_TRY(h, launch_bin(M, ws, g, s));
-        if (!learned) {
+        if (!slotted) {
             for (int cls = kClassWaveSmall; cls <= kClassHeavy; ++cls)
                 HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1, gr), s, gr));
         }
     }
-    if (learned) {
-        // predicted sizes -> slots; numeric into the slots (exact lengths and
-        // overflowing rows recorded); exact row pointers from the lengths
+    if (slotted) {
+        // predicted sizes (or the product counts, an upper bound) -> slots;
+        // numeric into the slots (exact lengths and overflowing rows
+        // recorded); exact row pointers from the lengths
         HIP_TRY(h, launch_zero_ctl(h->ctl2, s));
-        HIP_TRY(h, launch_mlp_sizes(M, lw.feats, lw.predicted, lw.lo, lw.hi, ws.row_nprod, h->mlp,
-                                    h->mlp + kMlpOffNorm, h->delta, (int)h->learned_force, lw.pred_size, s));
+        if (learned)
+            HIP_TRY(h, launch_mlp_sizes(M, lw.feats, lw.predicted, lw.lo, lw.hi, ws.row_nprod, h->mlp,
+                                        h->mlp + kMlpOffNorm, h->delta, (int)h->learned_force, lw.pred_size, s));
+        else
+            HIP_TRY(h, launch_upper_sizes(M, ws.row_nprod, lw.pred_size, s));
         HIP_TRY(h, launch_scan(M, lw.pred_size, ws.tile_sum, lw.slot_off, &h->ctl->pred_total, s));
         HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
@@ -647,7 +654,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     h->ovf_heavy = c.ovf_heavy;
     *c_nnz = c.nnz;
     h->plan_valid = true;
-    h->plan_learned = learned;
+    h->plan_learned = slotted;
     h->pa_rpt = A->rpt;
     h->pb_rpt = B->rpt;
     h->pa_col = A->col;
@@ -657,6 +664,31 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     h->pN = B->cols;
     h->pnnzA = A->nnz;
     h->pnnzB = B->nnz;
+    return SPG_OK;
+}
+
+int spgemm_row_products(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *row_nprod, void *stream) {
+    if (!h) return SPG_ERR_ARG;
+    h->err.clear();
+    int rc;
+    if ((rc = check_csr(h, A, "A", false)) || (rc = check_csr(h, B, "B", false))) return rc;
+    if (A->rows > 0 && !row_nprod) return fail(h, SPG_ERR_ARG, "row_nprod is NULL");
+    if (A->cols != B->rows)
+        return fail(h, SPG_ERR_DIM, "A is %lld x %lld but B has %lld rows", (long long)A->rows,
+                    (long long)A->cols, (long long)B->rows);
+    if (A->rows > INT32_MAX) return fail(h, SPG_ERR_ARG, "A has more than 2^31-1 rows");
+    HIP_TRY(h, hipSetDevice(h->device));
+    // the analysis reuses the workspace of the last plan
+    h->plan_valid = false;
+    const int64_t M = A->rows;
+    if (M == 0) return SPG_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace ws;
+    if ((rc = ensure_workspace(h, M, A->nnz, &ws))) return rc;
+    HIP_TRY(h, launch_zero_ctl(h->ctl, s));
+    const int g = (int)std::min<int64_t>((M + 255) / 256, 2048);
+    HIP_TRY(h, launch_analysis(view(A), view(B), thresholds(h, false), ws, g, s));
+    HIP_TRY(h, hipMemcpyAsync(row_nprod, ws.row_nprod, sizeof(int64_t) * (size_t)M, hipMemcpyDeviceToDevice, s));
     return SPG_OK;
 }
 

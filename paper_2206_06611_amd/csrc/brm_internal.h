@@ -100,6 +100,8 @@ hipError_t launch_row_ends(const CsrView &B, int32_t *ends, hipStream_t s);
 hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds &th,
                            const Workspace &ws, int grid, hipStream_t s, const RowFeatures *rf = nullptr);
 hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s);
+// slot sizes of the upper-bound allocation: the product count of every row
+hipError_t launch_upper_sizes(int64_t M, const int64_t *row_nprod, int32_t *size, hipStream_t s);
 // counts then bins the rows of a list by their class (ctl zeroed beforehand)
 hipError_t launch_bin_list(int64_t n, const int32_t *rows, const uint8_t *row_class, int32_t *class_rows,
                            Ctl *ctl, hipStream_t s);

@@ -435,6 +435,20 @@ hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+// the upper bound of Section II-B.1: a row of C has at most as many entries
+// as it has products
+__global__ __launch_bounds__(256) void k_upper_sizes(int64_t M, const int64_t *row_nprod, int32_t *size) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
+        size[i] = (int32_t)row_nprod[i];
+}
+
+hipError_t launch_upper_sizes(int64_t M, const int64_t *row_nprod, int32_t *size, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    const unsigned g = (unsigned)((M + 255) / 256 < 4096 ? (M + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_upper_sizes, dim3(g), dim3(256), 0, s, M, row_nprod, size);
+    return hipGetLastError();
+}
+
 // per-class counts of a row list (wavefront-aggregated atomics)
 __global__ __launch_bounds__(256) void k_count_list(int64_t n, const int32_t *rows, const uint8_t *row_class,
                                                     Ctl *ctl) {

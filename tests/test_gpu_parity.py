@@ -279,3 +279,52 @@ def test_wide_b_columns(handle):
     ref.col = wide[ref.col]
     assert_matches_oracle(Cw, ref)
     assert cls_w["wave_small"] > cls_c["wave_small"]
+
+
+def test_row_blocks_match_whole_product(handle):
+    print("case: R-MAT scale 12 in row blocks of at most 20000 products", flush=True)
+    A = synth.rmat(12, 16, 44)
+    dA = brm.DeviceCSR.from_host(A)
+    nprod = handle.row_products(dA, dA).cpu().numpy()
+    assert np.array_equal(nprod, oracle.row_nprod(A, A))
+    whole = to_host(handle.spgemm(dA, dA))
+    blocks = handle.row_blocks(dA, dA, 20000)
+    assert len(blocks) > 10
+    parts = []
+    for b, e in blocks:
+        assert nprod[b:e].sum() <= 20000 or e == b + 1
+        parts.append(to_host(handle.spgemm(dA.row_block(b, e), dA)))
+    rpt = np.concatenate([[0]] + [p[0][1:] + off for p, off in
+                                  zip(parts, np.cumsum([0] + [p[0][-1] for p in parts[:-1]]))])
+    assert np.array_equal(rpt, whole[0])
+    assert np.array_equal(np.concatenate([p[1] for p in parts]), whole[1])
+    assert np.array_equal(np.concatenate([p[2] for p in parts]).view(np.int64), whole[2].view(np.int64))
+    # empty and single-row blocks
+    C0 = handle.spgemm(dA.row_block(7, 7), dA)
+    assert C0.rows == 0 and C0.nnz == 0
+    C1 = to_host(handle.spgemm(dA.row_block(0, 1), dA))
+    assert np.array_equal(C1[1], whole[1][:whole[0][1]])
+
+
+def test_column_wise_dual(handle):
+    # CSC in, CSC out: column j of C = A*B merges the columns of A selected
+    # by column j of B; the same arrays are the row-wise product B^T A^T
+    print("case: column-wise product of CSC inputs", flush=True)
+    A = synth.random_csr(150, 90, 0.05, 81, empty_row_frac=0.1)
+    B = synth.random_csr(90, 200, 0.06, 82, empty_row_frac=0.1)
+    dA, dB = brm.DeviceCSC.from_host_csr(A), brm.DeviceCSC.from_host_csr(B)
+    assert np.array_equal(dA.row.cpu().numpy(), synth.csr_transpose(A).col)
+    C = handle.spgemm_csc(dA, dB)
+    torch.cuda.synchronize()
+    assert (C.rows, C.cols) == (150, 200)
+    Bt, At = synth.csr_transpose(B), synth.csr_transpose(A)
+    assert_matches_oracle(C.transposed_csr(), oracle.spgemm(Bt, At), oracle.brmerge(Bt, At))
+    # read back as CSR, C is the definition of A*B
+    ct = C.transposed_csr()
+    Ct = synth.CSR(ct.rows, ct.cols, ct.rpt.cpu().numpy(), ct.col.cpu().numpy(), ct.val.cpu().numpy())
+    Cr = synth.csr_transpose(Ct)
+    ref = oracle.spgemm(A, B)
+    assert np.array_equal(np.asarray(Cr.rpt, np.int64), ref.rpt) and np.array_equal(Cr.col, ref.col)
+    assert np.all(np.abs(Cr.val - ref.val) <= 1e-12 * ref.absval)
+    with pytest.raises(brm.SpgError):
+        handle.spgemm_csc(dA, dA)
