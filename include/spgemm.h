@@ -100,10 +100,11 @@ typedef enum {
     SPG_OPT_GROUP_MAX = 4,       /* largest row routed to a 256-thread workgroup (<= 1024) */
     SPG_OPT_BLOCK_MAX = 5,       /* largest row kept in one workgroup's LDS (<= 4096); larger
                                     rows take the heavy path with HBM spill */
-    SPG_OPT_FORCE_CLASS = 6,     /* -1: normal binning.  2..5: every non-empty row (single-list
+    SPG_OPT_FORCE_CLASS = 6,     /* -1: normal binning.  2..5, 7: every non-empty row (single-list
                                     rows included) that fits that class (2 wave-small, 3 wave,
-                                    4 group, 5 block) is routed there, every other row to the
-                                    heavy path; 6: every non-empty row to the heavy path */
+                                    4 group, 5 block, 7 multi-register windows) is routed there,
+                                    every other row to the heavy path; 6: every non-empty row to
+                                    the heavy path */
     SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (<= 4096) */
     SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
                                     per batch of heavy rows (default 16384) */
@@ -117,7 +118,10 @@ typedef enum {
                                     windows (the others go to the next class), and only when
                                     B has fewer than 2^26 columns (else 0 is used); 2 as 1, with
                                     symbolic counts by LDS hash instead of register merges; 0 one
-                                    row per wavefront in LDS; 4 four rows per wavefront in LDS */
+                                    row per wavefront in LDS; 4 four rows per wavefront in LDS.
+                                    With 1 and 2, rows of at most 64 lists whose lists fit lane
+                                    windows of 2 to 16 registers per lane take the multi-register
+                                    class (7) when B has at most 2^21 columns */
 } spg_option;
 
 /* Allocation methods (SPG_OPT_ALLOC). */
@@ -143,7 +147,9 @@ typedef enum {
     SPG_STAT_NPROD = 1,          /* total products of the last symbolic call */
     SPG_STAT_NNZ = 2,            /* nnz(C) of the last symbolic call */
     SPG_STAT_CLASS_ROWS0 = 10,   /* rows per class: +0 empty, +1 copy, +2 wave-small,
-                                    +3 wave, +4 group, +5 block, +6 heavy */
+                                    +3 wave, +4 group, +5 block, +6 heavy, +7 multi-register
+                                    windows (one wavefront per row, at most 64 lists padded to
+                                    128..1024 slots, B with at most 2^21 columns) */
     SPG_STAT_HEAVY_BATCHES = 20, /* spill batches the heavy path used in the last numeric call */
     SPG_STAT_PRED_TOTAL = 21,    /* learned / upper-bound allocation: sum of the slot sizes (entries) */
     SPG_STAT_OVERFLOW_ROWS = 22, /* learned allocation: rows longer than their predicted slot */

@@ -59,7 +59,7 @@ STAT_GRAPH_CAPTURES = 24
 STAT_GRAPH_LAUNCHES = 25
 STAT_DEVICE_ERR = 30
 
-CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy"]
+CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy", "multi"]
 
 
 class SpgError(RuntimeError):

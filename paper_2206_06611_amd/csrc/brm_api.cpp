@@ -333,7 +333,7 @@ int ensure_mlp_act(spg_handle h, int64_t rows) {
 
 // windows: the wave-small class is served by the register-window kernels,
 // which take only rows whose lists fit lane windows
-Thresholds thresholds(spg_handle h, bool windows) {
+Thresholds thresholds(spg_handle h, bool windows, bool multi = false) {
     Thresholds t;
     t.wave_small_max = h->wave_small_max;
     t.wave_max = h->wave_max;
@@ -341,6 +341,7 @@ Thresholds thresholds(spg_handle h, bool windows) {
     t.block_max = h->block_max;
     t.force = (int32_t)h->force;
     t.windows = windows ? 1 : 0;
+    t.multi = windows && multi ? 1 : 0;
     return t;
 }
 
@@ -356,6 +357,7 @@ int persistent_grid(spg_handle h, int cls, int64_t rows, int group_rows) {
             per_cu = 8;
             teams_per_wg = uses_windows(group_rows) ? 4 * 64 : 4 * (group_rows > 1 ? group_rows : 1);  // chunks of 64 rows
             break;
+        case kClassMulti: per_cu = 5; teams_per_wg = 4 * 64; break;  // chunks of 64 rows
         case kClassWave: per_cu = 4; teams_per_wg = 4; break;
         case kClassGroup: per_cu = 4; teams_per_wg = 1; break;
         case kClassBlock: per_cu = 1; teams_per_wg = 1; break;
@@ -452,8 +454,8 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             h->block_max = value;
             break;
         case SPG_OPT_FORCE_CLASS:
-            if (value != -1 && (value < kClassWaveSmall || value > kClassHeavy))
-                return fail(h, SPG_ERR_ARG, "force class must be -1 or 2..6");
+            if (value != -1 && (value < kClassWaveSmall || value > kClassMulti))
+                return fail(h, SPG_ERR_ARG, "force class must be -1 or 2..7");
             h->force = value;
             break;
         case SPG_OPT_HEAVY_LDS_MAX:
@@ -524,7 +526,7 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_OVERFLOW_ROWS: *value = h->ovf_light + h->ovf_heavy; return SPG_OK;
         case SPG_STAT_PREDICTED_ROWS: {
             int64_t n = 0;
-            for (int c = kClassWaveSmall; c <= kClassHeavy; ++c) n += h->counts[c];
+            for (int c = kClassWaveSmall; c < kNumClasses; ++c) n += h->counts[c];
             *value = n;
             return SPG_OK;
         }
@@ -598,10 +600,13 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     if (M > 0) {
         const int g = (int)std::min<int64_t>((M + 255) / 256, 2048);
         // the learned allocation takes the predictor's features from the same pass
-        HIP_TRY(h, launch_analysis(a, b, thresholds(h, uses_windows(gr)), ws, g, s, learned ? &rf : nullptr));
+        // multi-register windows key columns in 21 bits
+        const Thresholds th = thresholds(h, uses_windows(gr), B->cols <= ((int64_t)1 << 21));
+        HIP_TRY(h, launch_analysis(a, b, th, ws, g, s, learned ? &rf : nullptr));
         HIP_TRY(h, launch_bin(M, ws, g, s));
         if (!slotted) {
-            for (int cls = kClassWaveSmall; cls <= kClassHeavy; ++cls)
+            for (int cls : {(int)kClassWaveSmall, (int)kClassMulti, (int)kClassWave, (int)kClassGroup,
+                            (int)kClassBlock, (int)kClassHeavy})
                 HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1, gr), s, gr));
         }
     }
@@ -630,7 +635,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         no.row_size = ws.row_size;
         no.ovf_rows = lw.ovf_rows;
         no.M = M;
-        for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
+        for (int cls : kLightClasses) {
             if (h->counts[cls] == 0) continue;
             HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls], gr), lw.slot_off, s_col,
                                       s_val, no, s, gr));
@@ -729,7 +734,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
             if (h->ovf_light > 0) {
                 HIP_TRY(h, launch_bin_list(h->ovf_light, lw.ovf_rows + (M - h->ovf_light), ws.row_class,
                                            ws.class_rows, h->ctl2, s));
-                for (int cls = kClassCopy; cls <= kClassBlock; ++cls)
+                for (int cls : kLightClasses)
                     HIP_TRY(h, launch_numeric(a, b, ws2, cls, persistent_grid(h, cls, h->ovf_light, h->plan_group_rows),
                                               c_rpt, c_col, c_val, exact, s, h->plan_group_rows));
             }
@@ -745,7 +750,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
                                   (int)std::min<int64_t>((M + 3) / 4, (int64_t)h->num_cu * 8), s));
         return SPG_OK;
     }
-    for (int cls = kClassCopy; cls <= kClassBlock; ++cls) {
+    for (int cls : kLightClasses) {
         if (h->counts[cls] == 0) continue;
         HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls], h->plan_group_rows), c_rpt,
                                   c_col, c_val, exact, s, h->plan_group_rows));

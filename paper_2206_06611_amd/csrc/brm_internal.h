@@ -18,8 +18,13 @@ enum RowClass : int {
     kClassGroup = 4,   // 256-thread workgroup, LDS buffer
     kClassBlock = 5,   // 1024-thread workgroup, LDS buffer
     kClassHeavy = 6,   // beyond one workgroup's LDS: HBM spill
-    kNumClasses = 7
+    kClassMulti = 7,   // one wavefront, lane windows of 2 to 16 registers per lane
+    kNumClasses = 8
 };
+
+// The classes whose rows one kernel launch per class merges in LDS or in
+// registers (every class but empty, heavy), in launch order.
+constexpr int kLightClasses[] = {kClassCopy, kClassWaveSmall, kClassMulti, kClassWave, kClassGroup, kClassBlock};
 
 // Compile-time capacities (products per row) of the LDS classes.
 constexpr int kCapWaveSmall = 64;
@@ -35,10 +40,11 @@ struct Thresholds {
     int64_t block_max;
     int32_t force;  // -1: none
     int32_t windows;  // 1: the wave-small class holds only rows whose lists fit lane windows
+    int32_t multi;    // 1: rows whose lists fit windows of 2 to 16 registers per lane take kClassMulti
 };
 
-// row_class byte: the class in the low bits; for wave-small rows under
-// lane windows, log2 of the window width above them
+// row_class byte: the class in the low bits; for rows under lane windows
+// (wave-small, multi), log2 of the window width above them
 constexpr int kClassBits = 3;
 constexpr uint8_t kClassMask = (1u << kClassBits) - 1;
 

@@ -54,6 +54,19 @@ __device__ __forceinline__ int window_shift(int64_t nlists, int64_t maxlen) {
     return sw + sl <= 6 ? sw : -1;
 }
 
+// Lane windows of 2 to 16 registers per lane (kClassMulti): at most 64
+// lists, padded total between 128 and 1024 slots, and at most 8 slots per
+// product (more padding than that is cheaper in the LDS classes).  Returns
+// log2 of the window width, or -1 when the row does not fit.
+constexpr int kMwSlots = 1024;
+__device__ __forceinline__ int multi_shift(int64_t nlists, int64_t maxlen, int64_t nprod) {
+    if (nlists > kWave || maxlen > kMwSlots) return -1;
+    const int sw = ceil_log2(maxlen > 0 ? maxlen : 1);
+    const int t = sw + ceil_log2(nlists > 0 ? nlists : 1);
+    if (t <= 6 || t > 10 || ((int64_t)1 << t) > 8 * nprod) return -1;
+    return sw;
+}
+
 __device__ __forceinline__ int classify(int64_t nlists, int64_t nprod, int64_t maxlen, const Thresholds &th) {
     if (nprod == 0) return kClassEmpty;
     const int64_t w = nprod > nlists ? nprod : nlists;  // LDS holds both products and lists
@@ -68,10 +81,12 @@ __device__ __forceinline__ int classify(int64_t nlists, int64_t nprod, int64_t m
                             : th.force == kClassBlock   ? kCapBlock
                                                         : 0;
         if (th.force == kClassWaveSmall && !small_ok) return kClassHeavy;
+        if (th.force == kClassMulti) return th.multi && multi_shift(nlists, maxlen, nprod) >= 0 ? kClassMulti : kClassHeavy;
         return w <= cap ? th.force : kClassHeavy;
     }
     if (nlists == 1) return kClassCopy;
     if (w <= th.wave_small_max && small_ok) return kClassWaveSmall;
+    if (th.multi && multi_shift(nlists, maxlen, nprod) >= 0) return kClassMulti;
     if (w <= th.wave_max) return kClassWave;
     if (w <= th.group_max) return kClassGroup;
     if (w <= th.block_max) return kClassBlock;
@@ -297,7 +312,9 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             const int mx = s_mx[w][lane];
             const int cls = classify(a1 - a0, np, mx, th);
             row_nprod[i] = np;
-            const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx) : 0;
+            const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx)
+                           : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, np)
+                                                                  : 0;
             row_class[i] = (uint8_t)(cls | (sw << kClassBits));
             if constexpr (FEAT) {
                 // log1p of (lists, products, longest, shortest list, column span,
@@ -690,6 +707,11 @@ template <bool HASH, typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lists<IB> lists,
                                                  const int32_t *b_col, const uint8_t *row_class,
                                                  const int32_t *class_rows, int32_t *row_size, Ctl *ctl);
+// counting of rows under multi-register windows (defined with the numeric kernels)
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_sym_mw(int cls, const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
+                                                const uint8_t *row_class, const int32_t *class_rows,
+                                                int32_t *row_size, Ctl *ctl);
 
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                            int grid, hipStream_t s, int group_rows) {
@@ -740,6 +762,16 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
                 BRM_SYM((k_sym_group<64, 4, kGroupRows, 2 * kCapWaveSmall, int64_t, int32_t>), 256, int64_t, int32_t);
             else
                 BRM_SYM((k_sym_group<64, 4, kGroupRows, 2 * kCapWaveSmall, int64_t, int64_t>), 256, int64_t, int64_t);
+            break;
+        case kClassMulti:
+#define BRM_SYM_MW(IA, IB)                                                                                   \
+    hipLaunchKernelGGL((k_sym_mw<IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), \
+                       B.col, ws.row_class, ws.class_rows, ws.row_size, ws.ctl)
+            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_SYM_MW(int32_t, int32_t);
+            else if (A.rpt_bytes == 4) BRM_SYM_MW(int32_t, int64_t);
+            else if (B.rpt_bytes == 4) BRM_SYM_MW(int64_t, int32_t);
+            else BRM_SYM_MW(int64_t, int64_t);
+#undef BRM_SYM_MW
             break;
         case kClassWave: BRM_SYM_ALL(64, 4, 2 * kCapWave); break;
         case kClassGroup: BRM_SYM_ALL(256, 1, 2 * kCapGroup); break;
@@ -1788,6 +1820,319 @@ __global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lis
                                     (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
 }
 
+// ---------------------------------------------------------------------------
+// Rows whose lists fit lane windows of NR = 2..16 registers per lane
+// (kClassMulti, see multi_shift): the register merge above with NR keys per
+// lane.  Element x of the row's window lives in lane x / NR, register
+// x % NR, so list p occupies elements [p W0, (p+1) W0), and since there are
+// at most 64 lists, W0 >= NR: the NR elements of a lane are consecutive
+// entries of one list.  A merge stage at distance d >= NR exchanges between
+// lanes (lane xor d / NR), one at d < NR between two registers of a lane.
+//
+// The key is the column above kMwShift = 11 bits.  Its low 10 bits name the
+// LDS slot of the entry's value (register e of lane l stores at e * 64 + l,
+// so that the multiplying phase writes without bank conflicts); bit 10 marks
+// an entry that was added into its neighbour.  A dropped entry has all 11
+// low bits set: the dropped entries of a column are equal keys behind its
+// live one, so every window stays sorted without compaction.  After each
+// round, of two live entries with equal columns (one from each list of a
+// pair, next to each other) the first takes the sum and the second is
+// dropped.  Columns must be below 2^21 (a dropped entry of column 2^21 - 1
+// then equals the empty key; neither is live).
+// ---------------------------------------------------------------------------
+constexpr int kMwShift = 11;
+constexpr uint32_t kMwDrop = 1u << 10;
+constexpr uint32_t kMwLow = (1u << kMwShift) - 1;
+constexpr uint32_t kMwSlotMask = kMwDrop - 1;
+constexpr uint32_t kMwEmpty = ~0u;
+
+// compare-exchange of every register with the same register of lane ^ LD
+template <int NR, int LD>
+__device__ __forceinline__ void mw_cmpx_lanes(uint32_t (&k)[NR], int lane) {
+    const bool lower = (lane & LD) == 0;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        const uint32_t p = xor_lane<LD>(k[e], lane);
+        const uint32_t lo = p < k[e] ? p : k[e], hi = p < k[e] ? k[e] : p;
+        k[e] = lower ? lo : hi;
+    }
+}
+
+// half-cleaners at element distances D, D/2, ..., 1
+template <int NR, int D>
+__device__ __forceinline__ void mw_half_cleaners(uint32_t (&k)[NR], int lane) {
+    if constexpr (D >= 1) {
+        if constexpr (D >= NR) {
+            mw_cmpx_lanes<NR, D / NR>(k, lane);
+        } else {
+#pragma unroll
+            for (int e = 0; e < NR; ++e) {
+                if ((e & D) == 0) {
+                    const uint32_t a = k[e], b = k[e + D];
+                    k[e] = a < b ? a : b;
+                    k[e + D] = a < b ? b : a;
+                }
+            }
+        }
+        mw_half_cleaners<NR, D / 2>(k, lane);
+    }
+}
+
+// bitonic merge of every pair of sorted windows of width W: the mirror
+// stage (element x against x ^ (2W - 1)), then the half-cleaners
+template <int NR, int W>
+__device__ __forceinline__ void mw_merge(uint32_t (&k)[NR], int lane) {
+    if constexpr (2 * W <= NR) {
+#pragma unroll
+        for (int e = 0; e < NR; ++e) {
+            if ((e & W) == 0) {
+                const int f = e ^ (2 * W - 1);
+                const uint32_t a = k[e], b = k[f];
+                k[e] = a < b ? a : b;
+                k[f] = a < b ? b : a;
+            }
+        }
+    } else {
+        // the mirror of lane l, register e is lane l ^ (2W/NR - 1), register NR-1-e
+        const bool lower = (lane & (W / NR)) == 0;
+        uint32_t p[NR];
+#pragma unroll
+        for (int e = 0; e < NR; ++e) p[e] = xor_lane<2 * W / NR - 1>(k[NR - 1 - e], lane);
+#pragma unroll
+        for (int e = 0; e < NR; ++e) {
+            const uint32_t lo = p[e] < k[e] ? p[e] : k[e], hi = p[e] < k[e] ? k[e] : p[e];
+            k[e] = lower ? lo : hi;
+        }
+    }
+    mw_half_cleaners<NR, W / 2>(k, lane);
+}
+
+template <int NR>
+__device__ __forceinline__ void mw_merge_w(uint32_t (&k)[NR], int lane, int W) {
+#define BRM_MW_CASE(X)                                     \
+    case X:                                                \
+        if constexpr (X <= 32 * NR) mw_merge<NR, X>(k, lane); \
+        break;
+    switch (W) {
+        BRM_MW_CASE(1)
+        BRM_MW_CASE(2)
+        BRM_MW_CASE(4)
+        BRM_MW_CASE(8)
+        BRM_MW_CASE(16)
+        BRM_MW_CASE(32)
+        BRM_MW_CASE(64)
+        BRM_MW_CASE(128)
+        BRM_MW_CASE(256)
+        BRM_MW_CASE(512)
+        default: break;
+    }
+#undef BRM_MW_CASE
+}
+
+// after a merge into windows of W2: a live entry whose predecessor in its
+// window is live with the same column is added into it and dropped
+template <int NR>
+__device__ __forceinline__ void mw_dedup(uint32_t (&k)[NR], int lane, int W2, double *vals) {
+    uint32_t prev[NR];
+    prev[0] = lane_prev(k[NR - 1]);
+#pragma unroll
+    for (int e = 1; e < NR; ++e) prev[e] = k[e - 1];
+    bool dup[NR];
+    bool any = false;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        const int x = lane * NR + e;
+        dup[e] = (x & (W2 - 1)) != 0 && ((k[e] | prev[e]) & kMwDrop) == 0 &&
+                 (k[e] >> kMwShift) == (prev[e] >> kMwShift);
+        any = any || dup[e];
+    }
+    if (!wave_ballot(any)) return;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        if (dup[e]) {
+            const uint32_t a = prev[e] & kMwSlotMask, b = k[e] & kMwSlotMask;
+            vals[a] = vals[a] + vals[b];  // the two children of one node
+            k[e] |= kMwLow;
+        }
+    }
+}
+
+// One row under windows of NR registers: multiplying phase from the list
+// descriptors (lane t < L holds list t: B row start, length, A value),
+// accumulating rounds, write-out (VALUES) or count of distinct columns.
+// Returns the row's length to every lane.
+template <int NR, bool VALUES, typename IB>
+__device__ __forceinline__ int mw_row(int lane, int sw, IB bs, int ln, double av, const int32_t *b_col,
+                                      const double *b_val, double *vals, int32_t *out_col, double *out_val,
+                                      int cap) {
+    constexpr int T = kWave * NR;
+    const int W0 = 1 << sw;
+    // the lane's elements are entries o0 .. o0 + NR - 1 of list li
+    const int li = (lane * NR) >> sw;
+    const int o0 = (lane * NR) & (W0 - 1);
+    const int64_t lbs = __shfl((int64_t)bs, li, kWave);
+    const int lln = __shfl(ln, li, kWave);
+    double lav = 0.0;
+    if constexpr (VALUES) lav = __shfl(av, li, kWave);
+    uint32_t k[NR];
+    int32_t c[NR];
+    double bv[NR];
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        c[e] = kEmptyCol;
+        bv[e] = 0.0;
+        if (o0 + e < lln) {
+            c[e] = b_col[lbs + o0 + e];
+            if constexpr (VALUES) bv[e] = b_val[lbs + o0 + e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        if constexpr (VALUES) {
+            const int slot = e * kWave + lane;
+            vals[slot] = lav * bv[e];  // one rounded product
+            k[e] = c[e] == kEmptyCol ? kMwEmpty : (((uint32_t)c[e] << kMwShift) | (uint32_t)slot);
+        } else {
+            k[e] = c[e] == kEmptyCol ? kMwEmpty : (uint32_t)c[e];
+        }
+    }
+    for (int W = W0; W < T; W <<= 1) {
+        mw_merge_w<NR>(k, lane, W);
+        if constexpr (VALUES) mw_dedup<NR>(k, lane, 2 * W, vals);
+    }
+    if constexpr (VALUES) {
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < NR; ++e) cnt += (k[e] & kMwDrop) == 0;
+        const int incl = wave_incl_scan(cnt);
+        int pos = incl - cnt;
+#pragma unroll
+        for (int e = 0; e < NR; ++e) {
+            if ((k[e] & kMwDrop) == 0) {
+                if (pos < cap) {
+                    out_col[pos] = (int32_t)(k[e] >> kMwShift);
+                    out_val[pos] = vals[k[e] & kMwSlotMask];
+                }
+                ++pos;
+            }
+        }
+        return __builtin_amdgcn_readlane(incl, kWave - 1);
+    } else {
+        const uint32_t p0 = lane_prev(k[NR - 1]);
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < NR; ++e) {
+            const uint32_t prev = e == 0 ? p0 : k[e - 1];
+            cnt += k[e] != kMwEmpty && ((lane == 0 && e == 0) || k[e] != prev);
+        }
+        return __builtin_amdgcn_readlane(wave_incl_scan(cnt), kWave - 1);
+    }
+}
+
+// The rows of kClassMulti, one wavefront per row, in chunks of kWave rows
+// whose row ids, A row pointers, window widths and C row pointers are
+// loaded at once (lane j holds row j's).
+template <bool VALUES, typename IA, typename IB>
+__device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
+                                        const int32_t *b_col, const double *b_val, const uint8_t *row_class,
+                                        const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
+                                        double *c_val, int32_t *row_size, Ctl *ctl, const NumOut &no, double *vals,
+                                        int64_t first, int64_t stride) {
+    const int lane = lane_id();
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    const int64_t nchunks = (count + kWave - 1) / kWave;
+    const IB *ent_bs = static_cast<const IB *>(lists.ent_bs);
+    const int32_t *ent_len = lists.ent_len;
+    for (int64_t ch = first; ch < nchunks; ch += stride) {
+        const int64_t base = ch * kWave;
+        const int n = (int)(count - base < kWave ? count - base : kWave);
+        int64_t m_row = 0, m_a0 = 0, m_cs = 0;
+        int m_L = 0, m_sw = 0, m_cap = 0;
+        if (lane < n) {
+            m_row = class_rows[start + base + lane];
+            m_a0 = ld_rpt<IA>(a_rpt, m_row);
+            m_L = (int)(ld_rpt<IA>(a_rpt, m_row + 1) - m_a0);
+            m_sw = row_class[m_row] >> kClassBits;
+            if constexpr (VALUES) {
+                m_cs = c_rpt[m_row];
+                m_cap = (int)(c_rpt[m_row + 1] - m_cs);  // a row's size fits 31 bits
+            }
+        }
+        for (int j = 0; j < n; ++j) {
+            const int64_t row = lane_value(m_row, j);
+            const int64_t a0 = lane_value(m_a0, j);
+            const int L = lane_value(m_L, j);
+            const int sw = lane_value(m_sw, j);
+            IB bs = 0;
+            int ln = 0;
+            double av = 0.0;
+            if (lane < L) {
+                bs = ent_bs[a0 + lane];
+                ln = ent_len[a0 + lane];
+                if constexpr (VALUES) av = a_val[a0 + lane];
+            }
+            int64_t cs = 0;
+            int cap = 0;
+            if constexpr (VALUES) {
+                cs = lane_value(m_cs, j);
+                cap = lane_value(m_cap, j);
+            }
+            int32_t *oc = VALUES ? c_col + cs : nullptr;
+            double *ov = VALUES ? c_val + cs : nullptr;
+            const int t = sw + ceil_log2(L);  // log2 of the padded total, 7..10
+            int len;
+            switch (t) {
+                case 7: len = mw_row<2, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
+                case 8: len = mw_row<4, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
+                case 9: len = mw_row<8, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
+                default: len = mw_row<16, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
+            }
+            if constexpr (VALUES) {
+                if (no.bound) {
+                    // slot mode: exact length kept, an overflowing row listed
+                    // for the fallback (light rows fill the list from its end)
+                    if (lane == 0) {
+                        no.row_size[row] = len;
+                        if (len > cap) {
+                            const unsigned long long at =
+                                atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->ovf_light), 1ull);
+                            no.ovf_rows[no.M - 1 - (int64_t)at] = (int32_t)row;
+                        }
+                    }
+                } else if (lane == 0 && len != cap) {
+                    atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+                }
+            } else {
+                if (lane == 0) row_size[row] = len;
+            }
+        }
+    }
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_num_mw(int cls, const void *a_rpt, Lists<IB> lists, const double *a_val,
+                                                const int32_t *b_col, const double *b_val, const uint8_t *row_class,
+                                                const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
+                                                double *c_val, Ctl *ctl, NumOut no) {
+    __shared__ double vals[4][kMwSlots];
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    mw_rows<true, IA, IB>(cls, a_rpt, lists, a_val, b_col, b_val, row_class, class_rows, c_rpt, c_col, c_val,
+                          nullptr, ctl, no, vals[team], (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_sym_mw(int cls, const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
+                                                const uint8_t *row_class, const int32_t *class_rows,
+                                                int32_t *row_size, Ctl *ctl) {
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    NumOut no;
+    no.bound = 0;
+    mw_rows<false, IA, IB>(cls, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows, nullptr, nullptr,
+                           nullptr, row_size, ctl, no, nullptr, (int64_t)blockIdx.x * 4 + team,
+                           (int64_t)gridDim.x * 4);
+}
+
 // Several short rows per team: the rows of a class whose lists and products
 // each stay within CAP / G are merged G at a time, so that one wavefront
 // keeps G rows' loads in flight.
@@ -1871,6 +2216,16 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
                 BRM_NUM((k_num_group<64, 4, kGroupRows * kCapWaveSmall, kGroupRows, int64_t, int32_t>), 256, int32_t);
             else
                 BRM_NUM((k_num_group<64, 4, kGroupRows * kCapWaveSmall, kGroupRows, int64_t, int64_t>), 256, int64_t);
+            break;
+        case kClassMulti:
+#define BRM_NUM_MW(IA, IB)                                                                                      \
+    hipLaunchKernelGGL((k_num_mw<IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), A.val, \
+                       B.col, B.val, ws.row_class, ws.class_rows, c_rpt, c_col, c_val, ws.ctl, no)
+            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM_MW(int32_t, int32_t);
+            else if (A.rpt_bytes == 4) BRM_NUM_MW(int32_t, int64_t);
+            else if (B.rpt_bytes == 4) BRM_NUM_MW(int64_t, int32_t);
+            else BRM_NUM_MW(int64_t, int64_t);
+#undef BRM_NUM_MW
             break;
         case kClassWave: BRM_NUM_ALL(64, 4, kCapWave); break;
         case kClassGroup: BRM_NUM_ALL(256, 1, kCapGroup); break;

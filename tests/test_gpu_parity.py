@@ -99,11 +99,19 @@ def test_row_classes_all_used(handle):
     A = synth.CSR(len(rows), K, rpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
                   rng.uniform(-1, 1, rpt[-1]))
     B = synth.random_csr(K, N, 0.0025, 4)
-    C = run(handle, A, B)
-    cls = handle.class_rows()
-    assert cls["heavy"] == 0
-    assert cls["copy"] > 0 and cls["wave_small"] > 0 and cls["wave"] > 0 and cls["group"] > 0
-    assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+    ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+    try:
+        for g in (1, 0):  # with lane windows (wave-small, multi), then LDS only
+            handle.set_option(brm.OPT_GROUP_ROWS, g)
+            C = run(handle, A, B)
+            cls = handle.class_rows()
+            print(f"case: mixed row sizes, group rows {g}: {cls}", flush=True)
+            assert cls["heavy"] == 0
+            assert cls["copy"] > 0 and cls["wave_small"] > 0 and cls["group"] > 0
+            assert cls["multi"] > 0 if g == 1 else (cls["multi"] == 0 and cls["wave"] > 0)
+            assert_matches_oracle(C, ref, model)
+    finally:
+        handle.set_option(brm.OPT_GROUP_ROWS, 1)
 
 
 def test_int64_row_pointers(handle):
@@ -239,7 +247,8 @@ def test_short_row_kernels_agree(handle):
                                   y.view(np.int64) if y.dtype == np.float64 else y)
     assert classes[1]["wave_small"] > 0
     assert classes[1]["wave_small"] < classes[0]["wave_small"]
-    assert classes[1]["wave"] > classes[0]["wave"]
+    # (the rows that leave it go to the multi-register or the LDS classes)
+    assert classes[1]["wave"] + classes[1]["multi"] > classes[0]["wave"]
 
 
 def test_option_change_between_passes(handle):
@@ -328,3 +337,79 @@ def test_column_wise_dual(handle):
     assert np.all(np.abs(Cr.val - ref.val) <= 1e-12 * ref.absval)
     with pytest.raises(brm.SpgError):
         handle.spgemm_csc(dA, dA)
+
+
+def _multi_window_rows(seed, M=500):
+    # rows whose lists fit lane windows of 2 to 16 registers per lane: padded
+    # total 2^t (t = 7..10) split between list width 2^sw and list count
+    rng = np.random.default_rng(seed)
+    K, N = 2048, 4096
+    blens = rng.integers(0, 1025, K)
+    blens[:64] = np.arange(64)  # short rows of every length
+    order = np.argsort(blens, kind="stable")
+    sl_ = blens[order]
+    brows = [np.sort(rng.choice(N, size=int(l), replace=False)) for l in blens]
+    brpt = np.zeros(K + 1, np.int64)
+    brpt[1:] = np.cumsum(blens)
+    B = synth.CSR(K, N, brpt.astype(np.int32), np.concatenate(brows).astype(np.int32), rng.uniform(-1, 1, brpt[-1]))
+    rows = []
+    for i in range(M):
+        t = int(rng.integers(7, 11))
+        sw = int(rng.integers(max(t - 6, 0), t + 1))
+        L = int(rng.integers((1 << (t - sw - 1)) + 1, (1 << (t - sw)) + 1)) if t - sw > 0 else 1
+        L = max(L, 2)
+        mx = int(rng.integers((1 << (sw - 1)) + 1, (1 << sw) + 1)) if sw > 0 else 1
+        # one list of length mx, the others not longer
+        lo, hi = np.searchsorted(sl_, [mx, mx + 1])
+        if hi <= lo:
+            continue
+        first = order[rng.integers(lo, hi)]
+        short = order[:np.searchsorted(sl_, mx + 1)]
+        rest = rng.choice(short, size=min(L - 1, short.size), replace=False)
+        r = np.unique(np.concatenate([[first], rest]))
+        rng.shuffle(r)  # any stored order of the lists, columns sorted below
+        rows.append(np.sort(r))
+    rpt = np.zeros(len(rows) + 1, np.int64)
+    rpt[1:] = np.cumsum([len(r) for r in rows])
+    A = synth.CSR(len(rows), K, rpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                  rng.uniform(-1, 1, rpt[-1]))
+    return A, B
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_multi_register_windows(handle, seed):
+    A, B = _multi_window_rows(seed)
+    ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+    outs = {}
+    try:
+        for g, force in ((1, -1), (1, 7), (0, -1)):
+            print(f"case: multi-register windows seed {seed}, group rows {g}, force {force}", flush=True)
+            handle.set_option(brm.OPT_GROUP_ROWS, g)
+            handle.set_option(brm.OPT_FORCE_CLASS, force)
+            C = run(handle, A, B)
+            cls = handle.class_rows()
+            print(cls, flush=True)
+            if g == 1:
+                assert cls["multi"] > A.rows // 2
+            else:
+                assert cls["multi"] == 0
+            assert_matches_oracle(C, ref, model)
+            outs[(g, force)] = to_host(C)
+    finally:
+        handle.set_option(brm.OPT_FORCE_CLASS, -1)
+        handle.set_option(brm.OPT_GROUP_ROWS, 1)
+    # the symbolic counts of the multi class are the exact row sizes
+    assert np.array_equal(outs[(1, -1)][0], ref.rpt)
+
+
+def test_multi_register_windows_column_limit(handle):
+    # keys hold columns below 2^21: with B that wide the class is not used
+    A, B = _multi_window_rows(33, M=120)
+    ref = oracle.spgemm(A, B)
+    for N, want in ((1 << 21, True), ((1 << 21) + 1, False)):
+        Bw = synth.CSR(B.rows, N, B.rpt, (B.col.astype(np.int64) * (N - 1) // (B.cols - 1)).astype(np.int32), B.val)
+        refw = oracle.spgemm(A, Bw)
+        C = run(handle, A, Bw)
+        assert (handle.class_rows()["multi"] > 0) == want
+        assert_matches_oracle(C, refw, oracle.brmerge(A, Bw))
+    assert ref.nnz > 0
