@@ -142,7 +142,9 @@ enum {
 int spg_set_option(spg_handle h, int key, int64_t value);
 int spg_get_option(spg_handle h, int key, int64_t *value);
 
-/* Statistics of the last symbolic/numeric pair (spg_get_stat). */
+/* Statistics of the last symbolic/numeric pair (spg_get_stat); after
+ * spgemm_batched, SPG_STAT_NPROD covers the whole batch and the class counts
+ * the rows of its last stage. */
 typedef enum {
     SPG_STAT_NPROD = 1,          /* total products of the last symbolic call */
     SPG_STAT_NNZ = 2,            /* nnz(C) of the last symbolic call */

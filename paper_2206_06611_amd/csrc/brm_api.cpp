@@ -169,6 +169,7 @@ int ensure_workspace(spg_handle h, int64_t M, int64_t nnzA, Workspace *ws) {
     ws->tile_sum = reinterpret_cast<int64_t *>(base + off_tile);
     ws->ent_bs = base + off_ebs;
     ws->ent_len = reinterpret_cast<int32_t *>(base + off_elen);
+    ws->row_prob = nullptr;
     ws->ctl = h->ctl;
     return SPG_OK;
 }
@@ -1007,17 +1008,18 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     HIP_TRY(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     // stage ranges, row offsets, widths
-    struct StageInfo { int first, n; int64_t rows; int arb, brb; bool link; size_t roff; };
+    struct StageInfo { int first, n; int64_t rows, ents; int arb, brb; bool link; size_t roff; };
     std::vector<StageInfo> st;
     size_t roff_total = 0;
     for (int p = 0; p < count;) {
         int q = p;
-        StageInfo si{p, 0, 0, probs[p].A.rpt_bytes, probs[p].b_from >= 0 ? 8 : probs[p].B.rpt_bytes, false, roff_total};
+        StageInfo si{p, 0, 0, 0, probs[p].A.rpt_bytes, probs[p].b_from >= 0 ? 8 : probs[p].B.rpt_bytes, false, roff_total};
         while (q < count && stage[(size_t)q] == stage[(size_t)p]) {
             const int brb = probs[q].b_from >= 0 ? 8 : probs[q].B.rpt_bytes;
             if (probs[q].A.rpt_bytes != si.arb || brb != si.brb)
                 return fail(h, SPG_ERR_ARG, "problems of one stage must share row-pointer widths (problem %d)", q);
             si.rows += probs[q].A.rows;
+            si.ents += probs[q].A.nnz;
             si.link = si.link || probs[q].b_from >= 0;
             ++q;
         }
@@ -1026,8 +1028,12 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
         st.push_back(si);
         p = q;
     }
-    int64_t max_rows = 0;
-    for (auto &x : st) max_rows = std::max(max_rows, x.rows);
+    int64_t max_rows = 0, max_ents = 0, max_bcols = 0;
+    for (auto &x : st) {
+        max_rows = std::max(max_rows, x.rows);
+        max_ents = std::max(max_ents, x.ents);
+    }
+    for (int p = 0; p < count; ++p) max_bcols = std::max(max_bcols, ccols[(size_t)p]);
     if (max_rows > INT32_MAX) return fail(h, SPG_ERR_ARG, "too many rows in one stage");
     // arena: row pointers first (sizes known now), then C's columns and values
     int64_t rpt_end = 0;
@@ -1052,7 +1058,11 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     const size_t o_tab = align_up(o_roff + 8 * roff_total, a);
     const size_t o_stat = align_up(o_tab + sizeof(BatchProb) * (size_t)count, a);
     const size_t o_ctl = align_up(o_stat + sizeof(BatchStatus), a);
-    const size_t total = align_up(o_ctl + sizeof(Ctl), a);
+    // the window kernels' inputs: the problem of every row, list descriptors
+    const size_t o_prob = align_up(o_ctl + sizeof(Ctl), a);
+    const size_t o_ebs = align_up(o_prob + 4 * (size_t)max_rows, a);
+    const size_t o_elen = align_up(o_ebs + 8 * (size_t)max_ents, a);
+    const size_t total = align_up(o_elen + 4 * (size_t)max_ents, a);
     bool realloc = false;
     if (total > h->b_bytes) {
         if (h->graph_exec) {
@@ -1087,6 +1097,9 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     ws.class_rows = reinterpret_cast<int32_t *>(base + o_rows);
     ws.tile_sum = reinterpret_cast<int64_t *>(base + o_tile);
     ws.ctl = reinterpret_cast<Ctl *>(base + o_ctl);
+    ws.row_prob = reinterpret_cast<int32_t *>(base + o_prob);
+    ws.ent_bs = base + o_ebs;
+    ws.ent_len = reinterpret_cast<int32_t *>(base + o_elen);
     int64_t *d_S = reinterpret_cast<int64_t *>(base + o_S);
     int64_t *d_roff = reinterpret_cast<int64_t *>(base + o_roff);
     BatchProb *d_tab = reinterpret_cast<BatchProb *>(base + o_tab);
@@ -1094,7 +1107,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     char *arena_c = static_cast<char *>(arena);
     // host table
     for (auto &x : st) {
-        int64_t ro = 0;
+        int64_t ro = 0, eo = 0;
         for (int i = 0; i < x.n; ++i) {
             const int p = x.first + i;
             const spg_problem &q = probs[p];
@@ -1114,8 +1127,10 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
             b.c_rpt = reinterpret_cast<int64_t *>(arena_c + rpt_off[(size_t)p]);
             b.rpt_off = rpt_off[(size_t)p];
             b.b_from = q.b_from;
+            b.ent_off = eo;
             h->b_row_off_host[x.roff + (size_t)i] = ro;
             ro += q.A.rows;
+            eo += q.A.nnz;
         }
         h->b_row_off_host[x.roff + (size_t)x.n] = ro;
     }
@@ -1134,7 +1149,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
             sig.push_back((int64_t)reinterpret_cast<uintptr_t>(ptr));
     }
     for (int64_t v : {(int64_t)reinterpret_cast<uintptr_t>(arena), arena_bytes, h->wave_small_max, h->wave_max,
-                      h->group_max,
+                      h->group_max, h->group_rows,
                       h->block_max, h->force, h->grid_waves, (int64_t)reinterpret_cast<uintptr_t>(h->b_mem)})
         sig.push_back(v);
     if (realloc || !h->graph_exec || sig != h->graph_sig) {
@@ -1146,7 +1161,9 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
         hipStream_t cs = h->cap_stream;
         HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t e = launch_batched_begin(d_stat, cs);
-        const Thresholds th = thresholds(h, false);
+        // lane windows as in the single product (their keys bound B's columns)
+        const bool win = uses_windows(h->group_rows) && max_bcols < ((int64_t)1 << 26);
+        const Thresholds th = thresholds(h, win, max_bcols <= ((int64_t)1 << 21));
         for (auto &x : st) {
             if (e != hipSuccess) break;
             BatchStage bs;
@@ -1186,9 +1203,11 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
     HIP_TRY(h, launch_batched_describe(d_tab, count, out, d_stat, s));
     HIP_TRY(h, hipMemcpyAsync(h->b_status_host, d_stat, sizeof(BatchStatus), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(h->ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     const BatchStatus &bst = *h->b_status_host;
     h->nprod = bst.nprod;
+    for (int i = 0; i < kNumClasses; ++i) h->counts[i] = h->ctl_host->count[i];  // the last stage's rows
     if (bst.flags & kBatchHeavyRow) {
         *required_bytes = -1;
         return fail(h, SPG_ERR_CAPACITY, "a row has more than %d products; use the single-product calls", kCapBlock);

@@ -85,6 +85,7 @@ struct Workspace {
     Ctl *ctl;
     void *ent_bs;         // [nnz(A)] start of each A entry's B row (B's row-pointer type)
     int32_t *ent_len;     // [nnz(A)] length of each A entry's B row
+    int32_t *row_prob;    // batched stages: [M] the problem of every row
 };
 
 constexpr int kScanTile = 4096;  // rows per scan tile (256 threads x 16)
@@ -163,6 +164,7 @@ struct BatchProb {
     int64_t rpt_off, col_off, val_off;  // byte offsets in the arena
     int32_t b_from;    // -1, or the problem whose C is this problem's B
     int32_t pad;
+    int64_t ent_off;   // first entry of this problem's A in the stage's list descriptors
 };
 
 enum BatchFlags : int { kBatchOverflow = 1, kBatchHeavyRow = 2 };

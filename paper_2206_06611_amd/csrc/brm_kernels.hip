@@ -1612,6 +1612,13 @@ __device__ __forceinline__ int64_t lane_value(int64_t x, int j) {
 __device__ __forceinline__ int lane_value(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
 
 
+// Where the window kernels of a batched stage find a row's problem: the
+// stage's problem table and the problem of every row (from the analysis).
+struct BatchRows {
+    const BatchProb *tab = nullptr;
+    const int32_t *row_prob = nullptr;
+};
+
 // What masked lanes of the pipelined short-row kernels read instead of A's
 // and B's arrays: an empty column and zeros, so that no value needs masking
 // after its load.  Never written; not const, so that the compiler keeps them
@@ -1643,12 +1650,13 @@ __device__ __forceinline__ T load_opaque(const T *p) {
 // above), so the number of memory operations in flight does not depend on
 // the path and the waits stay partial.  VALUES = false counts row sizes;
 // HASH then selects counting by LDS hash instead of window merges.
-template <bool VALUES, bool HASH, typename IA, typename IB>
+template <bool VALUES, bool HASH, typename IA, typename IB, bool BATCH = false>
 __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
                                            const int32_t *b_col, const double *b_val, const uint8_t *row_class,
                                            const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
                                            double *c_val, int32_t *row_size, Ctl *ctl, const NumOut &no,
-                                           int32_t *tab, uint32_t *xk, double *xv, int64_t first, int64_t stride) {
+                                           int32_t *tab, uint32_t *xk, double *xv, int64_t first, int64_t stride,
+                                           BatchRows br = BatchRows{}) {
     const int lane = lane_id();
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
@@ -1662,25 +1670,58 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
         // window width (log2) and padded total (0 beyond the chunk)
         int64_t m_row = 0, m_a0 = 0, m_cs = 0;
         int m_L = 0, m_sw = 0, m_T = 0, m_cap = 0;
+        // batched: the row's problem (first descriptor, operand and output arrays)
+        int64_t m_eo = 0, m_aval = 0, m_bcol = 0, m_bval = 0, m_ccol = 0, m_cval = 0;
         if (lane < n) {
             m_row = class_rows[start + base + lane];
-            m_a0 = ld_rpt<IA>(a_rpt, m_row);
-            m_L = (int)(ld_rpt<IA>(a_rpt, m_row + 1) - m_a0);
+            const void *rpt = a_rpt;
+            const int64_t *crpt = c_rpt;
+            int64_t r = m_row;
+            if constexpr (BATCH) {
+                const BatchProb &pr = br.tab[br.row_prob[m_row]];
+                rpt = pr.a_rpt;
+                crpt = pr.c_rpt;
+                r = m_row - pr.row_off;
+                m_eo = pr.ent_off;
+                m_aval = reinterpret_cast<int64_t>(pr.a_val);
+                m_bcol = reinterpret_cast<int64_t>(pr.b_col);
+                m_bval = reinterpret_cast<int64_t>(pr.b_val);
+                m_ccol = reinterpret_cast<int64_t>(pr.c_col);
+                m_cval = reinterpret_cast<int64_t>(pr.c_val);
+            }
+            m_a0 = ld_rpt<IA>(rpt, r);
+            m_L = (int)(ld_rpt<IA>(rpt, r + 1) - m_a0);
             m_sw = row_class[m_row] >> kClassBits;
             m_T = 1 << (m_sw + ceil_log2(m_L > 0 ? m_L : 1));
             if constexpr (VALUES) {
-                m_cs = c_rpt[m_row];
-                m_cap = (int)(c_rpt[m_row + 1] - m_cs);  // a row's size fits 31 bits
+                m_cs = crpt[r];
+                m_cap = (int)(crpt[r + 1] - m_cs);  // a row's size fits 31 bits
             }
         }
+        auto a_val_of = [&](int j) -> const double * {
+            if constexpr (BATCH) return reinterpret_cast<const double *>(lane_value(m_aval, j));
+            else return a_val;
+        };
+        auto b_col_of = [&](int j) -> const int32_t * {
+            if constexpr (BATCH) return reinterpret_cast<const int32_t *>(lane_value(m_bcol, j));
+            else return b_col;
+        };
+        auto b_val_of = [&](int j) -> const double * {
+            if constexpr (BATCH) return reinterpret_cast<const double *>(lane_value(m_bval, j));
+            else return b_val;
+        };
         // list descriptors of row j: lane t < L holds list t (empty beyond)
         auto load_lists = [&](int j, IB &bs, int &ln, double &av) {
             const int jj = j < n ? j : 0;
             const int64_t p = lane_value(m_a0, jj) + lane;
+            const int64_t pe = BATCH ? lane_value(m_eo, jj) + p : p;
             const bool ok = j < n && lane < lane_value(m_L, jj);
-            bs = load_opaque(ok ? ent_bs + p : reinterpret_cast<const IB *>(&g_zeros[0]));
-            ln = load_opaque(ok ? ent_len + p : reinterpret_cast<const int32_t *>(&g_zeros[0]));
-            if constexpr (VALUES) av = load_opaque(ok ? a_val + p : reinterpret_cast<const double *>(&g_zeros[0]));
+            bs = load_opaque(ok ? ent_bs + pe : reinterpret_cast<const IB *>(&g_zeros[0]));
+            ln = load_opaque(ok ? ent_len + pe : reinterpret_cast<const int32_t *>(&g_zeros[0]));
+            if constexpr (VALUES) {
+                const double *av_p = a_val_of(jj);
+                av = load_opaque(ok ? av_p + p : reinterpret_cast<const double *>(&g_zeros[0]));
+            }
         };
         // multiplying phase of row j into the lane windows (the products are
         // formed where the row is consumed): lane t holds entry t mod W0 of
@@ -1696,9 +1737,13 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             lav = 0.0;
             if constexpr (VALUES) lav = __shfl(av, li, kWave);
             const bool ok = li < L && o < lln;
-            c = load_opaque(ok ? b_col + (lbs + o) : &g_empty_col[0]);
+            const int32_t *bc = b_col_of(jj);
+            c = load_opaque(ok ? bc + (lbs + o) : &g_empty_col[0]);
             bv = 0.0;
-            if constexpr (VALUES) bv = load_opaque(ok ? b_val + (lbs + o) : reinterpret_cast<const double *>(&g_zeros[0]));
+            if constexpr (VALUES) {
+                const double *bvp = b_val_of(jj);
+                bv = load_opaque(ok ? bvp + (lbs + o) : reinterpret_cast<const double *>(&g_zeros[0]));
+            }
         };
         struct ListStageRegs {  // list descriptors of one row
             IB bs;
@@ -1737,9 +1782,15 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                 len = __popcll(wave_ballot(live));
                 const int64_t cs = lane_value(m_cs, j);
                 const int cap = lane_value(m_cap, j);
+                int32_t *cc = c_col;
+                double *cv = c_val;
+                if constexpr (BATCH) {
+                    cc = reinterpret_cast<int32_t *>(lane_value(m_ccol, j));
+                    cv = reinterpret_cast<double *>(lane_value(m_cval, j));
+                }
                 if (live && lane < cap) {
-                    c_col[cs + lane] = (int32_t)(k >> kKeyLaneBits);
-                    c_val[cs + lane] = v;
+                    cc[cs + lane] = (int32_t)(k >> kKeyLaneBits);
+                    cv[cs + lane] = v;
                 }
             }
             if constexpr (VALUES) {
@@ -2032,12 +2083,12 @@ __device__ __forceinline__ int mw_row(int lane, int sw, IB bs, int ln, double av
 // The rows of kClassMulti, one wavefront per row, in chunks of kWave rows
 // whose row ids, A row pointers, window widths and C row pointers are
 // loaded at once (lane j holds row j's).
-template <bool VALUES, typename IA, typename IB>
+template <bool VALUES, typename IA, typename IB, bool BATCH = false>
 __device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
                                         const int32_t *b_col, const double *b_val, const uint8_t *row_class,
                                         const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
                                         double *c_val, int32_t *row_size, Ctl *ctl, const NumOut &no, double *vals,
-                                        int64_t first, int64_t stride) {
+                                        int64_t first, int64_t stride, BatchRows br = BatchRows{}) {
     const int lane = lane_id();
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
@@ -2049,14 +2100,31 @@ __device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<
         const int n = (int)(count - base < kWave ? count - base : kWave);
         int64_t m_row = 0, m_a0 = 0, m_cs = 0;
         int m_L = 0, m_sw = 0, m_cap = 0;
+        // batched: the row's problem (first descriptor, operand and output arrays)
+        int64_t m_eo = 0, m_aval = 0, m_bcol = 0, m_bval = 0, m_ccol = 0, m_cval = 0;
         if (lane < n) {
             m_row = class_rows[start + base + lane];
-            m_a0 = ld_rpt<IA>(a_rpt, m_row);
-            m_L = (int)(ld_rpt<IA>(a_rpt, m_row + 1) - m_a0);
+            const void *rpt = a_rpt;
+            const int64_t *crpt = c_rpt;
+            int64_t r = m_row;
+            if constexpr (BATCH) {
+                const BatchProb &pr = br.tab[br.row_prob[m_row]];
+                rpt = pr.a_rpt;
+                crpt = pr.c_rpt;
+                r = m_row - pr.row_off;
+                m_eo = pr.ent_off;
+                m_aval = reinterpret_cast<int64_t>(pr.a_val);
+                m_bcol = reinterpret_cast<int64_t>(pr.b_col);
+                m_bval = reinterpret_cast<int64_t>(pr.b_val);
+                m_ccol = reinterpret_cast<int64_t>(pr.c_col);
+                m_cval = reinterpret_cast<int64_t>(pr.c_val);
+            }
+            m_a0 = ld_rpt<IA>(rpt, r);
+            m_L = (int)(ld_rpt<IA>(rpt, r + 1) - m_a0);
             m_sw = row_class[m_row] >> kClassBits;
             if constexpr (VALUES) {
-                m_cs = c_rpt[m_row];
-                m_cap = (int)(c_rpt[m_row + 1] - m_cs);  // a row's size fits 31 bits
+                m_cs = crpt[r];
+                m_cap = (int)(crpt[r + 1] - m_cs);  // a row's size fits 31 bits
             }
         }
         for (int j = 0; j < n; ++j) {
@@ -2064,13 +2132,27 @@ __device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<
             const int64_t a0 = lane_value(m_a0, j);
             const int L = lane_value(m_L, j);
             const int sw = lane_value(m_sw, j);
+            const double *av_p = a_val;
+            const int32_t *bc_p = b_col;
+            const double *bv_p = b_val;
+            int32_t *cc_p = c_col;
+            double *cv_p = c_val;
+            int64_t e0 = a0;
+            if constexpr (BATCH) {
+                e0 = lane_value(m_eo, j) + a0;
+                av_p = reinterpret_cast<const double *>(lane_value(m_aval, j));
+                bc_p = reinterpret_cast<const int32_t *>(lane_value(m_bcol, j));
+                bv_p = reinterpret_cast<const double *>(lane_value(m_bval, j));
+                cc_p = reinterpret_cast<int32_t *>(lane_value(m_ccol, j));
+                cv_p = reinterpret_cast<double *>(lane_value(m_cval, j));
+            }
             IB bs = 0;
             int ln = 0;
             double av = 0.0;
             if (lane < L) {
-                bs = ent_bs[a0 + lane];
-                ln = ent_len[a0 + lane];
-                if constexpr (VALUES) av = a_val[a0 + lane];
+                bs = ent_bs[e0 + lane];
+                ln = ent_len[e0 + lane];
+                if constexpr (VALUES) av = av_p[a0 + lane];
             }
             int64_t cs = 0;
             int cap = 0;
@@ -2078,15 +2160,15 @@ __device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<
                 cs = lane_value(m_cs, j);
                 cap = lane_value(m_cap, j);
             }
-            int32_t *oc = VALUES ? c_col + cs : nullptr;
-            double *ov = VALUES ? c_val + cs : nullptr;
+            int32_t *oc = VALUES ? cc_p + cs : nullptr;
+            double *ov = VALUES ? cv_p + cs : nullptr;
             const int t = sw + ceil_log2(L);  // log2 of the padded total, 7..10
             int len;
             switch (t) {
-                case 7: len = mw_row<2, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
-                case 8: len = mw_row<4, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
-                case 9: len = mw_row<8, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
-                default: len = mw_row<16, VALUES, IB>(lane, sw, bs, ln, av, b_col, b_val, vals, oc, ov, cap); break;
+                case 7: len = mw_row<2, VALUES, IB>(lane, sw, bs, ln, av, bc_p, bv_p, vals, oc, ov, cap); break;
+                case 8: len = mw_row<4, VALUES, IB>(lane, sw, bs, ln, av, bc_p, bv_p, vals, oc, ov, cap); break;
+                case 9: len = mw_row<8, VALUES, IB>(lane, sw, bs, ln, av, bc_p, bv_p, vals, oc, ov, cap); break;
+                default: len = mw_row<16, VALUES, IB>(lane, sw, bs, ln, av, bc_p, bv_p, vals, oc, ov, cap); break;
             }
             if constexpr (VALUES) {
                 if (no.bound) {
@@ -2702,7 +2784,8 @@ template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const int64_t *row_off, int np,
                                                     int64_t R, Thresholds th, int64_t *row_nprod,
                                                     uint8_t *row_class, int32_t *row_size, Ctl *ctl,
-                                                    BatchStatus *st) {
+                                                    BatchStatus *st, int32_t *row_prob, IB *ent_bs,
+                                                    int32_t *ent_len) {
     __shared__ ProbLookup lk;
     __shared__ int64_t s_count[kNumClasses];
     __shared__ int64_t s_nprod;
@@ -2719,14 +2802,24 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         const BatchProb &pr = tab[p];
         const int64_t r = g - pr.row_off;
         const int64_t a0 = ld_rpt<IA>(pr.a_rpt, r), a1 = ld_rpt<IA>(pr.a_rpt, r + 1);
-        int64_t nprod = 0;
+        int64_t nprod = 0, mx = 0;
         for (int64_t q = a0; q < a1; ++q) {
+            // the list descriptors of the window kernels, as in the single product
             const int32_t k = pr.a_col[q];
-            nprod += ld_rpt<IB>(pr.b_rpt, k + 1) - ld_rpt<IB>(pr.b_rpt, k);
+            const IB bs = reinterpret_cast<const IB *>(pr.b_rpt)[k];
+            const int64_t n = (int64_t)reinterpret_cast<const IB *>(pr.b_rpt)[k + 1] - (int64_t)bs;
+            ent_bs[pr.ent_off + q] = bs;
+            ent_len[pr.ent_off + q] = (int32_t)n;
+            nprod += n;
+            mx = n > mx ? n : mx;
         }
-        const int cls = classify(a1 - a0, nprod, 0, th);
+        const int cls = classify(a1 - a0, nprod, mx, th);
+        const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx)
+                       : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, nprod)
+                                                              : 0;
         row_nprod[g] = nprod;
-        row_class[g] = (uint8_t)cls;
+        row_class[g] = (uint8_t)(cls | (sw << kClassBits));
+        row_prob[g] = p;
         if (cls == kClassEmpty || cls == kClassHeavy) row_size[g] = 0;  // heavy rows: unsupported, flagged
         if (cls == kClassCopy) row_size[g] = (int32_t)nprod;
 #pragma unroll
@@ -2881,6 +2974,85 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb
     }
 }
 
+// the window kernels over a batched stage's rows (lists from the analysis's
+// descriptors, every row's arrays from its problem)
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_b_num_win(int cls, const BatchProb *tab, const int32_t *row_prob,
+                                                   const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
+                                                   const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+    __shared__ uint32_t xk[4][kWave];
+    __shared__ double xv[4][kWave];
+    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
+    lists.ent_bs = ent_bs;
+    lists.ent_len = ent_len;
+    NumOut no;
+    no.bound = 0;
+    BatchRows br;
+    br.tab = tab;
+    br.row_prob = row_prob;
+    win_chunks<true, false, IA, IB, true>(cls, nullptr, lists, nullptr, nullptr, nullptr, row_class, class_rows,
+                                          nullptr, nullptr, nullptr, nullptr, ctl, no, nullptr, xk[team], xv[team],
+                                          (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4, br);
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_b_sym_win(int cls, const BatchProb *tab, const int32_t *row_prob,
+                                                   const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
+                                                   const int32_t *class_rows, int32_t *row_size, Ctl *ctl) {
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
+    lists.ent_bs = ent_bs;
+    lists.ent_len = ent_len;
+    NumOut no;
+    no.bound = 0;
+    BatchRows br;
+    br.tab = tab;
+    br.row_prob = row_prob;
+    win_chunks<false, false, IA, IB, true>(cls, nullptr, lists, nullptr, nullptr, nullptr, row_class, class_rows,
+                                           nullptr, nullptr, nullptr, row_size, ctl, no, nullptr, nullptr, nullptr,
+                                           (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4, br);
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_b_num_mw(int cls, const BatchProb *tab, const int32_t *row_prob,
+                                                  const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
+                                                  const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+    __shared__ double vals[4][kMwSlots];
+    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
+    lists.ent_bs = ent_bs;
+    lists.ent_len = ent_len;
+    NumOut no;
+    no.bound = 0;
+    BatchRows br;
+    br.tab = tab;
+    br.row_prob = row_prob;
+    mw_rows<true, IA, IB, true>(cls, nullptr, lists, nullptr, nullptr, nullptr, row_class, class_rows, nullptr,
+                                nullptr, nullptr, nullptr, ctl, no, vals[team], (int64_t)blockIdx.x * 4 + team,
+                                (int64_t)gridDim.x * 4, br);
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_b_sym_mw(int cls, const BatchProb *tab, const int32_t *row_prob,
+                                                  const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
+                                                  const int32_t *class_rows, int32_t *row_size, Ctl *ctl) {
+    const int team = wave_uniform((int)(threadIdx.x / kWave));
+    Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
+    lists.ent_bs = ent_bs;
+    lists.ent_len = ent_len;
+    NumOut no;
+    no.bound = 0;
+    BatchRows br;
+    br.tab = tab;
+    br.row_prob = row_prob;
+    mw_rows<false, IA, IB, true>(cls, nullptr, lists, nullptr, nullptr, nullptr, row_class, class_rows, nullptr,
+                                 nullptr, nullptr, row_size, ctl, no, nullptr, (int64_t)blockIdx.x * 4 + team,
+                                 (int64_t)gridDim.x * 4, br);
+}
+
 // caller-visible descriptors of the outputs (byte offsets into the arena)
 __global__ void k_b_describe(const BatchProb *all, int n, spg_batched_out *out, const BatchStatus *st) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -2922,10 +3094,20 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
 #define BRM_B_ALL(IA, IB)                                                                                       \
     do {                                                                                                        \
         hipLaunchKernelGGL((k_b_analysis<IA, IB>), dim3(ga), dim3(256), 0, s, tab, ro, np, R, th, ws.row_nprod, \
-                           ws.row_class, ws.row_size, ws.ctl, bs.status);                                       \
+                           ws.row_class, ws.row_size, ws.ctl, bs.status, ws.row_prob,                           \
+                           static_cast<IB *>(ws.ent_bs), ws.ent_len);                                           \
         hipLaunchKernelGGL(k_bin, dim3(ga), dim3(256), 0, s, R, nullptr, ws.row_class, ws.class_rows, ws.ctl); \
-        hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,  \
-                           (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);             \
+        if (th.windows)                                                                                         \
+            hipLaunchKernelGGL((k_b_sym_win<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall,   \
+                               tab, ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class, \
+                               ws.class_rows, ws.row_size, ws.ctl);                                             \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, \
+                               s, (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);       \
+        if (th.multi)                                                                                           \
+            hipLaunchKernelGGL((k_b_sym_mw<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassMulti, tab,   \
+                               ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class,      \
+                               ws.class_rows, ws.row_size, ws.ctl);                                             \
         hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,       \
                            (int)kClassWave, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                  \
         hipLaunchKernelGGL((k_b_sym_hash<256, 1, 2 * kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,     \
@@ -2938,8 +3120,17 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
         hipLaunchKernelGGL(k_b_rpt, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S, bs.status);                \
         hipLaunchKernelGGL((k_b_num_copy<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassCopy, tab, ro,  \
                            np, ws.class_rows, ws.ctl, bs.status);                                              \
-        hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,       \
-                           (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.ctl, bs.status);               \
+        if (th.windows)                                                                                         \
+            hipLaunchKernelGGL((k_b_num_win<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall,   \
+                               tab, ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class, \
+                               ws.class_rows, ws.ctl, bs.status);                                               \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,   \
+                               (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.ctl, bs.status);           \
+        if (th.multi)                                                                                           \
+            hipLaunchKernelGGL((k_b_num_mw<IA, IB>), grid_for(5, 4), dim3(256), 0, s, (int)kClassMulti, tab,   \
+                               ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class,      \
+                               ws.class_rows, ws.ctl, bs.status);                                               \
         hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,            \
                            (int)kClassWave, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                    \
         hipLaunchKernelGGL((k_b_num_lds<256, 1, kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,          \

@@ -138,3 +138,38 @@ def test_config4_full_batch(handle):
         same_bits(to_host(AP[i]), (ref_ap.rpt, ref_ap.col, ref_ap.val))
         ref_g = oracle.spgemm(Pt, synth.CSR(A.rows, P.cols, ref_ap.rpt, ref_ap.col, ref_ap.val))
         same_bits(to_host(G[i]), (ref_g.rpt, ref_g.col, ref_g.val))
+
+
+def test_kernel_choices_agree_in_batches(handle):
+    # short rows under lane windows (one and several registers per lane) and
+    # in LDS give the same bits; the window kernels take every row's arrays
+    # from its own problem
+    rng = np.random.default_rng(9)
+    host = []
+    for i in range(6):
+        M, K, N = (int(x) for x in rng.integers(50, 400, 3))
+        host.append((synth.random_csr(M, K, 0.04, 300 + i, empty_row_frac=0.1),
+                     synth.random_csr(K, N, 0.06, 400 + i)))
+    host.append((synth.stencil_3d_27pt(9), synth.stencil_3d_27pt(9)))  # rows of 27 lists of 27
+    host.append((synth.laplacian_2d_5pt(20), synth.laplacian_2d_5pt(20)))
+    dp = [(dev(A), dev(B)) for A, B in host]
+    outs, classes = {}, {}
+    try:
+        for g in (1, 0):
+            handle.set_option(brm.OPT_GROUP_ROWS, g)
+            arena = torch.empty(1 << 24, dtype=torch.uint8, device="cuda")
+            rc, req, res = handle.batched(dp, arena)
+            assert rc == brm.SPG_OK
+            outs[g] = [to_host(C) for C in res]
+            # the last stage's classes: the rows of every problem together
+            classes[g] = handle.class_rows()
+            print(f"case: batched kernel choices, group rows {g}: {classes[g]}", flush=True)
+    finally:
+        handle.set_option(brm.OPT_GROUP_ROWS, 1)
+    assert classes[1]["multi"] > 0 and classes[1]["wave_small"] > 0
+    assert classes[0]["multi"] == 0
+    for (A, B), x, y in zip(host, outs[1], outs[0]):
+        same_bits(x, y)
+        ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+        assert np.array_equal(x[0], ref.rpt) and np.array_equal(x[1], ref.col)
+        assert np.array_equal(x[2].view(np.int64), model.val.view(np.int64))
