@@ -237,6 +237,23 @@ def cut_row_blocks(row_nprod, max_products: int):
     return blocks
 
 
+class BatchedProblems:
+    """The problems of a batched call in the C ABI's layout, built once; it
+    keeps the matrices it points to alive."""
+
+    def __init__(self, problems):
+        self.n = len(problems)
+        self.arr = (_Problem * max(self.n, 1))()
+        self._keep = list(problems)
+        for i, (A, B) in enumerate(problems):
+            self.arr[i].A = A._struct()
+            if isinstance(B, int):
+                self.arr[i].b_from = B
+            else:
+                self.arr[i].B = B._struct()
+                self.arr[i].b_from = -1
+
+
 def _stream_ptr(stream):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
@@ -414,28 +431,24 @@ class Handle:
         self._check(_lib.spg_mlp_load(self._h, path.encode()))
 
     # ---- batched products -------------------------------------------------
-    def batched(self, problems, arena: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    def batched(self, problems, arena: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                views: bool = True):
         """problems: list of (A, B) where B is a DeviceCSR or the index of an
-        earlier problem whose C is B.  arena: uint8 device tensor.  Returns
-        (status, required_bytes, outputs); outputs are DeviceCSR views into the
-        arena (None when the arena was too small)."""
-        n = len(problems)
-        arr = (_Problem * max(n, 1))()
-        for i, (A, B) in enumerate(problems):
-            arr[i].A = A._struct()
-            if isinstance(B, int):
-                arr[i].b_from = B
-            else:
-                arr[i].B = B._struct()
-                arr[i].b_from = -1
+        earlier problem whose C is B, or a BatchedProblems made from such a
+        list once (repeated calls then skip the marshalling).  arena: uint8
+        device tensor.  Returns (status, required_bytes, outputs); outputs are
+        DeviceCSR views into the arena (None when the arena was too small, or
+        when views is False: `out` then holds the descriptors)."""
+        bp = problems if isinstance(problems, BatchedProblems) else BatchedProblems(problems)
+        n = bp.n
         if out is None:
             out = torch.empty((max(n, 1), 6), dtype=torch.int64, device=arena.device)
         req = ctypes.c_int64()
-        rc = _lib.spgemm_batched(self._h, n, arr, ctypes.c_void_p(arena.data_ptr()), arena.numel(),
+        rc = _lib.spgemm_batched(self._h, n, bp.arr, ctypes.c_void_p(arena.data_ptr()), arena.numel(),
                                  ctypes.c_void_p(out.data_ptr()), ctypes.byref(req), _stream_ptr(stream))
         if rc not in (SPG_OK, SPG_ERR_CAPACITY):
             self._check(rc)
-        if rc != SPG_OK:
+        if rc != SPG_OK or not views:
             return rc, req.value, None
         desc = out[:n].cpu().tolist()
         outs = []
@@ -446,12 +459,19 @@ class Handle:
             outs.append(DeviceCSR(int(rows), int(cols), rpt, col, val))
         return rc, req.value, outs
 
-    def galerkin(self, triples, arena: torch.Tensor | None = None, stream=None):
+    @staticmethod
+    def galerkin_problems(triples) -> "BatchedProblems":
+        """The batched problems of galerkin(triples), marshalled once."""
+        return BatchedProblems([(A, P) for A, P, _ in triples] + [(Pt, i) for i, (_, _, Pt) in enumerate(triples)])
+
+    def galerkin(self, triples, arena: torch.Tensor | None = None, stream=None, problems=None):
         """G_i = P_i^T (A_i P_i) for triples (A_i, P_i, Pt_i) in one batched
         call (stage 1: A_i P_i, stage 2: Pt_i times stage 1's output).  Grows
-        the arena when it is too small.  Returns (G list, AP list, arena)."""
+        the arena when it is too small.  `problems` may be
+        galerkin_problems(triples), made once.  Returns (G list, AP list,
+        arena)."""
         n = len(triples)
-        probs = [(A, P) for A, P, _ in triples] + [(Pt, i) for i, (_, _, Pt) in enumerate(triples)]
+        probs = problems if problems is not None else self.galerkin_problems(triples)
         if arena is None:
             est = sum(8 * (A.rows + 1) + 8 * (Pt.rows + 1) + 12 * 27 * A.rows + 8192 for A, _, Pt in triples)
             arena = torch.empty(est, dtype=torch.uint8, device=triples[0][0].rpt.device)

@@ -1055,7 +1055,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     const size_t o_tile = align_up(o_rows + 4 * (size_t)max_rows, a);
     const size_t o_S = align_up(o_tile + 8 * (size_t)((max_rows + kScanTile - 1) / kScanTile + 1), a);
     const size_t o_roff = align_up(o_S + 8 * (size_t)(max_rows + 1), a);
-    const size_t o_tab = align_up(o_roff + 8 * roff_total, a);
+    const size_t o_tab = align_up(o_roff + 16 * roff_total, a);  // row offsets, then chunk offsets
     const size_t o_stat = align_up(o_tab + sizeof(BatchProb) * (size_t)count, a);
     const size_t o_ctl = align_up(o_stat + sizeof(BatchStatus), a);
     // the window kernels' inputs: the problem of every row, list descriptors
@@ -1080,11 +1080,11 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
                                  hipHostMallocDefault));
         h->b_host_n = (size_t)count;
     }
-    if (roff_total > h->b_row_off_n) {
+    if (2 * roff_total > h->b_row_off_n) {
         if (h->b_row_off_host) HIP_TRY(h, hipHostFree(h->b_row_off_host));
         h->b_row_off_host = nullptr;
-        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_row_off_host), 8 * roff_total, hipHostMallocDefault));
-        h->b_row_off_n = roff_total;
+        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_row_off_host), 16 * roff_total, hipHostMallocDefault));
+        h->b_row_off_n = 2 * roff_total;
     }
     if (!h->b_status_host)
         HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_status_host), sizeof(BatchStatus), hipHostMallocDefault));
@@ -1106,8 +1106,10 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     BatchStatus *d_stat = reinterpret_cast<BatchStatus *>(base + o_stat);
     char *arena_c = static_cast<char *>(arena);
     // host table
-    for (auto &x : st) {
-        int64_t ro = 0, eo = 0;
+    std::vector<int64_t> stage_chunks(st.size(), 0);
+    for (size_t si = 0; si < st.size(); ++si) {
+        auto &x = st[si];
+        int64_t ro = 0, eo = 0, co = 0;
         for (int i = 0; i < x.n; ++i) {
             const int p = x.first + i;
             const spg_problem &q = probs[p];
@@ -1129,13 +1131,17 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
             b.b_from = q.b_from;
             b.ent_off = eo;
             h->b_row_off_host[x.roff + (size_t)i] = ro;
+            h->b_row_off_host[roff_total + x.roff + (size_t)i] = co;
             ro += q.A.rows;
             eo += q.A.nnz;
+            co += (q.A.rows + kBatchChunkRows - 1) / kBatchChunkRows;
         }
         h->b_row_off_host[x.roff + (size_t)x.n] = ro;
+        h->b_row_off_host[roff_total + x.roff + (size_t)x.n] = co;
+        stage_chunks[si] = co;
     }
     HIP_TRY(h, hipMemcpyAsync(d_tab, h->b_host, sizeof(BatchProb) * (size_t)count, hipMemcpyHostToDevice, s));
-    HIP_TRY(h, hipMemcpyAsync(d_roff, h->b_row_off_host, 8 * roff_total, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(d_roff, h->b_row_off_host, 16 * roff_total, hipMemcpyHostToDevice, s));
     // graph signature: problems, arena, outputs, options
     std::vector<int64_t> sig;
     sig.push_back(count);
@@ -1164,7 +1170,8 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
         // lane windows as in the single product (their keys bound B's columns)
         const bool win = uses_windows(h->group_rows) && max_bcols < ((int64_t)1 << 26);
         const Thresholds th = thresholds(h, win, max_bcols <= ((int64_t)1 << 21));
-        for (auto &x : st) {
+        for (size_t si = 0; si < st.size(); ++si) {
+            const auto &x = st[si];
             if (e != hipSuccess) break;
             BatchStage bs;
             bs.all = d_tab;
@@ -1172,6 +1179,8 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
             bs.first = x.first;
             bs.nprob = x.n;
             bs.row_off = d_roff + x.roff;
+            bs.chunk_off = d_roff + roff_total + x.roff;
+            bs.chunks = stage_chunks[si];
             bs.rows = x.rows;
             bs.a_rpt_bytes = x.arb;
             bs.b_rpt_bytes = x.brb;

@@ -177,11 +177,15 @@ struct BatchStatus {
     int64_t nprod;
 };
 
+constexpr int kBatchChunkRows = 64;  // rows per wavefront pass of the batched analysis (one wavefront)
+
 struct BatchStage {
     BatchProb *all;      // every problem of the call
     BatchProb *tab;      // this stage's problems (all + first)
     int first, nprob;
     int64_t *row_off;    // nprob + 1 entries
+    int64_t *chunk_off;  // nprob + 1 entries: first chunk of 64 rows of every problem
+    int64_t chunks;      // chunks of the stage
     int64_t rows;        // rows of the stage
     int a_rpt_bytes, b_rpt_bytes;
     int link;            // B operands come from earlier problems

@@ -2780,16 +2780,25 @@ __device__ __forceinline__ int find_prob(const ProbLookup &lk, const int64_t *ro
     return upper_bound(o, np, g) - 1;
 }
 
+// Row analysis of a batched stage, as in the single product: a wavefront
+// takes 64 consecutive rows of one problem (chunk c of the stage; the
+// problems' chunk ranges are consecutive) and walks their entries, one
+// contiguous range of that problem's A, coalesced.  Besides the per-row
+// products, class and list descriptors it records every row's problem.
 template <typename IA, typename IB>
-__global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const int64_t *row_off, int np,
-                                                    int64_t R, Thresholds th, int64_t *row_nprod,
+__global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const int64_t *chunk_off, int np,
+                                                    int64_t nchunks, Thresholds th, int64_t *row_nprod,
                                                     uint8_t *row_class, int32_t *row_size, Ctl *ctl,
                                                     BatchStatus *st, int32_t *row_prob, IB *ent_bs,
                                                     int32_t *ent_len) {
+    constexpr int kW = 256 / kWave;
     __shared__ ProbLookup lk;
     __shared__ int64_t s_count[kNumClasses];
     __shared__ int64_t s_nprod;
-    load_lookup(lk, row_off, np);
+    __shared__ int64_t s_start[kW][kWave + 1];
+    __shared__ unsigned long long s_np[kW][kWave];
+    __shared__ int32_t s_mx[kW][kWave];
+    load_lookup(lk, chunk_off, np);
     if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nprod = 0;
     __syncthreads();
@@ -2797,36 +2806,59 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
     int64_t my_nprod = 0;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R; g += (int64_t)gridDim.x * blockDim.x) {
-        const int p = find_prob(lk, row_off, np, g);
-        const BatchProb &pr = tab[p];
-        const int64_t r = g - pr.row_off;
-        const int64_t a0 = ld_rpt<IA>(pr.a_rpt, r), a1 = ld_rpt<IA>(pr.a_rpt, r + 1);
-        int64_t nprod = 0, mx = 0;
-        for (int64_t q = a0; q < a1; ++q) {
-            // the list descriptors of the window kernels, as in the single product
-            const int32_t k = pr.a_col[q];
-            const IB bs = reinterpret_cast<const IB *>(pr.b_rpt)[k];
-            const int64_t n = (int64_t)reinterpret_cast<const IB *>(pr.b_rpt)[k + 1] - (int64_t)bs;
-            ent_bs[pr.ent_off + q] = bs;
-            ent_len[pr.ent_off + q] = (int32_t)n;
-            nprod += n;
-            mx = n > mx ? n : mx;
-        }
-        const int cls = classify(a1 - a0, nprod, mx, th);
-        const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx)
-                       : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, nprod)
-                                                              : 0;
-        row_nprod[g] = nprod;
-        row_class[g] = (uint8_t)(cls | (sw << kClassBits));
-        row_prob[g] = p;
-        if (cls == kClassEmpty || cls == kClassHeavy) row_size[g] = 0;  // heavy rows: unsupported, flagged
-        if (cls == kClassCopy) row_size[g] = (int32_t)nprod;
-#pragma unroll
-        for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
-        my_nprod += nprod;
-    }
     const int lane = lane_id();
+    const int w = threadIdx.x / kWave;
+    const int64_t *coff = np < kMaxLdsProbs ? lk.off : chunk_off;
+    for (int64_t c = (int64_t)blockIdx.x * kW + w; c < nchunks; c += (int64_t)gridDim.x * kW) {
+        const int p = find_prob(lk, chunk_off, np, c);
+        const BatchProb &pr = tab[p];
+        static_assert(kBatchChunkRows == kWave, "a chunk is one wavefront's rows");
+        const int64_t r0 = (c - coff[p]) * kWave;
+        const int nrows = pr.rows - r0 < kWave ? (int)(pr.rows - r0) : kWave;
+        const int64_t i = r0 + lane;
+        const bool in = lane < nrows;
+        int64_t a0 = 0, a1 = 0;
+        if (in) {
+            a0 = ld_rpt<IA>(pr.a_rpt, i);
+            a1 = ld_rpt<IA>(pr.a_rpt, i + 1);
+            s_start[w][lane] = a0;
+            s_np[w][lane] = 0ull;
+            s_mx[w][lane] = 0;
+        }
+        if (lane == nrows - 1) s_start[w][nrows] = a1;
+        wave_sync();
+        const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
+        const IB *b_rpt = reinterpret_cast<const IB *>(pr.b_rpt);
+        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+            const int32_t k = pr.a_col[e];
+            const IB bs = b_rpt[k];
+            const int64_t n = (int64_t)b_rpt[k + 1] - (int64_t)bs;
+            ent_bs[pr.ent_off + e] = bs;
+            ent_len[pr.ent_off + e] = (int32_t)n;
+            const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
+            atomicAdd(&s_np[w][r], (unsigned long long)n);
+            atomicMax(&s_mx[w][r], (int32_t)n);
+        }
+        wave_sync();
+        if (in) {
+            const int64_t g = pr.row_off + i;
+            const int64_t nprod = (int64_t)s_np[w][lane];
+            const int mx = s_mx[w][lane];
+            const int cls = classify(a1 - a0, nprod, mx, th);
+            const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx)
+                           : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, nprod)
+                                                                  : 0;
+            row_nprod[g] = nprod;
+            row_class[g] = (uint8_t)(cls | (sw << kClassBits));
+            row_prob[g] = p;
+            if (cls == kClassEmpty || cls == kClassHeavy) row_size[g] = 0;  // heavy rows: unsupported, flagged
+            if (cls == kClassCopy) row_size[g] = (int32_t)nprod;
+#pragma unroll
+            for (int q = 0; q < kNumClasses; ++q) my_count[q] += (cls == q);
+            my_nprod += nprod;
+        }
+        wave_sync();
+    }
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) {
         const int64_t t = wave_sum(my_count[c]);
@@ -3084,6 +3116,8 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
     const int64_t *ro = bs.row_off;
     BatchProb *tab = bs.tab;
     const unsigned ga = (unsigned)(R > 0 ? ((R + 255) / 256 < 2048 ? (R + 255) / 256 : 2048) : 1);
+    // the analysis: four chunks of 64 rows per workgroup pass
+    const unsigned gc = (unsigned)(bs.chunks > 0 ? ((bs.chunks + 3) / 4 < 2048 ? (bs.chunks + 3) / 4 : 2048) : 1);
     hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, s, ws.ctl);
     if (bs.link) hipLaunchKernelGGL(k_b_link, dim3(1), dim3(256), 0, s, bs.all, bs.first, np);
     auto grid_for = [&](int per_cu, int waves_per_wg) {
@@ -3093,7 +3127,8 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
     };
 #define BRM_B_ALL(IA, IB)                                                                                       \
     do {                                                                                                        \
-        hipLaunchKernelGGL((k_b_analysis<IA, IB>), dim3(ga), dim3(256), 0, s, tab, ro, np, R, th, ws.row_nprod, \
+        hipLaunchKernelGGL((k_b_analysis<IA, IB>), dim3(gc), dim3(256), 0, s, tab, bs.chunk_off, np, bs.chunks,  \
+                           th, ws.row_nprod,                                                                    \
                            ws.row_class, ws.row_size, ws.ctl, bs.status, ws.row_prob,                           \
                            static_cast<IB *>(ws.ent_bs), ws.ent_len);                                           \
         hipLaunchKernelGGL(k_bin, dim3(ga), dim3(256), 0, s, R, nullptr, ws.row_class, ws.class_rows, ws.ctl); \
