@@ -284,6 +284,55 @@ def learned_rmat21(h, reps=1):
             "upper_bound_bitwise_equal_to_plain": bool(same_u), "blocks": per_block}
 
 
+def accumulator_extra(workloads=("er8_2e20", "stencil27_128", "rmat_s18"), reps=5):
+    """The numeric pass with BRMerge against the hash-accumulator comparator
+    (rows of at most 4096 products in an LDS hash table; heavier rows keep
+    BRMerge), after the same symbolic pass, on workloads of different
+    compression ratios."""
+    import torch
+    import paper_2206_06611_amd as brm
+
+    out = {}
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    for name in workloads:
+        progress(f"accumulators on {name}")
+        A = build_input(name)
+        dA = brm.DeviceCSR.from_host(A, device=dev)
+        h = brm.Handle(0)
+        res = {}
+        cols = {}
+        for acc, label in ((brm.ACC_BRMERGE, "brmerge"), (brm.ACC_HASH, "hash")):
+            h.set_option(brm.OPT_ACCUMULATOR, acc)
+            c_rpt, nnz = h.symbolic(dA, dA)
+            c_col = torch.empty(nnz, dtype=torch.int32, device=dev)
+            c_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+            h.numeric(dA, dA, c_rpt, c_col, c_val)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            torch.cuda.synchronize()
+            for a, b in ev:
+                a.record(stream)
+                h.numeric(dA, dA, c_rpt, c_col, c_val)
+                b.record(stream)
+            torch.cuda.synchronize()
+            res[label] = sum(a.elapsed_time(b) for a, b in ev) / reps
+            cols[label] = (c_col, c_val)
+            if h.stat(brm.STAT_DEVICE_ERR):
+                raise RuntimeError(f"device error with accumulator {label} on {name}")
+        nprod = h.stat(brm.STAT_NPROD)
+        same_cols = torch.equal(cols["brmerge"][0], cols["hash"][0])
+        vb, vh = cols["brmerge"][1], cols["hash"][1]
+        rel = float(((vb - vh).abs() / vb.abs().clamp_min(1e-300)).max()) if vb.numel() else 0.0
+        out[name] = {"compression_ratio": round(nprod / nnz, 4) if nnz else None,
+                     "numeric_ms_brmerge": round(res["brmerge"], 4), "numeric_ms_hash": round(res["hash"], 4),
+                     "brmerge_speedup_over_hash": round(res["hash"] / res["brmerge"], 3),
+                     "same_columns": bool(same_cols), "max_rel_value_difference": rel}
+        h.close()
+        del dA, cols
+        torch.cuda.empty_cache()
+    return out
+
+
 def learned_extra(reps=5, eval_workloads=("stencil27_128", "er8_2e20"), rmat21=True):
     """Size predictor trained on the symbolic counts of the 64^2 Laplacian,
     ER-8 2^20 (seed 2) and R-MAT scale 20 (seed 3), evaluated against the
@@ -457,6 +506,9 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = batched_extra()
         progress("batched Galerkin products done")
+        torch.cuda.empty_cache()
+        out["accumulators"] = accumulator_extra()
+        progress("accumulator comparison done")
         torch.cuda.empty_cache()
         out["learned"] = learned_extra()
         progress("learned allocation done")

@@ -112,6 +112,7 @@ typedef enum {
     SPG_OPT_ALLOC = 10,          /* SPG_ALLOC_PRECISE (default), SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER */
     SPG_OPT_LEARNED_FORCE = 11,  /* testing only: 1 sizes every predicted row at its lower bound
                                     (the longest list), so that most rows take the fallback */
+    SPG_OPT_ACCUMULATOR = 13,    /* SPG_ACC_BRMERGE (default) or SPG_ACC_HASH: see below */
     SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
                                     1 (default) one row per wavefront, merged in registers; the
                                     class then holds only rows whose lists fit power-of-two lane
@@ -128,12 +129,27 @@ typedef enum {
 enum {
     SPG_ALLOC_PRECISE = 0, /* symbolic count, prefix sum, numeric straight into C */
     SPG_ALLOC_LEARNED = 1, /* predicted sizes, numeric into predicted slots, exact fallback, compaction */
-    SPG_ALLOC_UPPER = 2    /* the upper-bound method (Section II-B.1, the "BRMerge-Upper" library of
+    SPG_ALLOC_UPPER = 2    /* the upper-bound method (Section II-B.2, the "BRMerge-Upper" library of
                               Section III-D.1): every row gets a slot of nprod_i entries, the numeric
                               pass runs into the slots inside spgemm_symbolic (no symbolic count), and
                               spgemm_numeric copies the rows into C.  The slots take 12 bytes per
                               product of device memory (SPG_ERR_NOMEM when they do not fit: cut A
                               into row blocks with spgemm_row_products) */
+};
+
+/* Accumulators of the numeric pass of the precise method (SPG_OPT_ACCUMULATOR).
+ * SPG_ACC_HASH is a comparator, not the paper's method: every row of at
+ * most 4096 products adds its products into a hash table in LDS (keyed by
+ * column, linear probing, atomic additions) and places each column by its
+ * rank, the hash-based accumulation that the paper describes among the
+ * prior methods (Section II-B.1) and compares BRMerge with (Section IV-B);
+ * rows with more products keep the
+ * BRMerge path.  Its values are within rounding of the definition but not
+ * equal to the merge tree's, and their last bits may change between runs.
+ * The learned and upper-bound allocations always use BRMerge. */
+enum {
+    SPG_ACC_BRMERGE = 0,
+    SPG_ACC_HASH = 1
 };
 
 /* Setting any option voids the plan of the last spgemm_symbolic: a

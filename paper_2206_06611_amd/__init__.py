@@ -42,6 +42,9 @@ OPT_GRID_WAVES = 9
 OPT_ALLOC = 10
 OPT_LEARNED_FORCE = 11
 OPT_GROUP_ROWS = 12
+OPT_ACCUMULATOR = 13
+ACC_BRMERGE = 0
+ACC_HASH = 1
 ALLOC_PRECISE = 0
 ALLOC_LEARNED = 1
 ALLOC_UPPER = 2

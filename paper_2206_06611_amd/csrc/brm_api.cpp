@@ -52,6 +52,7 @@ struct spg_handle_s {
     int64_t heavy_batches = 0;
     // learned allocation
     int64_t alloc = 0;          // 0 precise, 1 learned, 2 upper bound
+    int64_t accumulator = 0;    // 0 BRMerge, 1 hash table (comparator)
     int64_t learned_force = 0;  // testing: 1 = every predicted row at its lower bound
     bool plan_learned = false;
     void *lw_mem = nullptr;     // per-row learned workspace
@@ -459,6 +460,11 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
                 return fail(h, SPG_ERR_ARG, "force class must be -1 or 2..7");
             h->force = value;
             break;
+        case SPG_OPT_ACCUMULATOR:
+            if (value != SPG_ACC_BRMERGE && value != SPG_ACC_HASH)
+                return fail(h, SPG_ERR_ARG, "accumulator must be SPG_ACC_BRMERGE or SPG_ACC_HASH");
+            h->accumulator = value;
+            break;
         case SPG_OPT_HEAVY_LDS_MAX:
             if (value < 64 || value > kCapBlock) return fail(h, SPG_ERR_ARG, "heavy LDS max out of range");
             h->heavy_lds_max = value;
@@ -506,6 +512,7 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_ALLOC: *value = h->alloc; break;
         case SPG_OPT_GROUP_ROWS: *value = h->group_rows; break;
         case SPG_OPT_LEARNED_FORCE: *value = h->learned_force; break;
+        case SPG_OPT_ACCUMULATOR: *value = h->accumulator; break;
         default: return fail(h, SPG_ERR_ARG, "unknown option %d", key);
     }
     return SPG_OK;
@@ -753,6 +760,10 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     }
     for (int cls : kLightClasses) {
         if (h->counts[cls] == 0) continue;
+        if (h->accumulator == SPG_ACC_HASH && cls != kClassCopy) {
+            HIP_TRY(h, launch_numeric_hash(a, b, ws, cls, h->num_cu, c_rpt, c_col, c_val, s));
+            continue;
+        }
         HIP_TRY(h, launch_numeric(a, b, ws, cls, persistent_grid(h, cls, h->counts[cls], h->plan_group_rows), c_rpt,
                                   c_col, c_val, exact, s, h->plan_group_rows));
     }

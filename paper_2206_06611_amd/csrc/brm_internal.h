@@ -128,6 +128,9 @@ struct NumOut {
 hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                           int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val,
                           const NumOut &no, hipStream_t s, int group_rows);
+// the hash-accumulator comparator for one light class (exact slots)
+hipError_t launch_numeric_hash(const CsrView &A, const CsrView &B, const Workspace &ws, int cls, int num_cu,
+                               const int64_t *c_rpt, int32_t *c_col, double *c_val, hipStream_t s);
 
 // Heavy rows: one 1024-thread workgroup per row, spill buffers in HBM.
 struct HeavyArgs {

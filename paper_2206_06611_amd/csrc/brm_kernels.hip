@@ -452,7 +452,7 @@ hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-// the upper bound of Section II-B.1: a row of C has at most as many entries
+// the upper bound of Section II-B.2: a row of C has at most as many entries
 // as it has products
 __global__ __launch_bounds__(256) void k_upper_sizes(int64_t M, const int64_t *row_nprod, int32_t *size) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
@@ -2248,6 +2248,165 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_group(int cls, const void *a_r
         if (tid < n) finish_row(no, ctl, s.row[tid], s.seg_len[tid], s.seg[tid].out_cap, false);
         Team<T>::sync();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Hash accumulator (a comparator for the BRMerge kernels, not the paper's
+// method): a row's products are added into an LDS hash table keyed by
+// column (open addressing, linear probing, atomic compare-and-swap of the
+// key and atomic addition of the value), the occupied slots are packed and
+// each entry's place in the row is its rank among the row's columns.  Sums
+// are formed in whatever order the atomics land: within rounding of the
+// definition, not equal to the merge tree's bits, and not reproducible
+// between runs.  Rows must hold at most TS / 2 products (the table then
+// stays at most half full) and their exact sizes come from the symbolic
+// pass.
+// ---------------------------------------------------------------------------
+template <int T, int TS>
+struct HashLds {
+    int32_t key[TS];
+    double val[TS];
+    int32_t off[TS / 2 + 1];  // list offsets of the row's products
+    int32_t n;                // packed entries
+};
+
+template <int T, int TEAMS, int TS, typename IA, typename IB>
+__global__ __launch_bounds__(T *TEAMS) void k_num_hash(int cls, const void *a_rpt, Lists<IB> lists,
+                                                       const double *a_val, const int32_t *b_col,
+                                                       const double *b_val, const int32_t *class_rows,
+                                                       const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl) {
+    __shared__ HashLds<T, TS> lds[TEAMS];
+    __shared__ int32_t scan[TEAMS][Team<T>::kWaves + 1];
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    HashLds<T, TS> &s = lds[team];
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count; idx += (int64_t)gridDim.x * TEAMS) {
+        const int64_t row = class_rows[start + idx];
+        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+        const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
+        const int64_t cs = c_rpt[row];
+        const int cap = (int)(c_rpt[row + 1] - cs);
+        if (2 * (int64_t)cap > TS) {  // row pointers that are not the symbolic pass's
+            if (tid == 0)
+                atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+            continue;
+        }
+        // a table of at least twice the row's size, a power of two
+        int lg = 1;
+        while ((1 << lg) < 2 * cap) ++lg;
+        const int tsz = 1 << lg;
+        for (int i = tid; i < tsz; i += T) {
+            s.key[i] = -1;
+            s.val[i] = 0.0;
+        }
+        // list offsets
+        int carry = 0;
+        for (int lb = 0; lb < L; lb += T) {
+            const int t = lb + tid;
+            int64_t bs = 0;
+            int ln = 0;
+            if (t < L) lists.get(a0 + t, bs, ln);
+            int tot;
+            const int ex = Team<T>::excl_scan(ln, &tot, scan[team], tid);
+            if (t < L) s.off[t] = carry + ex;
+            carry += tot;
+        }
+        const int nprod = carry;
+        if (tid == 0) s.off[L] = nprod;
+        Team<T>::sync();
+        // multiplying phase straight into the table
+        bool lost = false;
+        for (int p = tid; p < nprod; p += T) {
+            const int t = upper_bound(s.off, L + 1, p) - 1;
+            int64_t bs;
+            int ln;
+            lists.get(a0 + t, bs, ln);
+            const int64_t q = bs + (p - s.off[t]);
+            const int32_t c = b_col[q];
+            const double v = a_val[a0 + t] * b_val[q];  // one rounded product
+            uint32_t h = ((uint32_t)c * 2654435761u) >> (32 - lg);
+            int probes = 0;
+            for (;;) {
+                const int k = atomicCAS(&s.key[h], -1, c);
+                if (k == -1 || k == c) {
+                    atomicAdd(&s.val[h], v);
+                    break;
+                }
+                h = (h + 1) & (uint32_t)(tsz - 1);
+                if (++probes == tsz) {  // only when the symbolic size is wrong
+                    lost = true;
+                    break;
+                }
+            }
+        }
+        if (lost) atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+        Team<T>::sync();
+        // pack the occupied slots to the front (slots -> registers -> front)
+        constexpr int PER = TS / T;
+        int32_t kc[PER];
+        double kv[PER];
+        int mine = 0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int i = tid * PER + e;
+            kc[e] = i < tsz ? s.key[i] : -1;
+            kv[e] = i < tsz ? s.val[i] : 0.0;
+            mine += kc[e] >= 0;
+        }
+        int n;
+        const int at = Team<T>::excl_scan(mine, &n, scan[team], tid);
+        Team<T>::sync();
+        int w = at;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            if (kc[e] >= 0) {
+                s.key[w] = kc[e];
+                s.val[w] = kv[e];
+                ++w;
+            }
+        }
+        Team<T>::sync();
+        // place = rank among the row's columns
+        for (int i = tid; i < n; i += T) {
+            const int32_t c = s.key[i];
+            int r = 0;
+            for (int j = 0; j < n; ++j) r += s.key[j] < c;
+            if (r < cap) {
+                c_col[cs + r] = c;
+                c_val[cs + r] = s.val[i];
+            }
+        }
+        if (tid == 0 && n != cap)
+            atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
+        Team<T>::sync();
+    }
+}
+
+hipError_t launch_numeric_hash(const CsrView &A, const CsrView &B, const Workspace &ws, int cls, int num_cu,
+                               const int64_t *c_rpt, int32_t *c_col, double *c_val, hipStream_t s) {
+#define BRM_HASH(T, TEAMS, TS, PER_CU, IA, IB)                                                                   \
+    hipLaunchKernelGGL((k_num_hash<T, TEAMS, TS, IA, IB>), dim3(num_cu * PER_CU), dim3(T * TEAMS), 0, s, cls,   \
+                       A.rpt, ws_lists<IB>(A, B, ws), A.val, B.col, B.val, ws.class_rows, c_rpt, c_col, c_val, \
+                       ws.ctl)
+#define BRM_HASH_ALL(T, TEAMS, TS, PER_CU)                                                     \
+    do {                                                                                       \
+        if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_HASH(T, TEAMS, TS, PER_CU, int32_t, int32_t); \
+        else if (A.rpt_bytes == 4) BRM_HASH(T, TEAMS, TS, PER_CU, int32_t, int64_t);           \
+        else if (B.rpt_bytes == 4) BRM_HASH(T, TEAMS, TS, PER_CU, int64_t, int32_t);           \
+        else BRM_HASH(T, TEAMS, TS, PER_CU, int64_t, int64_t);                                 \
+    } while (0)
+    switch (cls) {
+        case kClassWaveSmall: BRM_HASH_ALL(64, 4, 2 * kCapWaveSmall, 8); break;
+        case kClassWave: BRM_HASH_ALL(64, 4, 2 * kCapWave, 4); break;
+        case kClassMulti:  // at most 1024 products
+        case kClassGroup: BRM_HASH_ALL(256, 1, 2 * kCapGroup, 4); break;
+        case kClassBlock: BRM_HASH_ALL(1024, 1, 2 * kCapBlock, 1); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef BRM_HASH_ALL
+#undef BRM_HASH
+    return hipGetLastError();
 }
 
 hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,

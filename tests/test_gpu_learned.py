@@ -178,3 +178,54 @@ def test_learned_heavy_rows(handle):
     handle.set_option(brm.OPT_LEARNED_FORCE, 0)
     C = handle_spgemm_again(handle, A)
     assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+def _slot_stats(h, A):
+    """Learned-mode product of A*A: (slot entries, fallback rows, predicted
+    rows, nnz), the product checked bitwise against the precise path."""
+    d = dev(A)
+    h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+    base = to_host(h.spgemm(d, d))
+    h.set_option(brm.OPT_ALLOC, brm.ALLOC_LEARNED)
+    C = h.spgemm(d, d)
+    torch.cuda.synchronize()
+    stats = (h.stat(brm.STAT_PRED_TOTAL), h.stat(brm.STAT_OVERFLOW_ROWS), h.stat(brm.STAT_PREDICTED_ROWS), C.nnz)
+    got = to_host(C)
+    for x, y in zip(base, got):
+        assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                              y.view(np.int64) if y.dtype == np.float64 else y)
+    h.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
+    return stats
+
+
+def test_trained_network_gain(handle):
+    # What training buys on held-out inputs of the training families, against
+    # the same allocation without a trained network: the untrained network
+    # (same initialisation, normalisation and calibrated margin, no Adam
+    # steps), the upper bound (every slot nprod_i, no fallback) and the lower
+    # bound (every slot the longest list, most rows fall back).
+    feats, targets = training_set(handle)
+    held_out = [synth.rmat(13, 16, 71), synth.erdos_renyi_rows(1 << 14, 8, 72), synth.laplacian_2d_5pt(48)]
+    learned.train(handle, feats, targets, seed=4, epochs=0)
+    untrained = [_slot_stats(handle, A) for A in held_out]
+    learned.train(handle, feats, targets, seed=4, epochs=6)
+    trained = [_slot_stats(handle, A) for A in held_out]
+    handle.set_option(brm.OPT_LEARNED_FORCE, 1)
+    lower = [_slot_stats(handle, A) for A in held_out]
+    handle.set_option(brm.OPT_LEARNED_FORCE, 0)
+    nprod = [int(oracle.row_nprod(A, A).sum()) for A in held_out]
+    for A, t, u, lo, npd in zip(held_out, trained, untrained, lower, nprod):
+        slots, ovf, pred, nnz = t
+        print(f"rows {A.rows}: trained slots/nnz {slots / nnz:.3f} fallback {ovf}/{pred}; untrained slots/nnz "
+              f"{u[0] / nnz:.3f} fallback {u[1]}; upper bound slots/nnz {npd / nnz:.3f}; lower bound fallback {lo[1]}",
+              flush=True)
+    for A, t, u, lo, npd in zip(held_out, trained, untrained, lower, nprod):
+        slots, ovf, pred, nnz = t
+        assert slots <= npd and ovf <= 0.1 * pred  # bounded fallback on held-out rows
+        assert slots <= u[0] or ovf < u[1]  # no worse than the untrained network
+        assert ovf <= lo[1]
+    # summed over the held-out inputs: less memory than the upper bound, fewer
+    # fallback rows than the lower bound, less memory than the untrained net
+    assert sum(t[0] for t in trained) < 0.9 * sum(nprod)
+    assert sum(t[1] for t in trained) < 0.2 * sum(lo[1] for lo in lower)
+    assert sum(t[0] for t in trained) < sum(u[0] for u in untrained)
