@@ -413,3 +413,12 @@ def test_multi_register_windows_column_limit(handle):
         assert (handle.class_rows()["multi"] > 0) == want
         assert_matches_oracle(C, refw, oracle.brmerge(A, Bw))
     assert ref.nnz > 0
+
+
+def test_multi_register_windows_int64_row_pointers(handle):
+    # the multi-register class with 64-bit row pointers in A and B
+    A, B = _multi_window_rows(34, M=150)
+    ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+    C = run(handle, A, B, rpt_dtype=torch.int64)
+    assert handle.class_rows()["multi"] > 0
+    assert_matches_oracle(C, ref, model)
