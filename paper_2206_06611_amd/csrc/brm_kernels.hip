@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "brm_device.h"
 #include "brm_internal.h"
 
@@ -1587,8 +1589,10 @@ __device__ __forceinline__ bool key_rounds(uint32_t &k, double &v, int W0, int T
 }
 
 // Symbolic use: the same merges on bare columns (empty = all ones), equal
-// columns left in place; the distinct columns are counted at the end.
-__device__ __forceinline__ int count_distinct_merged(uint32_t k, int W0, int T, int lane) {
+// columns left in place; the lanes holding the first entry of a distinct
+// column are returned as a mask.  A second row may start at lane `seg`
+// (kWave: one row).
+__device__ __forceinline__ uint64_t distinct_merged(uint32_t k, int W0, int T, int lane, int seg) {
     for (int W = W0; W < T; W <<= 1) {
         switch (W) {
             case 1: key_merge<1>(k, lane); break;
@@ -1600,7 +1604,7 @@ __device__ __forceinline__ int count_distinct_merged(uint32_t k, int W0, int T, 
         }
     }
     const uint32_t pk = lane_prev(k);
-    return __popcll(wave_ballot(k != ~0u && (lane == 0 || pk != k)));
+    return wave_ballot(k != ~0u && (lane == 0 || lane == seg || pk != k));
 }
 
 // 64-bit value of lane j (j wavefront-uniform)
@@ -1648,8 +1652,10 @@ __device__ __forceinline__ T load_opaque(const T *p) {
 // j+1 and the list descriptors of row j+2 are in flight.  Every lane issues
 // every load of a stage on every iteration (masked lanes read the sentinels
 // above), so the number of memory operations in flight does not depend on
-// the path and the waits stay partial.  VALUES = false counts row sizes;
-// HASH then selects counting by LDS hash instead of window merges.
+// the path and the waits stay partial.  Rows 2i and 2i+1 of a chunk whose
+// windows both fit 32 lanes are merged together, one in each half of the
+// wavefront.  VALUES = false counts row sizes; HASH then selects counting by
+// LDS hash instead of window merges (one row at a time).
 template <bool VALUES, bool HASH, typename IA, typename IB, bool BATCH = false>
 __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
                                            const int32_t *b_col, const double *b_val, const uint8_t *row_class,
@@ -1663,6 +1669,7 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
     const int64_t nchunks = (count + kWave - 1) / kWave;
     const IB *ent_bs = static_cast<const IB *>(lists.ent_bs);
     const int32_t *ent_len = lists.ent_len;
+    constexpr int kHalf = kWave / 2;
     for (int64_t ch = first; ch < nchunks; ch += stride) {
         const int64_t base = ch * kWave;
         const int n = (int)(count - base < kWave ? count - base : kWave);
@@ -1698,101 +1705,24 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                 m_cap = (int)(crpt[r + 1] - m_cs);  // a row's size fits 31 bits
             }
         }
-        auto a_val_of = [&](int j) -> const double * {
-            if constexpr (BATCH) return reinterpret_cast<const double *>(lane_value(m_aval, j));
-            else return a_val;
-        };
-        auto b_col_of = [&](int j) -> const int32_t * {
-            if constexpr (BATCH) return reinterpret_cast<const int32_t *>(lane_value(m_bcol, j));
-            else return b_col;
-        };
-        auto b_val_of = [&](int j) -> const double * {
-            if constexpr (BATCH) return reinterpret_cast<const double *>(lane_value(m_bval, j));
-            else return b_val;
-        };
-        // list descriptors of row j: lane t < L holds list t (empty beyond)
-        auto load_lists = [&](int j, IB &bs, int &ln, double &av) {
-            const int jj = j < n ? j : 0;
-            const int64_t p = lane_value(m_a0, jj) + lane;
-            const int64_t pe = BATCH ? lane_value(m_eo, jj) + p : p;
-            const bool ok = j < n && lane < lane_value(m_L, jj);
-            bs = load_opaque(ok ? ent_bs + pe : reinterpret_cast<const IB *>(&g_zeros[0]));
-            ln = load_opaque(ok ? ent_len + pe : reinterpret_cast<const int32_t *>(&g_zeros[0]));
-            if constexpr (VALUES) {
-                const double *av_p = a_val_of(jj);
-                av = load_opaque(ok ? av_p + p : reinterpret_cast<const double *>(&g_zeros[0]));
-            }
-        };
-        // multiplying phase of row j into the lane windows (the products are
-        // formed where the row is consumed): lane t holds entry t mod W0 of
-        // list t / W0
-        auto gather = [&](int j, IB bs, int ln, double av, int32_t &c, double &bv, double &lav) {
-            const int jj = j < n ? j : 0;
-            const int L = j < n ? lane_value(m_L, jj) : 0;
-            const int sw = lane_value(m_sw, jj);
-            const int li = lane >> sw, o = lane & ((1 << sw) - 1);
-            // every shuffle with all lanes active
-            const int64_t lbs = __shfl((int64_t)bs, li, kWave);
-            const int lln = __shfl(ln, li, kWave);
-            lav = 0.0;
-            if constexpr (VALUES) lav = __shfl(av, li, kWave);
-            const bool ok = li < L && o < lln;
-            const int32_t *bc = b_col_of(jj);
-            c = load_opaque(ok ? bc + (lbs + o) : &g_empty_col[0]);
-            bv = 0.0;
-            if constexpr (VALUES) {
-                const double *bvp = b_val_of(jj);
-                bv = load_opaque(ok ? bvp + (lbs + o) : reinterpret_cast<const double *>(&g_zeros[0]));
-            }
-        };
-        struct ListStageRegs {  // list descriptors of one row
+        // When every row of the chunk fits 32 lanes, rows 2i and 2i+1 share
+        // one wavefront (the first in lanes 0..31, the second in lanes
+        // 32..63): the pipeline below runs over pairs (P) instead of rows.
+        // The two versions of the pipeline are separate code, so that the
+        // one-row version keeps its uniform per-row values and partial waits.
+        struct ListStageRegs {  // list descriptors of one item
             IB bs;
             int ln;
             double av;
         };
-        struct GatherRegs {  // B entries of one row in the lane windows
+        struct GatherRegs {  // B entries of one item in the lane windows
             int32_t c;
             double bv, av;
         };
         uint64_t ovf_mask = 0;  // rows of the chunk that overflowed their slot (slot mode)
-        // one pipeline step: lists of row j+2 -> lo, B entries of row j+1
-        // (from li) -> go, accumulating phase and write-out of row j (gi)
-        auto step = [&](int j, const ListStageRegs &li, ListStageRegs &lo, const GatherRegs &gi, GatherRegs &go) {
-            load_lists(j + 2, lo.bs, lo.ln, lo.av);
-            gather(j + 1, li.bs, li.ln, li.av, go.c, go.bv, go.av);
+        // the length of chunk row j is known: slot bookkeeping or the check
+        auto done = [&](int j, int len) {
             const int64_t row = lane_value(m_row, j);
-            const int sw = lane_value(m_sw, j);
-            const int T = lane_value(m_T, j);
-            int len;
-            if constexpr (!VALUES && HASH) {
-                tab[lane] = -1;
-                tab[lane + kWave] = -1;
-                wave_sync();
-                const int added = gi.c != kEmptyCol ? hash_insert<2 * kWave>(tab, gi.c) : 0;
-                len = __popcll(wave_ballot(added != 0));
-                wave_sync();
-            } else if constexpr (!VALUES) {
-                len = count_distinct_merged(gi.c == kEmptyCol ? ~0u : (uint32_t)gi.c, 1 << sw, T, lane);
-            } else {
-                uint32_t k = gi.c == kEmptyCol ? (kKeyEmpty | (uint32_t)lane)
-                                               : (((uint32_t)gi.c << kKeyLaneBits) | (uint32_t)lane);
-                double v = gi.av * gi.bv;  // one rounded product
-                if (!key_rounds(k, v, 1 << sw, T, lane, xk, xv)) v = __shfl(v, (int)(k & kKeyLaneMask), kWave);
-                const bool live = k < kKeyEmpty;
-                len = __popcll(wave_ballot(live));
-                const int64_t cs = lane_value(m_cs, j);
-                const int cap = lane_value(m_cap, j);
-                int32_t *cc = c_col;
-                double *cv = c_val;
-                if constexpr (BATCH) {
-                    cc = reinterpret_cast<int32_t *>(lane_value(m_ccol, j));
-                    cv = reinterpret_cast<double *>(lane_value(m_cval, j));
-                }
-                if (live && lane < cap) {
-                    cc[cs + lane] = (int32_t)(k >> kKeyLaneBits);
-                    cv[cs + lane] = v;
-                }
-            }
             if constexpr (VALUES) {
                 const int cap = lane_value(m_cap, j);
                 if (no.bound) {
@@ -1807,26 +1737,174 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                 if (lane == 0) row_size[row] = len;
             }
         };
-        ListStageRegs la, lb;
-        GatherRegs ga, gb;
-        la.av = lb.av = 0.0;
-        {
-            ListStageRegs l0;
-            l0.av = 0.0;
-            load_lists(0, l0.bs, l0.ln, l0.av);
-            load_lists(1, la.bs, la.ln, la.av);
-            gather(0, l0.bs, l0.ln, l0.av, ga.c, ga.bv, ga.av);
-        }
-        // unrolled by two: the register sets alternate roles, so no register
-        // with a load in flight is copied at the loop latch
-        for (int j = 0; j < n; j += 2) {
-            step(j, la, lb, ga, gb);
-            if (j + 1 < n) step(j + 1, lb, la, gb, ga);
-        }
-        // the stages loaded past the chunk's end are drained here, once
-        asm volatile("" ::"v"(ga.c), "v"(gb.c), "v"(la.ln), "v"(lb.ln), "v"(la.bs), "v"(lb.bs));
+        const bool all_small = !HASH && wave_ballot(lane < n && m_T > kHalf) == 0ull;
+        auto run = [&](auto pt) {
+            constexpr bool P = decltype(pt)::value;
+            const int nv = P ? (n + 1) / 2 : n;
+            // item v: row a (lanes 0..31 of a pair, all lanes of a single
+            // row) and row b (lanes 32..63 of a pair; -1 when missing)
+            auto item = [&](int v, int &a, int &b) {
+                const int vv = v < nv ? v : 0;
+                if constexpr (P) {
+                    a = 2 * vv;
+                    b = 2 * vv + 1 < n ? 2 * vv + 1 : -1;
+                } else {
+                    a = vv;
+                    b = -1;
+                }
+            };
+            // a per-row value for the lane's row; rows missing from a pair
+            // read row a's (every use of them is masked by their list count)
+            auto sel64 = [&](int64_t m, int a, int b) -> int64_t {
+                if constexpr (!P) {
+                    return lane_value(m, a);
+                } else {
+                    const int64_t xa = lane_value(m, a), xb = lane_value(m, b >= 0 ? b : a);
+                    return lane >= kHalf ? xb : xa;
+                }
+            };
+            auto sel32 = [&](int m, int a, int b) -> int {
+                if constexpr (!P) {
+                    return lane_value(m, a);
+                } else {
+                    const int xa = lane_value(m, a), xb = lane_value(m, b >= 0 ? b : a);
+                    return lane >= kHalf ? xb : xa;
+                }
+            };
+            auto lists_of = [&](int v, int a, int b) -> int {  // list count of the lane's row
+                if (v >= nv) return 0;
+                if constexpr (P) {
+                    if (b < 0 && lane >= kHalf) return 0;
+                }
+                return sel32(m_L, a, b);
+            };
+            // list descriptors of item v: lane t < L holds list t of its row
+            // (the lanes of each half for a pair)
+            auto load_lists = [&](int v, IB &bs, int &ln, double &av) {
+                int a, b;
+                item(v, a, b);
+                const int t = P ? (lane & (kHalf - 1)) : lane;
+                const int64_t p = sel64(m_a0, a, b) + t;
+                const int64_t pe = BATCH ? sel64(m_eo, a, b) + p : p;
+                const bool ok = t < lists_of(v, a, b);
+                bs = load_opaque(ok ? ent_bs + pe : reinterpret_cast<const IB *>(&g_zeros[0]));
+                ln = load_opaque(ok ? ent_len + pe : reinterpret_cast<const int32_t *>(&g_zeros[0]));
+                if constexpr (VALUES) {
+                    const double *av_p = BATCH ? reinterpret_cast<const double *>(sel64(m_aval, a, b)) : a_val;
+                    av = load_opaque(ok ? av_p + p : reinterpret_cast<const double *>(&g_zeros[0]));
+                }
+            };
+            // multiplying phase of item v into the lane windows (the products
+            // are formed where the row is consumed): lane t of a row's lanes
+            // holds entry t mod W0 of its list t / W0
+            auto gather = [&](int v, IB bs, int ln, double av, int32_t &c, double &bv, double &lav) {
+                int a, b;
+                item(v, a, b);
+                const int L = lists_of(v, a, b);
+                const int sw = sel32(m_sw, a, b);
+                const int t = P ? (lane & (kHalf - 1)) : lane;
+                const int li = t >> sw, o = t & ((1 << sw) - 1);
+                const int src = (P && lane >= kHalf ? kHalf : 0) + (li & (kWave - 1));
+                // every shuffle with all lanes active
+                const int64_t lbs = __shfl((int64_t)bs, src, kWave);
+                const int lln = __shfl(ln, src, kWave);
+                lav = 0.0;
+                if constexpr (VALUES) lav = __shfl(av, src, kWave);
+                const bool ok = li < L && o < lln;
+                const int32_t *bc = BATCH ? reinterpret_cast<const int32_t *>(sel64(m_bcol, a, b)) : b_col;
+                c = load_opaque(ok ? bc + (lbs + o) : &g_empty_col[0]);
+                bv = 0.0;
+                if constexpr (VALUES) {
+                    const double *bvp = BATCH ? reinterpret_cast<const double *>(sel64(m_bval, a, b)) : b_val;
+                    bv = load_opaque(ok ? bvp + (lbs + o) : reinterpret_cast<const double *>(&g_zeros[0]));
+                }
+            };
+            // one pipeline step: lists of item v+2 -> lo, B entries of item
+            // v+1 (from li) -> go, accumulating phase and write-out of item v
+            auto step = [&](int v, const ListStageRegs &li, ListStageRegs &lo, const GatherRegs &gi, GatherRegs &go) {
+                load_lists(v + 2, lo.bs, lo.ln, lo.av);
+                gather(v + 1, li.bs, li.ln, li.av, go.c, go.bv, go.av);
+                int a, b;
+                item(v, a, b);
+                // a pair runs the rounds of both rows: from the narrower list
+                // window to 32 lanes (a round below a row's own list width
+                // merges halves of its sorted lists, one above its total
+                // merges it with empty lanes: neither changes the row)
+                int sw = lane_value(m_sw, a);
+                if (P && b >= 0) {
+                    const int swb = lane_value(m_sw, b);
+                    sw = swb < sw ? swb : sw;
+                }
+                const int T = P ? kHalf : lane_value(m_T, a);
+                if constexpr (!VALUES && HASH) {
+                    tab[lane] = -1;
+                    tab[lane + kWave] = -1;
+                    wave_sync();
+                    const int added = gi.c != kEmptyCol ? hash_insert<2 * kWave>(tab, gi.c) : 0;
+                    const int len = __popcll(wave_ballot(added != 0));
+                    wave_sync();
+                    done(a, len);
+                } else if constexpr (!VALUES) {
+                    const uint64_t m = distinct_merged(gi.c == kEmptyCol ? ~0u : (uint32_t)gi.c, 1 << sw, T, lane,
+                                                       P ? kHalf : kWave);
+                    if constexpr (P) {
+                        done(a, __popcll(m & 0xffffffffull));
+                        if (b >= 0) done(b, __popcll(m >> kHalf));
+                    } else {
+                        done(a, __popcll(m));
+                    }
+                } else {
+                    uint32_t k = gi.c == kEmptyCol ? (kKeyEmpty | (uint32_t)lane)
+                                                   : (((uint32_t)gi.c << kKeyLaneBits) | (uint32_t)lane);
+                    double v = gi.av * gi.bv;  // one rounded product
+                    if (!key_rounds(k, v, 1 << sw, T, lane, xk, xv)) v = __shfl(v, (int)(k & kKeyLaneMask), kWave);
+                    const bool live = k < kKeyEmpty;
+                    const uint64_t lm = wave_ballot(live);
+                    // live entries sit at the front of their row's lanes
+                    const int pos = P ? (lane & (kHalf - 1)) : lane;
+                    const int64_t cs = sel64(m_cs, a, b);
+                    const int cap = sel32(m_cap, a, b);
+                    int32_t *cc = c_col;
+                    double *cv = c_val;
+                    if constexpr (BATCH) {
+                        cc = reinterpret_cast<int32_t *>(sel64(m_ccol, a, b));
+                        cv = reinterpret_cast<double *>(sel64(m_cval, a, b));
+                    }
+                    if (live && pos < cap) {
+                        cc[cs + pos] = (int32_t)(k >> kKeyLaneBits);
+                        cv[cs + pos] = v;
+                    }
+                    if constexpr (P) {
+                        done(a, __popcll(lm & 0xffffffffull));
+                        if (b >= 0) done(b, __popcll(lm >> kHalf));
+                    } else {
+                        done(a, __popcll(lm));
+                    }
+                }
+            };
+            ListStageRegs la, lb;
+            GatherRegs ga, gb;
+            la.av = lb.av = 0.0;
+            {
+                ListStageRegs l0;
+                l0.av = 0.0;
+                load_lists(0, l0.bs, l0.ln, l0.av);
+                load_lists(1, la.bs, la.ln, la.av);
+                gather(0, l0.bs, l0.ln, l0.av, ga.c, ga.bv, ga.av);
+            }
+            // unrolled by two: the register sets alternate roles, so no
+            // register with a load in flight is copied at the loop latch
+            for (int v = 0; v < nv; v += 2) {
+                step(v, la, lb, ga, gb);
+                if (v + 1 < nv) step(v + 1, lb, la, gb, ga);
+            }
+            // the stages loaded past the chunk's end are drained here, once
+            asm volatile("" ::"v"(ga.c), "v"(gb.c), "v"(la.ln), "v"(lb.ln), "v"(la.bs), "v"(lb.bs));
+            if constexpr (VALUES) asm volatile("" ::"v"(ga.bv), "v"(gb.bv), "v"(la.av), "v"(lb.av));
+        };
+        if (all_small) run(std::true_type{});
+        else run(std::false_type{});
         if constexpr (VALUES) {
-            asm volatile("" ::"v"(ga.bv), "v"(gb.bv), "v"(la.av), "v"(lb.av));
             if (ovf_mask) {
                 // one reservation for the chunk's overflowing rows (light rows
                 // fill the list from its end)

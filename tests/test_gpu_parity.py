@@ -422,3 +422,25 @@ def test_multi_register_windows_int64_row_pointers(handle):
     C = run(handle, A, B, rpt_dtype=torch.int64)
     assert handle.class_rows()["multi"] > 0
     assert_matches_oracle(C, ref, model)
+
+
+@pytest.mark.parametrize("seed", [61, 62])
+def test_paired_short_rows(handle, seed):
+    # rows whose windows fit 32 lanes share a wavefront in pairs; mixed with
+    # rows that need all 64 lanes and a count of rows that is no multiple of
+    # 64, so that pairs, single rows and a ragged last chunk all occur
+    rng = np.random.default_rng(seed)
+    K, N = 3000, 5000
+    B = synth.random_csr(K, N, 0.0015, seed + 100)  # B rows of about 7 entries
+    rows = []
+    for i in range(2000 + seed):
+        L = int(rng.choice([1, 2, 3, 4, 5, 6, 8]))
+        rows.append(np.sort(rng.choice(K, size=L, replace=False)))
+    rpt = np.zeros(len(rows) + 1, np.int64)
+    rpt[1:] = np.cumsum([len(r) for r in rows])
+    A = synth.CSR(len(rows), K, rpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                  rng.uniform(-1, 1, rpt[-1]))
+    ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+    C = run(handle, A, B)
+    assert handle.class_rows()["wave_small"] > 500
+    assert_matches_oracle(C, ref, model)
