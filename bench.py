@@ -284,6 +284,54 @@ def learned_rmat21(h, reps=1):
             "upper_bound_bitwise_equal_to_plain": bool(same_u), "blocks": per_block}
 
 
+def amg_hierarchy_extra(reps=5):
+    """Aggregation hierarchies of the 48 cubes of the batched workload (edges
+    U{16..64}, seed 4) down to edge 2: every level's 48 Galerkin products in
+    one batched call, against separate plain products."""
+    import torch
+    import synth
+    import paper_2206_06611_amd as brm
+
+    inp = synth.amg_batch(48, 4)
+    As = [brm.DeviceCSR.from_host(A) for _, A, _, _ in inp]
+    levels = [[(brm.DeviceCSR.from_host(P), brm.DeviceCSR.from_host(Pt)) for _, P, Pt in synth.amg_levels(n)]
+              for n, _, _, _ in inp]
+    h = brm.Handle(0)
+    out = h.amg_hierarchy(As, levels)  # warm-up, graph captures
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = h.amg_hierarchy(As, levels)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) * 1e3 / reps
+
+    def plain():
+        res = []
+        for A, lv in zip(As, levels):
+            cur, got = A, []
+            for P, Pt in lv:
+                cur = h.spgemm(Pt, h.spgemm(cur, P))
+                got.append(cur)
+            res.append(got)
+        return res
+
+    ref = plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, reps // 2)):
+        ref = plain()
+    torch.cuda.synchronize()
+    t_p = (time.perf_counter() - t0) * 1e3 / max(1, reps // 2)
+    same = all(torch.equal(g.col, r.col) and torch.equal(g.val.view(torch.int64), r.val.view(torch.int64))
+               for go, ro in zip(out, ref) for g, r in zip(go, ro))
+    nlev = max(len(lv) for lv in levels)
+    h.close()
+    return {"workload": "48 aggregation hierarchies (27-point cubes, edges U{16..64}, seed 4) to edge 2",
+            "levels": nlev, "products": 2 * sum(len(lv) for lv in levels),
+            "batched_ms": round(t_b, 4), "plain_ms": round(t_p, 4), "speedup_vs_plain": round(t_p / t_b, 3),
+            "bitwise_equal_to_plain": bool(same)}
+
+
 def accumulator_extra(workloads=("er8_2e20", "stencil27_128", "rmat_s18"), reps=5):
     """The numeric pass with BRMerge against the hash-accumulator comparator
     (rows of at most 4096 products in an LDS hash table; heavier rows keep
@@ -506,6 +554,9 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = batched_extra()
         progress("batched Galerkin products done")
+        torch.cuda.empty_cache()
+        out["amg_hierarchy"] = amg_hierarchy_extra()
+        progress("AMG hierarchies done")
         torch.cuda.empty_cache()
         out["accumulators"] = accumulator_extra()
         progress("accumulator comparison done")

@@ -487,6 +487,27 @@ class Handle:
             arena = torch.empty(req, dtype=torch.uint8, device=arena.device)
         raise SpgError(SPG_ERR_CAPACITY, "arena sizing failed")
 
+    def amg_hierarchy(self, As, levels, stream=None):
+        """Coarse operators of many aggregation hierarchies, level by level:
+        A_{l+1} = P_l^T (A_l P_l), with the products of every hierarchy at
+        level l in one batched call (whose two stages chain A_l P_l into
+        P_l^T times it); each level's outputs are the next level's A.
+        As: the finest operator of every hierarchy; levels: for every
+        hierarchy the list of its (P_l, Pt_l) pairs (hierarchies may differ
+        in depth).  Returns, per hierarchy, the list [A_1, ..., A_L] of
+        DeviceCSR views into the level arenas (kept alive by the views)."""
+        cur = list(As)
+        out = [[] for _ in As]
+        depth = max((len(lv) for lv in levels), default=0)
+        for l in range(depth):
+            ids = [i for i, lv in enumerate(levels) if l < len(lv)]
+            triples = [(cur[i], levels[i][l][0], levels[i][l][1]) for i in ids]
+            G, _, _ = self.galerkin(triples, stream=stream)
+            for i, g in zip(ids, G):
+                out[i].append(g)
+                cur[i] = g
+        return out
+
     def spgemm_csc(self, A: DeviceCSC, B: DeviceCSC, stream=None) -> DeviceCSC:
         """C = A*B with A, B and C in CSC: the column-wise dataflow (column j
         of C merges the columns of A selected by column j of B, Eq. (3)),

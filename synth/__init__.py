@@ -249,6 +249,17 @@ def amg_batch(count: int, seed: int, edge_lo: int = 16, edge_hi: int = 64):
     return out
 
 
+def amg_levels(n: int, coarsest: int = 2):
+    """The grid edges of an aggregation hierarchy on an n^3 cube: n, ceil(n/2),
+    ... down to the first edge <= ``coarsest``, with the prolongation and its
+    transpose of every level but the last: [(edge, P, Pt), ...]."""
+    out = []
+    while n > coarsest:
+        out.append((n, aggregation_p(n), aggregation_pt(n)))
+        n = (n + 1) // 2
+    return out
+
+
 def random_csr(rows: int, cols: int, density: float, seed: int, integer_values: bool = False,
                empty_row_frac: float = 0.0, lo: float = -1.0, hi: float = 1.0) -> CSR:
     """Bernoulli(density) pattern; values U[lo, hi) or small nonzero integers in

@@ -173,3 +173,27 @@ def test_kernel_choices_agree_in_batches(handle):
         ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
         assert np.array_equal(x[0], ref.rpt) and np.array_equal(x[1], ref.col)
         assert np.array_equal(x[2].view(np.int64), model.val.view(np.int64))
+
+
+def test_amg_hierarchy(handle):
+    # coarse operators of several aggregation hierarchies, level by level in
+    # batched calls; every level is again a 27-point pattern on the coarse
+    # grid, and the integer values make the oracle's sums exact
+    edges = [9, 16, 12, 5]
+    As = [dev(synth.stencil_3d_27pt(n)) for n in edges]
+    levels_h = [synth.amg_levels(n) for n in edges]
+    levels = [[(dev(P), dev(Pt)) for _, P, Pt in lv] for lv in levels_h]
+    out = handle.amg_hierarchy(As, levels)
+    torch.cuda.synchronize()
+    for n, lv, got in zip(edges, levels_h, out):
+        print(f"case: AMG hierarchy from edge {n}: {len(lv)} levels", flush=True)
+        A = synth.stencil_3d_27pt(n)
+        assert len(got) == len(lv)
+        for (e, P, Pt), g in zip(lv, got):
+            ref_ap = oracle.spgemm(A, P)
+            ap = synth.CSR(A.rows, P.cols, ref_ap.rpt, ref_ap.col, ref_ap.val)
+            ref = oracle.spgemm(Pt, ap)
+            same_bits(to_host(g), (ref.rpt, ref.col, ref.val))
+            m = (e + 1) // 2
+            assert g.rows == m ** 3 and g.nnz == (3 * m - 2) ** 3
+            A = synth.CSR(g.rows, g.cols, ref.rpt, ref.col, ref.val)
