@@ -107,7 +107,9 @@ typedef enum {
                                     the heavy path */
     SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (<= 4096) */
     SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
-                                    per batch of heavy rows (default 16384) */
+                                    per batch of heavy rows; 0 (default): 64 GiB, or half of
+                                    the device memory free at the call when that is less.
+                                    The handle keeps its pool (grow-only) until spg_destroy */
     SPG_OPT_GRID_WAVES = 9,      /* waves per launch of the persistent row kernels (0 = auto) */
     SPG_OPT_ALLOC = 10,          /* SPG_ALLOC_PRECISE (default), SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER */
     SPG_OPT_LEARNED_FORCE = 11,  /* testing only: 1 sizes every predicted row at its lower bound

@@ -28,7 +28,7 @@ struct spg_handle_s {
     int64_t block_max = kCapBlock;
     int64_t force = -1;
     int64_t heavy_lds_max = kCapBlock;
-    int64_t spill_budget_mb = 16384;
+    int64_t spill_budget_mb = 0;       // 0: half of the device memory free at the call
     int64_t grid_waves = 0;
     int64_t group_rows = 1;  // kernel of the wave-small class (see SPG_OPT_GROUP_ROWS)
     int plan_group_rows = 1;  // the one the last symbolic pass classified for
@@ -217,7 +217,19 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     std::vector<int32_t> rows((size_t)n);
     std::vector<int64_t> soff((size_t)n), loff((size_t)n);
     std::vector<std::pair<int64_t, int64_t>> batches;  // [begin, end)
-    const size_t budget = (size_t)h->spill_budget_mb << 20;
+    size_t budget = (size_t)h->spill_budget_mb << 20;
+    if (budget == 0) {
+        // automatic: 64 GiB, or half of the device memory free now (C is
+        // allocated by then) when that is less; fewer batches leave the
+        // device idle less often at batch ends
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(h, hipMemGetInfo(&free_b, &total_b));
+        budget = std::max<size_t>(std::min<size_t>(free_b / 2, (size_t)64 << 30), (size_t)1 << 30);
+        // a pool the handle already holds is used whole
+        budget = std::max(budget, h->spill_bytes);
+    }
+    // batches of consecutive rows in that order: the longest rows run side by
+    // side in the first batch (a batch lasts as long as its longest row)
     size_t max_elems = 0, max_leaf = 0;
     size_t used = 0, elems = 0, leafs = 0;
     int64_t b0 = 0;
@@ -470,7 +482,7 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             h->heavy_lds_max = value;
             break;
         case SPG_OPT_SPILL_BUDGET_MB:
-            if (value < 1) return fail(h, SPG_ERR_ARG, "spill budget must be positive");
+            if (value < 0) return fail(h, SPG_ERR_ARG, "spill budget must be >= 0 (0: automatic)");
             h->spill_budget_mb = value;
             break;
         case SPG_OPT_GRID_WAVES:
