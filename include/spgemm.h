@@ -268,8 +268,11 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *problems, void *a
  * Not in the paper: a stand-in for its allocation step (Section II-B.2).  A
  * perceptron 6 -> 64 -> 64 -> 1 (ReLU, float32) predicts y_i ~ log(nnz(C_i) /
  * nprod_i) for every row with two or more lists and at least one product, from
- * the features log1p of (lists, products, longest list, shortest list, column
- * span, products / span), each normalised as (x - mean) / std.  The row's
+ * the features log1p(lists), log((1 + products) / N), log1p(longest list),
+ * log1p(shortest list), log(column span / N) and log1p(products / span), with
+ * N the column count of B (products and span relative to the column space,
+ * so that a predictor trained on one matrix size carries over to others),
+ * each normalised as (x - mean) / std.  The row's
  * slot holds clamp(ceil(nprod_i exp(y_i + delta)), longest list, min(nprod_i,
  * span_i)) entries; rows with no product or one list get their exact size.
  * With SPG_OPT_ALLOC = SPG_ALLOC_LEARNED, spgemm_symbolic runs the numeric

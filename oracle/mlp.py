@@ -6,7 +6,7 @@ estimate learned from the precise method's own symbolic counts.  This module
 computes, in float64 and with plain numpy, everything the GPU kernels of the
 learned path compute, so that the kernels can be checked:
 
-  features(A, B)      the 6 per-row features and the exact size bounds
+  raw_features        the 6 per-row features (counts relative to B's columns)
   forward(params, x)  a 6 -> 64 -> 64 -> 1 perceptron with ReLU
   loss_and_grad       mean squared error and its analytic gradient
   adam_step           one step of Adam (Kingma & Ba, ICLR 2015, Algorithm 1)
@@ -53,13 +53,18 @@ def init_params(seed: int) -> np.ndarray:
     return pack(p).astype(np.float32)
 
 
-def raw_features(nnza, nprod, maxb, minb, span):
-    """The 6 features of a row: log1p of the list count, product count,
-    longest and shortest list, column span, and log1p(nprod / span)."""
+def raw_features(nnza, nprod, maxb, minb, span, ncols):
+    """The 6 features of a row of C = A*B: log1p of the list count,
+    log((1 + product count) / N), log1p of the longest and shortest list,
+    log(column span / N) and log1p(nprod / span), with N = max(1, B's column
+    count) and a span of 0 taken as 1.  The product count and the span enter
+    relative to the column space, so that rows of matrices of different sizes
+    with the same density of collisions look alike."""
     nnza, nprod, maxb, minb, span = (np.asarray(a, np.float64) for a in (nnza, nprod, maxb, minb, span))
+    n = float(max(int(ncols), 1))
     ratio = np.where(span > 0, nprod / np.maximum(span, 1.0), 0.0)
-    return np.stack([np.log1p(nnza), np.log1p(nprod), np.log1p(maxb), np.log1p(minb), np.log1p(span),
-                     np.log1p(ratio)], axis=1)
+    return np.stack([np.log1p(nnza), np.log((1.0 + nprod) / n), np.log1p(maxb), np.log1p(minb),
+                     np.log(np.maximum(span, 1.0) / n), np.log1p(ratio)], axis=1)
 
 
 def forward(theta, x):

@@ -616,6 +616,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         rf.lo = lw.lo;
         rf.hi = lw.hi;
         rf.predicted = lw.predicted;
+        rf.ncols = B->cols;
     }
     if (M > 0) {
         const int g = (int)std::min<int64_t>((M + 255) / 256, 2048);

@@ -55,6 +55,22 @@ __device__ __forceinline__ Tv wave_sum(Tv x) {
     return x;
 }
 
+// The size predictor's six inputs for a row of C: log1p(lists), log((1 +
+// products) / N), log1p(longest list), log1p(shortest list), log(column span
+// / N) and log1p(products / span), N the column count of B (taken as at
+// least 1, a span of 0 as 1).  Products and span relative to the column space
+// keep the features comparable between matrices of different sizes.
+__device__ __forceinline__ void row_features6(float *f, int64_t L, int64_t np, int64_t mx, int64_t mn,
+                                              int64_t span, int64_t ncols) {
+    const double n = (double)(ncols > 0 ? ncols : 1);
+    f[0] = log1pf((float)L);
+    f[1] = logf((float)((1.0 + (double)np) / n));
+    f[2] = log1pf((float)mx);
+    f[3] = log1pf((float)mn);
+    f[4] = logf((float)((double)(span > 0 ? span : 1) / n));
+    f[5] = log1pf(span > 0 ? (float)((double)np / (double)span) : 0.0f);
+}
+
 // A team is either one wavefront (T == 64) or a whole workgroup (T > 64).
 template <int T>
 struct Team {

@@ -101,6 +101,7 @@ struct RowFeatures {
     float *feats;       // [M * 6]
     int32_t *lo, *hi;   // bounds of the row size
     int8_t *predicted;  // 1: the row's size is predicted (products, two lists or more)
+    int64_t ncols;      // columns of B (the features relative to the column space)
 };
 // ends[2k], ends[2k+1]: first and last column of B's row k (-1, -1 when empty)
 hipError_t launch_row_ends(const CsrView &B, int32_t *ends, hipStream_t s);

@@ -319,19 +319,15 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
                                                                   : 0;
             row_class[i] = (uint8_t)(cls | (sw << kClassBits));
             if constexpr (FEAT) {
-                // log1p of (lists, products, longest, shortest list, column span,
-                // products per spanned column); bounds of the row size
+                // the predictor's features (lists, products and column span
+                // the last two relative to B's column count, longest and
+                // shortest list, products per spanned column); bounds of
+                // the row size
                 const int64_t L = a1 - a0;
                 const int64_t mn = L == 0 ? 0 : s_mn[w][lane];
                 const int64_t first = s_first[w][lane], last = s_last[w][lane];
                 const int64_t span = last >= first ? last - first + 1 : 0;
-                float *f = rf.feats + 6 * i;
-                f[0] = log1pf((float)L);
-                f[1] = log1pf((float)np);
-                f[2] = log1pf((float)mx);
-                f[3] = log1pf((float)mn);
-                f[4] = log1pf((float)span);
-                f[5] = log1pf(span > 0 ? (float)((double)np / (double)span) : 0.0f);
+                row_features6(rf.feats + 6 * i, L, np, mx, mn, span, rf.ncols);
                 rf.predicted[i] = (np > 0 && L >= 2) ? 1 : 0;
                 rf.lo[i] = (int32_t)(np == 0 ? 0 : (L == 1 ? np : mx));
                 rf.hi[i] = (int32_t)(np == 0 ? 0 : (L == 1 ? np : (np < span ? np : span)));

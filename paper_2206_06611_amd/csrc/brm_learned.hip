@@ -28,13 +28,12 @@ __device__ __forceinline__ int64_t ld_rpt_l(const void *p, int64_t i) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// features: log1p of (lists, products, longest list, shortest list, column
-// span, products / span); exact bounds of the row size: the longest list (a
-// row of C holds at least its distinct columns) and min(products, span)
+// features (row_features6); exact bounds of the row size: the longest list
+// (a row of C holds at least its distinct columns) and min(products, span)
 // ---------------------------------------------------------------------------
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_features(int64_t M, const void *a_rpt, const int32_t *a_col,
-                                                  const void *b_rpt, const int32_t *b_col,
+                                                  const void *b_rpt, const int32_t *b_col, int64_t ncols,
                                                   float *feats, int32_t *lo, int32_t *hi,
                                                   int8_t *predicted, const int64_t *c_rpt,
                                                   float *targets) {
@@ -107,13 +106,7 @@ __global__ __launch_bounds__(256) void k_features(int64_t M, const void *a_rpt, 
             const int64_t L = a1 - a0;
             const int64_t span = last >= first ? last - first + 1 : 0;
             if (L == 0) mn = 0;
-            float *f = feats + 6 * i;
-            f[0] = log1pf((float)L);
-            f[1] = log1pf((float)np);
-            f[2] = log1pf((float)mx);
-            f[3] = log1pf((float)mn);
-            f[4] = log1pf((float)span);
-            f[5] = log1pf(span > 0 ? (float)((double)np / (double)span) : 0.0f);
+            row_features6(feats + 6 * i, L, np, mx, mn, span, ncols);
             const bool pred = np > 0 && L >= 2;
             predicted[i] = pred ? 1 : 0;
             lo[i] = (int32_t)(np == 0 ? 0 : (L == 1 ? np : mx));
@@ -132,7 +125,7 @@ hipError_t launch_features(const CsrView &A, const CsrView &B, float *feats, int
     const unsigned g = (unsigned)((A.rows + 255) / 256 < 2048 ? (A.rows + 255) / 256 : 2048);
 #define BRM_F(IA, IB)                                                                            \
     hipLaunchKernelGGL((k_features<IA, IB>), dim3(g), dim3(256), 0, s, A.rows, A.rpt, A.col,       \
-                       B.rpt, B.col, feats, lo, hi, predicted, c_rpt, targets)
+                       B.rpt, B.col, B.cols, feats, lo, hi, predicted, c_rpt, targets)
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_F(int32_t, int32_t);
     else if (A.rpt_bytes == 4) BRM_F(int32_t, int64_t);
     else if (B.rpt_bytes == 4) BRM_F(int64_t, int32_t);

@@ -38,7 +38,7 @@ def test_features_match_definition(handle):
     c_rpt, _ = handle.symbolic(dA, dA)
     feats, targets, pred, lo, hi = handle.mlp_features(dA, dA, c_rpt)
     f = oracle.row_features(A, A)
-    raw = mlp.raw_features(f["nnza"], f["nprod"], f["maxb"], f["minb"], f["span"])
+    raw = mlp.raw_features(f["nnza"], f["nprod"], f["maxb"], f["minb"], f["span"], A.cols)
     assert np.allclose(feats.cpu().numpy(), raw, rtol=1e-6, atol=1e-6)
     want_pred = (f["nprod"] > 0) & (f["nnza"] >= 2)
     assert np.array_equal(pred.cpu().numpy().astype(bool), want_pred)

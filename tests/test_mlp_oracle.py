@@ -74,7 +74,7 @@ def test_feature_bounds_hold():
     assert np.all(nnzc[ok] >= f["maxb"][ok]) and np.all(nnzc[ok] <= np.minimum(f["nprod"], f["span"])[ok])
     single = f["nnza"] == 1
     assert np.all(nnzc[single] == f["nprod"][single])
-    x = mlp.raw_features(f["nnza"], f["nprod"], f["maxb"], f["minb"], f["span"])
+    x = mlp.raw_features(f["nnza"], f["nprod"], f["maxb"], f["minb"], f["span"], A.cols)
     assert x.shape == (A.rows, 6) and np.all(np.isfinite(x))
 
 
