@@ -107,7 +107,7 @@ typedef enum {
                                     the heavy path */
     SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (<= 4096) */
     SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
-                                    per batch of heavy rows; 0 (default): 64 GiB, or half of
+                                    per batch of heavy rows; 0 (default): 128 GiB, or 60% of
                                     the device memory free at the call when that is less.
                                     The handle keeps its pool (grow-only) until spg_destroy */
     SPG_OPT_GRID_WAVES = 9,      /* waves per launch of the persistent row kernels (0 = auto) */

@@ -219,12 +219,12 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     std::vector<std::pair<int64_t, int64_t>> batches;  // [begin, end)
     size_t budget = (size_t)h->spill_budget_mb << 20;
     if (budget == 0) {
-        // automatic: 64 GiB, or half of the device memory free now (C is
+        // automatic: 128 GiB, or 60% of the device memory free now (C is
         // allocated by then) when that is less; fewer batches leave the
         // device idle less often at batch ends
         size_t free_b = 0, total_b = 0;
         HIP_TRY(h, hipMemGetInfo(&free_b, &total_b));
-        budget = std::max<size_t>(std::min<size_t>(free_b / 2, (size_t)64 << 30), (size_t)1 << 30);
+        budget = std::max<size_t>(std::min<size_t>(free_b / 10 * 6, (size_t)128 << 30), (size_t)1 << 30);
         // a pool the handle already holds is used whole
         budget = std::max(budget, h->spill_bytes);
     }
