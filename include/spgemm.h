@@ -176,6 +176,9 @@ typedef enum {
     SPG_STAT_PREDICTED_ROWS = 23,/* rows whose size is predicted (two or more lists, a product) */
     SPG_STAT_GRAPH_CAPTURES = 24,/* batched calls that (re)captured their HIP graph */
     SPG_STAT_GRAPH_LAUNCHES = 25,/* batched calls that replayed a captured graph */
+    SPG_STAT_SPILL_POOL_BYTES = 26,/* device bytes of the handle's heavy-row spill pool (kept
+                                    between calls; a call whose batches fit it reuses it) */
+    SPG_STAT_SPILL_ALLOCS = 27,  /* allocations of that pool since the handle was created */
     SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call
                                     (16: a numeric row length differed from its symbolic count;
                                     the row was truncated to its slot).  Synchronizes the device. */

@@ -60,6 +60,8 @@ STAT_OVERFLOW_ROWS = 22
 STAT_PREDICTED_ROWS = 23
 STAT_GRAPH_CAPTURES = 24
 STAT_GRAPH_LAUNCHES = 25
+STAT_SPILL_POOL_BYTES = 26
+STAT_SPILL_ALLOCS = 27
 STAT_DEVICE_ERR = 30
 
 CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy", "multi"]

@@ -50,6 +50,7 @@ struct spg_handle_s {
     int64_t counts[8] = {0};
     int64_t nnz = 0, nprod = 0;
     int64_t heavy_batches = 0;
+    int64_t spill_allocs = 0;  // allocations of the spill pool
     // learned allocation
     int64_t alloc = 0;          // 0 precise, 1 learned, 2 upper bound
     int64_t accumulator = 0;    // 0 BRMerge, 1 hash table (comparator)
@@ -228,10 +229,17 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
         // a pool the handle already holds is used whole
         budget = std::max(budget, h->spill_bytes);
     }
+    // the pool holds every batch in turn: columns and values of the largest
+    // batch's two spill buffers, then the largest batch's list offsets
+    auto pool_bytes = [](size_t elems, size_t leafs) {
+        return align_up(4 * elems, 256) + align_up(8 * elems, 256) + align_up(4 * leafs, 256) + 256;
+    };
     // batches of consecutive rows in that order: the longest rows run side by
-    // side in the first batch (a batch lasts as long as its longest row)
+    // side in the first batch (a batch lasts as long as its longest row).  A
+    // batch is cut where the pool would outgrow the budget, so a pool already
+    // held is never reallocated by a call that fits it.
     size_t max_elems = 0, max_leaf = 0;
-    size_t used = 0, elems = 0, leafs = 0;
+    size_t elems = 0, leafs = 0;
     int64_t b0 = 0;
     for (int64_t j = 0; j < n; ++j) {
         const int64_t i = order[(size_t)j];
@@ -239,18 +247,17 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
         if (np >= INT32_MAX || nl >= INT32_MAX)
             return fail(h, SPG_ERR_CAPACITY, "row %lld has %lld products (limit 2^31-1 per row)",
                         (long long)info[3 * i], (long long)np);
-        const size_t need = 24 * (size_t)np + 4 * (size_t)(nl + 1);
-        if (j > b0 && used + need > budget) {
+        if (j > b0 && pool_bytes(std::max(max_elems, elems + 2 * (size_t)np),
+                                 std::max(max_leaf, leafs + (size_t)nl + 1)) > budget) {
             batches.emplace_back(b0, j);
             b0 = j;
-            used = elems = leafs = 0;
+            elems = leafs = 0;
         }
         rows[(size_t)j] = (int32_t)info[3 * i];
         soff[(size_t)j] = (int64_t)elems;
         loff[(size_t)j] = (int64_t)leafs;
         elems += 2 * (size_t)np;
         leafs += (size_t)nl + 1;
-        used += need;
         max_elems = std::max(max_elems, elems);
         max_leaf = std::max(max_leaf, leafs);
     }
@@ -260,8 +267,9 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     HIP_TRY(h, hipMemcpy(d_soff, soff.data(), 8 * (size_t)n, hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_loff, loff.data(), 8 * (size_t)n, hipMemcpyHostToDevice));
     const size_t col_b = align_up(4 * max_elems, 256), val_b = align_up(8 * max_elems, 256);
-    if ((rc = grow(h, &h->spill_mem, &h->spill_bytes, col_b + val_b + align_up(4 * max_leaf, 256) + 256, "spill buffers")))
-        return rc;
+    const size_t pool_need = pool_bytes(max_elems, max_leaf);
+    if (pool_need > h->spill_bytes) ++h->spill_allocs;
+    if ((rc = grow(h, &h->spill_mem, &h->spill_bytes, pool_need, "spill buffers"))) return rc;
     char *sp = static_cast<char *>(h->spill_mem);
     HIP_TRY(h, launch_zero_words(d_ticket, (int64_t)batches.size(), s));
     for (size_t bi = 0; bi < batches.size(); ++bi) {
@@ -543,6 +551,8 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_PRED_TOTAL: *value = h->pred_total; return SPG_OK;
         case SPG_STAT_GRAPH_CAPTURES: *value = h->graph_captures; return SPG_OK;
         case SPG_STAT_GRAPH_LAUNCHES: *value = h->graph_launches; return SPG_OK;
+        case SPG_STAT_SPILL_POOL_BYTES: *value = (int64_t)h->spill_bytes; return SPG_OK;
+        case SPG_STAT_SPILL_ALLOCS: *value = h->spill_allocs; return SPG_OK;
         case SPG_STAT_OVERFLOW_ROWS: *value = h->ovf_light + h->ovf_heavy; return SPG_OK;
         case SPG_STAT_PREDICTED_ROWS: {
             int64_t n = 0;

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import assert_matches_oracle
+from helpers import assert_matches_oracle, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +60,29 @@ def test_spill_batches(handle):
     C = run(handle, A, A)
     assert handle.stat(brm.STAT_HEAVY_BATCHES) > 1
     assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+@pytest.mark.parametrize("budget_mb", [0, 1, 3])
+def test_spill_pool_kept_between_calls(handle, budget_mb):
+    # the batches of a repeated call fit the pool the first call left, so it
+    # is neither freed nor allocated again
+    print(f"case: R-MAT scale 13 twice, spill budget {budget_mb} MB", flush=True)
+    A = synth.rmat(13, 16, 24)
+    handle.set_option(brm.OPT_SPILL_BUDGET_MB, budget_mb)
+    dA = brm.DeviceCSR.from_host(A)
+    first = to_host(handle.spgemm(dA, dA))
+    pool, batches = handle.stat(brm.STAT_SPILL_POOL_BYTES), handle.stat(brm.STAT_HEAVY_BATCHES)
+    assert handle.stat(brm.STAT_SPILL_ALLOCS) == 1 and pool > 0
+    for _ in range(2):
+        again = to_host(handle.spgemm(dA, dA))
+        assert handle.stat(brm.STAT_SPILL_ALLOCS) == 1
+        assert handle.stat(brm.STAT_SPILL_POOL_BYTES) == pool
+        assert handle.stat(brm.STAT_HEAVY_BATCHES) <= batches
+        for x, y in zip(first, again):
+            assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                                  y.view(np.int64) if y.dtype == np.float64 else y)
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    assert_matches_oracle(handle.spgemm(dA, dA), oracle.spgemm(A, A), oracle.brmerge(A, A))
 
 
 def test_long_single_lists(handle):
