@@ -2571,10 +2571,12 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 // tile boundaries through a carried element.  The root is written straight
 // into C.
 // ---------------------------------------------------------------------------
-// entries of each input staged per tile, and merge steps per thread
+// entries of each input staged per tile, and merge steps per thread (a tile
+// merges up to 2 kMergeWin entries, kMergeSteps per thread)
 constexpr int kMergeWin = kHeavyThreads * 2;
 constexpr int kMergeSteps = 4;
 constexpr int kWinPer = kMergeWin / kHeavyThreads;  // staged entries per thread and input
+static_assert(kHeavyThreads * kMergeSteps >= 2 * kMergeWin, "a tile's merge steps must cover both windows");
 
 struct MergeLds {
     int32_t xc[kMergeWin];
@@ -2668,6 +2670,7 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
     while (x0 < nx || y0 < ny) {
         const int wx = win(nx, x0), wy = win(ny, y0);
         // the tile: every entry of both windows up to the column `lim`
+        // (uniform values are moved to scalar registers)
         int cx = wx, cy = wy;
         {
             const bool tx = x0 + wx < nx, ty = y0 + wy < ny;
@@ -2675,24 +2678,28 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
                 int32_t lim = INT32_MAX;
                 if (tx) lim = m.xc[wx - 1];
                 if (ty && m.yc[wy - 1] < lim) lim = m.yc[wy - 1];
-                cx = upper_bound(m.xc, wx, lim);
-                cy = upper_bound(m.yc, wy, lim);
+                cx = wave_uniform(upper_bound(m.xc, wx, wave_uniform(lim)));
+                cy = wave_uniform(upper_bound(m.yc, wy, wave_uniform(lim)));
             }
         }
         const int64_t nx0 = x0 + cx, ny0 = y0 + cy;
         fetch(nx0, ny0);
-        // kMergeSteps merge steps per thread
+        // kMergeSteps merge steps per thread; every register array is
+        // indexed by unrolled constants only
         const int D = cx + cy;
         const int s0 = tid * kMergeSteps;
-        int cnt = 0;
+        const int cnt = s0 < D ? (D - s0 < kMergeSteps ? D - s0 : kMergeSteps) : 0;
         int32_t c[kMergeSteps];
         double v[kMergeSteps];
-        if (s0 < D) {
+        if (cnt > 0) {
             int x = mp_split_lds(m.xc, cx, m.yc, cy, s0);
             int y = s0 - x;
+            int32_t last = 0;
 #pragma unroll
             for (int j = 0; j < kMergeSteps; ++j) {
-                if (s0 + j < D) {
+                c[j] = 0;
+                v[j] = 0.0;
+                if (j < cnt) {
                     if (x < cx && (y >= cy || m.xc[x] <= m.yc[y])) {
                         c[j] = m.xc[x];
                         v[j] = m.xv[x];
@@ -2702,44 +2709,57 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
                         v[j] = m.yv[y];
                         ++y;
                     }
-                    ++cnt;
+                    last = c[j];
                 }
             }
             m.first_c[tid] = c[0];
             m.first_v[tid] = v[0];
-            m.last_c[tid] = c[cnt - 1];
+            m.last_c[tid] = last;
         }
         const int nthr = (D + kMergeSteps - 1) / kMergeSteps;
         __syncthreads();
         // heads (first entry of a column) and their values: the two entries
         // of a column are adjacent, the left one first
-        int items = 0;
-        for (int j = 0; j < cnt; ++j) {
-            const bool head = j > 0 ? c[j] != c[j - 1] : (tid == 0 || c[0] != m.last_c[tid - 1]);
-            if (!head) continue;
-            bool has_next = false;
-            int32_t nc = 0;
-            double nv = 0.0;
-            if (j + 1 < cnt) {
-                has_next = true;
-                nc = c[j + 1];
-                nv = v[j + 1];
-            } else if (tid + 1 < nthr) {
-                has_next = true;
-                nc = m.first_c[tid + 1];
-                nv = m.first_v[tid + 1];
+        bool nb = false;  // the next thread's first entry follows this thread's last
+        int32_t nbc = 0;
+        double nbv = 0.0;
+        bool head0 = true;
+        if (cnt > 0) {
+            if (tid + 1 < nthr) {
+                nb = true;
+                nbc = m.first_c[tid + 1];
+                nbv = m.first_v[tid + 1];
             }
-            c[items] = c[j];
-            v[items] = (has_next && nc == c[j]) ? v[j] + nv : v[j];  // left + right
-            ++items;
+            if (tid > 0) head0 = c[0] != m.last_c[tid - 1];
+        }
+        bool hd[kMergeSteps];
+        int items = 0;
+#pragma unroll
+        for (int j = 0; j < kMergeSteps; ++j) {
+            hd[j] = j < cnt && (j == 0 ? head0 : c[j] != c[j - 1]);
+            bool has_next = j + 1 < cnt;
+            int32_t nc = j + 1 < kMergeSteps ? c[j + 1 < kMergeSteps ? j + 1 : j] : 0;
+            double nv = j + 1 < kMergeSteps ? v[j + 1 < kMergeSteps ? j + 1 : j] : 0.0;
+            if (j == cnt - 1 && nb) {
+                has_next = true;
+                nc = nbc;
+                nv = nbv;
+            }
+            if (hd[j] && has_next && nc == c[j]) v[j] = v[j] + nv;  // left + right
+            items += hd[j] ? 1 : 0;
         }
         int tot;
         const int rank = Team<kHeavyThreads>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
-        for (int j = 0; j < items; ++j) {
-            const int64_t o = out + rank + j;
-            if (o < zcap) {
-                Zc[o] = c[j];
-                Zv[o] = v[j];
+        tot = wave_uniform(tot);
+        int64_t o = out + rank;
+#pragma unroll
+        for (int j = 0; j < kMergeSteps; ++j) {
+            if (hd[j]) {
+                if (o < zcap) {
+                    Zc[o] = c[j];
+                    Zv[o] = v[j];
+                }
+                ++o;
             }
         }
         out += tot;
@@ -2783,7 +2803,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
         // rows arrive largest first; a ticket hands the next one to a free workgroup
         if (tid == 0) s_bi = (int64_t)atomicAdd(hb.ticket, 1ull);
         __syncthreads();
-        const int64_t bi = s_bi;
+        const int64_t bi = wave_uniform(s_bi);
         __syncthreads();
         if (bi >= hb.nrows) break;
         const int64_t row = hb.rows[bi];
@@ -2804,7 +2824,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
             int64_t tot;
             const int64_t ex = Team<kHeavyThreads>::excl_scan(ln, &tot, st.scr, tid);
             if (l < L) leaf[l] = (int32_t)(carry + ex);
-            carry += tot;
+            carry += wave_uniform(tot);
         }
         const int64_t nprod = carry;
         if (tid == 0) leaf[L] = (int32_t)nprod;
@@ -2851,7 +2871,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                 st.action = act;
             }
             __syncthreads();
-            const int act = st.action;
+            const int act = wave_uniform(st.action);
             if (act == kActDone) break;
             if (act == kActFail) {
                 if (tid == 0)
@@ -2860,8 +2880,8 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                 break;
             }
             if (act == kActNode) {
-                const int64_t l0 = st.l0, l1 = st.l1;
-                const int root = st.root;
+                const int64_t l0 = wave_uniform(st.l0), l1 = wave_uniform(st.l1);
+                const int root = wave_uniform(st.root);
                 const int64_t r0 = leaf[l0];
                 const int64_t np = (int64_t)leaf[l1] - r0;
                 int32_t *oc = root ? c_col + cs : bcol[0] + r0;
@@ -2895,9 +2915,18 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                     st.next_list = l1;
                 }
             } else if (act == kActMerge) {
-                const HeavyNode x = st.stack[st.sp - 2];
-                const HeavyNode y = st.stack[st.sp - 1];
-                const int root = st.root;
+                const int sp = wave_uniform(st.sp);
+                HeavyNode x = st.stack[sp - 2];
+                HeavyNode y = st.stack[sp - 1];
+                x.p = wave_uniform(x.p);
+                x.len = wave_uniform(x.len);
+                x.h = wave_uniform(x.h);
+                x.buf = wave_uniform(x.buf);
+                y.p = wave_uniform(y.p);
+                y.len = wave_uniform(y.len);
+                y.h = wave_uniform(y.h);
+                y.buf = wave_uniform(y.buf);
+                const int root = wave_uniform(st.root);
                 const int64_t rx = leaf[x.p << x.h];
                 const int64_t ry = leaf[y.p << y.h];
                 const int ob = root ? 2 : (x.buf == y.buf ? 1 - x.buf : y.buf);
