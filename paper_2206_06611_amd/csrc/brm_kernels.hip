@@ -399,12 +399,17 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const int32_t *rows, con
     __shared__ int64_t s_base[kNumClasses];
     __shared__ int s_wave_cnt[kNumClasses];
     const int lane = lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every workgroup bins one contiguous range of rows, so the rows of a
+    // class sit in row order inside each workgroup's reservation
+    const int64_t per = ((M + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < M ? lo + per : M;
+    const int64_t stride = blockDim.x;
     // pass 1: this block's rows per class, one global reservation per class
     int64_t my_count[kNumClasses];
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += stride) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += stride) {
         const int cls = row_class[rows ? (int64_t)rows[i] : i] & kClassMask;
 #pragma unroll
         for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
@@ -428,11 +433,11 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const int32_t *rows, con
     }
     __syncthreads();
     // pass 2: scatter; wavefront-aggregated LDS cursors
-    const int64_t base0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1));
-    for (int64_t base = base0; base < M; base += stride) {
+    const int64_t base0 = lo + (threadIdx.x & ~(kWave - 1));
+    for (int64_t base = base0; base < hi; base += stride) {
         const int64_t i = base + lane;
-        const int64_t r = i < M ? (rows ? (int64_t)rows[i] : i) : 0;
-        const int cls = i < M ? (int)(row_class[r] & kClassMask) : -1;
+        const int64_t r = i < hi ? (rows ? (int64_t)rows[i] : i) : 0;
+        const int cls = i < hi ? (int)(row_class[r] & kClassMask) : -1;
 #pragma unroll
         for (int c = 0; c < kNumClasses; ++c) {
             const uint64_t m = wave_ballot(cls == c);
@@ -446,6 +451,10 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const int32_t *rows, con
 }
 
 hipError_t launch_bin(int64_t M, const Workspace &ws, int grid, hipStream_t s) {
+    // every workgroup reserves its class ranges with one atomic per class on
+    // the same counters: a grid of one workgroup per compute unit keeps
+    // that contention low (each thread bins M / 65536 rows)
+    grid = grid < 256 ? grid : 256;
     hipLaunchKernelGGL(k_bin, dim3(grid), dim3(256), 0, s, M, nullptr, ws.row_class, ws.class_rows, ws.ctl);
     return hipGetLastError();
 }
@@ -1652,6 +1661,9 @@ __device__ __forceinline__ T load_opaque(const T *p) {
 // windows both fit 32 lanes are merged together, one in each half of the
 // wavefront.  VALUES = false counts row sizes; HASH then selects counting by
 // LDS hash instead of window merges (one row at a time).
+// items in flight behind the one being merged in the numeric window pipeline
+constexpr int kWinNumDepth = 3;
+
 template <bool VALUES, bool HASH, typename IA, typename IB, bool BATCH = false>
 __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
                                            const int32_t *b_col, const double *b_val, const uint8_t *row_class,
@@ -1815,11 +1827,15 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     bv = load_opaque(ok ? bvp + (lbs + o) : reinterpret_cast<const double *>(&g_zeros[0]));
                 }
             };
-            // one pipeline step: lists of item v+2 -> lo, B entries of item
-            // v+1 (from li) -> go, accumulating phase and write-out of item v
+            // pipeline depth: the numeric pass keeps D = kWinNumDepth items in
+            // flight behind the one being merged, the symbolic pass (column
+            // gathers only, slower with more in flight) D = 2
+            constexpr int D = VALUES ? kWinNumDepth : 2;
+            // one pipeline step: lists of item v+D -> lo, B entries of item
+            // v+D-1 (from li) -> go, accumulating phase and write-out of item v
             auto step = [&](int v, const ListStageRegs &li, ListStageRegs &lo, const GatherRegs &gi, GatherRegs &go) {
-                load_lists(v + 2, lo.bs, lo.ln, lo.av);
-                gather(v + 1, li.bs, li.ln, li.av, go.c, go.bv, go.av);
+                load_lists(v + D, lo.bs, lo.ln, lo.av);
+                gather(v + D - 1, li.bs, li.ln, li.av, go.c, go.bv, go.av);
                 int a, b;
                 item(v, a, b);
                 // a pair runs the rounds of both rows: from the narrower list
@@ -1878,25 +1894,31 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     }
                 }
             };
-            ListStageRegs la, lb;
-            GatherRegs ga, gb;
-            la.av = lb.av = 0.0;
-            {
-                ListStageRegs l0;
-                l0.av = 0.0;
-                load_lists(0, l0.bs, l0.ln, l0.av);
-                load_lists(1, la.bs, la.ln, la.av);
-                gather(0, l0.bs, l0.ln, l0.av, ga.c, ga.bv, ga.av);
+            // D register sets of each kind: item v's lists sit in set v mod D
+            // until its B entries are gathered into gather set v mod D (the
+            // arrays are indexed by unrolled constants: registers)
+            ListStageRegs l[D];
+            GatherRegs g[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                l[i].av = 0.0;
+                load_lists(i, l[i].bs, l[i].ln, l[i].av);
             }
-            // unrolled by two: the register sets alternate roles, so no
-            // register with a load in flight is copied at the loop latch
-            for (int v = 0; v < nv; v += 2) {
-                step(v, la, lb, ga, gb);
-                if (v + 1 < nv) step(v + 1, lb, la, gb, ga);
+#pragma unroll
+            for (int i = 0; i + 1 < D; ++i) gather(i, l[i].bs, l[i].ln, l[i].av, g[i].c, g[i].bv, g[i].av);
+            // unrolled by D: the register sets rotate roles, so no register
+            // with a load in flight is copied at the loop latch
+            for (int v = 0; v < nv; v += D) {
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+                    if (v + i < nv) step(v + i, l[(i + D - 1) % D], l[i], g[i], g[(i + D - 1) % D]);
             }
             // the stages loaded past the chunk's end are drained here, once
-            asm volatile("" ::"v"(ga.c), "v"(gb.c), "v"(la.ln), "v"(lb.ln), "v"(la.bs), "v"(lb.bs));
-            if constexpr (VALUES) asm volatile("" ::"v"(ga.bv), "v"(gb.bv), "v"(la.av), "v"(lb.av));
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                asm volatile("" ::"v"(g[i].c), "v"(l[i].ln), "v"(l[i].bs));
+                if constexpr (VALUES) asm volatile("" ::"v"(g[i].bv), "v"(l[i].av));
+            }
         };
         if (all_small) run(std::true_type{});
         else run(std::false_type{});
