@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "48fd3a3b16fb89229e8db6013f15565e0ef8e8fcd16ee3e45e4158c9c7c2a998",
-                 "fetch_kib": 1095451.2, "write_kib": 858622.6, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "d04b7bff520f523b8f224b8afbf2b9c818ea992ef7c92d29580a16d94e60a646",
+                 "fetch_kib": 1094165.8, "write_kib": 839565.9, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
