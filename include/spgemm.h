@@ -105,7 +105,7 @@ typedef enum {
                                     4 group, 5 block, 7 multi-register windows) is routed there,
                                     every other row to the heavy path; 6: every non-empty row to
                                     the heavy path */
-    SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (<= 4096) */
+    SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (64..2048) */
     SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
                                     per batch of heavy rows; 0 (default): 128 GiB, or 60% of
                                     the device memory free at the call when that is less.

@@ -27,7 +27,7 @@ struct spg_handle_s {
     int64_t group_max = kCapGroup;
     int64_t block_max = kCapBlock;
     int64_t force = -1;
-    int64_t heavy_lds_max = kCapBlock;
+    int64_t heavy_lds_max = kHeavyLdsCap;
     int64_t spill_budget_mb = 0;       // 0: half of the device memory free at the call
     int64_t grid_waves = 0;
     int64_t group_rows = 1;  // kernel of the wave-small class (see SPG_OPT_GROUP_ROWS)
@@ -283,8 +283,9 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
         ha.spill_col = reinterpret_cast<int32_t *>(sp);
         ha.spill_val = reinterpret_cast<double *>(sp + col_b);
         ha.leaf = reinterpret_cast<int32_t *>(sp + col_b + val_b);
-        ha.lds_cap = (int)h->heavy_lds_max;
-        const int grid = (int)std::min<int64_t>(hi - lo, h->num_cu);
+        ha.lds_cap = (int)std::min<int64_t>(h->heavy_lds_max, kHeavyLdsCap);
+        // 1024 / kHeavyNumThreads workgroups per CU
+        const int grid = (int)std::min<int64_t>(hi - lo, (int64_t)(1024 / kHeavyNumThreads) * h->num_cu);
         HIP_TRY(h, launch_numeric_heavy(a, b, ws, ha, grid, c_rpt, c_col, c_val, ctl, no, s));
     }
     h->heavy_batches += (int64_t)batches.size();
@@ -486,7 +487,7 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             h->accumulator = value;
             break;
         case SPG_OPT_HEAVY_LDS_MAX:
-            if (value < 64 || value > kCapBlock) return fail(h, SPG_ERR_ARG, "heavy LDS max out of range");
+            if (value < 64 || value > kHeavyLdsCap) return fail(h, SPG_ERR_ARG, "heavy LDS max out of range");
             h->heavy_lds_max = value;
             break;
         case SPG_OPT_SPILL_BUDGET_MB:

@@ -2577,7 +2577,8 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 // ---------------------------------------------------------------------------
 // heavy rows: more products than one workgroup's LDS holds
 //
-// One 1024-thread workgroup per row.  The row's lists are consumed left to
+// One 512-thread workgroup per row, two per compute unit (each merges its own
+// row, so one waits at a barrier while the other works).  The row's lists are consumed left to
 // right as aligned ranges [p 2^h, (p+1) 2^h) -- nodes of the merge tree --
 // each the largest one whose products fit in LDS; such a node is merged in
 // LDS exactly like a light row, a single list too long for LDS is scaled
@@ -2595,19 +2596,19 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 // ---------------------------------------------------------------------------
 // entries of each input staged per tile, and merge steps per thread (a tile
 // merges up to 2 kMergeWin entries, kMergeSteps per thread)
-constexpr int kMergeWin = kHeavyThreads * 2;
+constexpr int kMergeWin = kHeavyNumThreads * 2;
 constexpr int kMergeSteps = 4;
-constexpr int kWinPer = kMergeWin / kHeavyThreads;  // staged entries per thread and input
-static_assert(kHeavyThreads * kMergeSteps >= 2 * kMergeWin, "a tile's merge steps must cover both windows");
+constexpr int kWinPer = kMergeWin / kHeavyNumThreads;  // staged entries per thread and input
+static_assert(kHeavyNumThreads * kMergeSteps >= 2 * kMergeWin, "a tile's merge steps must cover both windows");
 
 struct MergeLds {
     int32_t xc[kMergeWin];
     double xv[kMergeWin];
     int32_t yc[kMergeWin];
     double yv[kMergeWin];
-    int32_t first_c[kHeavyThreads];
-    double first_v[kHeavyThreads];
-    int32_t last_c[kHeavyThreads];
+    int32_t first_c[kHeavyNumThreads];
+    double first_v[kHeavyNumThreads];
+    int32_t last_c[kHeavyNumThreads];
 };
 
 struct HeavyNode {
@@ -2629,7 +2630,7 @@ struct HeavyState {
     double carry_v;
     int has_carry;
     int64_t out;
-    int64_t scr[Team<kHeavyThreads>::kWaves + 1];
+    int64_t scr[Team<kHeavyNumThreads>::kWaves + 1];
 };
 
 enum HeavyAction { kActNode = 0, kActMerge = 1, kActPromote = 2, kActToC = 3, kActDone = 4, kActFail = 5 };
@@ -2659,7 +2660,7 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
         const int wx = win(nx, xs), wy = win(ny, ys);
 #pragma unroll
         for (int e = 0; e < kWinPer; ++e) {
-            const int i = tid + e * kHeavyThreads;
+            const int i = tid + e * kHeavyNumThreads;
             if (i < wx) {
                 pxc[e] = Xc[xs + i];
                 pxv[e] = Xv[xs + i];
@@ -2674,7 +2675,7 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
         const int wx = win(nx, xs), wy = win(ny, ys);
 #pragma unroll
         for (int e = 0; e < kWinPer; ++e) {
-            const int i = tid + e * kHeavyThreads;
+            const int i = tid + e * kHeavyNumThreads;
             if (i < wx) {
                 m.xc[i] = pxc[e];
                 m.xv[i] = pxv[e];
@@ -2771,7 +2772,7 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
             items += hd[j] ? 1 : 0;
         }
         int tot;
-        const int rank = Team<kHeavyThreads>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
+        const int rank = Team<kHeavyNumThreads>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
         tot = wave_uniform(tot);
         int64_t o = out + rank;
 #pragma unroll
@@ -2808,16 +2809,16 @@ struct HeavyBatch {
 };
 
 template <typename IA, typename IB>
-__global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
+__global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
     HeavyBatch hb, const void *a_rpt, Lists<IB> lists, const double *a_val,
     const int32_t *b_col, const double *b_val, const int64_t *c_rpt, int32_t *c_col, double *c_val,
     Ctl *ctl, NumOut no) {
-    constexpr size_t kUnion = sizeof(NumLds<kHeavyThreads, kCapBlock>) > sizeof(MergeLds)
-                                  ? sizeof(NumLds<kHeavyThreads, kCapBlock>)
+    constexpr size_t kUnion = sizeof(NumLds<kHeavyNumThreads, kHeavyLdsCap>) > sizeof(MergeLds)
+                                  ? sizeof(NumLds<kHeavyNumThreads, kHeavyLdsCap>)
                                   : sizeof(MergeLds);
     __shared__ __align__(16) unsigned char raw[kUnion];
     __shared__ HeavyState st;
-    auto &node_lds = *reinterpret_cast<NumLds<kHeavyThreads, kCapBlock> *>(raw);
+    auto &node_lds = *reinterpret_cast<NumLds<kHeavyNumThreads, kHeavyLdsCap> *>(raw);
     auto &mrg = *reinterpret_cast<MergeLds *>(raw);
     const int tid = threadIdx.x;
     __shared__ int64_t s_bi;
@@ -2834,7 +2835,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
         int32_t *leaf = hb.leaf + hb.leaf_off[bi];
         // list offsets inside the row's product space
         int64_t carry = 0;
-        for (int64_t lb = 0; lb < L; lb += kHeavyThreads) {
+        for (int64_t lb = 0; lb < L; lb += kHeavyNumThreads) {
             const int64_t l = lb + tid;
             int64_t ln = 0;
             if (l < L) {
@@ -2844,7 +2845,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                 ln = n;
             }
             int64_t tot;
-            const int64_t ex = Team<kHeavyThreads>::excl_scan(ln, &tot, st.scr, tid);
+            const int64_t ex = Team<kHeavyNumThreads>::excl_scan(ln, &tot, st.scr, tid);
             if (l < L) leaf[l] = (int32_t)(carry + ex);
             carry += wave_uniform(tot);
         }
@@ -2911,7 +2912,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                 const int64_t cap = root ? ccap : np;
                 int64_t len;
                 if (np <= hb.lds_cap && (l1 - l0) <= hb.lds_cap) {
-                    len = brmerge_range_lds<kHeavyThreads, kCapBlock, 1, IB>(
+                    len = brmerge_range_lds<kHeavyNumThreads, kHeavyLdsCap, 1, IB>(
                         node_lds, tid, a0 + l0, (int)(l1 - l0), lists, a_val, b_col, b_val, oc, ov, cap);
                 } else {
                     // one list longer than LDS: the scaled B row is the node
@@ -2919,7 +2920,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
                     int64_t bs;
                     int nb;
                     lists.get(a0 + l0, bs, nb);
-                    for (int64_t j = tid; j < np && j < cap; j += kHeavyThreads) {
+                    for (int64_t j = tid; j < np && j < cap; j += kHeavyNumThreads) {
                         oc[j] = b_col[bs + j];
                         ov[j] = a * b_val[bs + j];
                     }
@@ -2974,7 +2975,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_num_heavy(
             } else if (act == kActToC) {
                 const HeavyNode x = st.stack[0];
                 const int64_t n = x.len < ccap ? x.len : ccap;
-                for (int64_t j = tid; j < n; j += kHeavyThreads) {
+                for (int64_t j = tid; j < n; j += kHeavyNumThreads) {
                     c_col[cs + j] = bcol[x.buf][j];
                     c_val[cs + j] = bval[x.buf][j];
                 }
@@ -3002,7 +3003,7 @@ hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Worksp
     hb.leaf = h.leaf;
     hb.lds_cap = h.lds_cap;
 #define BRM_HEAVY(IA, IB)                                                                          \
-    hipLaunchKernelGGL((k_num_heavy<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, hb, A.rpt,    \
+    hipLaunchKernelGGL((k_num_heavy<IA, IB>), dim3(grid), dim3(kHeavyNumThreads), 0, s, hb, A.rpt,    \
                        ws_lists<IB>(A, B, ws), A.val, B.col, B.val, c_rpt, c_col, c_val, ctl, no)
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_HEAVY(int32_t, int32_t);
     else if (A.rpt_bytes == 4) BRM_HEAVY(int32_t, int64_t);
