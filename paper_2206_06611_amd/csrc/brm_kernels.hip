@@ -2602,10 +2602,12 @@ constexpr int kWinPer = kMergeWin / kHeavyNumThreads;  // staged entries per thr
 static_assert(kHeavyNumThreads * kMergeSteps >= 2 * kMergeWin, "a tile's merge steps must cover both windows");
 
 struct MergeLds {
-    int32_t xc[kMergeWin];
-    double xv[kMergeWin];
-    int32_t yc[kMergeWin];
-    double yv[kMergeWin];
+    // two window sets: a tile merges from one while the next tile's windows
+    // are staged into the other
+    int32_t xc[2][kMergeWin];
+    double xv[2][kMergeWin];
+    int32_t yc[2][kMergeWin];
+    double yv[2][kMergeWin];
     int32_t first_c[kHeavyNumThreads];
     double first_v[kHeavyNumThreads];
     int32_t last_c[kHeavyNumThreads];
@@ -2671,26 +2673,29 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
             }
         }
     };
-    auto stage = [&](int64_t xs, int64_t ys) {
+    auto stage = [&](int64_t xs, int64_t ys, int buf) {
         const int wx = win(nx, xs), wy = win(ny, ys);
 #pragma unroll
         for (int e = 0; e < kWinPer; ++e) {
             const int i = tid + e * kHeavyNumThreads;
             if (i < wx) {
-                m.xc[i] = pxc[e];
-                m.xv[i] = pxv[e];
+                m.xc[buf][i] = pxc[e];
+                m.xv[buf][i] = pxv[e];
             }
             if (i < wy) {
-                m.yc[i] = pyc[e];
-                m.yv[i] = pyv[e];
+                m.yc[buf][i] = pyc[e];
+                m.yv[buf][i] = pyv[e];
             }
         }
     };
     int64_t x0 = 0, y0 = 0, out = 0;  // uniform
+    int cur = 0;  // window set of the current tile
     fetch(0, 0);
-    stage(0, 0);
+    stage(0, 0, 0);
     __syncthreads();
     while (x0 < nx || y0 < ny) {
+        const int32_t *xc = m.xc[cur], *yc = m.yc[cur];
+        const double *xv = m.xv[cur], *yv = m.yv[cur];
         const int wx = win(nx, x0), wy = win(ny, y0);
         // the tile: every entry of both windows up to the column `lim`
         // (uniform values are moved to scalar registers)
@@ -2699,10 +2704,13 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
             const bool tx = x0 + wx < nx, ty = y0 + wy < ny;
             if (tx || ty) {
                 int32_t lim = INT32_MAX;
-                if (tx) lim = m.xc[wx - 1];
-                if (ty && m.yc[wy - 1] < lim) lim = m.yc[wy - 1];
-                cx = wave_uniform(upper_bound(m.xc, wx, wave_uniform(lim)));
-                cy = wave_uniform(upper_bound(m.yc, wy, wave_uniform(lim)));
+                if (tx) lim = xc[wx - 1];
+                if (ty && yc[wy - 1] < lim) lim = yc[wy - 1];
+                lim = wave_uniform(lim);
+                // a window whose last column is the limit is taken whole
+                // (sorted): only the other one is searched
+                if (!(tx && wave_uniform(xc[wx - 1]) == lim)) cx = wave_uniform(upper_bound(xc, wx, lim));
+                if (!(ty && wave_uniform(yc[wy - 1]) == lim)) cy = wave_uniform(upper_bound(yc, wy, lim));
             }
         }
         const int64_t nx0 = x0 + cx, ny0 = y0 + cy;
@@ -2715,32 +2723,54 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
         int32_t c[kMergeSteps];
         double v[kMergeSteps];
         if (cnt > 0) {
-            int x = mp_split_lds(m.xc, cx, m.yc, cy, s0);
-            int y = s0 - x;
+            const int x = mp_split_lds(xc, cx, yc, cy, s0);
+            const int y = s0 - x;
+            // the next kMergeSteps columns of each side, read together; the
+            // steps are then decided in registers and their values read
+            // together (two LDS round trips instead of one per step)
+            int32_t xs[kMergeSteps], ys[kMergeSteps];
+#pragma unroll
+            for (int j = 0; j < kMergeSteps; ++j) {
+                xs[j] = x + j < cx ? xc[x + j] : 0;
+                ys[j] = y + j < cy ? yc[y + j] : 0;
+            }
+            int ix = 0, iy = 0;
+            int src[kMergeSteps];  // entry of the step: x index, or ~y index
             int32_t last = 0;
 #pragma unroll
             for (int j = 0; j < kMergeSteps; ++j) {
                 c[j] = 0;
-                v[j] = 0.0;
+                src[j] = 0;
                 if (j < cnt) {
-                    if (x < cx && (y >= cy || m.xc[x] <= m.yc[y])) {
-                        c[j] = m.xc[x];
-                        v[j] = m.xv[x];
-                        ++x;
+                    int32_t xcur = xs[0], ycur = ys[0];
+#pragma unroll
+                    for (int q = 1; q <= j; ++q) {
+                        if (ix == q) xcur = xs[q];
+                        if (iy == q) ycur = ys[q];
+                    }
+                    if (x + ix < cx && (y + iy >= cy || xcur <= ycur)) {
+                        c[j] = xcur;
+                        src[j] = x + ix;
+                        ++ix;
                     } else {
-                        c[j] = m.yc[y];
-                        v[j] = m.yv[y];
-                        ++y;
+                        c[j] = ycur;
+                        src[j] = ~(y + iy);
+                        ++iy;
                     }
                     last = c[j];
                 }
             }
+#pragma unroll
+            for (int j = 0; j < kMergeSteps; ++j) v[j] = j < cnt ? (src[j] >= 0 ? xv[src[j]] : yv[~src[j]]) : 0.0;
             m.first_c[tid] = c[0];
             m.first_v[tid] = v[0];
             m.last_c[tid] = last;
         }
         const int nthr = (D + kMergeSteps - 1) / kMergeSteps;
         __syncthreads();
+        // every thread is done with this tile's windows; the next tile's
+        // windows go to the other set, made visible by the scan's barriers
+        stage(nx0, ny0, cur ^ 1);
         // heads (first entry of a column) and their values: the two entries
         // of a column are adjacent, the left one first
         bool nb = false;  // the next thread's first entry follows this thread's last
@@ -2788,10 +2818,9 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
         out += tot;
         x0 = nx0;
         y0 = ny0;
-        // every thread is done with the windows and the boundary arrays
-        __syncthreads();
-        stage(x0, y0);
-        __syncthreads();
+        cur ^= 1;
+        // the boundary arrays were read before the scan's barriers: the next
+        // tile may overwrite them
     }
     return out;
 }
