@@ -105,7 +105,8 @@ typedef enum {
                                     4 group, 5 block, 7 multi-register windows) is routed there,
                                     every other row to the heavy path; 6: every non-empty row to
                                     the heavy path */
-    SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (64..2048) */
+    SPG_OPT_HEAVY_LDS_MAX = 7,   /* leaf-range size the heavy path merges in LDS (64..4096;
+                                    512-thread workgroups merge at most 2048) */
     SPG_OPT_SPILL_BUDGET_MB = 8, /* device memory the heavy path may use for spill buffers
                                     per batch of heavy rows; 0 (default): 128 GiB, or 60% of
                                     the device memory free at the call when that is less.
@@ -115,6 +116,12 @@ typedef enum {
     SPG_OPT_LEARNED_FORCE = 11,  /* testing only: 1 sizes every predicted row at its lower bound
                                     (the longest list), so that most rows take the fallback */
     SPG_OPT_ACCUMULATOR = 13,    /* SPG_ACC_BRMERGE (default) or SPG_ACC_HASH: see below */
+    SPG_OPT_HEAVY_THREADS = 14,  /* workgroup size of the heavy path, one row per workgroup:
+                                    0 (default) chosen per batch of heavy rows -- 1024 threads
+                                    (one workgroup per CU) when the batch's longest row
+                                    outweighs 1.3x the batch's products over 2 x CUs, else 512
+                                    (two per CU); 512 or 1024 forces one.  Results are
+                                    bitwise the same */
     SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
                                     1 (default) one row per wavefront, merged in registers; the
                                     class then holds only rows whose lists fit power-of-two lane
@@ -179,6 +186,8 @@ typedef enum {
     SPG_STAT_SPILL_POOL_BYTES = 26,/* device bytes of the handle's heavy-row spill pool (kept
                                     between calls; a call whose batches fit it reuses it) */
     SPG_STAT_SPILL_ALLOCS = 27,  /* allocations of that pool since the handle was created */
+    SPG_STAT_HEAVY_WIDE = 28,    /* spill batches of the last numeric call run by 1024-thread
+                                    workgroups (the others by 512-thread ones) */
     SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call
                                     (16: a numeric row length differed from its symbolic count;
                                     the row was truncated to its slot).  Synchronizes the device. */

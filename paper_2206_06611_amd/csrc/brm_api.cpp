@@ -27,7 +27,8 @@ struct spg_handle_s {
     int64_t group_max = kCapGroup;
     int64_t block_max = kCapBlock;
     int64_t force = -1;
-    int64_t heavy_lds_max = kHeavyLdsCap;
+    int64_t heavy_lds_max = kHeavyLdsCapMax;
+    int64_t heavy_threads = 0;         // 0: chosen per batch; 512 or 1024
     int64_t spill_budget_mb = 0;       // 0: half of the device memory free at the call
     int64_t grid_waves = 0;
     int64_t group_rows = 1;  // kernel of the wave-small class (see SPG_OPT_GROUP_ROWS)
@@ -51,6 +52,7 @@ struct spg_handle_s {
     int64_t nnz = 0, nprod = 0;
     int64_t heavy_batches = 0;
     int64_t spill_allocs = 0;  // allocations of the spill pool
+    int64_t heavy_wide = 0;    // heavy batches of the last numeric call run by 1024-thread workgroups
     // learned allocation
     int64_t alloc = 0;          // 0 precise, 1 learned, 2 upper bound
     int64_t accumulator = 0;    // 0 BRMerge, 1 hash table (comparator)
@@ -283,9 +285,23 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
         ha.spill_col = reinterpret_cast<int32_t *>(sp);
         ha.spill_val = reinterpret_cast<double *>(sp + col_b);
         ha.leaf = reinterpret_cast<int32_t *>(sp + col_b + val_b);
-        ha.lds_cap = (int)std::min<int64_t>(h->heavy_lds_max, kHeavyLdsCap);
-        // 1024 / kHeavyNumThreads workgroups per CU
-        const int grid = (int)std::min<int64_t>(hi - lo, (int64_t)(1024 / kHeavyNumThreads) * h->num_cu);
+        int threads = (int)h->heavy_threads;
+        if (threads == 0) {
+            // a batch lasts at least as long as its longest row (its first),
+            // merged by one workgroup: 1024-thread workgroups (one per CU,
+            // each about 1.4x as fast on one row) when that row outweighs a
+            // 512-thread workgroup's share of the batch by a margin, else
+            // 512-thread workgroups (two per CU, more rows side by side)
+            int64_t tot = 0;
+            for (int64_t j = lo; j < hi; ++j) tot += info[3 * order[(size_t)j] + 1];
+            const int64_t longest = info[3 * order[(size_t)lo] + 1];
+            threads = (double)longest > 1.3 * (double)tot / (2.0 * (double)h->num_cu) ? 1024 : 512;
+        }
+        ha.threads = threads;
+        ha.lds_cap = (int)std::min<int64_t>(h->heavy_lds_max, 4 * (int64_t)threads);
+        // 1024 / threads workgroups per CU
+        const int grid = (int)std::min<int64_t>(hi - lo, (int64_t)(1024 / threads) * h->num_cu);
+        if (threads == 1024) ++h->heavy_wide;
         HIP_TRY(h, launch_numeric_heavy(a, b, ws, ha, grid, c_rpt, c_col, c_val, ctl, no, s));
     }
     h->heavy_batches += (int64_t)batches.size();
@@ -487,8 +503,13 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             h->accumulator = value;
             break;
         case SPG_OPT_HEAVY_LDS_MAX:
-            if (value < 64 || value > kHeavyLdsCap) return fail(h, SPG_ERR_ARG, "heavy LDS max out of range");
+            if (value < 64 || value > kHeavyLdsCapMax) return fail(h, SPG_ERR_ARG, "heavy LDS max out of range");
             h->heavy_lds_max = value;
+            break;
+        case SPG_OPT_HEAVY_THREADS:
+            if (value != 0 && value != 512 && value != 1024)
+                return fail(h, SPG_ERR_ARG, "heavy threads must be 0 (automatic), 512 or 1024");
+            h->heavy_threads = value;
             break;
         case SPG_OPT_SPILL_BUDGET_MB:
             if (value < 0) return fail(h, SPG_ERR_ARG, "spill budget must be >= 0 (0: automatic)");
@@ -528,6 +549,7 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_BLOCK_MAX: *value = h->block_max; break;
         case SPG_OPT_FORCE_CLASS: *value = h->force; break;
         case SPG_OPT_HEAVY_LDS_MAX: *value = h->heavy_lds_max; break;
+        case SPG_OPT_HEAVY_THREADS: *value = h->heavy_threads; break;
         case SPG_OPT_SPILL_BUDGET_MB: *value = h->spill_budget_mb; break;
         case SPG_OPT_GRID_WAVES: *value = h->grid_waves; break;
         case SPG_OPT_ALLOC: *value = h->alloc; break;
@@ -554,6 +576,7 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_GRAPH_LAUNCHES: *value = h->graph_launches; return SPG_OK;
         case SPG_STAT_SPILL_POOL_BYTES: *value = (int64_t)h->spill_bytes; return SPG_OK;
         case SPG_STAT_SPILL_ALLOCS: *value = h->spill_allocs; return SPG_OK;
+        case SPG_STAT_HEAVY_WIDE: *value = h->heavy_wide; return SPG_OK;
         case SPG_STAT_OVERFLOW_ROWS: *value = h->ovf_light + h->ovf_heavy; return SPG_OK;
         case SPG_STAT_PREDICTED_ROWS: {
             int64_t n = 0;
@@ -616,6 +639,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     h->plan_group_rows = gr;
     if (learned && !h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "learned allocation needs a trained or loaded predictor");
     h->heavy_batches = 0;
+    h->heavy_wide = 0;
     h->pred_total = h->ovf_light = h->ovf_heavy = 0;
     LearnedWs lw;
     RowFeatures rf{};
@@ -746,6 +770,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     Workspace ws;
     if ((rc = ensure_workspace(h, A->rows, A->nnz, &ws))) return rc;
     h->heavy_batches = 0;
+    h->heavy_wide = 0;
     NumOut exact;
     exact.bound = 0;
     exact.row_size = nullptr;

@@ -32,10 +32,10 @@ constexpr int kCapWave = 256;
 constexpr int kCapGroup = 1024;
 constexpr int kCapBlock = 4096;
 constexpr int kGroupRows = 4;  // rows of the wave-small class merged together by one wavefront
-// Heavy rows: 512-thread workgroups, two per compute unit, each merging its
-// own row; tree nodes of at most kHeavyLdsCap products (and lists) in LDS.
-constexpr int kHeavyNumThreads = 512;
-constexpr int kHeavyLdsCap = 2048;
+// Heavy rows: one workgroup per row, of 512 threads (two per compute unit)
+// or 1024 (one per compute unit), chosen per batch; tree nodes of at most
+// 4 x threads products (and lists) in LDS.
+constexpr int kHeavyLdsCapMax = 4096;
 
 struct Thresholds {
     int64_t wave_small_max;
@@ -137,7 +137,7 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 hipError_t launch_numeric_hash(const CsrView &A, const CsrView &B, const Workspace &ws, int cls, int num_cu,
                                const int64_t *c_rpt, int32_t *c_col, double *c_val, hipStream_t s);
 
-// Heavy rows: one 512-thread workgroup per row (two per CU), spill buffers in HBM.
+// Heavy rows: one workgroup of 512 or 1024 threads per row, spill buffers in HBM.
 struct HeavyArgs {
     unsigned long long *ticket;  // zeroed counter handing out the batch's rows
     const int32_t *rows;       // heavy row ids of this batch, largest first
@@ -148,6 +148,7 @@ struct HeavyArgs {
     double *spill_val;
     int32_t *leaf;
     int lds_cap;               // largest list range merged in LDS (products and lists)
+    int threads;               // 512 or 1024 threads per workgroup
 };
 hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, const int32_t *rows, int64_t n,
                              int64_t *info, hipStream_t s);

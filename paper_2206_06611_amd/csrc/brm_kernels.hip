@@ -2596,21 +2596,23 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 // ---------------------------------------------------------------------------
 // entries of each input staged per tile, and merge steps per thread (a tile
 // merges up to 2 kMergeWin entries, kMergeSteps per thread)
-constexpr int kMergeWin = kHeavyNumThreads * 2;
+// (the heavy kernel exists for T = 512 and T = 1024 threads per workgroup;
+// its LDS nodes hold at most 4 T products)
 constexpr int kMergeSteps = 4;
-constexpr int kWinPer = kMergeWin / kHeavyNumThreads;  // staged entries per thread and input
-static_assert(kHeavyNumThreads * kMergeSteps >= 2 * kMergeWin, "a tile's merge steps must cover both windows");
+constexpr int kWinPer = 2;  // staged entries per thread and input: windows of kWinPer T entries
+static_assert(kMergeSteps >= 2 * kWinPer, "a tile's merge steps must cover both windows");
 
+template <int T>
 struct MergeLds {
     // two window sets: a tile merges from one while the next tile's windows
     // are staged into the other
-    int32_t xc[2][kMergeWin];
-    double xv[2][kMergeWin];
-    int32_t yc[2][kMergeWin];
-    double yv[2][kMergeWin];
-    int32_t first_c[kHeavyNumThreads];
-    double first_v[kHeavyNumThreads];
-    int32_t last_c[kHeavyNumThreads];
+    int32_t xc[2][kWinPer * T];
+    double xv[2][kWinPer * T];
+    int32_t yc[2][kWinPer * T];
+    double yv[2][kWinPer * T];
+    int32_t first_c[T];
+    double first_v[T];
+    int32_t last_c[T];
 };
 
 struct HeavyNode {
@@ -2620,6 +2622,7 @@ struct HeavyNode {
     int buf;      // 0 / 1: spill buffer, 2: C
 };
 
+template <int T>
 struct HeavyState {
     HeavyNode stack[64];
     int sp;
@@ -2632,7 +2635,7 @@ struct HeavyState {
     double carry_v;
     int has_carry;
     int64_t out;
-    int64_t scr[Team<kHeavyNumThreads>::kWaves + 1];
+    int64_t scr[Team<T>::kWaves + 1];
 };
 
 enum HeavyAction { kActNode = 0, kActMerge = 1, kActPromote = 2, kActToC = 3, kActDone = 4, kActFail = 5 };
@@ -2650,9 +2653,11 @@ enum HeavyAction { kActNode = 0, kActMerge = 1, kActPromote = 2, kActToC = 3, kA
 // passes the first Y entry not yet consumed, and the next windows are read
 // before the tile writes.  Writes at most zcap entries; returns the merged
 // length (uniform).
-__device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t *Xc,
+template <int T>
+__device__ int64_t merge_hbm(MergeLds<T> &m, HeavyState<T> &st, int tid, const int32_t *Xc,
                              const double *Xv, int64_t nx, const int32_t *Yc, const double *Yv,
                              int64_t ny, int32_t *Zc, double *Zv, int64_t zcap) {
+    constexpr int kMergeWin = kWinPer * T;
     int32_t pxc[kWinPer], pyc[kWinPer];
     double pxv[kWinPer], pyv[kWinPer];
     auto win = [](int64_t n, int64_t at) -> int {
@@ -2662,7 +2667,7 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
         const int wx = win(nx, xs), wy = win(ny, ys);
 #pragma unroll
         for (int e = 0; e < kWinPer; ++e) {
-            const int i = tid + e * kHeavyNumThreads;
+            const int i = tid + e * T;
             if (i < wx) {
                 pxc[e] = Xc[xs + i];
                 pxv[e] = Xv[xs + i];
@@ -2677,7 +2682,7 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
         const int wx = win(nx, xs), wy = win(ny, ys);
 #pragma unroll
         for (int e = 0; e < kWinPer; ++e) {
-            const int i = tid + e * kHeavyNumThreads;
+            const int i = tid + e * T;
             if (i < wx) {
                 m.xc[buf][i] = pxc[e];
                 m.xv[buf][i] = pxv[e];
@@ -2802,7 +2807,7 @@ __device__ int64_t merge_hbm(MergeLds &m, HeavyState &st, int tid, const int32_t
             items += hd[j] ? 1 : 0;
         }
         int tot;
-        const int rank = Team<kHeavyNumThreads>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
+        const int rank = Team<T>::excl_scan(items, &tot, reinterpret_cast<int *>(st.scr), tid);
         tot = wave_uniform(tot);
         int64_t o = out + rank;
 #pragma unroll
@@ -2837,18 +2842,18 @@ struct HeavyBatch {
     int lds_cap;
 };
 
-template <typename IA, typename IB>
-__global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
+template <typename IA, typename IB, int T>
+__global__ __launch_bounds__(T, 4) void k_num_heavy(
     HeavyBatch hb, const void *a_rpt, Lists<IB> lists, const double *a_val,
     const int32_t *b_col, const double *b_val, const int64_t *c_rpt, int32_t *c_col, double *c_val,
     Ctl *ctl, NumOut no) {
-    constexpr size_t kUnion = sizeof(NumLds<kHeavyNumThreads, kHeavyLdsCap>) > sizeof(MergeLds)
-                                  ? sizeof(NumLds<kHeavyNumThreads, kHeavyLdsCap>)
-                                  : sizeof(MergeLds);
+    constexpr int kCap = 4 * T;  // products (and lists) of an LDS node
+    constexpr size_t kUnion = sizeof(NumLds<T, kCap>) > sizeof(MergeLds<T>) ? sizeof(NumLds<T, kCap>)
+                                                                            : sizeof(MergeLds<T>);
     __shared__ __align__(16) unsigned char raw[kUnion];
-    __shared__ HeavyState st;
-    auto &node_lds = *reinterpret_cast<NumLds<kHeavyNumThreads, kHeavyLdsCap> *>(raw);
-    auto &mrg = *reinterpret_cast<MergeLds *>(raw);
+    __shared__ HeavyState<T> st;
+    auto &node_lds = *reinterpret_cast<NumLds<T, kCap> *>(raw);
+    auto &mrg = *reinterpret_cast<MergeLds<T> *>(raw);
     const int tid = threadIdx.x;
     __shared__ int64_t s_bi;
     while (true) {
@@ -2864,7 +2869,7 @@ __global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
         int32_t *leaf = hb.leaf + hb.leaf_off[bi];
         // list offsets inside the row's product space
         int64_t carry = 0;
-        for (int64_t lb = 0; lb < L; lb += kHeavyNumThreads) {
+        for (int64_t lb = 0; lb < L; lb += T) {
             const int64_t l = lb + tid;
             int64_t ln = 0;
             if (l < L) {
@@ -2874,7 +2879,7 @@ __global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
                 ln = n;
             }
             int64_t tot;
-            const int64_t ex = Team<kHeavyNumThreads>::excl_scan(ln, &tot, st.scr, tid);
+            const int64_t ex = Team<T>::excl_scan(ln, &tot, st.scr, tid);
             if (l < L) leaf[l] = (int32_t)(carry + ex);
             carry += wave_uniform(tot);
         }
@@ -2941,7 +2946,7 @@ __global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
                 const int64_t cap = root ? ccap : np;
                 int64_t len;
                 if (np <= hb.lds_cap && (l1 - l0) <= hb.lds_cap) {
-                    len = brmerge_range_lds<kHeavyNumThreads, kHeavyLdsCap, 1, IB>(
+                    len = brmerge_range_lds<T, kCap, 1, IB>(
                         node_lds, tid, a0 + l0, (int)(l1 - l0), lists, a_val, b_col, b_val, oc, ov, cap);
                 } else {
                     // one list longer than LDS: the scaled B row is the node
@@ -2949,7 +2954,7 @@ __global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
                     int64_t bs;
                     int nb;
                     lists.get(a0 + l0, bs, nb);
-                    for (int64_t j = tid; j < np && j < cap; j += kHeavyNumThreads) {
+                    for (int64_t j = tid; j < np && j < cap; j += T) {
                         oc[j] = b_col[bs + j];
                         ov[j] = a * b_val[bs + j];
                     }
@@ -2985,7 +2990,7 @@ __global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
                 int32_t *oc = root ? c_col + cs : bcol[ob] + rx;
                 double *ov = root ? c_val + cs : bval[ob] + rx;
                 const int64_t cap = root ? ccap : (nprod - rx);
-                const int64_t len = merge_hbm(mrg, st, tid, bcol[x.buf] + rx, bval[x.buf] + rx, x.len,
+                const int64_t len = merge_hbm<T>(mrg, st, tid, bcol[x.buf] + rx, bval[x.buf] + rx, x.len,
                                               bcol[y.buf] + ry, bval[y.buf] + ry, y.len, oc, ov, cap);
                 if (tid == 0) {
                     st.sp -= 2;
@@ -3004,7 +3009,7 @@ __global__ __launch_bounds__(kHeavyNumThreads, 4) void k_num_heavy(
             } else if (act == kActToC) {
                 const HeavyNode x = st.stack[0];
                 const int64_t n = x.len < ccap ? x.len : ccap;
-                for (int64_t j = tid; j < n; j += kHeavyNumThreads) {
+                for (int64_t j = tid; j < n; j += T) {
                     c_col[cs + j] = bcol[x.buf][j];
                     c_val[cs + j] = bval[x.buf][j];
                 }
@@ -3031,9 +3036,15 @@ hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Worksp
     hb.spill_val = h.spill_val;
     hb.leaf = h.leaf;
     hb.lds_cap = h.lds_cap;
-#define BRM_HEAVY(IA, IB)                                                                          \
-    hipLaunchKernelGGL((k_num_heavy<IA, IB>), dim3(grid), dim3(kHeavyNumThreads), 0, s, hb, A.rpt,    \
-                       ws_lists<IB>(A, B, ws), A.val, B.col, B.val, c_rpt, c_col, c_val, ctl, no)
+#define BRM_HEAVY(IA, IB)                                                                              \
+    do {                                                                                               \
+        if (h.threads == 1024)                                                                         \
+            hipLaunchKernelGGL((k_num_heavy<IA, IB, 1024>), dim3(grid), dim3(1024), 0, s, hb, A.rpt,  \
+                               ws_lists<IB>(A, B, ws), A.val, B.col, B.val, c_rpt, c_col, c_val, ctl, no); \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_num_heavy<IA, IB, 512>), dim3(grid), dim3(512), 0, s, hb, A.rpt,    \
+                               ws_lists<IB>(A, B, ws), A.val, B.col, B.val, c_rpt, c_col, c_val, ctl, no); \
+    } while (0)
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_HEAVY(int32_t, int32_t);
     else if (A.rpt_bytes == 4) BRM_HEAVY(int32_t, int64_t);
     else if (B.rpt_bytes == 4) BRM_HEAVY(int64_t, int32_t);

@@ -26,12 +26,53 @@ def run(h, A, B):
     return C
 
 
-@pytest.fixture()
-def handle():
+@pytest.fixture(params=[512, 1024])
+def handle(request):
+    # both heavy kernels (512- and 1024-thread workgroups) on every case
     h = brm.Handle(0)
     h.set_option(brm.OPT_VALIDATE, 1)
+    h.set_option(brm.OPT_HEAVY_THREADS, request.param)
+    print(f"heavy workgroups of {request.param} threads", flush=True)
     yield h
     h.close()
+
+
+def _uniform_heavy(nrows, lists, blen, ncols, seed):
+    """A (nrows x K) whose rows each take `lists` B rows of `blen` entries:
+    every row has lists * blen products (heavy beyond 4096)."""
+    rng = np.random.default_rng(seed)
+    K = lists * 8
+    b_cols = [np.sort(rng.choice(ncols, size=blen, replace=False)) for _ in range(K)]
+    B = synth.CSR(K, ncols, np.arange(0, K * blen + 1, blen, dtype=np.int32),
+                  np.concatenate(b_cols).astype(np.int32), rng.uniform(-1, 1, K * blen))
+    a_cols = [np.sort(rng.choice(K, size=lists, replace=False)) for _ in range(nrows)]
+    A = synth.CSR(nrows, K, np.arange(0, nrows * lists + 1, lists, dtype=np.int32),
+                  np.concatenate(a_cols).astype(np.int32), rng.uniform(-1, 1, nrows * lists))
+    return A, B
+
+
+def test_heavy_threads_chosen_per_batch():
+    # many heavy rows of equal size: 512-thread workgroups; one row far
+    # longer than a workgroup's share: 1024-thread workgroups
+    h = brm.Handle(0)
+    try:
+        h.set_option(brm.OPT_VALIDATE, 1)
+        A, B = _uniform_heavy(2400, 5, 1000, 20000, 25)
+        print("case: 2400 heavy rows of 5000 products", flush=True)
+        C = run(h, A, B)
+        assert h.stat(brm.STAT_HEAVY_BATCHES) == 1 and h.stat(brm.STAT_HEAVY_WIDE) == 0
+        assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+        # one more row taking every list of B: 40000 products
+        K = B.rows
+        A2 = synth.CSR(A.rows + 1, K, np.concatenate([A.rpt, [A.rpt[-1] + K]]).astype(np.int32),
+                       np.concatenate([A.col, np.arange(K)]).astype(np.int32),
+                       np.concatenate([A.val, np.ones(K)]))
+        print("case: plus one row of 40000 products", flush=True)
+        C2 = run(h, A2, B)
+        assert h.stat(brm.STAT_HEAVY_BATCHES) == 1 and h.stat(brm.STAT_HEAVY_WIDE) == 1
+        assert_matches_oracle(C2, oracle.spgemm(A2, B), oracle.brmerge(A2, B))
+    finally:
+        h.close()
 
 
 def test_rmat_all_rows_heavy(handle):
