@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "d04b7bff520f523b8f224b8afbf2b9c818ea992ef7c92d29580a16d94e60a646",
-                 "fetch_kib": 1094165.8, "write_kib": 839565.9, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "589baa841f4e3300a93f78e54f86014faa3268941fe76bb5ae13ea28f39622fc",
+                 "fetch_kib": 1094315.6, "write_kib": 840011.2, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
