@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "589baa841f4e3300a93f78e54f86014faa3268941fe76bb5ae13ea28f39622fc",
+    "er8_2e20": {"sources_sha256": "99f0f3e9f5418a1d5efbb5e1fc496bf0eb8a93d646cbfd314cae38bbfb66cc8c",
                  "fetch_kib": 1094315.6, "write_kib": 840011.2, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 

@@ -29,7 +29,7 @@ struct spg_handle_s {
     int64_t force = -1;
     int64_t heavy_lds_max = kHeavyLdsCapMax;
     int64_t heavy_threads = 0;         // 0: chosen per batch; 512 or 1024
-    int64_t spill_budget_mb = 0;       // 0: half of the device memory free at the call
+    int64_t spill_budget_mb = 0;       // 0: 128 GiB, or 60% of the device memory free at the call
     int64_t grid_waves = 0;
     int64_t group_rows = 1;  // kernel of the wave-small class (see SPG_OPT_GROUP_ROWS)
     int plan_group_rows = 1;  // the one the last symbolic pass classified for

@@ -2577,8 +2577,10 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 // ---------------------------------------------------------------------------
 // heavy rows: more products than one workgroup's LDS holds
 //
-// One 512-thread workgroup per row, two per compute unit (each merges its own
-// row, so one waits at a barrier while the other works).  The row's lists are consumed left to
+// One workgroup of T threads per row: T = 512 (two per compute unit, each
+// merging its own row, so one waits at a barrier while the other works; LDS
+// nodes of 2048 products) or T = 1024 (one per compute unit, nodes of 4096:
+// faster on one very long row).  The row's lists are consumed left to
 // right as aligned ranges [p 2^h, (p+1) 2^h) -- nodes of the merge tree --
 // each the largest one whose products fit in LDS; such a node is merged in
 // LDS exactly like a light row, a single list too long for LDS is scaled
