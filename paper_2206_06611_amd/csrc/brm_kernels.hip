@@ -399,6 +399,23 @@ __global__ __launch_bounds__(256) void k_bin(int64_t M, const int32_t *rows, con
     __shared__ int64_t s_base[kNumClasses];
     __shared__ int s_wave_cnt[kNumClasses];
     const int lane = lane_id();
+    if (rows == nullptr) {
+        // every row in one class (the counts hold exactly these M rows):
+        // the class list is the identity, written as one coalesced stream
+        int64_t tot = 0;
+        bool one = false;
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) {
+            const int64_t k = ctl->count[c];
+            tot += k;
+            one = one || k == M;
+        }
+        if (tot == M && one) {
+            for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
+                class_rows[i] = (int32_t)i;
+            return;
+        }
+    }
     // every workgroup bins one contiguous range of rows, so the rows of a
     // class sit in row order inside each workgroup's reservation
     const int64_t per = ((M + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
