@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "99f0f3e9f5418a1d5efbb5e1fc496bf0eb8a93d646cbfd314cae38bbfb66cc8c",
-                 "fetch_kib": 1094315.6, "write_kib": 840011.2, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "0beee35485282913f8a97f9cd65c0cafb32983209e0aff0de6ade608b5ac742c",
+                 "fetch_kib": 1093652.3, "write_kib": 842624.2, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
