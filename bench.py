@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "0beee35485282913f8a97f9cd65c0cafb32983209e0aff0de6ade608b5ac742c",
+    "er8_2e20": {"sources_sha256": "acc171537a76b063060303b2534dc876ba4c1e6a44e95f7a45c92419fe1780d6",
                  "fetch_kib": 1093652.3, "write_kib": 842624.2, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 

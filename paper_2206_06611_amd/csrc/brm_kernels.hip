@@ -1671,7 +1671,8 @@ __device__ __forceinline__ T load_opaque(const T *p) {
 // and C row pointers are loaded at once (lane j holds row j's), so the
 // per-row chain of dependent loads is list descriptors -> B entries only, and
 // that chain is software-pipelined: while row j merges, the B entries of row
-// j+1 and the list descriptors of row j+2 are in flight.  Every lane issues
+// j+D-1 and the list descriptors of row j+D are in flight (D = kWinNumDepth
+// for the numeric pass, 2 for counts).  Every lane issues
 // every load of a stage on every iteration (masked lanes read the sentinels
 // above), so the number of memory operations in flight does not depend on
 // the path and the waits stay partial.  Rows 2i and 2i+1 of a chunk whose
