@@ -875,9 +875,50 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t M, const in
     }
 }
 
+// The top-level scan folded into the apply pass, for at most kScanFusedTiles
+// tiles: every block adds up the sums of the tiles before its own (one
+// strided pass and a block reduction), the last one also writes the total.
+constexpr int64_t kScanFusedTiles = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply_fused(int64_t M, int64_t ntiles,
+                                                                   const int32_t *row_size,
+                                                                   const int64_t *tile_sum, int64_t *c_rpt,
+                                                                   int64_t *total) {
+    __shared__ int64_t scr[Team<kScanThreads>::kWaves + 1];
+    int64_t before = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) before += tile_sum[i];
+    before = Team<kScanThreads>::sum(before, scr, threadIdx.x);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = base + j < M ? row_size[base + j] : 0;
+        s += v[j];
+    }
+    int64_t tot;
+    int64_t run = before + Team<kScanThreads>::excl_scan(s, &tot, scr, threadIdx.x);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        if (base + j < M) c_rpt[base + j] = run;
+        run += v[j];
+    }
+    if ((int64_t)blockIdx.x == ntiles - 1 && threadIdx.x == 0) {
+        *total = before + tot;
+        c_rpt[M] = before + tot;
+    }
+}
+
 hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
                        int64_t *total, hipStream_t s) {
     const int64_t ntiles = (M + kScanTile - 1) / kScanTile;
+    if (ntiles > 0 && ntiles <= kScanFusedTiles) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, sizes,
+                           tile_sum);
+        hipLaunchKernelGGL(k_scan_apply_fused, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, ntiles,
+                           sizes, tile_sum, out_rpt, total);
+        return hipGetLastError();
+    }
     if (ntiles > 0)
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, sizes,
                            tile_sum);
