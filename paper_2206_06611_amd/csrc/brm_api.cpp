@@ -661,8 +661,12 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         HIP_TRY(h, launch_analysis(a, b, th, ws, g, s, learned ? &rf : nullptr));
         HIP_TRY(h, launch_bin(M, ws, g, s));
         if (!slotted) {
-            for (int cls : {(int)kClassWaveSmall, (int)kClassMulti, (int)kClassWave, (int)kClassGroup,
-                            (int)kClassBlock, (int)kClassHeavy})
+            HIP_TRY(h, launch_symbolic(a, b, ws, kClassWaveSmall, persistent_grid(h, kClassWaveSmall, -1, gr), s, gr));
+            // the multi-register, wave and group classes share one launch
+            HIP_TRY(h, launch_symbolic_mid(a, b, ws, persistent_grid(h, kClassMulti, -1, gr),
+                                           persistent_grid(h, kClassWave, -1, gr),
+                                           persistent_grid(h, kClassGroup, -1, gr), s));
+            for (int cls : {(int)kClassBlock, (int)kClassHeavy})
                 HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1, gr), s, gr));
         }
     }

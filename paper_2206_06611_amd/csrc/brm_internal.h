@@ -119,6 +119,10 @@ hipError_t launch_bin_list(int64_t n, const int32_t *rows, const uint8_t *row_cl
                            Ctl *ctl, hipStream_t s);
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                            int grid, hipStream_t s, int group_rows);
+// the symbolic passes of the multi-register, wave and group classes in one
+// launch of g_mw + g_wave + g_group workgroups of 256 threads
+hipError_t launch_symbolic_mid(const CsrView &A, const CsrView &B, const Workspace &ws, int g_mw, int g_wave,
+                               int g_group, hipStream_t s);
 hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
                        int64_t *total, hipStream_t s);
 

@@ -599,21 +599,30 @@ __device__ __forceinline__ int sym_hash_row(SymLds<T, TS> &s, int tid, int64_t r
     return total;
 }
 
+// the rows of one class counted by LDS hash, TEAMS rows at a time per
+// workgroup; `block` of `grid` workgroups take part
+template <int T, int TEAMS, int TS, typename IA, typename IB>
+__device__ __forceinline__ void sym_hash_rows(SymLds<T, TS> *lds, int cls, int64_t block, int64_t grid,
+                                              const void *a_rpt, const Lists<IB> &lists, const int32_t *b_col,
+                                              const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
+    const int team = threadIdx.x / T, tid = threadIdx.x % T;
+    SymLds<T, TS> &s = lds[team];
+    const int64_t count = ctl->count[cls];
+    const int64_t start = class_start(ctl, cls);
+    for (int64_t idx = block * TEAMS + team; idx < count; idx += grid * TEAMS) {
+        const int64_t row = class_rows[start + idx];
+        const int total = sym_hash_row<T, TS, IA, IB>(s, tid, row, a_rpt, lists, b_col);
+        if (tid == 0) row_size[row] = total;
+    }
+}
+
 template <int T, int TEAMS, int TS, typename IA, typename IB>
 __global__ __launch_bounds__(T *TEAMS) void k_sym_hash(
     int cls, const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
     const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
     __shared__ SymLds<T, TS> lds[TEAMS];
-    const int team = threadIdx.x / T, tid = threadIdx.x % T;
-    SymLds<T, TS> &s = lds[team];
-    const int64_t count = ctl->count[cls];
-    const int64_t start = class_start(ctl, cls);
-    for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count;
-         idx += (int64_t)gridDim.x * TEAMS) {
-        const int64_t row = class_rows[start + idx];
-        const int total = sym_hash_row<T, TS, IA, IB>(s, tid, row, a_rpt, lists, b_col);
-        if (tid == 0) row_size[row] = total;
-    }
+    sym_hash_rows<T, TEAMS, TS, IA, IB>(lds, cls, blockIdx.x, gridDim.x, a_rpt, lists, b_col, class_rows,
+                                        row_size, ctl);
 }
 
 // symbolic for heavy rows: LDS bitmap over column slabs of kBitmapBits
@@ -2368,6 +2377,51 @@ __global__ __launch_bounds__(256) void k_sym_mw(int cls, const void *a_rpt, List
     mw_rows<false, IA, IB>(cls, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows, nullptr, nullptr,
                            nullptr, row_size, ctl, no, nullptr, (int64_t)blockIdx.x * 4 + team,
                            (int64_t)gridDim.x * 4);
+}
+
+// The symbolic passes of the multi-register window, wave and group classes
+// (all 256-thread workgroups) in one launch: workgroups [0, g_mw) count the
+// multi-register rows, the next g_wave the wave class by LDS hash (four rows
+// per workgroup), the last g_group the group class (one row per workgroup).
+// A class without rows then costs no launch of its own.
+template <typename IA, typename IB>
+__global__ __launch_bounds__(256) void k_sym_mid(const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
+                                                 const uint8_t *row_class, const int32_t *class_rows,
+                                                 int32_t *row_size, Ctl *ctl, int g_mw, int g_wave, int g_group) {
+    using WaveLds = SymLds<64, 2 * kCapWave>;
+    using GroupLds = SymLds<256, 2 * kCapGroup>;
+    constexpr size_t kWaveBytes = 4 * sizeof(WaveLds), kGroupBytes = sizeof(GroupLds);
+    __shared__ __align__(16) unsigned char raw[kWaveBytes > kGroupBytes ? kWaveBytes : kGroupBytes];
+    const int b = blockIdx.x;  // uniform: every workgroup takes one branch whole
+    if (b < g_mw) {
+        const int team = wave_uniform((int)(threadIdx.x / kWave));
+        NumOut no;
+        no.bound = 0;
+        mw_rows<false, IA, IB>(kClassMulti, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows, nullptr,
+                               nullptr, nullptr, row_size, ctl, no, nullptr, (int64_t)b * 4 + team,
+                               (int64_t)g_mw * 4);
+    } else if (b < g_mw + g_wave) {
+        sym_hash_rows<64, 4, 2 * kCapWave, IA, IB>(reinterpret_cast<WaveLds *>(raw), kClassWave, b - g_mw, g_wave,
+                                                   a_rpt, lists, b_col, class_rows, row_size, ctl);
+    } else {
+        sym_hash_rows<256, 1, 2 * kCapGroup, IA, IB>(reinterpret_cast<GroupLds *>(raw), kClassGroup,
+                                                     b - g_mw - g_wave, g_group, a_rpt, lists, b_col, class_rows,
+                                                     row_size, ctl);
+    }
+}
+
+hipError_t launch_symbolic_mid(const CsrView &A, const CsrView &B, const Workspace &ws, int g_mw, int g_wave,
+                               int g_group, hipStream_t s) {
+    const int grid = g_mw + g_wave + g_group;
+#define BRM_SYM_MID(IA, IB)                                                                                  \
+    hipLaunchKernelGGL((k_sym_mid<IA, IB>), dim3(grid), dim3(256), 0, s, A.rpt, ws_lists<IB>(A, B, ws), B.col, \
+                       ws.row_class, ws.class_rows, ws.row_size, ws.ctl, g_mw, g_wave, g_group)
+    if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_SYM_MID(int32_t, int32_t);
+    else if (A.rpt_bytes == 4) BRM_SYM_MID(int32_t, int64_t);
+    else if (B.rpt_bytes == 4) BRM_SYM_MID(int64_t, int32_t);
+    else BRM_SYM_MID(int64_t, int64_t);
+#undef BRM_SYM_MID
+    return hipGetLastError();
 }
 
 // Several short rows per team: the rows of a class whose lists and products
