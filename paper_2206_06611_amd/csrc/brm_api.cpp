@@ -213,10 +213,33 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     std::vector<int64_t> info(3 * (size_t)n);
     HIP_TRY(h, hipMemcpyAsync(info.data(), d_info, 24 * (size_t)n, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
+    // rows ordered largest first, to within an eighth of an octave: one
+    // counting-sort pass over logarithmic buckets of the product count (a
+    // full comparison sort of ~3e5 rows cost ~40 ms of host time per call),
+    // visiting the rows by row id so that the order, and with it the batches
+    // and the spill pool they need, is the same on every call (the heavy rows
+    // arrive in the class list's order, which is not); the order decides
+    // batching and load balance only, never a result
     std::vector<int64_t> order((size_t)n);
-    for (int64_t i = 0; i < n; ++i) order[(size_t)i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int64_t x, int64_t y) { return info[3 * x + 1] > info[3 * y + 1]; });
+    {
+        std::vector<int32_t> at((size_t)a.rows, -1);  // info index of every heavy row
+        for (int64_t i = 0; i < n; ++i) at[(size_t)info[3 * i]] = (int32_t)i;
+        std::vector<uint8_t> bucket((size_t)n);
+        int64_t cnt[257] = {0};
+        for (int64_t i = 0; i < n; ++i) {
+            const uint64_t v = (uint64_t)std::max<int64_t>(info[3 * i + 1], 1);
+            const int lg = 63 - __builtin_clzll(v);
+            const int frac = lg >= 3 ? (int)((v >> (lg - 3)) & 7) : (int)((v << (3 - lg)) & 7);
+            const int bk = 255 - (8 * lg + frac);  // larger counts first
+            bucket[(size_t)i] = (uint8_t)(bk < 0 ? 0 : bk);
+            ++cnt[bucket[(size_t)i] + 1];
+        }
+        for (int k = 0; k < 256; ++k) cnt[k + 1] += cnt[k];
+        for (int64_t r = 0; r < a.rows; ++r) {
+            const int32_t i = at[(size_t)r];
+            if (i >= 0) order[(size_t)cnt[bucket[(size_t)i]]++] = i;
+        }
+    }
     std::vector<int32_t> rows((size_t)n);
     std::vector<int64_t> soff((size_t)n), loff((size_t)n);
     std::vector<std::pair<int64_t, int64_t>> batches;  // [begin, end)
@@ -287,14 +310,17 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
         ha.leaf = reinterpret_cast<int32_t *>(sp + col_b + val_b);
         int threads = (int)h->heavy_threads;
         if (threads == 0) {
-            // a batch lasts at least as long as its longest row (its first),
-            // merged by one workgroup: 1024-thread workgroups (one per CU,
-            // each about 1.4x as fast on one row) when that row outweighs a
-            // 512-thread workgroup's share of the batch by a margin, else
-            // 512-thread workgroups (two per CU, more rows side by side)
-            int64_t tot = 0;
-            for (int64_t j = lo; j < hi; ++j) tot += info[3 * order[(size_t)j] + 1];
-            const int64_t longest = info[3 * order[(size_t)lo] + 1];
+            // a batch lasts at least as long as its longest row, merged by
+            // one workgroup: 1024-thread workgroups (one per CU, each about
+            // 1.4x as fast on one row) when that row outweighs a 512-thread
+            // workgroup's share of the batch by a margin, else 512-thread
+            // workgroups (two per CU, more rows side by side)
+            int64_t tot = 0, longest = 0;
+            for (int64_t j = lo; j < hi; ++j) {
+                const int64_t np = info[3 * order[(size_t)j] + 1];
+                tot += np;
+                longest = std::max(longest, np);
+            }
             threads = (double)longest > 1.3 * (double)tot / (2.0 * (double)h->num_cu) ? 1024 : 512;
         }
         ha.threads = threads;
