@@ -128,3 +128,35 @@ def test_rmat_scale21_row_blocks():
     print("nnz(C)", total_nnz, "nprod", int(nprod.sum()), flush=True)
     assert total_nnz <= int(nprod.sum())
     h.close()
+
+
+@pytest.mark.parametrize("rows", [4096 * 1024, 4096 * 1024 + 1, 5_000_000])
+def test_row_pointer_scan_either_side_of_fused_limit(rows):
+    # the row-pointer scan folds its top level into the apply pass up to 1024
+    # tiles of 4096 rows and runs three passes beyond: a scaled permutation
+    # squared has one entry per row, C[i, p[p[i]]] = a[i] * a[p[i]]
+    print(f"case: permutation squared, {rows} rows", flush=True)
+    rng = np.random.default_rng(rows)
+    p = rng.permutation(rows).astype(np.int32)
+    a = rng.uniform(0.5, 2.0, rows)
+    empty = rng.random(rows) < 0.25  # a quarter of the rows empty: uneven tiles
+    cnt = (~empty).astype(np.int64)
+    rpt = np.zeros(rows + 1, np.int64)
+    rpt[1:] = np.cumsum(cnt)
+    A = synth.CSR(rows, rows, rpt, p[~empty], a[~empty])
+    dA = brm.DeviceCSR.from_host(A)
+    h = brm.Handle(0)
+    try:
+        C = h.spgemm(dA, dA)
+        torch.cuda.synchronize()
+        assert h.stat(brm.STAT_DEVICE_ERR) == 0
+        c_rpt = C.rpt.cpu().numpy()
+        # row i has an entry iff row i and row p[i] of A are both nonempty
+        has = ~empty & ~empty[p]
+        exp_rpt = np.zeros(rows + 1, np.int64)
+        exp_rpt[1:] = np.cumsum(has)
+        assert np.array_equal(c_rpt, exp_rpt)
+        assert np.array_equal(C.col.cpu().numpy(), p[p][has])
+        assert np.array_equal(C.val.cpu().numpy(), (a * a[p])[has])
+    finally:
+        h.close()
