@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "0305d04d4644f8f569da292b25fcff0a495a235c2d7c7ca0a7a7eb661f0708fe",
-                 "fetch_kib": 1093562.4, "write_kib": 842552.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "ac492352f5feb46d2a6766876fb2ec23c1a0b135909eba1a736f7e2fdd7b430e",
+                 "fetch_kib": 1093665.4, "write_kib": 842541.3, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 

@@ -626,6 +626,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_sym_hash(
 }
 
 // symbolic for heavy rows: LDS bitmap over column slabs of kBitmapBits
+constexpr int kBitmapUnroll = 8;  // products per thread whose column gathers are in flight together
 constexpr int kBitmapWords = 32768;  // 128 KB
 constexpr int64_t kBitmapBits = (int64_t)kBitmapWords * 32;
 constexpr int kHeavyThreads = 1024;
@@ -648,12 +649,40 @@ __global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
         for (int64_t lo = 0; lo < ncols; lo += kBitmapBits) {
             for (int w = tid; w < kBitmapWords; w += kHeavyThreads) bm[w] = 0u;
             __syncthreads();
-            for_each_product<kHeavyThreads, IB>(st, tid, a0, L, lists,
-                                                [&](int64_t, int64_t q, int) {
-                                                        const int64_t c = (int64_t)b_col[q] - lo;
-                                                        if (c >= 0 && c < kBitmapBits)
-                                                            atomicOr(&bm[c >> 5], 1u << (c & 31));
-                                                    });
+            // the lists in chunks of kHeavyThreads; every thread takes
+            // kBitmapUnroll products of a chunk at a time and gathers their
+            // columns before setting any bit, so the gathers are in flight
+            // together
+            for (int64_t lb = 0; lb < L; lb += kHeavyThreads) {
+                const int64_t l = lb + tid;
+                int ln = 0;
+                int64_t bs = 0;
+                if (l < L) lists.get(a0 + l, bs, ln);
+                int tot;
+                const int ex = Team<kHeavyThreads>::excl_scan(ln, &tot, st.scan, tid);
+                st.bs[tid] = bs;
+                st.off[tid] = ex;
+                const int nl = (int)((L - lb) < kHeavyThreads ? (L - lb) : kHeavyThreads);
+                __syncthreads();
+                for (int qb = 0; qb < tot; qb += kBitmapUnroll * kHeavyThreads) {
+                    int32_t col[kBitmapUnroll];
+#pragma unroll
+                    for (int u = 0; u < kBitmapUnroll; ++u) {
+                        const int q = qb + u * kHeavyThreads + tid;
+                        col[u] = -1;
+                        if (q < tot) {
+                            const int t = upper_bound(st.off, nl, q) - 1;
+                            col[u] = b_col[st.bs[t] + (q - st.off[t])];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBitmapUnroll; ++u) {
+                        const int64_t c = (int64_t)col[u] - lo;
+                        if (col[u] >= 0 && c >= 0 && c < kBitmapBits) atomicOr(&bm[c >> 5], 1u << (c & 31));
+                    }
+                }
+                __syncthreads();
+            }
             int64_t cnt = 0;
             for (int w = tid; w < kBitmapWords; w += kHeavyThreads) cnt += __popc(bm[w]);
             total += Team<kHeavyThreads>::sum(cnt, red, tid);
