@@ -76,7 +76,7 @@ typedef struct {
     const void *rpt;     /* rows + 1 entries of int32 or int64 */
     int32_t rpt_bytes;   /* 4 or 8 */
     const int32_t *col;  /* nnz entries */
-    const double *val;   /* nnz entries (may be NULL for spgemm_symbolic) */
+    const double *val;   /* nnz entries (may be NULL for spgemm_symbolic of the precise method) */
 } spg_csr;
 
 typedef struct spg_handle_s *spg_handle;
@@ -198,16 +198,27 @@ int spg_get_stat(spg_handle h, int key, int64_t *value);
 /* Symbolic pass of the precise allocation (Section II-B.2, Section III-D.2
  * steps 1-4): per-row product counts and binning, the exact number of
  * distinct columns of every row of C, and their exclusive prefix sum.
- *   A, B   : device CSR inputs (values not read).
+ *   A, B   : device CSR inputs.  With SPG_ALLOC_PRECISE the values are not
+ *            read and val may be NULL.
  *   c_rpt  : device int64[A->rows + 1], written with C's row pointers.
  *   c_nnz  : host int64, written with nnz(C).
  * This call BLOCKS until c_nnz is known (one device-to-host copy).  The row
  * analysis it makes is kept in the handle for the next spgemm_numeric call
- * with the same A and B.  With SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER
- * (spg_option) it computes the rows into slots in handle memory instead and
- * derives c_rpt from their exact lengths; the same contract holds.
+ * with the same A and B.
+ * With SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER (spg_option) this call already
+ * computes the rows, values included, into slots in handle memory and
+ * derives c_rpt from their exact lengths: A->val and B->val must then be
+ * non-NULL (else SPG_ERR_ARG before any launch), and C's values are those
+ * of the inputs at THIS call.  spgemm_numeric copies the rows from their
+ * slots; under SPG_ALLOC_UPPER every row comes from its slot, under
+ * SPG_ALLOC_LEARNED the rows that overflowed their predicted slot
+ * (SPG_STAT_OVERFLOW_ROWS) are recomputed by spgemm_numeric from the values
+ * at that call.  The values must therefore stay unchanged between the two
+ * calls in these modes; with SPG_ALLOC_PRECISE spgemm_numeric reads them.
  * Errors: SPG_ERR_ARG, SPG_ERR_DIM, SPG_ERR_INVALID_CSR (validation on),
  * SPG_ERR_NOT_TRAINED (learned allocation without a predictor),
+ * SPG_ERR_CAPACITY (a row of C has 2^31 or more products: the row kernels
+ * count a row's products in int32; no row is computed then),
  * SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c_rpt,
                     int64_t *c_nnz, void *stream);

@@ -18,15 +18,18 @@
  *    method under test only.  The sum of absolute products is returned too.
  *
  * 2. oracle_brmerge_rows -- the accumulation method of Section III-B
- *    (Algorithm 1) executed as the paper states it, one row at a time:
- *    a multiplying phase that appends the scaled rows B_k* for the entries of
- *    A_i* in stored order into one buffer while recording where each list
- *    starts, then an accumulating phase made of rounds; every round merges
- *    the lists two by two in order (lists 0 and 1, lists 2 and 3, ...), adds
- *    the values of equal columns, copies an odd last list unchanged, and swaps
- *    the two buffers.  Its floating-point additions are therefore grouped by
- *    the binary tree the method defines, which makes its values the bitwise
- *    expectation for any implementation that keeps that grouping.
+ *    (Algorithm 1), one row at a time: a multiplying phase that appends the
+ *    scaled rows B_k* for the entries of A_i* in stored order into one buffer
+ *    while recording where each list starts, then the accumulating phase.
+ *    The method's rounds merge the lists two by two in order (lists 0 and 1,
+ *    lists 2 and 3, ...; an odd last list passes unchanged) between two
+ *    buffers, adding the values of equal columns; after r rounds list p is
+ *    the merge of the original lists [p 2^r, (p+1) 2^r).  This file
+ *    evaluates that binary tree depth first (tree_node), each level in the
+ *    buffer its round would write.  Its floating-point additions are
+ *    therefore grouped exactly as the method groups them, which makes its
+ *    values the bitwise expectation for any implementation that keeps that
+ *    grouping.
  *
  * All products are single IEEE-754 double multiplications; the file must be
  * compiled without floating-point contraction (-ffp-contract=off) and without
@@ -205,18 +208,56 @@ static int64_t merge_two(const int32_t *xc, const double *xv, int64_t nx, const 
     return o;
 }
 
+/* One row's lists after the multiplying phase: list l occupies positions
+ * [start[l], start[l+1]) of buf[0]; buf[1] is scratch of the same size. */
+typedef struct {
+    int64_t nlists;
+    const int64_t *start;
+    int32_t *col[2];
+    double *val[2];
+} row_lists;
+
+/* The node of the merge tree at level h with index p: the merged list of the
+ * lists [p 2^h, (p+1) 2^h) (clipped to the row's list count).  Section III-B
+ * pairs the lists of a round two by two in order -- list 2p with list 2p+1 --
+ * and lets an odd last list through unchanged, round after round, so after h
+ * rounds the p-th list is exactly the merge of these leaves, and the left
+ * half is always added before the right half.  A node's result is placed at
+ * the position of its first leaf in buffer h mod 2: the children of a level-h
+ * node sit in buffer (h-1) mod 2 inside the node's own range of positions,
+ * so the two buffers alternate between levels as the ping-pong buffers of
+ * the method alternate between rounds.  Returns the node's length. */
+static int64_t tree_node(const row_lists *r, int h, int64_t p) {
+    const int64_t first = p << h;
+    if (h == 0) return r->start[first + 1] - r->start[first];
+    const int64_t half = (int64_t)1 << (h - 1);
+    const int64_t pos = r->start[first];
+    const int src = (h - 1) & 1, dst = h & 1;
+    const int64_t nl = tree_node(r, h - 1, 2 * p);
+    if (first + half >= r->nlists) {
+        /* no right half: the left child moves up a level as it is */
+        memcpy(r->col[dst] + pos, r->col[src] + pos, 4 * (size_t)nl);
+        memcpy(r->val[dst] + pos, r->val[src] + pos, 8 * (size_t)nl);
+        return nl;
+    }
+    const int64_t nr = tree_node(r, h - 1, 2 * p + 1);
+    const int64_t rpos = r->start[first + half];
+    return merge_two(r->col[src] + pos, r->val[src] + pos, nl, r->col[src] + rpos, r->val[src] + rpos, nr,
+                     r->col[dst] + pos, r->val[dst] + pos);
+}
+
 /* The accumulation method of Section III-B, one row at a time (see the file
  * header).  c_off as in oracle_spa_fill; row_len receives each row's length
- * and rounds (may be NULL) the number of merge rounds each row took.  Rows
- * whose list count is 0 produce an empty row; a single list is the result
- * as it is.  Empty B rows still count as lists. */
+ * and rounds (may be NULL) the number of merge rounds each row took,
+ * ceil(log2(lists)).  Rows whose list count is 0 produce an empty row; a
+ * single list is the result as it is.  Empty B rows still count as lists. */
 int oracle_brmerge_rows(int64_t row_begin, int64_t row_end, const int64_t *a_rpt,
                         const int32_t *a_col, const double *a_val, const int64_t *b_rpt,
                         const int32_t *b_col, const double *b_val, const int64_t *c_off,
                         int32_t *c_col, double *c_val, int64_t *row_len, int32_t *rounds,
                         int nthreads) {
     if (row_end < row_begin) return -2;
-    /* buffer capacities: the largest product count and list count of a row */
+    /* scratch sizes: the largest product count and list count of a row */
     int64_t max_nprod = 0, max_lists = 0;
     for (int64_t i = row_begin; i < row_end; ++i) {
         int64_t np = 0;
@@ -229,67 +270,52 @@ int oracle_brmerge_rows(int64_t row_begin, int64_t row_end, const int64_t *a_rpt
 #pragma omp parallel num_threads(nthreads)
     {
         size_t cap = (size_t)(max_nprod > 0 ? max_nprod : 1);
-        size_t lcap = (size_t)max_lists + 1;
-        int32_t *col_buf[2] = {(int32_t *)malloc(4 * cap), (int32_t *)malloc(4 * cap)};
-        double *val_buf[2] = {(double *)malloc(8 * cap), (double *)malloc(8 * cap)};
-        int64_t *off_buf[2] = {(int64_t *)malloc(8 * lcap), (int64_t *)malloc(8 * lcap)};
-        if (!col_buf[0] || !col_buf[1] || !val_buf[0] || !val_buf[1] || !off_buf[0] || !off_buf[1]) {
+        int64_t *start = (int64_t *)malloc(8 * ((size_t)max_lists + 1));
+        row_lists r;
+        r.start = start;
+        r.col[0] = (int32_t *)malloc(4 * cap);
+        r.col[1] = (int32_t *)malloc(4 * cap);
+        r.val[0] = (double *)malloc(8 * cap);
+        r.val[1] = (double *)malloc(8 * cap);
+        if (!start || !r.col[0] || !r.col[1] || !r.val[0] || !r.val[1]) {
 #pragma omp atomic write
             err = -1;
         } else {
 #pragma omp for schedule(dynamic, 64)
             for (int64_t i = row_begin; i < row_end; ++i) {
-                /* multiplying phase: one list per stored A_ik, in stored order */
-                int cur = 0;
-                int64_t nlists = 0, fill = 0;
-                off_buf[cur][0] = 0;
-                for (int64_t p = a_rpt[i]; p < a_rpt[i + 1]; ++p) {
-                    int32_t k = a_col[p];
-                    double a = a_val[p];
-                    for (int64_t q = b_rpt[k]; q < b_rpt[k + 1]; ++q) {
-                        col_buf[cur][fill] = b_col[q];
-                        val_buf[cur][fill] = a * b_val[q];
-                        ++fill;
+                /* multiplying phase: the scaled row B_k* of every stored A_ik,
+                 * in stored order, one list each, appended to buffer 0 */
+                int64_t L = a_rpt[i + 1] - a_rpt[i], fill = 0;
+                for (int64_t l = 0; l < L; ++l) {
+                    const int64_t p = a_rpt[i] + l;
+                    const int32_t k = a_col[p];
+                    start[l] = fill;
+                    for (int64_t q = b_rpt[k]; q < b_rpt[k + 1]; ++q, ++fill) {
+                        r.col[0][fill] = b_col[q];
+                        r.val[0][fill] = a_val[p] * b_val[q];
                     }
-                    off_buf[cur][++nlists] = fill;
                 }
-                /* accumulating phase: rounds of pairwise merges between buffers */
-                int32_t nround = 0;
-                while (nlists > 1) {
-                    int nxt = 1 - cur;
-                    int64_t out_lists = 0, out_fill = 0;
-                    off_buf[nxt][0] = 0;
-                    for (int64_t l = 0; l < nlists; l += 2) {
-                        int64_t xs = off_buf[cur][l], xe = off_buf[cur][l + 1];
-                        if (l + 1 < nlists) {
-                            int64_t ye = off_buf[cur][l + 2];
-                            out_fill += merge_two(col_buf[cur] + xs, val_buf[cur] + xs, xe - xs,
-                                                  col_buf[cur] + xe, val_buf[cur] + xe, ye - xe,
-                                                  col_buf[nxt] + out_fill, val_buf[nxt] + out_fill);
-                        } else {
-                            memcpy(col_buf[nxt] + out_fill, col_buf[cur] + xs, 4 * (size_t)(xe - xs));
-                            memcpy(val_buf[nxt] + out_fill, val_buf[cur] + xs, 8 * (size_t)(xe - xs));
-                            out_fill += xe - xs;
-                        }
-                        off_buf[nxt][++out_lists] = out_fill;
-                    }
-                    nlists = out_lists;
-                    cur = nxt;
-                    ++nround;
+                start[L] = fill;
+                /* accumulating phase: the root of the tree of ceil(log2 L)
+                 * levels holds the row */
+                int H = 0;
+                while (((int64_t)1 << H) < L) ++H;
+                int64_t len = 0;
+                if (L > 0) {
+                    r.nlists = L;
+                    len = tree_node(&r, H, 0);
                 }
-                int64_t len = nlists == 0 ? 0 : off_buf[cur][1];
-                memcpy(c_col + c_off[i - row_begin], col_buf[cur], 4 * (size_t)len);
-                memcpy(c_val + c_off[i - row_begin], val_buf[cur], 8 * (size_t)len);
+                memcpy(c_col + c_off[i - row_begin], r.col[H & 1], 4 * (size_t)len);
+                memcpy(c_val + c_off[i - row_begin], r.val[H & 1], 8 * (size_t)len);
                 row_len[i - row_begin] = len;
-                if (rounds) rounds[i - row_begin] = nround;
+                if (rounds) rounds[i - row_begin] = H;
             }
         }
-        free(col_buf[0]);
-        free(col_buf[1]);
-        free(val_buf[0]);
-        free(val_buf[1]);
-        free(off_buf[0]);
-        free(off_buf[1]);
+        free(start);
+        free(r.col[0]);
+        free(r.col[1]);
+        free(r.val[0]);
+        free(r.val[1]);
     }
     return err;
 }

@@ -116,6 +116,13 @@ int fail(spg_handle h, int code, const char *fmt, ...) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// a row whose product count does not fit int32 (the analysis routes it to
+// no kernel and raises kErrRowProducts)
+int fail_row_products(spg_handle h) {
+    return fail(h, SPG_ERR_CAPACITY, "a row of C has 2^31 or more products (limit 2^31-1 per row); "
+                                     "products per row are counted in int32 by the row kernels");
+}
+
 int check_csr(spg_handle h, const spg_csr *X, const char *name, bool need_val) {
     if (!X) return fail(h, SPG_ERR_ARG, "%s is NULL", name);
     if (X->rows < 0 || X->cols < 0 || X->nnz < 0)
@@ -629,7 +636,10 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     h->err.clear();
     h->plan_valid = false;
     int rc;
-    if ((rc = check_csr(h, A, "A", false)) || (rc = check_csr(h, B, "B", false))) return rc;
+    // learned and upper-bound allocation compute the rows' values into slots
+    // during this call: they read the values, the precise method does not
+    const bool slotted = h->alloc == SPG_ALLOC_LEARNED || h->alloc == SPG_ALLOC_UPPER;
+    if ((rc = check_csr(h, A, "A", slotted)) || (rc = check_csr(h, B, "B", slotted))) return rc;
     if (!c_rpt || !c_nnz) return fail(h, SPG_ERR_ARG, "c_rpt / c_nnz is NULL");
     if (A->cols != B->rows)
         return fail(h, SPG_ERR_DIM, "A is %lld x %lld but B has %lld rows", (long long)A->rows,
@@ -653,9 +663,6 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
                         (unsigned long long)h->ctl_host->err);
     }
     const bool learned = h->alloc == SPG_ALLOC_LEARNED;
-    // learned and upper-bound allocation both compute the rows into slots
-    // during this call and compact them in spgemm_numeric
-    const bool slotted = learned || h->alloc == SPG_ALLOC_UPPER;
     // the short-row kernels are fixed with the classification: the numeric
     // pass uses what this call chose
     int gr = (int)h->group_rows;
@@ -709,6 +716,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         HIP_TRY(h, launch_scan(M, lw.pred_size, ws.tile_sum, lw.slot_off, &h->ctl->pred_total, s));
         HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
+        if (h->ctl_host->err & kErrRowProducts) return fail_row_products(h);
         for (int i = 0; i < 8; ++i) h->counts[i] = h->ctl_host->count[i];
         h->pred_total = h->ctl_host->pred_total;
         const size_t pt = (size_t)std::max<int64_t>(h->pred_total, 1);
@@ -738,6 +746,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     const Ctl &c = *h->ctl_host;
+    if (c.err & kErrRowProducts) return fail_row_products(h);
     for (int i = 0; i < 8; ++i) h->counts[i] = c.count[i];
     h->nnz = c.nnz;
     h->nprod = c.nprod;

@@ -68,7 +68,8 @@ struct Ctl {
 enum CtlErr : int64_t {
     kErrRptA = 1, kErrColA = 2, kErrRptB = 4, kErrColB = 8,
     kErrSizeMismatch = 16,  // numeric row length differs from the symbolic count
-    kErrHeavyCapacity = 32
+    kErrHeavyCapacity = 32,
+    kErrRowProducts = 64    // a row has 2^31 or more products (routed to no kernel)
 };
 
 // Row-pointer types are dispatched at run time: 4 or 8 bytes.

@@ -312,7 +312,12 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
         if (in) {
             const int64_t np = (int64_t)s_np[w][lane];
             const int mx = s_mx[w][lane];
-            const int cls = classify(a1 - a0, np, mx, th);
+            // the row kernels count a row's products in int32: a longer row
+            // goes to no kernel and fails the call
+            const bool too_long = np > (int64_t)INT32_MAX;
+            if (too_long)
+                atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrRowProducts);
+            const int cls = too_long ? (int)kClassEmpty : classify(a1 - a0, np, mx, th);
             row_nprod[i] = np;
             const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx)
                            : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, np)

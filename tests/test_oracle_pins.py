@@ -277,24 +277,19 @@ def test_empty_shapes(shape):
 # ---- Algorithm 1 (the accumulation method) run on the CPU -------------------
 
 def _tree_value(leaf_vals, nleaves):
-    """Value of one output column from the leaves (list positions) holding it:
-    the node of level r and index p covers leaves [p 2^r, (p+1) 2^r); a node
-    adds its two children's values when both hold the column."""
-    levels = 0
-    while (1 << levels) < nleaves:
-        levels += 1
-
-    def node(level, p):
-        if level == 0:
-            return leaf_vals.get(p)
-        left, right = node(level - 1, 2 * p), node(level - 1, 2 * p + 1)
-        if left is None:
-            return right
-        if right is None:
-            return left
-        return left + right
-
-    return node(levels, 0)
+    """Value of one output column from the leaves (list positions) holding it,
+    by the rounds of Section III-B: every round combines the partial lists
+    2p and 2p+1 into list p of the next round (an odd last list passes), and
+    a column present in both adds the left value and the right value."""
+    cur = [leaf_vals.get(p) for p in range(nleaves)]
+    while len(cur) > 1:
+        nxt = []
+        for p in range(0, len(cur), 2):
+            left = cur[p]
+            right = cur[p + 1] if p + 1 < len(cur) else None
+            nxt.append(right if left is None else left if right is None else left + right)
+        cur = nxt
+    return cur[0] if cur else None
 
 
 @pytest.mark.parametrize("seed", range(6))
