@@ -14,6 +14,8 @@ Contents
                    row by row on the CPU: its values are the bitwise
                    expectation for any implementation that groups additions by
                    the same merge tree.
+``pattern_sums``   per row of C the entry count and the sum of its columns
+                   (the structure alone, for products too large to hold).
 ``row_nprod``      products per row (Section II-A.4).
 ``brute_force``    Eq. (1) on dense arrays, pure Python loops: tiny inputs only.
 ``compression_ratio``  Eq. (5).
@@ -59,10 +61,11 @@ def _load():
         I64 = ctypes.c_int64
         lib.oracle_row_nprod.argtypes = [I64, I64, P, P, P, P]
         lib.oracle_spa_counts.argtypes = [I64, I64, I64, P, P, P, P, P, ctypes.c_int]
+        lib.oracle_spa_pattern_sums.argtypes = [I64, I64, I64, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_spa_fill.argtypes = [I64, I64, I64, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_brmerge_rows.argtypes = [I64, I64, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_max_threads.argtypes = []
-        for f in (lib.oracle_row_nprod, lib.oracle_spa_counts, lib.oracle_spa_fill,
+        for f in (lib.oracle_row_nprod, lib.oracle_spa_counts, lib.oracle_spa_pattern_sums, lib.oracle_spa_fill,
                   lib.oracle_brmerge_rows, lib.oracle_max_threads):
             f.restype = ctypes.c_int
         _lib = lib
@@ -125,6 +128,22 @@ def row_nprod(A, B, rows=None) -> np.ndarray:
     out = np.zeros(rows.size, np.int64)
     lib.oracle_row_nprod(0, rows.size, _p(a_rpt), _p(a_col), _p(b_rpt), _p(out))
     return out
+
+
+def pattern_sums(A, B, rows=None, nthreads: int = 0):
+    """The structure of C = A*B without its values: per row the number of
+    stored entries (distinct columns) and the sum of their column indices
+    (int64 arrays).  For products whose C does not fit in host memory."""
+    lib = _load()
+    rows, a_rpt, a_col, _, b_rpt, b_col, _ = _prep(A, B, rows)
+    m = rows.size
+    counts = np.zeros(m, np.int64)
+    sums = np.zeros(m, np.int64)
+    rc = lib.oracle_spa_pattern_sums(B.cols, 0, m, _p(a_rpt), _p(a_col), _p(b_rpt), _p(b_col), _p(counts),
+                                     _p(sums), nthreads)
+    if rc:
+        raise MemoryError(f"oracle_spa_pattern_sums failed ({rc})")
+    return counts, sums
 
 
 def spgemm(A, B, rows=None, nthreads: int = 0) -> Result:

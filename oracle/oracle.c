@@ -113,6 +113,46 @@ int oracle_spa_counts(int64_t N, int64_t row_begin, int64_t row_end, const int64
     return err;
 }
 
+/* The structure of C alone, for products too large to hold on the host:
+ * per row the number of distinct columns (as oracle_spa_counts) and their
+ * sum, from the same marker-array walk. */
+int oracle_spa_pattern_sums(int64_t N, int64_t row_begin, int64_t row_end, const int64_t *a_rpt,
+                            const int32_t *a_col, const int64_t *b_rpt, const int32_t *b_col,
+                            int64_t *counts, int64_t *colsums, int nthreads) {
+    if (N < 0 || row_end < row_begin) return -2;
+    int err = 0;
+    nthreads = clamp_threads(nthreads);
+#pragma omp parallel num_threads(nthreads)
+    {
+        int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+        if (!mark) {
+#pragma omp atomic write
+            err = -1;
+        } else {
+            for (int64_t j = 0; j < N; ++j) mark[j] = -1;
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t i = row_begin; i < row_end; ++i) {
+                int64_t cnt = 0, sum = 0;
+                for (int64_t p = a_rpt[i]; p < a_rpt[i + 1]; ++p) {
+                    int32_t k = a_col[p];
+                    for (int64_t q = b_rpt[k]; q < b_rpt[k + 1]; ++q) {
+                        int32_t j = b_col[q];
+                        if (mark[j] != i) {
+                            mark[j] = i;
+                            ++cnt;
+                            sum += j;
+                        }
+                    }
+                }
+                counts[i - row_begin] = cnt;
+                colsums[i - row_begin] = sum;
+            }
+            free(mark);
+        }
+    }
+    return err;
+}
+
 /* Pass 2 of the definition.  c_off[i - row_begin] is where row i starts in
  * c_col / c_val / c_abs (so the caller can compute any subset of rows). */
 int oracle_spa_fill(int64_t N, int64_t row_begin, int64_t row_end, const int64_t *a_rpt,

@@ -1,11 +1,13 @@
-"""Full-size workloads in the benchmark's launch configuration, checked on
-sampled rows against the oracle (the whole C is too large to compare on the
-host): the heaviest rows, rows of every kernel class and random rows."""
+"""Full-size workloads in the benchmark's launch configuration: every row's
+length and column sum against the oracle's structure pass, and sampled rows
+element by element (the whole C is too large to compare on the host): the
+heaviest rows, rows of every kernel class and random rows."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from helpers import assert_structure_matches_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +41,7 @@ def sampled_check_rows(A, B, C, rows):
     assert np.array_equal(val.view(np.int64), model.val.view(np.int64)), "values differ from the merge-tree model"
 
 
+@pytest.mark.timeout(600)
 def test_rmat_scale20_sampled():
     print("case: R-MAT scale 20, edge factor 16, seed 3 (full size, sampled rows)", flush=True)
     A = synth.rmat(20, 16, 3)
@@ -61,9 +64,10 @@ def test_rmat_scale20_sampled():
         if band.size:
             sample += list(rng.choice(band, min(20, band.size), replace=False))
     sampled_check(A, C, sample)
-    # properties at full size: rows sorted and in range
-    last = C.rpt[-1].item()
-    assert last == C.nnz
+    # every row: length and column sum against the oracle's structure pass
+    print("whole-C structure check against the oracle", flush=True)
+    assert C.rpt[-1].item() == C.nnz
+    assert_structure_matches_oracle(A, A, C)
     h.close()
 
 
@@ -123,6 +127,7 @@ def test_rmat_scale21_row_blocks():
         sample = list(np.argsort(-nb)[:2]) + list(rng.choice(e - b, min(60, e - b), replace=False))
         print(f"block [{b}, {e}) nnz {C.nnz} classes {h.class_rows()}", flush=True)
         sampled_check_rows(Ab, A, C, sample)
+        assert_structure_matches_oracle(Ab, A, C)
         del C
         torch.cuda.empty_cache()
     print("nnz(C)", total_nnz, "nprod", int(nprod.sum()), flush=True)

@@ -144,6 +144,7 @@ def test_upper_bound_values_taken_at_symbolic_call(handle):
     dA, dB = brm.DeviceCSR.from_host(A), brm.DeviceCSR.from_host(B)
     handle.set_option(brm.OPT_ALLOC, brm.ALLOC_UPPER)
     c_rpt, nnz = handle.symbolic(dA, dB)
+    orig = dB.val.clone()
     dB.val.mul_(-3.0)
     c_col = torch.empty(nnz, dtype=torch.int32, device="cuda")
     c_val = torch.empty(nnz, dtype=torch.float64, device="cuda")
@@ -155,7 +156,7 @@ def test_upper_bound_values_taken_at_symbolic_call(handle):
     # the precise method reads the values in the numeric call
     handle.set_option(brm.OPT_ALLOC, brm.ALLOC_PRECISE)
     c_rpt, nnz = handle.symbolic(dA, dB)
-    dB.val.div_(-3.0)
+    dB.val.copy_(orig)
     handle.numeric(dA, dB, c_rpt, c_col, c_val)
     torch.cuda.synchronize()
     assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))

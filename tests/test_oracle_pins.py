@@ -361,3 +361,22 @@ def test_row_features_small():
     # every row of C lies between the longest B row used and min(nprod, span)
     assert np.all(nnzc >= f["maxb"])
     assert np.all(nnzc <= np.minimum(f["nprod"], f["span"]))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pattern_sums_match_brute_force(seed):
+    # the structure-only pass: entry count and column sum of every row from
+    # the boolean product of Eq. (1)
+    A = synth.random_csr(30, 40, 0.1 + 0.1 * seed, seed)
+    B = synth.random_csr(40, 50, 0.1, seed + 21, empty_row_frac=0.2)
+    cnt, csum = oracle.pattern_sums(A, B)
+    pat, _ = oracle.brute_force(A.to_dense(), _pattern(A),
+                                B.to_dense(), _pattern(B))
+    assert np.array_equal(cnt, pat.sum(axis=1))
+    assert np.array_equal(csum, (pat * np.arange(B.cols)[None, :]).sum(axis=1))
+
+
+def _pattern(X):
+    p = np.zeros((X.rows, X.cols), bool)
+    p[np.repeat(np.arange(X.rows), X.row_lengths()), X.col.astype(np.int64)] = True
+    return p
