@@ -282,8 +282,11 @@ typedef struct {
  * one stage must share the row-pointer widths of A and of B (chained B always
  * has int64 row pointers).
  * Errors: SPG_ERR_ARG, SPG_ERR_DIM (A_p.cols != B_p.rows), SPG_ERR_CAPACITY
- * (arena too small: *required_bytes is set to the size needed, the outputs
- * are invalid), SPG_ERR_NOMEM, SPG_ERR_HIP. */
+ * (arena too small: the outputs are invalid and *required_bytes is set to the
+ * size that the stages up to the first one that did not fit need; a stage
+ * after it computes nothing -- its B may be a C that was never written -- so
+ * with chained problems a call with an arena of that size may fail again
+ * with a larger *required_bytes), SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_batched(spg_handle h, int count, const spg_problem *problems, void *arena, int64_t arena_bytes,
                    spg_batched_out *out, int64_t *required_bytes, void *stream);
 

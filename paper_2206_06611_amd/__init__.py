@@ -482,7 +482,9 @@ class Handle:
         if arena is None:
             est = sum(8 * (A.rows + 1) + 8 * (Pt.rows + 1) + 12 * 27 * A.rows + 8192 for A, _, Pt in triples)
             arena = torch.empty(est, dtype=torch.uint8, device=triples[0][0].rpt.device)
-        for _ in range(2):
+        # each failed call reports what the stages up to the first one that
+        # did not fit need (a later stage's size depends on earlier outputs)
+        for _ in range(3):
             rc, req, outs = self.batched(probs, arena, stream=stream)
             if rc == SPG_OK:
                 return outs[n:], outs[:n], arena

@@ -185,7 +185,8 @@ enum BatchFlags : int { kBatchOverflow = 1, kBatchHeavyRow = 2 };
 
 struct BatchStatus {
     int flags;
-    int pad;
+    int skip;            // the flags were set when the current stage began: the stage reads no operand
+                         // (a chained B may be an unwritten C) and routes every row to the empty class
     int64_t required;    // arena bytes the batch needs
     int64_t arena_used;  // running arena fill (row pointers, then each stage's C)
     int64_t nprod;

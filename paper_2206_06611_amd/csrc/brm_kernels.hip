@@ -3283,6 +3283,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
     const int lane = lane_id();
     const int w = threadIdx.x / kWave;
     const int64_t *coff = np < kMaxLdsProbs ? lk.off : chunk_off;
+    const bool skip = st->skip != 0;  // one value for the whole stage (set before this launch)
     for (int64_t c = (int64_t)blockIdx.x * kW + w; c < nchunks; c += (int64_t)gridDim.x * kW) {
         const int p = find_prob(lk, chunk_off, np, c);
         const BatchProb &pr = tab[p];
@@ -3291,6 +3292,18 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         const int nrows = pr.rows - r0 < kWave ? (int)(pr.rows - r0) : kWave;
         const int64_t i = r0 + lane;
         const bool in = lane < nrows;
+        if (skip) {
+            // an earlier stage failed: this stage's B may be an unwritten C
+            if (in) {
+                const int64_t g = pr.row_off + i;
+                row_nprod[g] = 0;
+                row_class[g] = (uint8_t)kClassEmpty;
+                row_prob[g] = p;
+                row_size[g] = 0;
+                my_count[kClassEmpty] += 1;
+            }
+            continue;
+        }
         int64_t a0 = 0, a1 = 0;
         if (in) {
             a0 = ld_rpt<IA>(pr.a_rpt, i);
@@ -3574,9 +3587,20 @@ __global__ void k_b_describe(const BatchProb *all, int n, spg_batched_out *out, 
     }
 }
 
+// start of a batched stage: its control block cleared, and whether an
+// earlier stage has already failed (overflow or heavy row) fixed for the
+// whole stage
+__global__ void k_b_stage_begin(Ctl *ctl, BatchStatus *st) {
+    int64_t *p = reinterpret_cast<int64_t *>(ctl);
+    const int n = (int)(sizeof(Ctl) / sizeof(int64_t));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+    if (threadIdx.x == 0) st->skip = st->flags != 0;
+}
+
 __global__ void k_b_zero_status(BatchStatus *st) {
     if (threadIdx.x == 0) {
         st->flags = 0;
+        st->skip = 0;
         st->required = 0;
         st->arena_used = 0;
         st->nprod = 0;
@@ -3592,7 +3616,7 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
     const unsigned ga = (unsigned)(R > 0 ? ((R + 255) / 256 < 2048 ? (R + 255) / 256 : 2048) : 1);
     // the analysis: four chunks of 64 rows per workgroup pass
     const unsigned gc = (unsigned)(bs.chunks > 0 ? ((bs.chunks + 3) / 4 < 2048 ? (bs.chunks + 3) / 4 : 2048) : 1);
-    hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, s, ws.ctl);
+    hipLaunchKernelGGL(k_b_stage_begin, dim3(1), dim3(64), 0, s, ws.ctl, bs.status);
     if (bs.link) hipLaunchKernelGGL(k_b_link, dim3(1), dim3(256), 0, s, bs.all, bs.first, np);
     auto grid_for = [&](int per_cu, int waves_per_wg) {
         int64_t g = (int64_t)num_cu * per_cu;

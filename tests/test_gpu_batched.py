@@ -92,6 +92,42 @@ def test_arena_capacity(handle):
     assert rc == brm.SPG_OK and req2 == req
 
 
+def test_stage_after_overflow_reads_no_stale_arena(handle):
+    """A chained stage after a stage that overflowed computes nothing: here
+    the arena still holds an earlier batch's row pointers where the
+    overflowed stage's C would have gone, and the call must report the
+    capacity error (then succeed once the arena is large enough) without
+    reading them as its B."""
+    first = galerkin_inputs([10, 9])
+    t1 = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in first]
+    p1 = [(A, P) for A, P, _ in t1] + [(Pt, i) for i, (_, _, Pt) in enumerate(t1)]
+    size = 1 << 14
+    for _ in range(3):  # an arena of exactly the size the first batch needs
+        arena = torch.empty(size, dtype=torch.uint8, device="cuda")
+        rc, req, _ = handle.batched(p1, arena)
+        if rc == brm.SPG_OK:
+            break
+        size = req
+    assert rc == brm.SPG_OK and req == size
+    torch.cuda.synchronize()
+    second = galerkin_inputs([12, 11])
+    t2 = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in second]
+    probs = [(A, P) for A, P, _ in t2] + [(Pt, i) for i, (_, _, Pt) in enumerate(t2)]
+    rc, req, outs = handle.batched(probs, arena)
+    assert rc == brm.SPG_ERR_CAPACITY and req > size
+    for _ in range(3):
+        arena = torch.empty(req, dtype=torch.uint8, device="cuda")
+        rc, req, outs = handle.batched(probs, arena)
+        if rc == brm.SPG_OK:
+            break
+    assert rc == brm.SPG_OK
+    for (n, A, P, Pt), g in zip(second, outs[2:]):
+        ref_ap = oracle.spgemm(A, P)
+        apc = synth.CSR(A.rows, P.cols, ref_ap.rpt, ref_ap.col, ref_ap.val)
+        ref_g = oracle.spgemm(Pt, apc)
+        same_bits(to_host(g), (ref_g.rpt, ref_g.col, ref_g.val))
+
+
 def test_graph_replays_with_eager_work_between(handle):
     inp = galerkin_inputs([5, 8, 6])
     triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
