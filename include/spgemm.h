@@ -65,7 +65,9 @@ typedef enum {
     SPG_ERR_NOMEM = -5,        /* device allocation failed */
     SPG_ERR_HIP = -6,          /* a HIP runtime call failed (see spg_last_error) */
     SPG_ERR_NOT_TRAINED = -7,  /* learned allocation asked for before any training/loading */
-    SPG_ERR_STATE = -8         /* spgemm_numeric without a matching spgemm_symbolic */
+    SPG_ERR_STATE = -8,        /* spgemm_numeric without a matching spgemm_symbolic */
+    SPG_ERR_SCRATCH = -9       /* spgemm_batched_noalloc: the batch needs more workspace than
+                                  the fixed scratch array holds */
 } spg_status;
 
 /* A CSR matrix on the device. */
@@ -289,6 +291,27 @@ typedef struct {
  * with a larger *required_bytes), SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_batched(spg_handle h, int count, const spg_problem *problems, void *arena, int64_t arena_bytes,
                    spg_batched_out *out, int64_t *required_bytes, void *stream);
+
+/* The same batched product for callers that cannot allocate device memory
+ * (code that runs while a HIP graph is being captured around it, tight
+ * serving loops, harnesses that forbid hipMalloc): the arguments, the
+ * results (bitwise) and the errors are those of spgemm_batched, and it runs
+ * the same kernels, but the call allocates nothing -- no device or pinned
+ * memory, no HIP graph.  Its workspace (problem table, stage row arrays, list
+ * descriptors, status) is a fixed array of 64 MiB of device memory that the
+ * library holds on every GPU it runs on until the process ends; the kernels
+ * are launched one by one on `stream`.  A batch needs 29 bytes per row plus
+ * 12 bytes per entry of A of its largest stage, plus about 600 bytes per
+ * problem; a larger batch fails with SPG_ERR_SCRATCH before any launch (use
+ * spgemm_batched for it).  Blocks until the batch is done, like
+ * spgemm_batched.
+ * The array is shared by every call on one GPU, from any handle, and keeps
+ * the last call's contents (the call clears what must start at zero): calls
+ * that overlap on one GPU (from several host threads) race and must be
+ * serialized by the caller. */
+int spgemm_batched_noalloc(spg_handle h, int count, const spg_problem *problems, void *arena,
+                           int64_t arena_bytes, spg_batched_out *out, int64_t *required_bytes,
+                           void *stream);
 
 /* ---- Learned allocation --------------------------------------------------
  * Not in the paper: a stand-in for its allocation step (Section II-B.2).  A

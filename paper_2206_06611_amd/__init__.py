@@ -28,6 +28,7 @@ SPG_ERR_NOMEM = -5
 SPG_ERR_HIP = -6
 SPG_ERR_NOT_TRAINED = -7
 SPG_ERR_STATE = -8
+SPG_ERR_SCRATCH = -9
 
 # options
 OPT_VALIDATE = 1
@@ -125,6 +126,7 @@ def _load_library():
         "spg_mlp_save": ([P, ctypes.c_char_p], I32),
         "spg_mlp_load": ([P, ctypes.c_char_p], I32),
         "spgemm_batched": ([P, I32, ctypes.POINTER(_Problem), P, I64, P, ctypes.POINTER(I64), P], I32),
+        "spgemm_batched_noalloc": ([P, I32, ctypes.POINTER(_Problem), P, I64, P, ctypes.POINTER(I64), P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -140,7 +142,8 @@ EXPORTED = ("spg_create", "spg_destroy", "spg_set_option", "spg_get_option", "sp
             "spgemm_symbolic", "spgemm_numeric", "spg_last_error", "spg_mlp_set_params",
             "spg_mlp_get_params", "spg_mlp_features", "spg_mlp_forward", "spg_mlp_gradient",
             "spg_mlp_fit_normalization", "spg_mlp_train", "spg_mlp_loss", "spg_mlp_calibrate",
-            "spg_mlp_save", "spg_mlp_load", "spgemm_batched", "spgemm_row_products")
+            "spg_mlp_save", "spg_mlp_load", "spgemm_batched", "spgemm_row_products",
+            "spgemm_batched_noalloc")
 
 
 def library():
@@ -439,20 +442,23 @@ class Handle:
 
     # ---- batched products -------------------------------------------------
     def batched(self, problems, arena: torch.Tensor, out: torch.Tensor | None = None, stream=None,
-                views: bool = True):
+                views: bool = True, noalloc: bool = False):
         """problems: list of (A, B) where B is a DeviceCSR or the index of an
         earlier problem whose C is B, or a BatchedProblems made from such a
         list once (repeated calls then skip the marshalling).  arena: uint8
         device tensor.  Returns (status, required_bytes, outputs); outputs are
         DeviceCSR views into the arena (None when the arena was too small, or
-        when views is False: `out` then holds the descriptors)."""
+        when views is False: `out` then holds the descriptors).  noalloc:
+        call spgemm_batched_noalloc (workspace in the library's fixed
+        scratch array) instead of spgemm_batched."""
         bp = problems if isinstance(problems, BatchedProblems) else BatchedProblems(problems)
         n = bp.n
         if out is None:
             out = torch.empty((max(n, 1), 6), dtype=torch.int64, device=arena.device)
         req = ctypes.c_int64()
-        rc = _lib.spgemm_batched(self._h, n, bp.arr, ctypes.c_void_p(arena.data_ptr()), arena.numel(),
-                                 ctypes.c_void_p(out.data_ptr()), ctypes.byref(req), _stream_ptr(stream))
+        fn = _lib.spgemm_batched_noalloc if noalloc else _lib.spgemm_batched
+        rc = fn(self._h, n, bp.arr, ctypes.c_void_p(arena.data_ptr()), arena.numel(),
+                ctypes.c_void_p(out.data_ptr()), ctypes.byref(req), _stream_ptr(stream))
         if rc not in (SPG_OK, SPG_ERR_CAPACITY):
             self._check(rc)
         if rc != SPG_OK or not views:

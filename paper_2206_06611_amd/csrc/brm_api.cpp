@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,39 @@
 #include "spgemm.h"
 
 using namespace brm;
+
+// Workspace of spgemm_batched_noalloc: a fixed array in device memory that
+// every GPU the library runs on holds from the library's load until the
+// process ends.  Host code never uses this name as an address: its device
+// address is read once per device (scratch_address) and passed on.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The device address of `scratch` on `device`, which must be current:
+// looked up on the first call for that device, kept afterwards.
+hipError_t scratch_address(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+}  // namespace
 
 struct spg_handle_s {
     int device = 0;
@@ -83,6 +117,10 @@ struct spg_handle_s {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<int64_t> graph_sig;
     int64_t graph_captures = 0, graph_launches = 0;
+    // device address of the static scratch array on this handle's device
+    // (the allocation-free batched call); null when it could not be read
+    void *scratch = nullptr;
+    std::string scratch_err;
 };
 
 struct LearnedWs {
@@ -475,6 +513,10 @@ int spg_create(spg_handle *out, int device) {
         return SPG_ERR_NOMEM;
     }
     std::memset(h->ctl_host, 0, sizeof(Ctl));
+    {
+        const hipError_t e = scratch_address(device, &h->scratch);
+        if (e != hipSuccess) h->scratch_err = hipGetErrorString(e);
+    }
     *out = h;
     return SPG_OK;
 }
@@ -1071,10 +1113,26 @@ int spg_mlp_load(spg_handle h, const char *path) {
 
 // ---- batched products ------------------------------------------------------
 
-int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *arena, int64_t arena_bytes,
-                   spg_batched_out *out, int64_t *required_bytes, void *stream) {
-    if (!h) return SPG_ERR_ARG;
-    h->err.clear();
+}  // extern "C"
+
+namespace {
+
+// What both batched entry points derive on the host from the problems: the
+// stages (problems grouped by their dependencies), the arena's row-pointer
+// section, and the byte layout of the stage workspace.
+struct BatchedPlan {
+    struct Stage { int first, n; int64_t rows, ents; int arb, brb; bool link; size_t roff; };
+    std::vector<Stage> st;
+    std::vector<int64_t> ccols, rpt_off, stage_chunks;
+    size_t roff_total = 0;
+    int64_t rpt_end = 0, max_bcols = 0;
+    // workspace layout: rows | S | row offsets | table | status | ctl | row problems | list descriptors
+    size_t o_nprod, o_class, o_size, o_rows, o_tile, o_S, o_roff, o_tab, o_stat, o_ctl, o_prob, o_ebs, o_elen,
+        total;
+};
+
+int plan_batched(spg_handle h, int count, const spg_problem *probs, void *arena, int64_t arena_bytes,
+                 spg_batched_out *out, int64_t *required_bytes, BatchedPlan *pl) {
     if (count < 0 || (count > 0 && (!probs || !arena || !out)) || !required_bytes || arena_bytes < 0)
         return fail(h, SPG_ERR_ARG, "bad batched arguments");
     *required_bytes = 0;
@@ -1083,7 +1141,8 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     int rc;
     // stages from the dependencies; problems must come in stage order
     std::vector<int> stage((size_t)count, 0);
-    std::vector<int64_t> crows((size_t)count), ccols((size_t)count);
+    std::vector<int64_t> crows((size_t)count);
+    pl->ccols.assign((size_t)count, 0);
     for (int p = 0; p < count; ++p) {
         const spg_problem &q = probs[p];
         if ((rc = check_csr(h, &q.A, "A", true))) return rc;
@@ -1092,7 +1151,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
             if (q.b_from >= p) return fail(h, SPG_ERR_ARG, "problem %d: b_from must name an earlier problem", p);
             stage[(size_t)p] = stage[(size_t)q.b_from] + 1;
             brows = crows[(size_t)q.b_from];
-            bcols = ccols[(size_t)q.b_from];
+            bcols = pl->ccols[(size_t)q.b_from];
         } else {
             if ((rc = check_csr(h, &q.B, "B", true))) return rc;
             brows = q.B.rows;
@@ -1102,17 +1161,15 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
         if (p > 0 && stage[(size_t)p] < stage[(size_t)p - 1])
             return fail(h, SPG_ERR_ARG, "problems must be ordered by stage (problem %d)", p);
         crows[(size_t)p] = q.A.rows;
-        ccols[(size_t)p] = bcols;
+        pl->ccols[(size_t)p] = bcols;
     }
-    HIP_TRY(h, hipSetDevice(h->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     // stage ranges, row offsets, widths
-    struct StageInfo { int first, n; int64_t rows, ents; int arb, brb; bool link; size_t roff; };
-    std::vector<StageInfo> st;
-    size_t roff_total = 0;
+    pl->st.clear();
+    pl->roff_total = 0;
     for (int p = 0; p < count;) {
         int q = p;
-        StageInfo si{p, 0, 0, 0, probs[p].A.rpt_bytes, probs[p].b_from >= 0 ? 8 : probs[p].B.rpt_bytes, false, roff_total};
+        BatchedPlan::Stage si{p, 0, 0, 0, probs[p].A.rpt_bytes, probs[p].b_from >= 0 ? 8 : probs[p].B.rpt_bytes,
+                              false, pl->roff_total};
         while (q < count && stage[(size_t)q] == stage[(size_t)p]) {
             const int brb = probs[q].b_from >= 0 ? 8 : probs[q].B.rpt_bytes;
             if (probs[q].A.rpt_bytes != si.arb || brb != si.brb)
@@ -1123,53 +1180,176 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
             ++q;
         }
         si.n = q - p;
-        roff_total += (size_t)si.n + 1;
-        st.push_back(si);
+        pl->roff_total += (size_t)si.n + 1;
+        pl->st.push_back(si);
         p = q;
     }
-    int64_t max_rows = 0, max_ents = 0, max_bcols = 0;
-    for (auto &x : st) {
+    int64_t max_rows = 0, max_ents = 0;
+    for (auto &x : pl->st) {
         max_rows = std::max(max_rows, x.rows);
         max_ents = std::max(max_ents, x.ents);
     }
-    for (int p = 0; p < count; ++p) max_bcols = std::max(max_bcols, ccols[(size_t)p]);
+    pl->max_bcols = 0;
+    for (int p = 0; p < count; ++p) pl->max_bcols = std::max(pl->max_bcols, pl->ccols[(size_t)p]);
     if (max_rows > INT32_MAX) return fail(h, SPG_ERR_ARG, "too many rows in one stage");
     // arena: row pointers first (sizes known now), then C's columns and values
-    int64_t rpt_end = 0;
-    std::vector<int64_t> rpt_off((size_t)count);
+    pl->rpt_end = 0;
+    pl->rpt_off.assign((size_t)count, 0);
     for (int p = 0; p < count; ++p) {
-        rpt_off[(size_t)p] = rpt_end;
-        rpt_end += (int64_t)align_up(8 * (size_t)(crows[(size_t)p] + 1), 256);
+        pl->rpt_off[(size_t)p] = pl->rpt_end;
+        pl->rpt_end += (int64_t)align_up(8 * (size_t)(crows[(size_t)p] + 1), 256);
     }
-    if (rpt_end > arena_bytes) {
-        *required_bytes = rpt_end;
-        return fail(h, SPG_ERR_CAPACITY, "arena smaller than the row pointers alone (%lld bytes)", (long long)rpt_end);
+    if (pl->rpt_end > arena_bytes) {
+        *required_bytes = pl->rpt_end;
+        return fail(h, SPG_ERR_CAPACITY, "arena smaller than the row pointers alone (%lld bytes)",
+                    (long long)pl->rpt_end);
     }
-    // buffers: workspace rows | S | row offsets | table | status | ctl
     const size_t a = 256;
-    const size_t o_nprod = 0;
-    const size_t o_class = align_up(o_nprod + 8 * (size_t)max_rows, a);
-    const size_t o_size = align_up(o_class + (size_t)max_rows, a);
-    const size_t o_rows = align_up(o_size + 4 * (size_t)max_rows, a);
-    const size_t o_tile = align_up(o_rows + 4 * (size_t)max_rows, a);
-    const size_t o_S = align_up(o_tile + 8 * (size_t)((max_rows + kScanTile - 1) / kScanTile + 1), a);
-    const size_t o_roff = align_up(o_S + 8 * (size_t)(max_rows + 1), a);
-    const size_t o_tab = align_up(o_roff + 16 * roff_total, a);  // row offsets, then chunk offsets
-    const size_t o_stat = align_up(o_tab + sizeof(BatchProb) * (size_t)count, a);
-    const size_t o_ctl = align_up(o_stat + sizeof(BatchStatus), a);
+    pl->o_nprod = 0;
+    pl->o_class = align_up(pl->o_nprod + 8 * (size_t)max_rows, a);
+    pl->o_size = align_up(pl->o_class + (size_t)max_rows, a);
+    pl->o_rows = align_up(pl->o_size + 4 * (size_t)max_rows, a);
+    pl->o_tile = align_up(pl->o_rows + 4 * (size_t)max_rows, a);
+    pl->o_S = align_up(pl->o_tile + 8 * (size_t)((max_rows + kScanTile - 1) / kScanTile + 1), a);
+    pl->o_roff = align_up(pl->o_S + 8 * (size_t)(max_rows + 1), a);
+    pl->o_tab = align_up(pl->o_roff + 16 * pl->roff_total, a);  // row offsets, then chunk offsets
+    pl->o_stat = align_up(pl->o_tab + sizeof(BatchProb) * (size_t)count, a);
+    pl->o_ctl = align_up(pl->o_stat + sizeof(BatchStatus), a);
     // the window kernels' inputs: the problem of every row, list descriptors
-    const size_t o_prob = align_up(o_ctl + sizeof(Ctl), a);
-    const size_t o_ebs = align_up(o_prob + 4 * (size_t)max_rows, a);
-    const size_t o_elen = align_up(o_ebs + 8 * (size_t)max_ents, a);
-    const size_t total = align_up(o_elen + 4 * (size_t)max_ents, a);
+    pl->o_prob = align_up(pl->o_ctl + sizeof(Ctl), a);
+    pl->o_ebs = align_up(pl->o_prob + 4 * (size_t)max_rows, a);
+    pl->o_elen = align_up(pl->o_ebs + 8 * (size_t)max_ents, a);
+    pl->total = align_up(pl->o_elen + 4 * (size_t)max_ents, a);
+    return SPG_OK;
+}
+
+// The problem table and the row / chunk offsets of every stage, written
+// into host buffers (tab[count], roff[2 * roff_total]).
+void fill_batched_tables(const BatchedPlan &pl, const spg_problem *probs, char *arena_c, BatchProb *tab,
+                         int64_t *roff, std::vector<int64_t> *stage_chunks) {
+    stage_chunks->assign(pl.st.size(), 0);
+    for (size_t si = 0; si < pl.st.size(); ++si) {
+        const auto &x = pl.st[si];
+        int64_t ro = 0, eo = 0, co = 0;
+        for (int i = 0; i < x.n; ++i) {
+            const int p = x.first + i;
+            const spg_problem &q = probs[p];
+            BatchProb &b = tab[p];
+            std::memset(&b, 0, sizeof b);
+            b.row_off = ro;
+            b.rows = q.A.rows;
+            b.ncols_b = pl.ccols[(size_t)p];
+            b.a_rpt = q.A.rpt;
+            b.a_col = q.A.col;
+            b.a_val = q.A.val;
+            if (q.b_from < 0) {
+                b.b_rpt = q.B.rpt;
+                b.b_col = q.B.col;
+                b.b_val = q.B.val;
+            }
+            b.c_rpt = reinterpret_cast<int64_t *>(arena_c + pl.rpt_off[(size_t)p]);
+            b.rpt_off = pl.rpt_off[(size_t)p];
+            b.b_from = q.b_from;
+            b.ent_off = eo;
+            roff[x.roff + (size_t)i] = ro;
+            roff[pl.roff_total + x.roff + (size_t)i] = co;
+            ro += q.A.rows;
+            eo += q.A.nnz;
+            co += (q.A.rows + kBatchChunkRows - 1) / kBatchChunkRows;
+        }
+        roff[x.roff + (size_t)x.n] = ro;
+        roff[pl.roff_total + x.roff + (size_t)x.n] = co;
+        (*stage_chunks)[si] = co;
+    }
+}
+
+Workspace batched_workspace(const BatchedPlan &pl, char *base) {
+    Workspace ws;
+    ws.row_nprod = reinterpret_cast<int64_t *>(base + pl.o_nprod);
+    ws.row_class = reinterpret_cast<uint8_t *>(base + pl.o_class);
+    ws.row_size = reinterpret_cast<int32_t *>(base + pl.o_size);
+    ws.class_rows = reinterpret_cast<int32_t *>(base + pl.o_rows);
+    ws.tile_sum = reinterpret_cast<int64_t *>(base + pl.o_tile);
+    ws.ctl = reinterpret_cast<Ctl *>(base + pl.o_ctl);
+    ws.row_prob = reinterpret_cast<int32_t *>(base + pl.o_prob);
+    ws.ent_bs = base + pl.o_ebs;
+    ws.ent_len = reinterpret_cast<int32_t *>(base + pl.o_elen);
+    return ws;
+}
+
+// The launch sequence of a whole batch: status cleared, then every stage.
+hipError_t launch_batched_all(spg_handle h, const BatchedPlan &pl, const std::vector<int64_t> &stage_chunks,
+                              char *base, char *arena_c, int64_t arena_bytes, hipStream_t s) {
+    const Workspace ws = batched_workspace(pl, base);
+    int64_t *d_S = reinterpret_cast<int64_t *>(base + pl.o_S);
+    int64_t *d_roff = reinterpret_cast<int64_t *>(base + pl.o_roff);
+    BatchProb *d_tab = reinterpret_cast<BatchProb *>(base + pl.o_tab);
+    BatchStatus *d_stat = reinterpret_cast<BatchStatus *>(base + pl.o_stat);
+    hipError_t e = launch_batched_begin(d_stat, s);
+    // lane windows as in the single product (their keys bound B's columns)
+    const bool win = uses_windows(h->group_rows) && pl.max_bcols < ((int64_t)1 << 26);
+    const Thresholds th = thresholds(h, win, pl.max_bcols <= ((int64_t)1 << 21));
+    for (size_t si = 0; si < pl.st.size() && e == hipSuccess; ++si) {
+        const auto &x = pl.st[si];
+        BatchStage bs;
+        bs.all = d_tab;
+        bs.tab = d_tab + x.first;
+        bs.first = x.first;
+        bs.nprob = x.n;
+        bs.row_off = d_roff + x.roff;
+        bs.chunk_off = d_roff + pl.roff_total + x.roff;
+        bs.chunks = stage_chunks[si];
+        bs.rows = x.rows;
+        bs.a_rpt_bytes = x.arb;
+        bs.b_rpt_bytes = x.brb;
+        bs.link = x.link ? 1 : 0;
+        bs.S = d_S;
+        bs.arena = arena_c;
+        bs.arena_bytes = arena_bytes;
+        bs.data_off = pl.rpt_end;
+        bs.status = d_stat;
+        e = launch_batched_stage(bs, ws, th, h->num_cu, h->grid_waves, s);
+    }
+    return e;
+}
+
+// The call's result from the batch status read back after the batch.
+int finish_batched(spg_handle h, const BatchStatus &bst, const Ctl &ctl, const BatchedPlan &pl,
+                   int64_t *required_bytes) {
+    h->nprod = bst.nprod;
+    for (int i = 0; i < kNumClasses; ++i) h->counts[i] = ctl.count[i];  // the last stage's rows
+    if (bst.flags & kBatchHeavyRow) {
+        *required_bytes = -1;
+        return fail(h, SPG_ERR_CAPACITY, "a row has more than %d products; use the single-product calls", kCapBlock);
+    }
+    *required_bytes = std::max<int64_t>(bst.required, pl.rpt_end);
+    if (bst.flags & kBatchOverflow)
+        return fail(h, SPG_ERR_CAPACITY, "arena too small: %lld bytes needed", (long long)*required_bytes);
+    return SPG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *arena, int64_t arena_bytes,
+                   spg_batched_out *out, int64_t *required_bytes, void *stream) {
+    if (!h) return SPG_ERR_ARG;
+    h->err.clear();
+    BatchedPlan pl;
+    int rc;
+    if ((rc = plan_batched(h, count, probs, arena, arena_bytes, out, required_bytes, &pl))) return rc;
+    if (count == 0) return SPG_OK;
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
     bool realloc = false;
-    if (total > h->b_bytes) {
+    if (pl.total > h->b_bytes) {
         if (h->graph_exec) {
             HIP_TRY(h, hipStreamSynchronize(s));
             (void)hipGraphExecDestroy(h->graph_exec);
             h->graph_exec = nullptr;
         }
-        if ((rc = grow(h, &h->b_mem, &h->b_bytes, total, "batched workspace"))) return rc;
+        if ((rc = grow(h, &h->b_mem, &h->b_bytes, pl.total, "batched workspace"))) return rc;
         realloc = true;
     }
     if ((size_t)count > h->b_host_n) {
@@ -1179,68 +1359,24 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
                                  hipHostMallocDefault));
         h->b_host_n = (size_t)count;
     }
-    if (2 * roff_total > h->b_row_off_n) {
+    if (2 * pl.roff_total > h->b_row_off_n) {
         if (h->b_row_off_host) HIP_TRY(h, hipHostFree(h->b_row_off_host));
         h->b_row_off_host = nullptr;
-        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_row_off_host), 16 * roff_total, hipHostMallocDefault));
-        h->b_row_off_n = 2 * roff_total;
+        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_row_off_host), 16 * pl.roff_total,
+                                 hipHostMallocDefault));
+        h->b_row_off_n = 2 * pl.roff_total;
     }
     if (!h->b_status_host)
         HIP_TRY(h, hipHostMalloc(reinterpret_cast<void **>(&h->b_status_host), sizeof(BatchStatus), hipHostMallocDefault));
     if (!h->cap_stream) HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     char *base = static_cast<char *>(h->b_mem);
-    Workspace ws;
-    ws.row_nprod = reinterpret_cast<int64_t *>(base + o_nprod);
-    ws.row_class = reinterpret_cast<uint8_t *>(base + o_class);
-    ws.row_size = reinterpret_cast<int32_t *>(base + o_size);
-    ws.class_rows = reinterpret_cast<int32_t *>(base + o_rows);
-    ws.tile_sum = reinterpret_cast<int64_t *>(base + o_tile);
-    ws.ctl = reinterpret_cast<Ctl *>(base + o_ctl);
-    ws.row_prob = reinterpret_cast<int32_t *>(base + o_prob);
-    ws.ent_bs = base + o_ebs;
-    ws.ent_len = reinterpret_cast<int32_t *>(base + o_elen);
-    int64_t *d_S = reinterpret_cast<int64_t *>(base + o_S);
-    int64_t *d_roff = reinterpret_cast<int64_t *>(base + o_roff);
-    BatchProb *d_tab = reinterpret_cast<BatchProb *>(base + o_tab);
-    BatchStatus *d_stat = reinterpret_cast<BatchStatus *>(base + o_stat);
     char *arena_c = static_cast<char *>(arena);
-    // host table
-    std::vector<int64_t> stage_chunks(st.size(), 0);
-    for (size_t si = 0; si < st.size(); ++si) {
-        auto &x = st[si];
-        int64_t ro = 0, eo = 0, co = 0;
-        for (int i = 0; i < x.n; ++i) {
-            const int p = x.first + i;
-            const spg_problem &q = probs[p];
-            BatchProb &b = h->b_host[p];
-            std::memset(&b, 0, sizeof b);
-            b.row_off = ro;
-            b.rows = q.A.rows;
-            b.ncols_b = ccols[(size_t)p];
-            b.a_rpt = q.A.rpt;
-            b.a_col = q.A.col;
-            b.a_val = q.A.val;
-            if (q.b_from < 0) {
-                b.b_rpt = q.B.rpt;
-                b.b_col = q.B.col;
-                b.b_val = q.B.val;
-            }
-            b.c_rpt = reinterpret_cast<int64_t *>(arena_c + rpt_off[(size_t)p]);
-            b.rpt_off = rpt_off[(size_t)p];
-            b.b_from = q.b_from;
-            b.ent_off = eo;
-            h->b_row_off_host[x.roff + (size_t)i] = ro;
-            h->b_row_off_host[roff_total + x.roff + (size_t)i] = co;
-            ro += q.A.rows;
-            eo += q.A.nnz;
-            co += (q.A.rows + kBatchChunkRows - 1) / kBatchChunkRows;
-        }
-        h->b_row_off_host[x.roff + (size_t)x.n] = ro;
-        h->b_row_off_host[roff_total + x.roff + (size_t)x.n] = co;
-        stage_chunks[si] = co;
-    }
+    std::vector<int64_t> stage_chunks;
+    fill_batched_tables(pl, probs, arena_c, h->b_host, h->b_row_off_host, &stage_chunks);
+    BatchProb *d_tab = reinterpret_cast<BatchProb *>(base + pl.o_tab);
+    BatchStatus *d_stat = reinterpret_cast<BatchStatus *>(base + pl.o_stat);
     HIP_TRY(h, hipMemcpyAsync(d_tab, h->b_host, sizeof(BatchProb) * (size_t)count, hipMemcpyHostToDevice, s));
-    HIP_TRY(h, hipMemcpyAsync(d_roff, h->b_row_off_host, 16 * roff_total, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(base + pl.o_roff, h->b_row_off_host, 16 * pl.roff_total, hipMemcpyHostToDevice, s));
     // graph signature: problems, arena, outputs, options
     std::vector<int64_t> sig;
     sig.push_back(count);
@@ -1265,32 +1401,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
         }
         hipStream_t cs = h->cap_stream;
         HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        hipError_t e = launch_batched_begin(d_stat, cs);
-        // lane windows as in the single product (their keys bound B's columns)
-        const bool win = uses_windows(h->group_rows) && max_bcols < ((int64_t)1 << 26);
-        const Thresholds th = thresholds(h, win, max_bcols <= ((int64_t)1 << 21));
-        for (size_t si = 0; si < st.size(); ++si) {
-            const auto &x = st[si];
-            if (e != hipSuccess) break;
-            BatchStage bs;
-            bs.all = d_tab;
-            bs.tab = d_tab + x.first;
-            bs.first = x.first;
-            bs.nprob = x.n;
-            bs.row_off = d_roff + x.roff;
-            bs.chunk_off = d_roff + roff_total + x.roff;
-            bs.chunks = stage_chunks[si];
-            bs.rows = x.rows;
-            bs.a_rpt_bytes = x.arb;
-            bs.b_rpt_bytes = x.brb;
-            bs.link = x.link ? 1 : 0;
-            bs.S = d_S;
-            bs.arena = arena_c;
-            bs.arena_bytes = arena_bytes;
-            bs.data_off = rpt_end;
-            bs.status = d_stat;
-            e = launch_batched_stage(bs, ws, th, h->num_cu, h->grid_waves, cs);
-        }
+        hipError_t e = launch_batched_all(h, pl, stage_chunks, base, arena_c, arena_bytes, cs);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -1311,19 +1422,50 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
     HIP_TRY(h, launch_batched_describe(d_tab, count, out, d_stat, s));
     HIP_TRY(h, hipMemcpyAsync(h->b_status_host, d_stat, sizeof(BatchStatus), hipMemcpyDeviceToHost, s));
-    HIP_TRY(h, hipMemcpyAsync(h->ctl_host, ws.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(h->ctl_host, base + pl.o_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    const BatchStatus &bst = *h->b_status_host;
-    h->nprod = bst.nprod;
-    for (int i = 0; i < kNumClasses; ++i) h->counts[i] = h->ctl_host->count[i];  // the last stage's rows
-    if (bst.flags & kBatchHeavyRow) {
-        *required_bytes = -1;
-        return fail(h, SPG_ERR_CAPACITY, "a row has more than %d products; use the single-product calls", kCapBlock);
-    }
-    *required_bytes = std::max<int64_t>(bst.required, rpt_end);
-    if (bst.flags & kBatchOverflow)
-        return fail(h, SPG_ERR_CAPACITY, "arena too small: %lld bytes needed", (long long)*required_bytes);
-    return SPG_OK;
+    return finish_batched(h, *h->b_status_host, *h->ctl_host, pl, required_bytes);
+}
+
+int spgemm_batched_noalloc(spg_handle h, int count, const spg_problem *probs, void *arena, int64_t arena_bytes,
+                           spg_batched_out *out, int64_t *required_bytes, void *stream) {
+    if (!h) return SPG_ERR_ARG;
+    h->err.clear();
+    BatchedPlan pl;
+    int rc;
+    if ((rc = plan_batched(h, count, probs, arena, arena_bytes, out, required_bytes, &pl))) return rc;
+    if (count == 0) return SPG_OK;
+    if (!h->scratch)
+        return fail(h, SPG_ERR_HIP, "the device address of the static scratch array is unknown (%s)",
+                    h->scratch_err.c_str());
+    if (pl.total > (size_t)kNoAllocScratchBytes)
+        return fail(h, SPG_ERR_SCRATCH,
+                    "this batch needs %zu bytes of workspace; the allocation-free call has %lld "
+                    "(29 bytes per row and 12 per entry of A of the largest stage, plus the tables)",
+                    pl.total, (long long)kNoAllocScratchBytes);
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // host tables in ordinary host memory: the copies complete before the
+    // stream synchronization at the end of this call, while they still exist
+    std::vector<BatchProb> tab((size_t)count);
+    std::vector<int64_t> roff(2 * pl.roff_total);
+    std::vector<int64_t> stage_chunks;
+    char *base = static_cast<char *>(h->scratch);
+    char *arena_c = static_cast<char *>(arena);
+    fill_batched_tables(pl, probs, arena_c, tab.data(), roff.data(), &stage_chunks);
+    BatchProb *d_tab = reinterpret_cast<BatchProb *>(base + pl.o_tab);
+    BatchStatus *d_stat = reinterpret_cast<BatchStatus *>(base + pl.o_stat);
+    HIP_TRY(h, hipMemcpyAsync(d_tab, tab.data(), sizeof(BatchProb) * (size_t)count, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(base + pl.o_roff, roff.data(), 16 * pl.roff_total, hipMemcpyHostToDevice, s));
+    // launched directly: instantiating a graph may allocate
+    HIP_TRY(h, launch_batched_all(h, pl, stage_chunks, base, arena_c, arena_bytes, s));
+    HIP_TRY(h, launch_batched_describe(d_tab, count, out, d_stat, s));
+    BatchStatus bst;
+    Ctl ctl;
+    HIP_TRY(h, hipMemcpyAsync(&bst, d_stat, sizeof(BatchStatus), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(&ctl, base + pl.o_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    return finish_batched(h, bst, ctl, pl, required_bytes);
 }
 
 }  // extern "C"

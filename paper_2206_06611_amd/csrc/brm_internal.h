@@ -193,6 +193,8 @@ struct BatchStatus {
 };
 
 constexpr int kBatchChunkRows = 64;  // rows per wavefront pass of the batched analysis (one wavefront)
+// device bytes of the allocation-free batched call's static workspace
+constexpr int64_t kNoAllocScratchBytes = (int64_t)64 << 20;
 
 struct BatchStage {
     BatchProb *all;      // every problem of the call
