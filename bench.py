@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "ac492352f5feb46d2a6766876fb2ec23c1a0b135909eba1a736f7e2fdd7b430e",
-                 "fetch_kib": 1093665.4, "write_kib": 842541.3, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "eeae6cce9d088692b18043a0b396674bc574d159103be2c8d9eefa0153362681",
+                 "fetch_kib": 1093514.0, "write_kib": 842975.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
@@ -99,24 +99,54 @@ def scan_bytes(M):
     return 12 * M + 8
 
 
-def cpu_baseline(A, nprod, budget_s=15.0):
-    """The oracle as it stands, timed on this host's cores over whole passes
-    of the same workload (at least one, more while under the budget)."""
+def _time_oracle(A, nthreads, budget_s):
     import oracle
-    threads = oracle.max_threads()
-    oracle.spgemm(A, A)  # warm-up (page-in, thread pool)
+    oracle.spgemm(A, A, nthreads=nthreads)  # warm-up (page-in, thread pool)
     times = []
     t_start = time.perf_counter()
     while True:
         t0 = time.perf_counter()
-        oracle.spgemm(A, A)
+        oracle.spgemm(A, A, nthreads=nthreads)
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > budget_s or len(times) >= 10:
             break
-    t = sum(times) / len(times)
+    return sum(times) / len(times), len(times)
+
+
+def cpu_baseline(A, nprod, budget_s=12.0):
+    """The oracle as it stands, timed on this host's cores over whole passes
+    of the same workload (at least one, more while under the budget): with
+    every OpenMP thread, and with one."""
+    import oracle
+    threads = oracle.max_threads()
+    t, n = _time_oracle(A, 0, budget_s)
+    t1, n1 = _time_oracle(A, 1, budget_s)
     return {"value": 2.0 * nprod / t / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"whole workload (all {A.rows} rows), mean of {len(times)} runs after 1 warm-up, "
-                      f"{threads} OpenMP threads"}
+            "sample": f"whole workload (all {A.rows} rows), mean of {n} runs after 1 warm-up, "
+                      f"{threads} OpenMP threads",
+            "single_thread": {"value": 2.0 * nprod / t1 / 1e9, "unit": "GFLOP/s", "cores": 1,
+                              "sample": f"whole workload, mean of {n1} runs after 1 warm-up, 1 thread"}}
+
+
+def stream_copy_gbs(reps=10, nbytes=1 << 30):
+    """Device-to-device copy of nbytes (PyTorch's copy kernel), timed with HIP
+    events on the current stream: bytes read + written per second, the
+    measured bandwidth peak the roofline fraction is also quoted against."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms / 1e3) / 1e9
 
 
 def time_plain(h, dA, dB, reps, warmup=1):
@@ -144,8 +174,7 @@ def batched_extra(reps=10):
     triples = [(brm.DeviceCSR.from_host(A), brm.DeviceCSR.from_host(P), brm.DeviceCSR.from_host(Pt))
                for _, A, P, Pt in inp]
     h = brm.Handle(0)
-    tune = autotune.tune_galerkin(h, triples, cache=os.path.join(ROOT, "gpurun_out", "autotune.json")
-                                  if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    tune = autotune.tune_galerkin(h, triples)  # cached under the user's cache folder
     probs = h.galerkin_problems(triples)  # marshalled once
     G, AP, arena = h.galerkin(triples, problems=probs)
     torch.cuda.synchronize()
@@ -451,6 +480,73 @@ def learned_extra(reps=5, eval_workloads=("stencil27_128", "er8_2e20"), rmat21=T
     return out
 
 
+def measure_plain(A, steps, warmup, group_rows=None):
+    """Whole products C = A*A (symbolic, allocation of C, numeric) on the
+    current stream: wall time per step and the numeric pass's time from HIP
+    events around it."""
+    import numpy as np
+    import torch
+    import paper_2206_06611_amd as brm
+
+    dev = torch.device("cuda:0")
+    dA = brm.DeviceCSR.from_host(A, device=dev)
+    h = brm.Handle(0)
+    if group_rows is not None:
+        h.set_option(brm.OPT_GROUP_ROWS, group_rows)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        c_rpt, nnz = h.symbolic(dA, dA)
+        c_col = torch.empty(nnz, dtype=torch.int32, device=dev)
+        c_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+        if ev is not None:
+            ev[0].record(stream)
+        h.numeric(dA, dA, c_rpt, c_col, c_val)
+        if ev is not None:
+            ev[1].record(stream)
+        return nnz
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        nnz = step(events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed * 1e3 / steps
+    num_ms = sum(a.elapsed_time(b) for a, b in events) / steps
+    M, nnzA = A.rows, A.nnz
+    nprod = h.stat(brm.STAT_NPROD)
+    rb = 4 if A.rpt.dtype == np.int32 else 8
+    nb = numeric_bytes(M, nnzA, nprod, nnz, rb)
+    total = nb + symbolic_bytes(M, nnzA, nprod, rb) + analysis_bytes(M, nnzA, rb) + scan_bytes(M)
+    res = {"ms_per_step": ms_step, "numeric_ms": num_ms, "nb": nb, "total_bytes": total, "nprod": nprod,
+           "nnz": nnz, "classes": h.class_rows(), "heavy_batches": h.stat(brm.STAT_HEAVY_BATCHES)}
+    h.close()
+    del dA
+    torch.cuda.empty_cache()
+    return res
+
+
+def rmat20_extra(steps=2, warmup=1):
+    """The power-law workload (R-MAT scale 20, edge factor 16, seed 3) with the
+    same step as the main line: GFLOP/s and the numeric pass against the HBM
+    roofline (heavy rows dominate: they merge through HBM spill buffers)."""
+    import synth
+    A = synth.rmat(20, 16, 3)
+    r = measure_plain(A, steps, warmup)
+    achieved = r["nb"] / (r["numeric_ms"] / 1e3) / 1e9
+    return {"workload": WORKLOADS["rmat_s20"], "rows": A.rows, "nnz_a": A.nnz, "nprod": r["nprod"],
+            "nnz_c": r["nnz"], "steps": steps, "warmup": warmup, "ms_per_step": round(r["ms_per_step"], 2),
+            "gflops": round(2.0 * r["nprod"] / (r["ms_per_step"] / 1e3) / 1e9, 3),
+            "numeric_ms": round(r["numeric_ms"], 2), "numeric_algorithmic_bytes": r["nb"],
+            "numeric_achieved_gbs": round(achieved, 1), "numeric_frac_of_peak": round(achieved / PEAK_HBM_GBS, 4),
+            "heavy_batches": r["heavy_batches"], "classes": r["classes"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,7 +557,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the learned and batched comparisons")
     ap.add_argument("--group-rows", type=int, default=None, help="rows per wavefront for short rows (1 or 4)")
     ap.add_argument("--extra", default=None,
-                    choices=["laplace", "batched", "amg", "accumulators", "learned"],
+                    choices=["laplace", "batched", "amg", "accumulators", "learned", "rmat20"],
                     help="run only this comparison and print its JSON object (no main workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB once (a reference kernel for traffic counters)")
@@ -477,7 +573,7 @@ def main():
 
     if args.extra is not None:
         fn = {"laplace": laplace_throughput_extra, "batched": batched_extra, "amg": amg_hierarchy_extra,
-              "accumulators": accumulator_extra, "learned": learned_extra}[args.extra]
+              "accumulators": accumulator_extra, "learned": learned_extra, "rmat20": rmat20_extra}[args.extra]
         res = fn()
         if isinstance(res, dict) and "autotune" in res:
             res = {k: v for k, v in res.items() if k != "autotune"}
@@ -485,45 +581,12 @@ def main():
         return
 
     A = build_input(args.workload)
-    dev = torch.device("cuda:0")
-    dA = brm.DeviceCSR.from_host(A, device=dev)
-    h = brm.Handle(0)
-    if args.group_rows is not None:
-        h.set_option(brm.OPT_GROUP_ROWS, args.group_rows)
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        c_rpt, nnz = h.symbolic(dA, dA)
-        c_col = torch.empty(nnz, dtype=torch.int32, device=dev)
-        c_val = torch.empty(nnz, dtype=torch.float64, device=dev)
-        if ev is not None:
-            ev[0].record(stream)
-        h.numeric(dA, dA, c_rpt, c_col, c_val)
-        if ev is not None:
-            ev[1].record(stream)
-        return nnz
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        nnz = step(events[k])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = elapsed * 1e3 / args.steps
-    num_ms = sum(a.elapsed_time(b) for a, b in events) / args.steps
-
+    res = measure_plain(A, args.steps, args.warmup, args.group_rows)
+    ms_step, num_ms, nb, nprod, nnz = res["ms_per_step"], res["numeric_ms"], res["nb"], res["nprod"], res["nnz"]
     M, nnzA = A.rows, A.nnz
-    nprod = h.stat(brm.STAT_NPROD)
-    rb = 4 if A.rpt.dtype == np.int32 else 8
-    nb = numeric_bytes(M, nnzA, nprod, nnz, rb)
-    total_bytes = nb + symbolic_bytes(M, nnzA, nprod, rb) + analysis_bytes(M, nnzA, rb) + scan_bytes(M)
     gflops = 2.0 * nprod / (ms_step / 1e3) / 1e9
     achieved = nb / (num_ms / 1e3) / 1e9
+    stream_gbs = stream_copy_gbs()
     out = {
         "metric": "SpGEMM GFLOP/s (2*nprod/t, plain two-pass, fp64) + HBM GB/s % of peak",
         "value": round(gflops, 3),
@@ -540,18 +603,18 @@ def main():
         "config": {"workload": args.workload, "desc": WORKLOADS[args.workload], "rows": M,
                    "nnz_a": nnzA, "nprod": nprod, "nnz_c": nnz,
                    "compression_ratio": round(nprod / nnz, 5) if nnz else None,
-                   "classes": h.class_rows()},
-        "effective_gbs_all_phases": round(total_bytes / (ms_step / 1e3) / 1e9, 2),
+                   "classes": res["classes"]},
+        "effective_gbs_all_phases": round(res["total_bytes"] / (ms_step / 1e3) / 1e9, 2),
         "numeric_ms": round(num_ms, 4),
         "roofline": {"bound": "hbm", "kernel": ("numeric pass, rows of <= 64 products (k_num_win, BRMerge in registers)"
                                                 if args.workload == "er8_2e20" else
                                                 "numeric pass, every row class (the split is in config.classes)"),
                      "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload),
-                     "algorithmic_bytes": nb},
+                     "algorithmic_bytes": nb,
+                     "stream_copy_gbs": round(stream_gbs, 1),
+                     "frac_of_stream_copy": round(achieved / stream_gbs, 4)},
     }
-    h.close()
-    del dA
     torch.cuda.empty_cache()
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -563,6 +626,9 @@ def main():
         del src, dst
     progress(f"main workload done: {ms_step:.4f} ms per step")
     if not args.no_extras:
+        out["rmat_s20"] = rmat20_extra()
+        progress("R-MAT scale 20 done")
+        torch.cuda.empty_cache()
         out["laplace2d_64"] = laplace_throughput_extra()
         progress("64 x 64 Laplacian done")
         torch.cuda.empty_cache()

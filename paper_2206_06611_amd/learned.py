@@ -1,8 +1,9 @@
 """Training of the learned row-size predictor from the method's own symbolic
-counts.  Every arithmetic step (features, targets, normalisation statistics,
-forward and backward passes, Adam, the safety margin) runs in the library's
-HIP kernels; this module only gathers the rows, shuffles them and calls the
-entry points in order."""
+counts.  Features, targets, normalisation statistics, forward and backward
+passes and Adam run in the library's HIP kernels; for the safety margin the
+network's outputs come from the forward kernel and spg_mlp_calibrate takes the
+residuals and their quantile on the host (one selection).  This module only gathers
+the rows, shuffles them and calls the entry points in order."""
 from __future__ import annotations
 
 import numpy as np
