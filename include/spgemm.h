@@ -124,6 +124,13 @@ typedef enum {
                                     outweighs 1.3x the batch's products over 2 x CUs, else 512
                                     (two per CU); 512 or 1024 forces one.  Results are
                                     bitwise the same */
+    SPG_OPT_HEAVY_SPLIT = 15,    /* heavy rows much longer than their batch's share per workgroup
+                                    are merged as several aligned subtrees of their lists, one
+                                    workgroup each, and the levels above them by one launch per
+                                    level: products per subtree (rows of more than twice that are
+                                    split).  0 (default): a quarter of a 512-thread workgroup's share
+                                    of the batch, at least 2^18; -1: never split.  Results are
+                                    bitwise the same */
     SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
                                     1 (default) one row per wavefront, merged in registers; the
                                     class then holds only rows whose lists fit power-of-two lane
@@ -190,6 +197,7 @@ typedef enum {
     SPG_STAT_SPILL_ALLOCS = 27,  /* allocations of that pool since the handle was created */
     SPG_STAT_HEAVY_WIDE = 28,    /* spill batches of the last numeric call run by 1024-thread
                                     workgroups (the others by 512-thread ones) */
+    SPG_STAT_HEAVY_SPLIT_ROWS = 29,/* heavy rows of the last numeric call merged as several subtrees */
     SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call
                                     (16: a numeric row length differed from its symbolic count;
                                     the row was truncated to its slot).  Synchronizes the device. */

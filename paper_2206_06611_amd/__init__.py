@@ -45,6 +45,7 @@ OPT_LEARNED_FORCE = 11
 OPT_GROUP_ROWS = 12
 OPT_ACCUMULATOR = 13
 OPT_HEAVY_THREADS = 14
+OPT_HEAVY_SPLIT = 15
 ACC_BRMERGE = 0
 ACC_HASH = 1
 ALLOC_PRECISE = 0
@@ -65,6 +66,7 @@ STAT_GRAPH_LAUNCHES = 25
 STAT_SPILL_POOL_BYTES = 26
 STAT_SPILL_ALLOCS = 27
 STAT_HEAVY_WIDE = 28
+STAT_HEAVY_SPLIT_ROWS = 29
 STAT_DEVICE_ERR = 30
 
 CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy", "multi"]

@@ -87,6 +87,10 @@ struct spg_handle_s {
     int64_t heavy_batches = 0;
     int64_t spill_allocs = 0;  // allocations of the spill pool
     int64_t heavy_wide = 0;    // heavy batches of the last numeric call run by 1024-thread workgroups
+    int64_t heavy_split = 0;   // products per subtree item of a split heavy row (0: automatic, -1: never)
+    int64_t heavy_split_rows = 0;  // heavy rows split into subtrees in the last numeric call
+    void *hitem_mem = nullptr;     // heavy work items, top merges, subtree results, tickets
+    size_t hitem_bytes = 0;
     // learned allocation
     int64_t alloc = 0;          // 0 precise, 1 learned, 2 upper bound
     int64_t accumulator = 0;    // 0 BRMerge, 1 hash table (comparator)
@@ -253,7 +257,6 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     int32_t *d_rows = reinterpret_cast<int32_t *>(d + info_b);
     int64_t *d_soff = reinterpret_cast<int64_t *>(d + info_b + rows_b);
     int64_t *d_loff = reinterpret_cast<int64_t *>(d + info_b + rows_b + offs_b);
-    unsigned long long *d_ticket = reinterpret_cast<unsigned long long *>(d + info_b + rows_b + 2 * offs_b);
     HIP_TRY(h, launch_heavy_info(a, ws, heavy_rows, n, d_info, s));
     std::vector<int64_t> info(3 * (size_t)n);
     HIP_TRY(h, hipMemcpyAsync(info.data(), d_info, 24 * (size_t)n, hipMemcpyDeviceToHost, s));
@@ -333,47 +336,158 @@ int run_heavy(spg_handle h, const CsrView &a, const CsrView &b, const Workspace 
     }
     batches.emplace_back(b0, n);
     if (batches.size() > 4096) return fail(h, SPG_ERR_CAPACITY, "too many spill batches; raise the spill budget");
+    // work items of every batch: whole rows, or, for a row much longer than
+    // the batch's share per workgroup, aligned subtrees of its lists (the
+    // levels above them merged by one launch per level), so that no single
+    // row bounds its batch
+    struct Plan {
+        int64_t item0, nitem;  // items of the batch
+        int threads;
+        std::vector<std::pair<int64_t, int64_t>> levels;  // [first, count) of the top merges per level
+    };
+    std::vector<Plan> plans(batches.size());
+    std::vector<HeavyItem> items;
+    std::vector<HeavyTop> tops;
+    int64_t nres = 0;
+    int64_t split_rows = 0;
+    for (size_t bi = 0; bi < batches.size(); ++bi) {
+        const int64_t lo = batches[bi].first, hi = batches[bi].second;
+        int64_t tot = 0, longest_row = 0;
+        for (int64_t j = lo; j < hi; ++j) {
+            const int64_t np = info[3 * order[(size_t)j] + 1];
+            tot += np;
+            longest_row = std::max(longest_row, np);
+        }
+        // products per subtree item: a quarter of a workgroup's share of
+        // the batch (two 512-thread workgroups per CU), at least 2^18
+        int64_t target = h->heavy_split;
+        if (target == 0) target = std::max<int64_t>(tot / (8 * (int64_t)h->num_cu), (int64_t)1 << 18);
+        std::vector<std::pair<int64_t, HeavyItem>> bitems;  // (estimated products, item)
+        std::vector<std::vector<HeavyTop>> blevels;
+        for (int64_t j = lo; j < hi; ++j) {
+            const int64_t i = order[(size_t)j];
+            const int64_t np = info[3 * i + 1], L = info[3 * i + 2];
+            if (target < 0 || np <= 2 * target || L < 2) {
+                bitems.push_back({np, HeavyItem{(int32_t)(j - lo), -1, 0, L, np}});
+                continue;
+            }
+            // subtrees of 2^H lists, at least ceil(np / target) of them (at most 1024)
+            const int64_t want = std::min<int64_t>((np + target - 1) / target, 1024);
+            int H = 0;
+            while (((L + ((int64_t)1 << (H + 1)) - 1) >> (H + 1)) >= want) ++H;
+            const int64_t S = (L + ((int64_t)1 << H) - 1) >> H;
+            if (S < 2) {
+                bitems.push_back({np, HeavyItem{(int32_t)(j - lo), -1, 0, L, np}});
+                continue;
+            }
+            ++split_rows;
+            const int64_t base = nres;
+            nres += S;
+            for (int64_t q = 0; q < S; ++q) {
+                const int64_t l0 = q << H, l1 = std::min((q + 1) << H, L);
+                bitems.push_back({np * (l1 - l0) / L, HeavyItem{(int32_t)(j - lo), (int32_t)(base + q), l0, l1, np}});
+            }
+            // the levels above: node (r, q) keeps its result in slot base + (q << r)
+            for (int r = 1; ((S + ((int64_t)1 << (r - 1)) - 1) >> (r - 1)) > 1; ++r) {
+                const int64_t nprev = (S + ((int64_t)1 << (r - 1)) - 1) >> (r - 1);
+                const int64_t ncur = (S + ((int64_t)1 << r) - 1) >> r;
+                if ((int64_t)blevels.size() < r) blevels.resize((size_t)r);
+                for (int64_t q = 0; q < ncur; ++q) {
+                    const int64_t xq = 2 * q, yq = 2 * q + 1;
+                    const bool root = ncur == 1;
+                    if (yq >= nprev && !root) continue;  // promoted unchanged
+                    HeavyTop t;
+                    t.bi = (int32_t)(j - lo);
+                    t.res_x = (int32_t)(base + (xq << (r - 1)));
+                    t.res_y = yq < nprev ? (int32_t)(base + (yq << (r - 1))) : -1;
+                    t.root = root ? 1 : 0;
+                    t.lx = (xq << (r - 1)) << H;
+                    t.ly = yq < nprev ? (yq << (r - 1)) << H : 0;
+                    t.nprod = np;
+                    blevels[(size_t)r - 1].push_back(t);
+                }
+            }
+        }
+        // largest items first
+        std::stable_sort(bitems.begin(), bitems.end(),
+                         [](const std::pair<int64_t, HeavyItem> &a, const std::pair<int64_t, HeavyItem> &b) {
+                             return a.first > b.first;
+                         });
+        Plan &pl = plans[bi];
+        pl.item0 = (int64_t)items.size();
+        pl.nitem = (int64_t)bitems.size();
+        for (auto &x : bitems) items.push_back(x.second);
+        for (auto &lv : blevels) {
+            pl.levels.push_back({(int64_t)tops.size(), (int64_t)lv.size()});
+            tops.insert(tops.end(), lv.begin(), lv.end());
+        }
+        int threads = (int)h->heavy_threads;
+        if (threads == 0) {
+            // a batch lasts at least as long as its longest item, merged by
+            // one workgroup: 1024-thread workgroups (one per CU, each about
+            // 1.4x as fast on one row) when that item outweighs a 512-thread
+            // workgroup's share of the batch by a margin, else 512-thread
+            // workgroups (two per CU, more items side by side)
+            const int64_t longest = bitems.empty() ? 0 : bitems.front().first;
+            threads = (double)longest > 1.3 * (double)tot / (2.0 * (double)h->num_cu) ? 1024 : 512;
+        }
+        pl.threads = threads;
+    }
+    h->heavy_split_rows += split_rows;
+    // items | tops | results | tickets (one per launch)
+    int64_t nlaunch = 0;
+    for (auto &pl : plans) nlaunch += 1 + (int64_t)pl.levels.size();
+    const size_t it_b = align_up(sizeof(HeavyItem) * std::max<size_t>(items.size(), 1), 256);
+    const size_t tp_b = align_up(sizeof(HeavyTop) * std::max<size_t>(tops.size(), 1), 256);
+    const size_t rs_b = align_up(16 * (size_t)std::max<int64_t>(nres, 1), 256);
+    const size_t tk_b = align_up(8 * (size_t)nlaunch, 256);
+    if ((rc = grow(h, &h->hitem_mem, &h->hitem_bytes, it_b + tp_b + rs_b + tk_b, "heavy work items"))) return rc;
+    char *hm = static_cast<char *>(h->hitem_mem);
+    HeavyItem *d_items = reinterpret_cast<HeavyItem *>(hm);
+    HeavyTop *d_tops = reinterpret_cast<HeavyTop *>(hm + it_b);
+    int64_t *d_res = reinterpret_cast<int64_t *>(hm + it_b + tp_b);
+    unsigned long long *d_tick = reinterpret_cast<unsigned long long *>(hm + it_b + tp_b + rs_b);
     HIP_TRY(h, hipMemcpy(d_rows, rows.data(), 4 * (size_t)n, hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_soff, soff.data(), 8 * (size_t)n, hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_loff, loff.data(), 8 * (size_t)n, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_items, items.data(), sizeof(HeavyItem) * items.size(), hipMemcpyHostToDevice));
+    if (!tops.empty())
+        HIP_TRY(h, hipMemcpy(d_tops, tops.data(), sizeof(HeavyTop) * tops.size(), hipMemcpyHostToDevice));
     const size_t col_b = align_up(4 * max_elems, 256), val_b = align_up(8 * max_elems, 256);
     const size_t pool_need = pool_bytes(max_elems, max_leaf);
     if (pool_need > h->spill_bytes) ++h->spill_allocs;
     if ((rc = grow(h, &h->spill_mem, &h->spill_bytes, pool_need, "spill buffers"))) return rc;
     char *sp = static_cast<char *>(h->spill_mem);
-    HIP_TRY(h, launch_zero_words(d_ticket, (int64_t)batches.size(), s));
+    HIP_TRY(h, launch_zero_words(d_tick, nlaunch, s));
+    // results start as empty lists in buffer 0 (read only after their subtree wrote them)
+    if (nres > 0) HIP_TRY(h, launch_zero_words(reinterpret_cast<unsigned long long *>(d_res), 2 * nres, s));
+    int64_t tick = 0;
     for (size_t bi = 0; bi < batches.size(); ++bi) {
-        const int64_t lo = batches[bi].first, hi = batches[bi].second;
+        const int64_t lo = batches[bi].first;
+        const Plan &pl = plans[bi];
         HeavyArgs ha;
-        ha.ticket = d_ticket + bi;
+        ha.ticket = d_tick + tick++;
         ha.rows = d_rows + lo;
         ha.spill_off = d_soff + lo;
         ha.leaf_off = d_loff + lo;
-        ha.nrows = hi - lo;
+        ha.items = d_items + pl.item0;
+        ha.nitems = pl.nitem;
+        ha.res = d_res;
         ha.spill_col = reinterpret_cast<int32_t *>(sp);
         ha.spill_val = reinterpret_cast<double *>(sp + col_b);
         ha.leaf = reinterpret_cast<int32_t *>(sp + col_b + val_b);
-        int threads = (int)h->heavy_threads;
-        if (threads == 0) {
-            // a batch lasts at least as long as its longest row, merged by
-            // one workgroup: 1024-thread workgroups (one per CU, each about
-            // 1.4x as fast on one row) when that row outweighs a 512-thread
-            // workgroup's share of the batch by a margin, else 512-thread
-            // workgroups (two per CU, more rows side by side)
-            int64_t tot = 0, longest = 0;
-            for (int64_t j = lo; j < hi; ++j) {
-                const int64_t np = info[3 * order[(size_t)j] + 1];
-                tot += np;
-                longest = std::max(longest, np);
-            }
-            threads = (double)longest > 1.3 * (double)tot / (2.0 * (double)h->num_cu) ? 1024 : 512;
-        }
-        ha.threads = threads;
-        ha.lds_cap = (int)std::min<int64_t>(h->heavy_lds_max, 4 * (int64_t)threads);
+        ha.threads = pl.threads;
+        ha.lds_cap = (int)std::min<int64_t>(h->heavy_lds_max, 4 * (int64_t)pl.threads);
         // 1024 / threads workgroups per CU
-        const int grid = (int)std::min<int64_t>(hi - lo, (int64_t)(1024 / threads) * h->num_cu);
-        if (threads == 1024) ++h->heavy_wide;
+        const int grid = (int)std::min<int64_t>(pl.nitem, (int64_t)(1024 / pl.threads) * h->num_cu);
+        if (pl.threads == 1024) ++h->heavy_wide;
         HIP_TRY(h, launch_numeric_heavy(a, b, ws, ha, grid, c_rpt, c_col, c_val, ctl, no, s));
+        for (const auto &lv : pl.levels) {
+            ha.ticket = d_tick + tick++;
+            HIP_TRY(h, launch_heavy_top(ha, d_tops + lv.first, lv.second,
+                                        (int)std::min<int64_t>(lv.second, h->num_cu), c_rpt, c_col, c_val, ctl,
+                                        no, s));
+        }
     }
     h->heavy_batches += (int64_t)batches.size();
     return SPG_OK;
@@ -528,6 +642,7 @@ int spg_destroy(spg_handle h) {
     if (h->ws_mem) (void)hipFree(h->ws_mem);
     if (h->spill_mem) (void)hipFree(h->spill_mem);
     if (h->hdesc_mem) (void)hipFree(h->hdesc_mem);
+    if (h->hitem_mem) (void)hipFree(h->hitem_mem);
     if (h->lw_mem) (void)hipFree(h->lw_mem);
     if (h->slot_mem) (void)hipFree(h->slot_mem);
     if (h->ctl2) (void)hipFree(h->ctl2);
@@ -586,6 +701,10 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
                 return fail(h, SPG_ERR_ARG, "heavy threads must be 0 (automatic), 512 or 1024");
             h->heavy_threads = value;
             break;
+        case SPG_OPT_HEAVY_SPLIT:
+            if (value < -1) return fail(h, SPG_ERR_ARG, "heavy split must be -1 (never), 0 (automatic) or > 0");
+            h->heavy_split = value;
+            break;
         case SPG_OPT_SPILL_BUDGET_MB:
             if (value < 0) return fail(h, SPG_ERR_ARG, "spill budget must be >= 0 (0: automatic)");
             h->spill_budget_mb = value;
@@ -625,6 +744,7 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_FORCE_CLASS: *value = h->force; break;
         case SPG_OPT_HEAVY_LDS_MAX: *value = h->heavy_lds_max; break;
         case SPG_OPT_HEAVY_THREADS: *value = h->heavy_threads; break;
+        case SPG_OPT_HEAVY_SPLIT: *value = h->heavy_split; break;
         case SPG_OPT_SPILL_BUDGET_MB: *value = h->spill_budget_mb; break;
         case SPG_OPT_GRID_WAVES: *value = h->grid_waves; break;
         case SPG_OPT_ALLOC: *value = h->alloc; break;
@@ -652,6 +772,7 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_SPILL_POOL_BYTES: *value = (int64_t)h->spill_bytes; return SPG_OK;
         case SPG_STAT_SPILL_ALLOCS: *value = h->spill_allocs; return SPG_OK;
         case SPG_STAT_HEAVY_WIDE: *value = h->heavy_wide; return SPG_OK;
+        case SPG_STAT_HEAVY_SPLIT_ROWS: *value = h->heavy_split_rows; return SPG_OK;
         case SPG_STAT_OVERFLOW_ROWS: *value = h->ovf_light + h->ovf_heavy; return SPG_OK;
         case SPG_STAT_PREDICTED_ROWS: {
             int64_t n = 0;
@@ -715,6 +836,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     if (learned && !h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "learned allocation needs a trained or loaded predictor");
     h->heavy_batches = 0;
     h->heavy_wide = 0;
+    h->heavy_split_rows = 0;
     h->pred_total = h->ovf_light = h->ovf_heavy = 0;
     LearnedWs lw;
     RowFeatures rf{};
@@ -852,6 +974,7 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     if ((rc = ensure_workspace(h, A->rows, A->nnz, &ws))) return rc;
     h->heavy_batches = 0;
     h->heavy_wide = 0;
+    h->heavy_split_rows = 0;
     NumOut exact;
     exact.bound = 0;
     exact.row_size = nullptr;

@@ -142,13 +142,33 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
 hipError_t launch_numeric_hash(const CsrView &A, const CsrView &B, const Workspace &ws, int cls, int num_cu,
                                const int64_t *c_rpt, int32_t *c_col, double *c_val, hipStream_t s);
 
-// Heavy rows: one workgroup of 512 or 1024 threads per row, spill buffers in HBM.
+// Heavy rows: one workgroup of 512 or 1024 threads per work item, spill
+// buffers in HBM.  A work item is a whole row, or an aligned subtree of a long
+// row's lists (lists [q 2^H, (q+1) 2^H) of the merge tree) whose result stays
+// in the row's spill buffers; the levels above a split row's subtrees are
+// merged by later launches, one per level (HeavyTop items).
+struct HeavyItem {
+    int32_t bi;     // the row's index in the batch (rows, spill_off, leaf_off)
+    int32_t res;    // -1: the whole row (its root goes to C); else the subtree's result slot
+    int64_t l0, l1; // list range [l0, l1)
+    int64_t nprod;  // the row's products
+};
+struct HeavyTop {
+    int32_t bi;
+    int32_t res_x;  // result slot of the left node (the merged node's slot)
+    int32_t res_y;  // result slot of the right node; -1: the left node alone is the root
+    int32_t root;   // 1: the merged node is the row (written to C)
+    int64_t lx, ly; // first lists of the two nodes
+    int64_t nprod;
+};
 struct HeavyArgs {
-    unsigned long long *ticket;  // zeroed counter handing out the batch's rows
-    const int32_t *rows;       // heavy row ids of this batch, largest first
+    unsigned long long *ticket;  // zeroed counter handing out the work items
+    const int32_t *rows;       // heavy row ids of this batch
     const int64_t *spill_off;  // element offset of each row's two spill buffers (2 * nprod)
     const int64_t *leaf_off;   // offset of each row's list-offset array (lists + 1 entries)
-    int64_t nrows;
+    const HeavyItem *items;    // work items of this launch, largest first
+    int64_t nitems;
+    int64_t *res;              // subtree results: (buffer 0 / 1, length) per slot
     int32_t *spill_col;
     double *spill_val;
     int32_t *leaf;
@@ -160,6 +180,9 @@ hipError_t launch_heavy_info(const CsrView &A, const Workspace &ws, const int32_
 hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Workspace &ws, const HeavyArgs &h,
                                 int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
                                 const NumOut &no, hipStream_t s);
+// one level of merges above the subtrees of split rows (1024-thread workgroups)
+hipError_t launch_heavy_top(const HeavyArgs &h, const HeavyTop *tops, int64_t ntops, int grid, const int64_t *c_rpt,
+                            int32_t *c_col, double *c_val, Ctl *ctl, const NumOut &no, hipStream_t s);
 
 // ---- batched products ------------------------------------------------------
 struct BatchProb {

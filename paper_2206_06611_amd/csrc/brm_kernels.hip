@@ -2980,17 +2980,23 @@ __device__ int64_t merge_hbm(MergeLds<T> &m, HeavyState<T> &st, int tid, const i
 }
 
 struct HeavyBatch {
-    unsigned long long *ticket;  // next row of the batch (zeroed before the launch)
+    unsigned long long *ticket;  // next work item of the launch (zeroed before the launch)
     const int32_t *rows;
     const int64_t *spill_off;  // element offset of each row's two spill buffers
     const int64_t *leaf_off;   // offset of each row's list-offset array
-    int64_t nrows;
+    const HeavyItem *items;
+    int64_t nitems;
+    int64_t *res;              // (buffer, length) of every subtree result
     int32_t *spill_col;
     double *spill_val;
     int32_t *leaf;
     int lds_cap;
 };
 
+// One work item per workgroup: a whole row (its root written to C), or the
+// aligned subtree [l0, l1) of a long row's lists, whose merged list is left in
+// the row's spill buffers (at the offset of its first list's products) and
+// described in its result slot for the merges above it.
 template <typename IA, typename IB, int T>
 __global__ __launch_bounds__(T, 4) void k_num_heavy(
     HeavyBatch hb, const void *a_rpt, Lists<IB> lists, const double *a_val,
@@ -3006,22 +3012,42 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
     const int tid = threadIdx.x;
     __shared__ int64_t s_bi;
     while (true) {
-        // rows arrive largest first; a ticket hands the next one to a free workgroup
+        // items arrive largest first; a ticket hands the next one to a free workgroup
         if (tid == 0) s_bi = (int64_t)atomicAdd(hb.ticket, 1ull);
         __syncthreads();
-        const int64_t bi = wave_uniform(s_bi);
+        const int64_t ii = wave_uniform(s_bi);
         __syncthreads();
-        if (bi >= hb.nrows) break;
+        if (ii >= hb.nitems) break;
+        const HeavyItem &it = hb.items[ii];
+        const int64_t bi = wave_uniform((int64_t)it.bi);
+        const int res_slot = wave_uniform(it.res);
+        const bool whole = res_slot < 0;
+        const int64_t lb0 = wave_uniform(it.l0), lb1 = wave_uniform(it.l1);
+        const int64_t nprod = wave_uniform(it.nprod);
         const int64_t row = hb.rows[bi];
         const int64_t a0 = ld_rpt<IA>(a_rpt, row);
         const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
         int32_t *leaf = hb.leaf + hb.leaf_off[bi];
-        // list offsets inside the row's product space
+        // list offsets inside the row's product space, for lists [lb0, lb1]:
+        // the products of the lists before lb0 first (a reduction only)
         int64_t carry = 0;
-        for (int64_t lb = 0; lb < L; lb += T) {
+        for (int64_t lb = 0; lb < lb0; lb += T) {
             const int64_t l = lb + tid;
             int64_t ln = 0;
-            if (l < L) {
+            if (l < lb0) {
+                int64_t bs;
+                int n;
+                lists.get(a0 + l, bs, n);
+                ln = n;
+            }
+            int64_t tot;
+            (void)Team<T>::excl_scan(ln, &tot, st.scr, tid);
+            carry += wave_uniform(tot);
+        }
+        for (int64_t lb = lb0; lb < lb1; lb += T) {
+            const int64_t l = lb + tid;
+            int64_t ln = 0;
+            if (l < lb1) {
                 int64_t bs;
                 int n;
                 lists.get(a0 + l, bs, n);
@@ -3029,18 +3055,18 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
             }
             int64_t tot;
             const int64_t ex = Team<T>::excl_scan(ln, &tot, st.scr, tid);
-            if (l < L) leaf[l] = (int32_t)(carry + ex);
+            if (l < lb1) leaf[l] = (int32_t)(carry + ex);
             carry += wave_uniform(tot);
         }
-        const int64_t nprod = carry;
-        if (tid == 0) leaf[L] = (int32_t)nprod;
+        // the end offset (also the next item's first offset: the same value)
+        if (tid == 0) leaf[lb1] = (int32_t)carry;
         int32_t *bcol[2] = {hb.spill_col + hb.spill_off[bi], hb.spill_col + hb.spill_off[bi] + nprod};
         double *bval[2] = {hb.spill_val + hb.spill_off[bi], hb.spill_val + hb.spill_off[bi] + nprod};
         const int64_t cs = c_rpt[row];
         const int64_t ccap = c_rpt[row + 1] - cs;
         if (tid == 0) {
             st.sp = 0;
-            st.next_list = 0;
+            st.next_list = lb0;
         }
         // global stores of this workgroup become visible to it at the barrier (workgroup scope)
         __syncthreads();
@@ -3049,28 +3075,28 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
             if (tid == 0) {
                 int act = kActFail;
                 const int sp = st.sp;
-                if (++guard > 4 * (L + 64)) {
+                if (++guard > 4 * (lb1 - lb0 + 64)) {
                     act = kActFail;
                 } else if (sp >= 2 && st.stack[sp - 2].h == st.stack[sp - 1].h &&
                            (st.stack[sp - 1].p & 1) && st.stack[sp - 2].p == st.stack[sp - 1].p - 1) {
                     act = kActMerge;
                     const HeavyNode &y = st.stack[sp - 1];
-                    st.root = (y.p >> 1) == 0 && ((int64_t)1 << (y.h + 1)) >= L;
-                } else if (st.next_list < L) {
+                    st.root = whole && (y.p >> 1) == 0 && ((int64_t)1 << (y.h + 1)) >= L;
+                } else if (st.next_list < lb1) {
                     const int64_t l = st.next_list;
                     int h = 0;
-                    while (h < 40 && ((l >> h) & 1) == 0 && l + ((int64_t)1 << h) < L) {
-                        const int64_t e = (l + ((int64_t)1 << (h + 1))) < L ? l + ((int64_t)1 << (h + 1)) : L;
+                    while (h < 40 && ((l >> h) & 1) == 0 && l + ((int64_t)1 << h) < lb1) {
+                        const int64_t e = (l + ((int64_t)1 << (h + 1))) < lb1 ? l + ((int64_t)1 << (h + 1)) : lb1;
                         if ((int64_t)leaf[e] - leaf[l] <= hb.lds_cap && e - l <= hb.lds_cap) ++h;
                         else break;
                     }
                     st.h = h;
                     st.l0 = l;
-                    st.l1 = (l + ((int64_t)1 << h)) < L ? l + ((int64_t)1 << h) : L;
-                    st.root = (l == 0 && st.l1 == L);
+                    st.l1 = (l + ((int64_t)1 << h)) < lb1 ? l + ((int64_t)1 << h) : lb1;
+                    st.root = whole && l == 0 && st.l1 == L;
                     act = kActNode;
                 } else if (sp == 1) {
-                    act = st.stack[0].buf == 2 ? kActDone : kActToC;
+                    act = (!whole || st.stack[0].buf == 2) ? kActDone : kActToC;
                 } else if (sp >= 2 && (st.stack[sp - 1].p & 1) == 0) {
                     act = kActPromote;
                 }
@@ -3080,9 +3106,11 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
             const int act = wave_uniform(st.action);
             if (act == kActDone) break;
             if (act == kActFail) {
-                if (tid == 0)
+                if (tid == 0) {
                     atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err),
                              (unsigned long long)kErrHeavyCapacity);
+                    st.sp = 0;
+                }
                 break;
             }
             if (act == kActNode) {
@@ -3167,24 +3195,118 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
             // global stores of this workgroup become visible to it at the barrier (workgroup scope)
             __syncthreads();
         }
-        if (tid == 0 && st.sp == 1) finish_row(no, ctl, row, st.stack[0].len, ccap, true);
+        if (tid == 0) {
+            if (whole) {
+                if (st.sp == 1) finish_row(no, ctl, row, st.stack[0].len, ccap, true);
+            } else {
+                // a failed walk leaves an empty list in buffer 0 (the error bit is set)
+                const bool ok = st.sp == 1;
+                hb.res[2 * res_slot] = ok ? st.stack[0].buf : 0;
+                hb.res[2 * res_slot + 1] = ok ? st.stack[0].len : 0;
+            }
+        }
         __syncthreads();
     }
 }
 
-hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Workspace &ws, const HeavyArgs &h,
-                                int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
-                                const NumOut &no, hipStream_t s) {
+// The merges above the subtrees of split rows, one level per launch: the
+// two nodes (siblings of the merge tree, every level below already merged)
+// are merged into the other spill buffer or into the right node's region
+// (merge_hbm's overlap rule), or into C at the row's root; a root whose
+// right sibling does not exist is copied into C.  One workgroup per merge.
+template <int T>
+__global__ __launch_bounds__(T) void k_heavy_top(HeavyBatch hb, const HeavyTop *tops, int64_t ntops,
+                                                 const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+                                                 NumOut no) {
+    __shared__ MergeLds<T> mrg;
+    __shared__ HeavyState<T> st;
+    __shared__ int64_t s_i;
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) s_i = (int64_t)atomicAdd(hb.ticket, 1ull);
+        __syncthreads();
+        const int64_t ti = wave_uniform(s_i);
+        __syncthreads();
+        if (ti >= ntops) break;
+        const HeavyTop &t = tops[ti];
+        const int64_t bi = wave_uniform((int64_t)t.bi);
+        const int rxs = wave_uniform(t.res_x), rys = wave_uniform(t.res_y);
+        const bool root = wave_uniform(t.root) != 0;
+        const int64_t nprod = wave_uniform(t.nprod);
+        const int64_t row = hb.rows[bi];
+        const int32_t *leaf = hb.leaf + hb.leaf_off[bi];
+        int32_t *bcol[2] = {hb.spill_col + hb.spill_off[bi], hb.spill_col + hb.spill_off[bi] + nprod};
+        double *bval[2] = {hb.spill_val + hb.spill_off[bi], hb.spill_val + hb.spill_off[bi] + nprod};
+        const int64_t cs = c_rpt[row];
+        const int64_t ccap = c_rpt[row + 1] - cs;
+        const int64_t rx = wave_uniform((int64_t)leaf[wave_uniform(t.lx)]);
+        const int xb = (int)wave_uniform(hb.res[2 * rxs]);
+        const int64_t xl = wave_uniform(hb.res[2 * rxs + 1]);
+        int yb = 0;
+        int64_t yl = 0, ry = nprod;
+        if (rys >= 0) {
+            ry = wave_uniform((int64_t)leaf[wave_uniform(t.ly)]);
+            yb = (int)wave_uniform(hb.res[2 * rys]);
+            yl = wave_uniform(hb.res[2 * rys + 1]);
+        }
+        // every node lies inside its products: a result out of these bounds
+        // (a failed walk below) is reported, not read
+        const bool ok = (xb == 0 || xb == 1) && (yb == 0 || yb == 1) && rx >= 0 && xl >= 0 && rx + xl <= ry &&
+                        yl >= 0 && ry + yl <= nprod;
+        if (!ok) {
+            if (tid == 0)
+                atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrHeavyCapacity);
+            __syncthreads();
+            continue;
+        }
+        if (rys < 0) {
+            // the root is the left node alone
+            const int64_t n = xl < ccap ? xl : ccap;
+            for (int64_t j = tid; j < n; j += T) {
+                c_col[cs + j] = bcol[xb][rx + j];
+                c_val[cs + j] = bval[xb][rx + j];
+            }
+            if (tid == 0) finish_row(no, ctl, row, xl, ccap, true);
+        } else {
+            const int ob = root ? 2 : (xb == yb ? 1 - xb : yb);
+            int32_t *oc = root ? c_col + cs : bcol[ob] + rx;
+            double *ov = root ? c_val + cs : bval[ob] + rx;
+            const int64_t cap = root ? ccap : (nprod - rx);
+            const int64_t len = merge_hbm<T>(mrg, st, tid, bcol[xb] + rx, bval[xb] + rx, xl, bcol[yb] + ry,
+                                          bval[yb] + ry, yl, oc, ov, cap);
+            if (tid == 0) {
+                if (root) {
+                    finish_row(no, ctl, row, len, ccap, true);
+                } else {
+                    hb.res[2 * rxs] = ob;
+                    hb.res[2 * rxs + 1] = len;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+static HeavyBatch heavy_batch(const HeavyArgs &h) {
     HeavyBatch hb;
     hb.ticket = h.ticket;
     hb.rows = h.rows;
     hb.spill_off = h.spill_off;
     hb.leaf_off = h.leaf_off;
-    hb.nrows = h.nrows;
+    hb.items = h.items;
+    hb.nitems = h.nitems;
+    hb.res = h.res;
     hb.spill_col = h.spill_col;
     hb.spill_val = h.spill_val;
     hb.leaf = h.leaf;
     hb.lds_cap = h.lds_cap;
+    return hb;
+}
+
+hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Workspace &ws, const HeavyArgs &h,
+                                int grid, const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+                                const NumOut &no, hipStream_t s) {
+    const HeavyBatch hb = heavy_batch(h);
 #define BRM_HEAVY(IA, IB)                                                                              \
     do {                                                                                               \
         if (h.threads == 1024)                                                                         \
@@ -3199,6 +3321,15 @@ hipError_t launch_numeric_heavy(const CsrView &A, const CsrView &B, const Worksp
     else if (B.rpt_bytes == 4) BRM_HEAVY(int64_t, int32_t);
     else BRM_HEAVY(int64_t, int64_t);
 #undef BRM_HEAVY
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_top(const HeavyArgs &h, const HeavyTop *tops, int64_t ntops, int grid, const int64_t *c_rpt,
+                            int32_t *c_col, double *c_val, Ctl *ctl, const NumOut &no, hipStream_t s) {
+    if (ntops == 0) return hipSuccess;
+    const HeavyBatch hb = heavy_batch(h);
+    hipLaunchKernelGGL((k_heavy_top<1024>), dim3(grid), dim3(1024), 0, s, hb, tops, ntops, c_rpt, c_col, c_val,
+                       ctl, no);
     return hipGetLastError();
 }
 

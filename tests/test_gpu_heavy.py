@@ -149,3 +149,78 @@ def test_long_single_lists(handle):
         handle.set_option(brm.OPT_FORCE_CLASS, force)
         C = run(handle, A, B)
         assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+
+
+@pytest.mark.parametrize("split", [2048, 9000, 40000])
+def test_split_rows(handle, split):
+    # long rows merged as several aligned subtrees (one workgroup each) and
+    # the levels above them (one launch per level): bitwise the same tree
+    print(f"case: R-MAT scale 13, subtrees of {split} products", flush=True)
+    A = synth.rmat(13, 16, 27)
+    handle.set_option(brm.OPT_HEAVY_SPLIT, split)
+    C = run(handle, A, A)
+    assert handle.stat(brm.STAT_HEAVY_SPLIT_ROWS) > 0
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+def test_split_every_row_with_spill_batches(handle):
+    # every non-empty row heavy and split where it has 2 lists or more, in
+    # several spill batches (each with its own top levels)
+    print("case: R-MAT scale 12 all heavy, subtrees of 1024 products, 1 MB budget", flush=True)
+    A = synth.rmat(12, 16, 28)
+    handle.set_option(brm.OPT_FORCE_CLASS, 6)
+    handle.set_option(brm.OPT_HEAVY_SPLIT, 1024)
+    handle.set_option(brm.OPT_SPILL_BUDGET_MB, 1)
+    C = run(handle, A, A)
+    assert handle.stat(brm.STAT_HEAVY_SPLIT_ROWS) > 0 and handle.stat(brm.STAT_HEAVY_BATCHES) > 1
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+
+
+def test_split_with_long_single_lists(handle):
+    # subtrees whose nodes include single lists longer than LDS, and odd
+    # subtree counts (a promoted node on the way up)
+    print("case: long single lists, split rows", flush=True)
+    rng = np.random.default_rng(29)
+    ncols = 60000
+    lens = [9000, 3, 5000, 17, 2, 4500, 1, 64, 7000, 5, 900, 3000, 6, 11, 5200]
+    K = len(lens)
+    b_cols = [np.sort(rng.choice(ncols, size=n, replace=False)) for n in lens]
+    B = synth.CSR(K, ncols, np.concatenate([[0], np.cumsum(lens)]).astype(np.int32),
+                  np.concatenate(b_cols).astype(np.int32), rng.uniform(-1, 1, sum(lens)))
+    rows = [np.arange(K), np.arange(0, K, 2), np.arange(1, K), np.arange(K - 5)]
+    A = synth.CSR(len(rows), K, np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32),
+                  np.concatenate(rows).astype(np.int32), rng.uniform(-1, 1, sum(len(r) for r in rows)))
+    for split in (3000, 6000):
+        handle.set_option(brm.OPT_HEAVY_SPLIT, split)
+        C = run(handle, A, B)
+        assert handle.stat(brm.STAT_HEAVY_SPLIT_ROWS) > 0
+        assert_matches_oracle(C, oracle.spgemm(A, B), oracle.brmerge(A, B))
+
+
+@pytest.mark.parametrize("alloc", ["upper", "learned_force"])
+def test_split_rows_in_slotted_modes(alloc):
+    # split rows written into upper-bound slots, or into predicted slots that
+    # are too small (every heavy row falls back to the exact path)
+    print(f"case: R-MAT scale 13, split rows, {alloc}", flush=True)
+    from paper_2206_06611_amd import learned
+    A = synth.rmat(13, 16, 30)
+    dA = brm.DeviceCSR.from_host(A)
+    h = brm.Handle(0)
+    try:
+        h.set_option(brm.OPT_HEAVY_SPLIT, 4096)
+        ref = to_host(h.spgemm(dA, dA))
+        if alloc == "upper":
+            h.set_option(brm.OPT_ALLOC, brm.ALLOC_UPPER)
+        else:
+            feats, targets = learned.collect(h, [(dA, dA)])
+            learned.train(h, feats, targets, seed=1, epochs=1)
+            h.set_option(brm.OPT_ALLOC, brm.ALLOC_LEARNED)
+            h.set_option(brm.OPT_LEARNED_FORCE, 1)
+        got = to_host(h.spgemm(dA, dA))
+        torch.cuda.synchronize()
+        assert h.stat(brm.STAT_DEVICE_ERR) == 0
+        for x, y in zip(ref, got):
+            assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                                  y.view(np.int64) if y.dtype == np.float64 else y)
+    finally:
+        h.close()

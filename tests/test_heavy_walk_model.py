@@ -80,20 +80,30 @@ def merge_tiles(X, Y, T, rx, ry, zcap, same_buffer_as_y):
     return out
 
 
-def heavy_walk(list_cols, lds_cap, T, ccap, exact=True):
+def heavy_walk(list_cols, lds_cap, T, ccap, exact=True, l_begin=0, l_end=None, writes=None):
     """Replays the walk over one row whose lists have the given column
-    arrays (sorted, duplicate-free).  exact=False models every node as long
-    as its products (an upper bound of every length)."""
+    arrays (sorted, duplicate-free): the whole row (l_begin = 0, l_end =
+    None; its root goes to C), or the aligned subtree [l_begin, l_end) of a
+    split row, whose result stays in a spill buffer and is returned as
+    (buffer, length, columns).  exact=False models every node as long as its
+    products (an upper bound of every length).  `writes` collects the
+    (buffer, lo, hi) ranges written to the spill buffers."""
     L = len(list_cols)
+    whole = l_end is None
+    if whole:
+        l_end = L
     lens = np.array([len(c) for c in list_cols], dtype=np.int64)
     leaf = np.zeros(L + 1, dtype=np.int64)
     leaf[1:] = np.cumsum(lens)
     nprod = int(leaf[L])
     assert nprod < 2 ** 31 and L < 2 ** 31  # int32 list offsets
+    assert 0 <= l_begin < l_end <= L
     stack = []  # dicts p, h, len, buf, cols
-    next_list = 0
+    next_list = l_begin
     guard = 0
     actions = []
+    if writes is None:
+        writes = []
 
     def content(a, b):
         if not exact:
@@ -113,15 +123,15 @@ def heavy_walk(list_cols, lds_cap, T, ccap, exact=True):
     while True:
         guard += 1
         sp = len(stack)
-        if guard > 4 * (L + 64):
+        if guard > 4 * (l_end - l_begin + 64):
             raise AssertionError("walk guard exceeded")
         if sp >= 2 and stack[-2]["h"] == stack[-1]["h"] and (stack[-1]["p"] & 1) and \
                 stack[-2]["p"] == stack[-1]["p"] - 1:
             act = "merge"
-        elif next_list < L:
+        elif next_list < l_end:
             act = "node"
         elif sp == 1:
-            act = "done" if stack[0]["buf"] == 2 else "toC"
+            act = "done" if (not whole or stack[0]["buf"] == 2) else "toC"
         elif sp >= 2 and (stack[-1]["p"] & 1) == 0:
             act = "promote"
         else:
@@ -132,14 +142,14 @@ def heavy_walk(list_cols, lds_cap, T, ccap, exact=True):
         if act == "node":
             l = next_list
             h = 0
-            while h < 40 and ((l >> h) & 1) == 0 and l + (1 << h) < L:
-                e = min(l + (1 << (h + 1)), L)
+            while h < 40 and ((l >> h) & 1) == 0 and l + (1 << h) < l_end:
+                e = min(l + (1 << (h + 1)), l_end)
                 if leaf[e] - leaf[l] <= lds_cap and e - l <= lds_cap:
                     h += 1
                 else:
                     break
-            l0, l1 = l, min(l + (1 << h), L)
-            root = l0 == 0 and l1 == L
+            l0, l1 = l, min(l + (1 << h), l_end)
+            root = whole and l0 == 0 and l1 == L
             r0, np_ = int(leaf[l0]), int(leaf[l1] - leaf[l0])
             if np_ <= lds_cap and l1 - l0 <= lds_cap:
                 pass  # LDS node: brmerge_range_lds over lists [l0, l1)
@@ -152,15 +162,16 @@ def heavy_walk(list_cols, lds_cap, T, ccap, exact=True):
                 assert ln <= ccap
             else:
                 # written to buffer 0 at its first list's products
-                assert 0 <= r0 and r0 + ln <= nprod
+                assert leaf[l_begin] <= r0 and r0 + ln <= leaf[l_end], "node write outside its subtree"
                 for rg in live():
                     assert not rg.overlaps(0, r0, r0 + ln), "node write over a live node"
+                writes.append((0, r0, r0 + ln))
             assert len(stack) < 64, "node stack overflow"
             stack.append({"p": l0 >> h, "h": h, "len": ln, "buf": 2 if root else 0, "cols": cols})
             next_list = l1
         elif act == "merge":
             x, y = stack[-2], stack[-1]
-            root = (y["p"] >> 1) == 0 and (1 << (y["h"] + 1)) >= L
+            root = whole and (y["p"] >> 1) == 0 and (1 << (y["h"] + 1)) >= L
             rx, ry = int(leaf[x["p"] << x["h"]]), int(leaf[y["p"] << y["h"]])
             assert x["len"] <= ry - rx, "left child longer than its products"
             assert ry + y["len"] <= nprod
@@ -177,8 +188,10 @@ def heavy_walk(list_cols, lds_cap, T, ccap, exact=True):
                 if ob == y["buf"]:
                     assert rx + ln <= ry + y["len"]
             if not root:
+                assert leaf[l_begin] <= rx and rx + ln <= leaf[l_end], "merge write outside its subtree"
                 for rg in live(exclude=(len(stack) - 2, len(stack) - 1)):
                     assert not rg.overlaps(ob, rx, rx + ln), "merge write over a live node"
+                writes.append((ob, rx, rx + ln))
             stack[-2:] = [{"p": x["p"] >> 1, "h": x["h"] + 1, "len": ln, "buf": ob, "cols": cols}]
         elif act == "promote":
             stack[-1]["p"] >>= 1
@@ -187,7 +200,106 @@ def heavy_walk(list_cols, lds_cap, T, ccap, exact=True):
             assert stack[0]["len"] <= ccap
             stack[0]["buf"] = 2
     assert len(stack) == 1 and stack[0]["h"] >= 0
+    if not whole:
+        assert stack[0]["buf"] in (0, 1)
+        return (stack[0]["buf"], stack[0]["len"], stack[0]["cols"]), actions
     return stack[0]["len"], actions
+
+
+def plan_split(np_, L, target):
+    """run_heavy's cut of a long row: (H, S) subtrees of 2^H lists, or None
+    when the row stays whole."""
+    if target < 0 or np_ <= 2 * target or L < 2:
+        return None
+    want = min((np_ + target - 1) // target, 1024)
+    H = 0
+    while ((L + (1 << (H + 1)) - 1) >> (H + 1)) >= want:
+        H += 1
+    S = (L + (1 << H) - 1) >> H
+    return None if S < 2 else (H, S)
+
+
+def top_levels(S, H):
+    """The merges above S subtrees, level by level: (res_x, res_y or -1,
+    root, lx, ly) with result slots relative to the row's first slot."""
+    levels = []
+    r = 1
+    while ((S + (1 << (r - 1)) - 1) >> (r - 1)) > 1:
+        nprev = (S + (1 << (r - 1)) - 1) >> (r - 1)
+        ncur = (S + (1 << r) - 1) >> r
+        lv = []
+        for q in range(ncur):
+            xq, yq = 2 * q, 2 * q + 1
+            root = ncur == 1
+            if yq >= nprev and not root:
+                continue
+            lv.append((xq << (r - 1), (yq << (r - 1)) if yq < nprev else -1, root,
+                       (xq << (r - 1)) << H, ((yq << (r - 1)) << H) if yq < nprev else 0))
+        levels.append(lv)
+        r += 1
+    return levels
+
+
+def split_row(list_cols, lds_cap, T, target, exact=True):
+    """A split row end to end: every subtree walk (checked to write only
+    inside its own products, so that the subtrees of one launch never
+    meet), then the top merges level by level with the kernel's buffer rule
+    and bounds checks.  Returns the root's length."""
+    L = len(list_cols)
+    lens = np.array([len(c) for c in list_cols], dtype=np.int64)
+    leaf = np.zeros(L + 1, dtype=np.int64)
+    leaf[1:] = np.cumsum(lens)
+    nprod = int(leaf[L])
+    cut = plan_split(nprod, L, target)
+    assert cut is not None
+    H, S = cut
+    res = {}
+    spans = []
+    for q in range(S):
+        l0, l1 = q << H, min((q + 1) << H, L)
+        w = []
+        (buf, ln, cols), _ = heavy_walk(list_cols, lds_cap, T, ccap=nprod, exact=exact, l_begin=l0, l_end=l1,
+                                        writes=w)
+        for b, lo, hi in w:
+            assert leaf[l0] <= lo and hi <= leaf[l1]
+        spans.append((leaf[l0], leaf[l1]))
+        res[q] = (buf, ln, cols)
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert a1 <= b0
+    root_len = None
+    for lv in top_levels(S, H):
+        written = []
+        for rx_s, ry_s, root, lx, ly in lv:
+            xb, xl, xc = res[rx_s]
+            rx = int(leaf[lx])
+            if ry_s < 0:
+                assert root
+                root_len = xl
+                continue
+            yb, yl, yc = res[ry_s]
+            ry = int(leaf[ly])
+            assert xb in (0, 1) and yb in (0, 1)
+            assert rx + xl <= ry and ry + yl <= nprod
+            if root:
+                root_len = merge_tiles(xc, yc, T, rx, ry, nprod, False) if exact else xl + yl
+                continue
+            ob = 1 - xb if xb == yb else yb
+            if exact:
+                ln = merge_tiles(xc, yc, T, rx, ry, nprod - rx, ob == yb)
+                cols = np.union1d(xc, yc)
+            else:
+                ln, cols = xl + yl, None
+                if ob == yb:
+                    assert rx + ln <= ry + yl
+            # the node's products end where the next node of its level begins
+            end = int(leaf[min(ly + (ly - lx), L)])
+            assert rx + ln <= end
+            for b, lo, hi in written:
+                assert not (b == ob and lo < rx + ln and rx < hi), "two merges of a level overlap"
+            written.append((ob, rx, rx + ln))
+            res[rx_s] = (ob, ln, cols)
+    assert root_len is not None
+    return root_len
 
 
 def row_lists(A, B, i):
@@ -313,3 +425,42 @@ def test_pool_layout_bounds(budget):
             assert a1 <= b0, "two rows of a batch share spill entries"
     # the column, value and list-offset parts fit the pool
     assert ((4 * max_e + 255) // 256 * 256 + (8 * max_e + 255) // 256 * 256 + 4 * max_l) <= pool
+
+
+@pytest.mark.parametrize("T,target", [(512, 4096), (1024, 15000), (512, 9000)])
+def test_split_rows_exact(T, target):
+    A = synth.rmat(12, 16, 13)
+    rows, nprod = heavy_rows(A, 4096)
+    done = 0
+    for i in rows[np.argsort(-nprod[rows])][:25]:
+        lists = row_lists(A, A, i)
+        if plan_split(int(nprod[i]), len(lists), target) is None:
+            continue
+        ln = split_row(lists, 4 * T, T, target)
+        assert ln == len(np.unique(np.concatenate(lists)))
+        done += 1
+    assert done > 0
+
+
+def test_split_rows_upper_bound_scale15():
+    A = synth.rmat(15, 16, 14)
+    rows, nprod = heavy_rows(A, 4096)
+    for i in rows[np.argsort(-nprod[rows])][:20]:
+        lists = row_lists(A, A, i)
+        for target in (4096, 50000):
+            if plan_split(int(nprod[i]), len(lists), target) is not None:
+                assert split_row(lists, 2048, 512, target, exact=False) == nprod[i]
+
+
+def test_top_levels_cover_every_subtree():
+    for S in range(2, 70):
+        levels = top_levels(S, 3)
+        alive = set(range(S))
+        for lv in levels:
+            for x, y, root, lx, ly in lv:
+                assert x in alive
+                if y >= 0:
+                    assert y in alive and y > x
+                    alive.discard(y)
+        assert alive == {0}
+        assert levels[-1][0][2]  # the last level holds the root
