@@ -37,6 +37,21 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Loads and stores through pointers known to address global memory (device
+// buffers): pointers read from memory (a problem table) are otherwise
+// generic, and their flat accesses count against the LDS counter as well, so
+// that every LDS wait also waits for them.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p) {
+    using GP = const __attribute__((address_space(1))) T *;
+    return *(GP)p;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, T v) {
+    using GP = __attribute__((address_space(1))) T *;
+    *(GP)p = v;
+}
+
 template <typename Tv>
 __device__ __forceinline__ Tv wave_incl_scan(Tv x) {
     const int lane = lane_id();

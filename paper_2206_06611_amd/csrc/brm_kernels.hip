@@ -36,7 +36,7 @@ namespace brm {
 // ---------------------------------------------------------------------------
 template <typename I>
 __device__ __forceinline__ int64_t ld_rpt(const void *p, int64_t i) {
-    return (int64_t)(reinterpret_cast<const I *>(p)[i]);
+    return (int64_t)gload(reinterpret_cast<const I *>(p) + i);
 }
 
 __host__ __device__ __forceinline__ int ceil_log2(int64_t x) {
@@ -217,6 +217,47 @@ hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rp
 // ---------------------------------------------------------------------------
 constexpr int kAnalysisThreads = 256;
 
+// Per-row sums and maxima over one 64-entry window of a wavefront's chunk of
+// consecutive rows (whose entries are one contiguous range, row after row):
+// the window's lanes form segments that start at lane 0 and at every row
+// whose first entry lies in the window (flags in LDS, then a ballot); a
+// segmented inclusive scan leaves each lane its segment's sum and maximum so
+// far, and every row's lane adds the values of the lane that holds the row's
+// last entry in the window.  No atomics: rows of many entries in one window
+// (27 for a 27-point stencil) do not serialize on one LDS address.
+__device__ __forceinline__ void window_row_reduce(int64_t eb, bool in, int64_t a0, int64_t a1, int64_t n,
+                                                  int32_t *flag, int lane, int64_t &np_r, int &mx_r) {
+    flag[lane] = 0;
+    wave_sync();
+    if (in && a0 < a1 && a0 >= eb && a0 < eb + kWave) flag[a0 - eb] = 1;
+    wave_sync();
+    const uint64_t heads = wave_ballot(lane == 0 || flag[lane] != 0);
+    const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+    const int seg0 = 63 - __builtin_clzll(heads & upto);
+    int64_t sv = n;
+    int mv = (int)n;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t ys = __shfl_up(sv, d, kWave);
+        const int ym = __shfl_up(mv, d, kWave);
+        if (lane - d >= seg0) {
+            sv += ys;
+            mv = mv > ym ? mv : ym;
+        }
+    }
+    const int64_t lo = a0 > eb ? a0 : eb;
+    const int64_t hi = a1 < eb + kWave ? a1 : eb + kWave;
+    const bool mine = in && lo < hi;
+    const int src = mine ? (int)(hi - 1 - eb) : lane;
+    const int64_t gs = __shfl(sv, src, kWave);
+    const int gm = __shfl(mv, src, kWave);
+    if (mine) {
+        np_r += gs;
+        mx_r = mx_r > gm ? mx_r : gm;
+    }
+    wave_sync();  // the flags are cleared again by the next window
+}
+
 // first and last column of every row of B
 template <typename IB>
 __global__ __launch_bounds__(256) void k_row_ends(int64_t K, const IB *rpt, const int32_t *col, int2 *ends) {
@@ -249,8 +290,9 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
     __shared__ int64_t s_count[kNumClasses];
     __shared__ int64_t s_nprod;
     __shared__ int64_t s_start[kW][kWave + 1];  // entry offset of every row of the wave's chunk
-    __shared__ unsigned long long s_np[kW][kWave];
-    __shared__ int32_t s_mx[kW][kWave];  // longest list of every row
+    __shared__ unsigned long long s_np[FEAT ? kW : 1][kWave];
+    __shared__ int32_t s_mx[FEAT ? kW : 1][kWave];  // longest list of every row
+    __shared__ int32_t s_flag[kW][kWave];           // row heads of a window
     // features only: shortest list, lowest first column, highest last column
     __shared__ int32_t s_mn[FEAT ? kW : 1][kWave];
     __shared__ int32_t s_first[FEAT ? kW : 1][kWave];
@@ -279,9 +321,9 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             a0 = ld_rpt<IA>(a_rpt, i);
             a1 = ld_rpt<IA>(a_rpt, i + 1);
             s_start[w][lane] = a0;
-            s_np[w][lane] = 0ull;
-            s_mx[w][lane] = 0;
             if constexpr (FEAT) {
+                s_np[w][lane] = 0ull;
+                s_mx[w][lane] = 0;
                 s_mn[w][lane] = INT32_MAX;
                 s_first[w][lane] = INT32_MAX;
                 s_last[w][lane] = -1;
@@ -290,16 +332,20 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
         if (lane == nrows - 1) s_start[w][nrows] = a1;
         wave_sync();
         const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
-        for (int64_t e = e0 + lane; e < e1; e += kWave) {
-            const int32_t k = a_col[e];
-            const IB bs = reinterpret_cast<const IB *>(b_rpt)[k];
-            const int64_t n = (int64_t)reinterpret_cast<const IB *>(b_rpt)[k + 1] - (int64_t)bs;
-            ent_bs[e] = bs;
-            ent_len[e] = (int32_t)n;
-            const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
-            atomicAdd(&s_np[w][r], (unsigned long long)n);
-            atomicMax(&s_mx[w][r], (int32_t)n);
-            if constexpr (FEAT) {
+        int64_t np_r = 0;
+        int mx_r = 0;
+        if constexpr (FEAT) {
+            // the predictor's features need the shortest list and the column
+            // span as well: per-entry LDS atomics on the row's slots
+            for (int64_t e = e0 + lane; e < e1; e += kWave) {
+                const int32_t k = a_col[e];
+                const IB bs = reinterpret_cast<const IB *>(b_rpt)[k];
+                const int64_t n = (int64_t)reinterpret_cast<const IB *>(b_rpt)[k + 1] - (int64_t)bs;
+                ent_bs[e] = bs;
+                ent_len[e] = (int32_t)n;
+                const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
+                atomicAdd(&s_np[w][r], (unsigned long long)n);
+                atomicMax(&s_mx[w][r], (int32_t)n);
                 atomicMin(&s_mn[w][r], (int32_t)n);
                 if (n > 0) {
                     const int2 fl = reinterpret_cast<const int2 *>(rf.b_ends)[k];
@@ -307,11 +353,37 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
                     atomicMax(&s_last[w][r], fl.y);
                 }
             }
+            wave_sync();
+            if (in) {
+                np_r = (int64_t)s_np[w][lane];
+                mx_r = s_mx[w][lane];
+            }
+        } else {
+            // pipelined: the next window's columns are loaded while this
+            // window's B row pointers are gathered and reduced
+            const IB *brp = reinterpret_cast<const IB *>(b_rpt);
+            int32_t k_next = e0 + lane < e1 ? a_col[e0 + lane] : 0;
+            for (int64_t eb = e0; eb < e1; eb += kWave) {
+                const int64_t e = eb + lane;
+                const bool valid = e < e1;
+                const int32_t k = k_next;
+                IB bs = 0, be = 0;
+                if (valid) {
+                    bs = brp[k];
+                    be = brp[k + 1];
+                }
+                if (e + kWave < e1) k_next = a_col[e + kWave];
+                const int64_t n = valid ? (int64_t)be - (int64_t)bs : 0;
+                if (valid) {
+                    ent_bs[e] = bs;
+                    ent_len[e] = (int32_t)n;
+                }
+                window_row_reduce(eb, in, a0, a1, n, s_flag[w], lane, np_r, mx_r);
+            }
         }
-        wave_sync();
         if (in) {
-            const int64_t np = (int64_t)s_np[w][lane];
-            const int mx = s_mx[w][lane];
+            const int64_t np = np_r;
+            const int mx = mx_r;
             // the row kernels count a row's products in int32: a longer row
             // goes to no kernel and fails the call
             const bool too_long = np > (int64_t)INT32_MAX;
@@ -598,7 +670,7 @@ __device__ __forceinline__ int sym_hash_row(SymLds<T, TS> &s, int tid, int64_t r
     const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
     int added = 0;
     for_each_product<T, IB>(s.st, tid, a0, L, lists,
-                            [&](int64_t, int64_t q, int) { added += hash_insert<TS>(s.tab, b_col[q]); });
+                            [&](int64_t, int64_t q, int) { added += hash_insert<TS>(s.tab, gload(b_col + (q))); });
     const int total = Team<T>::sum(added, s.red, tid);
     Team<T>::sync();
     return total;
@@ -677,7 +749,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
                         col[u] = -1;
                         if (q < tot) {
                             const int t = upper_bound(st.off, nl, q) - 1;
-                            col[u] = b_col[st.bs[t] + (q - st.off[t])];
+                            col[u] = gload(b_col + (st.bs[t] + (q - st.off[t])));
                         }
                     }
 #pragma unroll
@@ -760,7 +832,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_sym_group(int cls, const void *a_r
             for (int q = tid; q < tot; q += T) {
                 const int t = upper_bound(s.off, nl, q) - 1;
                 const int jj = s.lseg[t];
-                if (hash_insert<TS>(s.tab[jj], b_col[s.bs[t] + (q - s.off[t])])) atomicAdd(&s.cnt[jj], 1);
+                if (hash_insert<TS>(s.tab[jj], gload(b_col + (s.bs[t] + (q - s.off[t]))))) atomicAdd(&s.cnt[jj], 1);
             }
             Team<T>::sync();
         }
@@ -1005,18 +1077,18 @@ __device__ __forceinline__ void copy_row(int lane, int64_t row, int64_t id, cons
                                          const int32_t *b_col, const double *b_val, const int64_t *c_rpt,
                                          int32_t *c_col, double *c_val, Ctl *ctl, const NumOut &no) {
     const int64_t p = ld_rpt<IA>(a_rpt, row);
-    const double a = a_val[p];
+    const double a = gload(a_val + (p));
     int64_t bs;
     int ln;
     lists.get(p, bs, ln);
     const int64_t n = ln;
-    const int64_t cs = c_rpt[row];
-    const int64_t cap = c_rpt[row + 1] - cs;
+    const int64_t cs = gload(c_rpt + (row));
+    const int64_t cap = gload(c_rpt + (row + 1)) - cs;
     if (lane == 0) finish_row(no, ctl, id, n, cap, false);
     const int64_t m = n < cap ? n : cap;
     for (int64_t j = lane; j < m; j += kWave) {
-        c_col[cs + j] = b_col[bs + j];
-        c_val[cs + j] = a * b_val[bs + j];
+        gstore(c_col + (cs + j), gload(b_col + (bs + j)));
+        gstore(c_val + (cs + j), a * gload(b_val + (bs + j)));
     }
 }
 
@@ -1163,7 +1235,7 @@ __device__ __forceinline__ void brmerge_segs_lds(NumLds<T, CAP, G> &s, int tid, 
         if (gl < LT) {
             const int j = upper_bound(s.fl, n, gl) - 1;
             const int64_t p = s.seg[j].a0 + (gl - s.fl[j]);
-            av = a_val[p];
+            av = gload(a_val + (p));
             lists.get(p, bs, ln);
         }
         int tot;
@@ -1194,8 +1266,8 @@ __device__ __forceinline__ void brmerge_segs_lds(NumLds<T, CAP, G> &s, int tid, 
             sg[e] = upper_bound(s.fl, n, gl) - 1;
             const int64_t bs = ((int64_t)s.len[gl] << 32) | (int64_t)(uint32_t)s.col[1][gl];
             const int64_t q = bs + (p - s.off[gl]);
-            s.col[0][p] = b_col[q];
-            s.val[0][p] = s.val[1][gl] * b_val[q];
+            s.col[0][p] = gload(b_col + (q));
+            s.val[0][p] = s.val[1][gl] * gload(b_val + (q));
         }
     }
     Team<T>::sync();
@@ -1300,8 +1372,8 @@ __device__ __forceinline__ void brmerge_segs_lds(NumLds<T, CAP, G> &s, int tid, 
             const int f = s.fl[j];
             const int o = p - s.off[f];
             if (o < s.len[f] && (int64_t)o < s.seg[j].out_cap) {
-                s.seg[j].out_col[o] = s.col[cur][p];
-                s.seg[j].out_val[o] = s.val[cur][p];
+                gstore(s.seg[j].out_col + (o), s.col[cur][p]);
+                gstore(s.seg[j].out_val + (o), s.val[cur][p]);
             }
         }
     }
@@ -1330,7 +1402,7 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP, G> &s, int tid, 
         int64_t bs = 0;
         double av = 0.0;
         if (l < L) {
-            av = a_val[a0 + l];
+            av = gload(a_val + (a0 + l));
             lists.get(a0 + l, bs, ln);
         }
         int tot;
@@ -1359,8 +1431,8 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP, G> &s, int tid, 
             leaf[e] = lf;
             const int64_t bs = ((int64_t)s.len[lf] << 32) | (int64_t)(uint32_t)s.col[1][lf];
             const int64_t q = bs + (p - s.off[lf]);
-            s.col[0][p] = b_col[q];
-            s.val[0][p] = s.val[1][lf] * b_val[q];
+            s.col[0][p] = gload(b_col + (q));
+            s.val[0][p] = s.val[1][lf] * gload(b_val + (q));
         }
     }
     Team<T>::sync();
@@ -1512,8 +1584,8 @@ __device__ __forceinline__ int brmerge_range_lds(NumLds<T, CAP, G> &s, int tid, 
     const int rl = s.len[0];
     const int m = (int64_t)rl < out_cap ? rl : (int)out_cap;
     for (int p = tid; p < m; p += T) {
-        out_col[p] = s.col[cur][p];
-        out_val[p] = s.val[cur][p];
+        gstore(out_col + (p), s.col[cur][p]);
+        gstore(out_val + (p), s.val[cur][p]);
     }
     Team<T>::sync();
     return rl;
@@ -1528,8 +1600,8 @@ __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int6
                                                 double *c_val, Ctl *ctl, const NumOut &no) {
     const int64_t a0 = ld_rpt<IA>(a_rpt, row);
     const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
-    const int64_t cs = c_rpt[row];
-    const int64_t cap = c_rpt[row + 1] - cs;
+    const int64_t cs = gload(c_rpt + (row));
+    const int64_t cap = gload(c_rpt + (row + 1)) - cs;
     const int rl = brmerge_range_lds<T, CAP, 1, IB>(s, tid, a0, L, lists, a_val, b_col, b_val,
                                                  c_col + cs, c_val + cs, cap);
     // Algorithm 1's final store went straight to C's row (truncated to the slot)
@@ -1811,8 +1883,8 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             m_sw = row_class[m_row] >> kClassBits;
             m_T = 1 << (m_sw + ceil_log2(m_L > 0 ? m_L : 1));
             if constexpr (VALUES) {
-                m_cs = crpt[r];
-                m_cap = (int)(crpt[r + 1] - m_cs);  // a row's size fits 31 bits
+                m_cs = gload(crpt + r);
+                m_cap = (int)(gload(crpt + r + 1) - m_cs);  // a row's size fits 31 bits
             }
         }
         // When every row of the chunk fits 32 lanes, rows 2i and 2i+1 share
@@ -1985,8 +2057,8 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                         cv = reinterpret_cast<double *>(sel64(m_cval, a, b));
                     }
                     if (live && pos < cap) {
-                        cc[cs + pos] = (int32_t)(k >> kKeyLaneBits);
-                        cv[cs + pos] = v;
+                        gstore(cc + cs + pos, (int32_t)(k >> kKeyLaneBits));
+                        gstore(cv + cs + pos, v);
                     }
                     if constexpr (P) {
                         done(a, __popcll(lm & 0xffffffffull));
@@ -2231,8 +2303,8 @@ __device__ __forceinline__ int mw_row(int lane, int sw, IB bs, int ln, double av
         c[e] = kEmptyCol;
         bv[e] = 0.0;
         if (o0 + e < lln) {
-            c[e] = b_col[lbs + o0 + e];
-            if constexpr (VALUES) bv[e] = b_val[lbs + o0 + e];
+            c[e] = gload(b_col + lbs + o0 + e);
+            if constexpr (VALUES) bv[e] = gload(b_val + lbs + o0 + e);
         }
     }
 #pragma unroll
@@ -2259,8 +2331,8 @@ __device__ __forceinline__ int mw_row(int lane, int sw, IB bs, int ln, double av
         for (int e = 0; e < NR; ++e) {
             if ((k[e] & kMwDrop) == 0) {
                 if (pos < cap) {
-                    out_col[pos] = (int32_t)(k[e] >> kMwShift);
-                    out_val[pos] = vals[k[e] & kMwSlotMask];
+                    gstore(out_col + pos, (int32_t)(k[e] >> kMwShift));
+                    gstore(out_val + pos, vals[k[e] & kMwSlotMask]);
                 }
                 ++pos;
             }
@@ -2321,8 +2393,8 @@ __device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<
             m_L = (int)(ld_rpt<IA>(rpt, r + 1) - m_a0);
             m_sw = row_class[m_row] >> kClassBits;
             if constexpr (VALUES) {
-                m_cs = crpt[r];
-                m_cap = (int)(crpt[r + 1] - m_cs);  // a row's size fits 31 bits
+                m_cs = gload(crpt + r);
+                m_cap = (int)(gload(crpt + r + 1) - m_cs);  // a row's size fits 31 bits
             }
         }
         for (int j = 0; j < n; ++j) {
@@ -2350,7 +2422,7 @@ __device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<
             if (lane < L) {
                 bs = ent_bs[e0 + lane];
                 ln = ent_len[e0 + lane];
-                if constexpr (VALUES) av = av_p[a0 + lane];
+                if constexpr (VALUES) av = gload(av_p + a0 + lane);
             }
             int64_t cs = 0;
             int cap = 0;
@@ -2478,13 +2550,13 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_group(int cls, const void *a_r
         if (tid < n) {
             const int64_t row = class_rows[start + base + tid];
             const int64_t a0 = ld_rpt<IA>(a_rpt, row);
-            const int64_t cs = c_rpt[row];
+            const int64_t cs = gload(c_rpt + (row));
             s.row[tid] = row;
             s.seg[tid].a0 = a0;
             s.seg[tid].L = (int32_t)(ld_rpt<IA>(a_rpt, row + 1) - a0);
             s.seg[tid].out_col = c_col + cs;
             s.seg[tid].out_val = c_val + cs;
-            s.seg[tid].out_cap = c_rpt[row + 1] - cs;
+            s.seg[tid].out_cap = gload(c_rpt + (row + 1)) - cs;
         }
         Team<T>::sync();
         brmerge_segs_lds<T, CAP, G, IB>(s, tid, n, lists, a_val, b_col, b_val);
@@ -2528,8 +2600,8 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_hash(int cls, const void *a_rp
         const int64_t row = class_rows[start + idx];
         const int64_t a0 = ld_rpt<IA>(a_rpt, row);
         const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
-        const int64_t cs = c_rpt[row];
-        const int cap = (int)(c_rpt[row + 1] - cs);
+        const int64_t cs = gload(c_rpt + (row));
+        const int cap = (int)(gload(c_rpt + (row + 1)) - cs);
         if (2 * (int64_t)cap > TS) {  // row pointers that are not the symbolic pass's
             if (tid == 0)
                 atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
@@ -2566,8 +2638,8 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_hash(int cls, const void *a_rp
             int ln;
             lists.get(a0 + t, bs, ln);
             const int64_t q = bs + (p - s.off[t]);
-            const int32_t c = b_col[q];
-            const double v = a_val[a0 + t] * b_val[q];  // one rounded product
+            const int32_t c = gload(b_col + (q));
+            const double v = gload(a_val + (a0 + t)) * gload(b_val + (q));  // one rounded product
             uint32_t h = ((uint32_t)c * 2654435761u) >> (32 - lg);
             int probes = 0;
             for (;;) {
@@ -2616,8 +2688,8 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_hash(int cls, const void *a_rp
             int r = 0;
             for (int j = 0; j < n; ++j) r += s.key[j] < c;
             if (r < cap) {
-                c_col[cs + r] = c;
-                c_val[cs + r] = s.val[i];
+                gstore(c_col + (cs + r), c);
+                gstore(c_val + (cs + r), s.val[i]);
             }
         }
         if (tid == 0 && n != cap)
@@ -2818,12 +2890,12 @@ __device__ int64_t merge_hbm(MergeLds<T> &m, HeavyState<T> &st, int tid, const i
         for (int e = 0; e < kWinPer; ++e) {
             const int i = tid + e * T;
             if (i < wx) {
-                pxc[e] = Xc[xs + i];
-                pxv[e] = Xv[xs + i];
+                pxc[e] = gload(Xc + xs + i);
+                pxv[e] = gload(Xv + xs + i);
             }
             if (i < wy) {
-                pyc[e] = Yc[ys + i];
-                pyv[e] = Yv[ys + i];
+                pyc[e] = gload(Yc + ys + i);
+                pyv[e] = gload(Yv + ys + i);
             }
         }
     };
@@ -2963,8 +3035,8 @@ __device__ int64_t merge_hbm(MergeLds<T> &m, HeavyState<T> &st, int tid, const i
         for (int j = 0; j < kMergeSteps; ++j) {
             if (hd[j]) {
                 if (o < zcap) {
-                    Zc[o] = c[j];
-                    Zv[o] = v[j];
+                    gstore(Zc + o, c[j]);
+                    gstore(Zv + o, v[j]);
                 }
                 ++o;
             }
@@ -3132,8 +3204,8 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
                     int nb;
                     lists.get(a0 + l0, bs, nb);
                     for (int64_t j = tid; j < np && j < cap; j += T) {
-                        oc[j] = b_col[bs + j];
-                        ov[j] = a * b_val[bs + j];
+                        gstore(oc + j, gload(b_col + bs + j));
+                        gstore(ov + j, a * gload(b_val + bs + j));
                     }
                     len = np;
                 }
@@ -3187,8 +3259,8 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
                 const HeavyNode x = st.stack[0];
                 const int64_t n = x.len < ccap ? x.len : ccap;
                 for (int64_t j = tid; j < n; j += T) {
-                    c_col[cs + j] = bcol[x.buf][j];
-                    c_val[cs + j] = bval[x.buf][j];
+                    gstore(c_col + cs + j, gload(bcol[x.buf] + j));
+                    gstore(c_val + cs + j, gload(bval[x.buf] + j));
                 }
                 if (tid == 0) st.stack[0].buf = 2;
             }
@@ -3263,8 +3335,8 @@ __global__ __launch_bounds__(T) void k_heavy_top(HeavyBatch hb, const HeavyTop *
             // the root is the left node alone
             const int64_t n = xl < ccap ? xl : ccap;
             for (int64_t j = tid; j < n; j += T) {
-                c_col[cs + j] = bcol[xb][rx + j];
-                c_val[cs + j] = bval[xb][rx + j];
+                gstore(c_col + cs + j, gload(bcol[xb] + rx + j));
+                gstore(c_val + cs + j, gload(bval[xb] + rx + j));
             }
             if (tid == 0) finish_row(no, ctl, row, xl, ccap, true);
         } else {
@@ -3401,8 +3473,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
     __shared__ int64_t s_count[kNumClasses];
     __shared__ int64_t s_nprod;
     __shared__ int64_t s_start[kW][kWave + 1];
-    __shared__ unsigned long long s_np[kW][kWave];
-    __shared__ int32_t s_mx[kW][kWave];
+    __shared__ int32_t s_flag[kW][kWave];  // row heads of a window
     load_lookup(lk, chunk_off, np);
     if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nprod = 0;
@@ -3413,13 +3484,20 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
     int64_t my_nprod = 0;
     const int lane = lane_id();
     const int w = threadIdx.x / kWave;
-    const int64_t *coff = np < kMaxLdsProbs ? lk.off : chunk_off;
     const bool skip = st->skip != 0;  // one value for the whole stage (set before this launch)
     for (int64_t c = (int64_t)blockIdx.x * kW + w; c < nchunks; c += (int64_t)gridDim.x * kW) {
         const int p = find_prob(lk, chunk_off, np, c);
-        const BatchProb &pr = tab[p];
+        // the problem's fields in registers once per chunk: the descriptor
+        // stores below could otherwise alias the table and force reloads
+        const BatchProb &tp = tab[p];
+        struct {
+            int64_t rows, row_off, ent_off;
+            const void *a_rpt, *b_rpt;
+            const int32_t *a_col;
+        } pr = {wave_uniform(tp.rows), wave_uniform(tp.row_off), wave_uniform(tp.ent_off), tp.a_rpt, tp.b_rpt,
+                tp.a_col};
         static_assert(kBatchChunkRows == kWave, "a chunk is one wavefront's rows");
-        const int64_t r0 = (c - coff[p]) * kWave;
+        const int64_t r0 = (c - (np < kMaxLdsProbs ? lk.off[p] : gload(chunk_off + p))) * kWave;
         const int nrows = pr.rows - r0 < kWave ? (int)(pr.rows - r0) : kWave;
         const int64_t i = r0 + lane;
         const bool in = lane < nrows;
@@ -3440,28 +3518,37 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
             a0 = ld_rpt<IA>(pr.a_rpt, i);
             a1 = ld_rpt<IA>(pr.a_rpt, i + 1);
             s_start[w][lane] = a0;
-            s_np[w][lane] = 0ull;
-            s_mx[w][lane] = 0;
         }
         if (lane == nrows - 1) s_start[w][nrows] = a1;
         wave_sync();
         const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
         const IB *b_rpt = reinterpret_cast<const IB *>(pr.b_rpt);
-        for (int64_t e = e0 + lane; e < e1; e += kWave) {
-            const int32_t k = pr.a_col[e];
-            const IB bs = b_rpt[k];
-            const int64_t n = (int64_t)b_rpt[k + 1] - (int64_t)bs;
-            ent_bs[pr.ent_off + e] = bs;
-            ent_len[pr.ent_off + e] = (int32_t)n;
-            const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
-            atomicAdd(&s_np[w][r], (unsigned long long)n);
-            atomicMax(&s_mx[w][r], (int32_t)n);
+        int64_t np_r = 0;
+        int mx_r = 0;
+        // pipelined: the next window's columns are loaded while this
+        // window's B row pointers are gathered and reduced
+        int32_t k_next = e0 + lane < e1 ? gload(pr.a_col + e0 + lane) : 0;
+        for (int64_t eb = e0; eb < e1; eb += kWave) {
+            const int64_t e = eb + lane;
+            const bool valid = e < e1;
+            const int32_t k = k_next;
+            IB bs = 0, be = 0;
+            if (valid) {
+                bs = gload(b_rpt + k);
+                be = gload(b_rpt + k + 1);
+            }
+            if (e + kWave < e1) k_next = gload(pr.a_col + e + kWave);
+            const int64_t n = valid ? (int64_t)be - (int64_t)bs : 0;
+            if (valid) {
+                ent_bs[pr.ent_off + e] = bs;
+                ent_len[pr.ent_off + e] = (int32_t)n;
+            }
+            window_row_reduce(eb, in, a0, a1, n, s_flag[w], lane, np_r, mx_r);
         }
-        wave_sync();
         if (in) {
             const int64_t g = pr.row_off + i;
-            const int64_t nprod = (int64_t)s_np[w][lane];
-            const int mx = s_mx[w][lane];
+            const int64_t nprod = np_r;
+            const int mx = mx_r;
             const int cls = classify(a1 - a0, nprod, mx, th);
             const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx)
                            : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, nprod)
@@ -3501,6 +3588,7 @@ template <int T, int TEAMS, int TS, typename IA, typename IB>
 __global__ __launch_bounds__(T *TEAMS) void k_b_sym_hash(int cls, const BatchProb *tab, const int64_t *row_off,
                                                          int np, const int32_t *class_rows, int32_t *row_size,
                                                          const Ctl *ctl) {
+    if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ ProbLookup lk;
     __shared__ SymLds<T, TS> lds[TEAMS];
     load_lookup(lk, row_off, np);
@@ -3561,11 +3649,11 @@ __global__ __launch_bounds__(256) void k_b_rpt(BatchProb *tab, const int64_t *ro
         const int p = find_prob(lk, row_off, np, g);
         const BatchProb &pr = tab[p];
         const int64_t r = g - pr.row_off;
-        pr.c_rpt[r] = S[g] - S[pr.row_off];
-        if (r == pr.rows - 1) pr.c_rpt[pr.rows] = S[g + 1] - S[pr.row_off];
+        gstore(pr.c_rpt + (r), S[g] - S[pr.row_off]);
+        if (r == pr.rows - 1) gstore(pr.c_rpt + (pr.rows), S[g + 1] - S[pr.row_off]);
     }
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x)
-        if (tab[p].rows == 0) tab[p].c_rpt[0] = 0;
+        if (tab[p].rows == 0) gstore(tab[p].c_rpt + (0), (int64_t)0);
 }
 
 // the B operand of a chained problem is the C of an earlier one
@@ -3584,6 +3672,7 @@ __global__ void k_b_link(BatchProb *all, int first, int np) {
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *tab, const int64_t *row_off, int np,
                                                     const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+    if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ ProbLookup lk;
     load_lookup(lk, row_off, np);
     if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
@@ -3606,6 +3695,7 @@ template <int T, int TEAMS, int CAP, typename IA, typename IB>
 __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb *tab, const int64_t *row_off,
                                                         int np, const int32_t *class_rows, Ctl *ctl,
                                                         const BatchStatus *st) {
+    if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ ProbLookup lk;
     __shared__ NumLds<T, CAP> lds[TEAMS];
     load_lookup(lk, row_off, np);
@@ -3630,6 +3720,7 @@ template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_num_win(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                    const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
                                                    const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+    if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ uint32_t xk[4][kWave];
     __shared__ double xv[4][kWave];
     if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
@@ -3651,6 +3742,7 @@ template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_sym_win(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                    const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
                                                    const int32_t *class_rows, int32_t *row_size, Ctl *ctl) {
+    if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
     lists.ent_bs = ent_bs;
@@ -3669,6 +3761,7 @@ template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_num_mw(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                   const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
                                                   const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+    if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ double vals[4][kMwSlots];
     if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
     const int team = wave_uniform((int)(threadIdx.x / kWave));
@@ -3689,6 +3782,7 @@ template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_sym_mw(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                   const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
                                                   const int32_t *class_rows, int32_t *row_size, Ctl *ctl) {
+    if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
     lists.ent_bs = ent_bs;
