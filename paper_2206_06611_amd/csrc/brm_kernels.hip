@@ -225,37 +225,65 @@ constexpr int kAnalysisThreads = 256;
 // far, and every row's lane adds the values of the lane that holds the row's
 // last entry in the window.  No atomics: rows of many entries in one window
 // (27 for a 27-point stencil) do not serialize on one LDS address.
-__device__ __forceinline__ void window_row_reduce(int64_t eb, bool in, int64_t a0, int64_t a1, int64_t n,
-                                                  int32_t *flag, int lane, int64_t &np_r, int &mx_r) {
+// The segment structure of one window: lane `seg0` is the first lane of the
+// calling lane's segment; `src` is the lane holding the calling row's last
+// entry in the window (or the calling lane), `mine` whether the row has
+// entries in it.
+struct WindowSegs {
+    int seg0, src;
+    bool mine;
+};
+__device__ __forceinline__ WindowSegs window_segs(int64_t eb, bool in, int64_t a0, int64_t a1, int32_t *flag,
+                                                  int lane) {
     flag[lane] = 0;
     wave_sync();
     if (in && a0 < a1 && a0 >= eb && a0 < eb + kWave) flag[a0 - eb] = 1;
     wave_sync();
     const uint64_t heads = wave_ballot(lane == 0 || flag[lane] != 0);
     const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
-    const int seg0 = 63 - __builtin_clzll(heads & upto);
-    int64_t sv = n;
-    int mv = (int)n;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int64_t ys = __shfl_up(sv, d, kWave);
-        const int ym = __shfl_up(mv, d, kWave);
-        if (lane - d >= seg0) {
-            sv += ys;
-            mv = mv > ym ? mv : ym;
-        }
-    }
+    WindowSegs w;
+    w.seg0 = 63 - __builtin_clzll(heads & upto);
     const int64_t lo = a0 > eb ? a0 : eb;
     const int64_t hi = a1 < eb + kWave ? a1 : eb + kWave;
-    const bool mine = in && lo < hi;
-    const int src = mine ? (int)(hi - 1 - eb) : lane;
-    const int64_t gs = __shfl(sv, src, kWave);
-    const int gm = __shfl(mv, src, kWave);
-    if (mine) {
+    w.mine = in && lo < hi;
+    w.src = w.mine ? (int)(hi - 1 - eb) : lane;
+    wave_sync();  // the flags are cleared again by the next window
+    return w;
+}
+
+// Segmented inclusive scan of one quantity over the window (op: 0 sum, 1
+// max, 2 min), then the value at the row's last entry.
+template <int OP, typename V>
+__device__ __forceinline__ V segmented_at_row_end(V v, const WindowSegs &w, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const V y = __shfl_up(v, d, kWave);
+        if (lane - d >= w.seg0) {
+            if constexpr (OP == 0) v += y;
+            else if constexpr (OP == 1) v = v > y ? v : y;
+            else v = v < y ? v : y;
+        }
+    }
+    return __shfl(v, w.src, kWave);
+}
+
+// Per-row sums and maxima over one 64-entry window of a wavefront's chunk of
+// consecutive rows (whose entries are one contiguous range, row after row):
+// the window's lanes form segments that start at lane 0 and at every row
+// whose first entry lies in the window (flags in LDS, then a ballot); a
+// segmented inclusive scan leaves each lane its segment's sum and maximum so
+// far, and every row's lane adds the values of the lane that holds the row's
+// last entry in the window.  No atomics: rows of many entries in one window
+// (27 for a 27-point stencil) do not serialize on one LDS address.
+__device__ __forceinline__ void window_row_reduce(int64_t eb, bool in, int64_t a0, int64_t a1, int64_t n,
+                                                  int32_t *flag, int lane, int64_t &np_r, int &mx_r) {
+    const WindowSegs w = window_segs(eb, in, a0, a1, flag, lane);
+    const int64_t gs = segmented_at_row_end<0>(n, w, lane);
+    const int gm = segmented_at_row_end<1>((int)n, w, lane);
+    if (w.mine) {
         np_r += gs;
         mx_r = mx_r > gm ? mx_r : gm;
     }
-    wave_sync();  // the flags are cleared again by the next window
 }
 
 // first and last column of every row of B
@@ -290,13 +318,7 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
     __shared__ int64_t s_count[kNumClasses];
     __shared__ int64_t s_nprod;
     __shared__ int64_t s_start[kW][kWave + 1];  // entry offset of every row of the wave's chunk
-    __shared__ unsigned long long s_np[FEAT ? kW : 1][kWave];
-    __shared__ int32_t s_mx[FEAT ? kW : 1][kWave];  // longest list of every row
-    __shared__ int32_t s_flag[kW][kWave];           // row heads of a window
-    // features only: shortest list, lowest first column, highest last column
-    __shared__ int32_t s_mn[FEAT ? kW : 1][kWave];
-    __shared__ int32_t s_first[FEAT ? kW : 1][kWave];
-    __shared__ int32_t s_last[FEAT ? kW : 1][kWave];
+    __shared__ int32_t s_flag[kW][kWave];  // row heads of a window
     if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nprod = 0;
     __syncthreads();
@@ -321,42 +343,48 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             a0 = ld_rpt<IA>(a_rpt, i);
             a1 = ld_rpt<IA>(a_rpt, i + 1);
             s_start[w][lane] = a0;
-            if constexpr (FEAT) {
-                s_np[w][lane] = 0ull;
-                s_mx[w][lane] = 0;
-                s_mn[w][lane] = INT32_MAX;
-                s_first[w][lane] = INT32_MAX;
-                s_last[w][lane] = -1;
-            }
         }
         if (lane == nrows - 1) s_start[w][nrows] = a1;
         wave_sync();
         const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
         int64_t np_r = 0;
         int mx_r = 0;
+        int mn_r = INT32_MAX, first_r = INT32_MAX, last_r = -1;
         if constexpr (FEAT) {
             // the predictor's features need the shortest list and the column
-            // span as well: per-entry LDS atomics on the row's slots
-            for (int64_t e = e0 + lane; e < e1; e += kWave) {
-                const int32_t k = a_col[e];
-                const IB bs = reinterpret_cast<const IB *>(b_rpt)[k];
-                const int64_t n = (int64_t)reinterpret_cast<const IB *>(b_rpt)[k + 1] - (int64_t)bs;
-                ent_bs[e] = bs;
-                ent_len[e] = (int32_t)n;
-                const int r = (int)(upper_bound64(s_start[w], (int64_t)nrows, e) - 1);
-                atomicAdd(&s_np[w][r], (unsigned long long)n);
-                atomicMax(&s_mx[w][r], (int32_t)n);
-                atomicMin(&s_mn[w][r], (int32_t)n);
-                if (n > 0) {
-                    const int2 fl = reinterpret_cast<const int2 *>(rf.b_ends)[k];
-                    atomicMin(&s_first[w][r], fl.x);
-                    atomicMax(&s_last[w][r], fl.y);
+            // span as well: three more segmented reductions per window
+            const IB *brp = reinterpret_cast<const IB *>(b_rpt);
+            for (int64_t eb = e0; eb < e1; eb += kWave) {
+                const int64_t e = eb + lane;
+                int64_t n = 0;
+                int f = INT32_MAX, l = -1;
+                int mnv = INT32_MAX;
+                if (e < e1) {
+                    const int32_t k = a_col[e];
+                    const IB bs = brp[k];
+                    n = (int64_t)brp[k + 1] - (int64_t)bs;
+                    ent_bs[e] = bs;
+                    ent_len[e] = (int32_t)n;
+                    mnv = (int)n;
+                    if (n > 0) {
+                        const int2 fl = reinterpret_cast<const int2 *>(rf.b_ends)[k];
+                        f = fl.x;
+                        l = fl.y;
+                    }
                 }
-            }
-            wave_sync();
-            if (in) {
-                np_r = (int64_t)s_np[w][lane];
-                mx_r = s_mx[w][lane];
+                const WindowSegs ws = window_segs(eb, in, a0, a1, s_flag[w], lane);
+                const int64_t gs = segmented_at_row_end<0>(n, ws, lane);
+                const int gm = segmented_at_row_end<1>((int)n, ws, lane);
+                const int gn = segmented_at_row_end<2>(mnv, ws, lane);
+                const int gf = segmented_at_row_end<2>(f, ws, lane);
+                const int gl = segmented_at_row_end<1>(l, ws, lane);
+                if (ws.mine) {
+                    np_r += gs;
+                    mx_r = mx_r > gm ? mx_r : gm;
+                    mn_r = mn_r < gn ? mn_r : gn;
+                    first_r = first_r < gf ? first_r : gf;
+                    last_r = last_r > gl ? last_r : gl;
+                }
             }
         } else {
             // pipelined: the next window's columns are loaded while this
@@ -401,8 +429,8 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
                 // shortest list, products per spanned column); bounds of
                 // the row size
                 const int64_t L = a1 - a0;
-                const int64_t mn = L == 0 ? 0 : s_mn[w][lane];
-                const int64_t first = s_first[w][lane], last = s_last[w][lane];
+                const int64_t mn = L == 0 ? 0 : mn_r;
+                const int64_t first = first_r, last = last_r;
                 const int64_t span = last >= first ? last - first + 1 : 0;
                 row_features6(rf.feats + 6 * i, L, np, mx, mn, span, rf.ncols);
                 rf.predicted[i] = (np > 0 && L >= 2) ? 1 : 0;
