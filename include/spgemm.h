@@ -115,6 +115,11 @@ typedef enum {
                                     The handle keeps its pool (grow-only) until spg_destroy */
     SPG_OPT_GRID_WAVES = 9,      /* waves per launch of the persistent row kernels (0 = auto) */
     SPG_OPT_ALLOC = 10,          /* SPG_ALLOC_PRECISE (default), SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER */
+    SPG_OPT_LEARNED_HEAVY_MARGIN = 16, /* learned allocation: extra margin, in thousandths, added to
+                                    delta for rows of more than SPG_OPT_BLOCK_MAX products (merged
+                                    through spill buffers, where an overflowing row is merged
+                                    twice): slot = clamp(ceil(nprod e^(y + delta + this)), ...).
+                                    Default 200 */
     SPG_OPT_LEARNED_FORCE = 11,  /* testing only: 1 sizes every predicted row at its lower bound
                                     (the longest list), so that most rows take the fallback */
     SPG_OPT_ACCUMULATOR = 13,    /* SPG_ACC_BRMERGE (default) or SPG_ACC_HASH: see below */
@@ -190,6 +195,8 @@ typedef enum {
     SPG_STAT_PRED_TOTAL = 21,    /* learned / upper-bound allocation: sum of the slot sizes (entries) */
     SPG_STAT_OVERFLOW_ROWS = 22, /* learned allocation: rows longer than their predicted slot */
     SPG_STAT_PREDICTED_ROWS = 23,/* rows whose size is predicted (two or more lists, a product) */
+    SPG_STAT_OVERFLOW_HEAVY_ROWS = 31,/* learned allocation: overflowing rows of more than
+                                    SPG_OPT_BLOCK_MAX products (part of SPG_STAT_OVERFLOW_ROWS) */
     SPG_STAT_GRAPH_CAPTURES = 24,/* batched calls that (re)captured their HIP graph */
     SPG_STAT_GRAPH_LAUNCHES = 25,/* batched calls that replayed a captured graph */
     SPG_STAT_SPILL_POOL_BYTES = 26,/* device bytes of the handle's heavy-row spill pool (kept
@@ -331,7 +338,9 @@ int spgemm_batched_noalloc(spg_handle h, int count, const spg_problem *problems,
  * so that a predictor trained on one matrix size carries over to others),
  * each normalised as (x - mean) / std.  The row's
  * slot holds clamp(ceil(nprod_i exp(y_i + delta)), longest list, min(nprod_i,
- * span_i)) entries; rows with no product or one list get their exact size.
+ * span_i)) entries; rows with no product or one list get their exact size,
+ * and rows with fewer than one expected repeat among their products
+ * (products^2 / span < 1) get min(nprod_i, span_i) without the network.
  * With SPG_OPT_ALLOC = SPG_ALLOC_LEARNED, spgemm_symbolic runs the numeric
  * kernels into the slots (no symbolic pass), records every row's exact length
  * and the rows that overflowed, and returns C's exact row pointers and nnz

@@ -46,6 +46,7 @@ OPT_GROUP_ROWS = 12
 OPT_ACCUMULATOR = 13
 OPT_HEAVY_THREADS = 14
 OPT_HEAVY_SPLIT = 15
+OPT_LEARNED_HEAVY_MARGIN = 16
 ACC_BRMERGE = 0
 ACC_HASH = 1
 ALLOC_PRECISE = 0
@@ -68,6 +69,7 @@ STAT_SPILL_ALLOCS = 27
 STAT_HEAVY_WIDE = 28
 STAT_HEAVY_SPLIT_ROWS = 29
 STAT_DEVICE_ERR = 30
+STAT_OVERFLOW_HEAVY_ROWS = 31
 
 CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy", "multi"]
 

@@ -95,6 +95,7 @@ struct spg_handle_s {
     int64_t alloc = 0;          // 0 precise, 1 learned, 2 upper bound
     int64_t accumulator = 0;    // 0 BRMerge, 1 hash table (comparator)
     int64_t learned_force = 0;  // testing: 1 = every predicted row at its lower bound
+    int64_t heavy_margin_milli = 200;  // extra margin (thousandths) of rows beyond one workgroup's LDS
     bool plan_learned = false;
     void *lw_mem = nullptr;     // per-row learned workspace
     size_t lw_bytes = 0;
@@ -134,7 +135,7 @@ struct LearnedWs {
     int32_t *pred_size; // [M]
     int64_t *slot_off;  // [M + 1]
     int32_t *ovf_rows;  // [2 M]
-    int32_t *b_ends;    // [2 K] first and last column of every row of B (-1 / -1 when empty)
+    int32_t *b_ends;    // [4 K] per row of B: first and last column (-1 / -1 when empty), length, start
 };
 
 namespace {
@@ -503,7 +504,7 @@ int ensure_learned_ws(spg_handle h, int64_t M, LearnedWs *lw, int64_t K = 0) {
     size_t o_so = align_up(o_ps + 4 * (size_t)M, a);
     size_t o_ov = align_up(o_so + 8 * (size_t)(M + 1), a);
     size_t o_be = align_up(o_ov + 8 * (size_t)M + 8, a);
-    size_t total = align_up(o_be + 8 * (size_t)K + 8, a);
+    size_t total = align_up(o_be + 16 * (size_t)K + 16, a);
     int rc;
     if ((rc = grow(h, &h->lw_mem, &h->lw_bytes, total, "learned workspace"))) return rc;
     char *b = static_cast<char *>(h->lw_mem);
@@ -723,6 +724,10 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
                 return fail(h, SPG_ERR_ARG, "allocation must be SPG_ALLOC_PRECISE, SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER");
             h->alloc = value;
             break;
+        case SPG_OPT_LEARNED_HEAVY_MARGIN:
+            if (value < 0 || value > 10000) return fail(h, SPG_ERR_ARG, "heavy margin must be 0..10000 (thousandths)");
+            h->heavy_margin_milli = value;
+            break;
         case SPG_OPT_LEARNED_FORCE:
             if (value != 0 && value != 1) return fail(h, SPG_ERR_ARG, "learned force must be 0 or 1");
             h->learned_force = value;
@@ -750,6 +755,7 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_ALLOC: *value = h->alloc; break;
         case SPG_OPT_GROUP_ROWS: *value = h->group_rows; break;
         case SPG_OPT_LEARNED_FORCE: *value = h->learned_force; break;
+        case SPG_OPT_LEARNED_HEAVY_MARGIN: *value = h->heavy_margin_milli; break;
         case SPG_OPT_ACCUMULATOR: *value = h->accumulator; break;
         default: return fail(h, SPG_ERR_ARG, "unknown option %d", key);
     }
@@ -774,6 +780,7 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_HEAVY_WIDE: *value = h->heavy_wide; return SPG_OK;
         case SPG_STAT_HEAVY_SPLIT_ROWS: *value = h->heavy_split_rows; return SPG_OK;
         case SPG_STAT_OVERFLOW_ROWS: *value = h->ovf_light + h->ovf_heavy; return SPG_OK;
+        case SPG_STAT_OVERFLOW_HEAVY_ROWS: *value = h->ovf_heavy; return SPG_OK;
         case SPG_STAT_PREDICTED_ROWS: {
             int64_t n = 0;
             for (int c = kClassWaveSmall; c < kNumClasses; ++c) n += h->counts[c];
@@ -874,7 +881,8 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
         HIP_TRY(h, launch_zero_ctl(h->ctl2, s));
         if (learned)
             HIP_TRY(h, launch_mlp_sizes(M, lw.feats, lw.predicted, lw.lo, lw.hi, ws.row_nprod, h->mlp,
-                                        h->mlp + kMlpOffNorm, h->delta, (int)h->learned_force, lw.pred_size, s));
+                                        h->mlp + kMlpOffNorm, h->delta, (int)h->learned_force, h->block_max,
+                                        (float)h->heavy_margin_milli / 1000.0f, lw.pred_size, s));
         else
             HIP_TRY(h, launch_upper_sizes(M, ws.row_nprod, lw.pred_size, s));
         HIP_TRY(h, launch_scan(M, lw.pred_size, ws.tile_sum, lw.slot_off, &h->ctl->pred_total, s));

@@ -102,13 +102,14 @@ hipError_t launch_validate(const CsrView &X, int64_t ncols_limit, int64_t err_rp
                            Ctl *ctl, hipStream_t s);
 // the size predictor's inputs per row, written by the analysis when asked
 struct RowFeatures {
-    const int32_t *b_ends;  // first and last column of every row of B (launch_row_ends)
+    const int32_t *b_ends;  // per row of B: first and last column, length, start (launch_row_ends)
     float *feats;       // [M * 6]
     int32_t *lo, *hi;   // bounds of the row size
     int8_t *predicted;  // 1: the row's size is predicted (products, two lists or more)
     int64_t ncols;      // columns of B (the features relative to the column space)
 };
-// ends[2k], ends[2k+1]: first and last column of B's row k (-1, -1 when empty)
+// ends[4k .. 4k+3]: first and last column of B's row k (-1, -1 when empty),
+// its length and its start (the low 32 bits)
 hipError_t launch_row_ends(const CsrView &B, int32_t *ends, hipStream_t s);
 hipError_t launch_analysis(const CsrView &A, const CsrView &B, const Thresholds &th,
                            const Workspace &ws, int grid, hipStream_t s, const RowFeatures *rf = nullptr);
@@ -249,7 +250,8 @@ hipError_t launch_features(const CsrView &A, const CsrView &B, float *feats, int
                            int8_t *predicted, const int64_t *c_rpt, float *targets, hipStream_t s);
 hipError_t launch_mlp_sizes(int64_t M, const float *feats, const int8_t *predicted, const int32_t *lo,
                             const int32_t *hi, const int64_t *row_nprod, const float *params,
-                            const float *norm, float delta, int force, int32_t *pred_size, hipStream_t s);
+                            const float *norm, float delta, int force, int64_t heavy_min, float heavy_margin,
+                            int32_t *pred_size, hipStream_t s);
 hipError_t launch_mlp_forward(int64_t n, const float *feats, const float *params, const float *norm,
                               float *y, hipStream_t s);
 hipError_t launch_mlp_gradient(int64_t n, const float *feats, const float *targets, const float *params,

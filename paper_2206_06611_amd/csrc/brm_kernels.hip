@@ -288,10 +288,14 @@ __device__ __forceinline__ void window_row_reduce(int64_t eb, bool in, int64_t a
 
 // first and last column of every row of B
 template <typename IB>
-__global__ __launch_bounds__(256) void k_row_ends(int64_t K, const IB *rpt, const int32_t *col, int2 *ends) {
+__global__ __launch_bounds__(256) void k_row_ends(int64_t K, const IB *rpt, const int32_t *col, int4 *ends) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b0 = rpt[k], b1 = rpt[k + 1];
-        ends[k] = b1 > b0 ? make_int2(col[b0], col[b1 - 1]) : make_int2(-1, -1);
+        // first and last column, length, start (low 32 bits; the whole start
+        // with 32-bit row pointers): one 16-byte gather per A entry gives the
+        // analysis of the features everything it needs of a B row
+        ends[k] = b1 > b0 ? make_int4(col[b0], col[b1 - 1], (int)(b1 - b0), (int)b0)
+                          : make_int4(-1, -1, 0, (int)b0);
     }
 }
 
@@ -300,10 +304,10 @@ hipError_t launch_row_ends(const CsrView &B, int32_t *ends, hipStream_t s) {
     const int g = (int)std::min<int64_t>((B.rows + 255) / 256, 4096);
     if (B.rpt_bytes == 4)
         hipLaunchKernelGGL((k_row_ends<int32_t>), dim3(g), dim3(256), 0, s, B.rows,
-                           static_cast<const int32_t *>(B.rpt), B.col, reinterpret_cast<int2 *>(ends));
+                           static_cast<const int32_t *>(B.rpt), B.col, reinterpret_cast<int4 *>(ends));
     else
         hipLaunchKernelGGL((k_row_ends<int64_t>), dim3(g), dim3(256), 0, s, B.rows,
-                           static_cast<const int64_t *>(B.rpt), B.col, reinterpret_cast<int2 *>(ends));
+                           static_cast<const int64_t *>(B.rpt), B.col, reinterpret_cast<int4 *>(ends));
     return hipGetLastError();
 }
 
@@ -361,15 +365,24 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
                 int mnv = INT32_MAX;
                 if (e < e1) {
                     const int32_t k = a_col[e];
-                    const IB bs = brp[k];
-                    n = (int64_t)brp[k + 1] - (int64_t)bs;
+                    // the row's 16-byte record, as two 64-bit words of one line
+                    const int64_t *rp = reinterpret_cast<const int64_t *>(rf.b_ends) + 2 * (int64_t)k;
+                    const int64_t w0 = gload(rp), w1 = gload(rp + 1);
+                    const int4 re = make_int4((int)w0, (int)(w0 >> 32), (int)w1, (int)(w1 >> 32));
+                    IB bs;
+                    if constexpr (sizeof(IB) == 4) {
+                        bs = (IB)re.w;  // the row's start: no gather of B's row pointers
+                        n = re.z;
+                    } else {
+                        bs = brp[k];
+                        n = (int64_t)brp[k + 1] - (int64_t)bs;
+                    }
                     ent_bs[e] = bs;
                     ent_len[e] = (int32_t)n;
                     mnv = (int)n;
                     if (n > 0) {
-                        const int2 fl = reinterpret_cast<const int2 *>(rf.b_ends)[k];
-                        f = fl.x;
-                        l = fl.y;
+                        f = re.x;
+                        l = re.y;
                     }
                 }
                 const WindowSegs ws = window_segs(eb, in, a0, a1, s_flag[w], lane);

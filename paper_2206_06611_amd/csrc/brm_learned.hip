@@ -194,17 +194,27 @@ __global__ __launch_bounds__(256) void k_mlp_sizes(int64_t M, const float *feats
                                                    const int32_t *lo, const int32_t *hi,
                                                    const int64_t *row_nprod, const float *__restrict__ params,
                                                    const float *__restrict__ norm, float delta, int force,
-                                                   int32_t *pred_size) {
+                                                   int64_t heavy_min, float heavy_margin, int32_t *pred_size) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t sz;
+        // products over the columns they span (a log1p feature): with fewer
+        // than one expected repeat among the products (products^2 / span <
+        // 1), the exact upper bound min(products, span) is as tight as a
+        // prediction could be and never overflows: no network needed
+        const double per_col = expm1((double)feats[6 * i + 5]);
         if (!predicted[i]) {
             sz = lo[i];
         } else if (force == 1) {
             sz = lo[i];
+        } else if ((double)row_nprod[i] * per_col < 1.0) {
+            sz = hi[i];
         } else {
             const float y = mlp_eval(params, norm, feats + 6 * i);
-            const double e = ceil((double)row_nprod[i] * exp((double)y + (double)delta));
+            // rows merged through spill buffers get a wider margin: re-merging
+            // one that overflows costs far more than its extra slot entries
+            const double m = (double)delta + (row_nprod[i] > heavy_min ? (double)heavy_margin : 0.0);
+            const double e = ceil((double)row_nprod[i] * exp((double)y + m));
             sz = e > (double)hi[i] ? hi[i] : (e < (double)lo[i] ? lo[i] : (int64_t)e);
         }
         pred_size[i] = (int32_t)sz;
@@ -213,11 +223,12 @@ __global__ __launch_bounds__(256) void k_mlp_sizes(int64_t M, const float *feats
 
 hipError_t launch_mlp_sizes(int64_t M, const float *feats, const int8_t *predicted, const int32_t *lo,
                             const int32_t *hi, const int64_t *row_nprod, const float *params,
-                            const float *norm, float delta, int force, int32_t *pred_size, hipStream_t s) {
+                            const float *norm, float delta, int force, int64_t heavy_min, float heavy_margin,
+                            int32_t *pred_size, hipStream_t s) {
     if (M == 0) return hipSuccess;
     const unsigned g = (unsigned)((M + 255) / 256 < 4096 ? (M + 255) / 256 : 4096);
     hipLaunchKernelGGL(k_mlp_sizes, dim3(g), dim3(256), 0, s, M, feats, predicted, lo, hi, row_nprod,
-                       params, norm, delta, force, pred_size);
+                       params, norm, delta, force, heavy_min, heavy_margin, pred_size);
     return hipGetLastError();
 }
 
