@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "eeae6cce9d088692b18043a0b396674bc574d159103be2c8d9eefa0153362681",
-                 "fetch_kib": 1093514.0, "write_kib": 842975.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "8c2ae1c690cdb4e4817afe63b7e523c66bac2d45df5557f8ee2ae0ab639ce5b4",
+                 "fetch_kib": 1094150.0, "write_kib": 843094.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
@@ -617,7 +617,7 @@ def main():
     }
     torch.cuda.empty_cache()
     if args.copy_probe:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
