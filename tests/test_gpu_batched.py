@@ -156,6 +156,25 @@ def test_heavy_rows_rejected(handle):
     assert rc == brm.SPG_ERR_CAPACITY and req == -1
 
 
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_heavy_row_in_first_stage_of_a_chain(handle, noalloc):
+    # stage 1 holds a row beyond 4096 products: the call fails with
+    # required_bytes = -1, and the chained stage 2 (whose B would be stage
+    # 1's C) reads nothing
+    A = synth.rmat(11, 16, 6)
+    dA = dev(A)
+    arena = torch.full((1 << 24,), 0x5A, dtype=torch.uint8, device="cuda")
+    rc, req, outs = handle.batched([(dA, dA), (dA, 0)], arena, noalloc=noalloc)
+    torch.cuda.synchronize()
+    assert rc == brm.SPG_ERR_CAPACITY and req == -1 and outs is None
+    # the handle serves a batch that fits afterwards
+    inp = galerkin_inputs([5, 4])
+    triples = [(dev(A_), dev(P), dev(Pt)) for _, A_, P, Pt in inp]
+    G, _, _ = handle.galerkin(triples)
+    for (n, A_, P, Pt), g in zip(inp, G):
+        assert g.nnz == (3 * ((n + 1) // 2) - 2) ** 3
+
+
 def test_config4_full_batch(handle):
     print("case: 48 Galerkin products, cube edges U{16..64}, seed 4", flush=True)
     inp = synth.amg_batch(48, 4)

@@ -224,3 +224,16 @@ def test_split_rows_in_slotted_modes(alloc):
                                   y.view(np.int64) if y.dtype == np.float64 else y)
     finally:
         h.close()
+
+
+def test_split_rows_int64_row_pointers(handle):
+    # the 64-bit row-pointer instantiations of the heavy kernel, split rows included
+    print("case: R-MAT scale 12, int64 row pointers, subtrees of 3000 products", flush=True)
+    A = synth.rmat(12, 16, 31)
+    dA = brm.DeviceCSR.from_host(A, rpt_dtype=torch.int64)
+    handle.set_option(brm.OPT_HEAVY_SPLIT, 3000)
+    C = handle.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    assert handle.stat(brm.STAT_HEAVY_SPLIT_ROWS) > 0
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))

@@ -157,3 +157,30 @@ def test_noalloc_arena_and_heavy_row_errors_match_batched():
 def test_noalloc_symbol_exported():
     assert hasattr(brm.library(), "spgemm_batched_noalloc")
     assert isinstance(brm.library().spgemm_batched_noalloc, ctypes._CFuncPtr)
+
+
+def test_noalloc_stage_after_overflow_reads_no_stale_arena():
+    """The allocation-free call on a chained batch whose arena still holds
+    an earlier batch's row pointers where stage 1's C would go."""
+    h = brm.Handle(0)
+    try:
+        first = galerkin_batch([10, 9], 4)[1]
+        p1 = brm.Handle.galerkin_problems(first)
+        size = 1 << 14
+        for _ in range(3):
+            rc, req, _, _ = run(h, p1, size, noalloc=True)
+            if rc == brm.SPG_OK:
+                break
+            size = req
+        assert rc == brm.SPG_OK
+        arena = torch.empty(size, dtype=torch.uint8, device="cuda")
+        rc, req, _ = h.batched(p1, arena, noalloc=True)
+        assert rc == brm.SPG_OK
+        inp, second = galerkin_batch([12, 11], 5)
+        p2 = brm.Handle.galerkin_problems(second)
+        rc, req, outs = h.batched(p2, arena, noalloc=True)
+        torch.cuda.synchronize()
+        assert rc == brm.SPG_ERR_CAPACITY and req > size
+        check_batch(h, inp, second, 1 << 24)
+    finally:
+        h.close()
