@@ -205,9 +205,11 @@ typedef enum {
     SPG_STAT_HEAVY_WIDE = 28,    /* spill batches of the last numeric call run by 1024-thread
                                     workgroups (the others by 512-thread ones) */
     SPG_STAT_HEAVY_SPLIT_ROWS = 29,/* heavy rows of the last numeric call merged as several subtrees */
-    SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call
-                                    (16: a numeric row length differed from its symbolic count;
-                                    the row was truncated to its slot).  Synchronizes the device. */
+    SPG_STAT_DEVICE_ERR = 30     /* error bits the kernels raised since the last symbolic call,
+                                    or in the last batched call (16: a numeric row length
+                                    differed from its symbolic count; the row was truncated to
+                                    its slot; 32: a heavy row's merge walk failed).
+                                    Synchronizes the device. */
 } spg_stat;
 
 int spg_get_stat(spg_handle h, int key, int64_t *value);
@@ -276,8 +278,15 @@ int spgemm_row_products(spg_handle h, const spg_csr *A, const spg_csr *B, int64_
  * sequence is captured once in a HIP graph and replayed while the problems
  * (pointers, sizes), the arena and the options stay the same.  Results are
  * bitwise equal to separate spgemm_symbolic / spgemm_numeric calls.
- * Rows with more than 4096 products are not supported here (SPG_ERR_CAPACITY
- * with *required_bytes = -1); use the single-product calls for them. */
+ * Rows beyond one workgroup's LDS (more than 4096 products) are merged as
+ * in the single product's heavy path (Algorithm 1's tree, spilled nodes
+ * merged through HBM), one 512-thread workgroup per row, each whole row in
+ * one workgroup (the single product's subtree split is not used here).
+ * Their spill buffers -- two lists of nprod_i entries per heavy row, 24
+ * bytes per product, plus 4 bytes per list -- lie in the arena after the
+ * stage's C and count towards *required_bytes; the next stage's C reuses
+ * that space.  A row of 2^31 or more products fails the call
+ * (SPG_ERR_CAPACITY with *required_bytes = -1). */
 typedef struct {
     spg_csr A;        /* device CSR */
     spg_csr B;        /* device CSR; ignored when b_from >= 0 */
@@ -298,12 +307,16 @@ typedef struct {
  * batch is done (one device-to-host read of the batch status).  Problems of
  * one stage must share the row-pointer widths of A and of B (chained B always
  * has int64 row pointers).
+ * On success *required_bytes is the arena size the batch needed (row
+ * pointers, every C, and the largest heavy-row spill space of a stage).
+ * Device errors of the kernels are read with SPG_STAT_DEVICE_ERR.
  * Errors: SPG_ERR_ARG, SPG_ERR_DIM (A_p.cols != B_p.rows), SPG_ERR_CAPACITY
  * (arena too small: the outputs are invalid and *required_bytes is set to the
  * size that the stages up to the first one that did not fit need; a stage
  * after it computes nothing -- its B may be a C that was never written -- so
  * with chained problems a call with an arena of that size may fail again
- * with a larger *required_bytes), SPG_ERR_NOMEM, SPG_ERR_HIP. */
+ * with a larger *required_bytes; or a row of 2^31 or more products:
+ * *required_bytes = -1), SPG_ERR_NOMEM, SPG_ERR_HIP. */
 int spgemm_batched(spg_handle h, int count, const spg_problem *problems, void *arena, int64_t arena_bytes,
                    spg_batched_out *out, int64_t *required_bytes, void *stream);
 

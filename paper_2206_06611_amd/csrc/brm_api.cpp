@@ -95,6 +95,7 @@ struct spg_handle_s {
     int64_t alloc = 0;          // 0 precise, 1 learned, 2 upper bound
     int64_t accumulator = 0;    // 0 BRMerge, 1 hash table (comparator)
     int64_t learned_force = 0;  // testing: 1 = every predicted row at its lower bound
+    int64_t b_err = 0;                 // device errors of the last batched call
     int64_t heavy_margin_milli = 200;  // extra margin (thousandths) of rows beyond one workgroup's LDS
     bool plan_learned = false;
     void *lw_mem = nullptr;     // per-row learned workspace
@@ -793,7 +794,7 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
             int64_t e = 0, e2 = 0;
             HIP_TRY(h, hipMemcpy(&e, &h->ctl->err, sizeof e, hipMemcpyDeviceToHost));
             if (h->ctl2) HIP_TRY(h, hipMemcpy(&e2, &h->ctl2->err, sizeof e2, hipMemcpyDeviceToHost));
-            *value = e | e2;
+            *value = e | e2 | h->b_err;
             return SPG_OK;
         }
         default: return fail(h, SPG_ERR_ARG, "unknown statistic %d", key);
@@ -804,6 +805,7 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
                     int64_t *c_nnz, void *stream) {
     if (!h) return SPG_ERR_ARG;
     h->err.clear();
+    h->b_err = 0;
     h->plan_valid = false;
     int rc;
     // learned and upper-bound allocation compute the rows' values into slots
@@ -1416,7 +1418,7 @@ hipError_t launch_batched_all(spg_handle h, const BatchedPlan &pl, const std::ve
     int64_t *d_roff = reinterpret_cast<int64_t *>(base + pl.o_roff);
     BatchProb *d_tab = reinterpret_cast<BatchProb *>(base + pl.o_tab);
     BatchStatus *d_stat = reinterpret_cast<BatchStatus *>(base + pl.o_stat);
-    hipError_t e = launch_batched_begin(d_stat, s);
+    hipError_t e = launch_batched_begin(d_stat, ws.ctl, s);
     // lane windows as in the single product (their keys bound B's columns)
     const bool win = uses_windows(h->group_rows) && pl.max_bcols < ((int64_t)1 << 26);
     const Thresholds th = thresholds(h, win, pl.max_bcols <= ((int64_t)1 << 21));
@@ -1439,6 +1441,7 @@ hipError_t launch_batched_all(spg_handle h, const BatchedPlan &pl, const std::ve
         bs.arena_bytes = arena_bytes;
         bs.data_off = pl.rpt_end;
         bs.status = d_stat;
+        bs.heavy_lds_cap = (int)std::min<int64_t>(h->heavy_lds_max, 4 * (int64_t)kBatchHeavyThreads);
         e = launch_batched_stage(bs, ws, th, h->num_cu, h->grid_waves, s);
     }
     return e;
@@ -1449,9 +1452,10 @@ int finish_batched(spg_handle h, const BatchStatus &bst, const Ctl &ctl, const B
                    int64_t *required_bytes) {
     h->nprod = bst.nprod;
     for (int i = 0; i < kNumClasses; ++i) h->counts[i] = ctl.count[i];  // the last stage's rows
-    if (bst.flags & kBatchHeavyRow) {
+    h->b_err = bst.err | ctl.err;
+    if (bst.flags & kBatchRowProducts) {
         *required_bytes = -1;
-        return fail(h, SPG_ERR_CAPACITY, "a row has more than %d products; use the single-product calls", kCapBlock);
+        return fail(h, SPG_ERR_CAPACITY, "a row has 2^31 or more products");
     }
     *required_bytes = std::max<int64_t>(bst.required, pl.rpt_end);
     if (bst.flags & kBatchOverflow)
@@ -1467,6 +1471,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
                    spg_batched_out *out, int64_t *required_bytes, void *stream) {
     if (!h) return SPG_ERR_ARG;
     h->err.clear();
+    h->b_err = 0;
     BatchedPlan pl;
     int rc;
     if ((rc = plan_batched(h, count, probs, arena, arena_bytes, out, required_bytes, &pl))) return rc;
@@ -1522,7 +1527,8 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     }
     for (int64_t v : {(int64_t)reinterpret_cast<uintptr_t>(arena), arena_bytes, h->wave_small_max, h->wave_max,
                       h->group_max, h->group_rows,
-                      h->block_max, h->force, h->grid_waves, (int64_t)reinterpret_cast<uintptr_t>(h->b_mem)})
+                      h->block_max, h->force, h->grid_waves, h->heavy_lds_max,
+                      (int64_t)reinterpret_cast<uintptr_t>(h->b_mem)})
         sig.push_back(v);
     if (realloc || !h->graph_exec || sig != h->graph_sig) {
         if (h->graph_exec) {
@@ -1562,6 +1568,7 @@ int spgemm_batched_noalloc(spg_handle h, int count, const spg_problem *probs, vo
                            spg_batched_out *out, int64_t *required_bytes, void *stream) {
     if (!h) return SPG_ERR_ARG;
     h->err.clear();
+    h->b_err = 0;
     BatchedPlan pl;
     int rc;
     if ((rc = plan_batched(h, count, probs, arena, arena_bytes, out, required_bytes, &pl))) return rc;

@@ -205,7 +205,7 @@ struct BatchProb {
     int64_t ent_off;   // first entry of this problem's A in the stage's list descriptors
 };
 
-enum BatchFlags : int { kBatchOverflow = 1, kBatchHeavyRow = 2 };
+enum BatchFlags : int { kBatchOverflow = 1, kBatchRowProducts = 2 };  // arena too small / a row of 2^31+ products
 
 struct BatchStatus {
     int flags;
@@ -214,8 +214,15 @@ struct BatchStatus {
     int64_t required;    // arena bytes the batch needs
     int64_t arena_used;  // running arena fill (row pointers, then each stage's C)
     int64_t nprod;
+    int64_t err;         // device errors (Ctl::err) of the stages before the current one
+    // the current stage's heavy-row spill space in the arena (set when it fits)
+    int64_t *h_tab;      // (spill offset, list-offset offset) per heavy row, in class order
+    int32_t *h_col;
+    double *h_val;
+    int32_t *h_leaf;
 };
 
+constexpr int kBatchHeavyThreads = 512;  // workgroup of the batched heavy-row merge
 constexpr int kBatchChunkRows = 64;  // rows per wavefront pass of the batched analysis (one wavefront)
 // device bytes of the allocation-free batched call's static workspace
 constexpr int64_t kNoAllocScratchBytes = (int64_t)64 << 20;
@@ -234,9 +241,10 @@ struct BatchStage {
     char *arena;
     int64_t arena_bytes, data_off;
     BatchStatus *status;
+    int heavy_lds_cap;   // largest list range of a heavy row merged in LDS
 };
 
-hipError_t launch_batched_begin(BatchStatus *st, hipStream_t s);
+hipError_t launch_batched_begin(BatchStatus *st, Ctl *ctl, hipStream_t s);
 hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const Thresholds &th, int num_cu,
                                 int64_t grid_waves, hipStream_t s);
 hipError_t launch_batched_describe(const BatchProb *all, int n, spg_batched_out *out, const BatchStatus *st,

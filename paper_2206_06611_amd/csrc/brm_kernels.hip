@@ -107,9 +107,9 @@ struct Lists {
     __device__ __forceinline__ void get(int64_t p, int64_t &bs, int &ln) const {
         if (ent_len) {
             bs = ld_rpt<IB>(ent_bs, p);
-            ln = ent_len[p];
+            ln = gload(ent_len + p);
         } else {
-            const int32_t k = a_col[p];
+            const int32_t k = gload(a_col + p);
             bs = ld_rpt<IB>(b_rpt, k);
             ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
         }
@@ -117,7 +117,7 @@ struct Lists {
     // the per-entry arrays only (they must be present)
     __device__ __forceinline__ void get_ent(int64_t p, int64_t &bs, int &ln) const {
         bs = ld_rpt<IB>(ent_bs, p);
-        ln = ent_len[p];
+        ln = gload(ent_len + p);
     }
 };
 
@@ -749,62 +749,75 @@ constexpr int kBitmapWords = 32768;  // 128 KB
 constexpr int64_t kBitmapBits = (int64_t)kBitmapWords * 32;
 constexpr int kHeavyThreads = 1024;
 
+struct BitmapLds {
+    uint32_t bm[kBitmapWords];
+    ListStage<kHeavyThreads> st;
+    int64_t red[Team<kHeavyThreads>::kWaves + 1];
+};
+
+// distinct columns of one row (columns below ncols) by the bitmap count
+template <typename IA, typename IB>
+__device__ __forceinline__ int64_t sym_bitmap_row(BitmapLds &s, int tid, int64_t row, int64_t ncols,
+                                                  const void *a_rpt, const Lists<IB> &lists,
+                                                  const int32_t *b_col) {
+    const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+    const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
+    int64_t total = 0;
+    for (int64_t lo = 0; lo < ncols; lo += kBitmapBits) {
+        for (int w = tid; w < kBitmapWords; w += kHeavyThreads) s.bm[w] = 0u;
+        __syncthreads();
+        // the lists in chunks of kHeavyThreads; every thread takes
+        // kBitmapUnroll products of a chunk at a time and gathers their
+        // columns before setting any bit, so the gathers are in flight
+        // together
+        for (int64_t lb = 0; lb < L; lb += kHeavyThreads) {
+            const int64_t l = lb + tid;
+            int ln = 0;
+            int64_t bs = 0;
+            if (l < L) lists.get(a0 + l, bs, ln);
+            int tot;
+            const int ex = Team<kHeavyThreads>::excl_scan(ln, &tot, s.st.scan, tid);
+            s.st.bs[tid] = bs;
+            s.st.off[tid] = ex;
+            const int nl = (int)((L - lb) < kHeavyThreads ? (L - lb) : kHeavyThreads);
+            __syncthreads();
+            for (int qb = 0; qb < tot; qb += kBitmapUnroll * kHeavyThreads) {
+                int32_t col[kBitmapUnroll];
+#pragma unroll
+                for (int u = 0; u < kBitmapUnroll; ++u) {
+                    const int q = qb + u * kHeavyThreads + tid;
+                    col[u] = -1;
+                    if (q < tot) {
+                        const int t = upper_bound(s.st.off, nl, q) - 1;
+                        col[u] = gload(b_col + (s.st.bs[t] + (q - s.st.off[t])));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kBitmapUnroll; ++u) {
+                    const int64_t c = (int64_t)col[u] - lo;
+                    if (col[u] >= 0 && c >= 0 && c < kBitmapBits) atomicOr(&s.bm[c >> 5], 1u << (c & 31));
+                }
+            }
+            __syncthreads();
+        }
+        int64_t cnt = 0;
+        for (int w = tid; w < kBitmapWords; w += kHeavyThreads) cnt += __popc(s.bm[w]);
+        total += Team<kHeavyThreads>::sum(cnt, s.red, tid);
+    }
+    return total;
+}
+
 template <typename IA, typename IB>
 __global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
     int cls, int64_t ncols, const void *a_rpt, Lists<IB> lists,
     const int32_t *b_col, const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
-    __shared__ uint32_t bm[kBitmapWords];
-    __shared__ ListStage<kHeavyThreads> st;
-    __shared__ int64_t red[Team<kHeavyThreads>::kWaves + 1];
+    __shared__ BitmapLds s;
     const int tid = threadIdx.x;
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
     for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int64_t row = class_rows[start + idx];
-        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
-        const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
-        int64_t total = 0;
-        for (int64_t lo = 0; lo < ncols; lo += kBitmapBits) {
-            for (int w = tid; w < kBitmapWords; w += kHeavyThreads) bm[w] = 0u;
-            __syncthreads();
-            // the lists in chunks of kHeavyThreads; every thread takes
-            // kBitmapUnroll products of a chunk at a time and gathers their
-            // columns before setting any bit, so the gathers are in flight
-            // together
-            for (int64_t lb = 0; lb < L; lb += kHeavyThreads) {
-                const int64_t l = lb + tid;
-                int ln = 0;
-                int64_t bs = 0;
-                if (l < L) lists.get(a0 + l, bs, ln);
-                int tot;
-                const int ex = Team<kHeavyThreads>::excl_scan(ln, &tot, st.scan, tid);
-                st.bs[tid] = bs;
-                st.off[tid] = ex;
-                const int nl = (int)((L - lb) < kHeavyThreads ? (L - lb) : kHeavyThreads);
-                __syncthreads();
-                for (int qb = 0; qb < tot; qb += kBitmapUnroll * kHeavyThreads) {
-                    int32_t col[kBitmapUnroll];
-#pragma unroll
-                    for (int u = 0; u < kBitmapUnroll; ++u) {
-                        const int q = qb + u * kHeavyThreads + tid;
-                        col[u] = -1;
-                        if (q < tot) {
-                            const int t = upper_bound(st.off, nl, q) - 1;
-                            col[u] = gload(b_col + (st.bs[t] + (q - st.off[t])));
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < kBitmapUnroll; ++u) {
-                        const int64_t c = (int64_t)col[u] - lo;
-                        if (col[u] >= 0 && c >= 0 && c < kBitmapBits) atomicOr(&bm[c >> 5], 1u << (c & 31));
-                    }
-                }
-                __syncthreads();
-            }
-            int64_t cnt = 0;
-            for (int w = tid; w < kBitmapWords; w += kHeavyThreads) cnt += __popc(bm[w]);
-            total += Team<kHeavyThreads>::sum(cnt, red, tid);
-        }
+        const int64_t total = sym_bitmap_row<IA, IB>(s, tid, row, ncols, a_rpt, lists, b_col);
         if (tid == 0) row_size[row] = (int32_t)total;
         __syncthreads();
     }
@@ -3106,6 +3119,206 @@ struct HeavyBatch {
     int lds_cap;
 };
 
+// The merge tree of lists [lb0, lb1) of one row, walked by one workgroup
+// (Algorithm 1's accumulating phase, §III-B): LDS nodes of up to lds_cap
+// products and lists, merges of two spilled nodes through HBM.  A whole row
+// (res_slot < 0) ends in C; a subtree leaves its merged list in the row's
+// spill buffers (spill_col / spill_val: two buffers of nprod entries) and
+// its (buffer, length) in res[2 * res_slot].  leaf receives the row's list
+// offsets inside its product space.
+template <typename IA, typename IB, int T>
+__device__ __forceinline__ void heavy_walk(NumLds<T, 4 * T> &node_lds, MergeLds<T> &mrg, HeavyState<T> &st,
+                                           int tid, int64_t row, int64_t lb0, int64_t lb1, int res_slot,
+                                           int64_t nprod, int32_t *leaf, int32_t *spill_col, double *spill_val,
+                                           int lds_cap, int64_t *res, const void *a_rpt, const Lists<IB> &lists,
+                                           const double *a_val, const int32_t *b_col, const double *b_val,
+                                           const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
+                                           const NumOut &no) {
+    constexpr int kCap = 4 * T;  // products (and lists) of an LDS node
+    const bool whole = res_slot < 0;
+    const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+    const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
+    // list offsets inside the row's product space, for lists [lb0, lb1]:
+    // the products of the lists before lb0 first (a reduction only)
+    int64_t carry = 0;
+    for (int64_t lb = 0; lb < lb0; lb += T) {
+        const int64_t l = lb + tid;
+        int64_t ln = 0;
+        if (l < lb0) {
+            int64_t bs;
+            int n;
+            lists.get(a0 + l, bs, n);
+            ln = n;
+        }
+        int64_t tot;
+        (void)Team<T>::excl_scan(ln, &tot, st.scr, tid);
+        carry += wave_uniform(tot);
+    }
+    for (int64_t lb = lb0; lb < lb1; lb += T) {
+        const int64_t l = lb + tid;
+        int64_t ln = 0;
+        if (l < lb1) {
+            int64_t bs;
+            int n;
+            lists.get(a0 + l, bs, n);
+            ln = n;
+        }
+        int64_t tot;
+        const int64_t ex = Team<T>::excl_scan(ln, &tot, st.scr, tid);
+        if (l < lb1) leaf[l] = (int32_t)(carry + ex);
+        carry += wave_uniform(tot);
+    }
+    // the end offset (also the next item's first offset: the same value)
+    if (tid == 0) leaf[lb1] = (int32_t)carry;
+    int32_t *bcol[2] = {spill_col, spill_col + nprod};
+    double *bval[2] = {spill_val, spill_val + nprod};
+    const int64_t cs = c_rpt[row];
+    const int64_t ccap = c_rpt[row + 1] - cs;
+    if (tid == 0) {
+        st.sp = 0;
+        st.next_list = lb0;
+    }
+    // global stores of this workgroup become visible to it at the barrier (workgroup scope)
+    __syncthreads();
+    int64_t guard = 0;
+    while (true) {
+        if (tid == 0) {
+            int act = kActFail;
+            const int sp = st.sp;
+            if (++guard > 4 * (lb1 - lb0 + 64)) {
+                act = kActFail;
+            } else if (sp >= 2 && st.stack[sp - 2].h == st.stack[sp - 1].h &&
+                       (st.stack[sp - 1].p & 1) && st.stack[sp - 2].p == st.stack[sp - 1].p - 1) {
+                act = kActMerge;
+                const HeavyNode &y = st.stack[sp - 1];
+                st.root = whole && (y.p >> 1) == 0 && ((int64_t)1 << (y.h + 1)) >= L;
+            } else if (st.next_list < lb1) {
+                const int64_t l = st.next_list;
+                int h = 0;
+                while (h < 40 && ((l >> h) & 1) == 0 && l + ((int64_t)1 << h) < lb1) {
+                    const int64_t e = (l + ((int64_t)1 << (h + 1))) < lb1 ? l + ((int64_t)1 << (h + 1)) : lb1;
+                    if ((int64_t)leaf[e] - leaf[l] <= lds_cap && e - l <= lds_cap) ++h;
+                    else break;
+                }
+                st.h = h;
+                st.l0 = l;
+                st.l1 = (l + ((int64_t)1 << h)) < lb1 ? l + ((int64_t)1 << h) : lb1;
+                st.root = whole && l == 0 && st.l1 == L;
+                act = kActNode;
+            } else if (sp == 1) {
+                act = (!whole || st.stack[0].buf == 2) ? kActDone : kActToC;
+            } else if (sp >= 2 && (st.stack[sp - 1].p & 1) == 0) {
+                act = kActPromote;
+            }
+            st.action = act;
+        }
+        __syncthreads();
+        const int act = wave_uniform(st.action);
+        if (act == kActDone) break;
+        if (act == kActFail) {
+            if (tid == 0) {
+                atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err),
+                         (unsigned long long)kErrHeavyCapacity);
+                st.sp = 0;
+            }
+            break;
+        }
+        if (act == kActNode) {
+            const int64_t l0 = wave_uniform(st.l0), l1 = wave_uniform(st.l1);
+            const int root = wave_uniform(st.root);
+            const int64_t r0 = leaf[l0];
+            const int64_t np = (int64_t)leaf[l1] - r0;
+            int32_t *oc = root ? c_col + cs : bcol[0] + r0;
+            double *ov = root ? c_val + cs : bval[0] + r0;
+            const int64_t cap = root ? ccap : np;
+            int64_t len;
+            if (np <= lds_cap && (l1 - l0) <= lds_cap) {
+                len = brmerge_range_lds<T, kCap, 1, IB>(
+                    node_lds, tid, a0 + l0, (int)(l1 - l0), lists, a_val, b_col, b_val, oc, ov, cap);
+            } else {
+                // one list longer than LDS: the scaled B row is the node
+                const double a = a_val[a0 + l0];
+                int64_t bs;
+                int nb;
+                lists.get(a0 + l0, bs, nb);
+                for (int64_t j = tid; j < np && j < cap; j += T) {
+                    gstore(oc + j, gload(b_col + bs + j));
+                    gstore(ov + j, a * gload(b_val + bs + j));
+                }
+                len = np;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                if (st.sp < 64) {
+                    HeavyNode &nd = st.stack[st.sp++];
+                    nd.p = l0 >> st.h;
+                    nd.h = st.h;
+                    nd.len = len;
+                    nd.buf = root ? 2 : 0;
+                }
+                st.next_list = l1;
+            }
+        } else if (act == kActMerge) {
+            const int sp = wave_uniform(st.sp);
+            HeavyNode x = st.stack[sp - 2];
+            HeavyNode y = st.stack[sp - 1];
+            x.p = wave_uniform(x.p);
+            x.len = wave_uniform(x.len);
+            x.h = wave_uniform(x.h);
+            x.buf = wave_uniform(x.buf);
+            y.p = wave_uniform(y.p);
+            y.len = wave_uniform(y.len);
+            y.h = wave_uniform(y.h);
+            y.buf = wave_uniform(y.buf);
+            const int root = wave_uniform(st.root);
+            const int64_t rx = leaf[x.p << x.h];
+            const int64_t ry = leaf[y.p << y.h];
+            const int ob = root ? 2 : (x.buf == y.buf ? 1 - x.buf : y.buf);
+            int32_t *oc = root ? c_col + cs : bcol[ob] + rx;
+            double *ov = root ? c_val + cs : bval[ob] + rx;
+            const int64_t cap = root ? ccap : (nprod - rx);
+            const int64_t len = merge_hbm<T>(mrg, st, tid, bcol[x.buf] + rx, bval[x.buf] + rx, x.len,
+                                          bcol[y.buf] + ry, bval[y.buf] + ry, y.len, oc, ov, cap);
+            if (tid == 0) {
+                st.sp -= 2;
+                HeavyNode &nd = st.stack[st.sp++];
+                nd.p = x.p >> 1;
+                nd.h = x.h + 1;
+                nd.len = len;
+                nd.buf = ob;
+            }
+        } else if (act == kActPromote) {
+            if (tid == 0) {
+                HeavyNode &nd = st.stack[st.sp - 1];
+                nd.p >>= 1;
+                nd.h += 1;
+            }
+        } else if (act == kActToC) {
+            const HeavyNode x = st.stack[0];
+            const int64_t n = x.len < ccap ? x.len : ccap;
+            for (int64_t j = tid; j < n; j += T) {
+                gstore(c_col + cs + j, gload(bcol[x.buf] + j));
+                gstore(c_val + cs + j, gload(bval[x.buf] + j));
+            }
+            if (tid == 0) st.stack[0].buf = 2;
+        }
+        // global stores of this workgroup become visible to it at the barrier (workgroup scope)
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (whole) {
+            if (st.sp == 1) finish_row(no, ctl, row, st.stack[0].len, ccap, true);
+        } else {
+            // a failed walk leaves an empty list in buffer 0 (the error bit is set)
+            const bool ok = st.sp == 1;
+            res[2 * res_slot] = ok ? st.stack[0].buf : 0;
+            res[2 * res_slot + 1] = ok ? st.stack[0].len : 0;
+        }
+    }
+    // the workgroup's LDS state is free again only after thread 0 has read it
+    __syncthreads();
+}
+
 // One work item per workgroup: a whole row (its root written to C), or the
 // aligned subtree [l0, l1) of a long row's lists, whose merged list is left in
 // the row's spill buffers (at the offset of its first list's products) and
@@ -3134,191 +3347,12 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
         const HeavyItem &it = hb.items[ii];
         const int64_t bi = wave_uniform((int64_t)it.bi);
         const int res_slot = wave_uniform(it.res);
-        const bool whole = res_slot < 0;
         const int64_t lb0 = wave_uniform(it.l0), lb1 = wave_uniform(it.l1);
         const int64_t nprod = wave_uniform(it.nprod);
-        const int64_t row = hb.rows[bi];
-        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
-        const int64_t L = ld_rpt<IA>(a_rpt, row + 1) - a0;
-        int32_t *leaf = hb.leaf + hb.leaf_off[bi];
-        // list offsets inside the row's product space, for lists [lb0, lb1]:
-        // the products of the lists before lb0 first (a reduction only)
-        int64_t carry = 0;
-        for (int64_t lb = 0; lb < lb0; lb += T) {
-            const int64_t l = lb + tid;
-            int64_t ln = 0;
-            if (l < lb0) {
-                int64_t bs;
-                int n;
-                lists.get(a0 + l, bs, n);
-                ln = n;
-            }
-            int64_t tot;
-            (void)Team<T>::excl_scan(ln, &tot, st.scr, tid);
-            carry += wave_uniform(tot);
-        }
-        for (int64_t lb = lb0; lb < lb1; lb += T) {
-            const int64_t l = lb + tid;
-            int64_t ln = 0;
-            if (l < lb1) {
-                int64_t bs;
-                int n;
-                lists.get(a0 + l, bs, n);
-                ln = n;
-            }
-            int64_t tot;
-            const int64_t ex = Team<T>::excl_scan(ln, &tot, st.scr, tid);
-            if (l < lb1) leaf[l] = (int32_t)(carry + ex);
-            carry += wave_uniform(tot);
-        }
-        // the end offset (also the next item's first offset: the same value)
-        if (tid == 0) leaf[lb1] = (int32_t)carry;
-        int32_t *bcol[2] = {hb.spill_col + hb.spill_off[bi], hb.spill_col + hb.spill_off[bi] + nprod};
-        double *bval[2] = {hb.spill_val + hb.spill_off[bi], hb.spill_val + hb.spill_off[bi] + nprod};
-        const int64_t cs = c_rpt[row];
-        const int64_t ccap = c_rpt[row + 1] - cs;
-        if (tid == 0) {
-            st.sp = 0;
-            st.next_list = lb0;
-        }
-        // global stores of this workgroup become visible to it at the barrier (workgroup scope)
-        __syncthreads();
-        int64_t guard = 0;
-        while (true) {
-            if (tid == 0) {
-                int act = kActFail;
-                const int sp = st.sp;
-                if (++guard > 4 * (lb1 - lb0 + 64)) {
-                    act = kActFail;
-                } else if (sp >= 2 && st.stack[sp - 2].h == st.stack[sp - 1].h &&
-                           (st.stack[sp - 1].p & 1) && st.stack[sp - 2].p == st.stack[sp - 1].p - 1) {
-                    act = kActMerge;
-                    const HeavyNode &y = st.stack[sp - 1];
-                    st.root = whole && (y.p >> 1) == 0 && ((int64_t)1 << (y.h + 1)) >= L;
-                } else if (st.next_list < lb1) {
-                    const int64_t l = st.next_list;
-                    int h = 0;
-                    while (h < 40 && ((l >> h) & 1) == 0 && l + ((int64_t)1 << h) < lb1) {
-                        const int64_t e = (l + ((int64_t)1 << (h + 1))) < lb1 ? l + ((int64_t)1 << (h + 1)) : lb1;
-                        if ((int64_t)leaf[e] - leaf[l] <= hb.lds_cap && e - l <= hb.lds_cap) ++h;
-                        else break;
-                    }
-                    st.h = h;
-                    st.l0 = l;
-                    st.l1 = (l + ((int64_t)1 << h)) < lb1 ? l + ((int64_t)1 << h) : lb1;
-                    st.root = whole && l == 0 && st.l1 == L;
-                    act = kActNode;
-                } else if (sp == 1) {
-                    act = (!whole || st.stack[0].buf == 2) ? kActDone : kActToC;
-                } else if (sp >= 2 && (st.stack[sp - 1].p & 1) == 0) {
-                    act = kActPromote;
-                }
-                st.action = act;
-            }
-            __syncthreads();
-            const int act = wave_uniform(st.action);
-            if (act == kActDone) break;
-            if (act == kActFail) {
-                if (tid == 0) {
-                    atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err),
-                             (unsigned long long)kErrHeavyCapacity);
-                    st.sp = 0;
-                }
-                break;
-            }
-            if (act == kActNode) {
-                const int64_t l0 = wave_uniform(st.l0), l1 = wave_uniform(st.l1);
-                const int root = wave_uniform(st.root);
-                const int64_t r0 = leaf[l0];
-                const int64_t np = (int64_t)leaf[l1] - r0;
-                int32_t *oc = root ? c_col + cs : bcol[0] + r0;
-                double *ov = root ? c_val + cs : bval[0] + r0;
-                const int64_t cap = root ? ccap : np;
-                int64_t len;
-                if (np <= hb.lds_cap && (l1 - l0) <= hb.lds_cap) {
-                    len = brmerge_range_lds<T, kCap, 1, IB>(
-                        node_lds, tid, a0 + l0, (int)(l1 - l0), lists, a_val, b_col, b_val, oc, ov, cap);
-                } else {
-                    // one list longer than LDS: the scaled B row is the node
-                    const double a = a_val[a0 + l0];
-                    int64_t bs;
-                    int nb;
-                    lists.get(a0 + l0, bs, nb);
-                    for (int64_t j = tid; j < np && j < cap; j += T) {
-                        gstore(oc + j, gload(b_col + bs + j));
-                        gstore(ov + j, a * gload(b_val + bs + j));
-                    }
-                    len = np;
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    if (st.sp < 64) {
-                        HeavyNode &nd = st.stack[st.sp++];
-                        nd.p = l0 >> st.h;
-                        nd.h = st.h;
-                        nd.len = len;
-                        nd.buf = root ? 2 : 0;
-                    }
-                    st.next_list = l1;
-                }
-            } else if (act == kActMerge) {
-                const int sp = wave_uniform(st.sp);
-                HeavyNode x = st.stack[sp - 2];
-                HeavyNode y = st.stack[sp - 1];
-                x.p = wave_uniform(x.p);
-                x.len = wave_uniform(x.len);
-                x.h = wave_uniform(x.h);
-                x.buf = wave_uniform(x.buf);
-                y.p = wave_uniform(y.p);
-                y.len = wave_uniform(y.len);
-                y.h = wave_uniform(y.h);
-                y.buf = wave_uniform(y.buf);
-                const int root = wave_uniform(st.root);
-                const int64_t rx = leaf[x.p << x.h];
-                const int64_t ry = leaf[y.p << y.h];
-                const int ob = root ? 2 : (x.buf == y.buf ? 1 - x.buf : y.buf);
-                int32_t *oc = root ? c_col + cs : bcol[ob] + rx;
-                double *ov = root ? c_val + cs : bval[ob] + rx;
-                const int64_t cap = root ? ccap : (nprod - rx);
-                const int64_t len = merge_hbm<T>(mrg, st, tid, bcol[x.buf] + rx, bval[x.buf] + rx, x.len,
-                                              bcol[y.buf] + ry, bval[y.buf] + ry, y.len, oc, ov, cap);
-                if (tid == 0) {
-                    st.sp -= 2;
-                    HeavyNode &nd = st.stack[st.sp++];
-                    nd.p = x.p >> 1;
-                    nd.h = x.h + 1;
-                    nd.len = len;
-                    nd.buf = ob;
-                }
-            } else if (act == kActPromote) {
-                if (tid == 0) {
-                    HeavyNode &nd = st.stack[st.sp - 1];
-                    nd.p >>= 1;
-                    nd.h += 1;
-                }
-            } else if (act == kActToC) {
-                const HeavyNode x = st.stack[0];
-                const int64_t n = x.len < ccap ? x.len : ccap;
-                for (int64_t j = tid; j < n; j += T) {
-                    gstore(c_col + cs + j, gload(bcol[x.buf] + j));
-                    gstore(c_val + cs + j, gload(bval[x.buf] + j));
-                }
-                if (tid == 0) st.stack[0].buf = 2;
-            }
-            // global stores of this workgroup become visible to it at the barrier (workgroup scope)
-            __syncthreads();
-        }
-        if (tid == 0) {
-            if (whole) {
-                if (st.sp == 1) finish_row(no, ctl, row, st.stack[0].len, ccap, true);
-            } else {
-                // a failed walk leaves an empty list in buffer 0 (the error bit is set)
-                const bool ok = st.sp == 1;
-                hb.res[2 * res_slot] = ok ? st.stack[0].buf : 0;
-                hb.res[2 * res_slot + 1] = ok ? st.stack[0].len : 0;
-            }
-        }
-        __syncthreads();
+        heavy_walk<IA, IB, T>(node_lds, mrg, st, tid, hb.rows[bi], lb0, lb1, res_slot, nprod,
+                              hb.leaf + hb.leaf_off[bi], hb.spill_col + hb.spill_off[bi],
+                              hb.spill_val + hb.spill_off[bi], hb.lds_cap, hb.res, a_rpt, lists, a_val, b_col,
+                              b_val, c_rpt, c_col, c_val, ctl, no);
     }
 }
 
@@ -3515,9 +3549,13 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
     __shared__ int64_t s_nprod;
     __shared__ int64_t s_start[kW][kWave + 1];
     __shared__ int32_t s_flag[kW][kWave];  // row heads of a window
+    __shared__ int s_long;                  // a row of 2^31 or more products
     load_lookup(lk, chunk_off, np);
     if (threadIdx.x < kNumClasses) s_count[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_nprod = 0;
+    if (threadIdx.x == 0) {
+        s_nprod = 0;
+        s_long = 0;
+    }
     __syncthreads();
     int64_t my_count[kNumClasses];
 #pragma unroll
@@ -3590,14 +3628,17 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
             const int64_t g = pr.row_off + i;
             const int64_t nprod = np_r;
             const int mx = mx_r;
-            const int cls = classify(a1 - a0, nprod, mx, th);
+            // rows of 2^31 or more products go to no kernel and fail the batch
+            const bool too_long = nprod > (int64_t)INT32_MAX;
+            if (too_long) s_long = 1;
+            const int cls = too_long ? (int)kClassEmpty : classify(a1 - a0, nprod, mx, th);
             const int sw = (cls == kClassWaveSmall && th.windows) ? window_shift(a1 - a0, mx)
                            : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, nprod)
                                                                   : 0;
             row_nprod[g] = nprod;
             row_class[g] = (uint8_t)(cls | (sw << kClassBits));
             row_prob[g] = p;
-            if (cls == kClassEmpty || cls == kClassHeavy) row_size[g] = 0;  // heavy rows: unsupported, flagged
+            if (cls == kClassEmpty) row_size[g] = 0;
             if (cls == kClassCopy) row_size[g] = (int32_t)nprod;
 #pragma unroll
             for (int q = 0; q < kNumClasses; ++q) my_count[q] += (cls == q);
@@ -3622,7 +3663,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         atomicAdd(reinterpret_cast<unsigned long long *>(&ctl->nprod), (unsigned long long)s_nprod);
         atomicAdd(reinterpret_cast<unsigned long long *>(&st->nprod), (unsigned long long)s_nprod);
     }
-    if (threadIdx.x == kNumClasses && s_count[kClassHeavy]) atomicOr(&st->flags, (int)kBatchHeavyRow);
+    if (threadIdx.x == kNumClasses && s_long) atomicOr(&st->flags, (int)kBatchRowProducts);
 }
 
 template <int T, int TEAMS, int TS, typename IA, typename IB>
@@ -3685,7 +3726,7 @@ __global__ __launch_bounds__(256) void k_b_rpt(BatchProb *tab, const int64_t *ro
                                                const int64_t *S, const BatchStatus *st) {
     __shared__ ProbLookup lk;
     load_lookup(lk, row_off, np);
-    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R; g += (int64_t)gridDim.x * blockDim.x) {
         const int p = find_prob(lk, row_off, np, g);
         const BatchProb &pr = tab[p];
@@ -3716,7 +3757,7 @@ __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *ta
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ ProbLookup lk;
     load_lookup(lk, row_off, np);
-    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
     const int lane = lane_id();
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
@@ -3740,7 +3781,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb
     __shared__ ProbLookup lk;
     __shared__ NumLds<T, CAP> lds[TEAMS];
     load_lookup(lk, row_off, np);
-    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
     const int team = threadIdx.x / T, tid = threadIdx.x % T;
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
@@ -3764,7 +3805,7 @@ __global__ __launch_bounds__(256) void k_b_num_win(int cls, const BatchProb *tab
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ uint32_t xk[4][kWave];
     __shared__ double xv[4][kWave];
-    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
     lists.ent_bs = ent_bs;
@@ -3804,7 +3845,7 @@ __global__ __launch_bounds__(256) void k_b_num_mw(int cls, const BatchProb *tab,
                                                   const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ double vals[4][kMwSlots];
-    if (st->flags & (kBatchOverflow | kBatchHeavyRow)) return;
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
     lists.ent_bs = ent_bs;
@@ -3838,6 +3879,139 @@ __global__ __launch_bounds__(256) void k_b_sym_mw(int cls, const BatchProb *tab,
                                  (int64_t)gridDim.x * 4, br);
 }
 
+// Heavy rows of a batched stage (more products than a 1024-thread LDS
+// row): the bitmap count for the symbolic pass, one 1024-thread workgroup
+// per row
+template <typename IA, typename IB>
+__global__ __launch_bounds__(kHeavyThreads) void k_b_sym_bitmap(const BatchProb *tab, const int32_t *row_prob,
+                                                                const int32_t *class_rows, int32_t *row_size,
+                                                                const Ctl *ctl) {
+    if (ctl->count[kClassHeavy] == 0) return;  // no heavy row in this stage
+    __shared__ BitmapLds s;
+    const int tid = threadIdx.x;
+    const int64_t count = ctl->count[kClassHeavy];
+    const int64_t start = class_start(ctl, kClassHeavy);
+    for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int64_t g = class_rows[start + idx];
+        const BatchProb &tp = tab[row_prob[g]];
+        const int64_t total = sym_bitmap_row<IA, IB>(s, tid, g - tp.row_off, tp.ncols_b, tp.a_rpt,
+                                                     direct_lists<IB>(tp.a_col, tp.b_rpt), tp.b_col);
+        if (tid == 0) row_size[g] = (int32_t)total;
+        __syncthreads();
+    }
+}
+
+// The heavy rows' spill space in the arena, after the stage's C (the next
+// stage's C may reuse it): a table of (spill offset, list-offset offset)
+// per heavy row in class order, then every row's two spill buffers (2 *
+// nprod columns, then 2 * nprod values) and its list offsets (lists + 1).
+// A space that does not fit sets the overflow flag; the need counts towards
+// the required arena size either way.
+template <typename IA>
+__global__ __launch_bounds__(1024) void k_b_heavy_plan(const BatchProb *tab, const int32_t *row_prob,
+                                                       const int64_t *row_nprod, const int32_t *class_rows,
+                                                       const Ctl *ctl, BatchStatus *st, char *arena,
+                                                       int64_t arena_bytes) {
+    const int64_t n = ctl->count[kClassHeavy];
+    if (n == 0) return;
+    __shared__ int64_t scr[Team<1024>::kWaves + 1];
+    const int tid = threadIdx.x;
+    const int64_t start = class_start(ctl, kClassHeavy);
+    auto sizes = [&](int64_t i, int64_t &e, int64_t &f) {
+        const int64_t g = class_rows[start + i];
+        const BatchProb &tp = tab[row_prob[g]];
+        const int64_t r = g - tp.row_off;
+        e = 2 * row_nprod[g];
+        f = ld_rpt<IA>(tp.a_rpt, r + 1) - ld_rpt<IA>(tp.a_rpt, r) + 1;
+    };
+    int64_t e_sum = 0, f_sum = 0;
+    for (int64_t i = tid; i < n; i += 1024) {
+        int64_t e, f;
+        sizes(i, e, f);
+        e_sum += e;
+        f_sum += f;
+    }
+    const int64_t E = Team<1024>::sum(e_sum, scr, tid);
+    const int64_t F = Team<1024>::sum(f_sum, scr, tid);
+    auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
+    const int64_t o_tab = al(st->arena_used);
+    const int64_t o_col = o_tab + al(16 * n);
+    const int64_t o_val = o_col + al(4 * E);
+    const int64_t o_leaf = o_val + al(8 * E);
+    const int64_t end = o_leaf + al(4 * F);
+    __syncthreads();  // every thread has read arena_used
+    if (tid == 0) {
+        if (end > st->required) st->required = end;
+        if (end > arena_bytes) {
+            atomicOr(&st->flags, (int)kBatchOverflow);
+        } else {
+            st->h_tab = reinterpret_cast<int64_t *>(arena + o_tab);
+            st->h_col = reinterpret_cast<int32_t *>(arena + o_col);
+            st->h_val = reinterpret_cast<double *>(arena + o_val);
+            st->h_leaf = reinterpret_cast<int32_t *>(arena + o_leaf);
+        }
+    }
+    if (end > arena_bytes) return;
+    int64_t *htab = reinterpret_cast<int64_t *>(arena + o_tab);
+    int64_t ce = 0, cf = 0;
+    for (int64_t b = 0; b < n; b += 1024) {
+        const int64_t i = b + tid;
+        int64_t e = 0, f = 0;
+        if (i < n) sizes(i, e, f);
+        int64_t te, tf;
+        const int64_t xe = Team<1024>::excl_scan(e, &te, scr, tid);
+        const int64_t xf = Team<1024>::excl_scan(f, &tf, scr, tid);
+        if (i < n) {
+            gstore(htab + 2 * i, ce + xe);
+            gstore(htab + 2 * i + 1, cf + xf);
+        }
+        ce += te;
+        cf += tf;
+    }
+}
+
+// the numeric pass of the heavy rows: one 512-thread workgroup merges a
+// whole row (LDS nodes, spilled nodes merged through HBM), as in the single
+// product
+template <typename IA, typename IB>
+__global__ __launch_bounds__(kBatchHeavyThreads, 4) void k_b_num_heavy(const BatchProb *tab, const int32_t *row_prob,
+                                                                       const int64_t *row_nprod,
+                                                                       const int32_t *class_rows, Ctl *ctl,
+                                                                       const BatchStatus *st, int lds_cap) {
+    constexpr int T = kBatchHeavyThreads;
+    constexpr int kCap = 4 * T;
+    if (ctl->count[kClassHeavy] == 0) return;  // no heavy row in this stage
+    constexpr size_t kUnion = sizeof(NumLds<T, kCap>) > sizeof(MergeLds<T>) ? sizeof(NumLds<T, kCap>)
+                                                                            : sizeof(MergeLds<T>);
+    __shared__ __align__(16) unsigned char raw[kUnion];
+    __shared__ HeavyState<T> hs;
+    auto &node_lds = *reinterpret_cast<NumLds<T, kCap> *>(raw);
+    auto &mrg = *reinterpret_cast<MergeLds<T> *>(raw);
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
+    const int tid = threadIdx.x;
+    const int64_t count = ctl->count[kClassHeavy];
+    const int64_t start = class_start(ctl, kClassHeavy);
+    const int64_t *htab = st->h_tab;
+    int32_t *hcol = st->h_col;
+    double *hval = st->h_val;
+    int32_t *hleaf = st->h_leaf;
+    NumOut no;
+    no.bound = 0;
+    for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int64_t g = class_rows[start + idx];
+        const BatchProb &tp = tab[row_prob[g]];
+        const int64_t row = g - wave_uniform(tp.row_off);
+        const void *a_rpt = tp.a_rpt;
+        const int64_t a0 = ld_rpt<IA>(a_rpt, row);
+        const int64_t L = wave_uniform(ld_rpt<IA>(a_rpt, row + 1) - a0);
+        const int64_t nprod = wave_uniform(gload(row_nprod + g));
+        const int64_t so = wave_uniform(gload(htab + 2 * idx)), lo = wave_uniform(gload(htab + 2 * idx + 1));
+        heavy_walk<IA, IB, T>(node_lds, mrg, hs, tid, row, 0, L, -1, nprod, hleaf + lo, hcol + so, hval + so,
+                              lds_cap, nullptr, a_rpt, direct_lists<IB>(tp.a_col, tp.b_rpt), tp.a_val, tp.b_col,
+                              tp.b_val, tp.c_rpt, tp.c_col, tp.c_val, ctl, no);
+    }
+}
+
 // caller-visible descriptors of the outputs (byte offsets into the arena)
 __global__ void k_b_describe(const BatchProb *all, int n, spg_batched_out *out, const BatchStatus *st) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -3845,7 +4019,7 @@ __global__ void k_b_describe(const BatchProb *all, int n, spg_batched_out *out, 
         spg_batched_out o;
         o.rows = p.rows;
         o.cols = p.ncols_b;
-        o.nnz = (st->flags & (kBatchOverflow | kBatchHeavyRow)) ? -1 : p.nnz;
+        o.nnz = (st->flags & (kBatchOverflow | kBatchRowProducts)) ? -1 : p.nnz;
         o.rpt_off = p.rpt_off;
         o.col_off = p.col_off;
         o.val_off = p.val_off;
@@ -3857,19 +4031,28 @@ __global__ void k_b_describe(const BatchProb *all, int n, spg_batched_out *out, 
 // earlier stage has already failed (overflow or heavy row) fixed for the
 // whole stage
 __global__ void k_b_stage_begin(Ctl *ctl, BatchStatus *st) {
+    // the previous stage's device errors are kept in the status
+    if (threadIdx.x == 0) st->err |= ctl->err;
+    __syncthreads();
     int64_t *p = reinterpret_cast<int64_t *>(ctl);
     const int n = (int)(sizeof(Ctl) / sizeof(int64_t));
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
     if (threadIdx.x == 0) st->skip = st->flags != 0;
 }
 
-__global__ void k_b_zero_status(BatchStatus *st) {
+__global__ void k_b_zero_status(BatchStatus *st, Ctl *ctl) {
     if (threadIdx.x == 0) {
         st->flags = 0;
         st->skip = 0;
         st->required = 0;
         st->arena_used = 0;
         st->nprod = 0;
+        st->err = 0;
+        st->h_tab = nullptr;
+        st->h_col = nullptr;
+        st->h_val = nullptr;
+        st->h_leaf = nullptr;
+        ctl->err = 0;
     }
 }
 
@@ -3913,9 +4096,13 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
                            (int)kClassGroup, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
         hipLaunchKernelGGL((k_b_sym_hash<1024, 1, 2 * kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,  \
                            (int)kClassBlock, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
+        hipLaunchKernelGGL((k_b_sym_bitmap<IA, IB>), dim3((unsigned)num_cu), dim3(kHeavyThreads), 0, s, tab,   \
+                           ws.row_prob, ws.class_rows, ws.row_size, ws.ctl);                                    \
         (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);                                        \
         hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes, \
                            bs.data_off, bs.status);                                                             \
+        hipLaunchKernelGGL(k_b_heavy_plan<IA>, dim3(1), dim3(1024), 0, s, tab, ws.row_prob, ws.row_nprod,        \
+                           ws.class_rows, ws.ctl, bs.status, bs.arena, bs.arena_bytes);                         \
         hipLaunchKernelGGL(k_b_rpt, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S, bs.status);                \
         hipLaunchKernelGGL((k_b_num_copy<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassCopy, tab, ro,  \
                            np, ws.class_rows, ws.ctl, bs.status);                                              \
@@ -3936,6 +4123,9 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
                            (int)kClassGroup, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                   \
         hipLaunchKernelGGL((k_b_num_lds<1024, 1, kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,       \
                            (int)kClassBlock, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                   \
+        hipLaunchKernelGGL((k_b_num_heavy<IA, IB>), dim3((unsigned)(2 * num_cu)), dim3(kBatchHeavyThreads), 0, \
+                           s, tab, ws.row_prob, ws.row_nprod, ws.class_rows, ws.ctl, bs.status,                 \
+                           bs.heavy_lds_cap);                                                                   \
     } while (0)
     if (bs.a_rpt_bytes == 4 && bs.b_rpt_bytes == 4) BRM_B_ALL(int32_t, int32_t);
     else if (bs.a_rpt_bytes == 4) BRM_B_ALL(int32_t, int64_t);
@@ -3945,8 +4135,8 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
     return hipGetLastError();
 }
 
-hipError_t launch_batched_begin(BatchStatus *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_b_zero_status, dim3(1), dim3(64), 0, s, st);
+hipError_t launch_batched_begin(BatchStatus *st, Ctl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_b_zero_status, dim3(1), dim3(64), 0, s, st, ctl);
     return hipGetLastError();
 }
 

@@ -148,25 +148,116 @@ def test_graph_replays_with_eager_work_between(handle):
     assert handle.stat(brm.STAT_GRAPH_LAUNCHES) >= 4
 
 
-def test_heavy_rows_rejected(handle):
-    A = synth.rmat(12, 16, 5)
-    dA = dev(A)
-    arena = torch.empty(1 << 26, dtype=torch.uint8, device="cuda")
-    rc, req, outs = handle.batched([(dA, dA)], arena)
-    assert rc == brm.SPG_ERR_CAPACITY and req == -1
+def run_until_fits(handle, problems, size, noalloc=False):
+    """Calls the batched product with growing arenas (each failed call
+    reports the need of the stages up to the first that did not fit)."""
+    for _ in range(4):
+        arena = torch.full((size,), 0x5A, dtype=torch.uint8, device="cuda")
+        rc, req, outs = handle.batched(problems, arena, noalloc=noalloc)
+        torch.cuda.synchronize()
+        if rc == brm.SPG_OK:
+            return outs, arena, req
+        assert rc == brm.SPG_ERR_CAPACITY and req > size
+        size = req
+    raise AssertionError("arena sizing did not converge")
+
+
+def host_csr(C):
+    rpt, col, val = to_host(C)
+    return synth.CSR(C.rows, C.cols, rpt, col, val)
 
 
 @pytest.mark.parametrize("noalloc", [False, True])
-def test_heavy_row_in_first_stage_of_a_chain(handle, noalloc):
-    # stage 1 holds a row beyond 4096 products: the call fails with
-    # required_bytes = -1, and the chained stage 2 (whose B would be stage
-    # 1's C) reads nothing
-    A = synth.rmat(11, 16, 6)
+def test_heavy_rows_in_a_batch(handle, noalloc):
+    # rows beyond 4096 products (R-MAT squares) beside light problems: the
+    # heavy rows take the bitmap count and the spill merge with their spill
+    # buffers in the arena; every output bitwise equal to Algorithm 1's model
+    print(f"case: batch with heavy rows, noalloc={noalloc}", flush=True)
+    mats = [synth.rmat(12, 16, 5), synth.erdos_renyi_rows(3000, 8, 7), synth.rmat(11, 16, 9),
+            synth.laplacian_2d_5pt(20)]
+    devs = [dev(M) for M in mats]
+    outs, arena, req = run_until_fits(handle, [(d, d) for d in devs], 1 << 16, noalloc=noalloc)
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    assert handle.stat(brm.STAT_CLASS_ROWS0 + 6) > 0  # heavy rows in the stage
+    for M, C in zip(mats, outs):
+        assert_matches_oracle(C, oracle.spgemm(M, M), oracle.brmerge(M, M))
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_heavy_rows_in_both_stages_of_a_chain(handle, noalloc):
+    # stage 1: C0 = A A with heavy rows; stage 2: A C0 (B is stage 1's
+    # output in the arena, 64-bit row pointers), heavier still
+    print(f"case: chained heavy stages, R-MAT scale 10, noalloc={noalloc}", flush=True)
+    A = synth.rmat(10, 16, 6)
     dA = dev(A)
-    arena = torch.full((1 << 24,), 0x5A, dtype=torch.uint8, device="cuda")
-    rc, req, outs = handle.batched([(dA, dA), (dA, 0)], arena, noalloc=noalloc)
+    outs, arena, req = run_until_fits(handle, [(dA, dA), (dA, 0)], 1 << 16, noalloc=noalloc)
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    assert handle.stat(brm.STAT_CLASS_ROWS0 + 6) > 0
+    C0 = host_csr(outs[0])
+    assert_matches_oracle(outs[0], oracle.spgemm(A, A), oracle.brmerge(A, A))
+    assert_matches_oracle(outs[1], oracle.spgemm(A, C0), oracle.brmerge(A, C0))
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_every_row_through_the_heavy_kernels(handle, noalloc):
+    # forced routing: every non-empty row of both Galerkin stages takes the
+    # heavy kernels (one list per row in stage 1, eight in stage 2)
+    handle.set_option(brm.OPT_FORCE_CLASS, 6)
+    inp = galerkin_inputs([4, 5, 6, 7])
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    probs = brm.Handle.galerkin_problems(triples)
+    outs, arena, req = run_until_fits(handle, probs, 1 << 16, noalloc=noalloc)
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    n = len(inp)
+    for (m, A, P, Pt), ap, g in zip(inp, outs[:n], outs[n:]):
+        ref_ap = oracle.spgemm(A, P)
+        apc = synth.CSR(A.rows, P.cols, ref_ap.rpt, ref_ap.col, ref_ap.val)
+        same_bits(to_host(ap), (ref_ap.rpt, ref_ap.col, ref_ap.val))  # integer values: exact
+        ref_g = oracle.spgemm(Pt, apc)
+        same_bits(to_host(g), (ref_g.rpt, ref_g.col, ref_g.val))
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_heavy_spill_counts_towards_required_bytes(handle, noalloc):
+    # the reported need includes the spill space: with it the call fits, one
+    # byte less fails and reports the same need
+    A = synth.rmat(11, 16, 9)
+    dA = dev(A)
+    probs = [(dA, dA)]
+    outs, arena, req = run_until_fits(handle, probs, 1 << 16, noalloc=noalloc)
+    ref = to_host(outs[0])
+    arena = torch.empty(req, dtype=torch.uint8, device="cuda")
+    rc, req2, outs = handle.batched(probs, arena, noalloc=noalloc)
+    torch.cuda.synchronize()
+    assert rc == brm.SPG_OK and req2 == req
+    same_bits(to_host(outs[0]), ref)
+    c = outs[0]
+    c_end = c.val.data_ptr() + 8 * c.nnz - arena.data_ptr()
+    assert req > c_end  # the spill space lies beyond C
+    arena = torch.empty(req - 1, dtype=torch.uint8, device="cuda")
+    rc, req3, outs = handle.batched(probs, arena, noalloc=noalloc)
+    torch.cuda.synchronize()
+    assert rc == brm.SPG_ERR_CAPACITY and req3 == req and outs is None
+
+
+def test_row_with_2_31_products_fails_the_batch(handle):
+    # one row of 2^20 entries, all in column 0, over a B row of 2049
+    # entries: 2^31 + 2^20 products.  The row goes to no kernel and the
+    # batch fails with required_bytes = -1 (validation off: the repeated
+    # column is the point of the input)
+    handle.set_option(brm.OPT_VALIDATE, 0)
+    K, blen = 1 << 20, 2049
+    A = brm.DeviceCSR(1, 1, torch.tensor([0, K], dtype=torch.int32, device="cuda"),
+                      torch.zeros(K, dtype=torch.int32, device="cuda"),
+                      torch.ones(K, dtype=torch.float64, device="cuda"))
+    B = brm.DeviceCSR(1, blen, torch.tensor([0, blen], dtype=torch.int32, device="cuda"),
+                      torch.arange(blen, dtype=torch.int32, device="cuda"),
+                      torch.ones(blen, dtype=torch.float64, device="cuda"))
+    arena = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    rc, req, outs = handle.batched([(A, B)], arena)
     torch.cuda.synchronize()
     assert rc == brm.SPG_ERR_CAPACITY and req == -1 and outs is None
+    assert b"2^31" in brm.library().spg_last_error(handle._h)
     # the handle serves a batch that fits afterwards
     inp = galerkin_inputs([5, 4])
     triples = [(dev(A_), dev(P), dev(Pt)) for _, A_, P, Pt in inp]

@@ -2,7 +2,8 @@
 batched product (workspace in the library's fixed scratch array, kernels
 launched directly): its outputs against spgemm_batched's (bitwise) and the
 oracle's, over two calls in a row whose second batch is smaller, and its
-errors (workspace beyond the scratch array, arena too small, heavy rows)."""
+errors (workspace beyond the scratch array, arena too small); batches with
+heavy rows, whose spill space lies in the arena."""
 import ctypes
 
 import numpy as np
@@ -126,7 +127,7 @@ def test_noalloc_rejects_workspace_beyond_scratch():
         h.close()
 
 
-def test_noalloc_arena_and_heavy_row_errors_match_batched():
+def test_noalloc_arena_errors_and_heavy_rows_match_batched():
     h = brm.Handle(0)
     try:
         inp, triples = galerkin_batch([8, 5], 3)
@@ -145,11 +146,17 @@ def test_noalloc_arena_and_heavy_row_errors_match_batched():
             assert (desc[:probs.n, 2] == -1).all()
             size = req1
         assert rc1 == brm.SPG_OK and attempt >= 1
+        # heavy rows (spill space in the arena): the same need and the same bits
         A = synth.rmat(12, 16, 5)
-        dA = dev(A)
-        arena = torch.empty(1 << 26, dtype=torch.uint8, device="cuda")
-        rc, req, _ = h.batched([(dA, dA)], arena, noalloc=True)
-        assert rc == brm.SPG_ERR_CAPACITY and req == -1
+        p2 = brm.BatchedProblems([(dev(A), dev(A))])
+        rc0, req0, _, _ = run(h, p2, 1 << 20, noalloc=False)
+        rc1, req1, _, _ = run(h, p2, 1 << 20, noalloc=True)
+        assert rc0 == rc1 == brm.SPG_ERR_CAPACITY and req0 == req1 > 1 << 20
+        rc0, req0, ref, _ = run(h, p2, req1, noalloc=False)
+        rc1, req1, outs, _ = run(h, p2, req1, noalloc=True)
+        assert rc0 == rc1 == brm.SPG_OK and req0 == req1
+        same_bits(to_host(outs[0]), to_host(ref[0]))
+        assert_matches_oracle(outs[0], oracle.spgemm(A, A), oracle.brmerge(A, A))
     finally:
         h.close()
 
