@@ -164,7 +164,8 @@ def time_plain(h, dA, dB, reps, warmup=1):
 
 def batched_extra(reps=10):
     """48 Galerkin products P^T (A P) (27-point cubes, edges U{16..64}, seed 4):
-    one graph-replayed batched call against 96 separate plain products."""
+    one graph-replayed batched call (the C call, problems marshalled once)
+    against 96 separate plain products."""
     import torch
     import synth
     import paper_2206_06611_amd as brm
@@ -176,14 +177,28 @@ def batched_extra(reps=10):
     h = brm.Handle(0)
     tune = autotune.tune_galerkin(h, triples)  # cached under the user's cache folder
     probs = h.galerkin_problems(triples)  # marshalled once
-    G, AP, arena = h.galerkin(triples, problems=probs)
-    torch.cuda.synchronize()
-    nprod = h.stat(brm.STAT_NPROD)
+    chosen = h.get_option(brm.OPT_BATCH_ALLOC)
+    desc = torch.empty((probs.n, 6), dtype=torch.int64, device=triples[0][0].rpt.device)
+    by_mode = {}
+    for mode in [m for m in (brm.BATCH_PRECISE, brm.BATCH_UPPER) if m != chosen] + [chosen]:
+        h.set_option(brm.OPT_BATCH_ALLOC, mode)  # the tuned options otherwise
+        G, AP, arena = h.galerkin(triples, problems=probs)  # sizes the arena, captures the graph
+        torch.cuda.synchronize()
+        nprod = h.stat(brm.STAT_NPROD)
+        t0 = time.perf_counter()
+        for _ in range(reps):  # the C call (blocking: it reads the batch status back)
+            rc, _, _ = h.batched(probs, arena, out=desc, views=False)
+        torch.cuda.synchronize()
+        if rc != brm.SPG_OK:
+            raise RuntimeError(f"batched call failed with status {rc}")
+        by_mode["upper" if mode == brm.BATCH_UPPER else "precise"] = (time.perf_counter() - t0) * 1e3 / reps
+    t_b = by_mode["upper" if chosen == brm.BATCH_UPPER else "precise"]
+    # the same through the Python helper, which also builds 96 output views
     t0 = time.perf_counter()
     for _ in range(reps):
         G, AP, arena = h.galerkin(triples, arena, problems=probs)
     torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) * 1e3 / reps
+    t_views = (time.perf_counter() - t0) * 1e3 / reps
     hp = brm.Handle(0)
     for A, P, Pt in triples:  # warm-up
         hp.spgemm(Pt, hp.spgemm(A, P))
@@ -202,7 +217,9 @@ def batched_extra(reps=10):
             "batched_gflops": round(2 * nprod / (t_b / 1e3) / 1e9, 3),
             "plain_gflops": round(2 * nprod / (t_p / 1e3) / 1e9, 3),
             "speedup_vs_plain": round(t_p / t_b, 3), "bitwise_equal_to_plain": bool(same),
-            "autotune": tune}
+            "stage_sizes_ms": {k: round(v, 4) for k, v in by_mode.items()},
+            "with_python_views_ms": round(t_views, 4),
+            "arena_bytes": int(arena.numel()), "autotune": tune}
 
 
 def laplace_throughput_extra(count=512, reps=20):
@@ -326,13 +343,17 @@ def amg_hierarchy_extra(reps=5):
     levels = [[(brm.DeviceCSR.from_host(P), brm.DeviceCSR.from_host(Pt)) for _, P, Pt in synth.amg_levels(n)]
               for n, _, _, _ in inp]
     h = brm.Handle(0)
-    out = h.amg_hierarchy(As, levels)  # warm-up, graph captures
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        out = h.amg_hierarchy(As, levels)
-    torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) * 1e3 / reps
+    by_mode = {}
+    for mode, name in ((brm.BATCH_PRECISE, "precise"), (brm.BATCH_UPPER, "upper")):
+        h.set_option(brm.OPT_BATCH_ALLOC, mode)
+        out = h.amg_hierarchy(As, levels)  # warm-up, graph captures
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = h.amg_hierarchy(As, levels)
+        torch.cuda.synchronize()
+        by_mode[name] = (time.perf_counter() - t0) * 1e3 / reps
+    t_b = min(by_mode.values())
 
     def plain():
         res = []
@@ -358,6 +379,7 @@ def amg_hierarchy_extra(reps=5):
     return {"workload": "48 aggregation hierarchies (27-point cubes, edges U{16..64}, seed 4) to edge 2",
             "levels": nlev, "products": 2 * sum(len(lv) for lv in levels),
             "batched_ms": round(t_b, 4), "plain_ms": round(t_p, 4), "speedup_vs_plain": round(t_p / t_b, 3),
+            "stage_sizes_ms": {k: round(v, 4) for k, v in by_mode.items()},
             "bitwise_equal_to_plain": bool(same)}
 
 
@@ -576,7 +598,7 @@ def main():
               "accumulators": accumulator_extra, "learned": learned_extra, "rmat20": rmat20_extra}[args.extra]
         res = fn()
         if isinstance(res, dict) and "autotune" in res:
-            res = {k: v for k, v in res.items() if k != "autotune"}
+            res = {**res, "autotune": {k: res["autotune"][k] for k in ("options", "tried") if k in res["autotune"]}}
         print(json.dumps({"extra": args.extra, "result": res}), flush=True)
         return
 

@@ -136,6 +136,9 @@ typedef enum {
                                     split).  0 (default): a quarter of a 512-thread workgroup's share
                                     of the batch, at least 2^18; -1: never split.  Results are
                                     bitwise the same */
+    SPG_OPT_BATCH_ALLOC = 17,    /* sizes of the batched stages (spgemm_batched[_noalloc]):
+                                    SPG_BATCH_PRECISE (default) or SPG_BATCH_UPPER, see below.
+                                    Results are bitwise the same */
     SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
                                     1 (default) one row per wavefront, merged in registers; the
                                     class then holds only rows whose lists fit power-of-two lane
@@ -147,6 +150,16 @@ typedef enum {
                                     windows of 2 to 16 registers per lane take the multi-register
                                     class (7) when B has at most 2^21 columns */
 } spg_option;
+
+/* Sizes of the batched stages (SPG_OPT_BATCH_ALLOC). */
+enum {
+    SPG_BATCH_PRECISE = 0, /* the symbolic pass of every class, then the numeric pass straight into C */
+    SPG_BATCH_UPPER = 1    /* the upper-bound method (Section II-B.2): every row gets a slot of nprod_i
+                              entries in the arena, the numeric pass runs into the slots (no symbolic
+                              pass), and the rows are then compacted into C.  A stage's arena need
+                              grows by 24 bytes per product (the slots, and room for C at its
+                              largest); the workspace by 16 bytes per row */
+};
 
 /* Allocation methods (SPG_OPT_ALLOC). */
 enum {
@@ -329,9 +342,9 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *problems, void *a
  * descriptors, status) is a fixed array of 64 MiB of device memory that the
  * library holds on every GPU it runs on until the process ends; the kernels
  * are launched one by one on `stream`.  A batch needs 29 bytes per row plus
- * 12 bytes per entry of A of its largest stage, plus about 600 bytes per
- * problem; a larger batch fails with SPG_ERR_SCRATCH before any launch (use
- * spgemm_batched for it).  Blocks until the batch is done, like
+ * 12 bytes per entry of A of its largest stage (16 more bytes per row with
+ * SPG_BATCH_UPPER), plus about 170 bytes per problem; a larger batch fails
+ * with SPG_ERR_SCRATCH before any launch (use spgemm_batched for it).  Blocks until the batch is done, like
  * spgemm_batched.
  * The array is shared by every call on one GPU, from any handle, and keeps
  * the last call's contents (the call clears what must start at zero): calls

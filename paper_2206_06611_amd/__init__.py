@@ -47,6 +47,9 @@ OPT_ACCUMULATOR = 13
 OPT_HEAVY_THREADS = 14
 OPT_HEAVY_SPLIT = 15
 OPT_LEARNED_HEAVY_MARGIN = 16
+OPT_BATCH_ALLOC = 17
+BATCH_PRECISE = 0
+BATCH_UPPER = 1
 ACC_BRMERGE = 0
 ACC_HASH = 1
 ALLOC_PRECISE = 0

@@ -1,28 +1,31 @@
-"""Autotuner of the batched path: bin thresholds (which kernel class a row
-goes to) and the size of the persistent launches, picked by timing graph
-replays of the caller's own batch.  Results are cached in a JSON file keyed by
-the device and a summary of the batch.  Outputs do not depend on the choice
-(the merge tree is fixed), which the tuner checks on every candidate."""
+"""Autotuner of the batched path: stage sizing (symbolic pass or upper-bound
+slots), the wave-small kernel, bin thresholds (which kernel class a row goes
+to) and the size of the persistent launches, picked by timing graph replays
+of the caller's own batch.  The search is coordinate-wise: starting from the
+handle's defaults, every option in turn takes each of its values with the
+others at their best so far, for two passes.  Results are cached in a JSON
+file keyed by the device and a summary of the batch.  Outputs do not depend
+on the choice (the merge tree is fixed), which the tuner checks on every
+candidate."""
 from __future__ import annotations
 
-import itertools
 import json
 import os
 
 import torch
 
-from . import (OPT_GRID_WAVES, OPT_GROUP_MAX, OPT_WAVE_MAX, OPT_WAVE_SMALL_MAX, Handle)
+from . import (OPT_BATCH_ALLOC, OPT_GRID_WAVES, OPT_GROUP_MAX, OPT_GROUP_ROWS, OPT_WAVE_MAX, OPT_WAVE_SMALL_MAX,
+               Handle)
 
 DEFAULT_CACHE = os.environ.get("BRMGPU_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "brmgpu", "autotune.json"))
 
-KEYS = {"wave_small_max": OPT_WAVE_SMALL_MAX, "wave_max": OPT_WAVE_MAX, "group_max": OPT_GROUP_MAX,
-        "grid_waves": OPT_GRID_WAVES}
+KEYS = {"batch_alloc": OPT_BATCH_ALLOC, "group_rows": OPT_GROUP_ROWS, "wave_small_max": OPT_WAVE_SMALL_MAX,
+        "wave_max": OPT_WAVE_MAX, "group_max": OPT_GROUP_MAX, "grid_waves": OPT_GRID_WAVES}
 
-
-def candidates():
-    for ws, w, g, gw in itertools.product((32, 64), (128, 256), (512, 1024), (0, 4096, 16384, 65536)):
-        yield {"wave_small_max": ws, "wave_max": w, "group_max": g, "grid_waves": gw}
+# the values each option may take (the first is the handle's default)
+SPACE = {"batch_alloc": (0, 1), "group_rows": (1, 2, 0), "wave_small_max": (64, 32), "wave_max": (256, 128),
+         "group_max": (1024, 512), "grid_waves": (0, 4096, 16384, 65536)}
 
 
 def apply(h: Handle, opts: dict):
@@ -66,23 +69,37 @@ def tune_galerkin(h: Handle, triples, arena=None, reps: int = 3, cache: str | No
     if key in table and not force:
         apply(h, table[key]["options"])
         return {**table[key], "cached": True}
-    best = None
     ref = None
-    tried = 0
-    for opts in candidates():
+    seen = {}
+
+    def trial(opts):
+        nonlocal arena, ref
+        key_ = tuple(sorted(opts.items()))
+        if key_ in seen:
+            return seen[key_]
         apply(h, opts)
         G, AP, arena = h.galerkin(triples, arena)  # capture
         torch.cuda.synchronize()
         ms, G, arena = _time_replays(h, triples, arena, reps)
-        tried += 1
         if ref is None:
             ref = [(g.col.clone(), g.val.clone()) for g in G]
         else:
             for (c, v), g in zip(ref, G):
                 if not (torch.equal(c, g.col) and torch.equal(v.view(torch.int64), g.val.view(torch.int64))):
                     raise RuntimeError(f"output changed with options {opts}")
-        if best is None or ms < best[1]:
-            best = (opts, ms)
+        seen[key_] = ms
+        return ms
+
+    cur = {k: v[0] for k, v in SPACE.items()}
+    best = (dict(cur), trial(cur))
+    for _ in range(2):
+        for k, values in SPACE.items():
+            for v in values:
+                cand = {**best[0], k: v}
+                ms = trial(cand)
+                if ms < best[1]:
+                    best = (cand, ms)
+    tried = len(seen)
     apply(h, best[0])
     entry = {"options": best[0], "ms": best[1], "tried": tried}
     if cache:

@@ -96,6 +96,7 @@ struct spg_handle_s {
     int64_t accumulator = 0;    // 0 BRMerge, 1 hash table (comparator)
     int64_t learned_force = 0;  // testing: 1 = every predicted row at its lower bound
     int64_t b_err = 0;                 // device errors of the last batched call
+    int64_t batch_alloc = SPG_BATCH_PRECISE;  // sizes of the batched stages: symbolic pass or upper bounds
     int64_t heavy_margin_milli = 200;  // extra margin (thousandths) of rows beyond one workgroup's LDS
     bool plan_learned = false;
     void *lw_mem = nullptr;     // per-row learned workspace
@@ -729,6 +730,11 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             if (value < 0 || value > 10000) return fail(h, SPG_ERR_ARG, "heavy margin must be 0..10000 (thousandths)");
             h->heavy_margin_milli = value;
             break;
+        case SPG_OPT_BATCH_ALLOC:
+            if (value != SPG_BATCH_PRECISE && value != SPG_BATCH_UPPER)
+                return fail(h, SPG_ERR_ARG, "batched allocation must be SPG_BATCH_PRECISE or SPG_BATCH_UPPER");
+            h->batch_alloc = value;
+            break;
         case SPG_OPT_LEARNED_FORCE:
             if (value != 0 && value != 1) return fail(h, SPG_ERR_ARG, "learned force must be 0 or 1");
             h->learned_force = value;
@@ -757,6 +763,7 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_GROUP_ROWS: *value = h->group_rows; break;
         case SPG_OPT_LEARNED_FORCE: *value = h->learned_force; break;
         case SPG_OPT_LEARNED_HEAVY_MARGIN: *value = h->heavy_margin_milli; break;
+        case SPG_OPT_BATCH_ALLOC: *value = h->batch_alloc; break;
         case SPG_OPT_ACCUMULATOR: *value = h->accumulator; break;
         default: return fail(h, SPG_ERR_ARG, "unknown option %d", key);
     }
@@ -1261,7 +1268,8 @@ struct BatchedPlan {
     int64_t rpt_end = 0, max_bcols = 0;
     // workspace layout: rows | S | row offsets | table | status | ctl | row problems | list descriptors
     size_t o_nprod, o_class, o_size, o_rows, o_tile, o_S, o_roff, o_tab, o_stat, o_ctl, o_prob, o_ebs, o_elen,
-        total;
+        o_S2, o_ovf, total;
+    bool upper = false;  // upper-bound slots (o_S2, o_ovf used)
 };
 
 int plan_batched(spg_handle h, int count, const spg_problem *probs, void *arena, int64_t arena_bytes,
@@ -1350,9 +1358,14 @@ int plan_batched(spg_handle h, int count, const spg_problem *probs, void *arena,
     pl->o_ctl = align_up(pl->o_stat + sizeof(BatchStatus), a);
     // the window kernels' inputs: the problem of every row, list descriptors
     pl->o_prob = align_up(pl->o_ctl + sizeof(Ctl), a);
+    // upper-bound slots: their offsets and the (never filled) overflow list
+    pl->upper = h->batch_alloc == SPG_BATCH_UPPER;
+    const size_t ub = pl->upper ? 1 : 0;
     pl->o_ebs = align_up(pl->o_prob + 4 * (size_t)max_rows, a);
     pl->o_elen = align_up(pl->o_ebs + 8 * (size_t)max_ents, a);
-    pl->total = align_up(pl->o_elen + 4 * (size_t)max_ents, a);
+    pl->o_S2 = align_up(pl->o_elen + 4 * (size_t)max_ents, a);
+    pl->o_ovf = align_up(pl->o_S2 + ub * 8 * (size_t)(max_rows + 1), a);
+    pl->total = align_up(pl->o_ovf + ub * 8 * (size_t)max_rows, a);
     return SPG_OK;
 }
 
@@ -1442,6 +1455,9 @@ hipError_t launch_batched_all(spg_handle h, const BatchedPlan &pl, const std::ve
         bs.data_off = pl.rpt_end;
         bs.status = d_stat;
         bs.heavy_lds_cap = (int)std::min<int64_t>(h->heavy_lds_max, 4 * (int64_t)kBatchHeavyThreads);
+        bs.upper = pl.upper ? 1 : 0;
+        bs.S2 = pl.upper ? reinterpret_cast<int64_t *>(base + pl.o_S2) : nullptr;
+        bs.ovf = pl.upper ? reinterpret_cast<int32_t *>(base + pl.o_ovf) : nullptr;
         e = launch_batched_stage(bs, ws, th, h->num_cu, h->grid_waves, s);
     }
     return e;
@@ -1527,7 +1543,7 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     }
     for (int64_t v : {(int64_t)reinterpret_cast<uintptr_t>(arena), arena_bytes, h->wave_small_max, h->wave_max,
                       h->group_max, h->group_rows,
-                      h->block_max, h->force, h->grid_waves, h->heavy_lds_max,
+                      h->block_max, h->force, h->grid_waves, h->heavy_lds_max, h->batch_alloc,
                       (int64_t)reinterpret_cast<uintptr_t>(h->b_mem)})
         sig.push_back(v);
     if (realloc || !h->graph_exec || sig != h->graph_sig) {
@@ -1579,7 +1595,8 @@ int spgemm_batched_noalloc(spg_handle h, int count, const spg_problem *probs, vo
     if (pl.total > (size_t)kNoAllocScratchBytes)
         return fail(h, SPG_ERR_SCRATCH,
                     "this batch needs %zu bytes of workspace; the allocation-free call has %lld "
-                    "(29 bytes per row and 12 per entry of A of the largest stage, plus the tables)",
+                    "(29 bytes per row and 12 per entry of A of the largest stage, 16 more per row with "
+                    "upper-bound slots, plus the tables)",
                     pl.total, (long long)kNoAllocScratchBytes);
     HIP_TRY(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);

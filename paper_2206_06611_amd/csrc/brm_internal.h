@@ -220,6 +220,10 @@ struct BatchStatus {
     int32_t *h_col;
     double *h_val;
     int32_t *h_leaf;
+    int64_t spill_base;  // arena offset where the current stage's heavy spill space may start
+    // the current stage's upper-bound slots (set when they fit)
+    int32_t *s_col;
+    double *s_val;
 };
 
 constexpr int kBatchHeavyThreads = 512;  // workgroup of the batched heavy-row merge
@@ -242,6 +246,10 @@ struct BatchStage {
     int64_t arena_bytes, data_off;
     BatchStatus *status;
     int heavy_lds_cap;   // largest list range of a heavy row merged in LDS
+    int upper;           // upper-bound slots instead of the symbolic pass
+    int64_t *S2;         // rows + 1: prefix sums of the slot sizes (upper)
+    int32_t *ovf;        // 2 * rows: overflow list of the bound-mode bookkeeping (upper; never filled,
+                         // a slot holds all of its row's products)
 };
 
 hipError_t launch_batched_begin(BatchStatus *st, Ctl *ctl, hipStream_t s);

@@ -286,6 +286,56 @@ __device__ __forceinline__ void window_row_reduce(int64_t eb, bool in, int64_t a
     }
 }
 
+// The windows of one wavefront's chunk of entries [e0, e1) (consecutive
+// rows), kAnaUnroll windows at a time: their columns, then B's row pointers
+// of all of them gathered together (the loads in flight at once) while the
+// next block's columns load, then each window's list descriptors stored and
+// its rows reduced in window order.
+constexpr int kAnaUnroll = 4;
+template <typename IB>
+__device__ __forceinline__ void analysis_windows(int64_t e0, int64_t e1, const int32_t *a_col, const IB *brp,
+                                                 IB *ent_bs, int32_t *ent_len, bool in, int64_t a0, int64_t a1,
+                                                 int32_t *flag, int lane, int64_t &np_r, int &mx_r) {
+    constexpr int U = kAnaUnroll;
+    int32_t k[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t e = e0 + u * kWave + lane;
+        k[u] = e < e1 ? gload(a_col + e) : 0;
+    }
+    for (int64_t eb = e0; eb < e1; eb += U * kWave) {
+        IB bs[U], be[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = eb + u * kWave + lane;
+            bs[u] = 0;
+            be[u] = 0;
+            if (e < e1) {
+                bs[u] = gload(brp + k[u]);
+                be[u] = gload(brp + k[u] + 1);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = eb + (U + u) * kWave + lane;
+            k[u] = e < e1 ? gload(a_col + e) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t wb = eb + u * kWave;
+            if (wb >= e1) break;  // uniform over the wavefront
+            const int64_t e = wb + lane;
+            const bool valid = e < e1;
+            const int64_t n = valid ? (int64_t)be[u] - (int64_t)bs[u] : 0;
+            if (valid) {
+                gstore(ent_bs + e, bs[u]);
+                gstore(ent_len + e, (int32_t)n);
+            }
+            window_row_reduce(wb, in, a0, a1, n, flag, lane, np_r, mx_r);
+        }
+    }
+}
+
 // first and last column of every row of B
 template <typename IB>
 __global__ __launch_bounds__(256) void k_row_ends(int64_t K, const IB *rpt, const int32_t *col, int4 *ends) {
@@ -400,27 +450,8 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
                 }
             }
         } else {
-            // pipelined: the next window's columns are loaded while this
-            // window's B row pointers are gathered and reduced
-            const IB *brp = reinterpret_cast<const IB *>(b_rpt);
-            int32_t k_next = e0 + lane < e1 ? a_col[e0 + lane] : 0;
-            for (int64_t eb = e0; eb < e1; eb += kWave) {
-                const int64_t e = eb + lane;
-                const bool valid = e < e1;
-                const int32_t k = k_next;
-                IB bs = 0, be = 0;
-                if (valid) {
-                    bs = brp[k];
-                    be = brp[k + 1];
-                }
-                if (e + kWave < e1) k_next = a_col[e + kWave];
-                const int64_t n = valid ? (int64_t)be - (int64_t)bs : 0;
-                if (valid) {
-                    ent_bs[e] = bs;
-                    ent_len[e] = (int32_t)n;
-                }
-                window_row_reduce(eb, in, a0, a1, n, s_flag[w], lane, np_r, mx_r);
-            }
+            analysis_windows<IB>(e0, e1, a_col, reinterpret_cast<const IB *>(b_rpt), ent_bs, ent_len, in, a0, a1,
+                                 s_flag[w], lane, np_r, mx_r);
         }
         if (in) {
             const int64_t np = np_r;
@@ -1651,7 +1682,7 @@ __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int6
                                                 const double *a_val,
                                                 const int32_t *b_col, const double *b_val,
                                                 const int64_t *c_rpt, int32_t *c_col,
-                                                double *c_val, Ctl *ctl, const NumOut &no) {
+                                                double *c_val, Ctl *ctl, const NumOut &no, int64_t id) {
     const int64_t a0 = ld_rpt<IA>(a_rpt, row);
     const int L = (int)(ld_rpt<IA>(a_rpt, row + 1) - a0);
     const int64_t cs = gload(c_rpt + (row));
@@ -1659,7 +1690,7 @@ __device__ __forceinline__ void brmerge_row_lds(NumLds<T, CAP> &s, int tid, int6
     const int rl = brmerge_range_lds<T, CAP, 1, IB>(s, tid, a0, L, lists, a_val, b_col, b_val,
                                                  c_col + cs, c_val + cs, cap);
     // Algorithm 1's final store went straight to C's row (truncated to the slot)
-    if (tid == 0) finish_row(no, ctl, row, rl, cap, false);
+    if (tid == 0) finish_row(no, ctl, id, rl, cap, false);
 }
 
 template <int T, int TEAMS, int CAP, typename IA, typename IB>
@@ -1677,7 +1708,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_num_lds(int cls, const void *a_rpt
          idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t row = class_rows[start + idx];
         brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, row, a_rpt, lists, a_val, b_col,
-                                        b_val, c_rpt, c_col, c_val, ctl, no);
+                                        b_val, c_rpt, c_col, c_val, ctl, no, row);
     }
 }
 
@@ -2474,8 +2505,8 @@ __device__ __forceinline__ void mw_rows(int cls, const void *a_rpt, const Lists<
             int ln = 0;
             double av = 0.0;
             if (lane < L) {
-                bs = ent_bs[e0 + lane];
-                ln = ent_len[e0 + lane];
+                bs = gload(ent_bs + e0 + lane);
+                ln = gload(ent_len + e0 + lane);
                 if constexpr (VALUES) av = gload(av_p + a0 + lane);
             }
             int64_t cs = 0;
@@ -3125,7 +3156,8 @@ struct HeavyBatch {
 // (res_slot < 0) ends in C; a subtree leaves its merged list in the row's
 // spill buffers (spill_col / spill_val: two buffers of nprod entries) and
 // its (buffer, length) in res[2 * res_slot].  leaf receives the row's list
-// offsets inside its product space.
+// offsets inside its product space.  `id` is the row's id for the
+// bound-mode bookkeeping.
 template <typename IA, typename IB, int T>
 __device__ __forceinline__ void heavy_walk(NumLds<T, 4 * T> &node_lds, MergeLds<T> &mrg, HeavyState<T> &st,
                                            int tid, int64_t row, int64_t lb0, int64_t lb1, int res_slot,
@@ -3133,7 +3165,7 @@ __device__ __forceinline__ void heavy_walk(NumLds<T, 4 * T> &node_lds, MergeLds<
                                            int lds_cap, int64_t *res, const void *a_rpt, const Lists<IB> &lists,
                                            const double *a_val, const int32_t *b_col, const double *b_val,
                                            const int64_t *c_rpt, int32_t *c_col, double *c_val, Ctl *ctl,
-                                           const NumOut &no) {
+                                           const NumOut &no, int64_t id) {
     constexpr int kCap = 4 * T;  // products (and lists) of an LDS node
     const bool whole = res_slot < 0;
     const int64_t a0 = ld_rpt<IA>(a_rpt, row);
@@ -3307,7 +3339,7 @@ __device__ __forceinline__ void heavy_walk(NumLds<T, 4 * T> &node_lds, MergeLds<
     }
     if (tid == 0) {
         if (whole) {
-            if (st.sp == 1) finish_row(no, ctl, row, st.stack[0].len, ccap, true);
+            if (st.sp == 1) finish_row(no, ctl, id, st.stack[0].len, ccap, true);
         } else {
             // a failed walk leaves an empty list in buffer 0 (the error bit is set)
             const bool ok = st.sp == 1;
@@ -3352,7 +3384,7 @@ __global__ __launch_bounds__(T, 4) void k_num_heavy(
         heavy_walk<IA, IB, T>(node_lds, mrg, st, tid, hb.rows[bi], lb0, lb1, res_slot, nprod,
                               hb.leaf + hb.leaf_off[bi], hb.spill_col + hb.spill_off[bi],
                               hb.spill_val + hb.spill_off[bi], hb.lds_cap, hb.res, a_rpt, lists, a_val, b_col,
-                              b_val, c_rpt, c_col, c_val, ctl, no);
+                              b_val, c_rpt, c_col, c_val, ctl, no, hb.rows[bi]);
     }
 }
 
@@ -3542,7 +3574,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
                                                     int64_t nchunks, Thresholds th, int64_t *row_nprod,
                                                     uint8_t *row_class, int32_t *row_size, Ctl *ctl,
                                                     BatchStatus *st, int32_t *row_prob, IB *ent_bs,
-                                                    int32_t *ent_len) {
+                                                    int32_t *ent_len, int upper) {
     constexpr int kW = 256 / kWave;
     __shared__ ProbLookup lk;
     __shared__ int64_t s_count[kNumClasses];
@@ -3566,8 +3598,8 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
     const bool skip = st->skip != 0;  // one value for the whole stage (set before this launch)
     for (int64_t c = (int64_t)blockIdx.x * kW + w; c < nchunks; c += (int64_t)gridDim.x * kW) {
         const int p = find_prob(lk, chunk_off, np, c);
-        // the problem's fields in registers once per chunk: the descriptor
-        // stores below could otherwise alias the table and force reloads
+        // the problem's fields in registers once per chunk: the stores below
+        // could otherwise alias the table and force reloads
         const BatchProb &tp = tab[p];
         struct {
             int64_t rows, row_off, ent_off;
@@ -3601,29 +3633,10 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         if (lane == nrows - 1) s_start[w][nrows] = a1;
         wave_sync();
         const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
-        const IB *b_rpt = reinterpret_cast<const IB *>(pr.b_rpt);
         int64_t np_r = 0;
         int mx_r = 0;
-        // pipelined: the next window's columns are loaded while this
-        // window's B row pointers are gathered and reduced
-        int32_t k_next = e0 + lane < e1 ? gload(pr.a_col + e0 + lane) : 0;
-        for (int64_t eb = e0; eb < e1; eb += kWave) {
-            const int64_t e = eb + lane;
-            const bool valid = e < e1;
-            const int32_t k = k_next;
-            IB bs = 0, be = 0;
-            if (valid) {
-                bs = gload(b_rpt + k);
-                be = gload(b_rpt + k + 1);
-            }
-            if (e + kWave < e1) k_next = gload(pr.a_col + e + kWave);
-            const int64_t n = valid ? (int64_t)be - (int64_t)bs : 0;
-            if (valid) {
-                ent_bs[pr.ent_off + e] = bs;
-                ent_len[pr.ent_off + e] = (int32_t)n;
-            }
-            window_row_reduce(eb, in, a0, a1, n, s_flag[w], lane, np_r, mx_r);
-        }
+        analysis_windows<IB>(e0, e1, pr.a_col, reinterpret_cast<const IB *>(pr.b_rpt), ent_bs + pr.ent_off,
+                             ent_len + pr.ent_off, in, a0, a1, s_flag[w], lane, np_r, mx_r);
         if (in) {
             const int64_t g = pr.row_off + i;
             const int64_t nprod = np_r;
@@ -3638,8 +3651,9 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
             row_nprod[g] = nprod;
             row_class[g] = (uint8_t)(cls | (sw << kClassBits));
             row_prob[g] = p;
+            // upper-bound slots: every row's slot holds its products
             if (cls == kClassEmpty) row_size[g] = 0;
-            if (cls == kClassCopy) row_size[g] = (int32_t)nprod;
+            else if (cls == kClassCopy || upper) row_size[g] = (int32_t)nprod;
 #pragma unroll
             for (int q = 0; q < kNumClasses; ++q) my_count[q] += (cls == q);
             my_nprod += nprod;
@@ -3711,11 +3725,13 @@ __global__ __launch_bounds__(1024) void k_b_distribute(BatchProb *tab, int np, c
             tab[p].val_off = o + ((4 * nnz + 255) / 256) * 256;
             tab[p].c_col = reinterpret_cast<int32_t *>(arena + o);
             tab[p].c_val = reinterpret_cast<double *>(arena + tab[p].val_off);
+            tab[p].c_rpt = reinterpret_cast<int64_t *>(arena + tab[p].rpt_off);  // (slots before, under upper bounds)
         }
         carry += tot;
     }
     if (threadIdx.x == 0) {
         st->arena_used = carry;
+        st->spill_base = carry;
         if (carry > arena_bytes) st->flags |= kBatchOverflow;
         if (carry > st->required) st->required = carry;
     }
@@ -3753,7 +3769,8 @@ __global__ void k_b_link(BatchProb *all, int first, int np) {
 
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *tab, const int64_t *row_off, int np,
-                                                    const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+                                                    const int32_t *class_rows, Ctl *ctl, const BatchStatus *st,
+                                                    NumOut no) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ ProbLookup lk;
     load_lookup(lk, row_off, np);
@@ -3762,8 +3779,6 @@ __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *ta
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    NumOut no;
-    no.bound = 0;
     for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; idx < count;
          idx += waves) {
         const int64_t g = class_rows[start + idx];
@@ -3776,7 +3791,7 @@ __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *ta
 template <int T, int TEAMS, int CAP, typename IA, typename IB>
 __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb *tab, const int64_t *row_off,
                                                         int np, const int32_t *class_rows, Ctl *ctl,
-                                                        const BatchStatus *st) {
+                                                        const BatchStatus *st, NumOut no) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ ProbLookup lk;
     __shared__ NumLds<T, CAP> lds[TEAMS];
@@ -3785,14 +3800,12 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb
     const int team = threadIdx.x / T, tid = threadIdx.x % T;
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
-    NumOut no;
-    no.bound = 0;
     for (int64_t idx = (int64_t)blockIdx.x * TEAMS + team; idx < count; idx += (int64_t)gridDim.x * TEAMS) {
         const int64_t g = class_rows[start + idx];
         const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
         brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt,
                                         direct_lists<IB>(pr.a_col, pr.b_rpt), pr.a_val, pr.b_col, pr.b_val,
-                                        pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
+                                        pr.c_rpt, pr.c_col, pr.c_val, ctl, no, g);
     }
 }
 
@@ -3801,7 +3814,8 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_num_win(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                    const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
-                                                   const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+                                                   const int32_t *class_rows, Ctl *ctl, const BatchStatus *st,
+                                                   NumOut no) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ uint32_t xk[4][kWave];
     __shared__ double xv[4][kWave];
@@ -3810,8 +3824,6 @@ __global__ __launch_bounds__(256) void k_b_num_win(int cls, const BatchProb *tab
     Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
     lists.ent_bs = ent_bs;
     lists.ent_len = ent_len;
-    NumOut no;
-    no.bound = 0;
     BatchRows br;
     br.tab = tab;
     br.row_prob = row_prob;
@@ -3842,7 +3854,8 @@ __global__ __launch_bounds__(256) void k_b_sym_win(int cls, const BatchProb *tab
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_b_num_mw(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                   const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
-                                                  const int32_t *class_rows, Ctl *ctl, const BatchStatus *st) {
+                                                  const int32_t *class_rows, Ctl *ctl, const BatchStatus *st,
+                                                  NumOut no) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
     __shared__ double vals[4][kMwSlots];
     if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
@@ -3850,8 +3863,6 @@ __global__ __launch_bounds__(256) void k_b_num_mw(int cls, const BatchProb *tab,
     Lists<IB> lists = direct_lists<IB>(nullptr, nullptr);
     lists.ent_bs = ent_bs;
     lists.ent_len = ent_len;
-    NumOut no;
-    no.bound = 0;
     BatchRows br;
     br.tab = tab;
     br.row_prob = row_prob;
@@ -3934,12 +3945,12 @@ __global__ __launch_bounds__(1024) void k_b_heavy_plan(const BatchProb *tab, con
     const int64_t E = Team<1024>::sum(e_sum, scr, tid);
     const int64_t F = Team<1024>::sum(f_sum, scr, tid);
     auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
-    const int64_t o_tab = al(st->arena_used);
+    const int64_t o_tab = al(st->spill_base);
     const int64_t o_col = o_tab + al(16 * n);
     const int64_t o_val = o_col + al(4 * E);
     const int64_t o_leaf = o_val + al(8 * E);
     const int64_t end = o_leaf + al(4 * F);
-    __syncthreads();  // every thread has read arena_used
+    __syncthreads();  // every thread has read spill_base
     if (tid == 0) {
         if (end > st->required) st->required = end;
         if (end > arena_bytes) {
@@ -3977,7 +3988,8 @@ template <typename IA, typename IB>
 __global__ __launch_bounds__(kBatchHeavyThreads, 4) void k_b_num_heavy(const BatchProb *tab, const int32_t *row_prob,
                                                                        const int64_t *row_nprod,
                                                                        const int32_t *class_rows, Ctl *ctl,
-                                                                       const BatchStatus *st, int lds_cap) {
+                                                                       const BatchStatus *st, int lds_cap,
+                                                                       NumOut no) {
     constexpr int T = kBatchHeavyThreads;
     constexpr int kCap = 4 * T;
     if (ctl->count[kClassHeavy] == 0) return;  // no heavy row in this stage
@@ -3995,8 +4007,6 @@ __global__ __launch_bounds__(kBatchHeavyThreads, 4) void k_b_num_heavy(const Bat
     int32_t *hcol = st->h_col;
     double *hval = st->h_val;
     int32_t *hleaf = st->h_leaf;
-    NumOut no;
-    no.bound = 0;
     for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int64_t g = class_rows[start + idx];
         const BatchProb &tp = tab[row_prob[g]];
@@ -4008,7 +4018,128 @@ __global__ __launch_bounds__(kBatchHeavyThreads, 4) void k_b_num_heavy(const Bat
         const int64_t so = wave_uniform(gload(htab + 2 * idx)), lo = wave_uniform(gload(htab + 2 * idx + 1));
         heavy_walk<IA, IB, T>(node_lds, mrg, hs, tid, row, 0, L, -1, nprod, hleaf + lo, hcol + so, hval + so,
                               lds_cap, nullptr, a_rpt, direct_lists<IB>(tp.a_col, tp.b_rpt), tp.a_val, tp.b_col,
-                              tp.b_val, tp.c_rpt, tp.c_col, tp.c_val, ctl, no);
+                              tp.b_val, tp.c_rpt, tp.c_col, tp.c_val, ctl, no, g);
+    }
+}
+
+// Upper-bound slots of a batched stage (every row's slot holds its
+// products; S2 is their prefix sum over the stage's rows): the region that
+// the stage's C may take at most (every problem's arrays at their largest,
+// from where the stage's C starts), then the slots' columns and values.
+// The numeric kernels then write into the slots through the problems' C
+// fields, and the compaction moves every row to C once its size is known.
+__global__ __launch_bounds__(1024) void k_b_slot_plan(BatchProb *tab, int np, int64_t *S2, int64_t R,
+                                                      BatchStatus *st, char *arena, int64_t arena_bytes,
+                                                      int64_t data_off) {
+    __shared__ int64_t scr[Team<1024>::kWaves + 1];
+    auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
+    const int64_t used = st->arena_used;
+    const int64_t base = al(used > data_off ? used : data_off);
+    int64_t cb = 0;
+    for (int p = threadIdx.x; p < np; p += 1024) {
+        const int64_t n = S2[tab[p].row_off + tab[p].rows] - S2[tab[p].row_off];
+        cb += al(4 * n) + al(8 * n);
+    }
+    const int64_t cbound = Team<1024>::sum(cb, scr, (int)threadIdx.x);
+    const int64_t total = S2[R];
+    const int64_t o_col = base + cbound;
+    const int64_t o_val = o_col + al(4 * total);
+    const int64_t end = o_val + al(8 * total);
+    __syncthreads();  // every thread has read arena_used
+    if (threadIdx.x == 0) {
+        if (end > st->required) st->required = end;
+        st->spill_base = end;  // heavy rows' spill space after the slots
+        if (end > arena_bytes) {
+            atomicOr(&st->flags, (int)kBatchOverflow);
+        } else {
+            st->s_col = reinterpret_cast<int32_t *>(arena + o_col);
+            st->s_val = reinterpret_cast<double *>(arena + o_val);
+        }
+    }
+    if (end > arena_bytes) return;
+    for (int p = threadIdx.x; p < np; p += 1024) {
+        tab[p].c_rpt = S2 + tab[p].row_off;
+        tab[p].c_col = reinterpret_cast<int32_t *>(arena + o_col);
+        tab[p].c_val = reinterpret_cast<double *>(arena + o_val);
+    }
+}
+
+// Compaction after upper-bound slots: the rows [g0, g0 + 256) of a
+// workgroup pass are consecutive in C (stage-wide offsets S) and in the
+// slots (S2); every thread takes every 256th entry of their C range and
+// finds its row by a search over the rows' first offsets in LDS.
+constexpr int kCompactUnroll = 8;
+__global__ __launch_bounds__(256) void k_b_compact(const BatchProb *tab, const int32_t *row_prob, const int64_t *S2,
+                                                   const int64_t *S, int64_t R, const BatchStatus *st) {
+    __shared__ int64_t c_beg[257];
+    __shared__ int64_t src[256], cap[256];  // slot offset and size of every row
+    __shared__ int64_t dcol[256], dval[256];  // addresses of the rows' first entries in C
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
+    const int32_t *scol = st->s_col;
+    const double *sval = st->s_val;
+    const int t = threadIdx.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * 256; g0 < R; g0 += (int64_t)gridDim.x * 256) {
+        const int n = R - g0 < 256 ? (int)(R - g0) : 256;
+        if (t < n) {
+            const int64_t g = g0 + t;
+            const BatchProb &pr = tab[row_prob[g]];
+            const int64_t cb = S[g];
+            const int64_t local = cb - S[pr.row_off];
+            c_beg[t] = cb;
+            src[t] = S2[g];
+            cap[t] = S2[g + 1] - S2[g];
+            dcol[t] = reinterpret_cast<int64_t>(pr.c_col + local);
+            dval[t] = reinterpret_cast<int64_t>(pr.c_val + local);
+        }
+        if (t == 0) c_beg[n] = S[g0 + n];
+        __syncthreads();
+        const int64_t q0 = c_beg[0], q1 = c_beg[n];
+        // kCompactUnroll entries per thread at a time, software-pipelined:
+        // the next block's loads are issued before this block's stores
+        int r[kCompactUnroll];
+        int64_t off[kCompactUnroll];
+        int32_t c[kCompactUnroll];
+        double v[kCompactUnroll];
+        auto load = [&](int64_t qb, int *rr, int64_t *oo, int32_t *cc, double *vv) {
+#pragma unroll
+            for (int u = 0; u < kCompactUnroll; ++u) {
+                const int64_t q = qb + u * 256 + t;
+                rr[u] = -1;
+                oo[u] = 0;
+                cc[u] = 0;
+                vv[u] = 0.0;
+                if (q < q1) {
+                    const int ru = upper_bound(c_beg, n, q) - 1;
+                    oo[u] = q - c_beg[ru];
+                    // (a row never outgrows its slot of all its products)
+                    if (oo[u] < cap[ru]) {
+                        rr[u] = ru;
+                        cc[u] = gload(scol + src[ru] + oo[u]);
+                        vv[u] = gload(sval + src[ru] + oo[u]);
+                    }
+                }
+            }
+        };
+        load(q0, r, off, c, v);
+        for (int64_t qb = q0; qb < q1; qb += 256 * kCompactUnroll) {
+            int nr[kCompactUnroll];
+            int64_t noff[kCompactUnroll];
+            int32_t nc[kCompactUnroll];
+            double nv[kCompactUnroll];
+            load(qb + 256 * kCompactUnroll, nr, noff, nc, nv);
+#pragma unroll
+            for (int u = 0; u < kCompactUnroll; ++u) {
+                if (r[u] >= 0) {
+                    gstore(reinterpret_cast<int32_t *>(dcol[r[u]]) + off[u], c[u]);
+                    gstore(reinterpret_cast<double *>(dval[r[u]]) + off[u], v[u]);
+                }
+                r[u] = nr[u];
+                off[u] = noff[u];
+                c[u] = nc[u];
+                v[u] = nv[u];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -4052,12 +4183,22 @@ __global__ void k_b_zero_status(BatchStatus *st, Ctl *ctl) {
         st->h_col = nullptr;
         st->h_val = nullptr;
         st->h_leaf = nullptr;
+        st->spill_base = 0;
+        st->s_col = nullptr;
+        st->s_val = nullptr;
         ctl->err = 0;
     }
 }
 
-hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const Thresholds &th, int num_cu,
-                                int64_t grid_waves, hipStream_t s) {
+// The launches of one batched stage.  Precise sizes: analysis, binning,
+// the symbolic pass of every class, scan, C's place in the arena (then the
+// heavy rows' spill space), row pointers, the numeric pass into C.  Upper
+// bounds: analysis (slot = products), binning, scan, slots in the arena
+// (then the spill space), the numeric pass into the slots, scan of the exact
+// sizes, C's place, row pointers, compaction.
+template <typename IA, typename IB>
+static void batched_stage_launches(const BatchStage &bs, const Workspace &ws, const Thresholds &th, int num_cu,
+                                   int64_t grid_waves, hipStream_t s) {
     const int np = bs.nprob;
     const int64_t R = bs.rows;
     const int64_t *ro = bs.row_off;
@@ -4065,73 +4206,95 @@ hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const
     const unsigned ga = (unsigned)(R > 0 ? ((R + 255) / 256 < 2048 ? (R + 255) / 256 : 2048) : 1);
     // the analysis: four chunks of 64 rows per workgroup pass
     const unsigned gc = (unsigned)(bs.chunks > 0 ? ((bs.chunks + 3) / 4 < 2048 ? (bs.chunks + 3) / 4 : 2048) : 1);
-    hipLaunchKernelGGL(k_b_stage_begin, dim3(1), dim3(64), 0, s, ws.ctl, bs.status);
-    if (bs.link) hipLaunchKernelGGL(k_b_link, dim3(1), dim3(256), 0, s, bs.all, bs.first, np);
     auto grid_for = [&](int per_cu, int waves_per_wg) {
         int64_t g = (int64_t)num_cu * per_cu;
         if (grid_waves > 0) g = grid_waves / waves_per_wg > 0 ? grid_waves / waves_per_wg : 1;
         return dim3((unsigned)g);
     };
-#define BRM_B_ALL(IA, IB)                                                                                       \
-    do {                                                                                                        \
-        hipLaunchKernelGGL((k_b_analysis<IA, IB>), dim3(gc), dim3(256), 0, s, tab, bs.chunk_off, np, bs.chunks,  \
-                           th, ws.row_nprod,                                                                    \
-                           ws.row_class, ws.row_size, ws.ctl, bs.status, ws.row_prob,                           \
-                           static_cast<IB *>(ws.ent_bs), ws.ent_len);                                           \
-        hipLaunchKernelGGL(k_bin, dim3(ga), dim3(256), 0, s, R, nullptr, ws.row_class, ws.class_rows, ws.ctl); \
-        if (th.windows)                                                                                         \
-            hipLaunchKernelGGL((k_b_sym_win<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall,   \
-                               tab, ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class, \
-                               ws.class_rows, ws.row_size, ws.ctl);                                             \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, \
-                               s, (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);       \
-        if (th.multi)                                                                                           \
-            hipLaunchKernelGGL((k_b_sym_mw<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassMulti, tab,   \
-                               ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class,      \
-                               ws.class_rows, ws.row_size, ws.ctl);                                             \
-        hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,       \
-                           (int)kClassWave, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                  \
-        hipLaunchKernelGGL((k_b_sym_hash<256, 1, 2 * kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,     \
-                           (int)kClassGroup, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
-        hipLaunchKernelGGL((k_b_sym_hash<1024, 1, 2 * kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,  \
-                           (int)kClassBlock, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);                 \
-        hipLaunchKernelGGL((k_b_sym_bitmap<IA, IB>), dim3((unsigned)num_cu), dim3(kHeavyThreads), 0, s, tab,   \
-                           ws.row_prob, ws.class_rows, ws.row_size, ws.ctl);                                    \
-        (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);                                        \
-        hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes, \
-                           bs.data_off, bs.status);                                                             \
-        hipLaunchKernelGGL(k_b_heavy_plan<IA>, dim3(1), dim3(1024), 0, s, tab, ws.row_prob, ws.row_nprod,        \
-                           ws.class_rows, ws.ctl, bs.status, bs.arena, bs.arena_bytes);                         \
-        hipLaunchKernelGGL(k_b_rpt, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S, bs.status);                \
-        hipLaunchKernelGGL((k_b_num_copy<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassCopy, tab, ro,  \
-                           np, ws.class_rows, ws.ctl, bs.status);                                              \
-        if (th.windows)                                                                                         \
-            hipLaunchKernelGGL((k_b_num_win<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall,   \
-                               tab, ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class, \
-                               ws.class_rows, ws.ctl, bs.status);                                               \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,   \
-                               (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.ctl, bs.status);           \
-        if (th.multi)                                                                                           \
-            hipLaunchKernelGGL((k_b_num_mw<IA, IB>), grid_for(5, 4), dim3(256), 0, s, (int)kClassMulti, tab,   \
-                               ws.row_prob, static_cast<const IB *>(ws.ent_bs), ws.ent_len, ws.row_class,      \
-                               ws.class_rows, ws.ctl, bs.status);                                               \
-        hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,            \
-                           (int)kClassWave, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                    \
-        hipLaunchKernelGGL((k_b_num_lds<256, 1, kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,          \
-                           (int)kClassGroup, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                   \
-        hipLaunchKernelGGL((k_b_num_lds<1024, 1, kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,       \
-                           (int)kClassBlock, tab, ro, np, ws.class_rows, ws.ctl, bs.status);                   \
-        hipLaunchKernelGGL((k_b_num_heavy<IA, IB>), dim3((unsigned)(2 * num_cu)), dim3(kBatchHeavyThreads), 0, \
-                           s, tab, ws.row_prob, ws.row_nprod, ws.class_rows, ws.ctl, bs.status,                 \
-                           bs.heavy_lds_cap);                                                                   \
-    } while (0)
-    if (bs.a_rpt_bytes == 4 && bs.b_rpt_bytes == 4) BRM_B_ALL(int32_t, int32_t);
-    else if (bs.a_rpt_bytes == 4) BRM_B_ALL(int32_t, int64_t);
-    else if (bs.b_rpt_bytes == 4) BRM_B_ALL(int64_t, int32_t);
-    else BRM_B_ALL(int64_t, int64_t);
-#undef BRM_B_ALL
+    const IB *ebs = static_cast<const IB *>(ws.ent_bs);
+    hipLaunchKernelGGL(k_b_stage_begin, dim3(1), dim3(64), 0, s, ws.ctl, bs.status);
+    if (bs.link) hipLaunchKernelGGL(k_b_link, dim3(1), dim3(256), 0, s, bs.all, bs.first, np);
+    hipLaunchKernelGGL((k_b_analysis<IA, IB>), dim3(gc), dim3(256), 0, s, tab, bs.chunk_off, np, bs.chunks, th,
+                       ws.row_nprod, ws.row_class, ws.row_size, ws.ctl, bs.status, ws.row_prob,
+                       static_cast<IB *>(ws.ent_bs), ws.ent_len, bs.upper);
+    hipLaunchKernelGGL(k_bin, dim3(ga), dim3(256), 0, s, R, nullptr, ws.row_class, ws.class_rows, ws.ctl);
+    NumOut no;
+    no.bound = 0;
+    no.row_size = nullptr;
+    no.ovf_rows = nullptr;
+    no.M = R;
+    if (!bs.upper) {
+        if (th.windows)
+            hipLaunchKernelGGL((k_b_sym_win<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall, tab,
+                               ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.row_size, ws.ctl);
+        else
+            hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,
+                               (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);
+        if (th.multi)
+            hipLaunchKernelGGL((k_b_sym_mw<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassMulti, tab,
+                               ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.row_size, ws.ctl);
+        hipLaunchKernelGGL((k_b_sym_hash<64, 4, 2 * kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s,
+                           (int)kClassWave, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);
+        hipLaunchKernelGGL((k_b_sym_hash<256, 1, 2 * kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,
+                           (int)kClassGroup, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);
+        hipLaunchKernelGGL((k_b_sym_hash<1024, 1, 2 * kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,
+                           (int)kClassBlock, tab, ro, np, ws.class_rows, ws.row_size, ws.ctl);
+        hipLaunchKernelGGL((k_b_sym_bitmap<IA, IB>), dim3((unsigned)num_cu), dim3(kHeavyThreads), 0, s, tab,
+                           ws.row_prob, ws.class_rows, ws.row_size, ws.ctl);
+        (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);
+        hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes,
+                           bs.data_off, bs.status);
+        hipLaunchKernelGGL(k_b_heavy_plan<IA>, dim3(1), dim3(1024), 0, s, tab, ws.row_prob, ws.row_nprod,
+                           ws.class_rows, ws.ctl, bs.status, bs.arena, bs.arena_bytes);
+        hipLaunchKernelGGL(k_b_rpt, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S, bs.status);
+    } else {
+        (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S2, &ws.ctl->nnz, s);
+        hipLaunchKernelGGL(k_b_slot_plan, dim3(1), dim3(1024), 0, s, tab, np, bs.S2, R, bs.status, bs.arena,
+                           bs.arena_bytes, bs.data_off);
+        hipLaunchKernelGGL(k_b_heavy_plan<IA>, dim3(1), dim3(1024), 0, s, tab, ws.row_prob, ws.row_nprod,
+                           ws.class_rows, ws.ctl, bs.status, bs.arena, bs.arena_bytes);
+        no.bound = 1;
+        no.row_size = ws.row_size;
+        no.ovf_rows = bs.ovf;
+    }
+    hipLaunchKernelGGL((k_b_num_copy<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassCopy, tab, ro, np,
+                       ws.class_rows, ws.ctl, bs.status, no);
+    if (th.windows)
+        hipLaunchKernelGGL((k_b_num_win<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall, tab,
+                           ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.ctl, bs.status, no);
+    else
+        hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,
+                           (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    if (th.multi)
+        hipLaunchKernelGGL((k_b_num_mw<IA, IB>), grid_for(5, 4), dim3(256), 0, s, (int)kClassMulti, tab,
+                           ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s, (int)kClassWave,
+                       tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_lds<256, 1, kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,
+                       (int)kClassGroup, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_lds<1024, 1, kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,
+                       (int)kClassBlock, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_heavy<IA, IB>), dim3((unsigned)(2 * num_cu)), dim3(kBatchHeavyThreads), 0, s, tab,
+                       ws.row_prob, ws.row_nprod, ws.class_rows, ws.ctl, bs.status, bs.heavy_lds_cap, no);
+    if (bs.upper) {
+        (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);
+        hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes,
+                           bs.data_off, bs.status);
+        hipLaunchKernelGGL(k_b_rpt, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S, bs.status);
+        hipLaunchKernelGGL(k_b_compact, dim3(ga), dim3(256), 0, s, tab, ws.row_prob, bs.S2, bs.S, R, bs.status);
+    }
+}
+
+hipError_t launch_batched_stage(const BatchStage &bs, const Workspace &ws, const Thresholds &th, int num_cu,
+                                int64_t grid_waves, hipStream_t s) {
+    if (bs.a_rpt_bytes == 4 && bs.b_rpt_bytes == 4)
+        batched_stage_launches<int32_t, int32_t>(bs, ws, th, num_cu, grid_waves, s);
+    else if (bs.a_rpt_bytes == 4)
+        batched_stage_launches<int32_t, int64_t>(bs, ws, th, num_cu, grid_waves, s);
+    else if (bs.b_rpt_bytes == 4)
+        batched_stage_launches<int64_t, int32_t>(bs, ws, th, num_cu, grid_waves, s);
+    else
+        batched_stage_launches<int64_t, int64_t>(bs, ws, th, num_cu, grid_waves, s);
     return hipGetLastError();
 }
 

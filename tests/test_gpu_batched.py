@@ -266,6 +266,101 @@ def test_row_with_2_31_products_fails_the_batch(handle):
         assert g.nnz == (3 * ((n + 1) // 2) - 2) ** 3
 
 
+def kernel_choice_inputs():
+    rng = np.random.default_rng(9)
+    host = []
+    for i in range(6):
+        M, K, N = (int(x) for x in rng.integers(50, 400, 3))
+        host.append((synth.random_csr(M, K, 0.04, 300 + i, empty_row_frac=0.1),
+                     synth.random_csr(K, N, 0.06, 400 + i)))
+    host.append((synth.stencil_3d_27pt(9), synth.stencil_3d_27pt(9)))  # rows of 27 lists of 27
+    host.append((synth.laplacian_2d_5pt(20), synth.laplacian_2d_5pt(20)))
+    return host
+
+
+def outputs_in_mode(handle, problems, mode, noalloc=False):
+    handle.set_option(brm.OPT_BATCH_ALLOC, mode)
+    try:
+        outs, arena, req = run_until_fits(handle, problems, 1 << 16, noalloc=noalloc)
+        assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+        return [to_host(C) for C in outs], req
+    finally:
+        handle.set_option(brm.OPT_BATCH_ALLOC, brm.BATCH_PRECISE)
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_upper_bound_stages_match_precise(handle, noalloc):
+    # upper-bound slots (numeric into slots, then compaction) against the
+    # symbolic pass: Galerkin chains, short rows of every light class, and a
+    # chain with heavy rows in both stages -- the same bits
+    print(f"case: batched upper-bound slots, noalloc={noalloc}", flush=True)
+    inp = galerkin_inputs([4, 5, 6, 7, 9])
+    gal = brm.Handle.galerkin_problems([(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp])
+    host = kernel_choice_inputs()
+    light = brm.BatchedProblems([(dev(A), dev(B)) for A, B in host])
+    R = synth.rmat(10, 16, 6)
+    dR = dev(R)
+    heavy = brm.BatchedProblems([(dR, dR), (dR, 0)])
+    for name, probs in (("galerkin", gal), ("light", light), ("heavy chain", heavy)):
+        x, req_p = outputs_in_mode(handle, probs, brm.BATCH_PRECISE, noalloc)
+        y, req_u = outputs_in_mode(handle, probs, brm.BATCH_UPPER, noalloc)
+        print(f"  {name}: arena {req_p} (precise), {req_u} (upper)", flush=True)
+        assert req_u > req_p
+        for a, b in zip(x, y):
+            same_bits(a, b)
+        if name == "light":
+            for (A, B), c in zip(host, y):
+                ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+                assert np.array_equal(c[0], ref.rpt) and np.array_equal(c[1], ref.col)
+                assert np.array_equal(c[2].view(np.int64), model.val.view(np.int64))
+
+
+@pytest.mark.parametrize("cls", [2, 3, 4, 5, 6, 7])
+def test_upper_bound_slots_in_every_class(handle, cls):
+    # every row forced into one class: its numeric kernel writes into the
+    # slots and records the rows' lengths
+    host = kernel_choice_inputs()[:6]
+    probs = brm.BatchedProblems([(dev(A), dev(B)) for A, B in host])
+    handle.set_option(brm.OPT_FORCE_CLASS, cls)
+    x, _ = outputs_in_mode(handle, probs, brm.BATCH_PRECISE)
+    y, _ = outputs_in_mode(handle, probs, brm.BATCH_UPPER)
+    for (A, B), a, b in zip(host, x, y):
+        same_bits(a, b)
+        ref = oracle.spgemm(A, B)
+        assert np.array_equal(b[0], ref.rpt) and np.array_equal(b[1], ref.col)
+
+
+def test_upper_bound_required_bytes_and_replays(handle):
+    # the reported need covers C at its largest and the slots: it fits, one
+    # byte less fails with the same need; graph replays with eager work
+    # between give the first replay's bits
+    inp = galerkin_inputs([5, 8, 6])
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    probs = brm.Handle.galerkin_problems(triples)
+    handle.set_option(brm.OPT_BATCH_ALLOC, brm.BATCH_UPPER)
+    outs, arena, req = run_until_fits(handle, probs, 1 << 16)
+    ref = [to_host(C) for C in outs]
+    arena = torch.empty(req - 1, dtype=torch.uint8, device="cuda")
+    rc, req2, outs = handle.batched(probs, arena)
+    torch.cuda.synchronize()
+    assert rc == brm.SPG_ERR_CAPACITY and req2 == req and outs is None
+    arena = torch.empty(req, dtype=torch.uint8, device="cuda")
+    caps = handle.stat(brm.STAT_GRAPH_CAPTURES)
+    other = dev(synth.erdos_renyi_rows(5000, 8, 3))
+    for it in range(4):
+        eager = handle.spgemm(other, other)
+        torch.cuda.synchronize()
+        rc, req3, outs = handle.batched(probs, arena)
+        torch.cuda.synchronize()
+        assert rc == brm.SPG_OK and req3 == req
+        for C, r in zip(outs, ref):
+            same_bits(to_host(C), r)
+        assert eager.nnz > 0
+    assert handle.stat(brm.STAT_GRAPH_CAPTURES) == caps + 1
+    for (n, A, P, Pt), g in zip(inp, outs[len(inp):]):
+        assert g.nnz == (3 * ((n + 1) // 2) - 2) ** 3
+
+
 def test_config4_full_batch(handle):
     print("case: 48 Galerkin products, cube edges U{16..64}, seed 4", flush=True)
     inp = synth.amg_batch(48, 4)
@@ -290,14 +385,7 @@ def test_kernel_choices_agree_in_batches(handle):
     # short rows under lane windows (one and several registers per lane) and
     # in LDS give the same bits; the window kernels take every row's arrays
     # from its own problem
-    rng = np.random.default_rng(9)
-    host = []
-    for i in range(6):
-        M, K, N = (int(x) for x in rng.integers(50, 400, 3))
-        host.append((synth.random_csr(M, K, 0.04, 300 + i, empty_row_frac=0.1),
-                     synth.random_csr(K, N, 0.06, 400 + i)))
-    host.append((synth.stencil_3d_27pt(9), synth.stencil_3d_27pt(9)))  # rows of 27 lists of 27
-    host.append((synth.laplacian_2d_5pt(20), synth.laplacian_2d_5pt(20)))
+    host = kernel_choice_inputs()
     dp = [(dev(A), dev(B)) for A, B in host]
     outs, classes = {}, {}
     try:
@@ -343,3 +431,33 @@ def test_amg_hierarchy(handle):
             m = (e + 1) // 2
             assert g.rows == m ** 3 and g.nnz == (3 * m - 2) ** 3
             A = synth.CSR(g.rows, g.cols, ref.rpt, ref.col, ref.val)
+
+
+def test_autotuner_search_and_cache(tmp_path):
+    # the coordinate search times every candidate on the caller's batch,
+    # checks that none changes the output, keeps the best on the handle, and
+    # answers from its cache the second time
+    from paper_2206_06611_amd import autotune
+    inp = galerkin_inputs([6, 8, 5])
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    cache = str(tmp_path / "tune.json")
+    h = brm.Handle(0)
+    try:
+        res = autotune.tune_galerkin(h, triples, reps=1, cache=cache)
+        assert not res["cached"] and res["tried"] >= 10
+        for k, v in res["options"].items():
+            assert v in autotune.SPACE[k]
+            assert h.get_option(autotune.KEYS[k]) == v
+        G, _, _ = h.galerkin(triples)
+        for (n, A, P, Pt), g in zip(inp, G):
+            ref_ap = oracle.spgemm(A, P)
+            ref_g = oracle.spgemm(Pt, synth.CSR(A.rows, P.cols, ref_ap.rpt, ref_ap.col, ref_ap.val))
+            same_bits(to_host(g), (ref_g.rpt, ref_g.col, ref_g.val))
+    finally:
+        h.close()
+    h2 = brm.Handle(0)
+    try:
+        res2 = autotune.tune_galerkin(h2, triples, reps=1, cache=cache)
+        assert res2["cached"] and res2["options"] == res["options"]
+    finally:
+        h2.close()
