@@ -1944,24 +1944,21 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
         // window width (log2) and padded total (0 beyond the chunk)
         int64_t m_row = 0, m_a0 = 0, m_cs = 0;
         int m_L = 0, m_sw = 0, m_T = 0, m_cap = 0;
-        // batched: the row's problem (first descriptor, operand and output arrays)
-        int64_t m_eo = 0, m_aval = 0, m_bcol = 0, m_bval = 0, m_ccol = 0, m_cval = 0;
+        // batched: the row's problem (its arrays are read through the scalar
+        // cache when an item needs them: one register per lane instead of
+        // twelve)
+        int m_prob = 0;
         if (lane < n) {
             m_row = class_rows[start + base + lane];
             const void *rpt = a_rpt;
             const int64_t *crpt = c_rpt;
             int64_t r = m_row;
             if constexpr (BATCH) {
-                const BatchProb &pr = br.tab[br.row_prob[m_row]];
+                m_prob = br.row_prob[m_row];
+                const BatchProb &pr = br.tab[m_prob];
                 rpt = pr.a_rpt;
                 crpt = pr.c_rpt;
                 r = m_row - pr.row_off;
-                m_eo = pr.ent_off;
-                m_aval = reinterpret_cast<int64_t>(pr.a_val);
-                m_bcol = reinterpret_cast<int64_t>(pr.b_col);
-                m_bval = reinterpret_cast<int64_t>(pr.b_val);
-                m_ccol = reinterpret_cast<int64_t>(pr.c_col);
-                m_cval = reinterpret_cast<int64_t>(pr.c_val);
             }
             m_a0 = ld_rpt<IA>(rpt, r);
             m_L = (int)(ld_rpt<IA>(rpt, r + 1) - m_a0);
@@ -1996,7 +1993,8 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     // slot mode: exact length kept; an overflowing row is
                     // listed for the fallback once per chunk (below)
                     if (lane == 0) no.row_size[row] = len;
-                    if (len > cap) ovf_mask |= 1ull << j;
+                    // (batched slots are upper bounds: no row outgrows its slot)
+                    if (!BATCH && len > cap) ovf_mask |= 1ull << j;
                 } else if (lane == 0 && len != cap) {
                     atomicOr(reinterpret_cast<unsigned long long *>(&ctl->err), (unsigned long long)kErrSizeMismatch);
                 }
@@ -2022,6 +2020,23 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             };
             // a per-row value for the lane's row; rows missing from a pair
             // read row a's (every use of them is masked by their list count)
+            // batched: a field of the problem of row a (of row b in the upper
+            // half of a pair), by scalar loads (the problem indices are
+            // uniform; the table does not change during the launch)
+            auto pick = [&](int a, int b, auto get) -> int64_t {
+                using CP = const __attribute__((address_space(4))) BatchProb *;
+                const CP ctab = (CP)br.tab;
+                const int pa = lane_value(m_prob, a);
+                const int64_t xa = get(ctab[pa]);
+                if constexpr (!P) {
+                    return xa;
+                } else {
+                    const int pb = lane_value(m_prob, b >= 0 ? b : a);
+                    if (pb == pa) return xa;
+                    const int64_t xb = get(ctab[pb]);
+                    return lane >= kHalf ? xb : xa;
+                }
+            };
             auto sel64 = [&](int64_t m, int a, int b) -> int64_t {
                 if constexpr (!P) {
                     return lane_value(m, a);
@@ -2052,12 +2067,15 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                 item(v, a, b);
                 const int t = P ? (lane & (kHalf - 1)) : lane;
                 const int64_t p = sel64(m_a0, a, b) + t;
-                const int64_t pe = BATCH ? sel64(m_eo, a, b) + p : p;
+                const int64_t pe = BATCH ? pick(a, b, [](const auto &q) { return q.ent_off; }) + p : p;
                 const bool ok = t < lists_of(v, a, b);
                 bs = load_opaque(ok ? ent_bs + pe : reinterpret_cast<const IB *>(&g_zeros[0]));
                 ln = load_opaque(ok ? ent_len + pe : reinterpret_cast<const int32_t *>(&g_zeros[0]));
                 if constexpr (VALUES) {
-                    const double *av_p = BATCH ? reinterpret_cast<const double *>(sel64(m_aval, a, b)) : a_val;
+                    const double *av_p =
+                        BATCH ? reinterpret_cast<const double *>(
+                                    pick(a, b, [](const auto &q) { return reinterpret_cast<int64_t>(q.a_val); }))
+                              : a_val;
                     av = load_opaque(ok ? av_p + p : reinterpret_cast<const double *>(&g_zeros[0]));
                 }
             };
@@ -2078,11 +2096,17 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                 lav = 0.0;
                 if constexpr (VALUES) lav = __shfl(av, src, kWave);
                 const bool ok = li < L && o < lln;
-                const int32_t *bc = BATCH ? reinterpret_cast<const int32_t *>(sel64(m_bcol, a, b)) : b_col;
+                const int32_t *bc =
+                    BATCH ? reinterpret_cast<const int32_t *>(
+                                pick(a, b, [](const auto &q) { return reinterpret_cast<int64_t>(q.b_col); }))
+                          : b_col;
                 c = load_opaque(ok ? bc + (lbs + o) : &g_empty_col[0]);
                 bv = 0.0;
                 if constexpr (VALUES) {
-                    const double *bvp = BATCH ? reinterpret_cast<const double *>(sel64(m_bval, a, b)) : b_val;
+                    const double *bvp =
+                        BATCH ? reinterpret_cast<const double *>(
+                                    pick(a, b, [](const auto &q) { return reinterpret_cast<int64_t>(q.b_val); }))
+                              : b_val;
                     bv = load_opaque(ok ? bvp + (lbs + o) : reinterpret_cast<const double *>(&g_zeros[0]));
                 }
             };
@@ -2138,8 +2162,10 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     int32_t *cc = c_col;
                     double *cv = c_val;
                     if constexpr (BATCH) {
-                        cc = reinterpret_cast<int32_t *>(sel64(m_ccol, a, b));
-                        cv = reinterpret_cast<double *>(sel64(m_cval, a, b));
+                        cc = reinterpret_cast<int32_t *>(
+                            pick(a, b, [](const auto &q) { return reinterpret_cast<int64_t>(q.c_col); }));
+                        cv = reinterpret_cast<double *>(
+                            pick(a, b, [](const auto &q) { return reinterpret_cast<int64_t>(q.c_val); }));
                     }
                     if (live && pos < cap) {
                         gstore(cc + cs + pos, (int32_t)(k >> kKeyLaneBits));
@@ -2181,7 +2207,7 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
         };
         if (all_small) run(std::true_type{});
         else run(std::false_type{});
-        if constexpr (VALUES) {
+        if constexpr (VALUES && !BATCH) {
             if (ovf_mask) {
                 // one reservation for the chunk's overflowing rows (light rows
                 // fill the list from its end)
@@ -3767,11 +3793,16 @@ __global__ void k_b_link(BatchProb *all, int first, int np) {
     }
 }
 
-template <typename IA, typename IB>
+// SLOT (every batched numeric kernel): C's rows are upper-bound slots whose
+// exact lengths are recorded (a compile-time choice: the bookkeeping of the
+// other mode costs the kernel nothing)
+template <typename IA, typename IB, bool SLOT>
 __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *tab, const int64_t *row_off, int np,
                                                     const int32_t *class_rows, Ctl *ctl, const BatchStatus *st,
-                                                    NumOut no) {
+                                                    NumOut no_in) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
+    NumOut no = no_in;
+    no.bound = SLOT ? 1 : 0;
     __shared__ ProbLookup lk;
     load_lookup(lk, row_off, np);
     if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
@@ -3788,11 +3819,13 @@ __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *ta
     }
 }
 
-template <int T, int TEAMS, int CAP, typename IA, typename IB>
+template <int T, int TEAMS, int CAP, typename IA, typename IB, bool SLOT>
 __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb *tab, const int64_t *row_off,
                                                         int np, const int32_t *class_rows, Ctl *ctl,
-                                                        const BatchStatus *st, NumOut no) {
+                                                        const BatchStatus *st, NumOut no_in) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
+    NumOut no = no_in;
+    no.bound = SLOT ? 1 : 0;
     __shared__ ProbLookup lk;
     __shared__ NumLds<T, CAP> lds[TEAMS];
     load_lookup(lk, row_off, np);
@@ -3811,12 +3844,14 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb
 
 // the window kernels over a batched stage's rows (lists from the analysis's
 // descriptors, every row's arrays from its problem)
-template <typename IA, typename IB>
+template <typename IA, typename IB, bool SLOT>
 __global__ __launch_bounds__(256) void k_b_num_win(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                    const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
                                                    const int32_t *class_rows, Ctl *ctl, const BatchStatus *st,
-                                                   NumOut no) {
+                                                   NumOut no_in) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
+    NumOut no = no_in;
+    no.bound = SLOT ? 1 : 0;
     __shared__ uint32_t xk[4][kWave];
     __shared__ double xv[4][kWave];
     if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
@@ -3851,12 +3886,14 @@ __global__ __launch_bounds__(256) void k_b_sym_win(int cls, const BatchProb *tab
                                            (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4, br);
 }
 
-template <typename IA, typename IB>
+template <typename IA, typename IB, bool SLOT>
 __global__ __launch_bounds__(256) void k_b_num_mw(int cls, const BatchProb *tab, const int32_t *row_prob,
                                                   const IB *ent_bs, const int32_t *ent_len, const uint8_t *row_class,
                                                   const int32_t *class_rows, Ctl *ctl, const BatchStatus *st,
-                                                  NumOut no) {
+                                                  NumOut no_in) {
     if (ctl->count[cls] == 0) return;  // an empty class: nothing to load or do
+    NumOut no = no_in;
+    no.bound = SLOT ? 1 : 0;
     __shared__ double vals[4][kMwSlots];
     if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
     const int team = wave_uniform((int)(threadIdx.x / kWave));
@@ -3984,15 +4021,17 @@ __global__ __launch_bounds__(1024) void k_b_heavy_plan(const BatchProb *tab, con
 // the numeric pass of the heavy rows: one 512-thread workgroup merges a
 // whole row (LDS nodes, spilled nodes merged through HBM), as in the single
 // product
-template <typename IA, typename IB>
+template <typename IA, typename IB, bool SLOT>
 __global__ __launch_bounds__(kBatchHeavyThreads, 4) void k_b_num_heavy(const BatchProb *tab, const int32_t *row_prob,
                                                                        const int64_t *row_nprod,
                                                                        const int32_t *class_rows, Ctl *ctl,
                                                                        const BatchStatus *st, int lds_cap,
-                                                                       NumOut no) {
+                                                                       NumOut no_in) {
     constexpr int T = kBatchHeavyThreads;
     constexpr int kCap = 4 * T;
     if (ctl->count[kClassHeavy] == 0) return;  // no heavy row in this stage
+    NumOut no = no_in;
+    no.bound = SLOT ? 1 : 0;
     constexpr size_t kUnion = sizeof(NumLds<T, kCap>) > sizeof(MergeLds<T>) ? sizeof(NumLds<T, kCap>)
                                                                             : sizeof(MergeLds<T>);
     __shared__ __align__(16) unsigned char raw[kUnion];
@@ -4190,6 +4229,35 @@ __global__ void k_b_zero_status(BatchStatus *st, Ctl *ctl) {
     }
 }
 
+// the numeric launches of a batched stage (every class; empty classes return at once)
+template <typename IA, typename IB, bool SLOT, typename G>
+static void batched_numeric_launches(const BatchStage &bs, const Workspace &ws, const Thresholds &th,
+                                     const NumOut &no, G &&grid_for, int num_cu, hipStream_t s) {
+    const int np = bs.nprob;
+    const int64_t *ro = bs.row_off;
+    BatchProb *tab = bs.tab;
+    const IB *ebs = static_cast<const IB *>(ws.ent_bs);
+    hipLaunchKernelGGL((k_b_num_copy<IA, IB, SLOT>), grid_for(8, 4), dim3(256), 0, s, (int)kClassCopy, tab, ro, np,
+                       ws.class_rows, ws.ctl, bs.status, no);
+    if (th.windows)
+        hipLaunchKernelGGL((k_b_num_win<IA, IB, SLOT>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall, tab,
+                           ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.ctl, bs.status, no);
+    else
+        hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWaveSmall, IA, IB, SLOT>), grid_for(8, 4), dim3(256), 0, s,
+                           (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    if (th.multi)
+        hipLaunchKernelGGL((k_b_num_mw<IA, IB, SLOT>), grid_for(5, 4), dim3(256), 0, s, (int)kClassMulti, tab,
+                           ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWave, IA, IB, SLOT>), grid_for(4, 4), dim3(256), 0, s, (int)kClassWave,
+                       tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_lds<256, 1, kCapGroup, IA, IB, SLOT>), grid_for(4, 4), dim3(256), 0, s,
+                       (int)kClassGroup, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_lds<1024, 1, kCapBlock, IA, IB, SLOT>), grid_for(1, 16), dim3(1024), 0, s,
+                       (int)kClassBlock, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
+    hipLaunchKernelGGL((k_b_num_heavy<IA, IB, SLOT>), dim3((unsigned)(2 * num_cu)), dim3(kBatchHeavyThreads), 0, s, tab,
+                       ws.row_prob, ws.row_nprod, ws.class_rows, ws.ctl, bs.status, bs.heavy_lds_cap, no);
+}
+
 // The launches of one batched stage.  Precise sizes: analysis, binning,
 // the symbolic pass of every class, scan, C's place in the arena (then the
 // heavy rows' spill space), row pointers, the numeric pass into C.  Upper
@@ -4257,25 +4325,8 @@ static void batched_stage_launches(const BatchStage &bs, const Workspace &ws, co
         no.row_size = ws.row_size;
         no.ovf_rows = bs.ovf;
     }
-    hipLaunchKernelGGL((k_b_num_copy<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassCopy, tab, ro, np,
-                       ws.class_rows, ws.ctl, bs.status, no);
-    if (th.windows)
-        hipLaunchKernelGGL((k_b_num_win<IA, IB>), grid_for(8, 4), dim3(256), 0, s, (int)kClassWaveSmall, tab,
-                           ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.ctl, bs.status, no);
-    else
-        hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWaveSmall, IA, IB>), grid_for(8, 4), dim3(256), 0, s,
-                           (int)kClassWaveSmall, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
-    if (th.multi)
-        hipLaunchKernelGGL((k_b_num_mw<IA, IB>), grid_for(5, 4), dim3(256), 0, s, (int)kClassMulti, tab,
-                           ws.row_prob, ebs, ws.ent_len, ws.row_class, ws.class_rows, ws.ctl, bs.status, no);
-    hipLaunchKernelGGL((k_b_num_lds<64, 4, kCapWave, IA, IB>), grid_for(4, 4), dim3(256), 0, s, (int)kClassWave,
-                       tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
-    hipLaunchKernelGGL((k_b_num_lds<256, 1, kCapGroup, IA, IB>), grid_for(4, 4), dim3(256), 0, s,
-                       (int)kClassGroup, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
-    hipLaunchKernelGGL((k_b_num_lds<1024, 1, kCapBlock, IA, IB>), grid_for(1, 16), dim3(1024), 0, s,
-                       (int)kClassBlock, tab, ro, np, ws.class_rows, ws.ctl, bs.status, no);
-    hipLaunchKernelGGL((k_b_num_heavy<IA, IB>), dim3((unsigned)(2 * num_cu)), dim3(kBatchHeavyThreads), 0, s, tab,
-                       ws.row_prob, ws.row_nprod, ws.class_rows, ws.ctl, bs.status, bs.heavy_lds_cap, no);
+    if (bs.upper) batched_numeric_launches<IA, IB, true>(bs, ws, th, no, grid_for, num_cu, s);
+    else batched_numeric_launches<IA, IB, false>(bs, ws, th, no, grid_for, num_cu, s);
     if (bs.upper) {
         (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);
         hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes,
