@@ -1940,9 +1940,11 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
     for (int64_t ch = first; ch < nchunks; ch += stride) {
         const int64_t base = ch * kWave;
         const int n = (int)(count - base < kWave ? count - base : kWave);
-        // chunk meta data, one row per lane: row, first entry of A, lists,
-        // window width (log2) and padded total (0 beyond the chunk)
-        int64_t m_row = 0, m_a0 = 0, m_cs = 0;
+        // chunk meta data, one row per lane: row (row ids fit 31 bits), first
+        // entry of A, lists, window width (log2) and padded total (0 beyond
+        // the chunk)
+        int32_t m_row = 0;
+        int64_t m_a0 = 0, m_cs = 0;
         int m_L = 0, m_sw = 0, m_T = 0, m_cap = 0;
         // batched: the row's problem (its arrays are read through the scalar
         // cache when an item needs them: one register per lane instead of
