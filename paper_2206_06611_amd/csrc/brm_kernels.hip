@@ -377,6 +377,7 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
     if (threadIdx.x == 0) s_nprod = 0;
     __syncthreads();
 
+    // rows per class, counted per chunk by ballots (wavefront totals: scalar registers)
     int64_t my_count[kNumClasses];
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
@@ -453,6 +454,7 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             analysis_windows<IB>(e0, e1, a_col, reinterpret_cast<const IB *>(b_rpt), ent_bs, ent_len, in, a0, a1,
                                  s_flag[w], lane, np_r, mx_r);
         }
+        int cls_l = -1;  // the lane's row's class
         if (in) {
             const int64_t np = np_r;
             const int mx = mx_r;
@@ -467,6 +469,7 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
                            : cls == kClassMulti                   ? multi_shift(a1 - a0, mx, np)
                                                                   : 0;
             row_class[i] = (uint8_t)(cls | (sw << kClassBits));
+            cls_l = cls;
             if constexpr (FEAT) {
                 // the predictor's features (lists, products and column span
                 // the last two relative to B's column count, longest and
@@ -483,15 +486,15 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
             }
             if (cls == kClassEmpty) row_size[i] = 0;
             if (cls == kClassCopy) row_size[i] = (int32_t)np;
-#pragma unroll
-            for (int c = 0; c < kNumClasses; ++c) my_count[c] += (cls == c);
             my_nprod += np;
         }
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) my_count[c] += __popcll(wave_ballot(cls_l == c));
         wave_sync();
     }
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) {
-        const int64_t t = wave_sum(my_count[c]);
+        const int64_t t = my_count[c];
         if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long *>(&s_count[c]),
                                       (unsigned long long)t);
     }
@@ -3617,6 +3620,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         s_long = 0;
     }
     __syncthreads();
+    // rows per class, counted per chunk by ballots (wavefront totals: scalar registers)
     int64_t my_count[kNumClasses];
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) my_count[c] = 0;
@@ -3648,8 +3652,8 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
                 row_class[g] = (uint8_t)kClassEmpty;
                 row_prob[g] = p;
                 row_size[g] = 0;
-                my_count[kClassEmpty] += 1;
             }
+            my_count[kClassEmpty] += __popcll(wave_ballot(in));
             continue;
         }
         int64_t a0 = 0, a1 = 0;
@@ -3665,6 +3669,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         int mx_r = 0;
         analysis_windows<IB>(e0, e1, pr.a_col, reinterpret_cast<const IB *>(pr.b_rpt), ent_bs + pr.ent_off,
                              ent_len + pr.ent_off, in, a0, a1, s_flag[w], lane, np_r, mx_r);
+        int cls_l = -1;  // the lane's row's class
         if (in) {
             const int64_t g = pr.row_off + i;
             const int64_t nprod = np_r;
@@ -3679,18 +3684,19 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
             row_nprod[g] = nprod;
             row_class[g] = (uint8_t)(cls | (sw << kClassBits));
             row_prob[g] = p;
+            cls_l = cls;
             // upper-bound slots: every row's slot holds its products
             if (cls == kClassEmpty) row_size[g] = 0;
             else if (cls == kClassCopy || upper) row_size[g] = (int32_t)nprod;
-#pragma unroll
-            for (int q = 0; q < kNumClasses; ++q) my_count[q] += (cls == q);
             my_nprod += nprod;
         }
+#pragma unroll
+        for (int q = 0; q < kNumClasses; ++q) my_count[q] += __popcll(wave_ballot(cls_l == q));
         wave_sync();
     }
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) {
-        const int64_t t = wave_sum(my_count[c]);
+        const int64_t t = my_count[c];
         if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long *>(&s_count[c]), (unsigned long long)t);
     }
     {
