@@ -182,7 +182,8 @@ def batched_extra(reps=10):
     by_mode = {}
     for mode in [m for m in (brm.BATCH_PRECISE, brm.BATCH_UPPER) if m != chosen] + [chosen]:
         h.set_option(brm.OPT_BATCH_ALLOC, mode)  # the tuned options otherwise
-        G, AP, arena = h.galerkin(triples, problems=probs)  # sizes the arena, captures the graph
+        G, AP, arena = h.galerkin(triples, problems=probs)  # sizes the arena
+        G, AP, arena = h.galerkin(triples, arena, problems=probs)  # captures the graph
         torch.cuda.synchronize()
         nprod = h.stat(brm.STAT_NPROD)
         t0 = time.perf_counter()
@@ -249,6 +250,7 @@ def laplace_throughput_extra(count=512, reps=20):
     if rc != brm.SPG_OK:
         raise RuntimeError(f"batched call failed with status {rc}")
     desc = torch.empty((count, 6), dtype=torch.int64, device=d1.rpt.device)
+    rc, req, _ = h.batched(problems, arena, out=desc, views=False)  # captures the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):  # the C call (blocking); output views are made after
@@ -346,7 +348,7 @@ def amg_hierarchy_extra(reps=5):
     by_mode = {}
     for mode, name in ((brm.BATCH_PRECISE, "precise"), (brm.BATCH_UPPER, "upper")):
         h.set_option(brm.OPT_BATCH_ALLOC, mode)
-        out = h.amg_hierarchy(As, levels)  # warm-up, graph captures
+        out = h.amg_hierarchy(As, levels)  # warm-up (every level is a new batch: launched directly)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):

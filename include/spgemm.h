@@ -212,6 +212,10 @@ typedef enum {
                                     SPG_OPT_BLOCK_MAX products (part of SPG_STAT_OVERFLOW_ROWS) */
     SPG_STAT_GRAPH_CAPTURES = 24,/* batched calls that (re)captured their HIP graph */
     SPG_STAT_GRAPH_LAUNCHES = 25,/* batched calls that replayed a captured graph */
+    SPG_STAT_BATCHED_DIRECT = 32,/* batched calls launched kernel by kernel: a batch (problems, arena,
+                                    options) unlike the previous call's is launched directly; when the
+                                    same batch comes again it is captured in a graph and replayed
+                                    from then on */
     SPG_STAT_SPILL_POOL_BYTES = 26,/* device bytes of the handle's heavy-row spill pool (kept
                                     between calls; a call whose batches fit it reuses it) */
     SPG_STAT_SPILL_ALLOCS = 27,  /* allocations of that pool since the handle was created */
@@ -287,9 +291,11 @@ int spgemm_row_products(spg_handle h, const spg_csr *A, const spg_csr *B, int64_
  * grouped into stages by their dependencies; each stage runs the same
  * analysis / binning / symbolic / scan / numeric kernels as the single
  * product over the union of its problems' rows, and C's arrays are placed
- * in the caller's arena at offsets computed on the device.  The whole launch
- * sequence is captured once in a HIP graph and replayed while the problems
- * (pointers, sizes), the arena and the options stay the same.  Results are
+ * in the caller's arena at offsets computed on the device.  A batch is
+ * launched kernel by kernel the first time; when the next call brings the
+ * same batch (problems' pointers and sizes, arena, options) the whole launch
+ * sequence is captured in a HIP graph, which is replayed while the batch
+ * stays the same (SPG_STAT_BATCHED_DIRECT, _GRAPH_CAPTURES, _LAUNCHES).  Results are
  * bitwise equal to separate spgemm_symbolic / spgemm_numeric calls.
  * Rows beyond one workgroup's LDS (more than 4096 products) are merged as
  * in the single product's heavy path (Algorithm 1's tree, spilled nodes

@@ -73,6 +73,7 @@ STAT_HEAVY_WIDE = 28
 STAT_HEAVY_SPLIT_ROWS = 29
 STAT_DEVICE_ERR = 30
 STAT_OVERFLOW_HEAVY_ROWS = 31
+STAT_BATCHED_DIRECT = 32
 
 CLASS_NAMES = ["empty", "copy", "wave_small", "wave", "group", "block", "heavy", "multi"]
 

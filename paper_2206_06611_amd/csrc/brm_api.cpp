@@ -123,7 +123,8 @@ struct spg_handle_s {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<int64_t> graph_sig;
-    int64_t graph_captures = 0, graph_launches = 0;
+    std::vector<int64_t> seen_sig;  // the last batch launched directly (captured when it comes again)
+    int64_t graph_captures = 0, graph_launches = 0, batched_direct = 0;
     // device address of the static scratch array on this handle's device
     // (the allocation-free batched call); null when it could not be read
     void *scratch = nullptr;
@@ -783,6 +784,7 @@ int spg_get_stat(spg_handle h, int key, int64_t *value) {
         case SPG_STAT_PRED_TOTAL: *value = h->pred_total; return SPG_OK;
         case SPG_STAT_GRAPH_CAPTURES: *value = h->graph_captures; return SPG_OK;
         case SPG_STAT_GRAPH_LAUNCHES: *value = h->graph_launches; return SPG_OK;
+        case SPG_STAT_BATCHED_DIRECT: *value = h->batched_direct; return SPG_OK;
         case SPG_STAT_SPILL_POOL_BYTES: *value = (int64_t)h->spill_bytes; return SPG_OK;
         case SPG_STAT_SPILL_ALLOCS: *value = h->spill_allocs; return SPG_OK;
         case SPG_STAT_HEAVY_WIDE: *value = h->heavy_wide; return SPG_OK;
@@ -1546,7 +1548,15 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
                       h->block_max, h->force, h->grid_waves, h->heavy_lds_max, h->batch_alloc,
                       (int64_t)reinterpret_cast<uintptr_t>(h->b_mem)})
         sig.push_back(v);
-    if (realloc || !h->graph_exec || sig != h->graph_sig) {
+    const bool replay = !realloc && h->graph_exec && sig == h->graph_sig;
+    if (!replay && sig != h->seen_sig) {
+        // a batch seen for the first time: its kernels are launched directly
+        // (capturing and instantiating a graph pays off only when it is
+        // replayed); the same batch in the next call is captured
+        h->seen_sig = sig;
+        ++h->batched_direct;
+        HIP_TRY(h, launch_batched_all(h, pl, stage_chunks, base, arena_c, arena_bytes, s));
+    } else if (!replay) {
         if (h->graph_exec) {
             HIP_TRY(h, hipStreamSynchronize(s));
             (void)hipGraphExecDestroy(h->graph_exec);
@@ -1569,10 +1579,11 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
         }
         h->graph_sig = sig;
         ++h->graph_captures;
+        HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
     } else {
         ++h->graph_launches;
+        HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
     }
-    HIP_TRY(h, hipGraphLaunch(h->graph_exec, s));
     HIP_TRY(h, launch_batched_describe(d_tab, count, out, d_stat, s));
     HIP_TRY(h, hipMemcpyAsync(h->b_status_host, d_stat, sizeof(BatchStatus), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipMemcpyAsync(h->ctl_host, base + pl.o_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

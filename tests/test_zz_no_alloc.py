@@ -74,7 +74,8 @@ def test_noalloc_matches_batched_on_two_calls_second_smaller():
         print("case: noalloc galerkin edges [6, 4] (smaller)", flush=True)
         inp, triples = galerkin_batch([6, 4], 1)
         check_batch(h, inp, triples, 1 << 22)
-        assert h.stat(brm.STAT_GRAPH_CAPTURES) == 2  # the spgemm_batched calls only
+        # the spgemm_batched calls only (each batch seen once: launched directly)
+        assert h.stat(brm.STAT_BATCHED_DIRECT) == 2 and h.stat(brm.STAT_GRAPH_CAPTURES) == 0
     finally:
         h.close()
 
