@@ -1854,6 +1854,64 @@ __device__ __forceinline__ bool key_rounds(uint32_t &k, double &v, int W0, int T
     return placed;
 }
 
+// The rounds' merge network on the keys alone, from sorted windows of width
+// W0 up to the padded total T: every row's window ends sorted by (column,
+// lane), and a row's lanes are in list order.
+__device__ __forceinline__ void key_sort(uint32_t &k, int W0, int T, int lane) {
+    for (int W = W0; W < T; W <<= 1) {
+        switch (W) {
+            case 1: key_merge<1>(k, lane); break;
+            case 2: key_merge<2>(k, lane); break;
+            case 4: key_merge<4>(k, lane); break;
+            case 8: key_merge<8>(k, lane); break;
+            case 16: key_merge<16>(k, lane); break;
+            default: key_merge<32>(k, lane); break;
+        }
+    }
+}
+
+// Algorithm 1's accumulating phase on a sorted key window, without moving
+// entries between rounds.  k: the lane's key (column, source lane), v: the
+// value of that key.  Two products of one column from lists a < b meet in
+// the merge tree at the level of the lowest common ancestor of a and b, the
+// position of the highest bit of a ^ b (list p of a row is the tree's leaf
+// p; node (r, q) covers lists [q 2^r, (q+1) 2^r)).  In a column's run of
+// lanes (ascending lists), the lanes joined by levels below r hold the
+// column's entries of one node of level r-1; level by level, each such run's
+// first lane adds the first lane of the next run when the two meet at level
+// r exactly (left + right).  So every column's sum has the tree's grouping,
+// as in the round-by-round merges.  lsw: log2 of the lane's row's list width;
+// rows are windows of T lanes.  Returns the lanes holding a column's sum
+// (its first lane in the row).
+__device__ __forceinline__ uint64_t tree_adds(uint32_t k, double &v, int lsw, int T, int lane, int levels) {
+    const bool live = k < kKeyEmpty;
+    const uint32_t col = k >> kKeyLaneBits;
+    const int li = (int)((k & kKeyLaneMask) & (uint32_t)(T - 1)) >> lsw;
+    const uint32_t nk = lane_next(k), pk = lane_prev(k);
+    const bool first = (lane & (T - 1)) == 0, last = ((lane + 1) & (T - 1)) == 0;
+    const bool same_next = live && !last && nk < kKeyEmpty && (nk >> kKeyLaneBits) == col;
+    const bool head = live && (first || pk >= kKeyEmpty || (pk >> kKeyLaneBits) != col);
+    const uint64_t heads = wave_ballot(head);
+    if (wave_ballot(same_next) == 0ull) return heads;  // no column repeats: nothing to add
+    const int li_next = (int)((nk & kKeyLaneMask) & (uint32_t)(T - 1)) >> lsw;
+    // the level at which this lane's entry meets the next lane's (64: never)
+    const int lvl = same_next ? 32 - __clz(li ^ li_next) : 64;
+    // the previous lane's level (64 at a row's first lane).  The shift is
+    // taken in every lane and then masked: a shift under a condition would
+    // run with the first lanes disabled, and their neighbours would read the
+    // shift's fallback instead of their level
+    const int plvl = (int)lane_prev((uint32_t)lvl) | (first ? 64 : 0);
+    for (int r = 1; r <= levels; ++r) {
+        const uint64_t ends = wave_ballot(lvl >= r);  // the last lane of every run
+        const uint64_t meet = wave_ballot(lvl == r);
+        const int e = lane + __builtin_ctzll(ends >> lane);  // this lane's run ends at lane e
+        const double w = __shfl(v, e + 1 < kWave ? e + 1 : e, kWave);
+        const bool rep = head || plvl >= r;  // the first lane of its run
+        if (live && rep && ((meet >> e) & 1ull)) v = v + w;  // left + right
+    }
+    return heads;
+}
+
 // Symbolic use: the same merges on bare columns (empty = all ones), equal
 // columns left in place; the lanes holding the first entry of a distinct
 // column are returned as a mask.  A second row may start at lane `seg`
@@ -2157,11 +2215,31 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     uint32_t k = gi.c == kEmptyCol ? (kKeyEmpty | (uint32_t)lane)
                                                    : (((uint32_t)gi.c << kKeyLaneBits) | (uint32_t)lane);
                     double v = gi.av * gi.bv;  // one rounded product
-                    if (!key_rounds(k, v, 1 << sw, T, lane, xk, xv)) v = __shfl(v, (int)(k & kKeyLaneMask), kWave);
-                    const bool live = k < kKeyEmpty;
-                    const uint64_t lm = wave_ballot(live);
-                    // live entries sit at the front of their row's lanes
-                    const int pos = P ? (lane & (kHalf - 1)) : lane;
+                    uint64_t lm;
+                    bool live;
+                    int pos;
+                    if constexpr (BATCH) {
+                        // one sort, then the tree's additions level by level
+                        // (rows of single-entry lists with many repeated
+                        // columns: no compaction between rounds)
+                        key_sort(k, 1 << sw, T, lane);
+                        v = __shfl(v, (int)(k & kKeyLaneMask), kWave);  // the values in key order
+                        // the lane's own row's list width (the rows of a pair may differ)
+                        const int lsw = P ? sel32(m_sw, a, b) : sw;
+                        lm = tree_adds(k, v, lsw, T, lane, ceil_log2(T) - sw);
+                        live = (lm >> lane) & 1ull;
+                        // a column's position in its row: the sums before it in the row's lanes
+                        const uint64_t rowm = !P ? ~0ull : lane >= kHalf ? ~0ull << kHalf : ~0ull >> kHalf;
+                        pos = __popcll(lm & rowm & ((1ull << lane) - 1ull));
+                    } else {
+                        // round by round, compacting after every round that
+                        // added (few repeats: most rounds only check)
+                        if (!key_rounds(k, v, 1 << sw, T, lane, xk, xv)) v = __shfl(v, (int)(k & kKeyLaneMask), kWave);
+                        live = k < kKeyEmpty;
+                        lm = wave_ballot(live);
+                        // live entries sit at the front of their row's lanes
+                        pos = P ? (lane & (kHalf - 1)) : lane;
+                    }
                     const int64_t cs = sel64(m_cs, a, b);
                     const int cap = sel32(m_cap, a, b);
                     int32_t *cc = c_col;
