@@ -3706,20 +3706,50 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
     const int lane = lane_id();
     const int w = threadIdx.x / kWave;
     const bool skip = st->skip != 0;  // one value for the whole stage (set before this launch)
-    for (int64_t c = (int64_t)blockIdx.x * kW + w; c < nchunks; c += (int64_t)gridDim.x * kW) {
-        const int p = find_prob(lk, chunk_off, np, c);
-        // the problem's fields in registers once per chunk: the stores below
-        // could otherwise alias the table and force reloads
-        const BatchProb &tp = tab[p];
+    // A chunk's problem (its fields in registers: the stores below could
+    // otherwise alias the table and force reloads), first row, row count and
+    // the lanes' row pointers.  The next chunk's are loaded while this one is
+    // walked, which takes the head of the chunk's chain of dependent loads
+    // off its critical path.
+    struct Meta {
+        int p, nrows;
+        int64_t rows, row_off, ent_off, r0, a0, a1;
+        const void *a_rpt, *b_rpt;
+        const int32_t *a_col;
+    };
+    static_assert(kBatchChunkRows == kWave, "a chunk is one wavefront's rows");
+    auto meta = [&](int64_t c, Meta &m) {
+        m.p = find_prob(lk, chunk_off, np, c);
+        const BatchProb &tp = tab[m.p];
+        m.rows = wave_uniform(tp.rows);
+        m.row_off = wave_uniform(tp.row_off);
+        m.ent_off = wave_uniform(tp.ent_off);
+        m.a_rpt = tp.a_rpt;
+        m.b_rpt = tp.b_rpt;
+        m.a_col = tp.a_col;
+        m.r0 = (c - (np < kMaxLdsProbs ? lk.off[m.p] : gload(chunk_off + m.p))) * kWave;
+        m.nrows = m.rows - m.r0 < kWave ? (int)(m.rows - m.r0) : kWave;
+        m.a0 = 0;
+        m.a1 = 0;
+        if (!skip && lane < m.nrows) {
+            m.a0 = ld_rpt<IA>(m.a_rpt, m.r0 + lane);
+            m.a1 = ld_rpt<IA>(m.a_rpt, m.r0 + lane + 1);
+        }
+    };
+    const int64_t cstride = (int64_t)gridDim.x * kW;
+    int64_t c = (int64_t)blockIdx.x * kW + w;
+    Meta cur, nxt;
+    if (c < nchunks) meta(c, cur);
+    for (; c < nchunks; c += cstride) {
+        if (c + cstride < nchunks) meta(c + cstride, nxt);
+        const int p = cur.p;
         struct {
             int64_t rows, row_off, ent_off;
             const void *a_rpt, *b_rpt;
             const int32_t *a_col;
-        } pr = {wave_uniform(tp.rows), wave_uniform(tp.row_off), wave_uniform(tp.ent_off), tp.a_rpt, tp.b_rpt,
-                tp.a_col};
-        static_assert(kBatchChunkRows == kWave, "a chunk is one wavefront's rows");
-        const int64_t r0 = (c - (np < kMaxLdsProbs ? lk.off[p] : gload(chunk_off + p))) * kWave;
-        const int nrows = pr.rows - r0 < kWave ? (int)(pr.rows - r0) : kWave;
+        } pr = {cur.rows, cur.row_off, cur.ent_off, cur.a_rpt, cur.b_rpt, cur.a_col};
+        const int64_t r0 = cur.r0;
+        const int nrows = cur.nrows;
         const int64_t i = r0 + lane;
         const bool in = lane < nrows;
         if (skip) {
@@ -3732,14 +3762,11 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
                 row_size[g] = 0;
             }
             my_count[kClassEmpty] += __popcll(wave_ballot(in));
+            cur = nxt;
             continue;
         }
-        int64_t a0 = 0, a1 = 0;
-        if (in) {
-            a0 = ld_rpt<IA>(pr.a_rpt, i);
-            a1 = ld_rpt<IA>(pr.a_rpt, i + 1);
-            s_start[w][lane] = a0;
-        }
+        const int64_t a0 = cur.a0, a1 = cur.a1;
+        if (in) s_start[w][lane] = a0;
         if (lane == nrows - 1) s_start[w][nrows] = a1;
         wave_sync();
         const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
@@ -3771,6 +3798,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
 #pragma unroll
         for (int q = 0; q < kNumClasses; ++q) my_count[q] += __popcll(wave_ballot(cls_l == q));
         wave_sync();
+        cur = nxt;
     }
 #pragma unroll
     for (int c = 0; c < kNumClasses; ++c) {
