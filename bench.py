@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "e86fbfa6d9fc038f43399328d428022cde53992a6322c42c9166cb2f03a80415",
-                 "fetch_kib": 1093928.0, "write_kib": 842961.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "a54cc054c0ff3902929435514106423d2e1c07304bad156c0b25087667d615d8",
+                 "fetch_kib": 1094044.0, "write_kib": 843590.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
