@@ -310,10 +310,25 @@ typedef struct {
     spg_csr A;        /* device CSR */
     spg_csr B;        /* device CSR; ignored when b_from >= 0 */
     int32_t b_from;   /* -1, or the index (< this one) of the problem whose C is B */
+    int32_t flags;    /* 0, or SPG_PROBLEM_OPERAND_ONLY */
 } spg_problem;
 
+/* Problem flags.  SPG_PROBLEM_OPERAND_ONLY: the problem's C is needed only as
+ * the B of later problems of the same call (the A P of a Galerkin product
+ * P^T (A P)).  When every problem of a stage carries it and the stage sizes
+ * are upper bounds (SPG_BATCH_UPPER), the stage's C stays in its slots of
+ * the arena -- no exact sizes, no row pointers, no compaction -- and the
+ * later problems read its rows from there: each row is described by its
+ * start and end in the slots, written where the problem's row pointers
+ * would be (that region takes 16 bytes per row instead of 8), and the
+ * problem's descriptor reports nnz = -2 (its C is not returned).  Otherwise
+ * the flag changes nothing.  The later problems' results are bitwise the
+ * same either way. */
+enum { SPG_PROBLEM_OPERAND_ONLY = 1 };
+
 /* Where problem p's C sits in the arena (byte offsets; nnz = -1 when the
- * arena was too small). */
+ * arena was too small, -2 when the C was kept as an operand only, see
+ * SPG_PROBLEM_OPERAND_ONLY; the offsets are then -1). */
 typedef struct {
     int64_t rows, cols, nnz;
     int64_t rpt_off;  /* int64[rows + 1] */

@@ -48,6 +48,7 @@ OPT_HEAVY_THREADS = 14
 OPT_HEAVY_SPLIT = 15
 OPT_LEARNED_HEAVY_MARGIN = 16
 OPT_BATCH_ALLOC = 17
+PROBLEM_OPERAND_ONLY = 1
 BATCH_PRECISE = 0
 BATCH_UPPER = 1
 ACC_BRMERGE = 0
@@ -97,7 +98,7 @@ class _Csr(ctypes.Structure):
 
 
 class _Problem(ctypes.Structure):
-    _fields_ = [("A", _Csr), ("B", _Csr), ("b_from", ctypes.c_int32)]
+    _fields_ = [("A", _Csr), ("B", _Csr), ("b_from", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class _BatchedOut(ctypes.Structure):
@@ -260,10 +261,13 @@ class BatchedProblems:
     keeps the matrices it points to alive."""
 
     def __init__(self, problems):
+        """problems: (A, B) or (A, B, flags) tuples (flags: PROBLEM_OPERAND_ONLY or 0)."""
         self.n = len(problems)
         self.arr = (_Problem * max(self.n, 1))()
         self._keep = list(problems)
-        for i, (A, B) in enumerate(problems):
+        for i, prob in enumerate(problems):
+            A, B = prob[0], prob[1]
+            self.arr[i].flags = prob[2] if len(prob) > 2 else 0
             self.arr[i].A = A._struct()
             if isinstance(B, int):
                 self.arr[i].b_from = B
@@ -474,6 +478,9 @@ class Handle:
         desc = out[:n].cpu().tolist()
         outs = []
         for rows, cols, nnz, ro, co, vo in desc:
+            if nnz == -2:  # an operand only, kept in slots: not returned
+                outs.append(None)
+                continue
             rpt = arena[ro:ro + 8 * (rows + 1)].view(torch.int64)
             col = arena[co:co + 4 * nnz].view(torch.int32)
             val = arena[vo:vo + 8 * nnz].view(torch.float64)
@@ -481,18 +488,24 @@ class Handle:
         return rc, req.value, outs
 
     @staticmethod
-    def galerkin_problems(triples) -> "BatchedProblems":
-        """The batched problems of galerkin(triples), marshalled once."""
-        return BatchedProblems([(A, P) for A, P, _ in triples] + [(Pt, i) for i, (_, _, Pt) in enumerate(triples)])
+    def galerkin_problems(triples, ap_operand_only: bool = False) -> "BatchedProblems":
+        """The batched problems of galerkin(triples), marshalled once;
+        ap_operand_only marks every A_i P_i as an operand only."""
+        f = PROBLEM_OPERAND_ONLY if ap_operand_only else 0
+        return BatchedProblems([(A, P, f) for A, P, _ in triples] +
+                               [(Pt, i) for i, (_, _, Pt) in enumerate(triples)])
 
-    def galerkin(self, triples, arena: torch.Tensor | None = None, stream=None, problems=None):
+    def galerkin(self, triples, arena: torch.Tensor | None = None, stream=None, problems=None,
+                 ap_operand_only: bool = False):
         """G_i = P_i^T (A_i P_i) for triples (A_i, P_i, Pt_i) in one batched
         call (stage 1: A_i P_i, stage 2: Pt_i times stage 1's output).  Grows
         the arena when it is too small.  `problems` may be
-        galerkin_problems(triples), made once.  Returns (G list, AP list,
-        arena)."""
+        galerkin_problems(triples, ap_operand_only), made once.
+        ap_operand_only: the A_i P_i are not returned (with upper-bound stage
+        sizes they stay in their slots: no compaction).  Returns (G list, AP
+        list -- None entries for operands kept in slots --, arena)."""
         n = len(triples)
-        probs = problems if problems is not None else self.galerkin_problems(triples)
+        probs = problems if problems is not None else self.galerkin_problems(triples, ap_operand_only)
         if arena is None:
             est = sum(8 * (A.rows + 1) + 8 * (Pt.rows + 1) + 12 * 27 * A.rows + 8192 for A, _, Pt in triples)
             arena = torch.empty(est, dtype=torch.uint8, device=triples[0][0].rpt.device)
@@ -522,7 +535,7 @@ class Handle:
         for l in range(depth):
             ids = [i for i, lv in enumerate(levels) if l < len(lv)]
             triples = [(cur[i], levels[i][l][0], levels[i][l][1]) for i in ids]
-            G, _, _ = self.galerkin(triples, stream=stream)
+            G, _, _ = self.galerkin(triples, stream=stream, ap_operand_only=True)
             for i, g in zip(ids, G):
                 out[i].append(g)
                 cur[i] = g

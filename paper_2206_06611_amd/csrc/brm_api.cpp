@@ -1263,7 +1263,7 @@ namespace {
 // stages (problems grouped by their dependencies), the arena's row-pointer
 // section, and the byte layout of the stage workspace.
 struct BatchedPlan {
-    struct Stage { int first, n; int64_t rows, ents; int arb, brb; bool link; size_t roff; };
+    struct Stage { int first, n; int64_t rows, ents; int arb, brb; bool link; size_t roff; bool keep; };
     std::vector<Stage> st;
     std::vector<int64_t> ccols, rpt_off, stage_chunks;
     size_t roff_total = 0;
@@ -1289,6 +1289,7 @@ int plan_batched(spg_handle h, int count, const spg_problem *probs, void *arena,
     for (int p = 0; p < count; ++p) {
         const spg_problem &q = probs[p];
         if ((rc = check_csr(h, &q.A, "A", true))) return rc;
+        if (q.flags & ~(int32_t)SPG_PROBLEM_OPERAND_ONLY) return fail(h, SPG_ERR_ARG, "problem %d: unknown flags", p);
         int64_t brows, bcols;
         if (q.b_from >= 0) {
             if (q.b_from >= p) return fail(h, SPG_ERR_ARG, "problem %d: b_from must name an earlier problem", p);
@@ -1312,7 +1313,9 @@ int plan_batched(spg_handle h, int count, const spg_problem *probs, void *arena,
     for (int p = 0; p < count;) {
         int q = p;
         BatchedPlan::Stage si{p, 0, 0, 0, probs[p].A.rpt_bytes, probs[p].b_from >= 0 ? 8 : probs[p].B.rpt_bytes,
-                              false, pl->roff_total};
+                              false, pl->roff_total, false};
+        // a stage keeps its upper-bound slots when every problem of it is an operand only
+        bool all_operands = h->batch_alloc == SPG_BATCH_UPPER;
         while (q < count && stage[(size_t)q] == stage[(size_t)p]) {
             const int brb = probs[q].b_from >= 0 ? 8 : probs[q].B.rpt_bytes;
             if (probs[q].A.rpt_bytes != si.arb || brb != si.brb)
@@ -1320,9 +1323,11 @@ int plan_batched(spg_handle h, int count, const spg_problem *probs, void *arena,
             si.rows += probs[q].A.rows;
             si.ents += probs[q].A.nnz;
             si.link = si.link || probs[q].b_from >= 0;
+            all_operands = all_operands && (probs[q].flags & SPG_PROBLEM_OPERAND_ONLY);
             ++q;
         }
         si.n = q - p;
+        si.keep = all_operands;
         pl->roff_total += (size_t)si.n + 1;
         pl->st.push_back(si);
         p = q;
@@ -1335,12 +1340,16 @@ int plan_batched(spg_handle h, int count, const spg_problem *probs, void *arena,
     pl->max_bcols = 0;
     for (int p = 0; p < count; ++p) pl->max_bcols = std::max(pl->max_bcols, pl->ccols[(size_t)p]);
     if (max_rows > INT32_MAX) return fail(h, SPG_ERR_ARG, "too many rows in one stage");
-    // arena: row pointers first (sizes known now), then C's columns and values
+    // arena: row pointers first (sizes known now), then C's columns and values;
+    // a problem of a stage that keeps its slots takes the starts and the ends of its rows
     pl->rpt_end = 0;
     pl->rpt_off.assign((size_t)count, 0);
+    std::vector<char> kept((size_t)count, 0);
+    for (const auto &x : pl->st)
+        for (int i = 0; i < x.n; ++i) kept[(size_t)(x.first + i)] = x.keep ? 1 : 0;
     for (int p = 0; p < count; ++p) {
         pl->rpt_off[(size_t)p] = pl->rpt_end;
-        pl->rpt_end += (int64_t)align_up(8 * (size_t)(crows[(size_t)p] + 1), 256);
+        pl->rpt_end += (int64_t)align_up((kept[(size_t)p] ? 16 : 8) * (size_t)(crows[(size_t)p] + 1), 256);
     }
     if (pl->rpt_end > arena_bytes) {
         *required_bytes = pl->rpt_end;
@@ -1460,6 +1469,7 @@ hipError_t launch_batched_all(spg_handle h, const BatchedPlan &pl, const std::ve
         bs.upper = pl.upper ? 1 : 0;
         bs.S2 = pl.upper ? reinterpret_cast<int64_t *>(base + pl.o_S2) : nullptr;
         bs.ovf = pl.upper ? reinterpret_cast<int32_t *>(base + pl.o_ovf) : nullptr;
+        bs.keep = x.keep ? 1 : 0;
         e = launch_batched_stage(bs, ws, th, h->num_cu, h->grid_waves, s);
     }
     return e;
@@ -1536,8 +1546,8 @@ int spgemm_batched(spg_handle h, int count, const spg_problem *probs, void *aren
     sig.push_back(count);
     for (int p = 0; p < count; ++p) {
         const spg_problem &q = probs[p];
-        for (int64_t v : {q.A.rows, q.A.cols, q.A.nnz, (int64_t)q.A.rpt_bytes, (int64_t)q.b_from, q.B.rows, q.B.cols,
-                          q.B.nnz, (int64_t)q.B.rpt_bytes})
+        for (int64_t v : {q.A.rows, q.A.cols, q.A.nnz, (int64_t)q.A.rpt_bytes, (int64_t)q.b_from, (int64_t)q.flags,
+                          q.B.rows, q.B.cols, q.B.nnz, (int64_t)q.B.rpt_bytes})
             sig.push_back(v);
         for (const void *ptr : {q.A.rpt, (const void *)q.A.col, (const void *)q.A.val, q.B.rpt,
                                 (const void *)q.B.col, (const void *)q.B.val})

@@ -193,9 +193,11 @@ struct BatchProb {
     const int32_t *a_col;
     const double *a_val;
     const void *b_rpt;
+    const int64_t *b_end;  // end of every row of B when B is a C kept in slots, else nullptr
     const int32_t *b_col;
     const double *b_val;
     int64_t *c_rpt;    // in the arena (offset chosen on the host)
+    int64_t *c_end;    // a C kept in slots: end of every row (c_rpt holds the starts), else nullptr
     int32_t *c_col;    // in the arena (offset chosen on the device)
     double *c_val;
     int64_t nnz;
@@ -224,6 +226,7 @@ struct BatchStatus {
     // the current stage's upper-bound slots (set when they fit)
     int32_t *s_col;
     double *s_val;
+    int64_t slots_end;   // arena offset where they end
 };
 
 constexpr int kBatchHeavyThreads = 512;  // workgroup of the batched heavy-row merge
@@ -250,6 +253,7 @@ struct BatchStage {
     int64_t *S2;         // rows + 1: prefix sums of the slot sizes (upper)
     int32_t *ovf;        // 2 * rows: overflow list of the bound-mode bookkeeping (upper; never filled,
                          // a slot holds all of its row's products)
+    int keep;            // upper: every problem of the stage is an operand only; its slots are kept
 };
 
 hipError_t launch_batched_begin(BatchStatus *st, Ctl *ctl, hipStream_t s);

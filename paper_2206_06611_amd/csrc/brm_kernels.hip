@@ -102,6 +102,7 @@ template <typename IB>
 struct Lists {
     const int32_t *a_col;
     const void *b_rpt;
+    const int64_t *b_end;    // end of every B row (B kept in slots), or nullptr: the next row's start
     const void *ent_bs;      // IB per entry of A, or nullptr
     const int32_t *ent_len;  // per entry of A, or nullptr
     __device__ __forceinline__ void get(int64_t p, int64_t &bs, int &ln) const {
@@ -111,7 +112,7 @@ struct Lists {
         } else {
             const int32_t k = gload(a_col + p);
             bs = ld_rpt<IB>(b_rpt, k);
-            ln = (int)(ld_rpt<IB>(b_rpt, k + 1) - bs);
+            ln = (int)((b_end ? gload(b_end + k) : (int64_t)ld_rpt<IB>(b_rpt, k + 1)) - bs);
         }
     }
     // the per-entry arrays only (they must be present)
@@ -122,10 +123,12 @@ struct Lists {
 };
 
 template <typename IB>
-__host__ __device__ __forceinline__ Lists<IB> direct_lists(const int32_t *a_col, const void *b_rpt) {
+__host__ __device__ __forceinline__ Lists<IB> direct_lists(const int32_t *a_col, const void *b_rpt,
+                                                           const int64_t *b_end = nullptr) {
     Lists<IB> l;
     l.a_col = a_col;
     l.b_rpt = b_rpt;
+    l.b_end = b_end;
     l.ent_bs = nullptr;
     l.ent_len = nullptr;
     return l;
@@ -136,6 +139,7 @@ __host__ __forceinline__ Lists<IB> ws_lists(const CsrView &A, const CsrView &B, 
     Lists<IB> l;
     l.a_col = A.col;
     l.b_rpt = B.rpt;
+    l.b_end = nullptr;
     l.ent_bs = ws.ent_bs;
     l.ent_len = ws.ent_len;
     return l;
@@ -294,7 +298,8 @@ __device__ __forceinline__ void window_row_reduce(int64_t eb, bool in, int64_t a
 constexpr int kAnaUnroll = 4;
 template <typename IB>
 __device__ __forceinline__ void analysis_windows(int64_t e0, int64_t e1, const int32_t *a_col, const IB *brp,
-                                                 IB *ent_bs, int32_t *ent_len, bool in, int64_t a0, int64_t a1,
+                                                 const int64_t *bend, IB *ent_bs, int32_t *ent_len, bool in,
+                                                 int64_t a0, int64_t a1,
                                                  int32_t *flag, int lane, int64_t &np_r, int &mx_r) {
     constexpr int U = kAnaUnroll;
     int32_t k[U];
@@ -312,7 +317,7 @@ __device__ __forceinline__ void analysis_windows(int64_t e0, int64_t e1, const i
             be[u] = 0;
             if (e < e1) {
                 bs[u] = gload(brp + k[u]);
-                be[u] = gload(brp + k[u] + 1);
+                be[u] = bend ? (IB)gload(bend + k[u]) : gload(brp + k[u] + 1);
             }
         }
 #pragma unroll
@@ -451,7 +456,8 @@ __global__ __launch_bounds__(kAnalysisThreads) void k_analysis(
                 }
             }
         } else {
-            analysis_windows<IB>(e0, e1, a_col, reinterpret_cast<const IB *>(b_rpt), ent_bs, ent_len, in, a0, a1,
+            analysis_windows<IB>(e0, e1, a_col, reinterpret_cast<const IB *>(b_rpt), nullptr, ent_bs, ent_len, in,
+                                 a0, a1,
                                  s_flag[w], lane, np_r, mx_r);
         }
         int cls_l = -1;  // the lane's row's class
@@ -3715,6 +3721,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         int p, nrows;
         int64_t rows, row_off, ent_off, r0, a0, a1;
         const void *a_rpt, *b_rpt;
+        const int64_t *b_end;
         const int32_t *a_col;
     };
     static_assert(kBatchChunkRows == kWave, "a chunk is one wavefront's rows");
@@ -3726,6 +3733,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         m.ent_off = wave_uniform(tp.ent_off);
         m.a_rpt = tp.a_rpt;
         m.b_rpt = tp.b_rpt;
+        m.b_end = tp.b_end;
         m.a_col = tp.a_col;
         m.r0 = (c - (np < kMaxLdsProbs ? lk.off[m.p] : gload(chunk_off + m.p))) * kWave;
         m.nrows = m.rows - m.r0 < kWave ? (int)(m.rows - m.r0) : kWave;
@@ -3746,8 +3754,9 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         struct {
             int64_t rows, row_off, ent_off;
             const void *a_rpt, *b_rpt;
+            const int64_t *b_end;
             const int32_t *a_col;
-        } pr = {cur.rows, cur.row_off, cur.ent_off, cur.a_rpt, cur.b_rpt, cur.a_col};
+        } pr = {cur.rows, cur.row_off, cur.ent_off, cur.a_rpt, cur.b_rpt, cur.b_end, cur.a_col};
         const int64_t r0 = cur.r0;
         const int nrows = cur.nrows;
         const int64_t i = r0 + lane;
@@ -3772,7 +3781,7 @@ __global__ __launch_bounds__(256) void k_b_analysis(const BatchProb *tab, const 
         const int64_t e0 = s_start[w][0], e1 = s_start[w][nrows];
         int64_t np_r = 0;
         int mx_r = 0;
-        analysis_windows<IB>(e0, e1, pr.a_col, reinterpret_cast<const IB *>(pr.b_rpt), ent_bs + pr.ent_off,
+        analysis_windows<IB>(e0, e1, pr.a_col, reinterpret_cast<const IB *>(pr.b_rpt), pr.b_end, ent_bs + pr.ent_off,
                              ent_len + pr.ent_off, in, a0, a1, s_flag[w], lane, np_r, mx_r);
         int cls_l = -1;  // the lane's row's class
         if (in) {
@@ -3835,7 +3844,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_sym_hash(int cls, const BatchPro
         const int64_t g = class_rows[start + idx];
         const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
         const int total = sym_hash_row<T, TS, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt,
-                                                      direct_lists<IB>(pr.a_col, pr.b_rpt), pr.b_col);
+                                                      direct_lists<IB>(pr.a_col, pr.b_rpt, pr.b_end), pr.b_col);
         if (tid == 0) row_size[g] = total;
     }
 }
@@ -3901,6 +3910,7 @@ __global__ void k_b_link(BatchProb *all, int first, int np) {
         if (q.b_from >= 0) {
             const BatchProb &src = all[q.b_from];
             q.b_rpt = src.c_rpt;
+            q.b_end = src.c_end;
             q.b_col = src.c_col;
             q.b_val = src.c_val;
         }
@@ -3928,7 +3938,7 @@ __global__ __launch_bounds__(256) void k_b_num_copy(int cls, const BatchProb *ta
          idx += waves) {
         const int64_t g = class_rows[start + idx];
         const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
-        copy_row<IA, IB>(lane, g - pr.row_off, g, pr.a_rpt, direct_lists<IB>(pr.a_col, pr.b_rpt), pr.a_val,
+        copy_row<IA, IB>(lane, g - pr.row_off, g, pr.a_rpt, direct_lists<IB>(pr.a_col, pr.b_rpt, pr.b_end), pr.a_val,
                          pr.b_col, pr.b_val, pr.c_rpt, pr.c_col, pr.c_val, ctl, no);
     }
 }
@@ -3951,7 +3961,7 @@ __global__ __launch_bounds__(T *TEAMS) void k_b_num_lds(int cls, const BatchProb
         const int64_t g = class_rows[start + idx];
         const BatchProb &pr = tab[find_prob(lk, row_off, np, g)];
         brmerge_row_lds<T, CAP, IA, IB>(lds[team], tid, g - pr.row_off, pr.a_rpt,
-                                        direct_lists<IB>(pr.a_col, pr.b_rpt), pr.a_val, pr.b_col, pr.b_val,
+                                        direct_lists<IB>(pr.a_col, pr.b_rpt, pr.b_end), pr.a_val, pr.b_col, pr.b_val,
                                         pr.c_rpt, pr.c_col, pr.c_val, ctl, no, g);
     }
 }
@@ -4057,7 +4067,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_b_sym_bitmap(const BatchProb 
         const int64_t g = class_rows[start + idx];
         const BatchProb &tp = tab[row_prob[g]];
         const int64_t total = sym_bitmap_row<IA, IB>(s, tid, g - tp.row_off, tp.ncols_b, tp.a_rpt,
-                                                     direct_lists<IB>(tp.a_col, tp.b_rpt), tp.b_col);
+                                                     direct_lists<IB>(tp.a_col, tp.b_rpt, tp.b_end), tp.b_col);
         if (tid == 0) row_size[g] = (int32_t)total;
         __syncthreads();
     }
@@ -4170,7 +4180,7 @@ __global__ __launch_bounds__(kBatchHeavyThreads, 4) void k_b_num_heavy(const Bat
         const int64_t nprod = wave_uniform(gload(row_nprod + g));
         const int64_t so = wave_uniform(gload(htab + 2 * idx)), lo = wave_uniform(gload(htab + 2 * idx + 1));
         heavy_walk<IA, IB, T>(node_lds, mrg, hs, tid, row, 0, L, -1, nprod, hleaf + lo, hcol + so, hval + so,
-                              lds_cap, nullptr, a_rpt, direct_lists<IB>(tp.a_col, tp.b_rpt), tp.a_val, tp.b_col,
+                              lds_cap, nullptr, a_rpt, direct_lists<IB>(tp.a_col, tp.b_rpt, tp.b_end), tp.a_val, tp.b_col,
                               tp.b_val, tp.c_rpt, tp.c_col, tp.c_val, ctl, no, g);
     }
 }
@@ -4183,7 +4193,7 @@ __global__ __launch_bounds__(kBatchHeavyThreads, 4) void k_b_num_heavy(const Bat
 // fields, and the compaction moves every row to C once its size is known.
 __global__ __launch_bounds__(1024) void k_b_slot_plan(BatchProb *tab, int np, int64_t *S2, int64_t R,
                                                       BatchStatus *st, char *arena, int64_t arena_bytes,
-                                                      int64_t data_off) {
+                                                      int64_t data_off, int keep) {
     __shared__ int64_t scr[Team<1024>::kWaves + 1];
     auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
     const int64_t used = st->arena_used;
@@ -4193,7 +4203,7 @@ __global__ __launch_bounds__(1024) void k_b_slot_plan(BatchProb *tab, int np, in
         const int64_t n = S2[tab[p].row_off + tab[p].rows] - S2[tab[p].row_off];
         cb += al(4 * n) + al(8 * n);
     }
-    const int64_t cbound = Team<1024>::sum(cb, scr, (int)threadIdx.x);
+    const int64_t cbound = keep ? 0 : Team<1024>::sum(cb, scr, (int)threadIdx.x);
     const int64_t total = S2[R];
     const int64_t o_col = base + cbound;
     const int64_t o_val = o_col + al(4 * total);
@@ -4202,6 +4212,7 @@ __global__ __launch_bounds__(1024) void k_b_slot_plan(BatchProb *tab, int np, in
     if (threadIdx.x == 0) {
         if (end > st->required) st->required = end;
         st->spill_base = end;  // heavy rows' spill space after the slots
+        st->slots_end = end;
         if (end > arena_bytes) {
             atomicOr(&st->flags, (int)kBatchOverflow);
         } else {
@@ -4297,13 +4308,53 @@ __global__ __launch_bounds__(256) void k_b_compact(const BatchProb *tab, const i
 }
 
 // caller-visible descriptors of the outputs (byte offsets into the arena)
+// A stage whose problems are all operands only (SPG_PROBLEM_OPERAND_ONLY)
+// keeps its upper-bound slots: every row of problem p is described by its
+// first and end position in the stage's slot arrays, written into p's row
+// pointer region of the arena (starts at c_rpt[0 .. rows), ends at
+// c_end[0 .. rows), c_end = c_rpt + rows + 1), and the later problems read
+// it through those two arrays (Lists::b_end).  The slots stay where they are:
+// the arena fill moves past them.
+__global__ __launch_bounds__(256) void k_b_keep_slots(BatchProb *tab, const int64_t *row_off, int np, int64_t R,
+                                                      const int64_t *S2, const int32_t *row_size, char *arena,
+                                                      BatchStatus *st) {
+    __shared__ ProbLookup lk;
+    load_lookup(lk, row_off, np);
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < R; g += (int64_t)gridDim.x * blockDim.x) {
+        const int p = find_prob(lk, row_off, np, g);
+        const BatchProb &pr = tab[p];
+        const int64_t r = g - pr.row_off;
+        int64_t *beg = reinterpret_cast<int64_t *>(arena + pr.rpt_off);
+        gstore(beg + r, S2[g]);
+        gstore(beg + (pr.rows + 1) + r, S2[g] + (int64_t)row_size[g]);
+    }
+}
+
+// then the kept problems' fields (the next launch: every row above has read them)
+
+__global__ __launch_bounds__(256) void k_b_keep_fields(BatchProb *tab, int np, char *arena, BatchStatus *st) {
+    if (st->flags & (kBatchOverflow | kBatchRowProducts)) return;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        BatchProb &pr = tab[p];
+        int64_t *beg = reinterpret_cast<int64_t *>(arena + pr.rpt_off);
+        pr.c_rpt = beg;
+        pr.c_end = beg + pr.rows + 1;
+        pr.nnz = -2;
+        pr.col_off = -1;
+        pr.val_off = -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) st->arena_used = st->slots_end;
+}
+
 __global__ void k_b_describe(const BatchProb *all, int n, spg_batched_out *out, const BatchStatus *st) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const BatchProb &p = all[i];
         spg_batched_out o;
         o.rows = p.rows;
         o.cols = p.ncols_b;
-        o.nnz = (st->flags & (kBatchOverflow | kBatchRowProducts)) ? -1 : p.nnz;
+        o.nnz = (st->flags & (kBatchOverflow | kBatchRowProducts)) ? -1 : p.nnz;  // -2: kept in slots
         o.rpt_off = p.rpt_off;
         o.col_off = p.col_off;
         o.val_off = p.val_off;
@@ -4339,6 +4390,7 @@ __global__ void k_b_zero_status(BatchStatus *st, Ctl *ctl) {
         st->spill_base = 0;
         st->s_col = nullptr;
         st->s_val = nullptr;
+        st->slots_end = 0;
         ctl->err = 0;
     }
 }
@@ -4432,7 +4484,7 @@ static void batched_stage_launches(const BatchStage &bs, const Workspace &ws, co
     } else {
         (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S2, &ws.ctl->nnz, s);
         hipLaunchKernelGGL(k_b_slot_plan, dim3(1), dim3(1024), 0, s, tab, np, bs.S2, R, bs.status, bs.arena,
-                           bs.arena_bytes, bs.data_off);
+                           bs.arena_bytes, bs.data_off, bs.keep);
         hipLaunchKernelGGL(k_b_heavy_plan<IA>, dim3(1), dim3(1024), 0, s, tab, ws.row_prob, ws.row_nprod,
                            ws.class_rows, ws.ctl, bs.status, bs.arena, bs.arena_bytes);
         no.bound = 1;
@@ -4441,7 +4493,12 @@ static void batched_stage_launches(const BatchStage &bs, const Workspace &ws, co
     }
     if (bs.upper) batched_numeric_launches<IA, IB, true>(bs, ws, th, no, grid_for, num_cu, s);
     else batched_numeric_launches<IA, IB, false>(bs, ws, th, no, grid_for, num_cu, s);
-    if (bs.upper) {
+    if (bs.upper && bs.keep) {
+        // operands only: the slots stay, described by their first and end positions
+        hipLaunchKernelGGL(k_b_keep_slots, dim3(ga), dim3(256), 0, s, tab, ro, np, R, bs.S2, ws.row_size, bs.arena,
+                           bs.status);
+        hipLaunchKernelGGL(k_b_keep_fields, dim3(1), dim3(256), 0, s, tab, np, bs.arena, bs.status);
+    } else if (bs.upper) {
         (void)launch_scan(R, ws.row_size, ws.tile_sum, bs.S, &ws.ctl->nnz, s);
         hipLaunchKernelGGL(k_b_distribute, dim3(1), dim3(1024), 0, s, tab, np, bs.S, bs.arena, bs.arena_bytes,
                            bs.data_off, bs.status);

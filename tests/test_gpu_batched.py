@@ -463,3 +463,94 @@ def test_autotuner_search_and_cache(tmp_path):
         assert res2["cached"] and res2["options"] == res["options"]
     finally:
         h2.close()
+
+
+def operand_only_cases():
+    """(name, problems without flags, index set of the stage-1 problems):
+    light chains (stage 2 has rows of one list: the copy class), Galerkin
+    chains, and a chain with heavy rows in both stages."""
+    rng = np.random.default_rng(12)
+    host = kernel_choice_inputs()[:6]
+    first = [(dev(A), dev(B)) for A, B in host]
+    second = []
+    for i, (A, B) in enumerate(host):
+        X = synth.random_csr(60, A.rows, 0.05, 500 + i, empty_row_frac=0.1)
+        second.append((dev(X), i))
+        second.append((dev(synth.permutation(rng.permutation(A.rows))), i))
+    light = (first, second)
+    inp = galerkin_inputs([4, 5, 6, 7, 9])
+    gal = ([(dev(A), dev(P)) for _, A, P, _ in inp], [(dev(Pt), i) for i, (_, _, _, Pt) in enumerate(inp)])
+    R = synth.rmat(10, 16, 6)
+    dR = dev(R)
+    heavy = ([(dR, dR)], [(dR, 0)])
+    return [("light", light), ("galerkin", gal), ("heavy chain", heavy)]
+
+
+def flagged(stages, flags):
+    first, second = stages
+    return brm.BatchedProblems([(A, B, flags) for A, B in first] + list(second))
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_operand_only_stage_keeps_its_slots(handle, noalloc):
+    # stage-1 outputs marked operand-only stay in their upper-bound slots and
+    # stage 2 reads them from there (rows described by start and end): stage
+    # 2's outputs are bitwise those of the materialized run; stage 1 reports
+    # nnz = -2 and returns nothing
+    handle.set_option(brm.OPT_BATCH_ALLOC, brm.BATCH_UPPER)
+    for name, stages in operand_only_cases():
+        print(f"case: operand-only stage 1, {name}, noalloc={noalloc}", flush=True)
+        n1 = len(stages[0])
+        ref, _, req_ref = run_until_fits(handle, flagged(stages, 0), 1 << 16, noalloc=noalloc)
+        ref = [to_host(C) for C in ref]
+        outs, arena, req = run_until_fits(handle, flagged(stages, brm.PROBLEM_OPERAND_ONLY), 1 << 16,
+                                          noalloc=noalloc)
+        assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+        assert all(o is None for o in outs[:n1])
+        for a, b in zip(ref[n1:], outs[n1:]):
+            same_bits(a, to_host(b))
+        print(f"  arena {req_ref} (materialized), {req} (kept)", flush=True)
+
+
+def test_operand_only_ignored_unless_whole_stage_and_upper(handle):
+    # precise sizes, or a stage where one problem is not an operand only:
+    # every C is materialized as usual
+    name, stages = operand_only_cases()[0]
+    first, second = stages
+    for mode in (brm.BATCH_PRECISE, brm.BATCH_UPPER):
+        handle.set_option(brm.OPT_BATCH_ALLOC, mode)
+        ref, _, _ = run_until_fits(handle, flagged(stages, 0), 1 << 16)
+        ref = [to_host(C) for C in ref]
+        mixed = [(A, B, brm.PROBLEM_OPERAND_ONLY if i else 0) for i, (A, B) in enumerate(first)]
+        cases = [brm.BatchedProblems(mixed + list(second))]
+        if mode == brm.BATCH_PRECISE:
+            cases.append(flagged(stages, brm.PROBLEM_OPERAND_ONLY))
+        for probs in cases:
+            outs, _, _ = run_until_fits(handle, probs, 1 << 16)
+            assert all(o is not None for o in outs)
+            for a, b in zip(ref, outs):
+                same_bits(a, to_host(b))
+    handle.set_option(brm.OPT_BATCH_ALLOC, brm.BATCH_PRECISE)
+
+
+def test_operand_only_galerkin_graph_replays(handle):
+    # the Galerkin call with A P kept in slots: direct launch, capture, replays
+    # with eager work between -- every G bitwise the materialized call's
+    inp = galerkin_inputs([5, 8, 6, 7])
+    triples = [(dev(A), dev(P), dev(Pt)) for _, A, P, Pt in inp]
+    handle.set_option(brm.OPT_BATCH_ALLOC, brm.BATCH_UPPER)
+    G0, AP0, _ = handle.galerkin(triples)
+    ref = [to_host(g) for g in G0]
+    probs = brm.Handle.galerkin_problems(triples, ap_operand_only=True)
+    arena = None
+    caps = handle.stat(brm.STAT_GRAPH_CAPTURES)
+    for k in range(4):
+        G, AP, arena = handle.galerkin(triples, arena, problems=probs)
+        torch.cuda.synchronize()
+        assert all(a is None for a in AP)
+        for r, g in zip(ref, G):
+            same_bits(r, to_host(g))
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    assert handle.stat(brm.STAT_GRAPH_CAPTURES) >= caps + 1 and handle.stat(brm.STAT_GRAPH_LAUNCHES) >= 2
+    handle.set_option(brm.OPT_BATCH_ALLOC, brm.BATCH_PRECISE)
