@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "a54cc054c0ff3902929435514106423d2e1c07304bad156c0b25087667d615d8",
-                 "fetch_kib": 1094044.0, "write_kib": 843590.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "8565506e8569df1cadf1e05825bc174952b59060833fc8cd0cde8c8d15a320cf",
+                 "fetch_kib": 1093985.0, "write_kib": 842868.5, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
