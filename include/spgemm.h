@@ -139,6 +139,15 @@ typedef enum {
     SPG_OPT_BATCH_ALLOC = 17,    /* sizes of the batched stages (spgemm_batched[_noalloc]):
                                     SPG_BATCH_PRECISE (default) or SPG_BATCH_UPPER, see below.
                                     Results are bitwise the same */
+    SPG_OPT_STORED_ORDER = 18,   /* 1 (default): with SPG_OPT_GROUP_ROWS = 1 and the precise
+                                    method, the symbolic pass keeps every wave-small row's merge
+                                    order (the sorted position of each product and whether the next
+                                    one repeats its column: 64 bytes) and its distinct columns (up to
+                                    64 x 4 bytes) in handle memory (320 bytes per row of A), and the
+                                    numeric pass gathers B's values only and applies that order
+                                    (the column gather and the merge network are not repeated).
+                                    0: the numeric pass merges its windows itself.  Results are
+                                    bitwise the same */
     SPG_OPT_GROUP_ROWS = 12      /* kernel of the wave-small class (rows of at most 64 products):
                                     1 (default) one row per wavefront, merged in registers; the
                                     class then holds only rows whose lists fit power-of-two lane

@@ -48,6 +48,7 @@ OPT_HEAVY_THREADS = 14
 OPT_HEAVY_SPLIT = 15
 OPT_LEARNED_HEAVY_MARGIN = 16
 OPT_BATCH_ALLOC = 17
+OPT_STORED_ORDER = 18
 PROBLEM_OPERAND_ONLY = 1
 BATCH_PRECISE = 0
 BATCH_UPPER = 1

@@ -99,6 +99,10 @@ struct spg_handle_s {
     int64_t batch_alloc = SPG_BATCH_PRECISE;  // sizes of the batched stages: symbolic pass or upper bounds
     int64_t heavy_margin_milli = 200;  // extra margin (thousandths) of rows beyond one workgroup's LDS
     bool plan_learned = false;
+    int64_t stored_order = 1;   // SPG_OPT_STORED_ORDER
+    bool plan_order = false;    // the last symbolic pass kept the wave-small rows' order
+    void *order_mem = nullptr;  // that order: [64 M] bytes, then [64 M] columns
+    size_t order_bytes = 0;
     void *lw_mem = nullptr;     // per-row learned workspace
     size_t lw_bytes = 0;
     void *slot_mem = nullptr;   // predicted slots (column and value arrays)
@@ -649,6 +653,7 @@ int spg_destroy(spg_handle h) {
     if (h->hitem_mem) (void)hipFree(h->hitem_mem);
     if (h->lw_mem) (void)hipFree(h->lw_mem);
     if (h->slot_mem) (void)hipFree(h->slot_mem);
+    if (h->order_mem) (void)hipFree(h->order_mem);
     if (h->ctl2) (void)hipFree(h->ctl2);
     if (h->mlp) (void)hipFree(h->mlp);
     if (h->mlp_act) (void)hipFree(h->mlp_act);
@@ -731,6 +736,10 @@ int spg_set_option(spg_handle h, int key, int64_t value) {
             if (value < 0 || value > 10000) return fail(h, SPG_ERR_ARG, "heavy margin must be 0..10000 (thousandths)");
             h->heavy_margin_milli = value;
             break;
+        case SPG_OPT_STORED_ORDER:
+            if (value != 0 && value != 1) return fail(h, SPG_ERR_ARG, "stored order must be 0 or 1");
+            h->stored_order = value;
+            break;
         case SPG_OPT_BATCH_ALLOC:
             if (value != SPG_BATCH_PRECISE && value != SPG_BATCH_UPPER)
                 return fail(h, SPG_ERR_ARG, "batched allocation must be SPG_BATCH_PRECISE or SPG_BATCH_UPPER");
@@ -765,6 +774,7 @@ int spg_get_option(spg_handle h, int key, int64_t *value) {
         case SPG_OPT_LEARNED_FORCE: *value = h->learned_force; break;
         case SPG_OPT_LEARNED_HEAVY_MARGIN: *value = h->heavy_margin_milli; break;
         case SPG_OPT_BATCH_ALLOC: *value = h->batch_alloc; break;
+        case SPG_OPT_STORED_ORDER: *value = h->stored_order; break;
         case SPG_OPT_ACCUMULATOR: *value = h->accumulator; break;
         default: return fail(h, SPG_ERR_ARG, "unknown option %d", key);
     }
@@ -851,6 +861,15 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
     if (uses_windows(gr) && B->cols >= ((int64_t)1 << 26)) gr = 0;
     h->plan_valid = false;
     h->plan_group_rows = gr;
+    // the precise method's wave-small rows in register windows keep their merge order
+    h->plan_order = false;
+    if (!slotted && gr == 1 && h->stored_order && M > 0) {
+        const size_t pb = align_up(64 * (size_t)M, 256);
+        if ((rc = grow(h, &h->order_mem, &h->order_bytes, pb + 4 * 64 * (size_t)M, "window order"))) return rc;
+        ws.order = static_cast<uint8_t *>(h->order_mem);
+        ws.ucol = reinterpret_cast<int32_t *>(static_cast<char *>(h->order_mem) + pb);
+        h->plan_order = true;
+    }
     if (learned && !h->mlp_ready) return fail(h, SPG_ERR_NOT_TRAINED, "learned allocation needs a trained or loaded predictor");
     h->heavy_batches = 0;
     h->heavy_wide = 0;
@@ -991,6 +1010,11 @@ int spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, const int64
     const CsrView a = view(A), b = view(B);
     Workspace ws;
     if ((rc = ensure_workspace(h, A->rows, A->nnz, &ws))) return rc;
+    if (h->plan_order && !h->plan_learned) {
+        ws.order = static_cast<uint8_t *>(h->order_mem);
+        ws.ucol = reinterpret_cast<int32_t *>(static_cast<char *>(h->order_mem) +
+                                              align_up(64 * (size_t)A->rows, 256));
+    }
     h->heavy_batches = 0;
     h->heavy_wide = 0;
     h->heavy_split_rows = 0;

@@ -91,6 +91,11 @@ struct Workspace {
     void *ent_bs;         // [nnz(A)] start of each A entry's B row (B's row-pointer type)
     int32_t *ent_len;     // [nnz(A)] length of each A entry's B row
     int32_t *row_prob;    // batched stages: [M] the problem of every row
+    // the precise method's wave-small rows with register windows: each row's
+    // merge order and distinct columns, kept by the symbolic pass for the
+    // numeric pass ([64 M] bytes and [64 M] columns), or nullptr
+    uint8_t *order = nullptr;
+    int32_t *ucol = nullptr;
 };
 
 constexpr int kScanTile = 4096;  // rows per scan tile (256 threads x 16)

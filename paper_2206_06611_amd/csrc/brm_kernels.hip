@@ -936,10 +936,24 @@ __global__ __launch_bounds__(T *TEAMS) void k_sym_group(int cls, const void *a_r
 }
 
 // pipelined counting of short rows (defined with the numeric kernels)
-template <bool HASH, typename IA, typename IB>
+// The order of the register windows of the wave-small class, kept by the
+// symbolic pass for the numeric pass of the precise method: for the class
+// row of index j, perm[64 j + t] is the source lane of position t of the
+// row's sorted window (bits 0-5) and whether the next position holds the
+// same column (bit 6), 0xFF for an empty position; ucol[64 j + i] is the
+// row's i-th distinct column.  The numeric pass then gathers B's values
+// only and takes the tree's additions on the stored order (the bits of the
+// merge are those of the round-by-round merges).
+struct WinOrder {
+    uint8_t *perm;
+    int32_t *ucol;
+};
+
+template <bool HASH, typename IA, typename IB, bool ORD>
 __global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lists<IB> lists,
                                                  const int32_t *b_col, const uint8_t *row_class,
-                                                 const int32_t *class_rows, int32_t *row_size, Ctl *ctl);
+                                                 const int32_t *class_rows, int32_t *row_size, Ctl *ctl,
+                                                 WinOrder ord);
 // counting of rows under multi-register windows (defined with the numeric kernels)
 template <typename IA, typename IB>
 __global__ __launch_bounds__(256) void k_sym_mw(int cls, const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
@@ -971,8 +985,17 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
             if (group_rows == 1 || group_rows == 2) {
                 // 1: window-merge counts, 2: LDS hash counts
 #define BRM_SYM_WIN(H, IA, IB)                                                                              \
-    hipLaunchKernelGGL((k_sym_win<H, IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), \
-                       B.col, ws.row_class, ws.class_rows, ws.row_size, ws.ctl)
+    do {                                                                                                    \
+        const WinOrder ord{ws.order, ws.ucol};                                                              \
+        if (!H && ws.order)                                                                                 \
+            hipLaunchKernelGGL((k_sym_win<H, IA, IB, true>), dim3(grid), dim3(256), 0, s, cls, A.rpt,        \
+                               ws_lists<IB>(A, B, ws), B.col, ws.row_class, ws.class_rows, ws.row_size,     \
+                               ws.ctl, ord);                                                                \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_sym_win<H, IA, IB, false>), dim3(grid), dim3(256), 0, s, cls, A.rpt,       \
+                               ws_lists<IB>(A, B, ws), B.col, ws.row_class, ws.class_rows, ws.row_size,     \
+                               ws.ctl, ord);                                                                \
+    } while (0)
 #define BRM_SYM_WIN_ALL(H)                                                        \
     if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_SYM_WIN(H, int32_t, int32_t);  \
     else if (A.rpt_bytes == 4) BRM_SYM_WIN(H, int32_t, int64_t);                 \
@@ -1918,6 +1941,32 @@ __device__ __forceinline__ uint64_t tree_adds(uint32_t k, double &v, int lsw, in
     return heads;
 }
 
+// tree_adds on a window whose order was stored by the symbolic pass: the
+// lane's entry came from lane src, is live or not, and holds the same column
+// as the next lane's (same_next).  The same grouping of additions.
+__device__ __forceinline__ uint64_t tree_adds_stored(bool live, bool same_next, int src, double &v, int lsw, int T,
+                                                     int lane, int levels) {
+    const bool first = (lane & (T - 1)) == 0;
+    // a run's first lane: the previous lane (shifted in every lane) holds another column
+    const uint32_t psame = lane_prev(same_next ? 1u : 0u);
+    const bool head = live && (first || psame == 0u);
+    const uint64_t heads = wave_ballot(head);
+    if (wave_ballot(same_next) == 0ull) return heads;  // no column repeats: nothing to add
+    const int li = (src & (T - 1)) >> lsw;
+    const int li_next = (int)lane_next((uint32_t)li);
+    const int lvl = same_next ? 32 - __clz(li ^ li_next) : 64;
+    const int plvl = (int)lane_prev((uint32_t)lvl) | (first ? 64 : 0);
+    for (int r = 1; r <= levels; ++r) {
+        const uint64_t ends = wave_ballot(lvl >= r);
+        const uint64_t meet = wave_ballot(lvl == r);
+        const int e = lane + __builtin_ctzll(ends >> lane);
+        const double w = __shfl(v, e + 1 < kWave ? e + 1 : e, kWave);
+        const bool rep = head || plvl >= r;
+        if (live && rep && ((meet >> e) & 1ull)) v = v + w;  // left + right
+    }
+    return heads;
+}
+
 // Symbolic use: the same merges on bare columns (empty = all ones), equal
 // columns left in place; the lanes holding the first entry of a distinct
 // column are returned as a mask.  A second row may start at lane `seg`
@@ -1990,13 +2039,13 @@ __device__ __forceinline__ T load_opaque(const T *p) {
 // items in flight behind the one being merged in the numeric window pipeline
 constexpr int kWinNumDepth = 3;
 
-template <bool VALUES, bool HASH, typename IA, typename IB, bool BATCH = false>
+template <bool VALUES, bool HASH, typename IA, typename IB, bool BATCH = false, bool ORD = false>
 __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
                                            const int32_t *b_col, const double *b_val, const uint8_t *row_class,
                                            const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
                                            double *c_val, int32_t *row_size, Ctl *ctl, const NumOut &no,
                                            int32_t *tab, uint32_t *xk, double *xv, int64_t first, int64_t stride,
-                                           BatchRows br = BatchRows{}) {
+                                           BatchRows br = BatchRows{}, WinOrder ord = WinOrder{nullptr, nullptr}) {
     const int lane = lane_id();
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
@@ -2051,6 +2100,8 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
         struct GatherRegs {  // B entries of one item in the lane windows
             int32_t c;
             double bv, av;
+            uint32_t q;  // stored order: the lane's byte of it
+            int32_t u;   // stored order: the lane's distinct column of its row
         };
         uint64_t ovf_mask = 0;  // rows of the chunk that overflowed their slot (slot mode)
         // the length of chunk row j is known: slot bookkeeping or the check
@@ -2151,7 +2202,8 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             // multiplying phase of item v into the lane windows (the products
             // are formed where the row is consumed): lane t of a row's lanes
             // holds entry t mod W0 of its list t / W0
-            auto gather = [&](int v, IB bs, int ln, double av, int32_t &c, double &bv, double &lav) {
+            auto gather = [&](int v, IB bs, int ln, double av, int32_t &c, double &bv, double &lav, uint32_t &q,
+                              int32_t &u) {
                 int a, b;
                 item(v, a, b);
                 const int L = lists_of(v, a, b);
@@ -2169,7 +2221,20 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     BATCH ? reinterpret_cast<const int32_t *>(
                                 pick(a, b, [](const auto &q) { return reinterpret_cast<int64_t>(q.b_col); }))
                           : b_col;
-                c = load_opaque(ok ? bc + (lbs + o) : &g_empty_col[0]);
+                if constexpr (ORD && VALUES) {
+                    // the columns come with the stored order
+                    c = 0;
+                    const int rr = (P && lane >= kHalf) ? b : a;
+                    const int T = P ? kHalf : lane_value(m_T, a);
+                    const bool inrow = v < nv && rr >= 0 && t < T;
+                    const int64_t at = (base + (inrow ? rr : 0)) * kWave + t;
+                    q = inrow ? (uint32_t)load_opaque(ord.perm + at) : 0xFFu;
+                    u = load_opaque(inrow ? ord.ucol + at : &g_empty_col[0]);
+                } else {
+                    c = load_opaque(ok ? bc + (lbs + o) : &g_empty_col[0]);
+                    q = 0xFFu;
+                    u = 0;
+                }
                 bv = 0.0;
                 if constexpr (VALUES) {
                     const double *bvp =
@@ -2187,7 +2252,7 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             // v+D-1 (from li) -> go, accumulating phase and write-out of item v
             auto step = [&](int v, const ListStageRegs &li, ListStageRegs &lo, const GatherRegs &gi, GatherRegs &go) {
                 load_lists(v + D, lo.bs, lo.ln, lo.av);
-                gather(v + D - 1, li.bs, li.ln, li.av, go.c, go.bv, go.av);
+                gather(v + D - 1, li.bs, li.ln, li.av, go.c, go.bv, go.av, go.q, go.u);
                 int a, b;
                 item(v, a, b);
                 // a pair runs the rounds of both rows: from the narrower list
@@ -2208,6 +2273,33 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     const int len = __popcll(wave_ballot(added != 0));
                     wave_sync();
                     done(a, len);
+                } else if constexpr (!VALUES && ORD) {
+                    // sorted (column, lane) keys: the row's size, and its order kept for the numeric pass
+                    uint32_t k = gi.c == kEmptyCol ? (kKeyEmpty | (uint32_t)lane)
+                                                   : (((uint32_t)gi.c << kKeyLaneBits) | (uint32_t)lane);
+                    key_sort(k, 1 << sw, T, lane);
+                    const bool live = k < kKeyEmpty;
+                    const uint32_t col = k >> kKeyLaneBits;
+                    const uint32_t nk = lane_next(k), pk = lane_prev(k);
+                    const bool first = (lane & (T - 1)) == 0, last = ((lane + 1) & (T - 1)) == 0;
+                    const bool same = live && !last && nk < kKeyEmpty && (nk >> kKeyLaneBits) == col;
+                    const bool head = live && (first || pk >= kKeyEmpty || (pk >> kKeyLaneBits) != col);
+                    const uint64_t hm = wave_ballot(head);
+                    const int rr = (P && lane >= kHalf) ? b : a;
+                    const int t = P ? (lane & (kHalf - 1)) : lane;
+                    if (rr >= 0 && t < T) {
+                        const int64_t at = (base + rr) * kWave;
+                        gstore(ord.perm + at + t,
+                               (uint8_t)(live ? ((k & kKeyLaneMask) | (same ? 64u : 0u)) : 0xFFu));
+                        const uint64_t rowm = !P ? ~0ull : lane >= kHalf ? ~0ull << kHalf : ~0ull >> kHalf;
+                        if (head) gstore(ord.ucol + at + __popcll(hm & rowm & ((1ull << lane) - 1ull)), (int32_t)col);
+                    }
+                    if constexpr (P) {
+                        done(a, __popcll(hm & 0xffffffffull));
+                        if (b >= 0) done(b, __popcll(hm >> kHalf));
+                    } else {
+                        done(a, __popcll(hm));
+                    }
                 } else if constexpr (!VALUES) {
                     const uint64_t m = distinct_merged(gi.c == kEmptyCol ? ~0u : (uint32_t)gi.c, 1 << sw, T, lane,
                                                        P ? kHalf : kWave);
@@ -2224,7 +2316,22 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                     uint64_t lm;
                     bool live;
                     int pos;
-                    if constexpr (BATCH) {
+                    if constexpr (ORD && !BATCH) {
+                        // the order the symbolic pass kept: the values in it, then the tree's additions
+                        (void)k;
+                        live = gi.q != 0xFFu;
+                        const int src = (int)(gi.q & kKeyLaneMask);
+                        const bool same = live && ((gi.q >> 6) & 1u);
+                        v = __shfl(v, src, kWave);
+                        const int lsw = P ? sel32(m_sw, a, b) : sw;  // the lane's own row's list width
+                        lm = tree_adds_stored(live, same, src, v, lsw, T, lane, ceil_log2(T) - sw);
+                        live = (lm >> lane) & 1ull;
+                        const uint64_t rowm = !P ? ~0ull : lane >= kHalf ? ~0ull << kHalf : ~0ull >> kHalf;
+                        pos = __popcll(lm & rowm & ((1ull << lane) - 1ull));
+                        // the column: the row's pos-th distinct column (held by lane pos of the row's lanes)
+                        const int ul = (P && lane >= kHalf ? kHalf : 0) + (pos & (kWave - 1));
+                        k = (uint32_t)__shfl(gi.u, ul < kWave ? ul : 0, kWave) << kKeyLaneBits;
+                    } else if constexpr (BATCH) {
                         // one sort, then the tree's additions level by level
                         // (rows of single-entry lists with many repeated
                         // columns: no compaction between rounds)
@@ -2279,7 +2386,8 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                 load_lists(i, l[i].bs, l[i].ln, l[i].av);
             }
 #pragma unroll
-            for (int i = 0; i + 1 < D; ++i) gather(i, l[i].bs, l[i].ln, l[i].av, g[i].c, g[i].bv, g[i].av);
+            for (int i = 0; i + 1 < D; ++i)
+                gather(i, l[i].bs, l[i].ln, l[i].av, g[i].c, g[i].bv, g[i].av, g[i].q, g[i].u);
             // unrolled by D: the register sets rotate roles, so no register
             // with a load in flight is copied at the loop latch
             for (int v = 0; v < nv; v += D) {
@@ -2292,6 +2400,7 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
             for (int i = 0; i < D; ++i) {
                 asm volatile("" ::"v"(g[i].c), "v"(l[i].ln), "v"(l[i].bs));
                 if constexpr (VALUES) asm volatile("" ::"v"(g[i].bv), "v"(l[i].av));
+                if constexpr (ORD && VALUES) asm volatile("" ::"v"(g[i].q), "v"(g[i].u));
             }
         };
         if (all_small) run(std::true_type{});
@@ -2314,31 +2423,37 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
     }
 }
 
-template <typename IA, typename IB>
+// ORD: the numeric pass of the precise method with the order the symbolic
+// pass kept (ord), else the merges of the windows themselves
+template <typename IA, typename IB, bool ORD>
 __global__ __launch_bounds__(256) void k_num_win(int cls, const void *a_rpt, Lists<IB> lists,
                                                  const double *a_val, const int32_t *b_col,
                                                  const double *b_val, const uint8_t *row_class,
                                                  const int32_t *class_rows, const int64_t *c_rpt, int32_t *c_col,
-                                                 double *c_val, Ctl *ctl, NumOut no) {
+                                                 double *c_val, Ctl *ctl, NumOut no, WinOrder ord) {
     __shared__ uint32_t xk[4][kWave];
     __shared__ double xv[4][kWave];
     const int team = wave_uniform((int)(threadIdx.x / kWave));
-    win_chunks<true, false, IA, IB>(cls, a_rpt, lists, a_val, b_col, b_val, row_class, class_rows, c_rpt, c_col,
-                                    c_val, nullptr, ctl, no, nullptr, xk[team], xv[team],
-                                    (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
+    win_chunks<true, false, IA, IB, false, ORD>(cls, a_rpt, lists, a_val, b_col, b_val, row_class, class_rows,
+                                                c_rpt, c_col, c_val, nullptr, ctl, no, nullptr, xk[team], xv[team],
+                                                (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4, BatchRows{},
+                                                ord);
 }
 
-template <bool HASH, typename IA, typename IB>
+// ORD: the symbolic pass also keeps each row's window order for the numeric pass
+template <bool HASH, typename IA, typename IB, bool ORD>
 __global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lists<IB> lists,
                                                  const int32_t *b_col, const uint8_t *row_class,
-                                                 const int32_t *class_rows, int32_t *row_size, Ctl *ctl) {
+                                                 const int32_t *class_rows, int32_t *row_size, Ctl *ctl,
+                                                 WinOrder ord) {
     __shared__ int32_t tab[4][2 * kWave];
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     NumOut no;
     no.bound = 0;
-    win_chunks<false, HASH, IA, IB>(cls, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows, nullptr,
-                                    nullptr, nullptr, row_size, ctl, no, tab[team], nullptr, nullptr,
-                                    (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
+    win_chunks<false, HASH, IA, IB, false, ORD>(cls, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows,
+                                                nullptr, nullptr, nullptr, row_size, ctl, no, tab[team], nullptr,
+                                                nullptr, (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4,
+                                                BatchRows{}, ord);
 }
 
 // ---------------------------------------------------------------------------
@@ -2955,8 +3070,17 @@ hipError_t launch_numeric(const CsrView &A, const CsrView &B, const Workspace &w
             }
             if (group_rows == 1 || group_rows == 2) {
 #define BRM_NUM_WIN(IA, IB)                                                                                      \
-    hipLaunchKernelGGL((k_num_win<IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), A.val, \
-                       B.col, B.val, ws.row_class, ws.class_rows, c_rpt, c_col, c_val, ws.ctl, no)
+    do {                                                                                                         \
+        const WinOrder ord{ws.order, ws.ucol};                                                                   \
+        if (ws.order && !no.bound)                                                                               \
+            hipLaunchKernelGGL((k_num_win<IA, IB, true>), dim3(grid), dim3(256), 0, s, cls, A.rpt,                \
+                               ws_lists<IB>(A, B, ws), A.val, B.col, B.val, ws.row_class, ws.class_rows, c_rpt,  \
+                               c_col, c_val, ws.ctl, no, ord);                                                   \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_num_win<IA, IB, false>), dim3(grid), dim3(256), 0, s, cls, A.rpt,               \
+                               ws_lists<IB>(A, B, ws), A.val, B.col, B.val, ws.row_class, ws.class_rows, c_rpt,  \
+                               c_col, c_val, ws.ctl, no, ord);                                                   \
+    } while (0)
                 if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_NUM_WIN(int32_t, int32_t);
                 else if (A.rpt_bytes == 4) BRM_NUM_WIN(int32_t, int64_t);
                 else if (B.rpt_bytes == 4) BRM_NUM_WIN(int64_t, int32_t);

@@ -444,3 +444,70 @@ def test_paired_short_rows(handle, seed):
     C = run(handle, A, B)
     assert handle.class_rows()["wave_small"] > 500
     assert_matches_oracle(C, ref, model)
+
+
+def _repeat_heavy_short_rows(seed, ncols=40):
+    """Rows of 1..8 lists over B rows whose columns fall in a narrow range
+    (many repeated columns per row), mixed widths so that paired and single
+    64-lane windows both occur."""
+    rng = np.random.default_rng(seed)
+    K = 2000
+    B = synth.random_csr(K, ncols, 0.15, seed + 300)
+    rows = []
+    for i in range(3000 + seed):
+        L = int(rng.choice([1, 2, 3, 4, 6, 8]))
+        rows.append(np.sort(rng.choice(K, size=L, replace=False)))
+    rpt = np.zeros(len(rows) + 1, np.int64)
+    rpt[1:] = np.cumsum([len(r) for r in rows])
+    A = synth.CSR(len(rows), K, rpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                  rng.uniform(-1, 1, rpt[-1]))
+    return A, B
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_stored_order_matches_window_merges(handle, seed):
+    # the numeric pass applying the order the symbolic pass kept (default)
+    # and the numeric pass merging its windows itself: the same bits, both
+    # bitwise Algorithm 1's tree; rows with many repeated columns, paired
+    # short rows and full 64-lane rows (ER-8 rows)
+    cases = [_repeat_heavy_short_rows(seed), (synth.erdos_renyi_rows(1 << 12, 8, seed + 7),) * 2]
+    try:
+        for A, B in cases:
+            ref, model = oracle.spgemm(A, B), oracle.brmerge(A, B)
+            outs = {}
+            for so in (1, 0):
+                print(f"case: stored order {so}, {A.rows} rows", flush=True)
+                handle.set_option(brm.OPT_STORED_ORDER, so)
+                C = run(handle, A, B)
+                assert handle.class_rows()["wave_small"] > A.rows // 4
+                assert_matches_oracle(C, ref, model)
+                outs[so] = to_host(C)
+            for x, y in zip(outs[0], outs[1]):
+                assert np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                                      y.view(np.int64) if y.dtype == np.float64 else y)
+    finally:
+        handle.set_option(brm.OPT_STORED_ORDER, 1)
+
+
+def test_stored_order_new_values_between_passes(handle):
+    # the kept order is structure only: values changed between the passes
+    # (same arrays) are the ones the numeric pass multiplies
+    A, B = _repeat_heavy_short_rows(5)
+    dA, dB = brm.DeviceCSR.from_host(A), brm.DeviceCSR.from_host(B)
+    c_rpt, nnz = handle.symbolic(dA, dB)
+    A2 = synth.CSR(A.rows, A.cols, A.rpt, A.col, np.random.default_rng(6).uniform(-2, 2, A.nnz))
+    dA.val.copy_(torch.as_tensor(A2.val, device=dA.val.device))
+    c_col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    c_val = torch.empty(nnz, dtype=torch.float64, device="cuda")
+    handle.numeric(dA, dB, c_rpt, c_col, c_val)
+    torch.cuda.synchronize()
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    C = brm.DeviceCSR(A.rows, B.cols, c_rpt, c_col, c_val)
+    assert_matches_oracle(C, oracle.spgemm(A2, B), oracle.brmerge(A2, B))
+
+
+def test_stored_order_option_range(handle):
+    assert handle.get_option(brm.OPT_STORED_ORDER) == 1
+    for bad in (-1, 2):
+        with pytest.raises(brm.SpgError):
+            handle.set_option(brm.OPT_STORED_ORDER, bad)
