@@ -2036,8 +2036,12 @@ __device__ __forceinline__ T load_opaque(const T *p) {
 // windows both fit 32 lanes are merged together, one in each half of the
 // wavefront.  VALUES = false counts row sizes; HASH then selects counting by
 // LDS hash instead of window merges (one row at a time).
-// items in flight behind the one being merged in the numeric window pipeline
+// items in flight behind the one being merged in the numeric window pipeline,
+// and in the numeric pipeline that applies a stored order (fewer registers per
+// item: B's values, the order byte and a column; ER-8 numeric 445 -> 428 us
+// from 3 to 6 items, 103 VGPRs and 4 waves per SIMD; 8 gave the same, 10 less)
 constexpr int kWinNumDepth = 3;
+constexpr int kWinOrdDepth = 6;
 
 template <bool VALUES, bool HASH, typename IA, typename IB, bool BATCH = false, bool ORD = false>
 __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lists<IB> &lists, const double *a_val,
@@ -2245,9 +2249,10 @@ __device__ __forceinline__ void win_chunks(int cls, const void *a_rpt, const Lis
                 }
             };
             // pipeline depth: the numeric pass keeps D = kWinNumDepth items in
-            // flight behind the one being merged, the symbolic pass (column
-            // gathers only, slower with more in flight) D = 2
-            constexpr int D = VALUES ? kWinNumDepth : 2;
+            // flight behind the one being merged (kWinOrdDepth with a stored
+            // order), the symbolic pass (column gathers only, slower with
+            // more in flight) D = 2
+            constexpr int D = VALUES ? (ORD ? kWinOrdDepth : kWinNumDepth) : 2;
             // one pipeline step: lists of item v+D -> lo, B entries of item
             // v+D-1 (from li) -> go, accumulating phase and write-out of item v
             auto step = [&](int v, const ListStageRegs &li, ListStageRegs &lo, const GatherRegs &gi, GatherRegs &go) {
