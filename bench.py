@@ -32,8 +32,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2206_06611_amd/csrc/brm_kernels.hip", "paper_2206_06611_amd/csrc/brm_device.h",
                   "paper_2206_06611_amd/csrc/brm_internal.h")
 TRAFFIC = {
-    "er8_2e20": {"sources_sha256": "f77fa5a602125883721ce9c71f81bdad8a4940bdc4bf9a1addd460bc7ea64b60",
-                 "fetch_kib": 758676.2, "write_kib": 842980.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "er8_2e20": {"sources_sha256": "a21609780e8d07028cbae61326edab5002c1967d066edc8846ce1614b99bf8aa",
+                 "fetch_kib": 748159.3, "write_kib": 809933.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
@@ -594,8 +594,8 @@ def rmat20_extra(steps=2, warmup=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="er8_2e20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the learned and batched comparisons")
