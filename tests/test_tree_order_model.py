@@ -102,3 +102,102 @@ def test_three_lists_group_as_the_tree():
     assert tree_adds_row([5, 5, 5], [a, b, c], [0, 1, 2]) == [(5, (a + b) + c)]
     assert tree_adds_row([5, 5, 5], [a, b, c], [0, 2, 3]) == [(5, a + (b + c))]
     assert (a + b) + c != a + (b + c)
+
+
+def stored_order_row(lists, avals, bvals):
+    """The symbolic and numeric passes of a wave-small row with a stored
+    order, as the window kernels lay them out: list p's entry o sits in lane
+    p * W0 + o (W0 the next power of two of the longest list, T = W0 times
+    the next power of two of the list count, at most 64 lanes).  The
+    symbolic pass sorts (column << 6 | lane) keys and keeps, for every
+    position t < T, the source lane (bits 0-5) and whether position t + 1
+    holds the same column (bit 6), 0xFF for an empty position, and the
+    distinct columns in order.  The numeric pass moves the lanes' products
+    into that order and adds by levels: a run's first position is live with
+    a previous position that does not repeat its column; two positions of
+    a column meet at the level of the highest bit of their lists' xor."""
+    L = len(lists)
+    W0 = 1
+    while W0 < max(len(c) for c in lists):
+        W0 *= 2
+    nl = 1
+    while nl < L:
+        nl *= 2
+    T = W0 * nl
+    assert T <= 64
+    lsw = W0.bit_length() - 1
+    EMPTY = (1 << 32) - 64
+    keys, prod = [], {}
+    for p, cols in enumerate(lists):
+        for o, c in enumerate(cols):
+            lane = p * W0 + o
+            keys.append((int(c) << 6) | lane)
+            prod[lane] = avals[p] * bvals[p][o]
+    keys.sort()
+    keys += [EMPTY | t for t in range(len(keys), T)]
+    # symbolic pass: the kept bytes and distinct columns
+    perm, ucol = [], []
+    for t in range(T):
+        k = keys[t]
+        live = k < EMPTY
+        same = live and t + 1 < T and keys[t + 1] < EMPTY and (keys[t + 1] >> 6) == (k >> 6)
+        perm.append(((k & 63) | (64 if same else 0)) if live else 0xFF)
+        head = live and (t == 0 or keys[t - 1] >= EMPTY or (keys[t - 1] >> 6) != (k >> 6))
+        if head:
+            ucol.append(k >> 6)
+    # numeric pass: only the bytes, the distinct columns and the products
+    live = [q != 0xFF for q in perm]
+    same = [live[t] and bool(perm[t] & 64) for t in range(T)]
+    src = [perm[t] & 63 for t in range(T)]
+    v = [prod[src[t]] if live[t] else 0.0 for t in range(T)]
+    head = [live[t] and (t == 0 or not same[t - 1]) for t in range(T)]
+    li = [(src[t] & (T - 1)) >> lsw for t in range(T)]
+    INF = 1 << 30
+    lvl = [lca_level(li[t], li[t + 1]) if same[t] else INF for t in range(T)]
+    for r in range(1, (T.bit_length() - 1) - lsw + 1):
+        nv = list(v)
+        for j in range(T):
+            if not (live[j] and (head[j] or (j > 0 and lvl[j - 1] >= r))):
+                continue
+            e = j
+            while lvl[e] < r:
+                e += 1
+            if lvl[e] == r:
+                nv[j] = v[j] + v[e + 1]
+        v = nv
+    out = [v[t] for t in range(T) if head[t]]
+    assert len(out) == len(ucol)
+    return list(zip(ucol, out))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_stored_order_bytes_give_algorithm_1_sums(seed):
+    # rows of at most 64 products in lane windows, many repeated columns;
+    # every row bitwise the oracle's run of Algorithm 1
+    rng = np.random.default_rng(40 + seed)
+    K, N = 300, int(rng.choice([5, 12, 60]))
+    B = synth.random_csr(K, N, float(rng.uniform(0.05, 0.3)), 300 + seed, empty_row_frac=0.1)
+    blen = np.diff(B.rpt.astype(np.int64))
+    rows = []
+    while len(rows) < 150:
+        L = int(rng.integers(1, 17))
+        lists = np.sort(rng.choice(K, size=L, replace=False))
+        W0 = 1 << int(max(1, int(blen[lists].max()))  - 1).bit_length()
+        nl = 1 << int(L - 1).bit_length()
+        if W0 * nl <= 64 and blen[lists].sum() > 0:
+            rows.append(lists)
+    rpt = np.zeros(len(rows) + 1, np.int64)
+    rpt[1:] = np.cumsum([len(r) for r in rows])
+    A = synth.CSR(len(rows), K, rpt.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                  rng.uniform(-1, 1, int(rpt[-1])))
+    ref = oracle.brmerge(A, B)
+    repeats = 0
+    for i in range(A.rows):
+        lists = [B.col[B.rpt[k]:B.rpt[k + 1]] for k in A.col[A.rpt[i]:A.rpt[i + 1]]]
+        bv = [B.val[B.rpt[k]:B.rpt[k + 1]] for k in A.col[A.rpt[i]:A.rpt[i + 1]]]
+        got = stored_order_row(lists, A.val[A.rpt[i]:A.rpt[i + 1]], bv)
+        exp = list(zip(ref.col[ref.rpt[i]:ref.rpt[i + 1]].tolist(), ref.val[ref.rpt[i]:ref.rpt[i + 1]].tolist()))
+        assert [c for c, _ in got] == [c for c, _ in exp], f"row {i}: columns"
+        assert all(same_bits(x, y) for (_, x), (_, y) in zip(got, exp)), f"row {i}: values"
+        repeats += sum(len(c) for c in lists) - len(exp)
+    assert repeats > 0
