@@ -900,8 +900,9 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
             HIP_TRY(h, launch_symbolic_mid(a, b, ws, persistent_grid(h, kClassMulti, -1, gr),
                                            persistent_grid(h, kClassWave, -1, gr),
                                            persistent_grid(h, kClassGroup, -1, gr), s));
-            for (int cls : {(int)kClassBlock, (int)kClassHeavy})
-                HIP_TRY(h, launch_symbolic(a, b, ws, cls, persistent_grid(h, cls, -1, gr), s, gr));
+            // so do the block class and the heavy rows
+            HIP_TRY(h, launch_symbolic_big(a, b, ws, persistent_grid(h, kClassBlock, -1, gr),
+                                           persistent_grid(h, kClassHeavy, -1, gr), s));
         }
     }
     if (slotted) {

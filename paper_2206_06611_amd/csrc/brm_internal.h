@@ -98,7 +98,7 @@ struct Workspace {
     int32_t *ucol = nullptr;
 };
 
-constexpr int kScanTile = 4096;  // rows per scan tile (256 threads x 16)
+constexpr int kScanTile = 1024;  // rows per scan tile (256 threads x 4)
 
 // ---- launchers (brm_kernels.hip) -----------------------------------------
 hipError_t launch_zero_ctl(Ctl *ctl, hipStream_t s);
@@ -130,6 +130,9 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
 // launch of g_mw + g_wave + g_group workgroups of 256 threads
 hipError_t launch_symbolic_mid(const CsrView &A, const CsrView &B, const Workspace &ws, int g_mw, int g_wave,
                                int g_group, hipStream_t s);
+// the block class and the heavy rows in one launch of 1024-thread workgroups
+hipError_t launch_symbolic_big(const CsrView &A, const CsrView &B, const Workspace &ws, int g_block, int g_heavy,
+                               hipStream_t s);
 hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
                        int64_t *total, hipStream_t s);
 

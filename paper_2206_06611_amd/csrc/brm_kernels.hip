@@ -847,20 +847,67 @@ __device__ __forceinline__ int64_t sym_bitmap_row(BitmapLds &s, int tid, int64_t
     return total;
 }
 
+// the rows of one class counted by the bitmap, one row per workgroup at a
+// time; `block` of `grid` workgroups take part
 template <typename IA, typename IB>
-__global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
-    int cls, int64_t ncols, const void *a_rpt, Lists<IB> lists,
-    const int32_t *b_col, const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
-    __shared__ BitmapLds s;
+__device__ __forceinline__ void sym_bitmap_rows(BitmapLds &s, int cls, int64_t block, int64_t grid, int64_t ncols,
+                                                const void *a_rpt, const Lists<IB> &lists, const int32_t *b_col,
+                                                const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
     const int tid = threadIdx.x;
     const int64_t count = ctl->count[cls];
     const int64_t start = class_start(ctl, cls);
-    for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    for (int64_t idx = block; idx < count; idx += grid) {
         const int64_t row = class_rows[start + idx];
         const int64_t total = sym_bitmap_row<IA, IB>(s, tid, row, ncols, a_rpt, lists, b_col);
         if (tid == 0) row_size[row] = (int32_t)total;
         __syncthreads();
     }
+}
+
+template <typename IA, typename IB>
+__global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
+    int cls, int64_t ncols, const void *a_rpt, Lists<IB> lists,
+    const int32_t *b_col, const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
+    __shared__ BitmapLds s;
+    sym_bitmap_rows<IA, IB>(s, cls, blockIdx.x, gridDim.x, ncols, a_rpt, lists, b_col, class_rows, row_size, ctl);
+}
+
+// The symbolic passes of the block class (LDS hash, one row per workgroup)
+// and of the heavy rows (LDS bitmap) in one launch of 1024-thread
+// workgroups: workgroups [0, g_block) count the block class, the rest the
+// heavy rows, each in the same LDS.  A class without rows then costs no
+// launch of its own, and the heavy rows start on the CUs the block class
+// has left.
+template <typename IA, typename IB>
+__global__ __launch_bounds__(kHeavyThreads) void k_sym_big(int64_t ncols, const void *a_rpt, Lists<IB> lists,
+                                                           const int32_t *b_col, const int32_t *class_rows,
+                                                           int32_t *row_size, const Ctl *ctl, int g_block) {
+    using BlockLds = SymLds<kHeavyThreads, 2 * kCapBlock>;
+    constexpr size_t kBlockBytes = sizeof(BlockLds), kHeavyBytes = sizeof(BitmapLds);
+    __shared__ __align__(16) unsigned char raw[kBlockBytes > kHeavyBytes ? kBlockBytes : kHeavyBytes];
+    const int b = blockIdx.x;  // uniform: every workgroup takes one branch whole
+    if (b < g_block)
+        sym_hash_rows<kHeavyThreads, 1, 2 * kCapBlock, IA, IB>(reinterpret_cast<BlockLds *>(raw), kClassBlock, b,
+                                                               g_block, a_rpt, lists, b_col, class_rows, row_size,
+                                                               ctl);
+    else
+        sym_bitmap_rows<IA, IB>(*reinterpret_cast<BitmapLds *>(raw), kClassHeavy, b - g_block,
+                                (int64_t)gridDim.x - g_block, ncols, a_rpt, lists, b_col, class_rows, row_size,
+                                ctl);
+}
+
+hipError_t launch_symbolic_big(const CsrView &A, const CsrView &B, const Workspace &ws, int g_block, int g_heavy,
+                               hipStream_t s) {
+    const int grid = g_block + g_heavy;
+#define BRM_SYM_BIG(IA, IB)                                                                                \
+    hipLaunchKernelGGL((k_sym_big<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, B.cols, A.rpt,             \
+                       ws_lists<IB>(A, B, ws), B.col, ws.class_rows, ws.row_size, ws.ctl, g_block)
+    if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_SYM_BIG(int32_t, int32_t);
+    else if (A.rpt_bytes == 4) BRM_SYM_BIG(int32_t, int64_t);
+    else if (B.rpt_bytes == 4) BRM_SYM_BIG(int64_t, int32_t);
+    else BRM_SYM_BIG(int64_t, int64_t);
+#undef BRM_SYM_BIG
+    return hipGetLastError();
 }
 
 // symbolic for several short rows per team: one hash table of TS slots per row
@@ -1054,7 +1101,7 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
 // scan: row sizes (int32) -> C's row pointers (int64) and nnz(C)
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 256;
-constexpr int kScanPer = kScanTile / kScanThreads;  // 16 rows per thread
+constexpr int kScanPer = kScanTile / kScanThreads;  // 4 rows per thread
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t M, const int32_t *row_size,
                                                               int64_t *tile_sum) {
@@ -1110,7 +1157,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t M, const in
 // The top-level scan folded into the apply pass, for at most kScanFusedTiles
 // tiles: every block adds up the sums of the tiles before its own (one
 // strided pass and a block reduction), the last one also writes the total.
-constexpr int64_t kScanFusedTiles = 1024;
+constexpr int64_t kScanFusedTiles = 4096;
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply_fused(int64_t M, int64_t ntiles,
                                                                    const int32_t *row_size,

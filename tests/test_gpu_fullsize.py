@@ -137,8 +137,8 @@ def test_rmat_scale21_row_blocks():
 
 @pytest.mark.parametrize("rows", [4096 * 1024, 4096 * 1024 + 1, 5_000_000])
 def test_row_pointer_scan_either_side_of_fused_limit(rows):
-    # the row-pointer scan folds its top level into the apply pass up to 1024
-    # tiles of 4096 rows and runs three passes beyond: a scaled permutation
+    # the row-pointer scan folds its top level into the apply pass up to 4096
+    # tiles of 1024 rows and runs three passes beyond: a scaled permutation
     # squared has one entry per row, C[i, p[p[i]]] = a[i] * a[p[i]]
     print(f"case: permutation squared, {rows} rows", flush=True)
     rng = np.random.default_rng(rows)
