@@ -72,6 +72,9 @@ struct spg_handle_s {
     size_t ws_bytes = 0;
     Ctl *ctl = nullptr;
     Ctl *ctl_host = nullptr;  // pinned
+    // device address of ctl_host (mapped, coherent): the row-pointer scan
+    // writes the control block there; null: it is read back by a copy
+    Ctl *ctl_host_dev = nullptr;
     // heavy-row spill pool and per-row descriptors
     void *spill_mem = nullptr;
     size_t spill_bytes = 0;
@@ -628,13 +631,17 @@ int spg_create(spg_handle *out, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->num_cu = prop.multiProcessorCount;
     if (hipMalloc(&h->ctl, sizeof(Ctl)) != hipSuccess ||
-        hipHostMalloc(&h->ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&h->ctl_host, sizeof(Ctl), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         (void)hipGetLastError();
         if (h->ctl) (void)hipFree(h->ctl);
         delete h;
         return SPG_ERR_NOMEM;
     }
     std::memset(h->ctl_host, 0, sizeof(Ctl));
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&h->ctl_host_dev), h->ctl_host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        h->ctl_host_dev = nullptr;
+    }
     {
         const hipError_t e = scratch_address(device, &h->scratch);
         if (e != hipSuccess) h->scratch_err = hipGetErrorString(e);
@@ -916,8 +923,9 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
                                         (float)h->heavy_margin_milli / 1000.0f, lw.pred_size, s));
         else
             HIP_TRY(h, launch_upper_sizes(M, ws.row_nprod, lw.pred_size, s));
-        HIP_TRY(h, launch_scan(M, lw.pred_size, ws.tile_sum, lw.slot_off, &h->ctl->pred_total, s));
-        HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, launch_scan(M, lw.pred_size, ws.tile_sum, lw.slot_off, &h->ctl->pred_total, s, h->ctl,
+                               h->ctl_host_dev));
+        if (!h->ctl_host_dev) HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
         if (h->ctl_host->err & kErrRowProducts) return fail_row_products(h);
         for (int i = 0; i < 8; ++i) h->counts[i] = h->ctl_host->count[i];
@@ -945,8 +953,8 @@ int spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t *c
                 return rc;
         }
     }
-    HIP_TRY(h, launch_scan(M, ws.row_size, ws.tile_sum, c_rpt, &h->ctl->nnz, s));
-    HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, launch_scan(M, ws.row_size, ws.tile_sum, c_rpt, &h->ctl->nnz, s, h->ctl, h->ctl_host_dev));
+    if (!h->ctl_host_dev) HIP_TRY(h, hipMemcpyAsync(h->ctl_host, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     const Ctl &c = *h->ctl_host;
     if (c.err & kErrRowProducts) return fail_row_products(h);

@@ -133,8 +133,11 @@ hipError_t launch_symbolic_mid(const CsrView &A, const CsrView &B, const Workspa
 // the block class and the heavy rows in one launch of 1024-thread workgroups
 hipError_t launch_symbolic_big(const CsrView &A, const CsrView &B, const Workspace &ws, int g_block, int g_heavy,
                                hipStream_t s);
+// row sizes -> row pointers and their total (*total, a word of ctl_src when
+// ctl_dst is given); with ctl_dst (the device address of a mapped host copy
+// of the control block) the scan also writes ctl_src, total in place, there
 hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
-                       int64_t *total, hipStream_t s);
+                       int64_t *total, hipStream_t s, const Ctl *ctl_src = nullptr, Ctl *ctl_dst = nullptr);
 
 // Output mode of the numeric kernels.
 struct NumOut {

@@ -1115,8 +1115,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t M, const i
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
 }
 
+// The control block into its host copy (pinned, mapped, coherent) with the
+// scan's total in place: the host reads it once the stream has drained,
+// without a copy of its own.  Called by every thread of the one workgroup
+// that holds the total.
+__device__ __forceinline__ void publish_ctl(const Ctl *src, Ctl *dst, const int64_t *total, int64_t value) {
+    if (!dst) return;
+    constexpr int kWords = (int)(sizeof(Ctl) / sizeof(int64_t));
+    static_assert(sizeof(Ctl) % sizeof(int64_t) == 0, "control block in 64-bit words");
+    const int t = threadIdx.x;
+    if (t < kWords) {
+        const int64_t *w = reinterpret_cast<const int64_t *>(src);
+        reinterpret_cast<int64_t *>(dst)[t] = (w + t == total) ? value : w[t];
+        __threadfence_system();
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_scan_top(int64_t ntiles, int64_t *tile_sum, int64_t M,
-                                                   int64_t *c_rpt, int64_t *total) {
+                                                   int64_t *c_rpt, int64_t *total, const Ctl *ctl_src,
+                                                   Ctl *ctl_dst) {
     __shared__ int64_t scr[Team<1024>::kWaves + 1];
     int64_t carry = 0;
     for (int64_t b = 0; b < ntiles; b += 1024) {
@@ -1131,6 +1148,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(int64_t ntiles, int64_t *tile
         *total = carry;
         c_rpt[M] = carry;
     }
+    publish_ctl(ctl_src, ctl_dst, total, carry);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t M, const int32_t *row_size,
@@ -1162,7 +1180,8 @@ constexpr int64_t kScanFusedTiles = 4096;
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply_fused(int64_t M, int64_t ntiles,
                                                                    const int32_t *row_size,
                                                                    const int64_t *tile_sum, int64_t *c_rpt,
-                                                                   int64_t *total) {
+                                                                   int64_t *total, const Ctl *ctl_src,
+                                                                   Ctl *ctl_dst) {
     __shared__ int64_t scr[Team<kScanThreads>::kWaves + 1];
     int64_t before = 0;
     for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) before += tile_sum[i];
@@ -1182,26 +1201,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply_fused(int64_t M, in
         if (base + j < M) c_rpt[base + j] = run;
         run += v[j];
     }
-    if ((int64_t)blockIdx.x == ntiles - 1 && threadIdx.x == 0) {
-        *total = before + tot;
-        c_rpt[M] = before + tot;
+    if ((int64_t)blockIdx.x == ntiles - 1) {
+        if (threadIdx.x == 0) {
+            *total = before + tot;
+            c_rpt[M] = before + tot;
+        }
+        publish_ctl(ctl_src, ctl_dst, total, before + tot);
     }
 }
 
 hipError_t launch_scan(int64_t M, const int32_t *sizes, int64_t *tile_sum, int64_t *out_rpt,
-                       int64_t *total, hipStream_t s) {
+                       int64_t *total, hipStream_t s, const Ctl *ctl_src, Ctl *ctl_dst) {
     const int64_t ntiles = (M + kScanTile - 1) / kScanTile;
     if (ntiles > 0 && ntiles <= kScanFusedTiles) {
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, sizes,
                            tile_sum);
         hipLaunchKernelGGL(k_scan_apply_fused, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, ntiles,
-                           sizes, tile_sum, out_rpt, total);
+                           sizes, tile_sum, out_rpt, total, ctl_src, ctl_dst);
         return hipGetLastError();
     }
     if (ntiles > 0)
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, sizes,
                            tile_sum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ntiles, tile_sum, M, out_rpt, total);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ntiles, tile_sum, M, out_rpt, total, ctl_src,
+                       ctl_dst);
     if (ntiles > 0)
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, M, sizes,
                            tile_sum, out_rpt);
