@@ -195,6 +195,15 @@ class DeviceCSR:
         return DeviceCSR(end - begin, self.cols, (rpt - lo).contiguous(), self.col[lo:hi], self.val[lo:hi])
 
     def _struct(self) -> _Csr:
+        # the last struct is kept while the same tensors, at the same
+        # addresses and sizes, make up the matrix (rebuilding it costs the
+        # checks below on every call)
+        rpt, col, val = self.rpt, self.col, self.val
+        key = (self.rows, self.cols, rpt.data_ptr(), col.data_ptr(), val.data_ptr(),
+               rpt.numel(), col.numel(), val.numel())
+        memo = self.__dict__.get("_memo")
+        if memo is not None and memo[0] == key and memo[1] is rpt and memo[2] is col and memo[3] is val:
+            return memo[4]
         if self.rpt.dtype not in (torch.int32, torch.int64):
             raise TypeError("rpt must be int32 or int64")
         for t in (self.rpt, self.col, self.val):
@@ -202,10 +211,12 @@ class DeviceCSR:
                 raise ValueError("CSR arrays must be contiguous device tensors")
         if self.col.dtype != torch.int32 or self.val.dtype != torch.float64:
             raise TypeError("col must be int32 and val float64")
-        return _Csr(self.rows, self.cols, self.nnz, self.rpt.data_ptr(),
-                    4 if self.rpt.dtype == torch.int32 else 8,
-                    self.col.data_ptr() if self.nnz else None,
-                    self.val.data_ptr() if self.nnz else None)
+        st = _Csr(self.rows, self.cols, self.nnz, self.rpt.data_ptr(),
+                  4 if self.rpt.dtype == torch.int32 else 8,
+                  self.col.data_ptr() if self.nnz else None,
+                  self.val.data_ptr() if self.nnz else None)
+        self.__dict__["_memo"] = (key, rpt, col, val, st)
+        return st
 
 
 @dataclass

@@ -511,3 +511,29 @@ def test_stored_order_option_range(handle):
     for bad in (-1, 2):
         with pytest.raises(brm.SpgError):
             handle.set_option(brm.OPT_STORED_ORDER, bad)
+
+
+def test_csr_struct_follows_replaced_tensors(handle):
+    # the binding keeps a matrix's last C struct while its tensors stay the
+    # same; a replaced value or row-pointer array is the one the library reads
+    A = synth.erdos_renyi_rows(700, 6, 11)
+    dA = brm.DeviceCSR.from_host(A)
+    assert dA._struct() is dA._struct()
+    run_C = handle.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    assert_matches_oracle(run_C, oracle.spgemm(A, A), oracle.brmerge(A, A))
+    A2 = synth.CSR(A.rows, A.cols, A.rpt, A.col, np.random.default_rng(12).uniform(-2, 2, A.nnz))
+    old = dA._struct()
+    dA.val = torch.as_tensor(A2.val, device=dA.val.device)
+    assert dA._struct() is not old and dA._struct().val == dA.val.data_ptr()
+    C2 = handle.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    assert_matches_oracle(C2, oracle.spgemm(A2, A2), oracle.brmerge(A2, A2))
+    # the same matrix with 32-bit row pointers: a new rpt tensor, a new width
+    dA.rpt = dA.rpt.to(torch.int32)
+    assert dA._struct().rpt_bytes == 4
+    C3 = handle.spgemm(dA, dA)
+    torch.cuda.synchronize()
+    assert handle.stat(brm.STAT_DEVICE_ERR) == 0
+    assert_matches_oracle(C3, oracle.spgemm(A2, A2), oracle.brmerge(A2, A2))
