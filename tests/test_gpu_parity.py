@@ -537,3 +537,26 @@ def test_csr_struct_follows_replaced_tensors(handle):
     torch.cuda.synchronize()
     assert handle.stat(brm.STAT_DEVICE_ERR) == 0
     assert_matches_oracle(C3, oracle.spgemm(A2, A2), oracle.brmerge(A2, A2))
+
+
+@pytest.mark.parametrize("rows", [1, 1023, 1024, 1025, 2047, 4097, 65537])
+def test_row_pointer_scan_tile_edges(handle, rows):
+    # the row-pointer scan works in tiles of 1024 rows: row counts on either
+    # side of a tile's end; a scaled permutation squared with a quarter of
+    # the rows empty has C[i, p[p[i]]] = a[i] * a[p[i]] where both rows hold
+    # an entry
+    rng = np.random.default_rng(rows + 7)
+    p = rng.permutation(rows).astype(np.int32)
+    a = rng.uniform(0.5, 2.0, rows)
+    empty = rng.random(rows) < 0.25
+    rpt = np.zeros(rows + 1, np.int64)
+    rpt[1:] = np.cumsum(~empty)
+    A = synth.CSR(rows, rows, rpt, p[~empty], a[~empty])
+    C = run(handle, A, A)
+    has = ~empty & ~empty[p]
+    exp_rpt = np.zeros(rows + 1, np.int64)
+    exp_rpt[1:] = np.cumsum(has)
+    assert np.array_equal(C.rpt.cpu().numpy(), exp_rpt)
+    assert np.array_equal(C.col.cpu().numpy(), p[p][has])
+    assert np.array_equal(C.val.cpu().numpy(), (a * a[p])[has])
+    assert_matches_oracle(C, oracle.spgemm(A, A), oracle.brmerge(A, A))
