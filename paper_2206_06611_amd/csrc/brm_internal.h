@@ -124,6 +124,9 @@ hipError_t launch_upper_sizes(int64_t M, const int64_t *row_nprod, int32_t *size
 // counts then bins the rows of a list by their class (ctl zeroed beforehand)
 hipError_t launch_bin_list(int64_t n, const int32_t *rows, const uint8_t *row_class, int32_t *class_rows,
                            Ctl *ctl, hipStream_t s);
+// the symbolic pass of the wave-small class (cls = kClassWaveSmall), in the
+// kernel group_rows selects; the other classes' passes share the two
+// launches below
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                            int grid, hipStream_t s, int group_rows);
 // the symbolic passes of the multi-register, wave and group classes in one

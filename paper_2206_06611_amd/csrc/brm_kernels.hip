@@ -864,14 +864,6 @@ __device__ __forceinline__ void sym_bitmap_rows(BitmapLds &s, int cls, int64_t b
     }
 }
 
-template <typename IA, typename IB>
-__global__ __launch_bounds__(kHeavyThreads) void k_sym_bitmap(
-    int cls, int64_t ncols, const void *a_rpt, Lists<IB> lists,
-    const int32_t *b_col, const int32_t *class_rows, int32_t *row_size, const Ctl *ctl) {
-    __shared__ BitmapLds s;
-    sym_bitmap_rows<IA, IB>(s, cls, blockIdx.x, gridDim.x, ncols, a_rpt, lists, b_col, class_rows, row_size, ctl);
-}
-
 // The symbolic passes of the block class (LDS hash, one row per workgroup)
 // and of the heavy rows (LDS bitmap) in one launch of 1024-thread
 // workgroups: workgroups [0, g_block) count the block class, the rest the
@@ -1001,12 +993,6 @@ __global__ __launch_bounds__(256) void k_sym_win(int cls, const void *a_rpt, Lis
                                                  const int32_t *b_col, const uint8_t *row_class,
                                                  const int32_t *class_rows, int32_t *row_size, Ctl *ctl,
                                                  WinOrder ord);
-// counting of rows under multi-register windows (defined with the numeric kernels)
-template <typename IA, typename IB>
-__global__ __launch_bounds__(256) void k_sym_mw(int cls, const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
-                                                const uint8_t *row_class, const int32_t *class_rows,
-                                                int32_t *row_size, Ctl *ctl);
-
 hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &ws, int cls,
                            int grid, hipStream_t s, int group_rows) {
 #define BRM_SYM(KERNEL, BLOCK, IA, IB)                                                        \
@@ -1066,30 +1052,6 @@ hipError_t launch_symbolic(const CsrView &A, const CsrView &B, const Workspace &
             else
                 BRM_SYM((k_sym_group<64, 4, kGroupRows, 2 * kCapWaveSmall, int64_t, int64_t>), 256, int64_t, int64_t);
             break;
-        case kClassMulti:
-#define BRM_SYM_MW(IA, IB)                                                                                   \
-    hipLaunchKernelGGL((k_sym_mw<IA, IB>), dim3(grid), dim3(256), 0, s, cls, A.rpt, ws_lists<IB>(A, B, ws), \
-                       B.col, ws.row_class, ws.class_rows, ws.row_size, ws.ctl)
-            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_SYM_MW(int32_t, int32_t);
-            else if (A.rpt_bytes == 4) BRM_SYM_MW(int32_t, int64_t);
-            else if (B.rpt_bytes == 4) BRM_SYM_MW(int64_t, int32_t);
-            else BRM_SYM_MW(int64_t, int64_t);
-#undef BRM_SYM_MW
-            break;
-        case kClassWave: BRM_SYM_ALL(64, 4, 2 * kCapWave); break;
-        case kClassGroup: BRM_SYM_ALL(256, 1, 2 * kCapGroup); break;
-        case kClassBlock: BRM_SYM_ALL(1024, 1, 2 * kCapBlock); break;
-        case kClassHeavy: {
-#define BRM_BM(IA, IB)                                                                         \
-    hipLaunchKernelGGL((k_sym_bitmap<IA, IB>), dim3(grid), dim3(kHeavyThreads), 0, s, cls,     \
-                       B.cols, A.rpt, ws_lists<IB>(A, B, ws), B.col, ws.class_rows, ws.row_size, ws.ctl)
-            if (A.rpt_bytes == 4 && B.rpt_bytes == 4) BRM_BM(int32_t, int32_t);
-            else if (A.rpt_bytes == 4) BRM_BM(int32_t, int64_t);
-            else if (B.rpt_bytes == 4) BRM_BM(int64_t, int32_t);
-            else BRM_BM(int64_t, int64_t);
-#undef BRM_BM
-            break;
-        }
         default: return hipErrorInvalidValue;
     }
 #undef BRM_SYM_ALL
@@ -2861,18 +2823,6 @@ __global__ __launch_bounds__(256) void k_num_mw(int cls, const void *a_rpt, List
     const int team = wave_uniform((int)(threadIdx.x / kWave));
     mw_rows<true, IA, IB>(cls, a_rpt, lists, a_val, b_col, b_val, row_class, class_rows, c_rpt, c_col, c_val,
                           nullptr, ctl, no, vals[team], (int64_t)blockIdx.x * 4 + team, (int64_t)gridDim.x * 4);
-}
-
-template <typename IA, typename IB>
-__global__ __launch_bounds__(256) void k_sym_mw(int cls, const void *a_rpt, Lists<IB> lists, const int32_t *b_col,
-                                                const uint8_t *row_class, const int32_t *class_rows,
-                                                int32_t *row_size, Ctl *ctl) {
-    const int team = wave_uniform((int)(threadIdx.x / kWave));
-    NumOut no;
-    no.bound = 0;
-    mw_rows<false, IA, IB>(cls, a_rpt, lists, nullptr, b_col, nullptr, row_class, class_rows, nullptr, nullptr,
-                           nullptr, row_size, ctl, no, nullptr, (int64_t)blockIdx.x * 4 + team,
-                           (int64_t)gridDim.x * 4);
 }
 
 // The symbolic passes of the multi-register window, wave and group classes
