@@ -247,7 +247,9 @@ int spg_get_stat(spg_handle h, int key, int64_t *value);
  *            read and val may be NULL.
  *   c_rpt  : device int64[A->rows + 1], written with C's row pointers.
  *   c_nnz  : host int64, written with nnz(C).
- * This call BLOCKS until c_nnz is known (one device-to-host copy).  The row
+ * This call BLOCKS until c_nnz is known (the device writes nnz and its error
+ * bits into pinned, mapped host memory of the handle; the call then waits for
+ * the stream, so `stream` must not be in graph capture).  The row
  * analysis it makes is kept in the handle for the next spgemm_numeric call
  * with the same A and B.
  * With SPG_ALLOC_LEARNED or SPG_ALLOC_UPPER (spg_option) this call already
@@ -400,7 +402,8 @@ int spgemm_batched_noalloc(spg_handle h, int count, const spg_problem *problems,
  * With SPG_OPT_ALLOC = SPG_ALLOC_LEARNED, spgemm_symbolic runs the numeric
  * kernels into the slots (no symbolic pass), records every row's exact length
  * and the rows that overflowed, and returns C's exact row pointers and nnz
- * (two device-to-host reads); spgemm_numeric recomputes the overflowed rows
+ * (two reads of the handle's mapped control block, each after the stream
+ * has drained); spgemm_numeric recomputes the overflowed rows
  * exactly into C and copies the others from their slots.  C is bitwise the
  * same as with the precise allocation.
  *
